@@ -1,0 +1,331 @@
+"""Pins of the CPU oracle against what the paper and the mathematics fix.
+
+None of these checks re-types the oracle's own formula: values come from
+brute force over subsets with an LU-based log-determinant, from closed forms
+derived by hand (tests/golden/closed_forms.json), from LAPACK's pivoted
+Cholesky, from the Schur-complement route of Algorithm 1 written independently,
+and from invariants (telescoping sum, diminishing returns, (1-1/e) bound).
+"""
+import itertools
+import json
+import math
+import os
+
+import numpy as np
+import pytest
+import scipy.linalg
+import scipy.linalg.lapack as lapack
+
+import oracle
+from oed_inputs import make_K
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden", "closed_forms.json")
+
+
+def rand_spd_instance(rng, N_s, N_t, n_m=None, c=0.05):
+    N_d = N_s * N_t
+    n_m = n_m or 2 * N_d
+    F = rng.standard_normal((N_d, n_m)) * (1.0 + np.arange(n_m)) ** -0.25
+    G = F @ F.T / n_m
+    s2 = c * float(np.mean(np.diag(G)))
+    return G + s2 * np.eye(N_d), s2
+
+
+def f_slogdet(K, N_t, sigma2, S):
+    """f(S) = 1/2 logdet(sigma^-2 K_SS) with numpy's LU-based slogdet."""
+    if len(S) == 0:
+        return 0.0
+    idx = oracle.block_index(N_t, S)
+    sign, ld = np.linalg.slogdet(oracle.symmetrize_lower(K)[np.ix_(idx, idx)] / sigma2)
+    assert sign > 0
+    return 0.5 * ld
+
+
+def brute_force_table(K, N_s, N_t, sigma2, B):
+    table = {(): 0.0}
+    for k in range(1, B + 1):
+        for S in itertools.combinations(range(N_s), k):
+            table[S] = f_slogdet(K, N_t, sigma2, S)
+    return table
+
+
+def greedy_from_table(table, N_s, B):
+    A, gains, gaps = [], [], []
+    for _ in range(B):
+        base = table[tuple(sorted(A))]
+        sc = [(table[tuple(sorted(A + [j]))] - base, j) for j in range(N_s) if j not in A]
+        best = max(sc, key=lambda x: (x[0], -x[1]))
+        rest = sorted((v for v, j in sc if j != best[1]), reverse=True)
+        gaps.append(best[0] - rest[0] if rest else math.inf)
+        A.append(best[1])
+        gains.append(best[0])
+    return A, gains, gaps
+
+
+# --------------------------------------------------------------------------- factorisation
+@pytest.mark.parametrize("n", [1, 2, 5, 17, 64, 130])
+def test_chol_logdet_vs_lu(n):
+    rng = np.random.default_rng(n)
+    X = rng.standard_normal((n, n + 3))
+    M = X @ X.T / n + 0.1 * np.eye(n)
+    got = oracle.chol_logdet(M)
+    sign, ref = np.linalg.slogdet(M)
+    assert sign > 0
+    assert abs(got - ref) <= 1e-12 * max(1.0, abs(ref))
+
+
+def test_chol_logdet_rejects_non_pd():
+    M = np.array([[1.0, 2.0], [2.0, 1.0]])
+    assert oracle.chol_logdet(M) is None
+    assert oracle.chol_logdet(np.array([[0.0]])) is None
+    assert oracle.chol_logdet(np.array([[np.nan]])) is None
+    assert oracle.chol_logdet(np.array([[1.0, 0.0], [np.inf, 1.0]])) is None
+
+
+# --------------------------------------------------------------------------- brute force
+@pytest.mark.parametrize("N_s,N_t,B,seed", [(6, 1, 3, 0), (7, 2, 3, 1), (8, 3, 4, 2), (10, 4, 4, 3),
+                                            (9, 2, 4, 4), (10, 1, 4, 5)])
+def test_greedy_matches_brute_force(N_s, N_t, B, seed):
+    rng = np.random.default_rng(seed)
+    K, s2 = rand_spd_instance(rng, N_s, N_t)
+    table = brute_force_table(K, N_s, N_t, s2, B)
+    A_ref, g_ref, gaps = greedy_from_table(table, N_s, B)
+    assert min(gaps) > 1e-8, "instance has a near-tie; pick another seed"
+    res = oracle.greedy(K, N_s, N_t, s2, B)
+    assert list(res["idx"]) == A_ref
+    np.testing.assert_allclose(res["gain"], g_ref, rtol=1e-11, atol=1e-12)
+    np.testing.assert_allclose(res["gap"], gaps, rtol=1e-8, atol=1e-10)
+    # (1 - 1/e) guarantee for monotone submodular maximisation (Sec. III-G)
+    opt = max(v for S, v in table.items() if len(S) == B)
+    assert table[tuple(sorted(A_ref))] >= (1.0 - 1.0 / math.e) * opt - 1e-12
+
+
+# --------------------------------------------------------------------------- closed forms
+def _det22(a, b, c, d):
+    return a * d - b * c
+
+
+@pytest.mark.parametrize("case", json.load(open(GOLDEN))["cases"], ids=lambda c: c["name"])
+def test_closed_form_golden(case):
+    K = np.array(case["K"], dtype=np.float64)
+    res = oracle.greedy(K, case["N_s"], case["N_t"], case["sigma2"], case["B"])
+    assert list(res["idx"]) == case["idx"]
+    expect = [eval(e, {"ln": math.log, "det22": _det22}) for e in case["gain_expr"]]
+    np.testing.assert_allclose(res["gain"], expect, rtol=1e-14, atol=1e-15)
+
+
+def test_scaled_identity_ties_go_to_lowest_index():
+    N_s, N_t, c, s2 = 9, 3, 2.5, 0.1
+    K = c * np.eye(N_s * N_t)
+    res = oracle.greedy(K, N_s, N_t, s2, 5)
+    assert list(res["idx"]) == [0, 1, 2, 3, 4]
+    np.testing.assert_allclose(res["gain"], 0.5 * N_t * math.log(c / s2), rtol=1e-15)
+    assert np.all(res["gap"] == 0.0)
+
+
+def test_block_diagonal_picks_top_blocks():
+    rng = np.random.default_rng(7)
+    N_s, N_t, s2 = 8, 3, 0.2
+    K = np.zeros((N_s * N_t, N_s * N_t))
+    vals = []
+    for i in range(N_s):
+        X = rng.standard_normal((N_t, N_t + 2))
+        blk = X @ X.T / N_t + 0.5 * np.eye(N_t)
+        if i == 5:
+            blk = K[3 * N_t:4 * N_t, 3 * N_t:4 * N_t].copy()  # exact copy of sensor 3: a tie
+        K[i * N_t:(i + 1) * N_t, i * N_t:(i + 1) * N_t] = blk
+        vals.append(0.5 * np.linalg.slogdet(blk / s2)[1])
+    order = sorted(range(N_s), key=lambda i: (-vals[i], i))
+    res = oracle.greedy(K, N_s, N_t, s2, 6)
+    assert list(res["idx"]) == order[:6]
+    np.testing.assert_allclose(res["gain"], [vals[i] for i in order[:6]], rtol=1e-12)
+
+
+def test_nt1_is_diagonally_pivoted_cholesky():
+    """With N_t = 1 the greedy is Cholesky with maximal-diagonal pivoting (LAPACK dpstrf)."""
+    rng = np.random.default_rng(11)
+    N_s, s2 = 30, 0.03
+    K, _ = rand_spd_instance(rng, N_s, 1, n_m=60)
+    K = K - np.diag(np.diag(K)) + np.diag(np.diag(K)) + s2 * np.eye(N_s)
+    L, piv, rank, info = lapack.dpstrf(np.asfortranarray(K), lower=1, tol=-1.0)
+    assert info == 0 and rank == N_s
+    res = oracle.greedy(K, N_s, 1, s2, N_s)
+    assert list(res["idx"]) == list(piv - 1)
+    np.testing.assert_allclose(res["gain"], np.log(np.abs(np.diag(L))) - 0.5 * math.log(s2),
+                               rtol=1e-12, atol=1e-13)
+
+
+# --------------------------------------------------------------------------- identities / invariants
+def _config0_like(seed=0):
+    K, s2 = make_K(24, 8, 512, seed)
+    return K.numpy(), s2
+
+
+def test_telescoping_and_diminishing_returns():
+    K, s2 = _config0_like()
+    N_s, N_t, B = 24, 8, 10
+    res = oracle.greedy(K, N_s, N_t, s2, B)
+    total = f_slogdet(K, N_t, s2, list(res["idx"]))
+    assert abs(res["gain"].sum() - total) <= 1e-11 * max(1.0, abs(total))
+    g = res["gain"]
+    assert np.all(g[1:] <= g[:-1] + 1e-12 * np.maximum(1.0, np.abs(g[:-1])))
+    assert np.all(g > 0)
+
+
+def test_scale_invariance():
+    K, s2 = _config0_like(3)
+    a = oracle.greedy(K, 24, 8, s2, 8)
+    b = oracle.greedy(7.0 * K, 24, 8, 7.0 * s2, 8)
+    assert list(a["idx"]) == list(b["idx"])
+    np.testing.assert_allclose(a["gain"], b["gain"], rtol=1e-11)
+
+
+def test_permutation_equivariance():
+    K, s2 = _config0_like(4)
+    N_s, N_t, B = 24, 8, 8
+    perm = np.random.default_rng(5).permutation(N_s)
+    idx = oracle.block_index(N_t, perm)
+    Ks = oracle.symmetrize_lower(K)
+    Kp = Ks[np.ix_(idx, idx)]
+    a = oracle.greedy(K, N_s, N_t, s2, B)
+    b = oracle.greedy(Kp, N_s, N_t, s2, B)
+    assert min(a["gap"]) > 1e-9
+    assert list(perm[b["idx"]]) == list(a["idx"])
+    np.testing.assert_allclose(a["gain"], b["gain"], rtol=1e-11)
+
+
+def test_only_lower_triangle_is_read():
+    K, s2 = _config0_like(6)
+    Kn = K.copy()
+    Kn[np.triu_indices_from(Kn, 1)] = np.nan
+    a = oracle.greedy(K, 24, 8, s2, 6)
+    b = oracle.greedy(Kn, 24, 8, s2, 6)
+    assert list(a["idx"]) == list(b["idx"])
+    np.testing.assert_array_equal(a["gain"], b["gain"])
+
+
+def test_schur_route_equals_from_scratch_scores():
+    """Scores equal 1/2 logdet(sigma^-2 M_s), M_s the Schur block of Algorithm 1 (Sec. III-D)."""
+    K, s2 = _config0_like(8)
+    N_s, N_t = 24, 8
+    A = [5, 17, 2]
+    rest = [j for j in range(N_s) if j not in A]
+    g = oracle.gains(K, N_t, s2, A, rest)
+    S = oracle.schur_complement(K, N_t, A, rest)
+    for p, j in enumerate(rest):
+        blk = S[p * N_t:(p + 1) * N_t, p * N_t:(p + 1) * N_t]
+        ref = 0.5 * np.linalg.slogdet(blk / s2)[1]
+        assert abs(g[p] - ref) <= 1e-11 * max(1.0, abs(ref))
+
+
+def _left_looking_greedy(K, N_s, N_t, s2, B):
+    """Greedy by the block Cholesky update of Sec. III-D, written independently:
+    a growing lower factor L of K_AA, a triangular solve for each candidate's
+    block column, the Schur block, its Cholesky, and a block-row append."""
+    Ks = oracle.symmetrize_lower(K)
+    A, gains = [], []
+    L = np.zeros((0, 0))
+    for _ in range(B):
+        best = None
+        for j in range(N_s):
+            if j in A:
+                continue
+            jj = oracle.block_index(N_t, [j])
+            Kjj = Ks[np.ix_(jj, jj)]
+            if A:
+                KAj = Ks[np.ix_(oracle.block_index(N_t, A), jj)]
+                Y = scipy.linalg.solve_triangular(L, KAj, lower=True)
+                M = Kjj - Y.T @ Y
+            else:
+                Y, M = None, Kjj
+            Lm = np.linalg.cholesky(M)
+            d = 2.0 * np.sum(np.log(np.diag(Lm)))
+            if best is None or d > best[0]:
+                best = (d, j, Y, Lm)
+        d, j, Y, Lm = best
+        n = L.shape[0]
+        Ln = np.zeros((n + N_t, n + N_t))
+        Ln[:n, :n] = L
+        if n:
+            Ln[n:, :n] = Y.T
+        Ln[n:, n:] = Lm
+        L = Ln
+        A.append(j)
+        gains.append(0.5 * d - 0.5 * N_t * math.log(s2))
+    return A, gains
+
+
+def test_left_looking_update_agrees():
+    K, s2 = _config0_like(9)
+    A, g = _left_looking_greedy(K, 24, 8, s2, 8)
+    res = oracle.greedy(K, 24, 8, s2, 8)
+    assert min(res["gap"]) > 1e-9
+    assert list(res["idx"]) == A
+    np.testing.assert_allclose(res["gain"], g, rtol=1e-11)
+
+
+# --------------------------------------------------------------------------- edge cases
+def test_non_pd_candidate_scores_minus_inf_and_all_fail_stops():
+    rng = np.random.default_rng(12)
+    N_s, N_t = 5, 2
+    K, s2 = rand_spd_instance(rng, N_s, N_t)
+    K[4 * N_t:, :] = 0.0          # sensor 4: zero block row -> not positive definite
+    g = oracle.gains(K, N_t, s2, [], range(N_s))
+    assert g[4] == -np.inf and np.all(np.isfinite(g[:4]))
+    res = oracle.greedy(K, N_s, N_t, s2, 4)
+    assert 4 not in list(res["idx"])
+    res = oracle.greedy(K, N_s, N_t, s2, 5, raise_on_error=False)
+    assert res["status"] == 2 and len(res["idx"]) == 4
+
+
+def test_candidates_subset_and_forced_prefix():
+    K, s2 = _config0_like(10)
+    cand = [3, 19, 7, 11, 0, 22, 15]
+    res = oracle.greedy(K, 24, 8, s2, 4, candidates=cand)
+    assert set(res["idx"]) <= set(cand)
+    # the restricted instance is the principal submatrix of those sensors
+    sub = oracle.symmetrize_lower(K)[np.ix_(oracle.block_index(8, sorted(cand)),
+                                            oracle.block_index(8, sorted(cand)))]
+    r2 = oracle.greedy(sub, len(cand), 8, s2, 4)
+    assert [sorted(cand)[i] for i in r2["idx"]] == list(res["idx"])
+    np.testing.assert_allclose(r2["gain"], res["gain"], rtol=1e-12)
+    # forcing a prefix reproduces the scores of gains() on that prefix
+    forced = oracle.greedy(K, 24, 8, s2, 3, prefix=[11, 3])
+    assert list(forced["idx"][:2]) == [11, 3]
+    g0 = oracle.gains(K, 8, s2, [], [11])[0]
+    g1 = oracle.gains(K, 8, s2, [11], [3])[0]
+    np.testing.assert_allclose(forced["gain"][:2], [g0, g1], rtol=1e-14)
+
+
+def test_argument_errors():
+    K = np.eye(4)
+    with pytest.raises(oracle.OracleError):
+        oracle.greedy(K, 4, 1, 0.0, 2)
+    with pytest.raises(oracle.OracleError):
+        oracle.greedy(K, 4, 1, 1.0, 5)
+    with pytest.raises(oracle.OracleError):
+        oracle.greedy(K, 4, 1, 1.0, 0)
+
+
+def test_thread_count_does_not_change_results():
+    K, s2 = _config0_like(13)
+    a = oracle.greedy(K, 24, 8, s2, 6, threads=1)
+    b = oracle.greedy(K, 24, 8, s2, 6, threads=4)
+    assert list(a["idx"]) == list(b["idx"])
+    np.testing.assert_array_equal(a["gain"], b["gain"])
+
+
+def test_small_fp64_config_properties():
+    """The 64 x 16 FP64 instance (n_m = 4096, seed 0, budget 16)."""
+    from oed_inputs import CONFIGS
+    sp = CONFIGS["small_fp64_64x16"]
+    K, s2 = make_K(sp.N_s, sp.N_t, sp.n_m, sp.seed)
+    K = K.numpy()
+    res = oracle.greedy(K, sp.N_s, sp.N_t, s2, sp.budget)
+    assert len(set(res["idx"])) == sp.budget
+    g = res["gain"]
+    assert np.all(g[1:] <= g[:-1] + 1e-12 * np.abs(g[:-1]))
+    total = 0.5 * oracle.logdet_lapack(
+        oracle.symmetrize_lower(K)[np.ix_(oracle.block_index(16, res["idx"]),
+                                          oracle.block_index(16, res["idx"]))] / s2)
+    assert abs(g.sum() - total) <= 1e-10 * abs(total)
