@@ -1,0 +1,189 @@
+#!/usr/bin/env python3
+"""Benchmark: greedy D-optimal sensor selection on one MI355X.
+
+One timed step = one complete selection of `budget` sensors on the synthetic
+600-sensor x 128-observation instance (K is 76,800 x 76,800 FP64, formed on the
+GPU before timing): reload of the working copy from K (oed_reset) plus
+oed_greedy(budget), all inside liboed's HIP kernels.  `value` is greedy steps
+(picks) per second of the mixed-precision path (FP32 downdate on MFMA, FP64
+factorisations); the plain FP64 path runs beside it on the same K.
+
+Prints one JSON line (rank 0).  Only N=1 is supported.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK_TFLOPS = {"fp64": 78.6, "mixed_f32": 157.3}
+HBM_PEAK_GBS = 8000.0
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--config", default="mixed_600x128")
+    ap.add_argument("--budget", type=int, default=None, help="override the budget (not the headline)")
+    ap.add_argument("--fp64-steps", type=int, default=1)
+    ap.add_argument("--no-fp64", action="store_true")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-budget", type=int, default=12, help="picks of the oracle sample")
+    ap.add_argument("--cpu-sensors", type=int, default=100)
+    return ap.parse_args()
+
+
+def timed_selections(sel, K, budget, steps):
+    import torch
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    out = None
+    for s in range(steps):
+        sel.reset(K)
+        out = sel.greedy(budget)
+    torch.cuda.synchronize()
+    return (time.perf_counter() - t0) * 1e3 / steps, out
+
+
+def roofline_syrk(prof, prec):
+    ms = prof["ms"]["syrk"]
+    n = max(1, prof["launches"]["syrk"])
+    tflops = prof["syrk_flops"] / (ms * 1e-3) / 1e12 if ms > 0 else 0.0
+    return {
+        "kernel": "syrk_kernel",
+        "bound": "mfma",
+        "achieved": round(tflops, 3),
+        "peak": PEAK_TFLOPS[prec],
+        "unit": "TFLOP/s",
+        "frac": round(tflops / PEAK_TFLOPS[prec], 4),
+        "traffic": None,
+        "avg_launch_ms": round(ms / n, 4),
+        "launches": n,
+        "algorithmic_gbs": round(prof["syrk_bytes"] / (ms * 1e-3) / 1e9, 1) if ms > 0 else 0.0,
+    }
+
+
+def cpu_baseline(K, N_t, s2, n_sensors, budget):
+    """The oracle (from-scratch FP64 Cholesky of every test matrix, OpenMP over candidates)
+    on the first n_sensors sensors of the same K."""
+    import numpy as np
+
+    import oracle
+    from oed_inputs import k_sub_lower
+    sub = k_sub_lower(K, N_t, list(range(n_sensors)))
+    threads = oracle.default_threads()
+    t0 = time.perf_counter()
+    res = oracle.greedy(sub, n_sensors, N_t, s2, budget, threads=threads)
+    dt = time.perf_counter() - t0
+    return {"value": round(budget / dt, 4), "unit": "greedy steps/s", "cores": threads, "kind": "oracle",
+            "sample": f"sensors 0..{n_sensors - 1} of the same K ({n_sensors * N_t}^2 principal block), "
+                      f"budget {budget}, {dt:.1f} s", "seconds": round(dt, 2),
+            "idx": [int(x) for x in res["idx"]], "gain": [float(x) for x in np.asarray(res["gain"])]}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py runs on one GPU only: the selection is a single-GPU kernel pipeline; "
+              "see the sharding paragraph of the design notes", file=sys.stderr)
+        sys.exit(2)
+    import numpy as np
+    import torch
+
+    from oed_inputs import CONFIGS, make_K_lower_panels
+    from paper_2604_08812_amd import Selector, library
+
+    library()
+    spec = CONFIGS[args.config]
+    budget = args.budget or spec.budget
+    prec = spec.precision
+    dev = torch.device("cuda:0")
+    log(f"forming K for {spec.name}: N_s={spec.N_s} N_t={spec.N_t} n_m={spec.n_m} seed={spec.seed}")
+    t0 = time.perf_counter()
+    kdt = torch.float64 if spec.k_dtype == "f64" else torch.float32
+    K, s2 = make_K_lower_panels(spec.N_s, spec.N_t, spec.n_m, spec.seed, spec.c, device=dev, dtype=kdt,
+                                progress=lambda i, n: log(f"  K column chunk {i}/{n}") if i % 4 == 0 or i == n
+                                else None)
+    torch.cuda.synchronize()
+    log(f"K formed in {time.perf_counter() - t0:.1f} s, sigma2={s2:.6e}")
+
+    # ---- headline path
+    sel = Selector(K, spec.N_s, spec.N_t, s2, precision=prec, profile=True)
+    for w in range(args.warmup):
+        timed_selections(sel, K, budget, 1)
+        log(f"warmup {w + 1}/{args.warmup} done")
+    sel.profile(reset=True)
+    ms, (idx, gain) = timed_selections(sel, K, budget, args.steps)
+    prof = sel.profile(reset=True)
+    log(f"{prec}: {ms:.1f} ms per selection of {budget}")
+    result = {
+        "metric": "greedy steps/s + SYRK TFLOP/s (% MFMA peak), mixed vs FP64, same picks",
+        "value": round(budget / (ms * 1e-3), 3),
+        "unit": "greedy steps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32" if prec != "fp64" else "f64",
+        "data": "synthetic",
+        "config": {"workload": spec.name, "N_s": spec.N_s, "N_t": spec.N_t, "n_m": spec.n_m, "seed": spec.seed,
+                   "budget": budget, "precision": prec, "K_dtype": spec.k_dtype,
+                   "step": "oed_reset + oed_greedy(budget)"},
+        "roofline": roofline_syrk(prof, prec),
+        "kernel_ms_per_step": {k: round(v / args.steps, 3) for k, v in prof["ms"].items()},
+    }
+    sel.close()
+
+    # ---- FP64 beside it, same K
+    if not args.no_fp64 and prec != "fp64":
+        sel64 = Selector(K, spec.N_s, spec.N_t, s2, precision="fp64", profile=True)
+        sel64.profile(reset=True)
+        ms64, (idx64, gain64) = timed_selections(sel64, K, budget, args.fp64_steps)
+        p64 = sel64.profile(reset=True)
+        sel64.close()
+        log(f"fp64: {ms64:.1f} ms per selection")
+        agree = int(np.sum(idx == idx64))
+        first_div = next((k for k in range(budget) if idx[k] != idx64[k]), None)
+        upto = budget if first_div is None else first_div
+        gerr = float(np.max(np.abs(gain[:upto] - gain64[:upto]) / np.maximum(1, np.abs(gain64[:upto])))) \
+            if upto else 0.0
+        result["fp64"] = {"value": round(budget / (ms64 * 1e-3), 3), "unit": "greedy steps/s",
+                          "ms_per_step": round(ms64, 3), "roofline": roofline_syrk(p64, "fp64"),
+                          "kernel_ms_per_step": {k: round(v / args.fp64_steps, 3) for k, v in p64["ms"].items()}}
+        result["mixed_vs_fp64"] = {"speedup": round(ms64 / ms, 3), "same_picks": agree == budget,
+                                   "picks_equal_at_position": agree, "first_divergence_step": first_div,
+                                   "max_rel_gain_diff_before_divergence": gerr}
+
+    # ---- CPU oracle baseline on a bounded sample of the same K
+    if not args.no_cpu_baseline:
+        log("cpu baseline (oracle) ...")
+        cb = cpu_baseline(K, spec.N_t, s2, args.cpu_sensors, args.cpu_budget)
+        sel_s = Selector(K, spec.N_s, spec.N_t, s2, precision=prec, candidates=range(args.cpu_sensors))
+        i_s, g_s = sel_s.greedy(args.cpu_budget)
+        sel_s.close()
+        cb["gpu_same_sample_picks_equal"] = [int(x) for x in i_s] == cb["idx"]
+        cb["gpu_same_sample_max_rel_gain_err"] = float(np.max(np.abs(g_s - np.array(cb["gain"])) /
+                                                             np.maximum(1, np.abs(np.array(cb["gain"])))))
+        del cb["idx"], cb["gain"]
+        result["cpu_baseline"] = cb
+        log(f"cpu baseline {cb['value']} steps/s on {cb['cores']} threads")
+    print(json.dumps(result), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,184 @@
+/*
+ * oed.h -- C ABI of liboed: greedy D-optimal sensor selection on one MI355X.
+ *
+ * The problem (paper, Sec. III-A to III-D): K is the dense data-space matrix
+ * K = Gamma_noise + F Gamma_prior F^* of a linear-Gaussian inverse problem,
+ * with one N_t x N_t block per candidate sensor (sensor i owns rows and
+ * columns i*N_t .. i*N_t+N_t-1).  With isotropic noise sigma^2 I, greedy
+ * D-optimal selection adds, at every step, the remaining candidate j with the
+ * largest information gain
+ *     g_j = 1/2 logdet(sigma^-2 S_j),
+ * where S_j is the N_t x N_t Schur complement of K_jj given the sensors
+ * already selected (the matrix M_s of Algorithm 1, Sec. III-D).  Exact ties go
+ * to the lowest sensor index.  The sum of the first k gains is
+ * 1/2 logdet(sigma^-2 K_AA) for the selected set A (Sec. III-C objective).
+ *
+ * The library keeps the Schur complement R of the candidate part of K in HBM
+ * and, per step, (a) factors every remaining diagonal block in FP64 and takes
+ * the argmax of the gains, (b) forms W = R[:, s] L_s^-T for the winner s, and
+ * (c) downdates R -= W W^T on its lower triangle.
+ *
+ * Conventions shared by all calls:
+ *  - Device pointers are HIP device memory of the current device; host
+ *    pointers are ordinary host memory.  The library never frees caller memory.
+ *  - K is row-major with leading dimension ld >= N_s*N_t elements, FP64 or
+ *    FP32; only its lower triangle (column <= row) is read, and only during
+ *    oed_create / oed_reset (the library keeps its own packed working copy).
+ *  - Sensor indices are 0-based indices into K's block rows.
+ *  - All work is enqueued on the stream given to oed_create (a hipStream_t;
+ *    NULL = the default stream).  Calls that return host results synchronise
+ *    that stream before returning.
+ *  - Every call returns an oed_status; no call aborts or throws.  The text of
+ *    the last error of a handle is available from oed_last_error().
+ *  - A handle is not thread-safe; distinct handles are independent.
+ */
+#ifndef OED_H
+#define OED_H
+
+#include <stdint.h>
+
+#ifndef OED_API
+#define OED_API __attribute__((visibility("default")))
+#endif
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct oed_ctx oed_ctx;
+
+typedef enum oed_status {
+    OED_OK = 0,
+    OED_E_ARG = 1,         /* invalid argument (sizes, sigma2 <= 0 or NaN, NULL, index) */
+    OED_E_NOT_SPD = 2,     /* every remaining candidate has a non-positive-definite Schur block */
+    OED_E_OOM = 3,         /* device or host allocation failed */
+    OED_E_HIP = 4,         /* a HIP runtime call failed */
+    OED_E_STATE = 5,       /* the handle cannot do this now (e.g. after OED_E_NOT_SPD) */
+    OED_E_UNSUPPORTED = 6  /* a valid request this build does not handle */
+} oed_status;
+
+typedef enum oed_dtype { OED_F64 = 0, OED_F32 = 1 } oed_dtype;
+
+/*
+ * Arithmetic of the working copy R and of the downdate R -= W W^T.
+ *  FP64         : R, W and the downdate in FP64 (FP64 MFMA).
+ *  MIXED_F32    : R and W stored in FP32, downdate on FP32 MFMA with FP32
+ *                 accumulation.  Diagonal-block Cholesky factorisations, gains,
+ *                 the winner's factor and the solve forming W run in FP64.
+ *  MIXED_BF16X3 : like MIXED_F32, but W is split into BF16 hi + lo parts and
+ *                 the product is hi*hi + hi*lo + lo*hi on BF16 MFMA with FP32
+ *                 accumulation.
+ * The paper keeps K in FP64 and runs the whole candidate loop in FP32 (Sec. IV);
+ * MIXED_F32 keeps the precision-critical factorisations in FP64 instead.
+ */
+typedef enum oed_precision {
+    OED_PREC_FP64 = 0,
+    OED_PREC_MIXED_F32 = 1,
+    OED_PREC_MIXED_BF16X3 = 2
+} oed_precision;
+
+/* oed_options.flags */
+#define OED_FLAG_PROFILE 0x1u /* time every kernel with HIP events (see oed_get_profile) */
+
+typedef struct oed_options {
+    uint32_t struct_size;       /* sizeof(oed_options); set by oed_options_init */
+    int32_t precision;          /* oed_precision, default OED_PREC_FP64 */
+    uint32_t flags;             /* OED_FLAG_* */
+    const int32_t *candidates;  /* host array of candidate sensors (the set C of Sec. III-A);
+                                   NULL = all N_s sensors.  Copied during oed_create. */
+    int32_t n_candidates;       /* length of candidates */
+    int32_t reserved[7];        /* must be 0 */
+} oed_options;
+
+/* Fill *opt with the defaults (FP64, no flags, all sensors). */
+OED_API void oed_options_init(oed_options *opt);
+
+/*
+ * Create a selection context for K (device memory, dtype OED_F64 or OED_F32,
+ * leading dimension ld) with N_s sensors of N_t observations each and noise
+ * variance sigma2 > 0.  The candidate part of K's lower triangle is copied into
+ * a packed working copy R (half of the dense size; FP64 or FP32 by precision).
+ * K is not referenced after this call returns.  All device memory the greedy
+ * loop needs is allocated here; later calls allocate nothing on the device.
+ * stream: a hipStream_t (NULL = default stream).  opt: NULL = defaults.
+ * On success *out is a new handle; on failure *out is NULL.
+ */
+OED_API oed_status oed_create(oed_ctx **out, const void *K_dev, int32_t dtype, int64_t ld, int32_t N_s,
+                      int32_t N_t, double sigma2, void *stream, const oed_options *opt);
+
+/*
+ * Reload the working copy from K_dev (same dtype, ld and shape as at creation)
+ * and forget all picks.  Allocates nothing.
+ */
+OED_API oed_status oed_reset(oed_ctx *h, const void *K_dev);
+
+/*
+ * Run `budget` more greedy steps (Sec. III-D): each step scores all remaining
+ * candidates, picks the best and conditions on it.  idx_out[k] (host,
+ * length budget) receives the sensor index of the k-th new pick, gain_out[k]
+ * (host, length budget) its gain in nats.  *n_out = picks actually made.
+ * 0 <= budget <= number of remaining candidates, else OED_E_ARG.
+ * Returns OED_E_NOT_SPD, with the picks made before it, when every remaining
+ * candidate has a non-positive-definite Schur block; the handle then only
+ * accepts oed_reset / oed_destroy / queries.  One host synchronisation per call.
+ */
+OED_API oed_status oed_greedy(oed_ctx *h, int32_t budget, int32_t *idx_out, double *gain_out,
+                      int32_t *n_out);
+
+/*
+ * Force the next pick to be sensor idx (a remaining candidate) instead of the
+ * argmax: used to resume from a saved selection or to replay another
+ * trajectory.  *gain_out (host, may be NULL) receives its gain.
+ */
+OED_API oed_status oed_force(oed_ctx *h, int32_t idx, double *gain_out);
+
+/*
+ * Gains of all candidates at the current step, as the next greedy step would
+ * score them.  gains_out: host, length N_s; -inf for sensors that are picked
+ * or not candidates (and for non-positive-definite Schur blocks).
+ */
+OED_API oed_status oed_scores(oed_ctx *h, double *gains_out);
+
+/*
+ * Block (i, j) of the current Schur complement of the remaining candidates
+ * (both i and j remaining candidates), in FP64, unpadded, row-major N_t x N_t
+ * into host memory out.  Any order of i, j is accepted (R is symmetric).
+ */
+OED_API oed_status oed_schur_block(oed_ctx *h, int32_t i, int32_t j, double *out);
+
+/* All picks so far (host arrays of capacity >= N_s); *n_out = count. */
+OED_API oed_status oed_picks(oed_ctx *h, int32_t *idx_out, double *gain_out, int32_t *n_out);
+
+/* Kernel classes reported by oed_get_profile. */
+enum { OED_K_GAIN = 0, OED_K_PICK = 1, OED_K_TRSM = 2, OED_K_SYRK = 3, OED_K_PACK = 4, OED_K_COUNT = 5 };
+
+typedef struct oed_profile {
+    double ms[OED_K_COUNT];        /* summed kernel time, from HIP events on the context stream */
+    int64_t launches[OED_K_COUNT];
+    double syrk_flops;             /* algorithmic flops of all downdates: sum N_t * n (n + 1),
+                                      n = remaining rows (remaining sensors * N_t) */
+    double syrk_bytes;             /* algorithmic HBM bytes: sum e * (n (n + N_t) + n N_t),
+                                      e = bytes per element of R (lower blocks read and
+                                      written once, W read once) */
+} oed_profile;
+
+/* Read (and with reset != 0 clear) the accumulated profile.  Needs OED_FLAG_PROFILE. */
+OED_API oed_status oed_get_profile(oed_ctx *h, oed_profile *out, int32_t reset);
+
+/* Bytes of device memory the handle holds. */
+OED_API oed_status oed_device_bytes(const oed_ctx *h, int64_t *bytes);
+
+/* Destroy the handle and free its device memory.  NULL is accepted. */
+OED_API oed_status oed_destroy(oed_ctx *h);
+
+/* Text of the handle's last error ("" if none; a static string for NULL). */
+OED_API const char *oed_last_error(const oed_ctx *h);
+
+/* Name of a status code. */
+OED_API const char *oed_status_string(int32_t status);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* OED_H */

@@ -13,5 +13,6 @@ from .synth import (  # noqa: F401
     f_tile,
     make_K,
     make_K_lower_panels,
+    k_sub_lower,
 )
 from .configs import CONFIGS, batched_instance_specs, Spec  # noqa: F401

@@ -107,3 +107,13 @@ def make_K_lower_panels(N_s: int, N_t: int, n_m: int, seed: int, c: float = 0.01
     sigma2 = float(c * d.to(torch.float64).mean().item())
     d.add_(sigma2)
     return K, sigma2
+
+
+def k_sub_lower(K: torch.Tensor, N_t: int, sensors) -> "numpy.ndarray":
+    """Dense FP64 host copy of the block sub-matrix of K for the ordered sensor list,
+    every element taken from K's lower triangle (K may live on the GPU)."""
+    idx = torch.as_tensor([int(s) * N_t + t for s in sensors for t in range(N_t)], device=K.device)
+    sub = K.index_select(0, idx).index_select(1, idx)
+    low = idx[:, None] >= idx[None, :]
+    # element (a, b) with idx[a] < idx[b] lies in K's upper triangle: take (b, a) instead
+    return torch.where(low, sub, sub.t()).to(torch.float64).cpu().numpy()

@@ -56,7 +56,7 @@ def lib():
         L.oedo_gains.argtypes = [dp, ctypes.c_int64, ctypes.c_int, ctypes.c_double, ip, ctypes.c_int,
                                  ip, ctypes.c_int, dp, ctypes.c_int]
         L.oedo_greedy.argtypes = [dp, ctypes.c_int64, ctypes.c_int, ctypes.c_double, ip, ctypes.c_int,
-                                  ip, ctypes.c_int, ctypes.c_int, ip, dp, dp, ip, ctypes.c_int]
+                                  ip, ctypes.c_int, ctypes.c_int, ip, dp, dp, ip, dp, ip, ctypes.c_int]
         _lib = L
     return _lib
 
@@ -126,7 +126,9 @@ def greedy(K, N_s, N_t, sigma2, B, candidates=None, prefix=None, threads=None, r
     """Greedy selection of B sensors.
 
     Returns a dict with ``idx`` (picked sensors, pick order), ``gain`` (their
-    scores), ``gap`` (best minus runner-up score at each step) and ``status``.
+    scores), ``gap`` (best minus runner-up score at each step), ``best`` and
+    ``best_gain`` (what the rule itself would pick at each step given the
+    prefix; equal to idx/gain except at forced steps) and ``status``.
     """
     K = _as_K(K)
     if K.shape[0] < N_s * N_t:
@@ -136,14 +138,18 @@ def greedy(K, N_s, N_t, sigma2, B, candidates=None, prefix=None, threads=None, r
     idx = np.full(B, -1, dtype=np.int32)
     gain = np.full(B, np.nan)
     gap = np.full(B, np.nan)
+    best = np.full(B, -1, dtype=np.int32)
+    best_gain = np.full(B, np.nan)
     n = ctypes.c_int()
     rc = lib().oedo_greedy(_dp(K), K.shape[1], N_t, float(sigma2), _ip(cand), len(cand), _ip(pre),
-                           len(pre), int(B), _ip(idx), _dp(gain), _dp(gap), ctypes.byref(n),
+                           len(pre), int(B), _ip(idx), _dp(gain), _dp(gap), _ip(best), _dp(best_gain),
+                           ctypes.byref(n),
                            threads or default_threads())
     if rc != 0 and raise_on_error:
         raise OracleError(rc, f"after {n.value} picks")
     m = n.value
-    return {"idx": idx[:m].copy(), "gain": gain[:m].copy(), "gap": gap[:m].copy(), "status": rc}
+    return {"idx": idx[:m].copy(), "gain": gain[:m].copy(), "gap": gap[:m].copy(), "best": best[:m].copy(),
+            "best_gain": best_gain[:m].copy(), "status": rc}
 
 
 def logdet_lapack(M):

@@ -168,11 +168,14 @@ int oedo_gains(const double *K, int64_t ld, int N_t, double sigma2, const int *A
  *   idx_out[k]  the sensor picked,
  *   gain_out[k] its score g,
  *   gap_out[k]  best score minus second-best score at that step (+inf when
- *               only one candidate has a finite score).
+ *               only one candidate has a finite score),
+ *   best_out[k], bestgain_out[k]  the candidate the rule would pick at that
+ *               step and its score (differs from idx_out[k] only when forced);
+ *               either pointer may be NULL.
  */
 int oedo_greedy(const double *K, int64_t ld, int N_t, double sigma2, const int *cand, int nc,
                 const int *prefix, int nprefix, int B, int *idx_out, double *gain_out,
-                double *gap_out, int *n_out, int nthreads)
+                double *gap_out, int *best_out, double *bestgain_out, int *n_out, int nthreads)
 {
     *n_out = 0;
     if (!K || N_t <= 0 || !(sigma2 > 0.0) || nc <= 0 || B < 1 || B > nc || nprefix < 0 ||
@@ -208,6 +211,10 @@ int oedo_greedy(const double *K, int64_t ld, int N_t, double sigma2, const int *
             if (g[c] > g[best])
                 best = c;
         }
+        if (best_out)
+            best_out[k] = pool[best];
+        if (bestgain_out)
+            bestgain_out[k] = g[best];
         if (k < nprefix) {
             best = -1;
             for (int c = 0; c < npool; ++c)

@@ -1,0 +1,23 @@
+"""Greedy D-optimal sensor selection on MI355X (gfx950).
+
+The selection runs in liboed.so (HIP kernels behind the C ABI of
+``include/oed.h``); ``oed`` is its thin ctypes binding.
+"""
+from .oed import (  # noqa: F401
+    EXPORTED,
+    LIB_PATH,
+    OedError,
+    PRECISIONS,
+    Selector,
+    library,
+    oed_create,
+    oed_destroy,
+    oed_device_bytes,
+    oed_force,
+    oed_get_profile,
+    oed_greedy,
+    oed_picks,
+    oed_reset,
+    oed_schur_block,
+    oed_scores,
+)

@@ -1,0 +1,516 @@
+// liboed C ABI: context, greedy loop and queries (declarations and contract in include/oed.h).
+//
+// The host enqueues the whole greedy loop without synchronising: the number
+// of remaining candidates after k picks is known on the host, the identity of
+// each pick stays on the device (active list, last pick, status word) and is
+// read back once per call.  All device memory is allocated in oed_create.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/oed.h"
+#include "oed_internal.h"
+
+using namespace oed;
+
+namespace {
+
+const int NKC = OED_K_COUNT;
+
+struct EvPair {
+    hipEvent_t a, b;
+};
+
+}  // namespace
+
+struct oed_ctx {
+    // problem
+    int N_s = 0, N_c = 0, N_t = 0, N_tp = 0;
+    int kdtype = 0;
+    int64_t ld = 0;
+    double sigma2 = 0, half_noise = 0;
+    int prec = OED_PREC_FP64;
+    int rtype = R_F64, wtype = W_F64;
+    uint32_t flags = 0;
+    hipStream_t stream = nullptr;
+    int device = 0;
+    std::vector<int> cmap;  // local -> original sensor index (ascending)
+    std::vector<int> lmap;  // original -> local (-1 = not a candidate)
+    // device memory
+    void *R = nullptr, *W = nullptr;
+    double *Linv = nullptr, *gains = nullptr, *pick_gain = nullptr, *scratch_gain = nullptr,
+           *scratch_pick = nullptr;
+    int *act[2] = {nullptr, nullptr}, *picks = nullptr, *state = nullptr, *dcmap = nullptr;
+    int64_t dev_bytes = 0;
+    // host mirror of the selection
+    int cur = 0;       // which act buffer is current
+    int n_act = 0;     // remaining candidates
+    int k = 0;         // picks made
+    bool pending = false;  // the last pick's downdate is not applied yet
+    bool poisoned = false;
+    std::vector<int> h_picks;   // local indices
+    std::vector<double> h_gains;
+    std::vector<char> picked;  // by local index
+    // profiling
+    std::vector<EvPair> ev_pool;
+    std::vector<std::pair<int, int>> ev_used;  // (kernel class, pool index)
+    double prof_ms[NKC] = {0};
+    int64_t prof_n[NKC] = {0};
+    double syrk_flops = 0, syrk_bytes = 0;
+    std::string err;
+};
+
+namespace {
+
+oed_status fail(oed_ctx *h, oed_status st, const std::string &msg)
+{
+    if (h) h->err = msg;
+    return st;
+}
+
+#define HIPCHK(h, call)                                                                                     \
+    do {                                                                                                    \
+        hipError_t e_ = (call);                                                                             \
+        if (e_ != hipSuccess)                                                                               \
+            return fail(h, e_ == hipErrorOutOfMemory ? OED_E_OOM : OED_E_HIP,                              \
+                        std::string(#call) + ": " + hipGetErrorString(e_));                                 \
+    } while (0)
+
+size_t relem(const oed_ctx *h) { return h->rtype == R_F64 ? 8 : 4; }
+
+hipError_t dmalloc(oed_ctx *h, void **p, size_t bytes)
+{
+    hipError_t e = hipMalloc(p, bytes);
+    if (e == hipSuccess) h->dev_bytes += (int64_t)bytes;
+    return e;
+}
+
+// Event bracketing of one kernel launch when profiling.
+struct Prof {
+    oed_ctx *h;
+    int cls;
+    int idx = -1;
+    Prof(oed_ctx *h_, int c) : h(h_), cls(c)
+    {
+        if (!(h->flags & OED_FLAG_PROFILE)) return;
+        idx = (int)h->ev_used.size();
+        if (idx >= (int)h->ev_pool.size()) {
+            EvPair p;
+            if (hipEventCreate(&p.a) != hipSuccess || hipEventCreate(&p.b) != hipSuccess) {
+                idx = -1;
+                return;
+            }
+            h->ev_pool.push_back(p);
+        }
+        h->ev_used.push_back({cls, idx});
+        (void)hipEventRecord(h->ev_pool[idx].a, h->stream);
+    }
+    ~Prof()
+    {
+        if (idx >= 0) (void)hipEventRecord(h->ev_pool[idx].b, h->stream);
+    }
+};
+
+// Called after a stream synchronisation: fold the recorded events into the totals.
+void collect_profile(oed_ctx *h)
+{
+    for (auto &u : h->ev_used) {
+        float ms = 0;
+        if (hipEventElapsedTime(&ms, h->ev_pool[u.second].a, h->ev_pool[u.second].b) == hipSuccess) {
+            h->prof_ms[u.first] += ms;
+            h->prof_n[u.first] += 1;
+        }
+    }
+    h->ev_used.clear();
+}
+
+void free_all(oed_ctx *h)
+{
+    void *ptrs[] = {h->R, h->W, h->Linv, h->gains, h->pick_gain, h->scratch_gain, h->scratch_pick,
+                    h->act[0], h->act[1], h->picks, h->state, h->dcmap};
+    for (void *p : ptrs)
+        if (p) (void)hipFree(p);
+    for (auto &e : h->ev_pool) {
+        (void)hipEventDestroy(e.a);
+        (void)hipEventDestroy(e.b);
+    }
+    h->ev_pool.clear();
+}
+
+oed_status load_R(oed_ctx *h, const void *K)
+{
+    {
+        Prof pr(h, OED_K_PACK);
+        HIPCHK(h, launch_pack(K, h->kdtype, h->ld, h->N_t, h->N_tp, h->dcmap, h->N_c, h->R, h->rtype, h->stream));
+    }
+    HIPCHK(h, launch_init_state(h->act[0], h->N_c, h->pick_gain, h->picks, h->state, h->stream));
+    h->cur = 0;
+    h->n_act = h->N_c;
+    h->k = 0;
+    h->pending = false;
+    h->poisoned = false;
+    h->h_picks.clear();
+    h->h_gains.clear();
+    h->picked.assign(h->N_c, 0);
+    return OED_OK;
+}
+
+// Enqueue the downdate of the last pick if it has not been applied.
+oed_status flush_pending(oed_ctx *h)
+{
+    if (!h->pending) return OED_OK;
+    h->pending = false;
+    if (h->n_act == 0) return OED_OK;
+    {
+        Prof pr(h, OED_K_TRSM);
+        HIPCHK(h, launch_trsm(h->R, h->rtype, h->act[h->cur], h->n_act, h->state, h->Linv, h->N_tp, h->W, h->wtype,
+                              h->stream));
+    }
+    {
+        Prof pr(h, OED_K_SYRK);
+        HIPCHK(h, launch_syrk(h->R, h->rtype, h->W, h->wtype, h->act[h->cur], h->n_act, h->N_tp, h->state, h->stream));
+    }
+    const double n = (double)h->n_act * h->N_t;
+    h->syrk_flops += (double)h->N_t * n * (n + 1.0);
+    h->syrk_bytes += (double)relem(h) * (n * (n + h->N_t) + n * h->N_t);
+    return OED_OK;
+}
+
+oed_status enqueue_gains(oed_ctx *h)
+{
+    Prof pr(h, OED_K_GAIN);
+    HIPCHK(h, launch_gain(h->R, h->rtype, h->act[h->cur], h->n_act, h->N_t, h->N_tp, h->half_noise, h->gains, h->state,
+                          h->scratch_gain, h->stream));
+    return OED_OK;
+}
+
+oed_status enqueue_pick(oed_ctx *h, int forced_local)
+{
+    {
+        Prof pr(h, OED_K_PICK);
+        HIPCHK(h, launch_pick(h->R, h->rtype, h->act[h->cur], h->act[h->cur ^ 1], h->n_act, h->gains, h->N_t, h->N_tp,
+                              h->half_noise, h->k, forced_local, h->picks, h->pick_gain, h->state, h->Linv,
+                              h->scratch_pick, h->stream));
+    }
+    h->cur ^= 1;
+    h->n_act -= 1;
+    h->k += 1;
+    h->pending = true;
+    return OED_OK;
+}
+
+// Read back picks [k0, k) and the status word; reconcile the host mirror.
+oed_status sync_picks(oed_ctx *h, int k0, oed_status *dev_status)
+{
+    const int n = h->k - k0;
+    std::vector<int> idx(std::max(n, 1));
+    std::vector<double> g(std::max(n, 1));
+    int st[ST_WORDS];
+    if (n > 0) {
+        HIPCHK(h, hipMemcpyAsync(idx.data(), h->picks + k0, sizeof(int) * n, hipMemcpyDeviceToHost, h->stream));
+        HIPCHK(h, hipMemcpyAsync(g.data(), h->pick_gain + k0, sizeof(double) * n, hipMemcpyDeviceToHost, h->stream));
+    }
+    HIPCHK(h, hipMemcpyAsync(st, h->state, sizeof(st), hipMemcpyDeviceToHost, h->stream));
+    HIPCHK(h, hipStreamSynchronize(h->stream));
+    collect_profile(h);
+    *dev_status = (oed_status)st[ST_STATUS];
+    const int made = std::min(n, std::max(0, st[ST_NPICKS] - k0));
+    if (st[ST_STATUS] != 0) {
+        // the device stopped after `made` picks; later kernels were no-ops
+        h->k = k0 + made;
+        h->n_act = h->N_c - h->k;
+        h->pending = false;
+        h->poisoned = true;
+    }
+    for (int q = 0; q < made; ++q) {
+        h->h_picks.push_back(idx[q]);
+        h->h_gains.push_back(g[q]);
+        if (idx[q] >= 0 && idx[q] < h->N_c) h->picked[idx[q]] = 1;
+    }
+    return OED_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+void oed_options_init(oed_options *opt)
+{
+    if (!opt) return;
+    std::memset(opt, 0, sizeof(*opt));
+    opt->struct_size = sizeof(oed_options);
+    opt->precision = OED_PREC_FP64;
+}
+
+const char *oed_status_string(int32_t s)
+{
+    switch (s) {
+    case OED_OK: return "OED_OK";
+    case OED_E_ARG: return "OED_E_ARG";
+    case OED_E_NOT_SPD: return "OED_E_NOT_SPD";
+    case OED_E_OOM: return "OED_E_OOM";
+    case OED_E_HIP: return "OED_E_HIP";
+    case OED_E_STATE: return "OED_E_STATE";
+    case OED_E_UNSUPPORTED: return "OED_E_UNSUPPORTED";
+    default: return "OED_E_UNKNOWN";
+    }
+}
+
+const char *oed_last_error(const oed_ctx *h) { return h ? h->err.c_str() : "null handle"; }
+
+oed_status oed_create(oed_ctx **out, const void *K, int32_t dtype, int64_t ld, int32_t N_s, int32_t N_t,
+                      double sigma2, void *stream, const oed_options *opt)
+{
+    if (!out) return OED_E_ARG;
+    *out = nullptr;
+    oed_options o;
+    oed_options_init(&o);
+    if (opt) {
+        if (opt->struct_size != sizeof(oed_options)) return OED_E_ARG;
+        o = *opt;
+    }
+    if (!K || (dtype != OED_F64 && dtype != OED_F32) || N_s < 1 || N_t < 1 || N_t > 4096 ||
+        ld < (int64_t)N_s * N_t || !(sigma2 > 0.0) || !std::isfinite(sigma2))
+        return OED_E_ARG;
+    if (o.precision != OED_PREC_FP64 && o.precision != OED_PREC_MIXED_F32 && o.precision != OED_PREC_MIXED_BF16X3)
+        return OED_E_ARG;
+    if (o.precision == OED_PREC_MIXED_BF16X3) return OED_E_UNSUPPORTED;
+    for (int r : o.reserved)
+        if (r != 0) return OED_E_ARG;
+
+    oed_ctx *h = new (std::nothrow) oed_ctx();
+    if (!h) return OED_E_OOM;
+    h->N_s = N_s;
+    h->N_t = N_t;
+    h->N_tp = (N_t + 15) / 16 * 16;
+    h->kdtype = dtype;
+    h->ld = ld;
+    h->sigma2 = sigma2;
+    h->half_noise = 0.5 * N_t * std::log(sigma2);
+    h->prec = o.precision;
+    h->rtype = o.precision == OED_PREC_FP64 ? R_F64 : R_F32;
+    h->wtype = o.precision == OED_PREC_FP64 ? W_F64 : W_F32;
+    h->flags = o.flags;
+    h->stream = (hipStream_t)stream;
+    h->lmap.assign(N_s, -1);
+    if (o.candidates) {
+        if (o.n_candidates < 1 || o.n_candidates > N_s) {
+            delete h;
+            return OED_E_ARG;
+        }
+        h->cmap.assign(o.candidates, o.candidates + o.n_candidates);
+        std::sort(h->cmap.begin(), h->cmap.end());
+        for (size_t q = 0; q < h->cmap.size(); ++q)
+            if (h->cmap[q] < 0 || h->cmap[q] >= N_s || (q > 0 && h->cmap[q] == h->cmap[q - 1])) {
+                delete h;
+                return OED_E_ARG;
+            }
+    } else {
+        h->cmap.resize(N_s);
+        for (int q = 0; q < N_s; ++q) h->cmap[q] = q;
+    }
+    h->N_c = (int)h->cmap.size();
+    for (int q = 0; q < h->N_c; ++q) h->lmap[h->cmap[q]] = q;
+
+    oed_status st = OED_OK;
+    auto setup = [&]() -> oed_status {
+        HIPCHK(h, hipGetDevice(&h->device));
+        const int64_t bs = (int64_t)h->N_tp * h->N_tp;
+        const int64_t nblk = (int64_t)h->N_c * (h->N_c + 1) / 2;
+        HIPCHK(h, dmalloc(h, &h->R, (size_t)(nblk * bs) * relem(h)));
+        HIPCHK(h, dmalloc(h, &h->W, (size_t)(h->N_c * bs) * (h->wtype == W_F64 ? 8 : 4)));
+        HIPCHK(h, dmalloc(h, (void **)&h->Linv, sizeof(double) * bs));
+        HIPCHK(h, dmalloc(h, (void **)&h->gains, sizeof(double) * h->N_c));
+        HIPCHK(h, dmalloc(h, (void **)&h->pick_gain, sizeof(double) * h->N_c));
+        HIPCHK(h, dmalloc(h, (void **)&h->act[0], sizeof(int) * h->N_c));
+        HIPCHK(h, dmalloc(h, (void **)&h->act[1], sizeof(int) * h->N_c));
+        HIPCHK(h, dmalloc(h, (void **)&h->picks, sizeof(int) * h->N_c));
+        HIPCHK(h, dmalloc(h, (void **)&h->state, sizeof(int) * ST_WORDS));
+        HIPCHK(h, dmalloc(h, (void **)&h->dcmap, sizeof(int) * h->N_c));
+        const int64_t tri = (int64_t)h->N_t * (h->N_t + 1) / 2;
+        if (gain_lds_bytes(h->N_t) == 0)
+            HIPCHK(h, dmalloc(h, (void **)&h->scratch_gain, sizeof(double) * tri * h->N_c));
+        if (pick_lds_bytes(h->N_t) == 0)
+            HIPCHK(h, dmalloc(h, (void **)&h->scratch_pick, sizeof(double) * tri * 2));
+        HIPCHK(h, hipMemcpyAsync(h->dcmap, h->cmap.data(), sizeof(int) * h->N_c, hipMemcpyHostToDevice, h->stream));
+        oed_status s2 = load_R(h, K);
+        if (s2 != OED_OK) return s2;
+        HIPCHK(h, hipStreamSynchronize(h->stream));
+        collect_profile(h);
+        return OED_OK;
+    };
+    st = setup();
+    if (st != OED_OK) {
+        free_all(h);
+        delete h;
+        return st;
+    }
+    *out = h;
+    return OED_OK;
+}
+
+oed_status oed_reset(oed_ctx *h, const void *K)
+{
+    if (!h) return OED_E_ARG;
+    if (!K) return fail(h, OED_E_ARG, "K is NULL");
+    oed_status st = load_R(h, K);
+    if (st != OED_OK) return st;
+    HIPCHK(h, hipStreamSynchronize(h->stream));
+    collect_profile(h);
+    return OED_OK;
+}
+
+oed_status oed_greedy(oed_ctx *h, int32_t budget, int32_t *idx_out, double *gain_out, int32_t *n_out)
+{
+    if (!h) return OED_E_ARG;
+    if (n_out) *n_out = 0;
+    if (h->poisoned) return fail(h, OED_E_STATE, "handle stopped after a non-positive-definite step; reset it");
+    if (budget < 0 || budget > h->n_act) return fail(h, OED_E_ARG, "budget out of range");
+    if (budget > 0 && (!idx_out || !gain_out)) return fail(h, OED_E_ARG, "NULL output array");
+    const int k0 = h->k;
+    for (int step = 0; step < budget; ++step) {
+        oed_status st = flush_pending(h);
+        if (st == OED_OK) st = enqueue_gains(h);
+        if (st == OED_OK) st = enqueue_pick(h, -1);
+        if (st != OED_OK) return st;
+    }
+    oed_status dev = OED_OK;
+    oed_status st = sync_picks(h, k0, &dev);
+    if (st != OED_OK) return st;
+    const int made = h->k - k0;
+    for (int q = 0; q < made; ++q) {
+        idx_out[q] = h->cmap[h->h_picks[k0 + q]];
+        gain_out[q] = h->h_gains[k0 + q];
+    }
+    if (n_out) *n_out = made;
+    if (dev == 2) return fail(h, OED_E_NOT_SPD, "every remaining candidate has a non-positive-definite Schur block");
+    if (dev != 0) return fail(h, OED_E_STATE, "device reported status " + std::to_string((int)dev));
+    return OED_OK;
+}
+
+oed_status oed_force(oed_ctx *h, int32_t idx, double *gain_out)
+{
+    if (!h) return OED_E_ARG;
+    if (h->poisoned) return fail(h, OED_E_STATE, "handle stopped; reset it");
+    if (idx < 0 || idx >= h->N_s || h->lmap[idx] < 0 || h->picked[h->lmap[idx]])
+        return fail(h, OED_E_ARG, "index is not a remaining candidate");
+    const int k0 = h->k;
+    oed_status st = flush_pending(h);
+    if (st == OED_OK) st = enqueue_pick(h, h->lmap[idx]);
+    if (st != OED_OK) return st;
+    oed_status dev = OED_OK;
+    st = sync_picks(h, k0, &dev);
+    if (st != OED_OK) return st;
+    if (dev == 2) return fail(h, OED_E_NOT_SPD, "Schur block of the forced sensor is not positive definite");
+    if (dev != 0) return fail(h, OED_E_STATE, "device reported status " + std::to_string((int)dev));
+    if (gain_out) *gain_out = h->h_gains.back();
+    return OED_OK;
+}
+
+oed_status oed_scores(oed_ctx *h, double *out)
+{
+    if (!h || !out) return OED_E_ARG;
+    if (h->poisoned) return fail(h, OED_E_STATE, "handle stopped; reset it");
+    for (int q = 0; q < h->N_s; ++q) out[q] = -INFINITY;
+    if (h->n_act == 0) return OED_OK;
+    oed_status st = flush_pending(h);
+    if (st == OED_OK) st = enqueue_gains(h);
+    if (st != OED_OK) return st;
+    std::vector<double> g(h->n_act);
+    std::vector<int> act(h->n_act);
+    HIPCHK(h, hipMemcpyAsync(g.data(), h->gains, sizeof(double) * h->n_act, hipMemcpyDeviceToHost, h->stream));
+    HIPCHK(h, hipMemcpyAsync(act.data(), h->act[h->cur], sizeof(int) * h->n_act, hipMemcpyDeviceToHost, h->stream));
+    HIPCHK(h, hipStreamSynchronize(h->stream));
+    collect_profile(h);
+    for (int p = 0; p < h->n_act; ++p) out[h->cmap[act[p]]] = g[p];
+    return OED_OK;
+}
+
+oed_status oed_schur_block(oed_ctx *h, int32_t i, int32_t j, double *out)
+{
+    if (!h || !out) return OED_E_ARG;
+    if (h->poisoned) return fail(h, OED_E_STATE, "handle stopped; reset it");
+    if (i < 0 || j < 0 || i >= h->N_s || j >= h->N_s) return fail(h, OED_E_ARG, "index out of range");
+    int li = h->lmap[i], lj = h->lmap[j];
+    if (li < 0 || lj < 0 || h->picked[li] || h->picked[lj]) return fail(h, OED_E_ARG, "not a remaining candidate");
+    oed_status st = flush_pending(h);
+    if (st != OED_OK) return st;
+    const bool tr = li < lj;
+    if (tr) std::swap(li, lj);
+    const int64_t bs = (int64_t)h->N_tp * h->N_tp;
+    const size_t e = relem(h);
+    std::vector<unsigned char> raw((size_t)bs * e);
+    HIPCHK(h, hipMemcpyAsync(raw.data(), (const char *)h->R + (size_t)(blk_index(li, lj) * bs) * e, raw.size(),
+                             hipMemcpyDeviceToHost, h->stream));
+    HIPCHK(h, hipStreamSynchronize(h->stream));
+    collect_profile(h);
+    const int nb = h->N_tp / 16;
+    const bool diag = li == lj;
+    for (int t = 0; t < h->N_t; ++t)
+        for (int u = 0; u < h->N_t; ++u) {
+            // a diagonal block is current on its lower triangle only: mirror it
+            const int o = (diag && u > t) ? acc_off(u, t, nb) : acc_off(t, u, nb);
+            const double v = e == 8 ? ((const double *)raw.data())[o] : (double)((const float *)raw.data())[o];
+            if (tr)
+                out[(size_t)u * h->N_t + t] = v;
+            else
+                out[(size_t)t * h->N_t + u] = v;
+        }
+    return OED_OK;
+}
+
+oed_status oed_picks(oed_ctx *h, int32_t *idx_out, double *gain_out, int32_t *n_out)
+{
+    if (!h || !n_out) return OED_E_ARG;
+    *n_out = (int32_t)h->h_picks.size();
+    for (size_t q = 0; q < h->h_picks.size(); ++q) {
+        if (idx_out) idx_out[q] = h->cmap[h->h_picks[q]];
+        if (gain_out) gain_out[q] = h->h_gains[q];
+    }
+    return OED_OK;
+}
+
+oed_status oed_get_profile(oed_ctx *h, oed_profile *out, int32_t reset)
+{
+    if (!h || !out) return OED_E_ARG;
+    if (!(h->flags & OED_FLAG_PROFILE)) return fail(h, OED_E_STATE, "created without OED_FLAG_PROFILE");
+    HIPCHK(h, hipStreamSynchronize(h->stream));
+    collect_profile(h);
+    for (int c = 0; c < NKC; ++c) {
+        out->ms[c] = h->prof_ms[c];
+        out->launches[c] = h->prof_n[c];
+    }
+    out->syrk_flops = h->syrk_flops;
+    out->syrk_bytes = h->syrk_bytes;
+    if (reset) {
+        for (int c = 0; c < NKC; ++c) {
+            h->prof_ms[c] = 0;
+            h->prof_n[c] = 0;
+        }
+        h->syrk_flops = h->syrk_bytes = 0;
+    }
+    return OED_OK;
+}
+
+oed_status oed_device_bytes(const oed_ctx *h, int64_t *bytes)
+{
+    if (!h || !bytes) return OED_E_ARG;
+    *bytes = h->dev_bytes;
+    return OED_OK;
+}
+
+oed_status oed_destroy(oed_ctx *h)
+{
+    if (!h) return OED_OK;
+    (void)hipStreamSynchronize(h->stream);
+    free_all(h);
+    delete h;
+    return OED_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,249 @@
+"""Thin ctypes binding of liboed (the C ABI in include/oed.h).
+
+Argument marshalling only: every step of the selection runs in the HIP
+kernels of liboed.so.  torch is used for device memory (``K`` is a CUDA/HIP
+tensor whose ``data_ptr()`` is handed over) and for the current stream.  If
+liboed.so has not been built, importing this module raises: there is no
+fallback path.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "liboed.so")
+
+OED_OK, OED_E_ARG, OED_E_NOT_SPD, OED_E_OOM, OED_E_HIP, OED_E_STATE, OED_E_UNSUPPORTED = range(7)
+OED_F64, OED_F32 = 0, 1
+PRECISIONS = {"fp64": 0, "mixed_f32": 1, "mixed_bf16x3": 2}
+OED_FLAG_PROFILE = 1
+KERNELS = ("gain", "pick", "trsm", "syrk", "pack")
+
+
+class oed_options(ctypes.Structure):
+    _fields_ = [("struct_size", ctypes.c_uint32), ("precision", ctypes.c_int32), ("flags", ctypes.c_uint32),
+                ("candidates", ctypes.POINTER(ctypes.c_int32)), ("n_candidates", ctypes.c_int32),
+                ("reserved", ctypes.c_int32 * 7)]
+
+
+class oed_profile(ctypes.Structure):
+    _fields_ = [("ms", ctypes.c_double * 5), ("launches", ctypes.c_int64 * 5), ("syrk_flops", ctypes.c_double),
+                ("syrk_bytes", ctypes.c_double)]
+
+
+class OedError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"{_status_name(status)}: {msg}")
+        self.status = status
+
+
+_lib = None
+
+
+def library() -> ctypes.CDLL:
+    """Load liboed.so (raises if it is missing: build it with __graft_entry__.build())."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"liboed.so not built at {LIB_PATH}; run __graft_entry__.build()")
+    L = ctypes.CDLL(LIB_PATH)
+    vp, ip, dp = ctypes.c_void_p, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_double)
+    L.oed_options_init.argtypes = [ctypes.POINTER(oed_options)]
+    L.oed_options_init.restype = None
+    L.oed_create.argtypes = [ctypes.POINTER(vp), vp, ctypes.c_int32, ctypes.c_int64, ctypes.c_int32, ctypes.c_int32,
+                             ctypes.c_double, vp, ctypes.POINTER(oed_options)]
+    L.oed_reset.argtypes = [vp, vp]
+    L.oed_greedy.argtypes = [vp, ctypes.c_int32, ip, dp, ip]
+    L.oed_force.argtypes = [vp, ctypes.c_int32, dp]
+    L.oed_scores.argtypes = [vp, dp]
+    L.oed_schur_block.argtypes = [vp, ctypes.c_int32, ctypes.c_int32, dp]
+    L.oed_picks.argtypes = [vp, ip, dp, ip]
+    L.oed_get_profile.argtypes = [vp, ctypes.POINTER(oed_profile), ctypes.c_int32]
+    L.oed_device_bytes.argtypes = [vp, ctypes.POINTER(ctypes.c_int64)]
+    L.oed_destroy.argtypes = [vp]
+    L.oed_last_error.argtypes = [vp]
+    L.oed_last_error.restype = ctypes.c_char_p
+    L.oed_status_string.argtypes = [ctypes.c_int32]
+    L.oed_status_string.restype = ctypes.c_char_p
+    for name in ("oed_create", "oed_reset", "oed_greedy", "oed_force", "oed_scores", "oed_schur_block", "oed_picks",
+                 "oed_get_profile", "oed_device_bytes", "oed_destroy"):
+        getattr(L, name).restype = ctypes.c_int32
+    _lib = L
+    return L
+
+
+EXPORTED = ("oed_options_init", "oed_create", "oed_reset", "oed_greedy", "oed_force", "oed_scores",
+            "oed_schur_block", "oed_picks", "oed_get_profile", "oed_device_bytes", "oed_destroy", "oed_last_error",
+            "oed_status_string")
+
+
+def _status_name(s):
+    try:
+        return library().oed_status_string(s).decode()
+    except Exception:  # pragma: no cover - only when the library itself is unusable
+        return f"status {s}"
+
+
+def _check(h, st):
+    if st != OED_OK:
+        msg = library().oed_last_error(h).decode() if h else ""
+        raise OedError(st, msg)
+
+
+def _ip(a):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))
+
+
+def _dp(a):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+def _stream_handle(stream):
+    import torch
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(int(s.cuda_stream))
+
+
+# ------------------------------------------------------------------ functions with the C names
+def oed_create(K, N_s, N_t, sigma2, precision="fp64", candidates=None, profile=False, stream=None):
+    """Create a handle for the device tensor K (2-D, float64/float32, row-major, lower triangle read)."""
+    import torch
+    L = library()
+    if not isinstance(K, torch.Tensor) or not K.is_cuda or K.dim() != 2 or K.stride(1) != 1:
+        raise ValueError("K must be a 2-D row-major device tensor")
+    dtype = {torch.float64: OED_F64, torch.float32: OED_F32}.get(K.dtype)
+    if dtype is None:
+        raise ValueError("K must be float64 or float32")
+    if K.shape[0] < N_s * N_t or K.shape[1] < N_s * N_t:
+        raise ValueError("K must have at least N_s*N_t rows and columns")
+    opt = oed_options()
+    L.oed_options_init(ctypes.byref(opt))
+    opt.precision = PRECISIONS[precision]
+    opt.flags = OED_FLAG_PROFILE if profile else 0
+    cand = None
+    if candidates is not None:
+        cand = np.ascontiguousarray(np.asarray(list(candidates), dtype=np.int32))
+        opt.candidates = _ip(cand)
+        opt.n_candidates = len(cand)
+    h = ctypes.c_void_p()
+    st = L.oed_create(ctypes.byref(h), ctypes.c_void_p(K.data_ptr()), dtype, K.stride(0), int(N_s), int(N_t),
+                      float(sigma2), _stream_handle(stream), ctypes.byref(opt))
+    _check(None, st)
+    return h
+
+
+def oed_reset(h, K):
+    _check(h, library().oed_reset(h, ctypes.c_void_p(K.data_ptr())))
+
+
+def oed_greedy(h, budget, check=True):
+    idx = np.full(max(budget, 1), -1, dtype=np.int32)
+    gain = np.full(max(budget, 1), np.nan)
+    n = ctypes.c_int32()
+    st = library().oed_greedy(h, int(budget), _ip(idx), _dp(gain), ctypes.byref(n))
+    if check:
+        _check(h, st)
+    return idx[:n.value].copy(), gain[:n.value].copy(), st
+
+
+def oed_force(h, idx):
+    g = ctypes.c_double()
+    _check(h, library().oed_force(h, int(idx), ctypes.byref(g)))
+    return g.value
+
+
+def oed_scores(h, N_s):
+    out = np.empty(N_s)
+    _check(h, library().oed_scores(h, _dp(out)))
+    return out
+
+
+def oed_schur_block(h, i, j, N_t):
+    out = np.empty((N_t, N_t))
+    _check(h, library().oed_schur_block(h, int(i), int(j), _dp(out)))
+    return out
+
+
+def oed_picks(h, N_s):
+    idx = np.empty(N_s, dtype=np.int32)
+    gain = np.empty(N_s)
+    n = ctypes.c_int32()
+    _check(h, library().oed_picks(h, _ip(idx), _dp(gain), ctypes.byref(n)))
+    return idx[:n.value].copy(), gain[:n.value].copy()
+
+
+def oed_get_profile(h, reset=False):
+    p = oed_profile()
+    _check(h, library().oed_get_profile(h, ctypes.byref(p), 1 if reset else 0))
+    return {"ms": {k: p.ms[i] for i, k in enumerate(KERNELS)},
+            "launches": {k: int(p.launches[i]) for i, k in enumerate(KERNELS)},
+            "syrk_flops": p.syrk_flops, "syrk_bytes": p.syrk_bytes}
+
+
+def oed_device_bytes(h):
+    b = ctypes.c_int64()
+    _check(h, library().oed_device_bytes(h, ctypes.byref(b)))
+    return b.value
+
+
+def oed_destroy(h):
+    if h:
+        library().oed_destroy(h)
+
+
+# ------------------------------------------------------------------ convenience wrapper
+class Selector:
+    """Owns one handle.  ``Selector(K, N_s, N_t, sigma2).greedy(B)`` -> (indices, gains)."""
+
+    def __init__(self, K, N_s, N_t, sigma2, precision="fp64", candidates=None, profile=False, stream=None):
+        self.N_s, self.N_t = int(N_s), int(N_t)
+        self.h = oed_create(K, N_s, N_t, sigma2, precision, candidates, profile, stream)
+
+    def greedy(self, budget):
+        idx, gain, _ = oed_greedy(self.h, budget)
+        return idx, gain
+
+    def greedy_status(self, budget):
+        return oed_greedy(self.h, budget, check=False)
+
+    def force(self, idx):
+        return oed_force(self.h, idx)
+
+    def scores(self):
+        return oed_scores(self.h, self.N_s)
+
+    def schur_block(self, i, j):
+        return oed_schur_block(self.h, i, j, self.N_t)
+
+    def picks(self):
+        return oed_picks(self.h, self.N_s)
+
+    def reset(self, K):
+        oed_reset(self.h, K)
+
+    def profile(self, reset=False):
+        return oed_get_profile(self.h, reset)
+
+    def device_bytes(self):
+        return oed_device_bytes(self.h)
+
+    def close(self):
+        if self.h:
+            oed_destroy(self.h)
+            self.h = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

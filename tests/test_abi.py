@@ -1,0 +1,79 @@
+"""The C ABI library: it loads, exports every symbol include/oed.h declares, and
+rejects invalid arguments on the host before any HIP call (no GPU needed)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "oed.h")
+
+
+def declared_symbols():
+    text = open(HEADER).read()
+    return sorted(set(re.findall(r"^OED_API\s+[\w\s\*]+?\b(oed_\w+)\s*\(", text, flags=re.M)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    from paper_2604_08812_amd import library
+    return library()
+
+
+def test_header_declares_the_boundary():
+    syms = declared_symbols()
+    for name in ("oed_create", "oed_greedy", "oed_destroy", "oed_last_error", "oed_force", "oed_reset",
+                 "oed_scores", "oed_schur_block", "oed_picks", "oed_get_profile"):
+        assert name in syms
+
+
+def test_every_declared_symbol_is_exported(lib):
+    from paper_2604_08812_amd import EXPORTED
+    syms = declared_symbols()
+    for name in syms:
+        assert hasattr(lib, name), name
+    assert sorted(EXPORTED) == syms
+
+
+def test_host_side_argument_validation(lib):
+    from paper_2604_08812_amd.oed import oed_options
+    opt = oed_options()
+    lib.oed_options_init(ctypes.byref(opt))
+    assert opt.struct_size == ctypes.sizeof(oed_options) and opt.precision == 0
+    h = ctypes.c_void_p()
+    fake = ctypes.c_void_p(0x1000)  # never dereferenced: every call below fails validation first
+    E_ARG = 1
+    assert lib.oed_create(ctypes.byref(h), fake, 0, 64, 4, 16, 0.0, None, ctypes.byref(opt)) == E_ARG
+    assert lib.oed_create(ctypes.byref(h), fake, 0, 64, 4, 16, float("nan"), None, ctypes.byref(opt)) == E_ARG
+    assert lib.oed_create(ctypes.byref(h), fake, 0, 63, 4, 16, 1.0, None, ctypes.byref(opt)) == E_ARG
+    assert lib.oed_create(ctypes.byref(h), fake, 7, 64, 4, 16, 1.0, None, ctypes.byref(opt)) == E_ARG
+    assert lib.oed_create(ctypes.byref(h), None, 0, 64, 4, 16, 1.0, None, ctypes.byref(opt)) == E_ARG
+    assert lib.oed_create(ctypes.byref(h), fake, 0, 64, 0, 16, 1.0, None, ctypes.byref(opt)) == E_ARG
+    bad = oed_options()
+    lib.oed_options_init(ctypes.byref(bad))
+    bad.precision = 9
+    assert lib.oed_create(ctypes.byref(h), fake, 0, 64, 4, 16, 1.0, None, ctypes.byref(bad)) == E_ARG
+    bad = oed_options()
+    lib.oed_options_init(ctypes.byref(bad))
+    bad.struct_size = 4
+    assert lib.oed_create(ctypes.byref(h), fake, 0, 64, 4, 16, 1.0, None, ctypes.byref(bad)) == E_ARG
+    cand = (ctypes.c_int32 * 2)(1, 9)
+    bad = oed_options()
+    lib.oed_options_init(ctypes.byref(bad))
+    bad.candidates = ctypes.cast(cand, ctypes.POINTER(ctypes.c_int32))
+    bad.n_candidates = 2
+    assert lib.oed_create(ctypes.byref(h), fake, 0, 64, 4, 16, 1.0, None, ctypes.byref(bad)) == E_ARG
+    assert not h.value
+    assert lib.oed_greedy(None, 1, None, None, None) == E_ARG
+    assert lib.oed_destroy(None) == 0
+    assert lib.oed_status_string(2) == b"OED_E_NOT_SPD"
+    assert lib.oed_last_error(None) == b"null handle"
+
+
+def test_binding_fails_loudly_without_library(monkeypatch, tmp_path):
+    import paper_2604_08812_amd.oed as b
+    monkeypatch.setattr(b, "_lib", None)
+    monkeypatch.setattr(b, "LIB_PATH", str(tmp_path / "missing.so"))
+    with pytest.raises(ImportError):
+        b.library()

@@ -1,0 +1,209 @@
+"""GPU parity: the HIP path through the C ABI against the CPU oracle.
+
+Each case runs the selection on cuda:0 through liboed and replays the GPU's
+trajectory in the oracle (from-scratch FP64 Cholesky of every candidate test
+matrix).  Sizes span several 128-row tiles with ragged tails and the padded
+block sizes (N_t = 1, 24, 160 are not multiples of 16 or exceed the LDS path).
+"""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from oed_inputs import make_K
+from parity import RTOL, check_trajectory, rel_err
+
+pytestmark = pytest.mark.gpu
+
+DEV = "cuda:0"
+
+
+def selector(*a, **k):
+    from paper_2604_08812_amd import Selector
+    return Selector(*a, **k)
+
+
+def instance(N_s, N_t, n_m, seed, c=0.01):
+    K, s2 = make_K(N_s, N_t, n_m, seed, c)
+    return K.numpy(), K.to(DEV), s2
+
+
+# (N_s, N_t, n_m, seed, budget)
+CASES = [
+    (64, 16, 4096, 0, 16),   # the 64 x 16 FP64 workload, budget 16
+    (37, 16, 1024, 3, 12),   # 592 rows: 5 row tiles, ragged last tile, 8 sensors per tile
+    (20, 128, 4000, 4, 8),   # one sensor per 128-row tile
+    (23, 96, 3000, 5, 8),    # 96-row blocks straddle the 128-row tiles
+    (30, 24, 1500, 6, 10),   # N_t padded 24 -> 32
+    (50, 1, 200, 7, 30),     # N_t = 1 padded to 16
+    (17, 48, 2000, 8, 9),
+    (9, 160, 2000, 9, 5),    # N_t > 128: factorisations in global scratch
+]
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed_f32"])
+@pytest.mark.parametrize("case", CASES, ids=lambda c: "x".join(map(str, c[:2])))
+def test_greedy_matches_oracle(case, prec):
+    N_s, N_t, n_m, seed, B = case
+    print(f"case N_s={N_s} N_t={N_t} seed={seed} B={B} prec={prec}", flush=True)
+    K, Kd, s2 = instance(N_s, N_t, n_m, seed)
+    with selector(Kd, N_s, N_t, s2, precision=prec) as sel:
+        idx, gain = sel.greedy(B)
+    rep = check_trajectory(K, N_s, N_t, s2, idx, gain, RTOL[prec])
+    print(f"  max rel gain err {rep['max_rel_err']:.2e}, near-tie divergences {rep['diverged_steps']}")
+    if prec == "fp64":
+        assert rep["diverged_steps"] == [] or min(rep["ref"]["gap"]) < 1e-9
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed_f32"])
+def test_scores_and_schur_blocks_after_forced_prefix(prec):
+    N_s, N_t = 29, 48
+    K, Kd, s2 = instance(N_s, N_t, 2000, 21)
+    A = [7, 0, 28, 13]
+    rest = [j for j in range(N_s) if j not in A]
+    tol = 1e-11 if prec == "fp64" else 2e-5
+    with selector(Kd, N_s, N_t, s2, precision=prec) as sel:
+        g0 = sel.scores()
+        ref0 = oracle.gains(K, N_t, s2, [], range(N_s))
+        assert np.all(rel_err(g0, ref0) <= RTOL[prec])
+        for a in A:
+            sel.force(a)
+        g = sel.scores()
+        ref = oracle.gains(K, N_t, s2, A, rest)
+        assert np.all(np.isneginf(g[A]))
+        assert np.all(rel_err(g[rest], ref) <= RTOL[prec])
+        S = oracle.schur_complement(K, N_t, A, rest)
+        scale = np.abs(S).max()
+        for (i, j) in [(1, 1), (27, 3), (3, 27), (20, 19), (27, 27), (14, 12), (2, 1)]:
+            blk = sel.schur_block(i, j)
+            pi, pj = rest.index(i), rest.index(j)
+            ref_blk = S[pi * N_t:(pi + 1) * N_t, pj * N_t:(pj + 1) * N_t]
+            assert np.abs(blk - ref_blk).max() <= tol * scale, (i, j)
+
+
+def test_exact_ties_go_to_lowest_index():
+    N_s, N_t, c, s2 = 40, 16, 3.0, 0.02
+    K = c * torch.eye(N_s * N_t, dtype=torch.float64)
+    for prec in ("fp64", "mixed_f32"):
+        with selector(K.to(DEV), N_s, N_t, s2, precision=prec) as sel:
+            idx, gain = sel.greedy(12)
+        assert list(idx) == list(range(12))
+        np.testing.assert_allclose(gain, 0.5 * N_t * math.log(c / s2), rtol=1e-12)
+
+
+def test_non_pd_and_nan_candidates_are_never_picked():
+    N_s, N_t = 12, 16
+    K, s2 = make_K(N_s, N_t, 500, 31)
+    K = K.clone()
+    K[5 * N_t:6 * N_t, :] = 0.0      # sensor 5: zero block row (its Schur block stays 0)
+    K[:, 5 * N_t:6 * N_t] = 0.0
+    K[3 * N_t + 2, 3 * N_t + 1] = float("nan")   # sensor 3: NaN inside its diagonal block
+    K[8 * N_t + 4, 0 * N_t + 7] = float("nan")   # sensor 8: NaN in its block column of sensor 0
+    Kn = K.numpy()
+    g_ref = oracle.gains(Kn, N_t, s2, [], range(N_s))
+    assert np.isneginf(g_ref[5]) and np.isneginf(g_ref[3])
+    ref = oracle.greedy(Kn, N_s, N_t, s2, N_s, raise_on_error=False)
+    assert ref["status"] == 2
+    # sensors 3 and 5 are never finite; once one of 0 and 8 is picked the other turns non-finite
+    assert not ({3, 5} & set(ref["idx"].tolist())) and len({0, 8} & set(ref["idx"].tolist())) == 1
+    for prec in ("fp64", "mixed_f32"):
+        with selector(K.to(DEV), N_s, N_t, s2, precision=prec) as sel:
+            g = sel.scores()
+            assert np.isneginf(g[5]) and np.isneginf(g[3]) and np.isfinite(g[8])
+            idx, gain, st = sel.greedy_status(N_s)
+        assert st == 2  # OED_E_NOT_SPD once only non-PD candidates remain
+        assert list(idx) == list(ref["idx"])
+        assert np.all(rel_err(gain, ref["gain"]) <= RTOL[prec])
+
+
+def test_upper_triangle_is_not_read():
+    N_s, N_t = 21, 32
+    K, s2 = make_K(N_s, N_t, 900, 41)
+    Kn = K.clone()
+    iu = torch.triu_indices(N_s * N_t, N_s * N_t, 1)
+    Kn[iu[0], iu[1]] = float("nan")
+    for prec in ("fp64", "mixed_f32"):
+        with selector(K.to(DEV), N_s, N_t, s2, precision=prec) as a, \
+                selector(Kn.to(DEV), N_s, N_t, s2, precision=prec) as b:
+            ia, ga = a.greedy(8)
+            ib, gb = b.greedy(8)
+        assert list(ia) == list(ib)
+        np.testing.assert_array_equal(ga, gb)
+
+
+def test_candidate_subset():
+    N_s, N_t = 45, 16
+    K, Kd, s2 = instance(N_s, N_t, 1500, 51)
+    cand = [44, 3, 17, 29, 8, 12, 40, 0, 21, 33, 5]
+    for prec in ("fp64", "mixed_f32"):
+        with selector(Kd, N_s, N_t, s2, precision=prec, candidates=cand) as sel:
+            idx, gain = sel.greedy(6)
+        assert set(idx.tolist()) <= set(cand)
+        check_trajectory(K, N_s, N_t, s2, idx, gain, RTOL[prec], candidates=cand)
+
+
+def test_force_then_greedy_and_split_calls():
+    N_s, N_t = 33, 32
+    K, Kd, s2 = instance(N_s, N_t, 1200, 61)
+    with selector(Kd, N_s, N_t, s2) as a:
+        ga = [a.force(5), a.force(2)]
+        idx, gain = a.greedy(6)
+    ref = oracle.greedy(K, N_s, N_t, s2, 8, prefix=[5, 2])
+    assert list(ref["idx"][2:]) == list(idx)
+    assert np.all(rel_err(np.r_[ga, gain], ref["gain"]) <= 1e-10)
+    with selector(Kd, N_s, N_t, s2) as b, selector(Kd, N_s, N_t, s2) as c:
+        i1, g1 = b.greedy(3)
+        i2, g2 = b.greedy(5)
+        i3, g3 = c.greedy(8)
+        pi, pg = b.picks()
+    assert list(np.r_[i1, i2]) == list(i3) == list(pi)
+    np.testing.assert_array_equal(np.r_[g1, g2], g3)
+    np.testing.assert_array_equal(pg, g3)
+
+
+def test_reset_reproduces_bitwise():
+    N_s, N_t = 40, 64
+    _, Kd, s2 = instance(N_s, N_t, 3000, 71)
+    for prec in ("fp64", "mixed_f32"):
+        with selector(Kd, N_s, N_t, s2, precision=prec) as sel:
+            i1, g1 = sel.greedy(10)
+            sel.reset(Kd)
+            i2, g2 = sel.greedy(10)
+        assert list(i1) == list(i2)
+        np.testing.assert_array_equal(g1, g2)
+
+
+def test_float32_input_matrix():
+    N_s, N_t = 26, 32
+    K, s2 = make_K(N_s, N_t, 1500, 81)
+    K32 = K.to(torch.float32)
+    with selector(K32.to(DEV), N_s, N_t, s2, precision="mixed_f32") as sel:
+        idx, gain = sel.greedy(7)
+    check_trajectory(K32.to(torch.float64).numpy(), N_s, N_t, s2, idx, gain, RTOL["mixed_f32"])
+
+
+def test_errors_and_states():
+    from paper_2604_08812_amd import OedError
+    N_s, N_t = 10, 16
+    _, Kd, s2 = instance(N_s, N_t, 300, 91)
+    with selector(Kd, N_s, N_t, s2) as sel:
+        with pytest.raises(OedError):
+            sel.greedy(11)
+        sel.greedy(4)
+        with pytest.raises(OedError):
+            sel.greedy(7)          # only 6 remain
+        picked = sel.picks()[0]
+        with pytest.raises(OedError):
+            sel.force(int(picked[0]))   # already picked
+        with pytest.raises(OedError):
+            sel.schur_block(int(picked[0]), 0)
+        idx, gain = sel.greedy(6)   # exactly the rest
+        assert len(idx) == 6
+        g = sel.scores()
+        assert np.all(np.isneginf(g))
+    with pytest.raises(OedError):
+        selector(Kd, N_s, N_t, -1.0)
+    with pytest.raises(OedError):
+        selector(Kd, N_s, N_t, s2, candidates=[1, 1, 2])
