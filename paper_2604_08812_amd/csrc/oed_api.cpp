@@ -36,6 +36,7 @@ struct oed_ctx {
     double sigma2 = 0, half_noise = 0;
     int prec = OED_PREC_FP64;
     int rtype = R_F64, wtype = W_F64;
+    int syrk_variant = SYRK_LDS;
     uint32_t flags = 0;
     hipStream_t stream = nullptr;
     int device = 0;
@@ -148,7 +149,7 @@ oed_status load_R(oed_ctx *h, const void *K)
         Prof pr(h, OED_K_PACK);
         HIPCHK(h, launch_pack(K, h->kdtype, h->ld, h->N_t, h->N_tp, h->dcmap, h->N_c, h->R, h->rtype, h->stream));
     }
-    HIPCHK(h, launch_init_state(h->act[0], h->N_c, h->pick_gain, h->picks, h->state, h->stream));
+    HIPCHK(h, launch_init_state(h->act[0], h->N_c, h->state, h->stream));
     h->cur = 0;
     h->n_act = h->N_c;
     h->k = 0;
@@ -160,20 +161,45 @@ oed_status load_R(oed_ctx *h, const void *K)
     return OED_OK;
 }
 
+// Descriptor of the handle's current state (see StepDesc).
+StepDesc desc(const oed_ctx *h)
+{
+    StepDesc d{};
+    d.R = h->R;
+    d.W = h->W;
+    d.act_in = h->act[h->cur];
+    d.act_out = h->act[h->cur ^ 1];
+    d.gains = h->gains;
+    d.Linv = h->Linv;
+    d.state = h->state;
+    d.picks = h->picks;
+    d.pick_gain = h->pick_gain;
+    d.half_noise = h->half_noise;
+    d.n_act = h->n_act;
+    d.N_t = h->N_t;
+    d.N_tp = h->N_tp;
+    d.step = h->k;
+    d.forced = -1;
+    d.item0 = 0;
+    d.nitems = h->n_act;
+    return d;
+}
+
 // Enqueue the downdate of the last pick if it has not been applied.
 oed_status flush_pending(oed_ctx *h)
 {
     if (!h->pending) return OED_OK;
     h->pending = false;
     if (h->n_act == 0) return OED_OK;
+    StepDesc d = desc(h);
     {
         Prof pr(h, OED_K_TRSM);
-        HIPCHK(h, launch_trsm(h->R, h->rtype, h->act[h->cur], h->n_act, h->state, h->Linv, h->N_tp, h->W, h->wtype,
-                              h->stream));
+        HIPCHK(h, launch_trsm(d, h->rtype, h->wtype, h->stream));
     }
+    d.nitems = syrk_tiles(h->n_act, h->N_tp);
     {
         Prof pr(h, OED_K_SYRK);
-        HIPCHK(h, launch_syrk(h->R, h->rtype, h->W, h->wtype, h->act[h->cur], h->n_act, h->N_tp, h->state, h->stream));
+        HIPCHK(h, launch_syrk(d, h->rtype, h->wtype, h->syrk_variant, h->stream));
     }
     const double n = (double)h->n_act * h->N_t;
     h->syrk_flops += (double)h->N_t * n * (n + 1.0);
@@ -183,19 +209,22 @@ oed_status flush_pending(oed_ctx *h)
 
 oed_status enqueue_gains(oed_ctx *h)
 {
+    StepDesc d = desc(h);
+    d.scratch = h->scratch_gain;
     Prof pr(h, OED_K_GAIN);
-    HIPCHK(h, launch_gain(h->R, h->rtype, h->act[h->cur], h->n_act, h->N_t, h->N_tp, h->half_noise, h->gains, h->state,
-                          h->scratch_gain, h->stream));
+    HIPCHK(h, launch_gain(d, h->rtype, h->stream));
     return OED_OK;
 }
 
 oed_status enqueue_pick(oed_ctx *h, int forced_local)
 {
+    StepDesc d = desc(h);
+    d.scratch = h->scratch_pick;
+    d.forced = forced_local;
+    d.nitems = 1;
     {
         Prof pr(h, OED_K_PICK);
-        HIPCHK(h, launch_pick(h->R, h->rtype, h->act[h->cur], h->act[h->cur ^ 1], h->n_act, h->gains, h->N_t, h->N_tp,
-                              h->half_noise, h->k, forced_local, h->picks, h->pick_gain, h->state, h->Linv,
-                              h->scratch_pick, h->stream));
+        HIPCHK(h, launch_pick(d, h->rtype, h->stream));
     }
     h->cur ^= 1;
     h->n_act -= 1;
@@ -333,9 +362,9 @@ oed_status oed_create(oed_ctx **out, const void *K, int32_t dtype, int64_t ld, i
         HIPCHK(h, dmalloc(h, (void **)&h->state, sizeof(int) * ST_WORDS));
         HIPCHK(h, dmalloc(h, (void **)&h->dcmap, sizeof(int) * h->N_c));
         const int64_t tri = (int64_t)h->N_t * (h->N_t + 1) / 2;
-        if (gain_lds_bytes(h->N_t) == 0)
+        if (h->N_t > REGS_MAX_NT && gain_lds_bytes(h->N_t) == 0)
             HIPCHK(h, dmalloc(h, (void **)&h->scratch_gain, sizeof(double) * tri * h->N_c));
-        if (pick_lds_bytes(h->N_t) == 0)
+        if (h->N_t > REGS_MAX_NT && pick_lds_bytes(h->N_t) == 0)
             HIPCHK(h, dmalloc(h, (void **)&h->scratch_pick, sizeof(double) * tri * 2));
         HIPCHK(h, hipMemcpyAsync(h->dcmap, h->cmap.data(), sizeof(int) * h->N_c, hipMemcpyHostToDevice, h->stream));
         oed_status s2 = load_R(h, K);

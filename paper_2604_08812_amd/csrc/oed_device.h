@@ -1,0 +1,90 @@
+// Device-side helpers shared by the liboed kernel units: vector types, the 16x16x4 MFMA
+// wrappers, vector loads/stores, triangular index maths and the batched-launch lookup.
+#pragma once
+#include <math.h>
+
+#include "oed_internal.h"
+
+namespace oed {
+
+typedef float floatx4 __attribute__((ext_vector_type(4)));
+typedef double doublex4 __attribute__((ext_vector_type(4)));
+
+template <typename T>
+struct V4;
+template <>
+struct V4<float> {
+    typedef floatx4 type;
+};
+template <>
+struct V4<double> {
+    typedef doublex4 type;
+};
+
+__device__ __forceinline__ floatx4 mfma16(float a, float b, floatx4 c)
+{
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+}
+__device__ __forceinline__ doublex4 mfma16(double a, double b, doublex4 c)
+{
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+
+// Lane whose stored operand row the A operand of `lane` must carry.  The FP32 16x16x4 MFMA
+// returns output row m of a 16x16 block at lane 16*(m/4) + n, register m%4; the FP64 one at
+// lane 16*(m%4) + n, register m/4.  Feeding the FP64 A operand the rows in the order
+// pi(r) = 4*(r%4) + r/4 (an involution) makes both land in the same accumulator storage order.
+template <typename T>
+__device__ __forceinline__ int a_lane(int lane)
+{
+    return lane;
+}
+template <>
+__device__ __forceinline__ int a_lane<double>(int lane)
+{
+    return (lane & 48) | ((lane & 3) << 2) | ((lane & 15) >> 2);
+}
+
+template <typename T>
+__device__ __forceinline__ typename V4<T>::type ld4(const T *p)
+{
+    return *reinterpret_cast<const typename V4<T>::type *>(p);
+}
+template <typename T>
+__device__ __forceinline__ void st4(T *p, typename V4<T>::type v)
+{
+    *reinterpret_cast<typename V4<T>::type *>(p) = v;
+}
+
+// Row of the packed lower triangle: element (t, u), u <= t, at tri(t) + u.
+__device__ __forceinline__ int tri(int t) { return t * (t + 1) / 2; }
+
+// Largest i with i(i+1)/2 <= b.
+__device__ __forceinline__ int64_t tri_row(int64_t b)
+{
+    int64_t i = (int64_t)((sqrt(8.0 * (double)b + 1.0) - 1.0) * 0.5);
+    while ((i + 1) * (i + 2) / 2 <= b) ++i;
+    while (i * (i + 1) / 2 > b) --i;
+    return i;
+}
+
+// Instance of a batched launch that owns work item `item`: the last descriptor with
+// item0 <= item (descriptors are sorted by item0).  -1 if the item is past its instance's end.
+__device__ __forceinline__ int find_instance(const StepDesc *ds, int n, int64_t item)
+{
+    int lo = 0, hi = n - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (ds[mid].item0 <= item)
+            lo = mid;
+        else
+            hi = mid - 1;
+    }
+    return item < ds[lo].item0 + ds[lo].nitems ? lo : -1;
+}
+
+// Work-group id -> work item, XCD by XCD: work-group g runs on XCD g % 8, and the items are
+// handed out so that each XCD processes one contiguous eighth of them.
+__device__ __forceinline__ int64_t xcd_item(int64_t wg, int64_t per_xcd) { return (wg & 7) * per_xcd + (wg >> 3); }
+
+}  // namespace oed

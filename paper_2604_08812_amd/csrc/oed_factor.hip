@@ -1,0 +1,571 @@
+// FP64 factorisation kernels of one greedy step: the gains of all remaining candidates (a
+// Cholesky of every diagonal block R_jj, i.e. of every matrix M_j of Algorithm 1, Sec. III-D),
+// and the pick (argmax with lowest-index ties, active-list update, factor of the winner and
+// its inverse).  Register-resident kernels serve N_t <= REGS_MAX_NT; LDS (or global-scratch)
+// kernels serve larger blocks.
+#include <algorithm>
+
+#include "oed_device.h"
+
+namespace oed {
+
+// ---------------------------------------------------------------------------------------------
+// FP64 factorisation helpers (whole work-group; A is a packed lower triangle).
+
+// Load the real N_t x N_t lower part of a diagonal block of R (accumulator order) into A.
+template <typename TR>
+__device__ void load_diag_block(const TR *__restrict__ Rb, int N_t, int N_tp, double *A)
+{
+    const int nb = N_tp >> 4;
+    const int n2 = N_tp * N_tp;
+    for (int o = threadIdx.x; o < n2; o += blockDim.x) {
+        const int sb = o >> 8, w = o & 255, lane = w >> 2, reg = w & 3;
+        const int t = (sb / nb) * 16 + ((lane >> 4) << 2) + reg;
+        const int u = (sb % nb) * 16 + (lane & 15);
+        if (t < N_t && u <= t) A[tri(t) + u] = (double)Rb[o];
+    }
+}
+
+// Right-looking Cholesky in place (A -> L).  Returns sum_t ln L_tt in every thread,
+// or -inf as soon as a pivot is not > 0 or not finite.  blockDim.x must be 256.
+__device__ double chol_packed(double *A, int n)
+{
+    double logsum = 0.0;
+    const int tr = threadIdx.x >> 4, tc = threadIdx.x & 15;
+    for (int j = 0; j < n; ++j) {
+        __syncthreads();
+        const int jj = tri(j) + j;
+        const double d = A[jj];
+        if (!(d > 0.0) || !isfinite(d)) return -INFINITY;
+        const double l = sqrt(d);
+        logsum += log(l);
+        for (int t = j + 1 + (int)threadIdx.x; t < n; t += blockDim.x) A[tri(t) + j] /= l;
+        __syncthreads();
+        if (threadIdx.x == 0) A[jj] = l;
+        for (int t = j + 1 + tr; t < n; t += 16) {
+            double *At = A + tri(t);
+            const double ltj = At[j];
+            for (int u = j + 1 + tc; u <= t; u += 16) At[u] -= ltj * A[tri(u) + j];
+        }
+    }
+    __syncthreads();
+    return logsum;
+}
+
+// X = L^-1 for the packed lower factor L (both packed lower, n x n).
+__device__ void tri_inverse(const double *L, double *X, int n)
+{
+    const int m = tri(n);
+    for (int o = threadIdx.x; o < m; o += blockDim.x) X[o] = 0.0;
+    __syncthreads();
+    for (int t = threadIdx.x; t < n; t += blockDim.x) X[tri(t) + t] = 1.0;
+    __syncthreads();
+    for (int j = 0; j < n; ++j) {
+        const double ljj = L[tri(j) + j];
+        double *Xj = X + tri(j);
+        for (int c = threadIdx.x; c <= j; c += blockDim.x) Xj[c] /= ljj;
+        __syncthreads();
+        const int w = j + 1, total = (n - j - 1) * w;
+        for (int f = threadIdx.x; f < total; f += blockDim.x) {
+            const int i = j + 1 + f / w, c = f - (f / w) * w;
+            X[tri(i) + c] -= L[tri(i) + j] * Xj[c];
+        }
+        __syncthreads();
+    }
+}
+
+// ---------------------------------------------------------------------------------------------
+// Register-resident FP64 factorisations for N_t <= 128 (work-group of 256 threads).
+//
+// Ownership: thread (wave w, lane l, g = l/16) holds the 16x16 sub-block rows I in {w, 7-w}
+// (so every wave gets the same share of the lower triangle) and, in sub-block (I, J), J <= I,
+// the four accumulator-order elements (16I + 4g + r, 16J + l%16), r = 0..3 -- the same order
+// R is stored in, so a diagonal block is loaded with one vector access per sub-block.
+//
+// Right-looking Cholesky, one barrier per column j: the owners of column j publish it
+// (unscaled, a_t = A[t][j]) in a double-buffered LDS vector; every thread then reads the pivot
+// d = a_j and applies A[t][u] -= a_t a_u / d to the elements it owns with t, u > j.  The
+// pivots are kept; sum_t ln L_tt = 1/2 sum_j ln d_j.
+template <typename TR>
+__device__ bool chol_regs(const TR *__restrict__ Rb, int N_t, int nb, double *colbuf, double *piv, double *Lout)
+{
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6, g = lane >> 4, l16 = lane & 15;
+    const int nbr = (N_t + 15) >> 4;
+    double A[2][8][4];
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+        const int I = h ? 7 - w : w;
+#pragma unroll
+        for (int J = 0; J < 8; ++J) {
+            if (I < nbr && J <= I) {
+                const typename V4<TR>::type v = ld4(Rb + ((I * nb + J) << 8) + lane * 4);
+#pragma unroll
+                for (int r = 0; r < 4; ++r) A[h][J][r] = (double)v[r];
+            } else {
+#pragma unroll
+                for (int r = 0; r < 4; ++r) A[h][J][r] = 0.0;
+            }
+        }
+    }
+    for (int j = 0; j < N_t; ++j) {
+        const int jb = j >> 4, jl = j & 15;
+        double *buf = colbuf + ((j & 1) << 7);
+        if (l16 == jl) {
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+                const int I = h ? 7 - w : w;
+                if (I < nbr && I >= jb) {
+#pragma unroll
+                    for (int J = 0; J < 8; ++J)
+                        if (J == jb) {
+#pragma unroll
+                            for (int r = 0; r < 4; ++r) buf[16 * I + 4 * g + r] = A[h][J][r];
+                        }
+                }
+            }
+        }
+        __syncthreads();
+        const double d = buf[j];
+        if (!(d > 0.0) || !isfinite(d)) return false;
+        if (tid == 0) piv[j] = d;
+        if (Lout) {
+            const double l = sqrt(d), il = 1.0 / l;
+            for (int t = j + tid; t < N_t; t += blockDim.x) Lout[tri(t) + j] = t == j ? l : buf[t] * il;
+        }
+        const double inv_d = 1.0 / d;
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            const int I = h ? 7 - w : w;
+            if (I < nbr && I >= jb) {
+                double wt[4];
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const int t = 16 * I + 4 * g + r;
+                    wt[r] = t > j ? buf[t] * inv_d : 0.0;
+                }
+                // branch-free over J: sub-blocks left of column j or above the diagonal get au = 0
+#pragma unroll
+                for (int J = 0; J < 8; ++J) {
+                    const int u = 16 * J + l16;
+                    const double au = (u > j && J <= I) ? buf[u] : 0.0;
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) A[h][J][r] = fma(-wt[r], au, A[h][J][r]);
+                }
+            }
+        }
+    }
+    __syncthreads();
+    return true;
+}
+
+// 1/2 sum_{j < n} ln piv[j] (n <= 256), the same value in every thread (fixed reduction order).
+__device__ double half_sum_log(const double *piv, int n, double *red)
+{
+    const int tid = threadIdx.x, lane = tid & 63;
+    double v = tid < n ? log(piv[tid]) : 0.0;
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+    if (lane == 0) red[tid >> 6] = v;
+    __syncthreads();
+    const double t = (red[0] + red[1]) + (red[2] + red[3]);
+    __syncthreads();
+    return 0.5 * t;
+}
+
+// Inverse X = L^-1 of the packed lower factor in LDS, register-resident with the ownership of
+// chol_regs (rowbuf: LDS, 2 x 4 x 128 doubles).  Row-oriented elimination: row j of X, once all earlier rows have been subtracted
+// from it, equals L_jj times its final value; its owners publish it and every thread applies
+// X[t][c] -= (L[t][j] / L_jj) X[j][c] for t > j.  Rows are divided by their L_tt at the end.
+// The result goes to global memory in operand order (N_tp x N_tp, identity on the padding).
+__device__ void inverse_regs(const double *Lout, int N_t, int N_tp, double *rowbuf, double *__restrict__ Linv)
+{
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6, g = lane >> 4, l16 = lane & 15;
+    const int nbr = (N_t + 15) >> 4, nb = N_tp >> 4;
+    double X[2][8][4];
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+        const int I = h ? 7 - w : w;
+#pragma unroll
+        for (int J = 0; J < 8; ++J)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) X[h][J][r] = (J == I && 4 * g + r == l16) ? 1.0 : 0.0;
+    }
+    for (int j = 0; j < N_t; ++j) {
+        const int jb = j >> 4;
+        // the owners of row j (lanes of group g = (j%16)/4, register j%4) publish all four of
+        // their rows, so no register is selected by a run-time index; readers take slot j%4
+        double *rb = rowbuf + ((j & 1) << 9);
+        if (g == ((j & 15) >> 2)) {
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+                const int I = h ? 7 - w : w;
+                if (I == jb) {
+#pragma unroll
+                    for (int J = 0; J < 8; ++J)
+                        if (J <= jb) {
+#pragma unroll
+                            for (int r = 0; r < 4; ++r) rb[(r << 7) + 16 * J + l16] = X[h][J][r];
+                        }
+                }
+            }
+        }
+        __syncthreads();
+        const double *rj = rb + ((j & 3) << 7);
+        const double inv_ljj = 1.0 / Lout[tri(j) + j];
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            const int I = h ? 7 - w : w;
+            if (I < nbr && I >= jb) {
+                double lt[4];
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const int t = 16 * I + 4 * g + r;
+                    lt[r] = (t > j && t < N_t) ? Lout[tri(t) + j] * inv_ljj : 0.0;
+                }
+#pragma unroll
+                for (int J = 0; J < 8; ++J) {
+                    const double xc = (J <= jb && J <= I) ? rj[16 * J + l16] : 0.0;
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) X[h][J][r] = fma(-lt[r], xc, X[h][J][r]);
+                }
+            }
+        }
+    }
+    // sub-blocks outside the factored part: zero above the diagonal, identity on the padding
+    for (int o = tid; o < N_tp * N_tp; o += blockDim.x) {
+        const int sb = o >> 8, ww = o & 255, ln = ww >> 2, reg = ww & 3;
+        const int I = sb / nb, J = sb % nb;
+        if (I >= nbr || J >= nbr || J > I) {
+            const int k = I * 16 + (ln & 15), kp = J * 16 + ((ln >> 4) << 2) + reg;
+            Linv[o] = k == kp ? 1.0 : 0.0;
+        }
+    }
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+        const int I = h ? 7 - w : w;
+        if (I < nbr) {
+            double il[4];
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int t = 16 * I + 4 * g + r;
+                il[r] = t < N_t ? 1.0 / Lout[tri(t) + t] : 1.0;
+            }
+#pragma unroll
+            for (int J = 0; J < 8; ++J)
+                if (J <= I) {
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) {
+                        const int t = 4 * g + r, c = l16;  // row / column inside sub-block (I, J)
+                        Linv[((I * nb + J) << 8) + ((((c >> 2) << 4) + t) << 2) + (c & 3)] = X[h][J][r] * il[r];
+                    }
+                }
+        }
+    }
+}
+
+// Argmax of the gains (exact ties -> lowest position, NaN -> -inf) or the position of a forced
+// sensor.  Returns the position (same in all threads) or -1 after setting the status word.
+__device__ int select_winner(const int *__restrict__ act_in, int n_act, const double *__restrict__ gains,
+                             int forced, int *state, double *gain_out)
+{
+    __shared__ double red_g[4];
+    __shared__ int red_p[4];
+    const int tid = threadIdx.x;
+    double bg = -INFINITY;
+    int bp = 0x7fffffff;
+    if (forced < 0) {
+        for (int p = tid; p < n_act; p += blockDim.x) {
+            double v = gains[p];
+            if (isnan(v)) v = -INFINITY;
+            if (v > bg || (v == bg && p < bp)) {
+                bg = v;
+                bp = p;
+            }
+        }
+    } else {
+        for (int p = tid; p < n_act; p += blockDim.x)
+            if (act_in[p] == forced) {
+                bg = 0.0;
+                bp = p;
+            }
+    }
+    for (int off = 32; off > 0; off >>= 1) {
+        const double og = __shfl_xor(bg, off);
+        const int op = __shfl_xor(bp, off);
+        if (og > bg || (og == bg && op < bp)) {
+            bg = og;
+            bp = op;
+        }
+    }
+    if ((tid & 63) == 0) {
+        red_g[tid >> 6] = bg;
+        red_p[tid >> 6] = bp;
+    }
+    __syncthreads();
+    double gsel = red_g[0];
+    int q = red_p[0];
+    for (int w = 1; w < 4; ++w)
+        if (red_g[w] > gsel || (red_g[w] == gsel && red_p[w] < q)) {
+            gsel = red_g[w];
+            q = red_p[w];
+        }
+    __syncthreads();
+    if (q < 0 || q >= n_act) {  // forced index not among the remaining candidates
+        if (tid == 0) state[ST_STATUS] = 1;
+        return -1;
+    }
+    if (forced < 0 && gsel == -INFINITY) {
+        if (tid == 0) state[ST_STATUS] = 2;
+        return -1;
+    }
+    *gain_out = gsel;
+    return q;
+}
+
+// ---------------------------------------------------------------------------------------------
+// Kernel bodies (one work-group; early exits are uniform across it).
+
+template <typename TR>
+__device__ void gain_regs_body(const StepDesc &d, int p)
+{
+    __shared__ double colbuf[256];
+    __shared__ double piv[128];
+    __shared__ double red[4];
+    if (d.state[ST_STATUS] != 0 || p >= d.n_act) return;
+    const int i = d.act_in[p];
+    const bool ok =
+        chol_regs((const TR *)d.R + blk_index(i, i) * (int64_t)d.N_tp * d.N_tp, d.N_t, d.N_tp >> 4, colbuf, piv, nullptr);
+    if (!ok) {
+        if (threadIdx.x == 0) d.gains[p] = -INFINITY;
+        return;
+    }
+    const double ls = half_sum_log(piv, d.N_t, red);
+    if (threadIdx.x == 0) d.gains[p] = ls - d.half_noise;
+}
+
+template <typename TR>
+__device__ void pick_regs_body(const StepDesc &d, double *Lout)
+{
+    __shared__ double colbuf[1024];
+    __shared__ double piv[128];
+    __shared__ double red[4];
+    if (d.state[ST_STATUS] != 0) return;
+    const int tid = threadIdx.x;
+    double g = 0.0;
+    const int pos = select_winner(d.act_in, d.n_act, d.gains, d.forced, d.state, &g);
+    if (pos < 0) return;
+    const int s = d.act_in[pos];
+    for (int p = tid; p < d.n_act - 1; p += blockDim.x) d.act_out[p] = d.act_in[p < pos ? p : p + 1];
+    const bool ok =
+        chol_regs((const TR *)d.R + blk_index(s, s) * (int64_t)d.N_tp * d.N_tp, d.N_t, d.N_tp >> 4, colbuf, piv, Lout);
+    if (!ok) {
+        if (tid == 0) d.state[ST_STATUS] = 2;
+        return;
+    }
+    const double ls = half_sum_log(piv, d.N_t, red);
+    if (tid == 0) {
+        d.picks[d.step] = s;
+        d.pick_gain[d.step] = d.forced < 0 ? g : ls - d.half_noise;
+        d.state[ST_NPICKS] = d.step + 1;
+        d.state[ST_LAST] = s;
+    }
+    inverse_regs(Lout, d.N_t, d.N_tp, colbuf, d.Linv);
+}
+
+template <typename TR>
+__device__ void gain_lds_body(const StepDesc &d, int p, double *lds)
+{
+    if (d.state[ST_STATUS] != 0 || p >= d.n_act) return;
+    double *A = d.scratch ? d.scratch + (int64_t)p * tri(d.N_t) : lds;
+    const int i = d.act_in[p];
+    load_diag_block((const TR *)d.R + blk_index(i, i) * (int64_t)d.N_tp * d.N_tp, d.N_t, d.N_tp, A);
+    const double ls = chol_packed(A, d.N_t);
+    if (threadIdx.x == 0) d.gains[p] = (ls == -INFINITY) ? -INFINITY : ls - d.half_noise;
+}
+
+template <typename TR>
+__device__ void pick_lds_body(const StepDesc &d, double *lds)
+{
+    if (d.state[ST_STATUS] != 0) return;
+    const int tid = threadIdx.x;
+    double g = 0.0;
+    const int pos = select_winner(d.act_in, d.n_act, d.gains, d.forced, d.state, &g);
+    if (pos < 0) return;
+    const int s = d.act_in[pos];
+    for (int p = tid; p < d.n_act - 1; p += blockDim.x) d.act_out[p] = d.act_in[p < pos ? p : p + 1];
+    double *A = d.scratch ? d.scratch : lds;
+    double *X = A + tri(d.N_t);
+    const int N_t = d.N_t, N_tp = d.N_tp;
+    load_diag_block((const TR *)d.R + blk_index(s, s) * (int64_t)N_tp * N_tp, N_t, N_tp, A);
+    const double ls = chol_packed(A, N_t);
+    if (ls == -INFINITY) {
+        if (tid == 0) d.state[ST_STATUS] = 2;
+        return;
+    }
+    if (tid == 0) {
+        d.picks[d.step] = s;
+        d.pick_gain[d.step] = d.forced < 0 ? g : ls - d.half_noise;
+        d.state[ST_NPICKS] = d.step + 1;
+        d.state[ST_LAST] = s;
+    }
+    tri_inverse(A, X, N_t);
+    const int nb = N_tp >> 4;
+    for (int o = tid; o < N_tp * N_tp; o += blockDim.x) {
+        const int sb = o >> 8, w = o & 255, lane = w >> 2, reg = w & 3;
+        const int k = (sb / nb) * 16 + (lane & 15);
+        const int kp = (sb % nb) * 16 + ((lane >> 4) << 2) + reg;
+        double v;
+        if (k < N_t && kp < N_t)
+            v = kp <= k ? X[tri(k) + kp] : 0.0;
+        else
+            v = (k == kp) ? 1.0 : 0.0;
+        d.Linv[o] = v;
+    }
+}
+
+// ---------------------------------------------------------------------------------------------
+// Kernels: single instance (descriptor by value) and batched (descriptor array).
+
+template <typename TR>
+__global__ void __launch_bounds__(256) gain_regs_kernel(StepDesc d)
+{
+    gain_regs_body<TR>(d, blockIdx.x);
+}
+
+template <typename TR>
+__global__ void __launch_bounds__(256) gain_regs_batched(const StepDesc *__restrict__ ds, int n)
+{
+    const int i = find_instance(ds, n, blockIdx.x);
+    if (i < 0) return;
+    const StepDesc d = ds[i];
+    gain_regs_body<TR>(d, (int)(blockIdx.x - d.item0));
+}
+
+template <typename TR>
+__global__ void __launch_bounds__(256) pick_regs_kernel(StepDesc d)
+{
+    extern __shared__ double dyn[];
+    pick_regs_body<TR>(d, dyn);
+}
+
+template <typename TR>
+__global__ void __launch_bounds__(256) pick_regs_batched(const StepDesc *__restrict__ ds, int n)
+{
+    extern __shared__ double dyn[];
+    const int i = find_instance(ds, n, blockIdx.x);
+    if (i < 0) return;
+    const StepDesc d = ds[i];
+    pick_regs_body<TR>(d, dyn);
+}
+
+template <typename TR>
+__global__ void __launch_bounds__(256) gain_lds_kernel(StepDesc d)
+{
+    extern __shared__ double dyn[];
+    gain_lds_body<TR>(d, blockIdx.x, dyn);
+}
+
+template <typename TR>
+__global__ void __launch_bounds__(256) pick_lds_kernel(StepDesc d)
+{
+    extern __shared__ double dyn[];
+    pick_lds_body<TR>(d, dyn);
+}
+
+// ---------------------------------------------------------------------------------------------
+// Launchers.
+
+static int g_max_lds = -1;
+static int max_lds()
+{
+    if (g_max_lds < 0) {
+        int dev = 0, v = 65536;
+        if (hipGetDevice(&dev) == hipSuccess &&
+            hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) == hipSuccess)
+            g_max_lds = v;
+        else
+            g_max_lds = 65536;
+    }
+    return g_max_lds;
+}
+
+size_t gain_lds_bytes(int N_t)
+{
+    const size_t b = sizeof(double) * (size_t)N_t * (N_t + 1) / 2;
+    return b <= (size_t)max_lds() ? b : 0;
+}
+size_t pick_lds_bytes(int N_t)
+{
+    const size_t b = 2 * sizeof(double) * (size_t)N_t * (N_t + 1) / 2;
+    return b <= (size_t)max_lds() - 256 ? b : 0;
+}
+
+template <typename K>
+static void allow_lds(K kernel, size_t bytes)
+{
+    if (bytes > 65536) (void)hipFuncSetAttribute((const void *)kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+}
+
+template <typename TR>
+static hipError_t launch_gain_t(const StepDesc &d, hipStream_t s)
+{
+    if (d.n_act <= 0) return hipSuccess;
+    if (d.N_t <= REGS_MAX_NT) {
+        hipLaunchKernelGGL(gain_regs_kernel<TR>, dim3(d.n_act), dim3(256), 0, s, d);
+    } else {
+        const size_t lds = d.scratch ? 0 : gain_lds_bytes(d.N_t);
+        allow_lds(gain_lds_kernel<TR>, lds);
+        hipLaunchKernelGGL(gain_lds_kernel<TR>, dim3(d.n_act), dim3(256), lds, s, d);
+    }
+    return hipGetLastError();
+}
+
+template <typename TR>
+static hipError_t launch_pick_t(const StepDesc &d, hipStream_t s)
+{
+    if (d.N_t <= REGS_MAX_NT) {
+        const size_t lds = sizeof(double) * (size_t)d.N_t * (d.N_t + 1) / 2;
+        allow_lds(pick_regs_kernel<TR>, lds);
+        hipLaunchKernelGGL(pick_regs_kernel<TR>, dim3(1), dim3(256), lds, s, d);
+    } else {
+        const size_t lds = d.scratch ? 0 : pick_lds_bytes(d.N_t);
+        allow_lds(pick_lds_kernel<TR>, lds);
+        hipLaunchKernelGGL(pick_lds_kernel<TR>, dim3(1), dim3(256), lds, s, d);
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_gain(const StepDesc &d, int rtype, hipStream_t s)
+{
+    return rtype == R_F64 ? launch_gain_t<double>(d, s) : launch_gain_t<float>(d, s);
+}
+
+hipError_t launch_pick(const StepDesc &d, int rtype, hipStream_t s)
+{
+    return rtype == R_F64 ? launch_pick_t<double>(d, s) : launch_pick_t<float>(d, s);
+}
+
+hipError_t launch_gain_batched(const StepDesc *descs, int n, int64_t total, int rtype, hipStream_t s)
+{
+    if (n <= 0 || total <= 0) return hipSuccess;
+    if (rtype == R_F64)
+        hipLaunchKernelGGL(gain_regs_batched<double>, dim3((unsigned)total), dim3(256), 0, s, descs, n);
+    else
+        hipLaunchKernelGGL(gain_regs_batched<float>, dim3((unsigned)total), dim3(256), 0, s, descs, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_pick_batched(const StepDesc *descs, int n, int max_Nt, int rtype, hipStream_t s)
+{
+    if (n <= 0) return hipSuccess;
+    const size_t lds = sizeof(double) * (size_t)max_Nt * (max_Nt + 1) / 2;
+    if (rtype == R_F64) {
+        allow_lds(pick_regs_batched<double>, lds);
+        hipLaunchKernelGGL(pick_regs_batched<double>, dim3(n), dim3(256), lds, s, descs, n);
+    } else {
+        allow_lds(pick_regs_batched<float>, lds);
+        hipLaunchKernelGGL(pick_regs_batched<float>, dim3(n), dim3(256), lds, s, descs, n);
+    }
+    return hipGetLastError();
+}
+
+}  // namespace oed

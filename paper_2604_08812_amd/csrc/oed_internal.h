@@ -58,25 +58,64 @@ __host__ __device__ inline int opd16_off(int t, int k, int nb32)
 // Device state words (int32) shared by the kernels of one context.
 enum StateWord { ST_STATUS = 0, ST_NPICKS = 1, ST_LAST = 2, ST_WORDS = 16 };
 
-struct Launch {
-    hipStream_t stream;
+// One instance at one phase of one greedy step: everything a kernel needs to know.  Single
+// launches pass it by value; batched launches pass a device array sorted by item0, and every
+// work-group finds its instance by binary search.
+struct StepDesc {
+    void *R;               // working copy (element type by precision)
+    void *W;               // W blocks (element type by precision)
+    const int *act_in;     // remaining candidates (gain, pick: before the pick; trsm, syrk: after it)
+    int *act_out;          // pick: remaining candidates after the pick
+    double *gains;         // gains by position in act_in
+    double *Linv;          // L_s^-1 of the last pick, operand order
+    int *state;            // ST_* words of the instance
+    int *picks;            // local index of every pick
+    double *pick_gain;     // gain of every pick
+    double *scratch;       // global scratch of the LDS factorisation kernels (N_t > REGS_MAX_NT)
+    double half_noise;     // (N_t / 2) ln sigma^2
+    int n_act;             // number of entries of act_in
+    int N_t, N_tp;         // real and padded block size
+    int step;              // pick: index of this pick
+    int forced;            // pick: forced local index, or -1 for the argmax
+    int pad_;
+    int64_t item0;         // batched launches: first work item of this instance
+    int64_t nitems;        // work items of this instance (gain, trsm: n_act; pick: 1; syrk: tiles)
 };
+
+// Tiles of the downdate over n remaining candidates (128 x 128 tiles of the lower triangle).
+inline int64_t syrk_tiles(int n_act, int N_tp)
+{
+    const int64_t T = ((int64_t)n_act * N_tp + 127) / 128;
+    return T * (T + 1) / 2;
+}
 
 hipError_t launch_pack(const void *K, int kdtype, int64_t ld, int N_t, int N_tp, const int *cmap, int N_c,
                        void *R, int rtype, hipStream_t s);
-hipError_t launch_init_state(int *act, int n, double *pick_gain, int *picks, int *state, hipStream_t s);
-hipError_t launch_gain(const void *R, int rtype, const int *act, int n_act, int N_t, int N_tp, double half_noise,
-                       double *gains, const int *state, double *scratch, hipStream_t s);
-hipError_t launch_pick(const void *R, int rtype, const int *act_in, int *act_out, int n_act, const double *gains,
-                       int N_t, int N_tp, double half_noise, int step, int forced, int *picks, double *pick_gain,
-                       int *state, double *Linv, double *scratch, hipStream_t s);
-hipError_t launch_trsm(const void *R, int rtype, const int *act, int n_act, const int *state, const double *Linv,
-                       int N_tp, void *W, int wtype, hipStream_t s);
-hipError_t launch_syrk(void *R, int rtype, const void *W, int wtype, const int *act, int n_act, int N_tp,
-                       const int *state, hipStream_t s);
-hipError_t launch_gather_block(const void *R, int rtype, int i, int j, int N_tp, double *out, hipStream_t s);
+hipError_t launch_init_state(int *act, int n, int *state, hipStream_t s);
 
-// Bytes of dynamic LDS the FP64 factorisation kernels need (0 = use global scratch).
+// Single-instance launches (d.item0 = 0, d.nitems = work items).
+hipError_t launch_gain(const StepDesc &d, int rtype, hipStream_t s);
+hipError_t launch_pick(const StepDesc &d, int rtype, hipStream_t s);
+hipError_t launch_trsm(const StepDesc &d, int rtype, int wtype, hipStream_t s);
+// Downdate kernels: SYRK_DIRECT streams W operands from global memory per wave (any N_tp);
+// SYRK_LDS stages them through LDS with a software pipeline (N_tp <= 128).
+enum SyrkVariant { SYRK_DIRECT = 0, SYRK_LDS = 1, SYRK_NVARIANTS = 2 };
+hipError_t launch_syrk(const StepDesc &d, int rtype, int wtype, int variant, hipStream_t s);
+
+// Batched launches over n instances (descs: device array sorted by item0, total work items).
+// The register factorisation kernels serve all of them (max_Nt <= REGS_MAX_NT); a batched
+// downdate launch needs one common N_tp.
+hipError_t launch_gain_batched(const StepDesc *descs, int n, int64_t total, int rtype, hipStream_t s);
+hipError_t launch_pick_batched(const StepDesc *descs, int n, int max_Nt, int rtype, hipStream_t s);
+hipError_t launch_trsm_batched(const StepDesc *descs, int n, int64_t total, int rtype, int wtype, hipStream_t s);
+hipError_t launch_syrk_batched(const StepDesc *descs, int n, int64_t total, int N_tp, int rtype, int wtype,
+                               int variant, hipStream_t s);
+
+// Largest N_t handled by the register-resident factorisation kernels; beyond it the
+// LDS / global-scratch kernels run.
+constexpr int REGS_MAX_NT = 128;
+
+// Bytes of dynamic LDS the LDS factorisation kernels need (0 = use global scratch).
 size_t gain_lds_bytes(int N_t);
 size_t pick_lds_bytes(int N_t);
 

@@ -1,0 +1,89 @@
+// Packing of the caller's K into the working copy R, and per-selection state reset.
+#include <algorithm>
+
+#include "oed_device.h"
+
+namespace oed {
+
+// ---------------------------------------------------------------------------------------------
+// Pack the candidate part of K's lower triangle into R (padded, packed, accumulator order).
+// One thread per (block, sub-block, lane): it writes the lane's 4 elements with one vector store.
+template <typename TK, typename TR>
+__global__ void __launch_bounds__(256) pack_kernel(const TK *__restrict__ K, int64_t ld, int N_t, int N_tp,
+                                                   const int *__restrict__ cmap, int64_t nblocks,
+                                                   TR *__restrict__ R)
+{
+    const int nb = N_tp >> 4;
+    const int64_t per_block = (int64_t)nb * nb * 64;
+    const int64_t total = nblocks * per_block;
+    const int64_t bs = (int64_t)N_tp * N_tp;
+    for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total;
+         e += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t b = e / per_block;
+        const int rem = (int)(e - b * per_block);
+        const int sb = rem >> 6, lane = rem & 63;
+        const int64_t i = tri_row(b), j = b - i * (i + 1) / 2;
+        const int tb = sb / nb, ub = sb - tb * nb;
+        const int u = ub * 16 + (lane & 15);
+        const int t0 = tb * 16 + ((lane >> 4) << 2);
+        const int64_t ci = cmap[i], cj = cmap[j];
+        typename V4<TR>::type v;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int t = t0 + r;
+            double x;
+            if (t < N_t && u < N_t) {
+                int64_t row, col;
+                if (i != j) {
+                    row = ci * N_t + t;
+                    col = cj * N_t + u;
+                } else {
+                    row = ci * N_t + (t >= u ? t : u);
+                    col = ci * N_t + (t >= u ? u : t);
+                }
+                x = (double)K[row * ld + col];
+            } else {
+                x = (i == j && t == u) ? 1.0 : 0.0;
+            }
+            v[r] = (TR)x;
+        }
+        st4(R + b * bs + ((int64_t)sb << 8) + lane * 4, v);
+    }
+}
+
+__global__ void init_state_kernel(int *act, int n, int *state)
+{
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p < n) act[p] = p;
+    if (p < ST_WORDS) state[p] = 0;
+}
+
+hipError_t launch_pack(const void *K, int kdtype, int64_t ld, int N_t, int N_tp, const int *cmap, int N_c,
+                       void *R, int rtype, hipStream_t s)
+{
+    const int64_t nblocks = (int64_t)N_c * (N_c + 1) / 2;
+    const int64_t threads = nblocks * (N_tp / 16) * (N_tp / 16) * 64;
+    const int64_t grid = std::min<int64_t>((threads + 255) / 256, 1 << 20);
+    if (kdtype == 0 && rtype == R_F64)
+        hipLaunchKernelGGL((pack_kernel<double, double>), dim3(grid), dim3(256), 0, s, (const double *)K, ld, N_t, N_tp,
+                           cmap, nblocks, (double *)R);
+    else if (kdtype == 0 && rtype == R_F32)
+        hipLaunchKernelGGL((pack_kernel<double, float>), dim3(grid), dim3(256), 0, s, (const double *)K, ld, N_t, N_tp,
+                           cmap, nblocks, (float *)R);
+    else if (kdtype == 1 && rtype == R_F64)
+        hipLaunchKernelGGL((pack_kernel<float, double>), dim3(grid), dim3(256), 0, s, (const float *)K, ld, N_t, N_tp,
+                           cmap, nblocks, (double *)R);
+    else
+        hipLaunchKernelGGL((pack_kernel<float, float>), dim3(grid), dim3(256), 0, s, (const float *)K, ld, N_t, N_tp,
+                           cmap, nblocks, (float *)R);
+    return hipGetLastError();
+}
+
+hipError_t launch_init_state(int *act, int n, int *state, hipStream_t s)
+{
+    const int threads = std::max(n, (int)ST_WORDS);
+    hipLaunchKernelGGL(init_state_kernel, dim3((threads + 255) / 256), dim3(256), 0, s, act, n, state);
+    return hipGetLastError();
+}
+
+}  // namespace oed

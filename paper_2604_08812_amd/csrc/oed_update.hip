@@ -1,0 +1,422 @@
+// Update kernels of one greedy step: the block column W = R[:, s] L_s^-T of the winner s (the
+// new block row of the factor in Algorithm 1, Sec. III-D) and the Schur-complement downdate
+// R -= W W^T on the lower triangle of the remaining rows, on MFMA.
+#include "oed_device.h"
+
+namespace oed {
+
+// W_i = C_i L_s^-T computed as W_i^T = L_s^-1 C_i^T on FP64 MFMA (16x16x4): the accumulator of
+// output sub-block (k-block kc, t-block tb) is then already in W's operand order.
+template <typename TW>
+__device__ __forceinline__ void store_w(TW *W, int64_t off, doublex4 a)
+{
+    typename V4<TW>::type v;
+    v[0] = (TW)a[0];
+    v[1] = (TW)a[1];
+    v[2] = (TW)a[2];
+    v[3] = (TW)a[3];
+    st4(W + off, v);
+}
+
+template <typename TR, typename TW>
+__device__ void trsm_body(const StepDesc &d, int p)
+{
+    if (d.state[ST_STATUS] != 0 || p >= d.n_act) return;
+    const TR *__restrict__ R = (const TR *)d.R;
+    TW *__restrict__ W = (TW *)d.W;
+    const double *__restrict__ Linv = d.Linv;
+    const int N_tp = d.N_tp;
+    const int i = d.act_in[p], s = d.state[ST_LAST];
+    const int nb = N_tp >> 4;
+    const int64_t bs = (int64_t)N_tp * N_tp;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, g = lane >> 4, l16 = lane & 15;
+    const int alane = a_lane<double>(lane);
+    const bool below = i > s;
+    const TR *Cb = R + blk_index(below ? i : s, below ? s : i) * bs;
+    TW *Wi = W + (int64_t)i * bs;
+    for (int tb = wave; tb < nb; tb += 4) {
+        for (int kg = 0; kg < nb; kg += 8) {
+            const int kend = min(nb, kg + 8);
+            doublex4 acc[8];
+#pragma unroll
+            for (int c = 0; c < 8; ++c) acc[c] = doublex4{0.0, 0.0, 0.0, 0.0};
+            for (int q = 0; q < kend; ++q) {
+                double b[4];
+                if (below) {
+                    const int t = 16 * tb + l16;
+#pragma unroll
+                    for (int s4 = 0; s4 < 4; ++s4) b[s4] = (double)Cb[acc_off(t, 16 * q + 4 * g + s4, nb)];
+                } else {
+                    const typename V4<TR>::type v = ld4(Cb + acc_off(16 * q + 4 * g, 16 * tb + l16, nb));
+#pragma unroll
+                    for (int s4 = 0; s4 < 4; ++s4) b[s4] = (double)v[s4];
+                }
+#pragma unroll
+                for (int c = 0; c < 8; ++c) {
+                    const int kc = kg + c;
+                    if (kc >= q && kc < kend) {
+                        const doublex4 a = ld4(Linv + ((kc * nb + q) << 8) + alane * 4);
+#pragma unroll
+                        for (int s4 = 0; s4 < 4; ++s4) acc[c] = mfma16(a[s4], b[s4], acc[c]);
+                    }
+                }
+            }
+#pragma unroll
+            for (int c = 0; c < 8; ++c) {
+                const int kc = kg + c;
+                if (kc < kend) store_w(Wi, ((int64_t)(tb * nb + kc) << 8) + lane * 4, acc[c]);
+            }
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------------------------
+// Downdate R_IJ -= W_I W_J^T over 128 x 128 tiles of the remaining rows, lower triangle only.
+// Four waves per tile, each a 64 x 64 quarter = 4 x 4 MFMA 16x16 blocks.  Tiles are handed
+// out XCD by XCD (work-group id mod 8 is the XCD) in contiguous chunks, so the row panel of
+// W that neighbouring tiles share stays in that XCD's L2.
+template <typename T>
+__device__ void syrk_direct_body(const StepDesc &d, int64_t tile)
+{
+    typedef typename V4<T>::type vec;
+    if (d.state[ST_STATUS] != 0) return;
+    T *__restrict__ R = (T *)d.R;
+    const T *__restrict__ W = (const T *)d.W;
+    const int *__restrict__ act = d.act_in;
+    const int n_act = d.n_act, N_tp = d.N_tp;
+    const int64_t P = tri_row(tile), Q = tile - P * (P + 1) / 2;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, wr = wave >> 1, wc = wave & 1;
+    const int alane = a_lane<T>(lane);
+    const int nb = N_tp >> 4;
+    const int rows = n_act * N_tp;
+    const int64_t bs = (int64_t)N_tp * N_tp;
+
+    int ia[4], ta[4], ja[4], tc[4];
+    bool vr[4], vc[4];
+#pragma unroll
+    for (int b = 0; b < 4; ++b) {
+        const int r = (int)P * 128 + wr * 64 + 16 * b;
+        vr[b] = r < rows;
+        ia[b] = vr[b] ? act[r / N_tp] : 0;
+        ta[b] = (r % N_tp) >> 4;
+        const int c = (int)Q * 128 + wc * 64 + 16 * b;
+        vc[b] = c < rows;
+        ja[b] = vc[b] ? act[c / N_tp] : 0;
+        tc[b] = (c % N_tp) >> 4;
+    }
+    bool any = false;
+#pragma unroll
+    for (int b = 0; b < 4; ++b)
+#pragma unroll
+        for (int c = 0; c < 4; ++c) any |= vr[b] && vc[c] && ia[b] >= ja[c];
+    if (!any) return;
+
+    vec acc[4][4];
+#pragma unroll
+    for (int b = 0; b < 4; ++b)
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+            if (vr[b] && vc[c] && ia[b] >= ja[c])
+                acc[b][c] = ld4(R + blk_index(ia[b], ja[c]) * bs + ((ta[b] * nb + tc[c]) << 8) + lane * 4);
+            else
+                acc[b][c] = vec{0, 0, 0, 0};
+        }
+    for (int q = 0; q < nb; ++q) {
+        vec a[4], w[4];
+#pragma unroll
+        for (int b = 0; b < 4; ++b) {
+            a[b] = vr[b] ? ld4(W + (int64_t)ia[b] * bs + ((ta[b] * nb + q) << 8) + alane * 4) : vec{0, 0, 0, 0};
+            w[b] = vc[b] ? ld4(W + (int64_t)ja[b] * bs + ((tc[b] * nb + q) << 8) + lane * 4) : vec{0, 0, 0, 0};
+        }
+#pragma unroll
+        for (int s4 = 0; s4 < 4; ++s4)
+#pragma unroll
+            for (int b = 0; b < 4; ++b)
+#pragma unroll
+                for (int c = 0; c < 4; ++c) acc[b][c] = mfma16(-a[b][s4], w[c][s4], acc[b][c]);
+    }
+#pragma unroll
+    for (int b = 0; b < 4; ++b)
+#pragma unroll
+        for (int c = 0; c < 4; ++c)
+            if (vr[b] && vc[c] && ia[b] >= ja[c])
+                st4(R + blk_index(ia[b], ja[c]) * bs + ((ta[b] * nb + tc[c]) << 8) + lane * 4, acc[b][c]);
+}
+
+// ---------------------------------------------------------------------------------------------
+// Downdate, LDS-staged and software-pipelined variant for N_tp = 16*NB <= 128.
+// Per 16-wide slice q of the inner index, the work-group stages the 128 x 16 A panel (tile
+// rows) and B panel (tile columns) of W into LDS once (double-buffered, one barrier per
+// slice) and every wave reads its operands from there; the next slice's global loads are in
+// flight while the current slice's MFMAs run.  The product W_I W_J^T accumulates from zero;
+// the R tile is fetched at the start (FP32: into registers, in flight during the MFMAs) and
+// subtracted at the end.
+template <typename T, int NB>
+__device__ void syrk_lds_body(const StepDesc &d, int64_t tile)
+{
+    typedef typename V4<T>::type vec;
+    constexpr int N_tp = 16 * NB;
+    constexpr bool PREFETCH_R = sizeof(T) == 4;
+    __shared__ vec lds[2][2][8 * 64];  // [buffer][A/B][sub-block * 64 + lane]
+    if (d.state[ST_STATUS] != 0) return;
+    T *__restrict__ R = (T *)d.R;
+    const T *__restrict__ W = (const T *)d.W;
+    const int *__restrict__ act = d.act_in;
+    const int n_act = d.n_act;
+    const int64_t P = tri_row(tile), Q = tile - P * (P + 1) / 2;
+    const int tid = threadIdx.x;
+    const int lane = tid & 63, wave = tid >> 6, wr = wave >> 1, wc = wave & 1;
+    const int alane = a_lane<T>(lane);
+    const int rows = n_act * N_tp;
+    const int64_t bs = (int64_t)N_tp * N_tp;
+
+    // staging assignment: thread loads sub-blocks sA = tid/64 and tid/64 + 4 of both panels
+    const T *gA[2], *gB[2];
+    bool okA[2], okB[2];
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+        const int sb = wave + 4 * h;
+        const int r = (int)P * 128 + 16 * sb, c = (int)Q * 128 + 16 * sb;
+        okA[h] = r < rows;
+        okB[h] = c < rows;
+        const int ia = okA[h] ? act[r / N_tp] : 0, ja = okB[h] ? act[c / N_tp] : 0;
+        gA[h] = W + (int64_t)ia * bs + (((r % N_tp) >> 4) * NB << 8) + lane * 4;
+        gB[h] = W + (int64_t)ja * bs + (((c % N_tp) >> 4) * NB << 8) + lane * 4;
+    }
+    // output blocks of this wave
+    int ia[4], ta[4], ja[4], tc[4];
+    bool vr[4], vc[4];
+#pragma unroll
+    for (int b = 0; b < 4; ++b) {
+        const int r = (int)P * 128 + wr * 64 + 16 * b;
+        vr[b] = r < rows;
+        ia[b] = vr[b] ? act[r / N_tp] : 0;
+        ta[b] = (r % N_tp) >> 4;
+        const int c = (int)Q * 128 + wc * 64 + 16 * b;
+        vc[b] = c < rows;
+        ja[b] = vc[b] ? act[c / N_tp] : 0;
+        tc[b] = (c % N_tp) >> 4;
+    }
+    bool ok[4][4];
+    bool any = false;
+#pragma unroll
+    for (int b = 0; b < 4; ++b)
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+            ok[b][c] = vr[b] && vc[c] && ia[b] >= ja[c];
+            any |= ok[b][c];
+        }
+    vec rt[4][4];
+    if (PREFETCH_R) {
+#pragma unroll
+        for (int b = 0; b < 4; ++b)
+#pragma unroll
+            for (int c = 0; c < 4; ++c)
+                rt[b][c] = ok[b][c] ? ld4(R + blk_index(ia[b], ja[c]) * bs + ((ta[b] * NB + tc[c]) << 8) + lane * 4)
+                                    : vec{0, 0, 0, 0};
+    }
+    vec acc[4][4];
+#pragma unroll
+    for (int b = 0; b < 4; ++b)
+#pragma unroll
+        for (int c = 0; c < 4; ++c) acc[b][c] = vec{0, 0, 0, 0};
+
+    vec sa[2], sbv[2];
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+        sa[h] = okA[h] ? ld4(gA[h]) : vec{0, 0, 0, 0};
+        sbv[h] = okB[h] ? ld4(gB[h]) : vec{0, 0, 0, 0};
+    }
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+        lds[0][0][(wave + 4 * h) * 64 + lane] = sa[h];
+        lds[0][1][(wave + 4 * h) * 64 + lane] = sbv[h];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < NB; ++q) {
+        const int buf = q & 1;
+        if (q + 1 < NB) {
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+                sa[h] = okA[h] ? ld4(gA[h] + ((q + 1) << 8)) : vec{0, 0, 0, 0};
+                sbv[h] = okB[h] ? ld4(gB[h] + ((q + 1) << 8)) : vec{0, 0, 0, 0};
+            }
+        }
+        if (any) {
+            vec a[4], w[4];
+#pragma unroll
+            for (int b = 0; b < 4; ++b) {
+                a[b] = lds[buf][0][(wr * 4 + b) * 64 + alane];
+                w[b] = lds[buf][1][(wc * 4 + b) * 64 + lane];
+            }
+#pragma unroll
+            for (int s4 = 0; s4 < 4; ++s4)
+#pragma unroll
+                for (int b = 0; b < 4; ++b)
+#pragma unroll
+                    for (int c = 0; c < 4; ++c) acc[b][c] = mfma16(a[b][s4], w[c][s4], acc[b][c]);
+        }
+        if (q + 1 < NB) {
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+                lds[buf ^ 1][0][(wave + 4 * h) * 64 + lane] = sa[h];
+                lds[buf ^ 1][1][(wave + 4 * h) * 64 + lane] = sbv[h];
+            }
+        }
+        __syncthreads();
+    }
+    if (!any) return;
+#pragma unroll
+    for (int b = 0; b < 4; ++b)
+#pragma unroll
+        for (int c = 0; c < 4; ++c)
+            if (ok[b][c]) {
+                T *p = R + blk_index(ia[b], ja[c]) * bs + ((ta[b] * NB + tc[c]) << 8) + lane * 4;
+                const vec r0 = PREFETCH_R ? rt[b][c] : ld4(p);
+                st4(p, r0 - acc[b][c]);
+            }
+}
+
+// ---------------------------------------------------------------------------------------------
+// Kernels: single instance (descriptor by value) and batched (descriptor array).
+
+template <typename TR, typename TW>
+__global__ void __launch_bounds__(256) trsm_kernel(StepDesc d)
+{
+    trsm_body<TR, TW>(d, blockIdx.x);
+}
+
+template <typename TR, typename TW>
+__global__ void __launch_bounds__(256) trsm_batched(const StepDesc *__restrict__ ds, int n)
+{
+    const int i = find_instance(ds, n, blockIdx.x);
+    if (i < 0) return;
+    const StepDesc d = ds[i];
+    trsm_body<TR, TW>(d, (int)(blockIdx.x - d.item0));
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256) syrk_direct_kernel(StepDesc d, int64_t per_xcd)
+{
+    const int64_t tile = xcd_item(blockIdx.x, per_xcd);
+    if (tile >= d.nitems) return;
+    syrk_direct_body<T>(d, tile);
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256) syrk_direct_batched(const StepDesc *__restrict__ ds, int n, int64_t total,
+                                                           int64_t per_xcd)
+{
+    const int64_t item = xcd_item(blockIdx.x, per_xcd);
+    if (item >= total) return;
+    const int i = find_instance(ds, n, item);
+    if (i < 0) return;
+    const StepDesc d = ds[i];
+    syrk_direct_body<T>(d, item - d.item0);
+}
+
+template <typename T, int NB>
+__global__ void __launch_bounds__(256, 2) syrk_lds_kernel(StepDesc d, int64_t per_xcd)
+{
+    const int64_t tile = xcd_item(blockIdx.x, per_xcd);
+    if (tile >= d.nitems) return;
+    syrk_lds_body<T, NB>(d, tile);
+}
+
+template <typename T, int NB>
+__global__ void __launch_bounds__(256, 2) syrk_lds_batched(const StepDesc *__restrict__ ds, int n, int64_t total,
+                                                           int64_t per_xcd)
+{
+    const int64_t item = xcd_item(blockIdx.x, per_xcd);
+    if (item >= total) return;
+    const int i = find_instance(ds, n, item);
+    if (i < 0) return;
+    const StepDesc d = ds[i];
+    syrk_lds_body<T, NB>(d, item - d.item0);
+}
+
+// ---------------------------------------------------------------------------------------------
+// Launchers.
+
+template <typename TR, typename TW>
+static hipError_t launch_trsm_t(const StepDesc *descs, const StepDesc &d, int n, int64_t total, hipStream_t s)
+{
+    if (descs)
+        hipLaunchKernelGGL((trsm_batched<TR, TW>), dim3((unsigned)total), dim3(256), 0, s, descs, n);
+    else
+        hipLaunchKernelGGL((trsm_kernel<TR, TW>), dim3((unsigned)total), dim3(256), 0, s, d);
+    return hipGetLastError();
+}
+
+hipError_t launch_trsm(const StepDesc &d, int rtype, int wtype, hipStream_t s)
+{
+    if (d.n_act <= 0) return hipSuccess;
+    if (rtype == R_F64 && wtype == W_F64) return launch_trsm_t<double, double>(nullptr, d, 1, d.n_act, s);
+    if (rtype == R_F32 && wtype == W_F32) return launch_trsm_t<float, float>(nullptr, d, 1, d.n_act, s);
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_trsm_batched(const StepDesc *descs, int n, int64_t total, int rtype, int wtype, hipStream_t s)
+{
+    if (n <= 0 || total <= 0) return hipSuccess;
+    StepDesc none{};
+    if (rtype == R_F64 && wtype == W_F64) return launch_trsm_t<double, double>(descs, none, n, total, s);
+    if (rtype == R_F32 && wtype == W_F32) return launch_trsm_t<float, float>(descs, none, n, total, s);
+    return hipErrorInvalidValue;
+}
+
+// Single (descs == nullptr: d by value) or batched downdate launch over `total` tiles.
+template <typename T>
+static hipError_t launch_syrk_t(const StepDesc *descs, const StepDesc &d, int n, int64_t total, int N_tp,
+                                int variant, hipStream_t s)
+{
+    const int64_t per_xcd = (total + 7) / 8;
+    const dim3 grid((unsigned)(per_xcd * 8)), block(256);
+    const int nb = N_tp / 16;
+    if (variant == SYRK_LDS && nb <= 8 && N_tp % 16 == 0) {
+        switch (nb) {
+#define OED_SYRK_CASE(NBV)                                                                                    \
+    case NBV:                                                                                                 \
+        if (descs)                                                                                            \
+            hipLaunchKernelGGL((syrk_lds_batched<T, NBV>), grid, block, 0, s, descs, n, total, per_xcd);      \
+        else                                                                                                  \
+            hipLaunchKernelGGL((syrk_lds_kernel<T, NBV>), grid, block, 0, s, d, per_xcd);                     \
+        break;
+            OED_SYRK_CASE(1)
+            OED_SYRK_CASE(2)
+            OED_SYRK_CASE(3)
+            OED_SYRK_CASE(4)
+            OED_SYRK_CASE(5)
+            OED_SYRK_CASE(6)
+            OED_SYRK_CASE(7)
+            OED_SYRK_CASE(8)
+#undef OED_SYRK_CASE
+        }
+    } else if (descs) {
+        hipLaunchKernelGGL(syrk_direct_batched<T>, grid, block, 0, s, descs, n, total, per_xcd);
+    } else {
+        hipLaunchKernelGGL(syrk_direct_kernel<T>, grid, block, 0, s, d, per_xcd);
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_syrk(const StepDesc &d, int rtype, int wtype, int variant, hipStream_t s)
+{
+    if (d.n_act <= 0 || d.nitems <= 0) return hipSuccess;
+    if (rtype == R_F64 && wtype == W_F64) return launch_syrk_t<double>(nullptr, d, 1, d.nitems, d.N_tp, variant, s);
+    if (rtype == R_F32 && wtype == W_F32) return launch_syrk_t<float>(nullptr, d, 1, d.nitems, d.N_tp, variant, s);
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_syrk_batched(const StepDesc *descs, int n, int64_t total, int N_tp, int rtype, int wtype,
+                               int variant, hipStream_t s)
+{
+    if (n <= 0 || total <= 0) return hipSuccess;
+    StepDesc none{};
+    if (rtype == R_F64 && wtype == W_F64) return launch_syrk_t<double>(descs, none, n, total, N_tp, variant, s);
+    if (rtype == R_F32 && wtype == W_F32) return launch_syrk_t<float>(descs, none, n, total, N_tp, variant, s);
+    return hipErrorInvalidValue;
+}
+
+}  // namespace oed
