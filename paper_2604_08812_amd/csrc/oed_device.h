@@ -83,6 +83,20 @@ __device__ __forceinline__ int find_instance(const StepDesc *ds, int n, int64_t 
     return item < ds[lo].item0 + ds[lo].nitems ? lo : -1;
 }
 
+// Downdate tile order: the 128 x 128 tiles (P, Q), Q <= P, of the lower triangle are grouped
+// in super-tiles of 8 x 8 tiles, taken in lower-triangular order; a super-tile holds 64 slots,
+// row-major.  The 64 work-groups an XCD runs at a time then share 8 row panels and 8 column
+// panels of W (1 MB at N_tp = 128) in that XCD's L2 instead of sweeping all of W.
+// Returns false for slots outside the triangle or past the last tile row T.
+__device__ __forceinline__ bool super_tile(int64_t slot, int64_t T, int64_t &P, int64_t &Q)
+{
+    const int64_t st = slot >> 6, r = slot & 63;
+    const int64_t SP = tri_row(st), SQ = st - SP * (SP + 1) / 2;
+    P = SP * 8 + (r >> 3);
+    Q = SQ * 8 + (r & 7);
+    return P < T && Q <= P;
+}
+
 // Work-group id -> work item, XCD by XCD: work-group g runs on XCD g % 8, and the items are
 // handed out so that each XCD processes one contiguous eighth of them.
 __device__ __forceinline__ int64_t xcd_item(int64_t wg, int64_t per_xcd) { return (wg & 7) * per_xcd + (wg >> 3); }

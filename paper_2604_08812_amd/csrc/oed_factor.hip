@@ -75,6 +75,19 @@ __device__ void tri_inverse(const double *L, double *X, int n)
 }
 
 // ---------------------------------------------------------------------------------------------
+// Makes loaded values opaque to the optimiser, so that loads followed by a mask are not turned
+// back into one load under a branch each (which serialises the LDS round trips of a column
+// step): all loads of a step are issued, then pinned together (one wait), then masked.
+__device__ __forceinline__ void pin8(double (&x)[8])
+{
+    __asm__ volatile("" : "+v"(x[0]), "+v"(x[1]), "+v"(x[2]), "+v"(x[3]), "+v"(x[4]), "+v"(x[5]), "+v"(x[6]),
+                     "+v"(x[7]));
+}
+__device__ __forceinline__ void pin4(double (&x)[4])
+{
+    __asm__ volatile("" : "+v"(x[0]), "+v"(x[1]), "+v"(x[2]), "+v"(x[3]));
+}
+
 // Register-resident FP64 factorisations for N_t <= 128 (work-group of 256 threads).
 //
 // Ownership: thread (wave w, lane l, g = l/16) holds the 16x16 sub-block rows I in {w, 7-w}
@@ -82,14 +95,81 @@ __device__ void tri_inverse(const double *L, double *X, int n)
 // the four accumulator-order elements (16I + 4g + r, 16J + l%16), r = 0..3 -- the same order
 // R is stored in, so a diagonal block is loaded with one vector access per sub-block.
 //
+// One block column JB (16 columns) of the register-resident Cholesky.  JB is a compile-time
+// constant, so the owners' register A[h][JB] and the column masks need no run-time selection.
+template <int JB>
+__device__ __forceinline__ bool chol_block(double (&A)[2][8][4], int N_t, int nbr, double *colbuf, double *piv,
+                                           double *Lout)
+{
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6, g = lane >> 4, l16 = lane & 15;
+    const int jend = min(16, N_t - 16 * JB);
+    for (int jl = 0; jl < jend; ++jl) {
+        const int j = 16 * JB + jl;
+        double *buf = colbuf + ((j & 1) << 7);
+        if (l16 == jl) {
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+                const int I = h ? 7 - w : w;
+                if (I < nbr && I >= JB) {
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) buf[16 * I + 4 * g + r] = A[h][JB][r];
+                }
+            }
+        }
+        __syncthreads();
+        // every LDS read of the step is issued before the first use (one wait)
+        double bu[8], bt[2][4], dv[4];
+#pragma unroll
+        for (int J = 0; J < 8; ++J) bu[J] = buf[16 * J + l16];
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            const int I = h ? 7 - w : w;
+#pragma unroll
+            for (int r = 0; r < 4; ++r) bt[h][r] = buf[16 * I + 4 * g + r];
+        }
+        dv[0] = buf[j];
+        dv[1] = dv[2] = dv[3] = 0.0;
+        pin8(bu);
+        pin4(bt[0]);
+        pin4(bt[1]);
+        pin4(dv);
+        const double d = dv[0];
+        if (!(d > 0.0) || !isfinite(d)) return false;
+        if (tid == 0) piv[j] = d;
+        if (Lout) {
+            const double l = sqrt(d), il = 1.0 / l;
+            for (int t = j + tid; t < N_t; t += blockDim.x) Lout[tri(t) + j] = t == j ? l : buf[t] * il;
+        }
+        const double inv_d = 1.0 / d;
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            const int I = h ? 7 - w : w;
+            if (I < nbr && I >= JB) {
+                double wt[4];
+#pragma unroll
+                for (int r = 0; r < 4; ++r) wt[r] = 16 * I + 4 * g + r > j ? bt[h][r] * inv_d : 0.0;
+                // sub-blocks left of column j are final; above the diagonal (J > I) au = 0
+#pragma unroll
+                for (int J = JB; J < 8; ++J) {
+                    const double au = (16 * J + l16 > j && J <= I) ? bu[J] : 0.0;
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) A[h][J][r] = fma(-wt[r], au, A[h][J][r]);
+                }
+            }
+        }
+    }
+    return true;
+}
+
 // Right-looking Cholesky, one barrier per column j: the owners of column j publish it
 // (unscaled, a_t = A[t][j]) in a double-buffered LDS vector; every thread then reads the pivot
 // d = a_j and applies A[t][u] -= a_t a_u / d to the elements it owns with t, u > j.  The
-// pivots are kept; sum_t ln L_tt = 1/2 sum_j ln d_j.
+// pivots are kept; sum_t ln L_tt = 1/2 sum_j ln d_j.  With Lout, L is also written (packed).
 template <typename TR>
-__device__ bool chol_regs(const TR *__restrict__ Rb, int N_t, int nb, double *colbuf, double *piv, double *Lout)
+__device__ __forceinline__ bool chol_regs(const TR *__restrict__ Rb, int N_t, int nb, double *colbuf, double *piv,
+                                          double *Lout)
 {
-    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6, g = lane >> 4, l16 = lane & 15;
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     const int nbr = (N_t + 15) >> 4;
     double A[2][8][4];
 #pragma unroll
@@ -107,59 +187,20 @@ __device__ bool chol_regs(const TR *__restrict__ Rb, int N_t, int nb, double *co
             }
         }
     }
-    for (int j = 0; j < N_t; ++j) {
-        const int jb = j >> 4, jl = j & 15;
-        double *buf = colbuf + ((j & 1) << 7);
-        if (l16 == jl) {
-#pragma unroll
-            for (int h = 0; h < 2; ++h) {
-                const int I = h ? 7 - w : w;
-                if (I < nbr && I >= jb) {
-#pragma unroll
-                    for (int J = 0; J < 8; ++J)
-                        if (J == jb) {
-#pragma unroll
-                            for (int r = 0; r < 4; ++r) buf[16 * I + 4 * g + r] = A[h][J][r];
-                        }
-                }
-            }
-        }
-        __syncthreads();
-        const double d = buf[j];
-        if (!(d > 0.0) || !isfinite(d)) return false;
-        if (tid == 0) piv[j] = d;
-        if (Lout) {
-            const double l = sqrt(d), il = 1.0 / l;
-            for (int t = j + tid; t < N_t; t += blockDim.x) Lout[tri(t) + j] = t == j ? l : buf[t] * il;
-        }
-        const double inv_d = 1.0 / d;
-#pragma unroll
-        for (int h = 0; h < 2; ++h) {
-            const int I = h ? 7 - w : w;
-            if (I < nbr && I >= jb) {
-                double wt[4];
-#pragma unroll
-                for (int r = 0; r < 4; ++r) {
-                    const int t = 16 * I + 4 * g + r;
-                    wt[r] = t > j ? buf[t] * inv_d : 0.0;
-                }
-                // branch-free over J: sub-blocks left of column j or above the diagonal get au = 0
-#pragma unroll
-                for (int J = 0; J < 8; ++J) {
-                    const int u = 16 * J + l16;
-                    const double au = (u > j && J <= I) ? buf[u] : 0.0;
-#pragma unroll
-                    for (int r = 0; r < 4; ++r) A[h][J][r] = fma(-wt[r], au, A[h][J][r]);
-                }
-            }
-        }
-    }
+    bool ok = chol_block<0>(A, N_t, nbr, colbuf, piv, Lout);
+    if (ok && nbr > 1) ok = chol_block<1>(A, N_t, nbr, colbuf, piv, Lout);
+    if (ok && nbr > 2) ok = chol_block<2>(A, N_t, nbr, colbuf, piv, Lout);
+    if (ok && nbr > 3) ok = chol_block<3>(A, N_t, nbr, colbuf, piv, Lout);
+    if (ok && nbr > 4) ok = chol_block<4>(A, N_t, nbr, colbuf, piv, Lout);
+    if (ok && nbr > 5) ok = chol_block<5>(A, N_t, nbr, colbuf, piv, Lout);
+    if (ok && nbr > 6) ok = chol_block<6>(A, N_t, nbr, colbuf, piv, Lout);
+    if (ok && nbr > 7) ok = chol_block<7>(A, N_t, nbr, colbuf, piv, Lout);
     __syncthreads();
-    return true;
+    return ok;
 }
 
 // 1/2 sum_{j < n} ln piv[j] (n <= 256), the same value in every thread (fixed reduction order).
-__device__ double half_sum_log(const double *piv, int n, double *red)
+__device__ __forceinline__ double half_sum_log(const double *piv, int n, double *red)
 {
     const int tid = threadIdx.x, lane = tid & 63;
     double v = tid < n ? log(piv[tid]) : 0.0;
@@ -171,12 +212,73 @@ __device__ double half_sum_log(const double *piv, int n, double *red)
     return 0.5 * t;
 }
 
+// One block row JB (16 rows) of the register-resident inverse (see inverse_regs); JB is a
+// compile-time constant so the published registers and the column range are fixed.
+template <int JB>
+__device__ __forceinline__ void inv_block(double (&X)[2][8][4], const double *Lout, int N_t, int nbr, double *rowbuf)
+{
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, g = lane >> 4, l16 = lane & 15;
+    const int jend = min(16, N_t - 16 * JB);
+    for (int jl = 0; jl < jend; ++jl) {
+        const int j = 16 * JB + jl;
+        // the owners of row j (lanes of group g = jl/4, register j%4) publish all four of their
+        // rows, so no register is selected by a run-time index; readers take slot j%4
+        double *rb = rowbuf + ((j & 1) << 9);
+        if (g == (jl >> 2)) {
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+                const int I = h ? 7 - w : w;
+                if (I == JB) {
+#pragma unroll
+                    for (int J = 0; J <= JB; ++J)
+#pragma unroll
+                        for (int r = 0; r < 4; ++r) rb[(r << 7) + 16 * J + l16] = X[h][J][r];
+                }
+            }
+        }
+        __syncthreads();
+        const double *rj = rb + ((j & 3) << 7);
+        double xv[8], lv[2][4], dl[4];
+#pragma unroll
+        for (int J = 0; J < 8; ++J) xv[J] = rj[16 * J + l16];
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            const int I = h ? 7 - w : w;
+#pragma unroll
+            for (int r = 0; r < 4; ++r) lv[h][r] = Lout[tri(min(16 * I + 4 * g + r, N_t - 1)) + j];
+        }
+        dl[0] = Lout[tri(j) + j];
+        dl[1] = dl[2] = dl[3] = 0.0;
+        pin8(xv);
+        pin4(lv[0]);
+        pin4(lv[1]);
+        pin4(dl);
+        const double inv_ljj = 1.0 / dl[0];
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            const int I = h ? 7 - w : w;
+            if (I < nbr && I >= JB) {
+                double lt[4];
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const int t = 16 * I + 4 * g + r;
+                    lt[r] = (t > j && t < N_t) ? lv[h][r] * inv_ljj : 0.0;
+                }
+#pragma unroll
+                for (int J = 0; J <= JB; ++J)
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) X[h][J][r] = fma(-lt[r], xv[J], X[h][J][r]);
+            }
+        }
+    }
+}
+
 // Inverse X = L^-1 of the packed lower factor in LDS, register-resident with the ownership of
 // chol_regs (rowbuf: LDS, 2 x 4 x 128 doubles).  Row-oriented elimination: row j of X, once all earlier rows have been subtracted
 // from it, equals L_jj times its final value; its owners publish it and every thread applies
 // X[t][c] -= (L[t][j] / L_jj) X[j][c] for t > j.  Rows are divided by their L_tt at the end.
 // The result goes to global memory in operand order (N_tp x N_tp, identity on the padding).
-__device__ void inverse_regs(const double *Lout, int N_t, int N_tp, double *rowbuf, double *__restrict__ Linv)
+__device__ __forceinline__ void inverse_regs(const double *Lout, int N_t, int N_tp, double *rowbuf, double *__restrict__ Linv)
 {
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6, g = lane >> 4, l16 = lane & 15;
     const int nbr = (N_t + 15) >> 4, nb = N_tp >> 4;
@@ -189,47 +291,14 @@ __device__ void inverse_regs(const double *Lout, int N_t, int N_tp, double *rowb
 #pragma unroll
             for (int r = 0; r < 4; ++r) X[h][J][r] = (J == I && 4 * g + r == l16) ? 1.0 : 0.0;
     }
-    for (int j = 0; j < N_t; ++j) {
-        const int jb = j >> 4;
-        // the owners of row j (lanes of group g = (j%16)/4, register j%4) publish all four of
-        // their rows, so no register is selected by a run-time index; readers take slot j%4
-        double *rb = rowbuf + ((j & 1) << 9);
-        if (g == ((j & 15) >> 2)) {
-#pragma unroll
-            for (int h = 0; h < 2; ++h) {
-                const int I = h ? 7 - w : w;
-                if (I == jb) {
-#pragma unroll
-                    for (int J = 0; J < 8; ++J)
-                        if (J <= jb) {
-#pragma unroll
-                            for (int r = 0; r < 4; ++r) rb[(r << 7) + 16 * J + l16] = X[h][J][r];
-                        }
-                }
-            }
-        }
-        __syncthreads();
-        const double *rj = rb + ((j & 3) << 7);
-        const double inv_ljj = 1.0 / Lout[tri(j) + j];
-#pragma unroll
-        for (int h = 0; h < 2; ++h) {
-            const int I = h ? 7 - w : w;
-            if (I < nbr && I >= jb) {
-                double lt[4];
-#pragma unroll
-                for (int r = 0; r < 4; ++r) {
-                    const int t = 16 * I + 4 * g + r;
-                    lt[r] = (t > j && t < N_t) ? Lout[tri(t) + j] * inv_ljj : 0.0;
-                }
-#pragma unroll
-                for (int J = 0; J < 8; ++J) {
-                    const double xc = (J <= jb && J <= I) ? rj[16 * J + l16] : 0.0;
-#pragma unroll
-                    for (int r = 0; r < 4; ++r) X[h][J][r] = fma(-lt[r], xc, X[h][J][r]);
-                }
-            }
-        }
-    }
+    inv_block<0>(X, Lout, N_t, nbr, rowbuf);
+    if (nbr > 1) inv_block<1>(X, Lout, N_t, nbr, rowbuf);
+    if (nbr > 2) inv_block<2>(X, Lout, N_t, nbr, rowbuf);
+    if (nbr > 3) inv_block<3>(X, Lout, N_t, nbr, rowbuf);
+    if (nbr > 4) inv_block<4>(X, Lout, N_t, nbr, rowbuf);
+    if (nbr > 5) inv_block<5>(X, Lout, N_t, nbr, rowbuf);
+    if (nbr > 6) inv_block<6>(X, Lout, N_t, nbr, rowbuf);
+    if (nbr > 7) inv_block<7>(X, Lout, N_t, nbr, rowbuf);
     // sub-blocks outside the factored part: zero above the diagonal, identity on the padding
     for (int o = tid; o < N_tp * N_tp; o += blockDim.x) {
         const int sb = o >> 8, ww = o & 255, ln = ww >> 2, reg = ww & 3;
@@ -264,7 +333,7 @@ __device__ void inverse_regs(const double *Lout, int N_t, int N_tp, double *rowb
 
 // Argmax of the gains (exact ties -> lowest position, NaN -> -inf) or the position of a forced
 // sensor.  Returns the position (same in all threads) or -1 after setting the status word.
-__device__ int select_winner(const int *__restrict__ act_in, int n_act, const double *__restrict__ gains,
+__device__ __forceinline__ int select_winner(const int *__restrict__ act_in, int n_act, const double *__restrict__ gains,
                              int forced, int *state, double *gain_out)
 {
     __shared__ double red_g[4];

@@ -82,11 +82,13 @@ struct StepDesc {
     int64_t nitems;        // work items of this instance (gain, trsm: n_act; pick: 1; syrk: tiles)
 };
 
-// Tiles of the downdate over n remaining candidates (128 x 128 tiles of the lower triangle).
-inline int64_t syrk_tiles(int n_act, int N_tp)
+// Work items (tile slots) of the downdate over n remaining candidates: 128 x 128 tiles of the
+// lower triangle, grouped in 8 x 8 super-tiles of 64 slots each (see super_tile()).
+__host__ __device__ inline int64_t syrk_tile_rows(int n_act, int N_tp) { return ((int64_t)n_act * N_tp + 127) / 128; }
+__host__ __device__ inline int64_t syrk_tiles(int n_act, int N_tp)
 {
-    const int64_t T = ((int64_t)n_act * N_tp + 127) / 128;
-    return T * (T + 1) / 2;
+    const int64_t ST = (syrk_tile_rows(n_act, N_tp) + 7) / 8;
+    return 64 * (ST * (ST + 1) / 2);
 }
 
 hipError_t launch_pack(const void *K, int kdtype, int64_t ld, int N_t, int N_tp, const int *cmap, int N_c,

@@ -84,7 +84,8 @@ __device__ void syrk_direct_body(const StepDesc &d, int64_t tile)
     const T *__restrict__ W = (const T *)d.W;
     const int *__restrict__ act = d.act_in;
     const int n_act = d.n_act, N_tp = d.N_tp;
-    const int64_t P = tri_row(tile), Q = tile - P * (P + 1) / 2;
+    int64_t P, Q;
+    if (!super_tile(tile, syrk_tile_rows(d.n_act, d.N_tp), P, Q)) return;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, wr = wave >> 1, wc = wave & 1;
     const int alane = a_lane<T>(lane);
     const int nb = N_tp >> 4;
@@ -163,7 +164,8 @@ __device__ void syrk_lds_body(const StepDesc &d, int64_t tile)
     const T *__restrict__ W = (const T *)d.W;
     const int *__restrict__ act = d.act_in;
     const int n_act = d.n_act;
-    const int64_t P = tri_row(tile), Q = tile - P * (P + 1) / 2;
+    int64_t P, Q;
+    if (!super_tile(tile, syrk_tile_rows(d.n_act, d.N_tp), P, Q)) return;
     const int tid = threadIdx.x;
     const int lane = tid & 63, wave = tid >> 6, wr = wave >> 1, wc = wave & 1;
     const int alane = a_lane<T>(lane);
