@@ -165,6 +165,56 @@ typedef struct oed_profile {
 /* Read (and with reset != 0 clear) the accumulated profile.  Needs OED_FLAG_PROFILE. */
 OED_API oed_status oed_get_profile(oed_ctx *h, oed_profile *out, int32_t reset);
 
+/*
+ * Batched selection: many independent designs of uneven sizes (candidate counts, N_t, sigma2,
+ * budgets) selected together.  Every step's work for all instances still running is issued
+ * as one launch per kernel (gains, pick, block column, downdate per block size), and the whole
+ * schedule of all steps is captured once into a HIP graph, so oed_batch_run is one graph
+ * launch plus one copy of the results.  Same precisions and conventions as the single-design
+ * calls; every instance needs 1 <= N_t <= 128.
+ */
+typedef struct oed_instance {
+    const void *K_dev;  /* device, row-major, lower triangle read (during create / reset only) */
+    int32_t dtype;      /* OED_F64 or OED_F32 */
+    int32_t N_s, N_t;   /* sensors and observations per sensor */
+    int32_t budget;     /* picks, 1 <= budget <= N_s */
+    int64_t ld;         /* leading dimension of K, >= N_s * N_t */
+    double sigma2;      /* noise variance, > 0 */
+} oed_instance;
+
+typedef struct oed_batch oed_batch;
+
+/* Don't capture the schedule into a HIP graph: enqueue the launches on every run. */
+#define OED_BATCH_NO_GRAPH 0x2u
+
+/*
+ * Create a batch over inst[0..n): validates every instance, allocates all device memory,
+ * packs every working copy and builds the launch schedule.  flags: OED_FLAG_PROFILE (time
+ * each run with HIP events), OED_BATCH_NO_GRAPH.  On failure *out is NULL.
+ */
+OED_API oed_status oed_batch_create(oed_batch **out, const oed_instance *inst, int32_t n, int32_t precision,
+                                    void *stream, uint32_t flags);
+
+/*
+ * Run every instance's greedy selection from its start.  Outputs (host):
+ * idx_out / gain_out: picks of instance i at offset sum_{j<i} budget_j, length budget_i;
+ * n_out[i]: picks made; status_out[i]: OED_OK, or OED_E_NOT_SPD if instance i stopped early.
+ * A second run without oed_batch_reset selects on the already conditioned working copies and
+ * is rejected (OED_E_STATE).
+ */
+OED_API oed_status oed_batch_run(oed_batch *b, int32_t *idx_out, double *gain_out, int32_t *n_out,
+                                 int32_t *status_out);
+
+/* Reload every working copy from inst[] (same shapes as at creation); allocates nothing. */
+OED_API oed_status oed_batch_reset(oed_batch *b, const oed_instance *inst, int32_t n);
+
+/* Milliseconds of the last run (HIP events around it; needs OED_FLAG_PROFILE), and the
+ * algorithmic downdate flops and bytes of one run (definitions as in oed_profile). */
+OED_API oed_status oed_batch_stats(const oed_batch *b, double *run_ms, double *syrk_flops, double *syrk_bytes);
+
+OED_API oed_status oed_batch_destroy(oed_batch *b);
+OED_API const char *oed_batch_last_error(const oed_batch *b);
+
 /* Bytes of device memory the handle holds. */
 OED_API oed_status oed_device_bytes(const oed_ctx *h, int64_t *bytes);
 

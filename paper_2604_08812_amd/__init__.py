@@ -5,6 +5,12 @@ The selection runs in liboed.so (HIP kernels behind the C ABI of
 """
 from .oed import (  # noqa: F401
     EXPORTED,
+    BatchSelector,
+    oed_batch_create,
+    oed_batch_destroy,
+    oed_batch_reset,
+    oed_batch_run,
+    oed_batch_stats,
     LIB_PATH,
     OedError,
     PRECISIONS,

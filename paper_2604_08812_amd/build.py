@@ -8,7 +8,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "liboed.so")
-SOURCES = ["oed_pack.hip", "oed_factor.hip", "oed_update.hip", "oed_api.cpp"]
+SOURCES = ["oed_pack.hip", "oed_factor.hip", "oed_update.hip", "oed_api.cpp", "oed_batch.cpp"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 FLAGS = [

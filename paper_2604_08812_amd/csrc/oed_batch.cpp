@@ -1,0 +1,418 @@
+// Batched selection over many independent designs (declarations and contract in include/oed.h).
+//
+// Each instance has its own working copy, W blocks, active lists and state words.  The
+// schedule of the whole run is known on the host before anything executes (instance i runs
+// budget_i steps; after its k-th pick N_c - k - 1 candidates remain), so all step descriptors
+// are built once and uploaded once, and a run is a fixed sequence of batched launches:
+//   init state (per instance), then for every step k:
+//   gains (all instances with budget > k), pick (same), and, for the instances that pick again,
+//   the block column W and the downdate (one launch per padded block size N_tp).
+// That sequence is captured into a HIP graph on the first run and replayed afterwards.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <map>
+#include <string>
+#include <vector>
+
+#include "../../include/oed.h"
+#include "oed_internal.h"
+
+using namespace oed;
+
+namespace {
+
+struct Inst {
+    int N_s = 0, N_t = 0, N_tp = 0, budget = 0, kdtype = 0;
+    int64_t ld = 0;
+    double sigma2 = 0, half_noise = 0;
+    void *R = nullptr, *W = nullptr;
+    double *Linv = nullptr, *gains = nullptr, *pick_gain = nullptr;
+    int *act[2] = {nullptr, nullptr}, *cmap = nullptr, *picks = nullptr, *state = nullptr;
+    size_t off_gain = 0, off_int = 0;  // offsets of this instance's results in the results block
+};
+
+enum LaunchKind { L_INIT, L_GAIN, L_PICK, L_TRSM, L_SYRK };
+
+struct Launch {
+    int kind = L_INIT;
+    int inst = -1;       // L_INIT
+    int64_t desc0 = 0;   // first descriptor
+    int ndesc = 0;
+    int64_t total = 0;   // work items
+    int N_tp = 0;        // L_SYRK
+    int max_Nt = 0;      // L_PICK
+};
+
+Launch make_launch(int kind, int64_t desc0)
+{
+    Launch L;
+    L.kind = kind;
+    L.desc0 = desc0;
+    return L;
+}
+
+}  // namespace
+
+struct oed_batch {
+    std::vector<Inst> in;
+    int prec = OED_PREC_FP64, rtype = R_F64, wtype = W_F64;
+    uint32_t flags = 0;
+    hipStream_t stream = nullptr;
+    std::vector<void *> allocs;
+    char *results = nullptr;  // [gains of all picks (double)][picks + state words (int)]
+    size_t results_bytes = 0, n_gain = 0;
+    StepDesc *d_descs = nullptr;
+    std::vector<StepDesc> descs;
+    std::vector<Launch> launches;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    hipEvent_t ev0 = nullptr, ev1 = nullptr;
+    bool ran = false;
+    double last_ms = 0, syrk_flops = 0, syrk_bytes = 0;
+    std::string err;
+};
+
+namespace {
+
+oed_status bfail(oed_batch *b, oed_status st, const std::string &msg)
+{
+    if (b) b->err = msg;
+    return st;
+}
+
+#define BCHK(b, call)                                                                                       \
+    do {                                                                                                    \
+        hipError_t e_ = (call);                                                                             \
+        if (e_ != hipSuccess)                                                                               \
+            return bfail(b, e_ == hipErrorOutOfMemory ? OED_E_OOM : OED_E_HIP,                             \
+                         std::string(#call) + ": " + hipGetErrorString(e_));                                \
+    } while (0)
+
+hipError_t balloc(oed_batch *b, void **p, size_t bytes)
+{
+    hipError_t e = hipMalloc(p, bytes);
+    if (e == hipSuccess) b->allocs.push_back(*p);
+    return e;
+}
+
+void bfree(oed_batch *b)
+{
+    if (b->exec) (void)hipGraphExecDestroy(b->exec);
+    if (b->graph) (void)hipGraphDestroy(b->graph);
+    for (void *p : b->allocs) (void)hipFree(p);
+    b->allocs.clear();
+    if (b->ev0) (void)hipEventDestroy(b->ev0);
+    if (b->ev1) (void)hipEventDestroy(b->ev1);
+    if (b->stream) (void)hipStreamDestroy(b->stream);
+}
+
+oed_status check_instances(const oed_instance *inst, int32_t n)
+{
+    if (!inst || n < 1) return OED_E_ARG;
+    for (int i = 0; i < n; ++i) {
+        const oed_instance &x = inst[i];
+        if (!x.K_dev || (x.dtype != OED_F64 && x.dtype != OED_F32) || x.N_s < 1 || x.N_t < 1 ||
+            x.ld < (int64_t)x.N_s * x.N_t || !(x.sigma2 > 0.0) || !std::isfinite(x.sigma2) || x.budget < 1 ||
+            x.budget > x.N_s)
+            return OED_E_ARG;
+        if (x.N_t > REGS_MAX_NT) return OED_E_UNSUPPORTED;
+    }
+    return OED_OK;
+}
+
+oed_status pack_all(oed_batch *b, const oed_instance *inst)
+{
+    for (size_t i = 0; i < b->in.size(); ++i) {
+        const Inst &x = b->in[i];
+        BCHK(b, launch_pack(inst[i].K_dev, x.kdtype, x.ld, x.N_t, x.N_tp, x.cmap, x.N_s, x.R, b->rtype, b->stream));
+    }
+    BCHK(b, hipStreamSynchronize(b->stream));
+    b->ran = false;
+    return OED_OK;
+}
+
+StepDesc inst_desc(const Inst &x, int k, bool after_pick)
+{
+    StepDesc d{};
+    d.R = x.R;
+    d.W = x.W;
+    d.act_in = x.act[(k + (after_pick ? 1 : 0)) & 1];
+    d.act_out = x.act[(k + 1) & 1];
+    d.gains = x.gains;
+    d.Linv = x.Linv;
+    d.state = x.state;
+    d.picks = x.picks;
+    d.pick_gain = x.pick_gain;
+    d.half_noise = x.half_noise;
+    d.n_act = x.N_s - k - (after_pick ? 1 : 0);
+    d.N_t = x.N_t;
+    d.N_tp = x.N_tp;
+    d.step = k;
+    d.forced = -1;
+    return d;
+}
+
+// Build the descriptor array and the launch list of one run.
+void build_schedule(oed_batch *b)
+{
+    b->descs.clear();
+    b->launches.clear();
+    b->syrk_flops = b->syrk_bytes = 0;
+    const double e = b->rtype == R_F64 ? 8.0 : 4.0;
+    int maxB = 0;
+    for (size_t i = 0; i < b->in.size(); ++i) {
+        maxB = std::max(maxB, b->in[i].budget);
+        Launch L = make_launch(L_INIT, 0);
+        L.inst = (int)i;
+        b->launches.push_back(L);
+    }
+    for (int k = 0; k < maxB; ++k) {
+        // gains and pick of step k
+        Launch g = make_launch(L_GAIN, (int64_t)b->descs.size());
+        for (const Inst &x : b->in)
+            if (x.budget > k) {
+                StepDesc d = inst_desc(x, k, false);
+                d.item0 = g.total;
+                d.nitems = d.n_act;
+                g.total += d.nitems;
+                b->descs.push_back(d);
+                ++g.ndesc;
+            }
+        b->launches.push_back(g);
+        Launch p = make_launch(L_PICK, (int64_t)b->descs.size());
+        for (const Inst &x : b->in)
+            if (x.budget > k) {
+                StepDesc d = inst_desc(x, k, false);
+                d.item0 = p.total;
+                d.nitems = 1;
+                p.total += 1;
+                p.max_Nt = std::max(p.max_Nt, x.N_t);
+                b->descs.push_back(d);
+                ++p.ndesc;
+            }
+        b->launches.push_back(p);
+        // downdate for the instances that pick again
+        Launch t = make_launch(L_TRSM, (int64_t)b->descs.size());
+        std::map<int, std::vector<const Inst *>> by_ntp;
+        for (const Inst &x : b->in)
+            if (x.budget > k + 1) {
+                StepDesc d = inst_desc(x, k, true);
+                d.item0 = t.total;
+                d.nitems = d.n_act;
+                t.total += d.nitems;
+                b->descs.push_back(d);
+                ++t.ndesc;
+                by_ntp[x.N_tp].push_back(&x);
+                const double nr = (double)d.n_act * x.N_t;
+                b->syrk_flops += (double)x.N_t * nr * (nr + 1.0);
+                b->syrk_bytes += e * (nr * (nr + x.N_t) + nr * x.N_t);
+            }
+        if (t.ndesc == 0) continue;
+        b->launches.push_back(t);
+        for (auto &kv : by_ntp) {
+            Launch s = make_launch(L_SYRK, (int64_t)b->descs.size());
+            s.N_tp = kv.first;
+            for (const Inst *x : kv.second) {
+                StepDesc d = inst_desc(*x, k, true);
+                d.item0 = s.total;
+                d.nitems = syrk_tiles(d.n_act, d.N_tp);
+                s.total += d.nitems;
+                b->descs.push_back(d);
+                ++s.ndesc;
+            }
+            b->launches.push_back(s);
+        }
+    }
+}
+
+oed_status enqueue_run(oed_batch *b)
+{
+    for (const Launch &L : b->launches) {
+        const StepDesc *d = b->d_descs + L.desc0;
+        switch (L.kind) {
+        case L_INIT: {
+            const Inst &x = b->in[L.inst];
+            BCHK(b, launch_init_state(x.act[0], x.N_s, x.state, b->stream));
+            break;
+        }
+        case L_GAIN: BCHK(b, launch_gain_batched(d, L.ndesc, L.total, b->rtype, b->stream)); break;
+        case L_PICK: BCHK(b, launch_pick_batched(d, L.ndesc, L.max_Nt, b->rtype, b->stream)); break;
+        case L_TRSM: BCHK(b, launch_trsm_batched(d, L.ndesc, L.total, b->rtype, b->wtype, b->stream)); break;
+        case L_SYRK:
+            BCHK(b, launch_syrk_batched(d, L.ndesc, L.total, L.N_tp, b->rtype, b->wtype, SYRK_LDS, b->stream));
+            break;
+        }
+    }
+    return OED_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+oed_status oed_batch_create(oed_batch **out, const oed_instance *inst, int32_t n, int32_t precision, void *stream,
+                            uint32_t flags)
+{
+    if (!out) return OED_E_ARG;
+    *out = nullptr;
+    oed_status st = check_instances(inst, n);
+    if (st != OED_OK) return st;
+    if (precision != OED_PREC_FP64 && precision != OED_PREC_MIXED_F32) return OED_E_UNSUPPORTED;
+    oed_batch *b = new (std::nothrow) oed_batch();
+    if (!b) return OED_E_OOM;
+    b->prec = precision;
+    b->rtype = precision == OED_PREC_FP64 ? R_F64 : R_F32;
+    b->wtype = precision == OED_PREC_FP64 ? W_F64 : W_F32;
+    b->flags = flags;
+    auto setup = [&]() -> oed_status {
+        // the caller's K must be complete before the batch stream reads it
+        BCHK(b, hipStreamSynchronize((hipStream_t)stream));
+        BCHK(b, hipStreamCreateWithFlags(&b->stream, hipStreamNonBlocking));
+        BCHK(b, hipEventCreate(&b->ev0));
+        BCHK(b, hipEventCreate(&b->ev1));
+        const size_t er = b->rtype == R_F64 ? 8 : 4;
+        size_t n_gain = 0, n_int = 0;
+        b->in.resize(n);
+        for (int i = 0; i < n; ++i) {
+            Inst &x = b->in[i];
+            const oed_instance &y = inst[i];
+            x.N_s = y.N_s;
+            x.N_t = y.N_t;
+            x.N_tp = (y.N_t + 15) / 16 * 16;
+            x.budget = y.budget;
+            x.kdtype = y.dtype;
+            x.ld = y.ld;
+            x.sigma2 = y.sigma2;
+            x.half_noise = 0.5 * y.N_t * std::log(y.sigma2);
+            const int64_t bs = (int64_t)x.N_tp * x.N_tp, nblk = (int64_t)x.N_s * (x.N_s + 1) / 2;
+            BCHK(b, balloc(b, &x.R, (size_t)(nblk * bs) * er));
+            BCHK(b, balloc(b, &x.W, (size_t)(x.N_s * bs) * er));
+            BCHK(b, balloc(b, (void **)&x.Linv, sizeof(double) * bs));
+            BCHK(b, balloc(b, (void **)&x.gains, sizeof(double) * x.N_s));
+            BCHK(b, balloc(b, (void **)&x.act[0], sizeof(int) * x.N_s));
+            BCHK(b, balloc(b, (void **)&x.act[1], sizeof(int) * x.N_s));
+            BCHK(b, balloc(b, (void **)&x.cmap, sizeof(int) * x.N_s));
+            std::vector<int> id(x.N_s);
+            for (int q = 0; q < x.N_s; ++q) id[q] = q;
+            BCHK(b, hipMemcpy(x.cmap, id.data(), sizeof(int) * x.N_s, hipMemcpyHostToDevice));
+            x.off_gain = n_gain;
+            n_gain += x.budget;
+            x.off_int = n_int;
+            n_int += x.budget + ST_WORDS;
+        }
+        b->n_gain = n_gain;
+        b->results_bytes = sizeof(double) * n_gain + sizeof(int) * n_int;
+        BCHK(b, balloc(b, (void **)&b->results, b->results_bytes));
+        int *ires = (int *)(b->results + sizeof(double) * n_gain);
+        for (Inst &x : b->in) {
+            x.pick_gain = (double *)b->results + x.off_gain;
+            x.picks = ires + x.off_int;
+            x.state = x.picks + x.budget;
+        }
+        build_schedule(b);
+        BCHK(b, balloc(b, (void **)&b->d_descs, sizeof(StepDesc) * std::max<size_t>(1, b->descs.size())));
+        BCHK(b, hipMemcpy(b->d_descs, b->descs.data(), sizeof(StepDesc) * b->descs.size(), hipMemcpyHostToDevice));
+        return pack_all(b, inst);
+    };
+    st = setup();
+    if (st != OED_OK) {
+        bfree(b);
+        delete b;
+        return st;
+    }
+    *out = b;
+    return OED_OK;
+}
+
+oed_status oed_batch_reset(oed_batch *b, const oed_instance *inst, int32_t n)
+{
+    if (!b) return OED_E_ARG;
+    if (n != (int32_t)b->in.size() || check_instances(inst, n) != OED_OK) return bfail(b, OED_E_ARG, "bad instances");
+    for (int i = 0; i < n; ++i)
+        if (inst[i].N_s != b->in[i].N_s || inst[i].N_t != b->in[i].N_t || inst[i].budget != b->in[i].budget ||
+            inst[i].dtype != b->in[i].kdtype || inst[i].ld != b->in[i].ld)
+            return bfail(b, OED_E_ARG, "instance shape differs from creation");
+    return pack_all(b, inst);
+}
+
+oed_status oed_batch_run(oed_batch *b, int32_t *idx_out, double *gain_out, int32_t *n_out, int32_t *status_out)
+{
+    if (!b || !idx_out || !gain_out || !n_out || !status_out) return OED_E_ARG;
+    if (b->ran) return bfail(b, OED_E_STATE, "batch already ran: reset it first");
+    const bool graph = !(b->flags & OED_BATCH_NO_GRAPH);
+    if (graph && !b->exec) {
+        BCHK(b, hipStreamBeginCapture(b->stream, hipStreamCaptureModeRelaxed));
+        oed_status st = enqueue_run(b);
+        hipGraph_t g = nullptr;
+        hipError_t e = hipStreamEndCapture(b->stream, &g);
+        if (st != OED_OK) {
+            if (g) (void)hipGraphDestroy(g);
+            return st;
+        }
+        BCHK(b, e);
+        b->graph = g;
+        BCHK(b, hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0));
+    }
+    const bool prof = b->flags & OED_FLAG_PROFILE;
+    if (prof) BCHK(b, hipEventRecord(b->ev0, b->stream));
+    if (graph) {
+        BCHK(b, hipGraphLaunch(b->exec, b->stream));
+    } else {
+        oed_status st = enqueue_run(b);
+        if (st != OED_OK) return st;
+    }
+    if (prof) BCHK(b, hipEventRecord(b->ev1, b->stream));
+    std::vector<char> h(b->results_bytes);
+    BCHK(b, hipMemcpyAsync(h.data(), b->results, b->results_bytes, hipMemcpyDeviceToHost, b->stream));
+    BCHK(b, hipStreamSynchronize(b->stream));
+    b->ran = true;
+    if (prof) {
+        float ms = 0;
+        BCHK(b, hipEventElapsedTime(&ms, b->ev0, b->ev1));
+        b->last_ms = ms;
+    }
+    const double *hg = (const double *)h.data();
+    const int *hi = (const int *)(h.data() + sizeof(double) * b->n_gain);
+    size_t o = 0;
+    oed_status worst = OED_OK;
+    for (size_t i = 0; i < b->in.size(); ++i) {
+        const Inst &x = b->in[i];
+        const int *picks = hi + x.off_int, *state = picks + x.budget;
+        const int made = std::max(0, std::min(x.budget, state[ST_NPICKS]));
+        for (int q = 0; q < x.budget; ++q) {
+            idx_out[o + q] = q < made ? picks[q] : -1;
+            gain_out[o + q] = q < made ? hg[x.off_gain + q] : NAN;
+        }
+        n_out[i] = made;
+        status_out[i] = state[ST_STATUS] == 0 ? OED_OK : state[ST_STATUS] == 2 ? OED_E_NOT_SPD : OED_E_STATE;
+        if (status_out[i] != OED_OK) worst = OED_E_NOT_SPD;
+        o += x.budget;
+    }
+    if (worst != OED_OK) return bfail(b, worst, "an instance stopped early; see status_out");
+    return OED_OK;
+}
+
+oed_status oed_batch_stats(const oed_batch *b, double *run_ms, double *syrk_flops, double *syrk_bytes)
+{
+    if (!b) return OED_E_ARG;
+    if (run_ms) *run_ms = b->last_ms;
+    if (syrk_flops) *syrk_flops = b->syrk_flops;
+    if (syrk_bytes) *syrk_bytes = b->syrk_bytes;
+    return OED_OK;
+}
+
+oed_status oed_batch_destroy(oed_batch *b)
+{
+    if (!b) return OED_OK;
+    if (b->stream) (void)hipStreamSynchronize(b->stream);
+    bfree(b);
+    delete b;
+    return OED_OK;
+}
+
+const char *oed_batch_last_error(const oed_batch *b) { return b ? b->err.c_str() : "null batch"; }
+
+}  // extern "C"

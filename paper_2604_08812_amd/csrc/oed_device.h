@@ -62,6 +62,7 @@ __device__ __forceinline__ int tri(int t) { return t * (t + 1) / 2; }
 // Largest i with i(i+1)/2 <= b.
 __device__ __forceinline__ int64_t tri_row(int64_t b)
 {
+    if (b <= 0) return b < 0 ? -1 : 0;
     int64_t i = (int64_t)((sqrt(8.0 * (double)b + 1.0) - 1.0) * 0.5);
     while ((i + 1) * (i + 2) / 2 <= b) ++i;
     while (i * (i + 1) / 2 > b) --i;
@@ -69,7 +70,7 @@ __device__ __forceinline__ int64_t tri_row(int64_t b)
 }
 
 // Instance of a batched launch that owns work item `item`: the last descriptor with
-// item0 <= item (descriptors are sorted by item0).  -1 if the item is past its instance's end.
+// item0 <= item (descriptors are sorted by item0).  -1 if no instance owns the item.
 __device__ __forceinline__ int find_instance(const StepDesc *ds, int n, int64_t item)
 {
     int lo = 0, hi = n - 1;
@@ -80,7 +81,7 @@ __device__ __forceinline__ int find_instance(const StepDesc *ds, int n, int64_t 
         else
             hi = mid - 1;
     }
-    return item < ds[lo].item0 + ds[lo].nitems ? lo : -1;
+    return (item >= ds[lo].item0 && item < ds[lo].item0 + ds[lo].nitems) ? lo : -1;
 }
 
 // Downdate tile order: the 128 x 128 tiles (P, Q), Q <= P, of the lower triangle are grouped
@@ -90,6 +91,7 @@ __device__ __forceinline__ int find_instance(const StepDesc *ds, int n, int64_t 
 // Returns false for slots outside the triangle or past the last tile row T.
 __device__ __forceinline__ bool super_tile(int64_t slot, int64_t T, int64_t &P, int64_t &Q)
 {
+    if (slot < 0) return false;
     const int64_t st = slot >> 6, r = slot & 63;
     const int64_t SP = tri_row(st), SQ = st - SP * (SP + 1) / 2;
     P = SP * 8 + (r >> 3);

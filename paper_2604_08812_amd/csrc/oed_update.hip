@@ -373,10 +373,11 @@ template <typename T>
 static hipError_t launch_syrk_t(const StepDesc *descs, const StepDesc &d, int n, int64_t total, int N_tp,
                                 int variant, hipStream_t s)
 {
+    if (N_tp < 16 || N_tp % 16 != 0) return hipErrorInvalidValue;
     const int64_t per_xcd = (total + 7) / 8;
     const dim3 grid((unsigned)(per_xcd * 8)), block(256);
     const int nb = N_tp / 16;
-    if (variant == SYRK_LDS && nb <= 8 && N_tp % 16 == 0) {
+    if (variant == SYRK_LDS && nb <= 8) {
         switch (nb) {
 #define OED_SYRK_CASE(NBV)                                                                                    \
     case NBV:                                                                                                 \

@@ -34,6 +34,15 @@ class oed_profile(ctypes.Structure):
                 ("syrk_bytes", ctypes.c_double)]
 
 
+class oed_instance(ctypes.Structure):
+    _fields_ = [("K_dev", ctypes.c_void_p), ("dtype", ctypes.c_int32), ("N_s", ctypes.c_int32),
+                ("N_t", ctypes.c_int32), ("budget", ctypes.c_int32), ("ld", ctypes.c_int64),
+                ("sigma2", ctypes.c_double)]
+
+
+OED_BATCH_NO_GRAPH = 2
+
+
 class OedError(RuntimeError):
     def __init__(self, status, msg):
         super().__init__(f"{_status_name(status)}: {msg}")
@@ -69,8 +78,17 @@ def library() -> ctypes.CDLL:
     L.oed_last_error.restype = ctypes.c_char_p
     L.oed_status_string.argtypes = [ctypes.c_int32]
     L.oed_status_string.restype = ctypes.c_char_p
+    L.oed_batch_create.argtypes = [ctypes.POINTER(vp), ctypes.POINTER(oed_instance), ctypes.c_int32, ctypes.c_int32,
+                                   vp, ctypes.c_uint32]
+    L.oed_batch_run.argtypes = [vp, ip, dp, ip, ip]
+    L.oed_batch_reset.argtypes = [vp, ctypes.POINTER(oed_instance), ctypes.c_int32]
+    L.oed_batch_stats.argtypes = [vp, dp, dp, dp]
+    L.oed_batch_destroy.argtypes = [vp]
+    L.oed_batch_last_error.argtypes = [vp]
+    L.oed_batch_last_error.restype = ctypes.c_char_p
     for name in ("oed_create", "oed_reset", "oed_greedy", "oed_force", "oed_scores", "oed_schur_block", "oed_picks",
-                 "oed_get_profile", "oed_device_bytes", "oed_destroy"):
+                 "oed_get_profile", "oed_device_bytes", "oed_destroy", "oed_batch_create", "oed_batch_run",
+                 "oed_batch_reset", "oed_batch_stats", "oed_batch_destroy"):
         getattr(L, name).restype = ctypes.c_int32
     _lib = L
     return L
@@ -78,7 +96,8 @@ def library() -> ctypes.CDLL:
 
 EXPORTED = ("oed_options_init", "oed_create", "oed_reset", "oed_greedy", "oed_force", "oed_scores",
             "oed_schur_block", "oed_picks", "oed_get_profile", "oed_device_bytes", "oed_destroy", "oed_last_error",
-            "oed_status_string")
+            "oed_status_string", "oed_batch_create", "oed_batch_run", "oed_batch_reset", "oed_batch_stats",
+            "oed_batch_destroy", "oed_batch_last_error")
 
 
 def _status_name(s):
@@ -193,6 +212,103 @@ def oed_device_bytes(h):
 def oed_destroy(h):
     if h:
         library().oed_destroy(h)
+
+
+def _instances(items):
+    """items: sequence of (K tensor, N_s, N_t, sigma2, budget)."""
+    import torch
+    arr = (oed_instance * len(items))()
+    for q, (K, N_s, N_t, sigma2, budget) in enumerate(items):
+        if not isinstance(K, torch.Tensor) or not K.is_cuda or K.dim() != 2 or K.stride(1) != 1:
+            raise ValueError("K must be a 2-D row-major device tensor")
+        if K.shape[0] < N_s * N_t or K.shape[1] < N_s * N_t:
+            raise ValueError("K must have at least N_s*N_t rows and columns")
+        dt = {torch.float64: OED_F64, torch.float32: OED_F32}.get(K.dtype)
+        if dt is None:
+            raise ValueError("K must be float64 or float32")
+        arr[q] = oed_instance(K.data_ptr(), dt, int(N_s), int(N_t), int(budget), K.stride(0), float(sigma2))
+    return arr
+
+
+def _bcheck(b, st):
+    if st != OED_OK:
+        msg = library().oed_batch_last_error(b).decode() if b else ""
+        raise OedError(st, msg)
+
+
+def oed_batch_create(items, precision="fp64", profile=False, graph=True, stream=None):
+    arr = _instances(items)
+    b = ctypes.c_void_p()
+    flags = (OED_FLAG_PROFILE if profile else 0) | (0 if graph else OED_BATCH_NO_GRAPH)
+    st = library().oed_batch_create(ctypes.byref(b), arr, len(items), PRECISIONS[precision], _stream_handle(stream),
+                                    flags)
+    _bcheck(None, st)
+    return b
+
+
+def oed_batch_run(b, budgets, check=True):
+    tot = int(sum(budgets))
+    idx = np.empty(max(tot, 1), dtype=np.int32)
+    gain = np.empty(max(tot, 1))
+    n = np.zeros(len(budgets), dtype=np.int32)
+    status = np.zeros(len(budgets), dtype=np.int32)
+    st = library().oed_batch_run(b, _ip(idx), _dp(gain), _ip(n), _ip(status))
+    if check:
+        _bcheck(b, st)
+    out, o = [], 0
+    for q, B in enumerate(budgets):
+        out.append((idx[o:o + n[q]].copy(), gain[o:o + n[q]].copy(), int(status[q])))
+        o += B
+    return out, st
+
+
+def oed_batch_reset(b, items):
+    _bcheck(b, library().oed_batch_reset(b, _instances(items), len(items)))
+
+
+def oed_batch_stats(b):
+    ms, fl, by = ctypes.c_double(), ctypes.c_double(), ctypes.c_double()
+    _bcheck(b, library().oed_batch_stats(b, ctypes.byref(ms), ctypes.byref(fl), ctypes.byref(by)))
+    return {"run_ms": ms.value, "syrk_flops": fl.value, "syrk_bytes": by.value}
+
+
+def oed_batch_destroy(b):
+    if b:
+        library().oed_batch_destroy(b)
+
+
+class BatchSelector:
+    """Owns one batch.  ``BatchSelector([(K, N_s, N_t, sigma2, B), ...]).run()`` -> [(idx, gain, status)]."""
+
+    def __init__(self, items, precision="fp64", profile=False, graph=True, stream=None):
+        self.budgets = [int(it[4]) for it in items]
+        self.b = oed_batch_create(items, precision, profile, graph, stream)
+
+    def run(self, check=True):
+        return oed_batch_run(self.b, self.budgets, check)[0]
+
+    def reset(self, items):
+        oed_batch_reset(self.b, items)
+
+    def stats(self):
+        return oed_batch_stats(self.b)
+
+    def close(self):
+        if self.b:
+            oed_batch_destroy(self.b)
+            self.b = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 # ------------------------------------------------------------------ convenience wrapper

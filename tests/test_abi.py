@@ -77,3 +77,21 @@ def test_binding_fails_loudly_without_library(monkeypatch, tmp_path):
     monkeypatch.setattr(b, "LIB_PATH", str(tmp_path / "missing.so"))
     with pytest.raises(ImportError):
         b.library()
+
+
+def test_batch_host_side_validation(lib):
+    from paper_2604_08812_amd.oed import oed_instance
+    b = ctypes.c_void_p()
+    fake = 0x1000  # never dereferenced: validation fails before any device call
+    ok = oed_instance(fake, 0, 8, 16, 4, 128, 1.0)
+    bad_budget = oed_instance(fake, 0, 8, 16, 9, 128, 1.0)
+    big_nt = oed_instance(fake, 0, 2, 160, 1, 320, 1.0)
+    bad_sigma = oed_instance(fake, 0, 8, 16, 4, 128, -1.0)
+    for inst, code in ((bad_budget, 1), (bad_sigma, 1), (big_nt, 6)):
+        arr = (oed_instance * 2)(ok, inst)
+        assert lib.oed_batch_create(ctypes.byref(b), arr, 2, 1, None, 0) == code
+    arr = (oed_instance * 1)(ok)
+    assert lib.oed_batch_create(ctypes.byref(b), arr, 0, 1, None, 0) == 1
+    assert lib.oed_batch_create(ctypes.byref(b), arr, 1, 2, None, 0) == 6   # BF16x3 not batched
+    assert not b.value
+    assert lib.oed_batch_destroy(None) == 0
