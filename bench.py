@@ -22,7 +22,10 @@ import time
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-PEAK_TFLOPS = {"fp64": 78.6, "mixed_f32": 157.3}
+# dense MFMA peaks of the downdate's arithmetic type (the split-product variant runs on BF16)
+PEAK_TFLOPS = {"fp64": 78.6, "mixed_f32": 157.3, "mixed_bf16x3": 2500.0}
+SYRK_KERNEL = {"fp64": "syrk_lds_kernel<double>", "mixed_f32": "syrk_lds_kernel<float>",
+               "mixed_bf16x3": "syrk_bf16_kernel"}
 HBM_PEAK_GBS = 8000.0
 
 
@@ -39,6 +42,7 @@ def parse():
     ap.add_argument("--budget", type=int, default=None, help="override the budget (not the headline)")
     ap.add_argument("--fp64-steps", type=int, default=1)
     ap.add_argument("--no-fp64", action="store_true")
+    ap.add_argument("--no-bf16x3", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-budget", type=int, default=12, help="picks of the oracle sample")
     ap.add_argument("--cpu-sensors", type=int, default=100)
@@ -58,21 +62,47 @@ def timed_selections(sel, K, budget, steps):
 
 
 def roofline_syrk(prof, prec):
+    """The downdate R -= W W^T: algorithmic flops (2 per multiply-add of the lower-triangle
+    blocks) over its summed HIP-event time.  The BF16 split product executes three MFMA
+    products per algorithmic one; its fraction is taken of the BF16 peak on the executed
+    flops, and the HBM view (algorithmic bytes / time) is given beside it."""
     ms = prof["ms"]["syrk"]
     n = max(1, prof["launches"]["syrk"])
     tflops = prof["syrk_flops"] / (ms * 1e-3) / 1e12 if ms > 0 else 0.0
-    return {
-        "kernel": "syrk_kernel",
+    gbs = prof["syrk_bytes"] / (ms * 1e-3) / 1e9 if ms > 0 else 0.0
+    executed = tflops * (3 if prec == "mixed_bf16x3" else 1)
+    out = {
+        "kernel": SYRK_KERNEL[prec],
         "bound": "mfma",
-        "achieved": round(tflops, 3),
+        "achieved": round(executed, 3),
         "peak": PEAK_TFLOPS[prec],
         "unit": "TFLOP/s",
-        "frac": round(tflops / PEAK_TFLOPS[prec], 4),
+        "frac": round(executed / PEAK_TFLOPS[prec], 4),
         "traffic": None,
         "avg_launch_ms": round(ms / n, 4),
         "launches": n,
-        "algorithmic_gbs": round(prof["syrk_bytes"] / (ms * 1e-3) / 1e9, 1) if ms > 0 else 0.0,
+        "algorithmic_tflops": round(tflops, 3),
+        "algorithmic_gbs": round(gbs, 1),
+        "hbm_frac": round(gbs / HBM_PEAK_GBS, 4),
     }
+    if prec == "mixed_bf16x3":
+        # three BF16 products per FP32 one: the kernel is bound by its HBM stream instead
+        out.update({"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                    "frac": round(gbs / HBM_PEAK_GBS, 4), "executed_bf16_tflops": round(executed, 3),
+                    "bf16_mfma_frac": round(executed / PEAK_TFLOPS[prec], 4)})
+    return out
+
+
+def compare_picks(idx, gain, idx_ref, gain_ref):
+    import numpy as np
+    budget = len(idx_ref)
+    agree = int(np.sum(idx == idx_ref))
+    first_div = next((k for k in range(budget) if idx[k] != idx_ref[k]), None)
+    upto = budget if first_div is None else first_div
+    gerr = float(np.max(np.abs(gain[:upto] - gain_ref[:upto]) / np.maximum(1, np.abs(gain_ref[:upto])))) \
+        if upto else 0.0
+    return {"same_picks": agree == budget, "picks_equal_at_position": agree, "first_divergence_step": first_div,
+            "max_rel_gain_diff_before_divergence": gerr}
 
 
 def cpu_baseline(K, N_t, s2, n_sensors, budget):
@@ -211,17 +241,27 @@ def main():
         p64 = sel64.profile(reset=True)
         sel64.close()
         log(f"fp64: {ms64:.1f} ms per selection")
-        agree = int(np.sum(idx == idx64))
-        first_div = next((k for k in range(budget) if idx[k] != idx64[k]), None)
-        upto = budget if first_div is None else first_div
-        gerr = float(np.max(np.abs(gain[:upto] - gain64[:upto]) / np.maximum(1, np.abs(gain64[:upto])))) \
-            if upto else 0.0
         result["fp64"] = {"value": round(budget / (ms64 * 1e-3), 3), "unit": "greedy steps/s",
                           "ms_per_step": round(ms64, 3), "roofline": roofline_syrk(p64, "fp64"),
                           "kernel_ms_per_step": {k: round(v / args.fp64_steps, 3) for k, v in p64["ms"].items()}}
-        result["mixed_vs_fp64"] = {"speedup": round(ms64 / ms, 3), "same_picks": agree == budget,
-                                   "picks_equal_at_position": agree, "first_divergence_step": first_div,
-                                   "max_rel_gain_diff_before_divergence": gerr}
+        result["mixed_vs_fp64"] = {"speedup": round(ms64 / ms, 3), **compare_picks(idx, gain, idx64, gain64)}
+
+    # ---- the BF16 split-product downdate beside it, same K
+    if not args.no_bf16x3 and prec == "mixed_f32" and spec.N_t <= 128:
+        selb = Selector(K, spec.N_s, spec.N_t, s2, precision="mixed_bf16x3", profile=True)
+        timed_selections(selb, K, budget, 1)
+        selb.profile(reset=True)
+        msb, (idxb, gainb) = timed_selections(selb, K, budget, args.steps)
+        pb = selb.profile(reset=True)
+        selb.close()
+        log(f"mixed_bf16x3: {msb:.1f} ms per selection")
+        result["mixed_bf16x3"] = {"value": round(budget / (msb * 1e-3), 3), "unit": "greedy steps/s",
+                                  "ms_per_step": round(msb, 3), "roofline": roofline_syrk(pb, "mixed_bf16x3"),
+                                  "kernel_ms_per_step": {k: round(v / args.steps, 3) for k, v in pb["ms"].items()},
+                                  "speedup_vs_mixed_f32": round(ms / msb, 3),
+                                  "vs_mixed_f32": compare_picks(idxb, gainb, idx, gain)}
+        if "fp64" in result:
+            result["mixed_bf16x3"]["vs_fp64"] = compare_picks(idxb, gainb, idx64, gain64)
 
     # ---- CPU oracle baseline on a bounded sample of the same K
     if not args.no_cpu_baseline:

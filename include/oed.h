@@ -65,9 +65,12 @@ typedef enum oed_dtype { OED_F64 = 0, OED_F32 = 1 } oed_dtype;
  *  MIXED_F32    : R and W stored in FP32, downdate on FP32 MFMA with FP32
  *                 accumulation.  Diagonal-block Cholesky factorisations, gains,
  *                 the winner's factor and the solve forming W run in FP64.
- *  MIXED_BF16X3 : like MIXED_F32, but W is split into BF16 hi + lo parts and
- *                 the product is hi*hi + hi*lo + lo*hi on BF16 MFMA with FP32
- *                 accumulation.
+ *  MIXED_BF16X3 : like MIXED_F32, but W is split into BF16 hi + lo parts
+ *                 (hi = bf16(w), lo = bf16(w - hi)) and the product is
+ *                 hi*hi + hi*lo + lo*hi on BF16 MFMA with FP32 accumulation
+ *                 (relative error of each product term about 2^-16).  Needs
+ *                 N_t <= 128 (else OED_E_UNSUPPORTED); blocks are padded to a
+ *                 multiple of 32 rows instead of 16.
  * The paper keeps K in FP64 and runs the whole candidate loop in FP32 (Sec. IV);
  * MIXED_F32 keeps the precision-critical factorisations in FP64 instead.
  */

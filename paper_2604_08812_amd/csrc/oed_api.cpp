@@ -43,7 +43,7 @@ struct oed_ctx {
     std::vector<int> cmap;  // local -> original sensor index (ascending)
     std::vector<int> lmap;  // original -> local (-1 = not a candidate)
     // device memory
-    void *R = nullptr, *W = nullptr;
+    void *R = nullptr, *W = nullptr, *W2 = nullptr;
     double *Linv = nullptr, *gains = nullptr, *pick_gain = nullptr, *scratch_gain = nullptr,
            *scratch_pick = nullptr;
     int *act[2] = {nullptr, nullptr}, *picks = nullptr, *state = nullptr, *dcmap = nullptr;
@@ -132,7 +132,7 @@ void collect_profile(oed_ctx *h)
 
 void free_all(oed_ctx *h)
 {
-    void *ptrs[] = {h->R, h->W, h->Linv, h->gains, h->pick_gain, h->scratch_gain, h->scratch_pick,
+    void *ptrs[] = {h->R, h->W, h->W2, h->Linv, h->gains, h->pick_gain, h->scratch_gain, h->scratch_pick,
                     h->act[0], h->act[1], h->picks, h->state, h->dcmap};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
@@ -167,6 +167,7 @@ StepDesc desc(const oed_ctx *h)
     StepDesc d{};
     d.R = h->R;
     d.W = h->W;
+    d.W2 = h->W2;
     d.act_in = h->act[h->cur];
     d.act_out = h->act[h->cur ^ 1];
     d.gains = h->gains;
@@ -308,7 +309,7 @@ oed_status oed_create(oed_ctx **out, const void *K, int32_t dtype, int64_t ld, i
         return OED_E_ARG;
     if (o.precision != OED_PREC_FP64 && o.precision != OED_PREC_MIXED_F32 && o.precision != OED_PREC_MIXED_BF16X3)
         return OED_E_ARG;
-    if (o.precision == OED_PREC_MIXED_BF16X3) return OED_E_UNSUPPORTED;
+    if (o.precision == OED_PREC_MIXED_BF16X3 && N_t > 128) return OED_E_UNSUPPORTED;
     for (int r : o.reserved)
         if (r != 0) return OED_E_ARG;
 
@@ -316,14 +317,15 @@ oed_status oed_create(oed_ctx **out, const void *K, int32_t dtype, int64_t ld, i
     if (!h) return OED_E_OOM;
     h->N_s = N_s;
     h->N_t = N_t;
-    h->N_tp = (N_t + 15) / 16 * 16;
+    // the BF16 operands hold 32 inner indices per lane group of four
+    h->N_tp = o.precision == OED_PREC_MIXED_BF16X3 ? (N_t + 31) / 32 * 32 : (N_t + 15) / 16 * 16;
     h->kdtype = dtype;
     h->ld = ld;
     h->sigma2 = sigma2;
     h->half_noise = 0.5 * N_t * std::log(sigma2);
     h->prec = o.precision;
     h->rtype = o.precision == OED_PREC_FP64 ? R_F64 : R_F32;
-    h->wtype = o.precision == OED_PREC_FP64 ? W_F64 : W_F32;
+    h->wtype = o.precision == OED_PREC_FP64 ? W_F64 : o.precision == OED_PREC_MIXED_F32 ? W_F32 : W_BF16X3;
     h->flags = o.flags;
     h->stream = (hipStream_t)stream;
     h->lmap.assign(N_s, -1);
@@ -352,7 +354,8 @@ oed_status oed_create(oed_ctx **out, const void *K, int32_t dtype, int64_t ld, i
         const int64_t bs = (int64_t)h->N_tp * h->N_tp;
         const int64_t nblk = (int64_t)h->N_c * (h->N_c + 1) / 2;
         HIPCHK(h, dmalloc(h, &h->R, (size_t)(nblk * bs) * relem(h)));
-        HIPCHK(h, dmalloc(h, &h->W, (size_t)(h->N_c * bs) * (h->wtype == W_F64 ? 8 : 4)));
+        HIPCHK(h, dmalloc(h, &h->W, (size_t)(h->N_c * bs) * (h->wtype == W_F64 ? 8 : h->wtype == W_F32 ? 4 : 2)));
+        if (h->wtype == W_BF16X3) HIPCHK(h, dmalloc(h, &h->W2, (size_t)(h->N_c * bs) * 2));
         HIPCHK(h, dmalloc(h, (void **)&h->Linv, sizeof(double) * bs));
         HIPCHK(h, dmalloc(h, (void **)&h->gains, sizeof(double) * h->N_c));
         HIPCHK(h, dmalloc(h, (void **)&h->pick_gain, sizeof(double) * h->N_c));

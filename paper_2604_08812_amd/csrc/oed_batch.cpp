@@ -28,7 +28,7 @@ struct Inst {
     int N_s = 0, N_t = 0, N_tp = 0, budget = 0, kdtype = 0;
     int64_t ld = 0;
     double sigma2 = 0, half_noise = 0;
-    void *R = nullptr, *W = nullptr;
+    void *R = nullptr, *W = nullptr, *W2 = nullptr;
     double *Linv = nullptr, *gains = nullptr, *pick_gain = nullptr;
     int *act[2] = {nullptr, nullptr}, *cmap = nullptr, *picks = nullptr, *state = nullptr;
     size_t off_gain = 0, off_int = 0;  // offsets of this instance's results in the results block
@@ -139,6 +139,7 @@ StepDesc inst_desc(const Inst &x, int k, bool after_pick)
     StepDesc d{};
     d.R = x.R;
     d.W = x.W;
+    d.W2 = x.W2;
     d.act_in = x.act[(k + (after_pick ? 1 : 0)) & 1];
     d.act_out = x.act[(k + 1) & 1];
     d.gains = x.gains;
@@ -260,12 +261,13 @@ oed_status oed_batch_create(oed_batch **out, const oed_instance *inst, int32_t n
     *out = nullptr;
     oed_status st = check_instances(inst, n);
     if (st != OED_OK) return st;
-    if (precision != OED_PREC_FP64 && precision != OED_PREC_MIXED_F32) return OED_E_UNSUPPORTED;
+    if (precision != OED_PREC_FP64 && precision != OED_PREC_MIXED_F32 && precision != OED_PREC_MIXED_BF16X3)
+        return OED_E_ARG;
     oed_batch *b = new (std::nothrow) oed_batch();
     if (!b) return OED_E_OOM;
     b->prec = precision;
     b->rtype = precision == OED_PREC_FP64 ? R_F64 : R_F32;
-    b->wtype = precision == OED_PREC_FP64 ? W_F64 : W_F32;
+    b->wtype = precision == OED_PREC_FP64 ? W_F64 : precision == OED_PREC_MIXED_F32 ? W_F32 : W_BF16X3;
     b->flags = flags;
     auto setup = [&]() -> oed_status {
         // the caller's K must be complete before the batch stream reads it
@@ -281,7 +283,7 @@ oed_status oed_batch_create(oed_batch **out, const oed_instance *inst, int32_t n
             const oed_instance &y = inst[i];
             x.N_s = y.N_s;
             x.N_t = y.N_t;
-            x.N_tp = (y.N_t + 15) / 16 * 16;
+            x.N_tp = b->wtype == W_BF16X3 ? (y.N_t + 31) / 32 * 32 : (y.N_t + 15) / 16 * 16;
             x.budget = y.budget;
             x.kdtype = y.dtype;
             x.ld = y.ld;
@@ -289,7 +291,12 @@ oed_status oed_batch_create(oed_batch **out, const oed_instance *inst, int32_t n
             x.half_noise = 0.5 * y.N_t * std::log(y.sigma2);
             const int64_t bs = (int64_t)x.N_tp * x.N_tp, nblk = (int64_t)x.N_s * (x.N_s + 1) / 2;
             BCHK(b, balloc(b, &x.R, (size_t)(nblk * bs) * er));
-            BCHK(b, balloc(b, &x.W, (size_t)(x.N_s * bs) * er));
+            if (b->wtype == W_BF16X3) {
+                BCHK(b, balloc(b, &x.W, (size_t)(x.N_s * bs) * 2));
+                BCHK(b, balloc(b, &x.W2, (size_t)(x.N_s * bs) * 2));
+            } else {
+                BCHK(b, balloc(b, &x.W, (size_t)(x.N_s * bs) * er));
+            }
             BCHK(b, balloc(b, (void **)&x.Linv, sizeof(double) * bs));
             BCHK(b, balloc(b, (void **)&x.gains, sizeof(double) * x.N_s));
             BCHK(b, balloc(b, (void **)&x.act[0], sizeof(int) * x.N_s));

@@ -45,6 +45,26 @@ __device__ __forceinline__ int a_lane<double>(int lane)
     return (lane & 48) | ((lane & 3) << 2) | ((lane & 15) >> 2);
 }
 
+// BF16 (stored as its 16 bits): round to nearest even from FP32, and back.
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+typedef unsigned short u16x4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ unsigned short f2bf(float x)
+{
+    unsigned int u = __float_as_uint(x);
+    u += 0x7FFFu + ((u >> 16) & 1u);
+    return (unsigned short)(u >> 16);
+}
+__device__ __forceinline__ float bf2f(unsigned short h) { return __uint_as_float((unsigned int)h << 16); }
+
+// D += A B on 16 x 16 x 32 BF16 operands (8 per lane, passed as 4 dwords), FP32 accumulation.
+__device__ __forceinline__ floatx4 mfma_bf16(u32x4 a, u32x4 b, floatx4 c)
+{
+    return __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, a), __builtin_bit_cast(bf16x8, b), c, 0,
+                                                   0, 0);
+}
+
 template <typename T>
 __device__ __forceinline__ typename V4<T>::type ld4(const T *p)
 {

@@ -63,7 +63,8 @@ enum StateWord { ST_STATUS = 0, ST_NPICKS = 1, ST_LAST = 2, ST_WORDS = 16 };
 // work-group finds its instance by binary search.
 struct StepDesc {
     void *R;               // working copy (element type by precision)
-    void *W;               // W blocks (element type by precision)
+    void *W;               // W blocks (element type by precision; BF16X3: the hi parts)
+    void *W2;              // BF16X3: the lo parts of W (same layout), else unused
     const int *act_in;     // remaining candidates (gain, pick: before the pick; trsm, syrk: after it)
     int *act_out;          // pick: remaining candidates after the pick
     double *gains;         // gains by position in act_in
@@ -100,7 +101,8 @@ hipError_t launch_gain(const StepDesc &d, int rtype, hipStream_t s);
 hipError_t launch_pick(const StepDesc &d, int rtype, hipStream_t s);
 hipError_t launch_trsm(const StepDesc &d, int rtype, int wtype, hipStream_t s);
 // Downdate kernels: SYRK_DIRECT streams W operands from global memory per wave (any N_tp);
-// SYRK_LDS stages them through LDS with a software pipeline (N_tp <= 128).
+// SYRK_LDS stages them through LDS with a software pipeline (N_tp <= 128).  W_BF16X3 always
+// runs the BF16 split-product kernel (N_tp a multiple of 32, <= 128).
 enum SyrkVariant { SYRK_DIRECT = 0, SYRK_LDS = 1, SYRK_NVARIANTS = 2 };
 hipError_t launch_syrk(const StepDesc &d, int rtype, int wtype, int variant, hipStream_t s);
 

@@ -18,6 +18,27 @@ __device__ __forceinline__ void store_w(TW *W, int64_t off, doublex4 a)
     st4(W + off, v);
 }
 
+// W in BF16 hi/lo parts: the accumulator of sub-block (tb, kc) holds rows 16tb + l%16 and
+// inner indices 16kc + 4g + r; in the 16 x 32 BF16 operand order those four values are
+// consecutive (lane ((k%32)/8)*16 + l%16, elements k%8), so each part is one 8-byte store.
+// hi = bf16(w), lo = bf16(w - hi) with the residual taken in FP64.
+__device__ __forceinline__ void store_w_bf16(unsigned short *Wh, unsigned short *Wl, int tb, int kc, int nb32, int lane,
+                                             doublex4 a)
+{
+    const int g = lane >> 4, l16 = lane & 15;
+    const int64_t off = ((int64_t)(tb * nb32 + (kc >> 1)) << 9) + ((((((kc & 1) << 1) + (g >> 1)) << 4) + l16) << 3) +
+                        4 * (g & 1);
+    u16x4 hi, lo;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        const unsigned short h = f2bf((float)a[r]);
+        hi[r] = h;
+        lo[r] = f2bf((float)(a[r] - (double)bf2f(h)));
+    }
+    *reinterpret_cast<u16x4 *>(Wh + off) = hi;
+    *reinterpret_cast<u16x4 *>(Wl + off) = lo;
+}
+
 template <typename TR, typename TW>
 __device__ void trsm_body(const StepDesc &d, int p)
 {
@@ -34,6 +55,7 @@ __device__ void trsm_body(const StepDesc &d, int p)
     const bool below = i > s;
     const TR *Cb = R + blk_index(below ? i : s, below ? s : i) * bs;
     TW *Wi = W + (int64_t)i * bs;
+    TW *Wi2 = (TW *)d.W2 + (int64_t)i * bs;
     for (int tb = wave; tb < nb; tb += 4) {
         for (int kg = 0; kg < nb; kg += 8) {
             const int kend = min(nb, kg + 8);
@@ -64,7 +86,12 @@ __device__ void trsm_body(const StepDesc &d, int p)
 #pragma unroll
             for (int c = 0; c < 8; ++c) {
                 const int kc = kg + c;
-                if (kc < kend) store_w(Wi, ((int64_t)(tb * nb + kc) << 8) + lane * 4, acc[c]);
+                if (kc < kend) {
+                    if constexpr (sizeof(TW) == 2)
+                        store_w_bf16(Wi, Wi2, tb, kc, nb >> 1, lane, acc[c]);
+                    else
+                        store_w(Wi, ((int64_t)(tb * nb + kc) << 8) + lane * 4, acc[c]);
+                }
             }
         }
     }
@@ -281,6 +308,133 @@ __device__ void syrk_lds_body(const StepDesc &d, int64_t tile)
 }
 
 // ---------------------------------------------------------------------------------------------
+// Downdate with W split into BF16 hi + lo parts (N_tp = 32 * NB32): R_IJ -= hi_I hi_J^T +
+// hi_I lo_J^T + lo_I hi_J^T on the 16x16x32 BF16 MFMA with FP32 accumulation.  Per 32-wide
+// inner slice the work-group stages the hi and lo parts of both W panels in LDS (double
+// buffered); otherwise as syrk_lds_body.
+template <int NB32>
+__device__ void syrk_bf16_body(const StepDesc &d, int64_t tile)
+{
+    constexpr int N_tp = 32 * NB32, NB = 2 * NB32;
+    __shared__ u32x4 lds[2][4][8 * 64];  // [buffer][A hi, A lo, B hi, B lo][sub-block * 64 + lane]
+    if (d.state[ST_STATUS] != 0) return;
+    int64_t P, Q;
+    if (!super_tile(tile, syrk_tile_rows(d.n_act, d.N_tp), P, Q)) return;
+    float *__restrict__ R = (float *)d.R;
+    const unsigned short *__restrict__ Wh = (const unsigned short *)d.W;
+    const unsigned short *__restrict__ Wl = (const unsigned short *)d.W2;
+    const int *__restrict__ act = d.act_in;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, wr = wave >> 1, wc = wave & 1;
+    const int rows = d.n_act * N_tp;
+    const int64_t bs = (int64_t)N_tp * N_tp;
+
+    int64_t gA[2], gB[2];
+    bool okA[2], okB[2];
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+        const int sb = wave + 4 * h;
+        const int r = (int)P * 128 + 16 * sb, c = (int)Q * 128 + 16 * sb;
+        okA[h] = r < rows;
+        okB[h] = c < rows;
+        const int ia = okA[h] ? act[r / N_tp] : 0, ja = okB[h] ? act[c / N_tp] : 0;
+        gA[h] = (int64_t)ia * bs + ((((r % N_tp) >> 4) * NB32) << 9) + lane * 8;
+        gB[h] = (int64_t)ja * bs + ((((c % N_tp) >> 4) * NB32) << 9) + lane * 8;
+    }
+    int ia[4], ta[4], ja[4], tc[4];
+    bool vr[4], vc[4];
+#pragma unroll
+    for (int b = 0; b < 4; ++b) {
+        const int r = (int)P * 128 + wr * 64 + 16 * b;
+        vr[b] = r < rows;
+        ia[b] = vr[b] ? act[r / N_tp] : 0;
+        ta[b] = (r % N_tp) >> 4;
+        const int c = (int)Q * 128 + wc * 64 + 16 * b;
+        vc[b] = c < rows;
+        ja[b] = vc[b] ? act[c / N_tp] : 0;
+        tc[b] = (c % N_tp) >> 4;
+    }
+    bool ok[4][4];
+    bool any = false;
+#pragma unroll
+    for (int b = 0; b < 4; ++b)
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+            ok[b][c] = vr[b] && vc[c] && ia[b] >= ja[c];
+            any |= ok[b][c];
+        }
+    floatx4 rt[4][4], acc[4][4];
+#pragma unroll
+    for (int b = 0; b < 4; ++b)
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+            rt[b][c] = ok[b][c] ? ld4(R + blk_index(ia[b], ja[c]) * bs + ((ta[b] * NB + tc[c]) << 8) + lane * 4)
+                                : floatx4{0, 0, 0, 0};
+            acc[b][c] = floatx4{0, 0, 0, 0};
+        }
+    const u32x4 zero{0, 0, 0, 0};
+    u32x4 st[2][4];  // [h][A hi, A lo, B hi, B lo]
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+        st[h][0] = okA[h] ? *reinterpret_cast<const u32x4 *>(Wh + gA[h]) : zero;
+        st[h][1] = okA[h] ? *reinterpret_cast<const u32x4 *>(Wl + gA[h]) : zero;
+        st[h][2] = okB[h] ? *reinterpret_cast<const u32x4 *>(Wh + gB[h]) : zero;
+        st[h][3] = okB[h] ? *reinterpret_cast<const u32x4 *>(Wl + gB[h]) : zero;
+    }
+#pragma unroll
+    for (int h = 0; h < 2; ++h)
+#pragma unroll
+        for (int m = 0; m < 4; ++m) lds[0][m][(wave + 4 * h) * 64 + lane] = st[h][m];
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < NB32; ++q) {
+        const int buf = q & 1;
+        if (q + 1 < NB32) {
+            const int64_t o = (int64_t)(q + 1) << 9;
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+                st[h][0] = okA[h] ? *reinterpret_cast<const u32x4 *>(Wh + gA[h] + o) : zero;
+                st[h][1] = okA[h] ? *reinterpret_cast<const u32x4 *>(Wl + gA[h] + o) : zero;
+                st[h][2] = okB[h] ? *reinterpret_cast<const u32x4 *>(Wh + gB[h] + o) : zero;
+                st[h][3] = okB[h] ? *reinterpret_cast<const u32x4 *>(Wl + gB[h] + o) : zero;
+            }
+        }
+        if (any) {
+            u32x4 wh[4], wl[4];
+#pragma unroll
+            for (int c = 0; c < 4; ++c) {
+                wh[c] = lds[buf][2][(wc * 4 + c) * 64 + lane];
+                wl[c] = lds[buf][3][(wc * 4 + c) * 64 + lane];
+            }
+#pragma unroll
+            for (int b = 0; b < 4; ++b) {
+                const u32x4 ah = lds[buf][0][(wr * 4 + b) * 64 + lane];
+                const u32x4 al = lds[buf][1][(wr * 4 + b) * 64 + lane];
+#pragma unroll
+                for (int c = 0; c < 4; ++c) {
+                    acc[b][c] = mfma_bf16(ah, wh[c], acc[b][c]);
+                    acc[b][c] = mfma_bf16(ah, wl[c], acc[b][c]);
+                    acc[b][c] = mfma_bf16(al, wh[c], acc[b][c]);
+                }
+            }
+        }
+        if (q + 1 < NB32) {
+#pragma unroll
+            for (int h = 0; h < 2; ++h)
+#pragma unroll
+                for (int m = 0; m < 4; ++m) lds[buf ^ 1][m][(wave + 4 * h) * 64 + lane] = st[h][m];
+        }
+        __syncthreads();
+    }
+    if (!any) return;
+#pragma unroll
+    for (int b = 0; b < 4; ++b)
+#pragma unroll
+        for (int c = 0; c < 4; ++c)
+            if (ok[b][c])
+                st4(R + blk_index(ia[b], ja[c]) * bs + ((ta[b] * NB + tc[c]) << 8) + lane * 4, rt[b][c] - acc[b][c]);
+}
+
+// ---------------------------------------------------------------------------------------------
 // Kernels: single instance (descriptor by value) and batched (descriptor array).
 
 template <typename TR, typename TW>
@@ -338,6 +492,26 @@ __global__ void __launch_bounds__(256, 2) syrk_lds_batched(const StepDesc *__res
     syrk_lds_body<T, NB>(d, item - d.item0);
 }
 
+template <int NB32>
+__global__ void __launch_bounds__(256, 2) syrk_bf16_kernel(StepDesc d, int64_t per_xcd)
+{
+    const int64_t tile = xcd_item(blockIdx.x, per_xcd);
+    if (tile >= d.nitems) return;
+    syrk_bf16_body<NB32>(d, tile);
+}
+
+template <int NB32>
+__global__ void __launch_bounds__(256, 2) syrk_bf16_batched(const StepDesc *__restrict__ ds, int n, int64_t total,
+                                                            int64_t per_xcd)
+{
+    const int64_t item = xcd_item(blockIdx.x, per_xcd);
+    if (item >= total) return;
+    const int i = find_instance(ds, n, item);
+    if (i < 0) return;
+    const StepDesc d = ds[i];
+    syrk_bf16_body<NB32>(d, item - d.item0);
+}
+
 // ---------------------------------------------------------------------------------------------
 // Launchers.
 
@@ -356,6 +530,7 @@ hipError_t launch_trsm(const StepDesc &d, int rtype, int wtype, hipStream_t s)
     if (d.n_act <= 0) return hipSuccess;
     if (rtype == R_F64 && wtype == W_F64) return launch_trsm_t<double, double>(nullptr, d, 1, d.n_act, s);
     if (rtype == R_F32 && wtype == W_F32) return launch_trsm_t<float, float>(nullptr, d, 1, d.n_act, s);
+    if (rtype == R_F32 && wtype == W_BF16X3) return launch_trsm_t<float, unsigned short>(nullptr, d, 1, d.n_act, s);
     return hipErrorInvalidValue;
 }
 
@@ -365,6 +540,7 @@ hipError_t launch_trsm_batched(const StepDesc *descs, int n, int64_t total, int 
     StepDesc none{};
     if (rtype == R_F64 && wtype == W_F64) return launch_trsm_t<double, double>(descs, none, n, total, s);
     if (rtype == R_F32 && wtype == W_F32) return launch_trsm_t<float, float>(descs, none, n, total, s);
+    if (rtype == R_F32 && wtype == W_BF16X3) return launch_trsm_t<float, unsigned short>(descs, none, n, total, s);
     return hipErrorInvalidValue;
 }
 
@@ -404,8 +580,33 @@ static hipError_t launch_syrk_t(const StepDesc *descs, const StepDesc &d, int n,
     return hipGetLastError();
 }
 
+// BF16 split-product downdate (single or batched).
+static hipError_t launch_syrk_bf16(const StepDesc *descs, const StepDesc &d, int n, int64_t total, int N_tp,
+                                   hipStream_t s)
+{
+    if (N_tp < 32 || N_tp % 32 != 0 || N_tp > 128) return hipErrorInvalidValue;
+    const int64_t per_xcd = (total + 7) / 8;
+    const dim3 grid((unsigned)(per_xcd * 8)), block(256);
+    switch (N_tp / 32) {
+#define OED_BF16_CASE(V)                                                                                     \
+    case V:                                                                                                  \
+        if (descs)                                                                                           \
+            hipLaunchKernelGGL((syrk_bf16_batched<V>), grid, block, 0, s, descs, n, total, per_xcd);         \
+        else                                                                                                 \
+            hipLaunchKernelGGL((syrk_bf16_kernel<V>), grid, block, 0, s, d, per_xcd);                        \
+        break;
+        OED_BF16_CASE(1)
+        OED_BF16_CASE(2)
+        OED_BF16_CASE(3)
+        OED_BF16_CASE(4)
+#undef OED_BF16_CASE
+    }
+    return hipGetLastError();
+}
+
 hipError_t launch_syrk(const StepDesc &d, int rtype, int wtype, int variant, hipStream_t s)
 {
+    if (rtype == R_F32 && wtype == W_BF16X3) return d.n_act <= 0 ? hipSuccess : launch_syrk_bf16(nullptr, d, 1, d.nitems, d.N_tp, s);
     if (d.n_act <= 0 || d.nitems <= 0) return hipSuccess;
     if (rtype == R_F64 && wtype == W_F64) return launch_syrk_t<double>(nullptr, d, 1, d.nitems, d.N_tp, variant, s);
     if (rtype == R_F32 && wtype == W_F32) return launch_syrk_t<float>(nullptr, d, 1, d.nitems, d.N_tp, variant, s);
@@ -417,6 +618,7 @@ hipError_t launch_syrk_batched(const StepDesc *descs, int n, int64_t total, int 
 {
     if (n <= 0 || total <= 0) return hipSuccess;
     StepDesc none{};
+    if (rtype == R_F32 && wtype == W_BF16X3) return launch_syrk_bf16(descs, none, n, total, N_tp, s);
     if (rtype == R_F64 && wtype == W_F64) return launch_syrk_t<double>(descs, none, n, total, N_tp, variant, s);
     if (rtype == R_F32 && wtype == W_F32) return launch_syrk_t<float>(descs, none, n, total, N_tp, variant, s);
     return hipErrorInvalidValue;

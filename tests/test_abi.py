@@ -54,6 +54,8 @@ def test_host_side_argument_validation(lib):
     lib.oed_options_init(ctypes.byref(bad))
     bad.precision = 9
     assert lib.oed_create(ctypes.byref(h), fake, 0, 64, 4, 16, 1.0, None, ctypes.byref(bad)) == E_ARG
+    bad.precision = 2  # BF16 split product: N_t <= 128 only
+    assert lib.oed_create(ctypes.byref(h), fake, 0, 4 * 160, 4, 160, 1.0, None, ctypes.byref(bad)) == 6
     bad = oed_options()
     lib.oed_options_init(ctypes.byref(bad))
     bad.struct_size = 4
@@ -92,6 +94,6 @@ def test_batch_host_side_validation(lib):
         assert lib.oed_batch_create(ctypes.byref(b), arr, 2, 1, None, 0) == code
     arr = (oed_instance * 1)(ok)
     assert lib.oed_batch_create(ctypes.byref(b), arr, 0, 1, None, 0) == 1
-    assert lib.oed_batch_create(ctypes.byref(b), arr, 1, 2, None, 0) == 6   # BF16x3 not batched
+    assert lib.oed_batch_create(ctypes.byref(b), arr, 1, 9, None, 0) == 1   # no such precision
     assert not b.value
     assert lib.oed_batch_destroy(None) == 0

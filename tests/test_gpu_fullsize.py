@@ -21,6 +21,8 @@ from parity import RTOL, check_trajectory, rel_err
 
 pytestmark = pytest.mark.gpu
 
+PRECS = ("fp64", "mixed_f32", "mixed_bf16x3")
+
 
 @pytest.fixture(scope="module")
 def big():
@@ -39,7 +41,7 @@ def runs(big):
     from paper_2604_08812_amd import Selector
     spec, K, s2 = big
     out = {}
-    for prec in ("fp64", "mixed_f32"):
+    for prec in PRECS:
         print(f"greedy {prec} B={spec.budget}", flush=True)
         with Selector(K, spec.N_s, spec.N_t, s2, precision=prec) as sel:
             out[prec] = sel.greedy(spec.budget)
@@ -49,7 +51,7 @@ def runs(big):
 @pytest.mark.timeout(900)
 def test_fullsize_telescoping_and_monotone(big, runs):
     spec, K, s2 = big
-    for prec in ("fp64", "mixed_f32"):
+    for prec in PRECS:
         idx, gain = runs[prec]
         assert len(set(idx.tolist())) == spec.budget
         rtol = RTOL[prec]
@@ -67,7 +69,7 @@ def test_fullsize_sampled_steps_against_oracle(big, runs):
     spec, K, s2 = big
     idx64, g64 = runs["fp64"]
     rng = np.random.default_rng(0)
-    for prec in ("fp64", "mixed_f32"):
+    for prec in PRECS:
         with Selector(K, spec.N_s, spec.N_t, s2, precision=prec) as sel:
             done = 0
             for k in (0, 1, 2, 40):
@@ -104,15 +106,16 @@ def test_fullsize_sampled_steps_against_oracle(big, runs):
 
 
 @pytest.mark.timeout(900)
-def test_fullsize_mixed_vs_fp64(big, runs):
+@pytest.mark.parametrize("prec", ["mixed_f32", "mixed_bf16x3"])
+def test_fullsize_mixed_vs_fp64(big, runs, prec):
     spec, K, s2 = big
     i64, g64 = runs["fp64"]
-    i32, g32 = runs["mixed_f32"]
+    i32, g32 = runs[prec]
     div = next((k for k in range(spec.budget) if i64[k] != i32[k]), None)
     upto = spec.budget if div is None else div
     err = rel_err(g32[:upto], g64[:upto]).max()
-    print(f"mixed vs fp64: first divergence {div}, max rel gain diff before it {err:.2e}")
-    assert err <= RTOL["mixed_f32"]
+    print(f"{prec} vs fp64: first divergence {div}, max rel gain diff before it {err:.2e}")
+    assert err <= RTOL[prec]
     if div is not None:
         # a divergence must be a near-tie at that step for the FP64 scores
         from paper_2604_08812_amd import Selector
@@ -120,11 +123,11 @@ def test_fullsize_mixed_vs_fp64(big, runs):
             for k in range(div):
                 sel.force(int(i64[k]))
             g = sel.scores()
-        assert g[i64[div]] - g[i32[div]] <= 2 * RTOL["mixed_f32"] * abs(g[i64[div]])
+        assert g[i64[div]] - g[i32[div]] <= 2 * RTOL[prec] * abs(g[i64[div]])
 
 
 @pytest.mark.timeout(900)
-@pytest.mark.parametrize("prec", ["fp64", "mixed_f32"])
+@pytest.mark.parametrize("prec", PRECS)
 def test_subsample_100_against_oracle(big, prec):
     from paper_2604_08812_amd import Selector
     spec, K, s2 = big

@@ -43,10 +43,20 @@ CASES = [
 ]
 
 
-@pytest.mark.parametrize("prec", ["fp64", "mixed_f32"])
+PRECS = ["fp64", "mixed_f32", "mixed_bf16x3"]
+
+
+def supported(prec, N_t):
+    """The BF16 split-product downdate handles N_t <= 128 only."""
+    return prec != "mixed_bf16x3" or N_t <= 128
+
+
+@pytest.mark.parametrize("prec", PRECS)
 @pytest.mark.parametrize("case", CASES, ids=lambda c: "x".join(map(str, c[:2])))
 def test_greedy_matches_oracle(case, prec):
     N_s, N_t, n_m, seed, B = case
+    if not supported(prec, N_t):
+        pytest.skip("N_t > 128 has no BF16 split-product downdate")
     print(f"case N_s={N_s} N_t={N_t} seed={seed} B={B} prec={prec}", flush=True)
     K, Kd, s2 = instance(N_s, N_t, n_m, seed)
     with selector(Kd, N_s, N_t, s2, precision=prec) as sel:
@@ -57,13 +67,14 @@ def test_greedy_matches_oracle(case, prec):
         assert rep["diverged_steps"] == [] or min(rep["ref"]["gap"]) < 1e-9
 
 
-@pytest.mark.parametrize("prec", ["fp64", "mixed_f32"])
+@pytest.mark.parametrize("prec", PRECS)
 def test_scores_and_schur_blocks_after_forced_prefix(prec):
     N_s, N_t = 29, 48
     K, Kd, s2 = instance(N_s, N_t, 2000, 21)
     A = [7, 0, 28, 13]
     rest = [j for j in range(N_s) if j not in A]
-    tol = 1e-11 if prec == "fp64" else 2e-5
+    # W hi + lo in BF16 represents w to about 2^-17 relative (lo * lo is dropped)
+    tol = {"fp64": 1e-11, "mixed_f32": 2e-5, "mixed_bf16x3": 5e-5}[prec]
     with selector(Kd, N_s, N_t, s2, precision=prec) as sel:
         g0 = sel.scores()
         ref0 = oracle.gains(K, N_t, s2, [], range(N_s))
@@ -86,7 +97,7 @@ def test_scores_and_schur_blocks_after_forced_prefix(prec):
 def test_exact_ties_go_to_lowest_index():
     N_s, N_t, c, s2 = 40, 16, 3.0, 0.02
     K = c * torch.eye(N_s * N_t, dtype=torch.float64)
-    for prec in ("fp64", "mixed_f32"):
+    for prec in PRECS:
         with selector(K.to(DEV), N_s, N_t, s2, precision=prec) as sel:
             idx, gain = sel.greedy(12)
         assert list(idx) == list(range(12))
@@ -108,7 +119,7 @@ def test_non_pd_and_nan_candidates_are_never_picked():
     assert ref["status"] == 2
     # sensors 3 and 5 are never finite; once one of 0 and 8 is picked the other turns non-finite
     assert not ({3, 5} & set(ref["idx"].tolist())) and len({0, 8} & set(ref["idx"].tolist())) == 1
-    for prec in ("fp64", "mixed_f32"):
+    for prec in PRECS:
         with selector(K.to(DEV), N_s, N_t, s2, precision=prec) as sel:
             g = sel.scores()
             assert np.isneginf(g[5]) and np.isneginf(g[3]) and np.isfinite(g[8])
@@ -124,7 +135,7 @@ def test_upper_triangle_is_not_read():
     Kn = K.clone()
     iu = torch.triu_indices(N_s * N_t, N_s * N_t, 1)
     Kn[iu[0], iu[1]] = float("nan")
-    for prec in ("fp64", "mixed_f32"):
+    for prec in PRECS:
         with selector(K.to(DEV), N_s, N_t, s2, precision=prec) as a, \
                 selector(Kn.to(DEV), N_s, N_t, s2, precision=prec) as b:
             ia, ga = a.greedy(8)
@@ -137,7 +148,7 @@ def test_candidate_subset():
     N_s, N_t = 45, 16
     K, Kd, s2 = instance(N_s, N_t, 1500, 51)
     cand = [44, 3, 17, 29, 8, 12, 40, 0, 21, 33, 5]
-    for prec in ("fp64", "mixed_f32"):
+    for prec in PRECS:
         with selector(Kd, N_s, N_t, s2, precision=prec, candidates=cand) as sel:
             idx, gain = sel.greedy(6)
         assert set(idx.tolist()) <= set(cand)
@@ -166,7 +177,7 @@ def test_force_then_greedy_and_split_calls():
 def test_reset_reproduces_bitwise():
     N_s, N_t = 40, 64
     _, Kd, s2 = instance(N_s, N_t, 3000, 71)
-    for prec in ("fp64", "mixed_f32"):
+    for prec in PRECS:
         with selector(Kd, N_s, N_t, s2, precision=prec) as sel:
             i1, g1 = sel.greedy(10)
             sel.reset(Kd)
