@@ -40,6 +40,10 @@ def parse():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--config", default="mixed_600x128")
     ap.add_argument("--budget", type=int, default=None, help="override the budget (not the headline)")
+    ap.add_argument("--precision", default=None, choices=["fp64", "mixed_f32", "mixed_bf16x3"],
+                    help="override the configuration's precision (not the headline)")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run a plain 1 GiB device copy 4 times (HBM counter calibration)")
     ap.add_argument("--fp64-steps", type=int, default=1)
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-bf16x3", action="store_true")
@@ -61,7 +65,7 @@ def timed_selections(sel, K, budget, steps):
     return (time.perf_counter() - t0) * 1e3 / steps, out
 
 
-def roofline_syrk(prof, prec):
+def roofline_syrk(prof, prec, workload=None):
     """The downdate R -= W W^T: algorithmic flops (2 per multiply-add of the lower-triangle
     blocks) over its summed HIP-event time.  The BF16 split product executes three MFMA
     products per algorithmic one; its fraction is taken of the BF16 peak on the executed
@@ -78,7 +82,9 @@ def roofline_syrk(prof, prec):
         "peak": PEAK_TFLOPS[prec],
         "unit": "TFLOP/s",
         "frac": round(executed / PEAK_TFLOPS[prec], 4),
-        "traffic": None,
+        "traffic": counted_traffic(workload, prec, SYRK_KERNEL[prec]) if workload else None,
+        "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
+        "algorithmic_bytes_per_launch": round(prof["syrk_bytes"] / n),
         "avg_launch_ms": round(ms / n, 4),
         "launches": n,
         "algorithmic_tflops": round(tflops, 3),
@@ -103,6 +109,45 @@ def compare_picks(idx, gain, idx_ref, gain_ref):
         if upto else 0.0
     return {"same_picks": agree == budget, "picks_equal_at_position": agree, "first_divergence_step": first_div,
             "max_rel_gain_diff_before_divergence": gerr}
+
+
+def copy_calibration():
+    """A plain device-to-device copy of 2^28 floats (1 GiB read + 1 GiB written), four times:
+    what FETCH_SIZE / WRITE_SIZE read for it scales the counters of the selection kernels."""
+    import torch
+    src = torch.ones(1 << 28, dtype=torch.float32, device="cuda:0")
+    dst = torch.empty_like(src)
+    torch.cuda.synchronize()
+    for _ in range(4):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_calibration": {"bytes_read": 1 << 30, "bytes_written": 1 << 30, "launches": 4}}),
+          flush=True)
+
+
+def source_digest():
+    """SHA-256 of the downdate kernels' source: HBM traffic counted for other source is stale."""
+    import hashlib
+    h = hashlib.sha256()
+    for f in ("oed_update.hip", "oed_device.h", "oed_internal.h"):
+        with open(os.path.join(ROOT, "paper_2604_08812_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def counted_traffic(workload, prec, kernel_name):
+    """HBM bytes per launch of the downdate from the committed rocprofv3 FETCH_SIZE / WRITE_SIZE
+    summary (scaled by the copy calibration), or None when absent or taken on other source."""
+    path = os.path.join(ROOT, "profiles", f"syrk_hbm_traffic_{workload}.json")
+    try:
+        with open(path) as fh:
+            rec = json.load(fh)
+    except (OSError, ValueError):
+        return None
+    ent = rec.get("kernels", {}).get(prec)
+    if not ent or ent.get("source_sha256") != source_digest() or ent.get("kernel") != kernel_name:
+        return None
+    return ent.get("hbm_bytes_per_launch")
 
 
 def cpu_baseline(K, N_t, s2, n_sensors, budget):
@@ -187,12 +232,14 @@ def main():
     from oed_inputs import CONFIGS, make_K_lower_panels
     from paper_2604_08812_amd import Selector, library
 
+    if args.copy_calibration:
+        return copy_calibration()
     library()
     if args.config == "batched_48":
         return run_batched(args)
     spec = CONFIGS[args.config]
     budget = args.budget or spec.budget
-    prec = spec.precision
+    prec = args.precision or spec.precision
     dev = torch.device("cuda:0")
     log(f"forming K for {spec.name}: N_s={spec.N_s} N_t={spec.N_t} n_m={spec.n_m} seed={spec.seed}")
     t0 = time.perf_counter()
@@ -228,7 +275,7 @@ def main():
         "config": {"workload": spec.name, "N_s": spec.N_s, "N_t": spec.N_t, "n_m": spec.n_m, "seed": spec.seed,
                    "budget": budget, "precision": prec, "K_dtype": spec.k_dtype,
                    "step": "oed_reset + oed_greedy(budget)"},
-        "roofline": roofline_syrk(prof, prec),
+        "roofline": roofline_syrk(prof, prec, spec.name),
         "kernel_ms_per_step": {k: round(v / args.steps, 3) for k, v in prof["ms"].items()},
     }
     sel.close()
@@ -242,12 +289,12 @@ def main():
         sel64.close()
         log(f"fp64: {ms64:.1f} ms per selection")
         result["fp64"] = {"value": round(budget / (ms64 * 1e-3), 3), "unit": "greedy steps/s",
-                          "ms_per_step": round(ms64, 3), "roofline": roofline_syrk(p64, "fp64"),
+                          "ms_per_step": round(ms64, 3), "roofline": roofline_syrk(p64, "fp64", spec.name),
                           "kernel_ms_per_step": {k: round(v / args.fp64_steps, 3) for k, v in p64["ms"].items()}}
         result["mixed_vs_fp64"] = {"speedup": round(ms64 / ms, 3), **compare_picks(idx, gain, idx64, gain64)}
 
     # ---- the BF16 split-product downdate beside it, same K
-    if not args.no_bf16x3 and prec == "mixed_f32" and spec.N_t <= 128:
+    if not args.no_bf16x3 and prec == "mixed_f32" and spec.N_t <= 128 and not args.precision:
         selb = Selector(K, spec.N_s, spec.N_t, s2, precision="mixed_bf16x3", profile=True)
         timed_selections(selb, K, budget, 1)
         selb.profile(reset=True)
@@ -256,7 +303,7 @@ def main():
         selb.close()
         log(f"mixed_bf16x3: {msb:.1f} ms per selection")
         result["mixed_bf16x3"] = {"value": round(budget / (msb * 1e-3), 3), "unit": "greedy steps/s",
-                                  "ms_per_step": round(msb, 3), "roofline": roofline_syrk(pb, "mixed_bf16x3"),
+                                  "ms_per_step": round(msb, 3), "roofline": roofline_syrk(pb, "mixed_bf16x3", spec.name),
                                   "kernel_ms_per_step": {k: round(v / args.steps, 3) for k, v in pb["ms"].items()},
                                   "speedup_vs_mixed_f32": round(ms / msb, 3),
                                   "vs_mixed_f32": compare_picks(idxb, gainb, idx, gain)}

@@ -172,89 +172,94 @@ __device__ void syrk_direct_body(const StepDesc &d, int64_t tile)
 }
 
 // ---------------------------------------------------------------------------------------------
+// Addresses shared by the LDS-staged downdates.  The work-group's tile (P, Q) covers rows
+// 128P.. and columns 128Q..; wave w stages sub-block rows w and w + 4 of both W panels and
+// owns output quarter (w / 2, w % 2) = 4 x 4 blocks of 16 x 16.  Every global load is
+// unconditional: rows past the last active block read a valid (clamped) address and the
+// blocks that would use them are never stored, so a wait for one batch of loads never has
+// to wait for another issued later.  The active-list lookups are wave-uniform (scalar).
+// All fields are wave-uniform (scalar registers); lane offsets are added at each access.
+struct TileMap {
+    int64_t wA[2], wB[2];  // element offsets of the wave's staged W sub-blocks (slice 0)
+    int64_t rblk[16];      // element offsets of the wave's output blocks in R
+    bool ok[16];           // output block is in the lower triangle of active rows
+    bool any;
+};
+
+template <int N_tp>
+__device__ __forceinline__ void tile_map(const StepDesc &d, int64_t P, int64_t Q, int wave, TileMap &m)
+{
+    constexpr int NB = N_tp / 16;
+    const int *__restrict__ act = d.act_in;
+    const int rows = d.n_act * N_tp, last = d.n_act - 1;
+    const int64_t bs = (int64_t)N_tp * N_tp;
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+        const int sb = wave + 4 * h;
+        const int r = (int)P * 128 + 16 * sb, c = (int)Q * 128 + 16 * sb;
+        const int ia = act[min(r / N_tp, last)], ja = act[min(c / N_tp, last)];
+        m.wA[h] = (int64_t)ia * bs + (int64_t)((r % N_tp) >> 4) * (NB * 256);
+        m.wB[h] = (int64_t)ja * bs + (int64_t)((c % N_tp) >> 4) * (NB * 256);
+    }
+    m.any = false;
+#pragma unroll
+    for (int b = 0; b < 4; ++b) {
+        const int r = (int)P * 128 + (wave >> 1) * 64 + 16 * b;
+        const int ia = act[min(r / N_tp, last)], ta = (r % N_tp) >> 4;
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+            const int cc = (int)Q * 128 + (wave & 1) * 64 + 16 * c;
+            const int ja = act[min(cc / N_tp, last)], tc = (cc % N_tp) >> 4;
+            const bool o = r < rows && cc < rows && ia >= ja;
+            m.ok[4 * b + c] = o;
+            m.any |= o;
+            m.rblk[4 * b + c] = o ? blk_index(ia, ja) * bs + ((ta * NB + tc) << 8) : 0;
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------------------------
 // Downdate, LDS-staged and software-pipelined variant for N_tp = 16*NB <= 128.
 // Per 16-wide slice q of the inner index, the work-group stages the 128 x 16 A panel (tile
 // rows) and B panel (tile columns) of W into LDS once (double-buffered, one barrier per
 // slice) and every wave reads its operands from there; the next slice's global loads are in
-// flight while the current slice's MFMAs run.  The product W_I W_J^T accumulates from zero;
-// the R tile is fetched at the start (FP32: into registers, in flight during the MFMAs) and
-// subtracted at the end.
+// flight while the current slice's MFMAs run.  The product W_I W_J^T accumulates from zero
+// and is subtracted from R at the end.  FP32: the R tile is loaded into registers a few
+// blocks per slice, behind the next slice's W loads, so it streams in during the MFMAs.
+// FP64 (no registers for the tile) reads R in the epilogue.
 template <typename T, int NB>
 __device__ void syrk_lds_body(const StepDesc &d, int64_t tile)
 {
     typedef typename V4<T>::type vec;
     constexpr int N_tp = 16 * NB;
     constexpr bool PREFETCH_R = sizeof(T) == 4;
-    __shared__ vec lds[2][2][8 * 64];  // [buffer][A/B][sub-block * 64 + lane]
+    constexpr int PER = (16 + NB - 1) / NB;  // R blocks fetched per slice
+    __shared__ vec lds[2][2][8 * 64];        // [buffer][A/B][sub-block * 64 + lane]
     if (d.state[ST_STATUS] != 0) return;
-    T *__restrict__ R = (T *)d.R;
-    const T *__restrict__ W = (const T *)d.W;
-    const int *__restrict__ act = d.act_in;
-    const int n_act = d.n_act;
     int64_t P, Q;
     if (!super_tile(tile, syrk_tile_rows(d.n_act, d.N_tp), P, Q)) return;
-    const int tid = threadIdx.x;
-    const int lane = tid & 63, wave = tid >> 6, wr = wave >> 1, wc = wave & 1;
+    T *__restrict__ R = (T *)d.R;
+    const T *__restrict__ W = (const T *)d.W;
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6), wr = wave >> 1, wc = wave & 1;
     const int alane = a_lane<T>(lane);
-    const int rows = n_act * N_tp;
-    const int64_t bs = (int64_t)N_tp * N_tp;
+    TileMap m;
+    tile_map<N_tp>(d, P, Q, wave, m);
+    const T *Wl = W + lane * 4;  // this lane's element of a staged sub-block
+    T *Rl = R + lane * 4;         // this lane's element of an output block
 
-    // staging assignment: thread loads sub-blocks sA = tid/64 and tid/64 + 4 of both panels
-    const T *gA[2], *gB[2];
-    bool okA[2], okB[2];
+    vec rt[16], acc[16];
 #pragma unroll
-    for (int h = 0; h < 2; ++h) {
-        const int sb = wave + 4 * h;
-        const int r = (int)P * 128 + 16 * sb, c = (int)Q * 128 + 16 * sb;
-        okA[h] = r < rows;
-        okB[h] = c < rows;
-        const int ia = okA[h] ? act[r / N_tp] : 0, ja = okB[h] ? act[c / N_tp] : 0;
-        gA[h] = W + (int64_t)ia * bs + (((r % N_tp) >> 4) * NB << 8) + lane * 4;
-        gB[h] = W + (int64_t)ja * bs + (((c % N_tp) >> 4) * NB << 8) + lane * 4;
-    }
-    // output blocks of this wave
-    int ia[4], ta[4], ja[4], tc[4];
-    bool vr[4], vc[4];
-#pragma unroll
-    for (int b = 0; b < 4; ++b) {
-        const int r = (int)P * 128 + wr * 64 + 16 * b;
-        vr[b] = r < rows;
-        ia[b] = vr[b] ? act[r / N_tp] : 0;
-        ta[b] = (r % N_tp) >> 4;
-        const int c = (int)Q * 128 + wc * 64 + 16 * b;
-        vc[b] = c < rows;
-        ja[b] = vc[b] ? act[c / N_tp] : 0;
-        tc[b] = (c % N_tp) >> 4;
-    }
-    bool ok[4][4];
-    bool any = false;
-#pragma unroll
-    for (int b = 0; b < 4; ++b)
-#pragma unroll
-        for (int c = 0; c < 4; ++c) {
-            ok[b][c] = vr[b] && vc[c] && ia[b] >= ja[c];
-            any |= ok[b][c];
-        }
-    vec rt[4][4];
-    if (PREFETCH_R) {
-#pragma unroll
-        for (int b = 0; b < 4; ++b)
-#pragma unroll
-            for (int c = 0; c < 4; ++c)
-                rt[b][c] = ok[b][c] ? ld4(R + blk_index(ia[b], ja[c]) * bs + ((ta[b] * NB + tc[c]) << 8) + lane * 4)
-                                    : vec{0, 0, 0, 0};
-    }
-    vec acc[4][4];
-#pragma unroll
-    for (int b = 0; b < 4; ++b)
-#pragma unroll
-        for (int c = 0; c < 4; ++c) acc[b][c] = vec{0, 0, 0, 0};
-
+    for (int f = 0; f < 16; ++f) acc[f] = vec{0, 0, 0, 0};
     vec sa[2], sbv[2];
 #pragma unroll
     for (int h = 0; h < 2; ++h) {
-        sa[h] = okA[h] ? ld4(gA[h]) : vec{0, 0, 0, 0};
-        sbv[h] = okB[h] ? ld4(gB[h]) : vec{0, 0, 0, 0};
+        sa[h] = ld4(Wl + m.wA[h]);
+        sbv[h] = ld4(Wl + m.wB[h]);
+    }
+    if (PREFETCH_R) {
+#pragma unroll
+        for (int f = 0; f < PER && f < 16; ++f) rt[f] = ld4(Rl + m.rblk[f]);
     }
 #pragma unroll
     for (int h = 0; h < 2; ++h) {
@@ -268,11 +273,15 @@ __device__ void syrk_lds_body(const StepDesc &d, int64_t tile)
         if (q + 1 < NB) {
 #pragma unroll
             for (int h = 0; h < 2; ++h) {
-                sa[h] = okA[h] ? ld4(gA[h] + ((q + 1) << 8)) : vec{0, 0, 0, 0};
-                sbv[h] = okB[h] ? ld4(gB[h] + ((q + 1) << 8)) : vec{0, 0, 0, 0};
+                sa[h] = ld4(Wl + m.wA[h] + ((q + 1) << 8));
+                sbv[h] = ld4(Wl + m.wB[h] + ((q + 1) << 8));
+            }
+            if (PREFETCH_R) {
+#pragma unroll
+                for (int f = (q + 1) * PER; f < (q + 2) * PER && f < 16; ++f) rt[f] = ld4(Rl + m.rblk[f]);
             }
         }
-        if (any) {
+        if (m.any) {
             vec a[4], w[4];
 #pragma unroll
             for (int b = 0; b < 4; ++b) {
@@ -284,7 +293,7 @@ __device__ void syrk_lds_body(const StepDesc &d, int64_t tile)
 #pragma unroll
                 for (int b = 0; b < 4; ++b)
 #pragma unroll
-                    for (int c = 0; c < 4; ++c) acc[b][c] = mfma16(a[b][s4], w[c][s4], acc[b][c]);
+                    for (int c = 0; c < 4; ++c) acc[4 * b + c] = mfma16(a[b][s4], w[c][s4], acc[4 * b + c]);
         }
         if (q + 1 < NB) {
 #pragma unroll
@@ -295,16 +304,14 @@ __device__ void syrk_lds_body(const StepDesc &d, int64_t tile)
         }
         __syncthreads();
     }
-    if (!any) return;
+    if (!m.any) return;
+    if (PREFETCH_R) {
 #pragma unroll
-    for (int b = 0; b < 4; ++b)
+        for (int f = NB * PER; f < 16; ++f) rt[f] = ld4(Rl + m.rblk[f]);
+    }
 #pragma unroll
-        for (int c = 0; c < 4; ++c)
-            if (ok[b][c]) {
-                T *p = R + blk_index(ia[b], ja[c]) * bs + ((ta[b] * NB + tc[c]) << 8) + lane * 4;
-                const vec r0 = PREFETCH_R ? rt[b][c] : ld4(p);
-                st4(p, r0 - acc[b][c]);
-            }
+    for (int f = 0; f < 16; ++f)
+        if (m.ok[f]) st4(Rl + m.rblk[f], (PREFETCH_R ? rt[f] : ld4(Rl + m.rblk[f])) - acc[f]);
 }
 
 // ---------------------------------------------------------------------------------------------
@@ -315,75 +322,39 @@ __device__ void syrk_lds_body(const StepDesc &d, int64_t tile)
 template <int NB32>
 __device__ void syrk_bf16_body(const StepDesc &d, int64_t tile)
 {
-    constexpr int N_tp = 32 * NB32, NB = 2 * NB32;
-    __shared__ u32x4 lds[2][4][8 * 64];  // [buffer][A hi, A lo, B hi, B lo][sub-block * 64 + lane]
+    constexpr int N_tp = 32 * NB32;
+    constexpr int PER = (16 + NB32 - 1) / NB32;  // R blocks fetched per slice
+    __shared__ u32x4 lds[2][4][8 * 64];          // [buffer][A hi, A lo, B hi, B lo][sub-block * 64 + lane]
     if (d.state[ST_STATUS] != 0) return;
     int64_t P, Q;
     if (!super_tile(tile, syrk_tile_rows(d.n_act, d.N_tp), P, Q)) return;
     float *__restrict__ R = (float *)d.R;
     const unsigned short *__restrict__ Wh = (const unsigned short *)d.W;
     const unsigned short *__restrict__ Wl = (const unsigned short *)d.W2;
-    const int *__restrict__ act = d.act_in;
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, wr = wave >> 1, wc = wave & 1;
-    const int rows = d.n_act * N_tp;
-    const int64_t bs = (int64_t)N_tp * N_tp;
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6), wr = wave >> 1, wc = wave & 1;
+    TileMap m;
+    tile_map<N_tp>(d, P, Q, wave, m);  // W offsets in BF16 elements: a 16 x 32 tile is 512
+    const unsigned short *Whl = Wh + lane * 8, *Wll = Wl + lane * 8;
+    float *Rl = R + lane * 4;
 
-    int64_t gA[2], gB[2];
-    bool okA[2], okB[2];
+    floatx4 rt[16], acc[16];
 #pragma unroll
-    for (int h = 0; h < 2; ++h) {
-        const int sb = wave + 4 * h;
-        const int r = (int)P * 128 + 16 * sb, c = (int)Q * 128 + 16 * sb;
-        okA[h] = r < rows;
-        okB[h] = c < rows;
-        const int ia = okA[h] ? act[r / N_tp] : 0, ja = okB[h] ? act[c / N_tp] : 0;
-        gA[h] = (int64_t)ia * bs + ((((r % N_tp) >> 4) * NB32) << 9) + lane * 8;
-        gB[h] = (int64_t)ja * bs + ((((c % N_tp) >> 4) * NB32) << 9) + lane * 8;
-    }
-    int ia[4], ta[4], ja[4], tc[4];
-    bool vr[4], vc[4];
-#pragma unroll
-    for (int b = 0; b < 4; ++b) {
-        const int r = (int)P * 128 + wr * 64 + 16 * b;
-        vr[b] = r < rows;
-        ia[b] = vr[b] ? act[r / N_tp] : 0;
-        ta[b] = (r % N_tp) >> 4;
-        const int c = (int)Q * 128 + wc * 64 + 16 * b;
-        vc[b] = c < rows;
-        ja[b] = vc[b] ? act[c / N_tp] : 0;
-        tc[b] = (c % N_tp) >> 4;
-    }
-    bool ok[4][4];
-    bool any = false;
-#pragma unroll
-    for (int b = 0; b < 4; ++b)
-#pragma unroll
-        for (int c = 0; c < 4; ++c) {
-            ok[b][c] = vr[b] && vc[c] && ia[b] >= ja[c];
-            any |= ok[b][c];
-        }
-    floatx4 rt[4][4], acc[4][4];
-#pragma unroll
-    for (int b = 0; b < 4; ++b)
-#pragma unroll
-        for (int c = 0; c < 4; ++c) {
-            rt[b][c] = ok[b][c] ? ld4(R + blk_index(ia[b], ja[c]) * bs + ((ta[b] * NB + tc[c]) << 8) + lane * 4)
-                                : floatx4{0, 0, 0, 0};
-            acc[b][c] = floatx4{0, 0, 0, 0};
-        }
-    const u32x4 zero{0, 0, 0, 0};
+    for (int f = 0; f < 16; ++f) acc[f] = floatx4{0, 0, 0, 0};
     u32x4 st[2][4];  // [h][A hi, A lo, B hi, B lo]
 #pragma unroll
     for (int h = 0; h < 2; ++h) {
-        st[h][0] = okA[h] ? *reinterpret_cast<const u32x4 *>(Wh + gA[h]) : zero;
-        st[h][1] = okA[h] ? *reinterpret_cast<const u32x4 *>(Wl + gA[h]) : zero;
-        st[h][2] = okB[h] ? *reinterpret_cast<const u32x4 *>(Wh + gB[h]) : zero;
-        st[h][3] = okB[h] ? *reinterpret_cast<const u32x4 *>(Wl + gB[h]) : zero;
+        st[h][0] = *reinterpret_cast<const u32x4 *>(Whl + m.wA[h]);
+        st[h][1] = *reinterpret_cast<const u32x4 *>(Wll + m.wA[h]);
+        st[h][2] = *reinterpret_cast<const u32x4 *>(Whl + m.wB[h]);
+        st[h][3] = *reinterpret_cast<const u32x4 *>(Wll + m.wB[h]);
     }
+#pragma unroll
+    for (int f = 0; f < PER && f < 16; ++f) rt[f] = ld4(Rl + m.rblk[f]);
 #pragma unroll
     for (int h = 0; h < 2; ++h)
 #pragma unroll
-        for (int m = 0; m < 4; ++m) lds[0][m][(wave + 4 * h) * 64 + lane] = st[h][m];
+        for (int k = 0; k < 4; ++k) lds[0][k][(wave + 4 * h) * 64 + lane] = st[h][k];
     __syncthreads();
 #pragma unroll
     for (int q = 0; q < NB32; ++q) {
@@ -392,13 +363,15 @@ __device__ void syrk_bf16_body(const StepDesc &d, int64_t tile)
             const int64_t o = (int64_t)(q + 1) << 9;
 #pragma unroll
             for (int h = 0; h < 2; ++h) {
-                st[h][0] = okA[h] ? *reinterpret_cast<const u32x4 *>(Wh + gA[h] + o) : zero;
-                st[h][1] = okA[h] ? *reinterpret_cast<const u32x4 *>(Wl + gA[h] + o) : zero;
-                st[h][2] = okB[h] ? *reinterpret_cast<const u32x4 *>(Wh + gB[h] + o) : zero;
-                st[h][3] = okB[h] ? *reinterpret_cast<const u32x4 *>(Wl + gB[h] + o) : zero;
+                st[h][0] = *reinterpret_cast<const u32x4 *>(Whl + m.wA[h] + o);
+                st[h][1] = *reinterpret_cast<const u32x4 *>(Wll + m.wA[h] + o);
+                st[h][2] = *reinterpret_cast<const u32x4 *>(Whl + m.wB[h] + o);
+                st[h][3] = *reinterpret_cast<const u32x4 *>(Wll + m.wB[h] + o);
             }
+#pragma unroll
+            for (int f = (q + 1) * PER; f < (q + 2) * PER && f < 16; ++f) rt[f] = ld4(Rl + m.rblk[f]);
         }
-        if (any) {
+        if (m.any) {
             u32x4 wh[4], wl[4];
 #pragma unroll
             for (int c = 0; c < 4; ++c) {
@@ -411,9 +384,9 @@ __device__ void syrk_bf16_body(const StepDesc &d, int64_t tile)
                 const u32x4 al = lds[buf][1][(wr * 4 + b) * 64 + lane];
 #pragma unroll
                 for (int c = 0; c < 4; ++c) {
-                    acc[b][c] = mfma_bf16(ah, wh[c], acc[b][c]);
-                    acc[b][c] = mfma_bf16(ah, wl[c], acc[b][c]);
-                    acc[b][c] = mfma_bf16(al, wh[c], acc[b][c]);
+                    acc[4 * b + c] = mfma_bf16(ah, wh[c], acc[4 * b + c]);
+                    acc[4 * b + c] = mfma_bf16(ah, wl[c], acc[4 * b + c]);
+                    acc[4 * b + c] = mfma_bf16(al, wh[c], acc[4 * b + c]);
                 }
             }
         }
@@ -421,17 +394,16 @@ __device__ void syrk_bf16_body(const StepDesc &d, int64_t tile)
 #pragma unroll
             for (int h = 0; h < 2; ++h)
 #pragma unroll
-                for (int m = 0; m < 4; ++m) lds[buf ^ 1][m][(wave + 4 * h) * 64 + lane] = st[h][m];
+                for (int k = 0; k < 4; ++k) lds[buf ^ 1][k][(wave + 4 * h) * 64 + lane] = st[h][k];
         }
         __syncthreads();
     }
-    if (!any) return;
+    if (!m.any) return;
 #pragma unroll
-    for (int b = 0; b < 4; ++b)
+    for (int f = NB32 * PER; f < 16; ++f) rt[f] = ld4(Rl + m.rblk[f]);
 #pragma unroll
-        for (int c = 0; c < 4; ++c)
-            if (ok[b][c])
-                st4(R + blk_index(ia[b], ja[c]) * bs + ((ta[b] * NB + tc[c]) << 8) + lane * 4, rt[b][c] - acc[b][c]);
+    for (int f = 0; f < 16; ++f)
+        if (m.ok[f]) st4(Rl + m.rblk[f], rt[f] - acc[f]);
 }
 
 // ---------------------------------------------------------------------------------------------
