@@ -48,7 +48,7 @@ def parse():
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-bf16x3", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-budget", type=int, default=12, help="picks of the oracle sample")
+    ap.add_argument("--cpu-budget", type=int, default=16, help="picks of the oracle sample")
     ap.add_argument("--cpu-sensors", type=int, default=100)
     return ap.parse_args()
 
