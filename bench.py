@@ -47,6 +47,7 @@ def parse():
     ap.add_argument("--fp64-steps", type=int, default=1)
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-bf16x3", action="store_true")
+    ap.add_argument("--no-gaps", action="store_true", help="skip the per-step top-two gap scan (FP64)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-budget", type=int, default=16, help="picks of the oracle sample")
     ap.add_argument("--cpu-sensors", type=int, default=100)
@@ -108,7 +109,7 @@ def compare_picks(idx, gain, idx_ref, gain_ref):
     gerr = float(np.max(np.abs(gain[:upto] - gain_ref[:upto]) / np.maximum(1, np.abs(gain_ref[:upto])))) \
         if upto else 0.0
     return {"same_picks": agree == budget, "picks_equal_at_position": agree, "first_divergence_step": first_div,
-            "max_rel_gain_diff_before_divergence": gerr}
+            "max_rel_gain_diff_before_divergence": gerr, "per_step_rel_gain_diff": per_step_diff(gain, gain_ref, upto)}
 
 
 def copy_calibration():
@@ -150,9 +151,27 @@ def counted_traffic(workload, prec, kernel_name):
     return ent.get("hbm_bytes_per_launch")
 
 
-def cpu_baseline(K, N_t, s2, n_sensors, budget):
+def naive_flops(n, N_t, budget):
+    """Flops of the oracle's from-scratch greedy: at step k (1-based) every one of the n - k + 1
+    remaining candidates factors a (k N_t)^2 matrix, (k N_t)^3 / 3 flops."""
+    return sum((n - k + 1) * (k * N_t) ** 3 / 3.0 for k in range(1, budget + 1))
+
+
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for ln in f:
+                if ln.startswith("model name"):
+                    return ln.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(K, N_t, s2, n_sensors, budget, full_shape=None, single_budget=6):
     """The oracle (from-scratch FP64 Cholesky of every test matrix, OpenMP over candidates)
-    on the first n_sensors sensors of the same K."""
+    on the first n_sensors sensors of the same K; a shorter single-thread run beside it, and
+    the full-size time extrapolated from the measured flop rate."""
     import numpy as np
 
     import oracle
@@ -162,10 +181,52 @@ def cpu_baseline(K, N_t, s2, n_sensors, budget):
     t0 = time.perf_counter()
     res = oracle.greedy(sub, n_sensors, N_t, s2, budget, threads=threads)
     dt = time.perf_counter() - t0
-    return {"value": round(budget / dt, 4), "unit": "greedy steps/s", "cores": threads, "kind": "oracle",
-            "sample": f"sensors 0..{n_sensors - 1} of the same K ({n_sensors * N_t}^2 principal block), "
-                      f"budget {budget}, {dt:.1f} s", "seconds": round(dt, 2),
-            "idx": [int(x) for x in res["idx"]], "gain": [float(x) for x in np.asarray(res["gain"])]}
+    rate = naive_flops(n_sensors, N_t, budget) / dt
+    t1 = time.perf_counter()
+    oracle.greedy(sub, n_sensors, N_t, s2, single_budget, threads=1)
+    dt1 = time.perf_counter() - t1
+    out = {"value": round(budget / dt, 4), "unit": "greedy steps/s", "cores": threads, "kind": "oracle",
+           "sample": f"sensors 0..{n_sensors - 1} of the same K ({n_sensors * N_t}^2 principal block), "
+                     f"budget {budget}, {dt:.1f} s", "seconds": round(dt, 2),
+           "cpu_model": cpu_model(), "nproc": os.cpu_count(),
+           "oracle_gflops": round(rate / 1e9, 2),
+           "single_thread": {"budget": single_budget, "seconds": round(dt1, 2),
+                             "greedy_steps_per_s": round(single_budget / dt1, 4),
+                             "gflops": round(naive_flops(n_sensors, N_t, single_budget) / dt1 / 1e9, 2)},
+           "idx": [int(x) for x in res["idx"]], "gain": [float(x) for x in np.asarray(res["gain"])]}
+    if full_shape:
+        N_s, B = full_shape
+        out["full_size_extrapolated_s"] = {
+            "value": round(naive_flops(N_s, N_t, B) / rate, 1),
+            "note": f"extrapolated, not measured: {naive_flops(N_s, N_t, B):.3g} oracle flops for "
+                    f"{N_s} sensors, budget {B}, at the sample's measured rate"}
+    return out
+
+
+def top_two_gaps(sel, K, budget):
+    """Relative gap between the best and second-best FP64 score at every step (the near-tie
+    margin that the pick comparisons depend on)."""
+    import numpy as np
+    sel.reset(K)
+    gaps = []
+    for k in range(budget):
+        g = sel.scores()
+        fin = np.sort(g[np.isfinite(g)])
+        if fin.size >= 2:
+            gaps.append((fin[-1] - fin[-2]) / max(abs(fin[-1]), 1.0))
+        sel.greedy(1)
+    gaps = np.array(gaps)
+    return {"per_step": [float(x) for x in gaps], "steps": int(gaps.size), "min": float(gaps.min()), "median": float(np.median(gaps)),
+            "below_2e-4": int(np.sum(gaps <= 2e-4)), "below_2e-10": int(np.sum(gaps <= 2e-10)),
+            "quantiles_10_50_90": [float(x) for x in np.quantile(gaps, [0.1, 0.5, 0.9])]}
+
+
+def per_step_diff(gain, gain_ref, upto):
+    import numpy as np
+    if not upto:
+        return None
+    d = np.abs(gain[:upto] - gain_ref[:upto]) / np.maximum(1, np.abs(gain_ref[:upto]))
+    return {"max": float(d.max()), "median": float(np.median(d)), "p90": float(np.quantile(d, 0.9))}
 
 
 def run_batched(args):
@@ -286,12 +347,20 @@ def main():
         sel64.profile(reset=True)
         ms64, (idx64, gain64) = timed_selections(sel64, K, budget, args.fp64_steps)
         p64 = sel64.profile(reset=True)
+        if not args.no_gaps:
+            gaps = top_two_gaps(sel64, K, budget)
         sel64.close()
         log(f"fp64: {ms64:.1f} ms per selection")
         result["fp64"] = {"value": round(budget / (ms64 * 1e-3), 3), "unit": "greedy steps/s",
                           "ms_per_step": round(ms64, 3), "roofline": roofline_syrk(p64, "fp64", spec.name),
                           "kernel_ms_per_step": {k: round(v / args.fp64_steps, 3) for k, v in p64["ms"].items()}}
         result["mixed_vs_fp64"] = {"speedup": round(ms64 / ms, 3), **compare_picks(idx, gain, idx64, gain64)}
+        if not args.no_gaps:
+            per = gaps.pop("per_step")
+            result["fp64"]["top_two_gap"] = gaps
+            fd = result["mixed_vs_fp64"]["first_divergence_step"]
+            if fd is not None and fd < len(per):
+                result["mixed_vs_fp64"]["fp64_top_two_gap_at_divergence"] = per[fd]
 
     # ---- the BF16 split-product downdate beside it, same K
     if not args.no_bf16x3 and prec == "mixed_f32" and spec.N_t <= 128 and not args.precision:
@@ -309,11 +378,14 @@ def main():
                                   "vs_mixed_f32": compare_picks(idxb, gainb, idx, gain)}
         if "fp64" in result:
             result["mixed_bf16x3"]["vs_fp64"] = compare_picks(idxb, gainb, idx64, gain64)
+            fd = result["mixed_bf16x3"]["vs_fp64"]["first_divergence_step"]
+            if fd is not None and not args.no_gaps and fd < len(per):
+                result["mixed_bf16x3"]["vs_fp64"]["fp64_top_two_gap_at_divergence"] = per[fd]
 
     # ---- CPU oracle baseline on a bounded sample of the same K
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle) ...")
-        cb = cpu_baseline(K, spec.N_t, s2, args.cpu_sensors, args.cpu_budget)
+        cb = cpu_baseline(K, spec.N_t, s2, args.cpu_sensors, args.cpu_budget, full_shape=(spec.N_s, budget))
         sel_s = Selector(K, spec.N_s, spec.N_t, s2, precision=prec, candidates=range(args.cpu_sensors))
         i_s, g_s = sel_s.greedy(args.cpu_budget)
         sel_s.close()
