@@ -90,7 +90,12 @@ typedef struct oed_options {
     const int32_t *candidates;  /* host array of candidate sensors (the set C of Sec. III-A);
                                    NULL = all N_s sensors.  Copied during oed_create. */
     int32_t n_candidates;       /* length of candidates */
-    int32_t reserved[7];        /* must be 0 */
+    int32_t delay;              /* downdate delay depth: 1 = subtract every pick's W W^T at the
+                                   next step; 2 = hold one pick's W and subtract it together with
+                                   the next one (the gain and pick steps correct the held blocks
+                                   exactly; same picks, half the R traffic per pick); 0 = automatic
+                                   (2 for N_t <= 128, else 1).  2 with N_t > 128: OED_E_UNSUPPORTED */
+    int32_t reserved[6];        /* must be 0 */
 } oed_options;
 
 /* Fill *opt with the defaults (FP64, no flags, all sensors). */
@@ -189,11 +194,14 @@ typedef struct oed_batch oed_batch;
 
 /* Don't capture the schedule into a HIP graph: enqueue the launches on every run. */
 #define OED_BATCH_NO_GRAPH 0x2u
+/* Downdate delay depth 1 (subtract every pick's W W^T at once) instead of the default 2 (see
+   oed_options.delay). */
+#define OED_BATCH_DELAY1 0x4u
 
 /*
  * Create a batch over inst[0..n): validates every instance, allocates all device memory,
  * packs every working copy and builds the launch schedule.  flags: OED_FLAG_PROFILE (time
- * each run with HIP events), OED_BATCH_NO_GRAPH.  On failure *out is NULL.
+ * each run with HIP events), OED_BATCH_NO_GRAPH, OED_BATCH_DELAY1.  On failure *out is NULL.
  */
 OED_API oed_status oed_batch_create(oed_batch **out, const oed_instance *inst, int32_t n, int32_t precision,
                                     void *stream, uint32_t flags);

@@ -37,13 +37,15 @@ struct oed_ctx {
     int prec = OED_PREC_FP64;
     int rtype = R_F64, wtype = W_F64;
     int syrk_variant = SYRK_LDS;
+    int delay = 1;  // 2: a pick's block column may be held and applied with the next one
     uint32_t flags = 0;
     hipStream_t stream = nullptr;
     int device = 0;
     std::vector<int> cmap;  // local -> original sensor index (ascending)
     std::vector<int> lmap;  // original -> local (-1 = not a candidate)
     // device memory
-    void *R = nullptr, *W = nullptr, *W2 = nullptr;
+    void *R = nullptr, *Wb[2] = {nullptr, nullptr}, *W2b[2] = {nullptr, nullptr};  // W slots (BF16: hi, lo)
+    double *V = nullptr;
     double *Linv = nullptr, *gains = nullptr, *pick_gain = nullptr, *scratch_gain = nullptr,
            *scratch_pick = nullptr;
     int *act[2] = {nullptr, nullptr}, *picks = nullptr, *state = nullptr, *dcmap = nullptr;
@@ -52,7 +54,8 @@ struct oed_ctx {
     int cur = 0;       // which act buffer is current
     int n_act = 0;     // remaining candidates
     int k = 0;         // picks made
-    bool pending = false;  // the last pick's downdate is not applied yet
+    bool pending = false;  // the last pick's block column and downdate are not formed yet
+    int held = -1;         // W slot formed but not yet subtracted from R (delay 2), or -1
     bool poisoned = false;
     std::vector<int> h_picks;   // local indices
     std::vector<double> h_gains;
@@ -132,7 +135,7 @@ void collect_profile(oed_ctx *h)
 
 void free_all(oed_ctx *h)
 {
-    void *ptrs[] = {h->R, h->W, h->W2, h->Linv, h->gains, h->pick_gain, h->scratch_gain, h->scratch_pick,
+    void *ptrs[] = {h->R, h->Wb[0], h->Wb[1], h->W2b[0], h->W2b[1], h->V, h->Linv, h->gains, h->pick_gain, h->scratch_gain, h->scratch_pick,
                     h->act[0], h->act[1], h->picks, h->state, h->dcmap};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
@@ -154,6 +157,7 @@ oed_status load_R(oed_ctx *h, const void *K)
     h->n_act = h->N_c;
     h->k = 0;
     h->pending = false;
+    h->held = -1;
     h->poisoned = false;
     h->h_picks.clear();
     h->h_gains.clear();
@@ -166,8 +170,16 @@ StepDesc desc(const oed_ctx *h)
 {
     StepDesc d{};
     d.R = h->R;
-    d.W = h->W;
-    d.W2 = h->W2;
+    // the slot the next block column goes to, and the held one
+    const int ws = h->held >= 0 ? h->held ^ 1 : 0;
+    d.W = h->Wb[ws];
+    d.W2 = h->W2b[ws];
+    if (h->held >= 0) {
+        d.P = h->Wb[h->held];
+        d.P2 = h->W2b[h->held];
+    }
+    d.V = h->V;
+    d.nw = 1;
     d.act_in = h->act[h->cur];
     d.act_out = h->act[h->cur ^ 1];
     d.gains = h->gains;
@@ -186,25 +198,53 @@ StepDesc desc(const oed_ctx *h)
     return d;
 }
 
-// Enqueue the downdate of the last pick if it has not been applied.
-oed_status flush_pending(oed_ctx *h)
+oed_status enqueue_syrk(oed_ctx *h, StepDesc d)
 {
-    if (!h->pending) return OED_OK;
-    h->pending = false;
-    if (h->n_act == 0) return OED_OK;
-    StepDesc d = desc(h);
-    {
-        Prof pr(h, OED_K_TRSM);
-        HIPCHK(h, launch_trsm(d, h->rtype, h->wtype, h->stream));
-    }
     d.nitems = syrk_tiles(h->n_act, h->N_tp);
     {
         Prof pr(h, OED_K_SYRK);
         HIPCHK(h, launch_syrk(d, h->rtype, h->wtype, h->syrk_variant, h->stream));
     }
     const double n = (double)h->n_act * h->N_t;
-    h->syrk_flops += (double)h->N_t * n * (n + 1.0);
-    h->syrk_bytes += (double)relem(h) * (n * (n + h->N_t) + n * h->N_t);
+    h->syrk_flops += d.nw * (double)h->N_t * n * (n + 1.0);
+    h->syrk_bytes += (double)relem(h) * (n * (n + h->N_t) + d.nw * n * h->N_t);
+    return OED_OK;
+}
+
+// Form the block column W of the last pick (Sec. III-D: the new block row of the factor) and
+// subtract the outer products from R.  With delay 2 and `full` false, a W with no held
+// predecessor is held: the gain and pick kernels correct for it, and it is subtracted together
+// with the next pick's W (one downdate of inner dimension 2 N_t, half the R traffic per pick).
+// `full` leaves R current.
+oed_status advance(oed_ctx *h, bool full)
+{
+    if (h->pending) {
+        h->pending = false;
+        if (h->n_act == 0) {
+            h->held = -1;
+            return OED_OK;
+        }
+        StepDesc d = desc(h);
+        {
+            Prof pr(h, OED_K_TRSM);
+            if (d.P) HIPCHK(h, launch_vcorr(d, h->wtype, h->stream));
+            HIPCHK(h, launch_trsm(d, h->rtype, h->wtype, h->stream));
+        }
+        const int ws = h->held >= 0 ? h->held ^ 1 : 0;
+        if (h->held >= 0 || full || h->delay == 1) {
+            d.nw = h->held >= 0 ? 2 : 1;
+            h->held = -1;
+            return enqueue_syrk(h, d);
+        }
+        h->held = ws;
+    } else if (full && h->held >= 0) {
+        StepDesc d = desc(h);
+        d.W = h->Wb[h->held];
+        d.W2 = h->W2b[h->held];
+        d.P = d.P2 = nullptr;
+        h->held = -1;
+        return enqueue_syrk(h, d);
+    }
     return OED_OK;
 }
 
@@ -213,7 +253,7 @@ oed_status enqueue_gains(oed_ctx *h)
     StepDesc d = desc(h);
     d.scratch = h->scratch_gain;
     Prof pr(h, OED_K_GAIN);
-    HIPCHK(h, launch_gain(d, h->rtype, h->stream));
+    HIPCHK(h, launch_gain(d, h->rtype, h->wtype, h->stream));
     return OED_OK;
 }
 
@@ -225,7 +265,7 @@ oed_status enqueue_pick(oed_ctx *h, int forced_local)
     d.nitems = 1;
     {
         Prof pr(h, OED_K_PICK);
-        HIPCHK(h, launch_pick(d, h->rtype, h->stream));
+        HIPCHK(h, launch_pick(d, h->rtype, h->wtype, h->stream));
     }
     h->cur ^= 1;
     h->n_act -= 1;
@@ -255,6 +295,7 @@ oed_status sync_picks(oed_ctx *h, int k0, oed_status *dev_status)
         h->k = k0 + made;
         h->n_act = h->N_c - h->k;
         h->pending = false;
+        h->held = -1;
         h->poisoned = true;
     }
     for (int q = 0; q < made; ++q) {
@@ -310,6 +351,8 @@ oed_status oed_create(oed_ctx **out, const void *K, int32_t dtype, int64_t ld, i
     if (o.precision != OED_PREC_FP64 && o.precision != OED_PREC_MIXED_F32 && o.precision != OED_PREC_MIXED_BF16X3)
         return OED_E_ARG;
     if (o.precision == OED_PREC_MIXED_BF16X3 && N_t > 128) return OED_E_UNSUPPORTED;
+    if (o.delay < 0 || o.delay > 2) return OED_E_ARG;
+    if (o.delay == 2 && N_t > REGS_MAX_NT) return OED_E_UNSUPPORTED;
     for (int r : o.reserved)
         if (r != 0) return OED_E_ARG;
 
@@ -327,6 +370,9 @@ oed_status oed_create(oed_ctx **out, const void *K, int32_t dtype, int64_t ld, i
     h->rtype = o.precision == OED_PREC_FP64 ? R_F64 : R_F32;
     h->wtype = o.precision == OED_PREC_FP64 ? W_F64 : o.precision == OED_PREC_MIXED_F32 ? W_F32 : W_BF16X3;
     h->flags = o.flags;
+    // delay 0 (automatic): hold one block column whenever the register factorisations and the
+    // LDS downdate serve the block size
+    h->delay = o.delay == 0 ? (N_t <= REGS_MAX_NT ? 2 : 1) : o.delay;
     h->stream = (hipStream_t)stream;
     h->lmap.assign(N_s, -1);
     if (o.candidates) {
@@ -354,8 +400,12 @@ oed_status oed_create(oed_ctx **out, const void *K, int32_t dtype, int64_t ld, i
         const int64_t bs = (int64_t)h->N_tp * h->N_tp;
         const int64_t nblk = (int64_t)h->N_c * (h->N_c + 1) / 2;
         HIPCHK(h, dmalloc(h, &h->R, (size_t)(nblk * bs) * relem(h)));
-        HIPCHK(h, dmalloc(h, &h->W, (size_t)(h->N_c * bs) * (h->wtype == W_F64 ? 8 : h->wtype == W_F32 ? 4 : 2)));
-        if (h->wtype == W_BF16X3) HIPCHK(h, dmalloc(h, &h->W2, (size_t)(h->N_c * bs) * 2));
+        const size_t we = h->wtype == W_F64 ? 8 : h->wtype == W_F32 ? 4 : 2;
+        for (int q = 0; q < h->delay; ++q) {
+            HIPCHK(h, dmalloc(h, &h->Wb[q], (size_t)(h->N_c * bs) * we));
+            if (h->wtype == W_BF16X3) HIPCHK(h, dmalloc(h, &h->W2b[q], (size_t)(h->N_c * bs) * 2));
+        }
+        if (h->delay == 2) HIPCHK(h, dmalloc(h, (void **)&h->V, sizeof(double) * bs));
         HIPCHK(h, dmalloc(h, (void **)&h->Linv, sizeof(double) * bs));
         HIPCHK(h, dmalloc(h, (void **)&h->gains, sizeof(double) * h->N_c));
         HIPCHK(h, dmalloc(h, (void **)&h->pick_gain, sizeof(double) * h->N_c));
@@ -406,7 +456,7 @@ oed_status oed_greedy(oed_ctx *h, int32_t budget, int32_t *idx_out, double *gain
     if (budget > 0 && (!idx_out || !gain_out)) return fail(h, OED_E_ARG, "NULL output array");
     const int k0 = h->k;
     for (int step = 0; step < budget; ++step) {
-        oed_status st = flush_pending(h);
+        oed_status st = advance(h, false);
         if (st == OED_OK) st = enqueue_gains(h);
         if (st == OED_OK) st = enqueue_pick(h, -1);
         if (st != OED_OK) return st;
@@ -432,7 +482,7 @@ oed_status oed_force(oed_ctx *h, int32_t idx, double *gain_out)
     if (idx < 0 || idx >= h->N_s || h->lmap[idx] < 0 || h->picked[h->lmap[idx]])
         return fail(h, OED_E_ARG, "index is not a remaining candidate");
     const int k0 = h->k;
-    oed_status st = flush_pending(h);
+    oed_status st = advance(h, false);
     if (st == OED_OK) st = enqueue_pick(h, h->lmap[idx]);
     if (st != OED_OK) return st;
     oed_status dev = OED_OK;
@@ -450,7 +500,7 @@ oed_status oed_scores(oed_ctx *h, double *out)
     if (h->poisoned) return fail(h, OED_E_STATE, "handle stopped; reset it");
     for (int q = 0; q < h->N_s; ++q) out[q] = -INFINITY;
     if (h->n_act == 0) return OED_OK;
-    oed_status st = flush_pending(h);
+    oed_status st = advance(h, false);
     if (st == OED_OK) st = enqueue_gains(h);
     if (st != OED_OK) return st;
     std::vector<double> g(h->n_act);
@@ -470,7 +520,7 @@ oed_status oed_schur_block(oed_ctx *h, int32_t i, int32_t j, double *out)
     if (i < 0 || j < 0 || i >= h->N_s || j >= h->N_s) return fail(h, OED_E_ARG, "index out of range");
     int li = h->lmap[i], lj = h->lmap[j];
     if (li < 0 || lj < 0 || h->picked[li] || h->picked[lj]) return fail(h, OED_E_ARG, "not a remaining candidate");
-    oed_status st = flush_pending(h);
+    oed_status st = advance(h, true);
     if (st != OED_OK) return st;
     const bool tr = li < lj;
     if (tr) std::swap(li, lj);

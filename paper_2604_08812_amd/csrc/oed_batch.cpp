@@ -28,13 +28,14 @@ struct Inst {
     int N_s = 0, N_t = 0, N_tp = 0, budget = 0, kdtype = 0;
     int64_t ld = 0;
     double sigma2 = 0, half_noise = 0;
-    void *R = nullptr, *W = nullptr, *W2 = nullptr;
+    void *R = nullptr, *W[2] = {nullptr, nullptr}, *W2[2] = {nullptr, nullptr};  // W slots (BF16: hi, lo)
+    double *V = nullptr;
     double *Linv = nullptr, *gains = nullptr, *pick_gain = nullptr;
     int *act[2] = {nullptr, nullptr}, *cmap = nullptr, *picks = nullptr, *state = nullptr;
     size_t off_gain = 0, off_int = 0;  // offsets of this instance's results in the results block
 };
 
-enum LaunchKind { L_INIT, L_GAIN, L_PICK, L_TRSM, L_SYRK };
+enum LaunchKind { L_INIT, L_GAIN, L_PICK, L_VCORR, L_TRSM, L_SYRK };
 
 struct Launch {
     int kind = L_INIT;
@@ -43,6 +44,7 @@ struct Launch {
     int ndesc = 0;
     int64_t total = 0;   // work items
     int N_tp = 0;        // L_SYRK
+    int nw = 1;          // L_SYRK
     int max_Nt = 0;      // L_PICK
 };
 
@@ -59,6 +61,7 @@ Launch make_launch(int kind, int64_t desc0)
 struct oed_batch {
     std::vector<Inst> in;
     int prec = OED_PREC_FP64, rtype = R_F64, wtype = W_F64;
+    int delay = 2;
     uint32_t flags = 0;
     hipStream_t stream = nullptr;
     std::vector<void *> allocs;
@@ -134,12 +137,24 @@ oed_status pack_all(oed_batch *b, const oed_instance *inst)
     return OED_OK;
 }
 
-StepDesc inst_desc(const Inst &x, int k, bool after_pick)
+// Descriptor of instance x at step k, before (gains, pick) or after (block column, downdate)
+// its k-th pick.  With delay 2 the block column of an even pick goes to slot 0 and is held; the
+// next (odd) pick's gains and pick correct for it, its block column goes to slot 1, and both are
+// subtracted in one downdate.
+StepDesc inst_desc(const Inst &x, int k, bool after_pick, int delay)
 {
     StepDesc d{};
     d.R = x.R;
-    d.W = x.W;
-    d.W2 = x.W2;
+    const bool held = delay == 2 && (k & 1) != 0;  // pick k - 1's block column is held in slot 0
+    const int ws = held && after_pick ? 1 : 0;
+    d.W = x.W[ws];
+    d.W2 = x.W2[ws];
+    if (held) {
+        d.P = x.W[0];
+        d.P2 = x.W2[0];
+    }
+    d.V = x.V;
+    d.nw = 1;
     d.act_in = x.act[(k + (after_pick ? 1 : 0)) & 1];
     d.act_out = x.act[(k + 1) & 1];
     d.gains = x.gains;
@@ -175,7 +190,7 @@ void build_schedule(oed_batch *b)
         Launch g = make_launch(L_GAIN, (int64_t)b->descs.size());
         for (const Inst &x : b->in)
             if (x.budget > k) {
-                StepDesc d = inst_desc(x, k, false);
+                StepDesc d = inst_desc(x, k, false, b->delay);
                 d.item0 = g.total;
                 d.nitems = d.n_act;
                 g.total += d.nitems;
@@ -186,7 +201,7 @@ void build_schedule(oed_batch *b)
         Launch p = make_launch(L_PICK, (int64_t)b->descs.size());
         for (const Inst &x : b->in)
             if (x.budget > k) {
-                StepDesc d = inst_desc(x, k, false);
+                StepDesc d = inst_desc(x, k, false, b->delay);
                 d.item0 = p.total;
                 d.nitems = 1;
                 p.total += 1;
@@ -195,29 +210,51 @@ void build_schedule(oed_batch *b)
                 ++p.ndesc;
             }
         b->launches.push_back(p);
-        // downdate for the instances that pick again
+        // block column and downdate for the instances that pick again; with delay 2 an even
+        // pick's block column is held (no downdate) and an odd pick's is corrected for it
+        const bool hold = b->delay == 2 && (k & 1) == 0;
+        const bool corr = b->delay == 2 && (k & 1) == 1;
+        if (corr) {
+            Launch v = make_launch(L_VCORR, (int64_t)b->descs.size());
+            for (const Inst &x : b->in)
+                if (x.budget > k + 1) {
+                    StepDesc d = inst_desc(x, k, true, b->delay);
+                    d.item0 = v.total;
+                    d.nitems = (int64_t)(x.N_tp / 16) * (x.N_tp / 16);
+                    v.total += d.nitems;
+                    b->descs.push_back(d);
+                    ++v.ndesc;
+                }
+            if (v.ndesc) b->launches.push_back(v);
+        }
         Launch t = make_launch(L_TRSM, (int64_t)b->descs.size());
         std::map<int, std::vector<const Inst *>> by_ntp;
         for (const Inst &x : b->in)
             if (x.budget > k + 1) {
-                StepDesc d = inst_desc(x, k, true);
+                StepDesc d = inst_desc(x, k, true, b->delay);
                 d.item0 = t.total;
                 d.nitems = d.n_act;
                 t.total += d.nitems;
                 b->descs.push_back(d);
                 ++t.ndesc;
                 by_ntp[x.N_tp].push_back(&x);
-                const double nr = (double)d.n_act * x.N_t;
-                b->syrk_flops += (double)x.N_t * nr * (nr + 1.0);
-                b->syrk_bytes += e * (nr * (nr + x.N_t) + nr * x.N_t);
+                if (!hold) {
+                    const int nw = corr ? 2 : 1;
+                    const double nr = (double)d.n_act * x.N_t;
+                    b->syrk_flops += nw * (double)x.N_t * nr * (nr + 1.0);
+                    b->syrk_bytes += e * (nr * (nr + x.N_t) + nw * nr * x.N_t);
+                }
             }
         if (t.ndesc == 0) continue;
         b->launches.push_back(t);
+        if (hold) continue;
         for (auto &kv : by_ntp) {
             Launch s = make_launch(L_SYRK, (int64_t)b->descs.size());
             s.N_tp = kv.first;
+            s.nw = corr ? 2 : 1;
             for (const Inst *x : kv.second) {
-                StepDesc d = inst_desc(*x, k, true);
+                StepDesc d = inst_desc(*x, k, true, b->delay);
+                d.nw = s.nw;
                 d.item0 = s.total;
                 d.nitems = syrk_tiles(d.n_act, d.N_tp);
                 s.total += d.nitems;
@@ -239,11 +276,12 @@ oed_status enqueue_run(oed_batch *b)
             BCHK(b, launch_init_state(x.act[0], x.N_s, x.state, b->stream));
             break;
         }
-        case L_GAIN: BCHK(b, launch_gain_batched(d, L.ndesc, L.total, b->rtype, b->stream)); break;
-        case L_PICK: BCHK(b, launch_pick_batched(d, L.ndesc, L.max_Nt, b->rtype, b->stream)); break;
+        case L_GAIN: BCHK(b, launch_gain_batched(d, L.ndesc, L.total, b->rtype, b->wtype, b->stream)); break;
+        case L_PICK: BCHK(b, launch_pick_batched(d, L.ndesc, L.max_Nt, b->rtype, b->wtype, b->stream)); break;
+        case L_VCORR: BCHK(b, launch_vcorr_batched(d, L.ndesc, L.total, b->wtype, b->stream)); break;
         case L_TRSM: BCHK(b, launch_trsm_batched(d, L.ndesc, L.total, b->rtype, b->wtype, b->stream)); break;
         case L_SYRK:
-            BCHK(b, launch_syrk_batched(d, L.ndesc, L.total, L.N_tp, b->rtype, b->wtype, SYRK_LDS, b->stream));
+            BCHK(b, launch_syrk_batched(d, L.ndesc, L.total, L.N_tp, L.nw, b->rtype, b->wtype, SYRK_LDS, b->stream));
             break;
         }
     }
@@ -269,6 +307,7 @@ oed_status oed_batch_create(oed_batch **out, const oed_instance *inst, int32_t n
     b->rtype = precision == OED_PREC_FP64 ? R_F64 : R_F32;
     b->wtype = precision == OED_PREC_FP64 ? W_F64 : precision == OED_PREC_MIXED_F32 ? W_F32 : W_BF16X3;
     b->flags = flags;
+    b->delay = (flags & OED_BATCH_DELAY1) ? 1 : 2;
     auto setup = [&]() -> oed_status {
         // the caller's K must be complete before the batch stream reads it
         BCHK(b, hipStreamSynchronize((hipStream_t)stream));
@@ -291,12 +330,15 @@ oed_status oed_batch_create(oed_batch **out, const oed_instance *inst, int32_t n
             x.half_noise = 0.5 * y.N_t * std::log(y.sigma2);
             const int64_t bs = (int64_t)x.N_tp * x.N_tp, nblk = (int64_t)x.N_s * (x.N_s + 1) / 2;
             BCHK(b, balloc(b, &x.R, (size_t)(nblk * bs) * er));
-            if (b->wtype == W_BF16X3) {
-                BCHK(b, balloc(b, &x.W, (size_t)(x.N_s * bs) * 2));
-                BCHK(b, balloc(b, &x.W2, (size_t)(x.N_s * bs) * 2));
-            } else {
-                BCHK(b, balloc(b, &x.W, (size_t)(x.N_s * bs) * er));
+            for (int q = 0; q < b->delay; ++q) {
+                if (b->wtype == W_BF16X3) {
+                    BCHK(b, balloc(b, &x.W[q], (size_t)(x.N_s * bs) * 2));
+                    BCHK(b, balloc(b, &x.W2[q], (size_t)(x.N_s * bs) * 2));
+                } else {
+                    BCHK(b, balloc(b, &x.W[q], (size_t)(x.N_s * bs) * er));
+                }
             }
+            if (b->delay == 2) BCHK(b, balloc(b, (void **)&x.V, sizeof(double) * bs));
             BCHK(b, balloc(b, (void **)&x.Linv, sizeof(double) * bs));
             BCHK(b, balloc(b, (void **)&x.gains, sizeof(double) * x.N_s));
             BCHK(b, balloc(b, (void **)&x.act[0], sizeof(int) * x.N_s));

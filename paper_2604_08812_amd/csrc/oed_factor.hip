@@ -165,9 +165,68 @@ __device__ __forceinline__ bool chol_block(double (&A)[2][8][4], int N_t, int nb
 // (unscaled, a_t = A[t][j]) in a double-buffered LDS vector; every thread then reads the pivot
 // d = a_j and applies A[t][u] -= a_t a_u / d to the elements it owns with t, u > j.  The
 // pivots are kept; sum_t ln L_tt = 1/2 sum_j ln d_j.  With Lout, L is also written (packed).
-template <typename TR>
+// Product P_I P_J^T of sub-block rows I and J of one candidate's held W block (the W of an
+// earlier pick that R does not include yet), over its first nk 16-wide inner blocks (the rest
+// is padding, zero), in the 16x16 accumulator order of R: element (4g + r, l % 16) of lane l,
+// register r.  Same operand orders and MFMA types as the downdate.
+template <typename TW>
+struct HeldProd;
+template <>
+struct HeldProd<double> {
+    __device__ static __forceinline__ doublex4 run(const double *P, const double *, int I, int J, int nb, int nk,
+                                                   int lane)
+    {
+        const int al = a_lane<double>(lane);
+        doublex4 acc{0.0, 0.0, 0.0, 0.0};
+        for (int kc = 0; kc < nk; ++kc) {
+            const doublex4 a = ld4(P + ((I * nb + kc) << 8) + al * 4);
+            const doublex4 b = ld4(P + ((J * nb + kc) << 8) + lane * 4);
+#pragma unroll
+            for (int s4 = 0; s4 < 4; ++s4) acc = mfma16(a[s4], b[s4], acc);
+        }
+        return acc;
+    }
+};
+template <>
+struct HeldProd<float> {
+    __device__ static __forceinline__ floatx4 run(const float *P, const float *, int I, int J, int nb, int nk,
+                                                  int lane)
+    {
+        floatx4 acc{0.f, 0.f, 0.f, 0.f};
+        for (int kc = 0; kc < nk; ++kc) {
+            const floatx4 a = ld4(P + ((I * nb + kc) << 8) + lane * 4);
+            const floatx4 b = ld4(P + ((J * nb + kc) << 8) + lane * 4);
+#pragma unroll
+            for (int s4 = 0; s4 < 4; ++s4) acc = mfma16(a[s4], b[s4], acc);
+        }
+        return acc;
+    }
+};
+template <>
+struct HeldProd<unsigned short> {
+    // BF16 hi (P) and lo (P2) parts, 16 x 32 sub-blocks: hi hi^T + hi lo^T + lo hi^T
+    __device__ static __forceinline__ floatx4 run(const unsigned short *P, const unsigned short *P2, int I, int J,
+                                                  int nb, int nk, int lane)
+    {
+        const int nb32 = nb >> 1;
+        floatx4 acc{0.f, 0.f, 0.f, 0.f};
+        for (int kc = 0; kc < (nk + 1) >> 1; ++kc) {
+            const int64_t oa = ((int64_t)(I * nb32 + kc) << 9) + lane * 8, ob = ((int64_t)(J * nb32 + kc) << 9) + lane * 8;
+            const u32x4 ah = *reinterpret_cast<const u32x4 *>(P + oa), al = *reinterpret_cast<const u32x4 *>(P2 + oa);
+            const u32x4 bh = *reinterpret_cast<const u32x4 *>(P + ob), bl = *reinterpret_cast<const u32x4 *>(P2 + ob);
+            acc = mfma_bf16(ah, bh, acc);
+            acc = mfma_bf16(ah, bl, acc);
+            acc = mfma_bf16(al, bh, acc);
+        }
+        return acc;
+    }
+};
+
+// With P (the candidate's held W block; P2 its BF16 lo parts) the factored matrix is
+// R_jj - P_j P_j^T, the candidate's current Schur block.
+template <typename TR, typename TW>
 __device__ __forceinline__ bool chol_regs(const TR *__restrict__ Rb, int N_t, int nb, double *colbuf, double *piv,
-                                          double *Lout)
+                                          double *Lout, const TW *P, const TW *P2)
 {
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     const int nbr = (N_t + 15) >> 4;
@@ -185,6 +244,19 @@ __device__ __forceinline__ bool chol_regs(const TR *__restrict__ Rb, int N_t, in
 #pragma unroll
                 for (int r = 0; r < 4; ++r) A[h][J][r] = 0.0;
             }
+        }
+    }
+    if (P) {
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            const int I = h ? 7 - w : w;
+#pragma unroll
+            for (int J = 0; J < 8; ++J)
+                if (I < nbr && J <= I) {
+                    const auto c = HeldProd<TW>::run(P, P2, I, J, nb, nbr, lane);
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) A[h][J][r] -= (double)c[r];
+                }
         }
     }
     bool ok = chol_block<0>(A, N_t, nbr, colbuf, piv, Lout);
@@ -393,7 +465,7 @@ __device__ __forceinline__ int select_winner(const int *__restrict__ act_in, int
 // ---------------------------------------------------------------------------------------------
 // Kernel bodies (one work-group; early exits are uniform across it).
 
-template <typename TR>
+template <typename TR, typename TW>
 __device__ void gain_regs_body(const StepDesc &d, int p)
 {
     __shared__ double colbuf[256];
@@ -401,8 +473,11 @@ __device__ void gain_regs_body(const StepDesc &d, int p)
     __shared__ double red[4];
     if (d.state[ST_STATUS] != 0 || p >= d.n_act) return;
     const int i = d.act_in[p];
-    const bool ok =
-        chol_regs((const TR *)d.R + blk_index(i, i) * (int64_t)d.N_tp * d.N_tp, d.N_t, d.N_tp >> 4, colbuf, piv, nullptr);
+    const int64_t bs = (int64_t)d.N_tp * d.N_tp;
+    const TW *P = d.P ? (const TW *)d.P + i * bs : nullptr;
+    const TW *P2 = d.P2 ? (const TW *)d.P2 + i * bs : nullptr;
+    const bool ok = chol_regs<TR, TW>((const TR *)d.R + blk_index(i, i) * bs, d.N_t, d.N_tp >> 4, colbuf, piv, nullptr,
+                                      P, P2);
     if (!ok) {
         if (threadIdx.x == 0) d.gains[p] = -INFINITY;
         return;
@@ -411,7 +486,7 @@ __device__ void gain_regs_body(const StepDesc &d, int p)
     if (threadIdx.x == 0) d.gains[p] = ls - d.half_noise;
 }
 
-template <typename TR>
+template <typename TR, typename TW>
 __device__ void pick_regs_body(const StepDesc &d, double *Lout)
 {
     __shared__ double colbuf[1024];
@@ -424,8 +499,11 @@ __device__ void pick_regs_body(const StepDesc &d, double *Lout)
     if (pos < 0) return;
     const int s = d.act_in[pos];
     for (int p = tid; p < d.n_act - 1; p += blockDim.x) d.act_out[p] = d.act_in[p < pos ? p : p + 1];
+    const int64_t bs = (int64_t)d.N_tp * d.N_tp;
+    const TW *P = d.P ? (const TW *)d.P + s * bs : nullptr;
+    const TW *P2 = d.P2 ? (const TW *)d.P2 + s * bs : nullptr;
     const bool ok =
-        chol_regs((const TR *)d.R + blk_index(s, s) * (int64_t)d.N_tp * d.N_tp, d.N_t, d.N_tp >> 4, colbuf, piv, Lout);
+        chol_regs<TR, TW>((const TR *)d.R + blk_index(s, s) * bs, d.N_t, d.N_tp >> 4, colbuf, piv, Lout, P, P2);
     if (!ok) {
         if (tid == 0) d.state[ST_STATUS] = 2;
         return;
@@ -494,36 +572,36 @@ __device__ void pick_lds_body(const StepDesc &d, double *lds)
 // ---------------------------------------------------------------------------------------------
 // Kernels: single instance (descriptor by value) and batched (descriptor array).
 
-template <typename TR>
+template <typename TR, typename TW>
 __global__ void __launch_bounds__(256) gain_regs_kernel(StepDesc d)
 {
-    gain_regs_body<TR>(d, blockIdx.x);
+    gain_regs_body<TR, TW>(d, blockIdx.x);
 }
 
-template <typename TR>
+template <typename TR, typename TW>
 __global__ void __launch_bounds__(256) gain_regs_batched(const StepDesc *__restrict__ ds, int n)
 {
     const int i = find_instance(ds, n, blockIdx.x);
     if (i < 0) return;
     const StepDesc d = ds[i];
-    gain_regs_body<TR>(d, (int)(blockIdx.x - d.item0));
+    gain_regs_body<TR, TW>(d, (int)(blockIdx.x - d.item0));
 }
 
-template <typename TR>
+template <typename TR, typename TW>
 __global__ void __launch_bounds__(256) pick_regs_kernel(StepDesc d)
 {
     extern __shared__ double dyn[];
-    pick_regs_body<TR>(d, dyn);
+    pick_regs_body<TR, TW>(d, dyn);
 }
 
-template <typename TR>
+template <typename TR, typename TW>
 __global__ void __launch_bounds__(256) pick_regs_batched(const StepDesc *__restrict__ ds, int n)
 {
     extern __shared__ double dyn[];
     const int i = find_instance(ds, n, blockIdx.x);
     if (i < 0) return;
     const StepDesc d = ds[i];
-    pick_regs_body<TR>(d, dyn);
+    pick_regs_body<TR, TW>(d, dyn);
 }
 
 template <typename TR>
@@ -574,13 +652,15 @@ static void allow_lds(K kernel, size_t bytes)
     if (bytes > 65536) (void)hipFuncSetAttribute((const void *)kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
 }
 
-template <typename TR>
+// The LDS factorisation kernels (N_t > REGS_MAX_NT) take no held W.
+template <typename TR, typename TW>
 static hipError_t launch_gain_t(const StepDesc &d, hipStream_t s)
 {
     if (d.n_act <= 0) return hipSuccess;
     if (d.N_t <= REGS_MAX_NT) {
-        hipLaunchKernelGGL(gain_regs_kernel<TR>, dim3(d.n_act), dim3(256), 0, s, d);
+        hipLaunchKernelGGL((gain_regs_kernel<TR, TW>), dim3(d.n_act), dim3(256), 0, s, d);
     } else {
+        if (d.P) return hipErrorInvalidValue;
         const size_t lds = d.scratch ? 0 : gain_lds_bytes(d.N_t);
         allow_lds(gain_lds_kernel<TR>, lds);
         hipLaunchKernelGGL(gain_lds_kernel<TR>, dim3(d.n_act), dim3(256), lds, s, d);
@@ -588,14 +668,15 @@ static hipError_t launch_gain_t(const StepDesc &d, hipStream_t s)
     return hipGetLastError();
 }
 
-template <typename TR>
+template <typename TR, typename TW>
 static hipError_t launch_pick_t(const StepDesc &d, hipStream_t s)
 {
     if (d.N_t <= REGS_MAX_NT) {
         const size_t lds = sizeof(double) * (size_t)d.N_t * (d.N_t + 1) / 2;
-        allow_lds(pick_regs_kernel<TR>, lds);
-        hipLaunchKernelGGL(pick_regs_kernel<TR>, dim3(1), dim3(256), lds, s, d);
+        allow_lds(pick_regs_kernel<TR, TW>, lds);
+        hipLaunchKernelGGL((pick_regs_kernel<TR, TW>), dim3(1), dim3(256), lds, s, d);
     } else {
+        if (d.P) return hipErrorInvalidValue;
         const size_t lds = d.scratch ? 0 : pick_lds_bytes(d.N_t);
         allow_lds(pick_lds_kernel<TR>, lds);
         hipLaunchKernelGGL(pick_lds_kernel<TR>, dim3(1), dim3(256), lds, s, d);
@@ -603,37 +684,61 @@ static hipError_t launch_pick_t(const StepDesc &d, hipStream_t s)
     return hipGetLastError();
 }
 
-hipError_t launch_gain(const StepDesc &d, int rtype, hipStream_t s)
+hipError_t launch_gain(const StepDesc &d, int rtype, int wtype, hipStream_t s)
 {
-    return rtype == R_F64 ? launch_gain_t<double>(d, s) : launch_gain_t<float>(d, s);
+    if (rtype == R_F64 && wtype == W_F64) return launch_gain_t<double, double>(d, s);
+    if (rtype == R_F32 && wtype == W_F32) return launch_gain_t<float, float>(d, s);
+    if (rtype == R_F32 && wtype == W_BF16X3) return launch_gain_t<float, unsigned short>(d, s);
+    return hipErrorInvalidValue;
 }
 
-hipError_t launch_pick(const StepDesc &d, int rtype, hipStream_t s)
+hipError_t launch_pick(const StepDesc &d, int rtype, int wtype, hipStream_t s)
 {
-    return rtype == R_F64 ? launch_pick_t<double>(d, s) : launch_pick_t<float>(d, s);
+    if (rtype == R_F64 && wtype == W_F64) return launch_pick_t<double, double>(d, s);
+    if (rtype == R_F32 && wtype == W_F32) return launch_pick_t<float, float>(d, s);
+    if (rtype == R_F32 && wtype == W_BF16X3) return launch_pick_t<float, unsigned short>(d, s);
+    return hipErrorInvalidValue;
 }
 
-hipError_t launch_gain_batched(const StepDesc *descs, int n, int64_t total, int rtype, hipStream_t s)
+template <typename TR, typename TW>
+static void gain_batched_t(const StepDesc *descs, int n, int64_t total, hipStream_t s)
+{
+    hipLaunchKernelGGL((gain_regs_batched<TR, TW>), dim3((unsigned)total), dim3(256), 0, s, descs, n);
+}
+
+hipError_t launch_gain_batched(const StepDesc *descs, int n, int64_t total, int rtype, int wtype, hipStream_t s)
 {
     if (n <= 0 || total <= 0) return hipSuccess;
-    if (rtype == R_F64)
-        hipLaunchKernelGGL(gain_regs_batched<double>, dim3((unsigned)total), dim3(256), 0, s, descs, n);
+    if (rtype == R_F64 && wtype == W_F64)
+        gain_batched_t<double, double>(descs, n, total, s);
+    else if (rtype == R_F32 && wtype == W_F32)
+        gain_batched_t<float, float>(descs, n, total, s);
+    else if (rtype == R_F32 && wtype == W_BF16X3)
+        gain_batched_t<float, unsigned short>(descs, n, total, s);
     else
-        hipLaunchKernelGGL(gain_regs_batched<float>, dim3((unsigned)total), dim3(256), 0, s, descs, n);
+        return hipErrorInvalidValue;
     return hipGetLastError();
 }
 
-hipError_t launch_pick_batched(const StepDesc *descs, int n, int max_Nt, int rtype, hipStream_t s)
+template <typename TR, typename TW>
+static void pick_batched_t(const StepDesc *descs, int n, size_t lds, hipStream_t s)
+{
+    allow_lds(pick_regs_batched<TR, TW>, lds);
+    hipLaunchKernelGGL((pick_regs_batched<TR, TW>), dim3(n), dim3(256), lds, s, descs, n);
+}
+
+hipError_t launch_pick_batched(const StepDesc *descs, int n, int max_Nt, int rtype, int wtype, hipStream_t s)
 {
     if (n <= 0) return hipSuccess;
     const size_t lds = sizeof(double) * (size_t)max_Nt * (max_Nt + 1) / 2;
-    if (rtype == R_F64) {
-        allow_lds(pick_regs_batched<double>, lds);
-        hipLaunchKernelGGL(pick_regs_batched<double>, dim3(n), dim3(256), lds, s, descs, n);
-    } else {
-        allow_lds(pick_regs_batched<float>, lds);
-        hipLaunchKernelGGL(pick_regs_batched<float>, dim3(n), dim3(256), lds, s, descs, n);
-    }
+    if (rtype == R_F64 && wtype == W_F64)
+        pick_batched_t<double, double>(descs, n, lds, s);
+    else if (rtype == R_F32 && wtype == W_F32)
+        pick_batched_t<float, float>(descs, n, lds, s);
+    else if (rtype == R_F32 && wtype == W_BF16X3)
+        pick_batched_t<float, unsigned short>(descs, n, lds, s);
+    else
+        return hipErrorInvalidValue;
     return hipGetLastError();
 }
 

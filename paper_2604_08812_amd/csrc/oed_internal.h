@@ -65,6 +65,9 @@ struct StepDesc {
     void *R;               // working copy (element type by precision)
     void *W;               // W blocks (element type by precision; BF16X3: the hi parts)
     void *W2;              // BF16X3: the lo parts of W (same layout), else unused
+    void *P;               // held W of an earlier pick whose downdate is not yet applied, or null
+    void *P2;              // BF16X3: its lo parts
+    double *V;             // L_s^-1 P_s of the last pick s when P is held (operand order, N_tp^2)
     const int *act_in;     // remaining candidates (gain, pick: before the pick; trsm, syrk: after it)
     int *act_out;          // pick: remaining candidates after the pick
     double *gains;         // gains by position in act_in
@@ -78,7 +81,7 @@ struct StepDesc {
     int N_t, N_tp;         // real and padded block size
     int step;              // pick: index of this pick
     int forced;            // pick: forced local index, or -1 for the argmax
-    int pad_;
+    int nw;                // syrk: W blocks applied (1: W; 2: W and P, inner dimension 2 N_tp)
     int64_t item0;         // batched launches: first work item of this instance
     int64_t nitems;        // work items of this instance (gain, trsm: n_act; pick: 1; syrk: tiles)
 };
@@ -97,8 +100,12 @@ hipError_t launch_pack(const void *K, int kdtype, int64_t ld, int N_t, int N_tp,
 hipError_t launch_init_state(int *act, int n, int *state, hipStream_t s);
 
 // Single-instance launches (d.item0 = 0, d.nitems = work items).
-hipError_t launch_gain(const StepDesc &d, int rtype, hipStream_t s);
-hipError_t launch_pick(const StepDesc &d, int rtype, hipStream_t s);
+// Delayed downdate: while d.P holds the W of an earlier pick that R does not include yet,
+// the gain and pick kernels factor R_jj - P_j P_j^T, launch_vcorr forms V = L_s^-1 P_s for the
+// new pick s, and the block-column kernel returns W_i = R_is L_s^-T - P_i V^T.
+hipError_t launch_gain(const StepDesc &d, int rtype, int wtype, hipStream_t s);
+hipError_t launch_pick(const StepDesc &d, int rtype, int wtype, hipStream_t s);
+hipError_t launch_vcorr(const StepDesc &d, int wtype, hipStream_t s);
 hipError_t launch_trsm(const StepDesc &d, int rtype, int wtype, hipStream_t s);
 // Downdate kernels: SYRK_DIRECT streams W operands from global memory per wave (any N_tp);
 // SYRK_LDS stages them through LDS with a software pipeline (N_tp <= 128).  W_BF16X3 always
@@ -109,10 +116,12 @@ hipError_t launch_syrk(const StepDesc &d, int rtype, int wtype, int variant, hip
 // Batched launches over n instances (descs: device array sorted by item0, total work items).
 // The register factorisation kernels serve all of them (max_Nt <= REGS_MAX_NT); a batched
 // downdate launch needs one common N_tp.
-hipError_t launch_gain_batched(const StepDesc *descs, int n, int64_t total, int rtype, hipStream_t s);
-hipError_t launch_pick_batched(const StepDesc *descs, int n, int max_Nt, int rtype, hipStream_t s);
+hipError_t launch_gain_batched(const StepDesc *descs, int n, int64_t total, int rtype, int wtype, hipStream_t s);
+hipError_t launch_pick_batched(const StepDesc *descs, int n, int max_Nt, int rtype, int wtype, hipStream_t s);
+hipError_t launch_vcorr_batched(const StepDesc *descs, int n, int64_t total, int wtype, hipStream_t s);
 hipError_t launch_trsm_batched(const StepDesc *descs, int n, int64_t total, int rtype, int wtype, hipStream_t s);
-hipError_t launch_syrk_batched(const StepDesc *descs, int n, int64_t total, int N_tp, int rtype, int wtype,
+// nw: W blocks every instance of the launch applies (its descriptors' nw)
+hipError_t launch_syrk_batched(const StepDesc *descs, int n, int64_t total, int N_tp, int nw, int rtype, int wtype,
                                int variant, hipStream_t s);
 
 // Largest N_t handled by the register-resident factorisation kernels; beyond it the

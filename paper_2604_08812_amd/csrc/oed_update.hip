@@ -39,6 +39,69 @@ __device__ __forceinline__ void store_w_bf16(unsigned short *Wh, unsigned short 
     *reinterpret_cast<u16x4 *>(Wl + off) = lo;
 }
 
+// Four consecutive inner indices k = 16q + 4g .. 16q + 4g + 3 of row t = 16 tb + l % 16 of a W
+// block, as doubles (lane l = 16 g + l % 16): one vector load in the FP32 / FP64 operand order,
+// hi + lo of two 8-byte loads in the BF16 16 x 32 order.
+template <typename TW>
+__device__ __forceinline__ void w_row4(const TW *Wb, const TW *, int tb, int q, int nb, int lane, double (&v)[4])
+{
+    const typename V4<TW>::type x = ld4(Wb + ((int64_t)(tb * nb + q) << 8) + lane * 4);
+#pragma unroll
+    for (int r = 0; r < 4; ++r) v[r] = (double)x[r];
+}
+template <>
+__device__ __forceinline__ void w_row4<unsigned short>(const unsigned short *Wh, const unsigned short *Wl, int tb, int q,
+                                                       int nb, int lane, double (&v)[4])
+{
+    const int g = lane >> 4, l16 = lane & 15;
+    const int64_t off = ((int64_t)(tb * (nb >> 1) + (q >> 1)) << 9) +
+                        (((((q & 1) << 1) + (g >> 1)) << 4) + l16) * 8 + 4 * (g & 1);
+    const u16x4 h = *reinterpret_cast<const u16x4 *>(Wh + off), l = *reinterpret_cast<const u16x4 *>(Wl + off);
+#pragma unroll
+    for (int r = 0; r < 4; ++r) v[r] = (double)bf2f(h[r]) + (double)bf2f(l[r]);
+}
+
+// One element (t, k) of a W block as a double.
+template <typename TW>
+__device__ __forceinline__ double w_elem(const TW *Wb, const TW *, int t, int k, int nb)
+{
+    return (double)Wb[((int64_t)((t >> 4) * nb + (k >> 4)) << 8) + ((((k & 15) >> 2) << 4) + (t & 15)) * 4 + (k & 3)];
+}
+template <>
+__device__ __forceinline__ double w_elem<unsigned short>(const unsigned short *Wh, const unsigned short *Wl, int t, int k,
+                                                         int nb)
+{
+    const int64_t o = ((int64_t)((t >> 4) * (nb >> 1) + (k >> 5)) << 9) + ((((k & 31) >> 3) << 4) + (t & 15)) * 8 + (k & 7);
+    return (double)bf2f(Wh[o]) + (double)bf2f(Wl[o]);
+}
+
+// Correction of a delayed downdate: with the W of an earlier pick held back (P), the block
+// column of the new pick s is W_i = (R_is - P_i P_s^T) L_s^-T = R_is L_s^-T - P_i V^T with
+// V = L_s^-1 P_s.  One wave per 16 x 16 sub-block of V: V^T = P_s^T L_s^-T accumulated on FP64
+// MFMA lands in the accumulator order, which is V's operand order (the order of L_s^-1).
+template <typename TW>
+__device__ void vcorr_body(const StepDesc &d, int item)
+{
+    if (d.state[ST_STATUS] != 0) return;
+    const int nb = d.N_tp >> 4;
+    if (item >= nb * nb) return;
+    const int kb = item / nb, ab = item % nb;  // V^T sub-block (kb, ab) = V sub-block (ab, kb)
+    const int lane = threadIdx.x & 63, g = lane >> 4, al = a_lane<double>(lane) & 15;
+    const int s = d.state[ST_LAST];
+    const int64_t bs = (int64_t)d.N_tp * d.N_tp;
+    const TW *Ps = (const TW *)d.P + s * bs;
+    const TW *Ps2 = d.P2 ? (const TW *)d.P2 + s * bs : nullptr;
+    const int nbr = (d.N_t + 15) >> 4;  // rows of P_s past N_t are zero
+    doublex4 acc{0.0, 0.0, 0.0, 0.0};
+    for (int mq = 0; mq < nbr; ++mq) {
+        const doublex4 b = ld4(d.Linv + ((ab * nb + mq) << 8) + lane * 4);
+#pragma unroll
+        for (int s4 = 0; s4 < 4; ++s4)
+            acc = mfma16(w_elem<TW>(Ps, Ps2, 16 * mq + 4 * g + s4, 16 * kb + al, nb), b[s4], acc);
+    }
+    st4(d.V + ((ab * nb + kb) << 8) + lane * 4, acc);
+}
+
 template <typename TR, typename TW>
 __device__ void trsm_body(const StepDesc &d, int p)
 {
@@ -80,6 +143,27 @@ __device__ void trsm_body(const StepDesc &d, int p)
                         const doublex4 a = ld4(Linv + ((kc * nb + q) << 8) + alane * 4);
 #pragma unroll
                         for (int s4 = 0; s4 < 4; ++s4) acc[c] = mfma16(a[s4], b[s4], acc[c]);
+                    }
+                }
+            }
+            if (d.P) {
+                // - P_i V^T: inner index over the held pick's block, V in L_s^-1's order
+                const TW *Pi = (const TW *)d.P + (int64_t)i * bs;
+                const TW *Pi2 = d.P2 ? (const TW *)d.P2 + (int64_t)i * bs : nullptr;
+                const int nbr = (d.N_t + 15) >> 4;
+                for (int q = 0; q < nbr; ++q) {
+                    double b[4];
+                    w_row4<TW>(Pi, Pi2, tb, q, nb, lane, b);
+#pragma unroll
+                    for (int s4 = 0; s4 < 4; ++s4) b[s4] = -b[s4];
+#pragma unroll
+                    for (int c = 0; c < 8; ++c) {
+                        const int kc = kg + c;
+                        if (kc < kend) {
+                            const doublex4 a = ld4(d.V + ((kc * nb + q) << 8) + alane * 4);
+#pragma unroll
+                            for (int s4 = 0; s4 < 4; ++s4) acc[c] = mfma16(a[s4], b[s4], acc[c]);
+                        }
                     }
                 }
             }
@@ -227,26 +311,27 @@ __device__ __forceinline__ void tile_map(const StepDesc &d, int64_t P, int64_t Q
 // and is subtracted from R at the end.  FP32: the R tile is loaded into registers a few
 // blocks per slice, behind the next slice's W loads, so it streams in during the MFMAs.
 // FP64 (no registers for the tile) reads R in the epilogue.
-template <typename T, int NB>
+template <typename T, int NB, int NW>
 __device__ void syrk_lds_body(const StepDesc &d, int64_t tile)
 {
     typedef typename V4<T>::type vec;
     constexpr int N_tp = 16 * NB;
+    constexpr int NS = NB * NW;                  // 16-wide inner slices: W's, then the held P's
     constexpr bool PREFETCH_R = sizeof(T) == 4;
-    constexpr int PER = (16 + NB - 1) / NB;  // R blocks fetched per slice
-    __shared__ vec lds[2][2][8 * 64];        // [buffer][A/B][sub-block * 64 + lane]
+    constexpr int PER = (16 + NS - 1) / NS;      // R blocks fetched per slice
+    __shared__ vec lds[2][2][8 * 64];            // [buffer][A/B][sub-block * 64 + lane]
     if (d.state[ST_STATUS] != 0) return;
     int64_t P, Q;
     if (!super_tile(tile, syrk_tile_rows(d.n_act, d.N_tp), P, Q)) return;
     T *__restrict__ R = (T *)d.R;
-    const T *__restrict__ W = (const T *)d.W;
     const int tid = threadIdx.x, lane = tid & 63;
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6), wr = wave >> 1, wc = wave & 1;
     const int alane = a_lane<T>(lane);
     TileMap m;
     tile_map<N_tp>(d, P, Q, wave, m);
-    const T *Wl = W + lane * 4;  // this lane's element of a staged sub-block
-    T *Rl = R + lane * 4;         // this lane's element of an output block
+    const T *Wl = (const T *)d.W + lane * 4;                     // this lane's element of a staged sub-block
+    const T *Pl = NW > 1 ? (const T *)d.P + lane * 4 : Wl;       // same for the held W
+    T *Rl = R + lane * 4;                                        // this lane's element of an output block
 
     vec rt[16], acc[16];
 #pragma unroll
@@ -268,13 +353,15 @@ __device__ void syrk_lds_body(const StepDesc &d, int64_t tile)
     }
     __syncthreads();
 #pragma unroll
-    for (int q = 0; q < NB; ++q) {
+    for (int q = 0; q < NS; ++q) {
         const int buf = q & 1;
-        if (q + 1 < NB) {
+        if (q + 1 < NS) {
+            const T *src = (q + 1) < NB ? Wl : Pl;
+            const int o = ((q + 1) % NB) << 8;
 #pragma unroll
             for (int h = 0; h < 2; ++h) {
-                sa[h] = ld4(Wl + m.wA[h] + ((q + 1) << 8));
-                sbv[h] = ld4(Wl + m.wB[h] + ((q + 1) << 8));
+                sa[h] = ld4(src + m.wA[h] + o);
+                sbv[h] = ld4(src + m.wB[h] + o);
             }
             if (PREFETCH_R) {
 #pragma unroll
@@ -295,7 +382,7 @@ __device__ void syrk_lds_body(const StepDesc &d, int64_t tile)
 #pragma unroll
                     for (int c = 0; c < 4; ++c) acc[4 * b + c] = mfma16(a[b][s4], w[c][s4], acc[4 * b + c]);
         }
-        if (q + 1 < NB) {
+        if (q + 1 < NS) {
 #pragma unroll
             for (int h = 0; h < 2; ++h) {
                 lds[buf ^ 1][0][(wave + 4 * h) * 64 + lane] = sa[h];
@@ -307,7 +394,7 @@ __device__ void syrk_lds_body(const StepDesc &d, int64_t tile)
     if (!m.any) return;
     if (PREFETCH_R) {
 #pragma unroll
-        for (int f = NB * PER; f < 16; ++f) rt[f] = ld4(Rl + m.rblk[f]);
+        for (int f = NS * PER; f < 16; ++f) rt[f] = ld4(Rl + m.rblk[f]);
     }
 #pragma unroll
     for (int f = 0; f < 16; ++f)
@@ -319,23 +406,24 @@ __device__ void syrk_lds_body(const StepDesc &d, int64_t tile)
 // hi_I lo_J^T + lo_I hi_J^T on the 16x16x32 BF16 MFMA with FP32 accumulation.  Per 32-wide
 // inner slice the work-group stages the hi and lo parts of both W panels in LDS (double
 // buffered); otherwise as syrk_lds_body.
-template <int NB32>
+template <int NB32, int NW>
 __device__ void syrk_bf16_body(const StepDesc &d, int64_t tile)
 {
     constexpr int N_tp = 32 * NB32;
-    constexpr int PER = (16 + NB32 - 1) / NB32;  // R blocks fetched per slice
-    __shared__ u32x4 lds[2][4][8 * 64];          // [buffer][A hi, A lo, B hi, B lo][sub-block * 64 + lane]
+    constexpr int NS = NB32 * NW;                 // 32-wide inner slices: W's, then the held P's
+    constexpr int PER = (16 + NS - 1) / NS;       // R blocks fetched per slice
+    __shared__ u32x4 lds[2][4][8 * 64];           // [buffer][A hi, A lo, B hi, B lo][sub-block * 64 + lane]
     if (d.state[ST_STATUS] != 0) return;
     int64_t P, Q;
     if (!super_tile(tile, syrk_tile_rows(d.n_act, d.N_tp), P, Q)) return;
     float *__restrict__ R = (float *)d.R;
-    const unsigned short *__restrict__ Wh = (const unsigned short *)d.W;
-    const unsigned short *__restrict__ Wl = (const unsigned short *)d.W2;
     const int tid = threadIdx.x, lane = tid & 63;
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6), wr = wave >> 1, wc = wave & 1;
     TileMap m;
     tile_map<N_tp>(d, P, Q, wave, m);  // W offsets in BF16 elements: a 16 x 32 tile is 512
-    const unsigned short *Whl = Wh + lane * 8, *Wll = Wl + lane * 8;
+    const unsigned short *Whl = (const unsigned short *)d.W + lane * 8, *Wll = (const unsigned short *)d.W2 + lane * 8;
+    const unsigned short *Phl = NW > 1 ? (const unsigned short *)d.P + lane * 8 : Whl;
+    const unsigned short *Pll = NW > 1 ? (const unsigned short *)d.P2 + lane * 8 : Wll;
     float *Rl = R + lane * 4;
 
     floatx4 rt[16], acc[16];
@@ -357,16 +445,17 @@ __device__ void syrk_bf16_body(const StepDesc &d, int64_t tile)
         for (int k = 0; k < 4; ++k) lds[0][k][(wave + 4 * h) * 64 + lane] = st[h][k];
     __syncthreads();
 #pragma unroll
-    for (int q = 0; q < NB32; ++q) {
+    for (int q = 0; q < NS; ++q) {
         const int buf = q & 1;
-        if (q + 1 < NB32) {
-            const int64_t o = (int64_t)(q + 1) << 9;
+        if (q + 1 < NS) {
+            const unsigned short *hi = (q + 1) < NB32 ? Whl : Phl, *lo = (q + 1) < NB32 ? Wll : Pll;
+            const int64_t o = (int64_t)((q + 1) % NB32) << 9;
 #pragma unroll
             for (int h = 0; h < 2; ++h) {
-                st[h][0] = *reinterpret_cast<const u32x4 *>(Whl + m.wA[h] + o);
-                st[h][1] = *reinterpret_cast<const u32x4 *>(Wll + m.wA[h] + o);
-                st[h][2] = *reinterpret_cast<const u32x4 *>(Whl + m.wB[h] + o);
-                st[h][3] = *reinterpret_cast<const u32x4 *>(Wll + m.wB[h] + o);
+                st[h][0] = *reinterpret_cast<const u32x4 *>(hi + m.wA[h] + o);
+                st[h][1] = *reinterpret_cast<const u32x4 *>(lo + m.wA[h] + o);
+                st[h][2] = *reinterpret_cast<const u32x4 *>(hi + m.wB[h] + o);
+                st[h][3] = *reinterpret_cast<const u32x4 *>(lo + m.wB[h] + o);
             }
 #pragma unroll
             for (int f = (q + 1) * PER; f < (q + 2) * PER && f < 16; ++f) rt[f] = ld4(Rl + m.rblk[f]);
@@ -390,7 +479,7 @@ __device__ void syrk_bf16_body(const StepDesc &d, int64_t tile)
                 }
             }
         }
-        if (q + 1 < NB32) {
+        if (q + 1 < NS) {
 #pragma unroll
             for (int h = 0; h < 2; ++h)
 #pragma unroll
@@ -400,7 +489,7 @@ __device__ void syrk_bf16_body(const StepDesc &d, int64_t tile)
     }
     if (!m.any) return;
 #pragma unroll
-    for (int f = NB32 * PER; f < 16; ++f) rt[f] = ld4(Rl + m.rblk[f]);
+    for (int f = NS * PER; f < 16; ++f) rt[f] = ld4(Rl + m.rblk[f]);
 #pragma unroll
     for (int f = 0; f < 16; ++f)
         if (m.ok[f]) st4(Rl + m.rblk[f], rt[f] - acc[f]);
@@ -444,15 +533,15 @@ __global__ void __launch_bounds__(256) syrk_direct_batched(const StepDesc *__res
     syrk_direct_body<T>(d, item - d.item0);
 }
 
-template <typename T, int NB>
+template <typename T, int NB, int NW>
 __global__ void __launch_bounds__(256, 2) syrk_lds_kernel(StepDesc d, int64_t per_xcd)
 {
     const int64_t tile = xcd_item(blockIdx.x, per_xcd);
     if (tile >= d.nitems) return;
-    syrk_lds_body<T, NB>(d, tile);
+    syrk_lds_body<T, NB, NW>(d, tile);
 }
 
-template <typename T, int NB>
+template <typename T, int NB, int NW>
 __global__ void __launch_bounds__(256, 2) syrk_lds_batched(const StepDesc *__restrict__ ds, int n, int64_t total,
                                                            int64_t per_xcd)
 {
@@ -461,18 +550,18 @@ __global__ void __launch_bounds__(256, 2) syrk_lds_batched(const StepDesc *__res
     const int i = find_instance(ds, n, item);
     if (i < 0) return;
     const StepDesc d = ds[i];
-    syrk_lds_body<T, NB>(d, item - d.item0);
+    syrk_lds_body<T, NB, NW>(d, item - d.item0);
 }
 
-template <int NB32>
+template <int NB32, int NW>
 __global__ void __launch_bounds__(256, 2) syrk_bf16_kernel(StepDesc d, int64_t per_xcd)
 {
     const int64_t tile = xcd_item(blockIdx.x, per_xcd);
     if (tile >= d.nitems) return;
-    syrk_bf16_body<NB32>(d, tile);
+    syrk_bf16_body<NB32, NW>(d, tile);
 }
 
-template <int NB32>
+template <int NB32, int NW>
 __global__ void __launch_bounds__(256, 2) syrk_bf16_batched(const StepDesc *__restrict__ ds, int n, int64_t total,
                                                             int64_t per_xcd)
 {
@@ -481,7 +570,22 @@ __global__ void __launch_bounds__(256, 2) syrk_bf16_batched(const StepDesc *__re
     const int i = find_instance(ds, n, item);
     if (i < 0) return;
     const StepDesc d = ds[i];
-    syrk_bf16_body<NB32>(d, item - d.item0);
+    syrk_bf16_body<NB32, NW>(d, item - d.item0);
+}
+
+template <typename TW>
+__global__ void __launch_bounds__(64) vcorr_kernel(StepDesc d)
+{
+    vcorr_body<TW>(d, blockIdx.x);
+}
+
+template <typename TW>
+__global__ void __launch_bounds__(64) vcorr_batched(const StepDesc *__restrict__ ds, int n)
+{
+    const int i = find_instance(ds, n, blockIdx.x);
+    if (i < 0) return;
+    const StepDesc d = ds[i];
+    vcorr_body<TW>(d, (int)(blockIdx.x - d.item0));
 }
 
 // ---------------------------------------------------------------------------------------------
@@ -516,83 +620,139 @@ hipError_t launch_trsm_batched(const StepDesc *descs, int n, int64_t total, int 
     return hipErrorInvalidValue;
 }
 
-// Single (descs == nullptr: d by value) or batched downdate launch over `total` tiles.
-template <typename T>
-static hipError_t launch_syrk_t(const StepDesc *descs, const StepDesc &d, int n, int64_t total, int N_tp,
-                                int variant, hipStream_t s)
+template <typename TW>
+static hipError_t launch_vcorr_t(const StepDesc *descs, const StepDesc &d, int n, int64_t total, hipStream_t s)
 {
-    if (N_tp < 16 || N_tp % 16 != 0) return hipErrorInvalidValue;
+    if (descs)
+        hipLaunchKernelGGL((vcorr_batched<TW>), dim3((unsigned)total), dim3(64), 0, s, descs, n);
+    else
+        hipLaunchKernelGGL((vcorr_kernel<TW>), dim3((unsigned)total), dim3(64), 0, s, d);
+    return hipGetLastError();
+}
+
+// One work-group per 16 x 16 sub-block of V (single: d.nitems ignored, (N_tp / 16)^2 groups).
+hipError_t launch_vcorr(const StepDesc &d, int wtype, hipStream_t s)
+{
+    if (!d.P || !d.V) return hipErrorInvalidValue;
+    const int64_t total = (int64_t)(d.N_tp / 16) * (d.N_tp / 16);
+    if (wtype == W_F64) return launch_vcorr_t<double>(nullptr, d, 1, total, s);
+    if (wtype == W_F32) return launch_vcorr_t<float>(nullptr, d, 1, total, s);
+    if (wtype == W_BF16X3) return launch_vcorr_t<unsigned short>(nullptr, d, 1, total, s);
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_vcorr_batched(const StepDesc *descs, int n, int64_t total, int wtype, hipStream_t s)
+{
+    if (n <= 0 || total <= 0) return hipSuccess;
+    StepDesc none{};
+    if (wtype == W_F64) return launch_vcorr_t<double>(descs, none, n, total, s);
+    if (wtype == W_F32) return launch_vcorr_t<float>(descs, none, n, total, s);
+    if (wtype == W_BF16X3) return launch_vcorr_t<unsigned short>(descs, none, n, total, s);
+    return hipErrorInvalidValue;
+}
+
+// Single (descs == nullptr: d by value) or batched downdate launch over `total` tiles.
+// nw = 2 (a held W applied with the new one) needs the LDS variant.
+template <typename T, int NW>
+static hipError_t launch_syrk_lds(const StepDesc *descs, const StepDesc &d, int n, int64_t total, int nb,
+                                  hipStream_t s)
+{
     const int64_t per_xcd = (total + 7) / 8;
     const dim3 grid((unsigned)(per_xcd * 8)), block(256);
-    const int nb = N_tp / 16;
-    if (variant == SYRK_LDS && nb <= 8) {
-        switch (nb) {
+    switch (nb) {
 #define OED_SYRK_CASE(NBV)                                                                                    \
     case NBV:                                                                                                 \
         if (descs)                                                                                            \
-            hipLaunchKernelGGL((syrk_lds_batched<T, NBV>), grid, block, 0, s, descs, n, total, per_xcd);      \
+            hipLaunchKernelGGL((syrk_lds_batched<T, NBV, NW>), grid, block, 0, s, descs, n, total, per_xcd);  \
         else                                                                                                  \
-            hipLaunchKernelGGL((syrk_lds_kernel<T, NBV>), grid, block, 0, s, d, per_xcd);                     \
+            hipLaunchKernelGGL((syrk_lds_kernel<T, NBV, NW>), grid, block, 0, s, d, per_xcd);                 \
         break;
-            OED_SYRK_CASE(1)
-            OED_SYRK_CASE(2)
-            OED_SYRK_CASE(3)
-            OED_SYRK_CASE(4)
-            OED_SYRK_CASE(5)
-            OED_SYRK_CASE(6)
-            OED_SYRK_CASE(7)
-            OED_SYRK_CASE(8)
+        OED_SYRK_CASE(1)
+        OED_SYRK_CASE(2)
+        OED_SYRK_CASE(3)
+        OED_SYRK_CASE(4)
+        OED_SYRK_CASE(5)
+        OED_SYRK_CASE(6)
+        OED_SYRK_CASE(7)
+        OED_SYRK_CASE(8)
 #undef OED_SYRK_CASE
-        }
-    } else if (descs) {
-        hipLaunchKernelGGL(syrk_direct_batched<T>, grid, block, 0, s, descs, n, total, per_xcd);
-    } else {
-        hipLaunchKernelGGL(syrk_direct_kernel<T>, grid, block, 0, s, d, per_xcd);
+    default:
+        return hipErrorInvalidValue;
     }
     return hipGetLastError();
 }
 
-// BF16 split-product downdate (single or batched).
-static hipError_t launch_syrk_bf16(const StepDesc *descs, const StepDesc &d, int n, int64_t total, int N_tp,
-                                   hipStream_t s)
+template <typename T>
+static hipError_t launch_syrk_t(const StepDesc *descs, const StepDesc &d, int n, int64_t total, int N_tp, int nw,
+                                int variant, hipStream_t s)
 {
-    if (N_tp < 32 || N_tp % 32 != 0 || N_tp > 128) return hipErrorInvalidValue;
+    if (N_tp < 16 || N_tp % 16 != 0 || nw < 1 || nw > 2) return hipErrorInvalidValue;
+    const int nb = N_tp / 16;
+    if (variant == SYRK_LDS && nb <= 8)
+        return nw == 2 ? launch_syrk_lds<T, 2>(descs, d, n, total, nb, s) : launch_syrk_lds<T, 1>(descs, d, n, total, nb, s);
+    if (nw != 1) return hipErrorInvalidValue;
+    const int64_t per_xcd = (total + 7) / 8;
+    const dim3 grid((unsigned)(per_xcd * 8)), block(256);
+    if (descs)
+        hipLaunchKernelGGL(syrk_direct_batched<T>, grid, block, 0, s, descs, n, total, per_xcd);
+    else
+        hipLaunchKernelGGL(syrk_direct_kernel<T>, grid, block, 0, s, d, per_xcd);
+    return hipGetLastError();
+}
+
+// BF16 split-product downdate (single or batched).
+template <int NW>
+static hipError_t launch_syrk_bf16_t(const StepDesc *descs, const StepDesc &d, int n, int64_t total, int N_tp,
+                                     hipStream_t s)
+{
     const int64_t per_xcd = (total + 7) / 8;
     const dim3 grid((unsigned)(per_xcd * 8)), block(256);
     switch (N_tp / 32) {
 #define OED_BF16_CASE(V)                                                                                     \
     case V:                                                                                                  \
         if (descs)                                                                                           \
-            hipLaunchKernelGGL((syrk_bf16_batched<V>), grid, block, 0, s, descs, n, total, per_xcd);         \
+            hipLaunchKernelGGL((syrk_bf16_batched<V, NW>), grid, block, 0, s, descs, n, total, per_xcd);     \
         else                                                                                                 \
-            hipLaunchKernelGGL((syrk_bf16_kernel<V>), grid, block, 0, s, d, per_xcd);                        \
+            hipLaunchKernelGGL((syrk_bf16_kernel<V, NW>), grid, block, 0, s, d, per_xcd);                    \
         break;
         OED_BF16_CASE(1)
         OED_BF16_CASE(2)
         OED_BF16_CASE(3)
         OED_BF16_CASE(4)
 #undef OED_BF16_CASE
+    default:
+        return hipErrorInvalidValue;
     }
     return hipGetLastError();
 }
 
-hipError_t launch_syrk(const StepDesc &d, int rtype, int wtype, int variant, hipStream_t s)
+static hipError_t launch_syrk_bf16(const StepDesc *descs, const StepDesc &d, int n, int64_t total, int N_tp, int nw,
+                                   hipStream_t s)
 {
-    if (rtype == R_F32 && wtype == W_BF16X3) return d.n_act <= 0 ? hipSuccess : launch_syrk_bf16(nullptr, d, 1, d.nitems, d.N_tp, s);
-    if (d.n_act <= 0 || d.nitems <= 0) return hipSuccess;
-    if (rtype == R_F64 && wtype == W_F64) return launch_syrk_t<double>(nullptr, d, 1, d.nitems, d.N_tp, variant, s);
-    if (rtype == R_F32 && wtype == W_F32) return launch_syrk_t<float>(nullptr, d, 1, d.nitems, d.N_tp, variant, s);
+    if (N_tp < 32 || N_tp % 32 != 0 || N_tp > 128) return hipErrorInvalidValue;
+    if (nw == 1) return launch_syrk_bf16_t<1>(descs, d, n, total, N_tp, s);
+    if (nw == 2) return launch_syrk_bf16_t<2>(descs, d, n, total, N_tp, s);
     return hipErrorInvalidValue;
 }
 
-hipError_t launch_syrk_batched(const StepDesc *descs, int n, int64_t total, int N_tp, int rtype, int wtype,
+hipError_t launch_syrk(const StepDesc &d, int rtype, int wtype, int variant, hipStream_t s)
+{
+    if (d.n_act <= 0 || d.nitems <= 0) return hipSuccess;
+    if (d.nw == 2 && !d.P) return hipErrorInvalidValue;
+    if (rtype == R_F32 && wtype == W_BF16X3) return launch_syrk_bf16(nullptr, d, 1, d.nitems, d.N_tp, d.nw, s);
+    if (rtype == R_F64 && wtype == W_F64) return launch_syrk_t<double>(nullptr, d, 1, d.nitems, d.N_tp, d.nw, variant, s);
+    if (rtype == R_F32 && wtype == W_F32) return launch_syrk_t<float>(nullptr, d, 1, d.nitems, d.N_tp, d.nw, variant, s);
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_syrk_batched(const StepDesc *descs, int n, int64_t total, int N_tp, int nw, int rtype, int wtype,
                                int variant, hipStream_t s)
 {
     if (n <= 0 || total <= 0) return hipSuccess;
     StepDesc none{};
-    if (rtype == R_F32 && wtype == W_BF16X3) return launch_syrk_bf16(descs, none, n, total, N_tp, s);
-    if (rtype == R_F64 && wtype == W_F64) return launch_syrk_t<double>(descs, none, n, total, N_tp, variant, s);
-    if (rtype == R_F32 && wtype == W_F32) return launch_syrk_t<float>(descs, none, n, total, N_tp, variant, s);
+    if (rtype == R_F32 && wtype == W_BF16X3) return launch_syrk_bf16(descs, none, n, total, N_tp, nw, s);
+    if (rtype == R_F64 && wtype == W_F64) return launch_syrk_t<double>(descs, none, n, total, N_tp, nw, variant, s);
+    if (rtype == R_F32 && wtype == W_F32) return launch_syrk_t<float>(descs, none, n, total, N_tp, nw, variant, s);
     return hipErrorInvalidValue;
 }
 

@@ -26,7 +26,7 @@ KERNELS = ("gain", "pick", "trsm", "syrk", "pack")
 class oed_options(ctypes.Structure):
     _fields_ = [("struct_size", ctypes.c_uint32), ("precision", ctypes.c_int32), ("flags", ctypes.c_uint32),
                 ("candidates", ctypes.POINTER(ctypes.c_int32)), ("n_candidates", ctypes.c_int32),
-                ("reserved", ctypes.c_int32 * 7)]
+                ("delay", ctypes.c_int32), ("reserved", ctypes.c_int32 * 6)]
 
 
 class oed_profile(ctypes.Structure):
@@ -41,6 +41,7 @@ class oed_instance(ctypes.Structure):
 
 
 OED_BATCH_NO_GRAPH = 2
+OED_BATCH_DELAY1 = 4
 
 
 class OedError(RuntimeError):
@@ -128,8 +129,9 @@ def _stream_handle(stream):
 
 
 # ------------------------------------------------------------------ functions with the C names
-def oed_create(K, N_s, N_t, sigma2, precision="fp64", candidates=None, profile=False, stream=None):
-    """Create a handle for the device tensor K (2-D, float64/float32, row-major, lower triangle read)."""
+def oed_create(K, N_s, N_t, sigma2, precision="fp64", candidates=None, profile=False, stream=None, delay=0):
+    """Create a handle for the device tensor K (2-D, float64/float32, row-major, lower triangle read).
+    delay: downdate delay depth (0 automatic, 1, 2)."""
     import torch
     L = library()
     if not isinstance(K, torch.Tensor) or not K.is_cuda or K.dim() != 2 or K.stride(1) != 1:
@@ -143,6 +145,7 @@ def oed_create(K, N_s, N_t, sigma2, precision="fp64", candidates=None, profile=F
     L.oed_options_init(ctypes.byref(opt))
     opt.precision = PRECISIONS[precision]
     opt.flags = OED_FLAG_PROFILE if profile else 0
+    opt.delay = int(delay)
     cand = None
     if candidates is not None:
         cand = np.ascontiguousarray(np.asarray(list(candidates), dtype=np.int32))
@@ -236,10 +239,11 @@ def _bcheck(b, st):
         raise OedError(st, msg)
 
 
-def oed_batch_create(items, precision="fp64", profile=False, graph=True, stream=None):
+def oed_batch_create(items, precision="fp64", profile=False, graph=True, stream=None, delay=2):
     arr = _instances(items)
     b = ctypes.c_void_p()
-    flags = (OED_FLAG_PROFILE if profile else 0) | (0 if graph else OED_BATCH_NO_GRAPH)
+    flags = ((OED_FLAG_PROFILE if profile else 0) | (0 if graph else OED_BATCH_NO_GRAPH) |
+             (OED_BATCH_DELAY1 if delay == 1 else 0))
     st = library().oed_batch_create(ctypes.byref(b), arr, len(items), PRECISIONS[precision], _stream_handle(stream),
                                     flags)
     _bcheck(None, st)
@@ -280,9 +284,9 @@ def oed_batch_destroy(b):
 class BatchSelector:
     """Owns one batch.  ``BatchSelector([(K, N_s, N_t, sigma2, B), ...]).run()`` -> [(idx, gain, status)]."""
 
-    def __init__(self, items, precision="fp64", profile=False, graph=True, stream=None):
+    def __init__(self, items, precision="fp64", profile=False, graph=True, stream=None, delay=2):
         self.budgets = [int(it[4]) for it in items]
-        self.b = oed_batch_create(items, precision, profile, graph, stream)
+        self.b = oed_batch_create(items, precision, profile, graph, stream, delay)
 
     def run(self, check=True):
         return oed_batch_run(self.b, self.budgets, check)[0]
@@ -315,9 +319,10 @@ class BatchSelector:
 class Selector:
     """Owns one handle.  ``Selector(K, N_s, N_t, sigma2).greedy(B)`` -> (indices, gains)."""
 
-    def __init__(self, K, N_s, N_t, sigma2, precision="fp64", candidates=None, profile=False, stream=None):
+    def __init__(self, K, N_s, N_t, sigma2, precision="fp64", candidates=None, profile=False, stream=None,
+                 delay=0):
         self.N_s, self.N_t = int(N_s), int(N_t)
-        self.h = oed_create(K, N_s, N_t, sigma2, precision, candidates, profile, stream)
+        self.h = oed_create(K, N_s, N_t, sigma2, precision, candidates, profile, stream, delay)
 
     def greedy(self, budget):
         idx, gain, _ = oed_greedy(self.h, budget)

@@ -34,15 +34,16 @@ def items(insts, dtype=torch.float64):
     return [(Kd.to(dtype), N_s, N_t, s2, B) for (_, Kd, N_s, N_t, s2, B) in insts]
 
 
+@pytest.mark.parametrize("delay", [1, 2])
 @pytest.mark.parametrize("prec", ["fp64", "mixed_f32", "mixed_bf16x3"])
-def test_batch_equals_single_and_oracle(insts, prec):
+def test_batch_equals_single_and_oracle(insts, prec, delay):
     from paper_2604_08812_amd import BatchSelector, Selector
-    with BatchSelector(items(insts), precision=prec) as bs:
+    with BatchSelector(items(insts), precision=prec, delay=delay) as bs:
         res = bs.run()
     for q, (K, Kd, N_s, N_t, s2, B) in enumerate(insts):
         idx, gain, st = res[q]
         assert st == 0 and len(idx) == B
-        with Selector(Kd, N_s, N_t, s2, precision=prec) as sel:
+        with Selector(Kd, N_s, N_t, s2, precision=prec, delay=delay) as sel:
             i1, g1 = sel.greedy(B)
         assert list(idx) == list(i1), q
         np.testing.assert_array_equal(gain, g1)

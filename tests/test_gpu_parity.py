@@ -51,15 +51,18 @@ def supported(prec, N_t):
     return prec != "mixed_bf16x3" or N_t <= 128
 
 
+@pytest.mark.parametrize("delay", [1, 2])
 @pytest.mark.parametrize("prec", PRECS)
 @pytest.mark.parametrize("case", CASES, ids=lambda c: "x".join(map(str, c[:2])))
-def test_greedy_matches_oracle(case, prec):
+def test_greedy_matches_oracle(case, prec, delay):
     N_s, N_t, n_m, seed, B = case
     if not supported(prec, N_t):
         pytest.skip("N_t > 128 has no BF16 split-product downdate")
-    print(f"case N_s={N_s} N_t={N_t} seed={seed} B={B} prec={prec}", flush=True)
+    if delay == 2 and N_t > 128:
+        pytest.skip("the delayed downdate needs the register factorisations (N_t <= 128)")
+    print(f"case N_s={N_s} N_t={N_t} seed={seed} B={B} prec={prec} delay={delay}", flush=True)
     K, Kd, s2 = instance(N_s, N_t, n_m, seed)
-    with selector(Kd, N_s, N_t, s2, precision=prec) as sel:
+    with selector(Kd, N_s, N_t, s2, precision=prec, delay=delay) as sel:
         idx, gain = sel.greedy(B)
     rep = check_trajectory(K, N_s, N_t, s2, idx, gain, RTOL[prec])
     print(f"  max rel gain err {rep['max_rel_err']:.2e}, near-tie divergences {rep['diverged_steps']}")
@@ -67,11 +70,14 @@ def test_greedy_matches_oracle(case, prec):
         assert rep["diverged_steps"] == [] or min(rep["ref"]["gap"]) < 1e-9
 
 
+@pytest.mark.parametrize("prefix", [[7, 0, 28, 13], [7, 0, 28]], ids=["even", "odd"])
 @pytest.mark.parametrize("prec", PRECS)
-def test_scores_and_schur_blocks_after_forced_prefix(prec):
+def test_scores_and_schur_blocks_after_forced_prefix(prec, prefix):
+    # odd prefix with the delayed downdate: the scores are taken with a block column held
+    # (gain-kernel correction), the Schur blocks after applying it alone
     N_s, N_t = 29, 48
     K, Kd, s2 = instance(N_s, N_t, 2000, 21)
-    A = [7, 0, 28, 13]
+    A = list(prefix)
     rest = [j for j in range(N_s) if j not in A]
     # W hi + lo in BF16 represents w to about 2^-17 relative (lo * lo is dropped)
     tol = {"fp64": 1e-11, "mixed_f32": 2e-5, "mixed_bf16x3": 5e-5}[prec]
@@ -88,6 +94,8 @@ def test_scores_and_schur_blocks_after_forced_prefix(prec):
         S = oracle.schur_complement(K, N_t, A, rest)
         scale = np.abs(S).max()
         for (i, j) in [(1, 1), (27, 3), (3, 27), (20, 19), (27, 27), (14, 12), (2, 1)]:
+            if i in A or j in A:
+                continue
             blk = sel.schur_block(i, j)
             pi, pj = rest.index(i), rest.index(j)
             ref_blk = S[pi * N_t:(pi + 1) * N_t, pj * N_t:(pj + 1) * N_t]
@@ -218,3 +226,19 @@ def test_errors_and_states():
         selector(Kd, N_s, N_t, -1.0)
     with pytest.raises(OedError):
         selector(Kd, N_s, N_t, s2, candidates=[1, 1, 2])
+
+
+@pytest.mark.parametrize("prec", PRECS)
+def test_delay_two_matches_delay_one(prec):
+    """Holding every other block column changes the rounding only: same picks, gains equal to
+    the precision's tolerance (FP64: 1e-12)."""
+    N_s, N_t = 48, 64
+    _, Kd, s2 = instance(N_s, N_t, 4000, 23)
+    with selector(Kd, N_s, N_t, s2, precision=prec, delay=1) as a, \
+            selector(Kd, N_s, N_t, s2, precision=prec, delay=2) as b:
+        i1, g1 = a.greedy(20)
+        i2a, g2a = b.greedy(7)      # odd split: the next call starts with a block column held
+        i2b, g2b = b.greedy(13)
+    assert list(i1) == list(np.r_[i2a, i2b])
+    tol = 1e-12 if prec == "fp64" else RTOL[prec]
+    assert np.all(rel_err(np.r_[g2a, g2b], g1) <= tol)
