@@ -48,6 +48,9 @@ def parse():
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-bf16x3", action="store_true")
     ap.add_argument("--no-gaps", action="store_true", help="skip the per-step top-two gap scan (FP64)")
+    ap.add_argument("--delay", type=int, default=0, help="downdate delay depth (0: the library's choice)")
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="with --delay 0, take the library's fixed default instead of its autotuner")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-budget", type=int, default=16, help="picks of the oracle sample")
     ap.add_argument("--cpu-sensors", type=int, default=100)
@@ -248,7 +251,9 @@ def run_batched(args):
     torch.cuda.synchronize()
     log(f"48 instances formed in {time.perf_counter() - t0:.1f} s")
     total_steps = sum(sp.budget for sp in specs)
-    bs = BatchSelector(items, precision="mixed_f32", profile=True)
+    tune = args.delay == 0 and not args.no_autotune
+    bs = BatchSelector(items, precision=args.precision or "mixed_f32", profile=True, delay=args.delay, autotune=tune)
+    delay, tuned = bs.config()
     for w in range(args.warmup):
         bs.reset(items)
         bs.run()
@@ -271,7 +276,9 @@ def run_batched(args):
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms, 3), "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
         "config": {"workload": "batched_48_uneven", "instances": len(specs), "total_picks": total_steps,
-                   "precision": "mixed_f32", "K_dtype": "f32", "step": "oed_batch_reset + oed_batch_run"},
+                   "precision": args.precision or "mixed_f32", "K_dtype": "f32", "delay": delay, "autotuned": tune,
+                   "autotuner_run_ms_by_delay": [round(float(x), 3) for x in tuned] if tune else None,
+                   "step": "oed_batch_reset + oed_batch_run"},
         "roofline": {"kernel": "whole batched run (graph)", "bound": "hbm", "achieved": round(gbs, 1),
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(gbs / HBM_PEAK_GBS, 4), "traffic": None,
                      "note": "algorithmic downdate bytes / whole-run time (gains, picks and W included in the time)",
@@ -312,7 +319,9 @@ def main():
     log(f"K formed in {time.perf_counter() - t0:.1f} s, sigma2={s2:.6e}")
 
     # ---- headline path
-    sel = Selector(K, spec.N_s, spec.N_t, s2, precision=prec, profile=True)
+    tune = args.delay == 0 and not args.no_autotune
+    sel = Selector(K, spec.N_s, spec.N_t, s2, precision=prec, profile=True, delay=args.delay, autotune=tune)
+    delay, variant, tuned = sel.config()
     for w in range(args.warmup):
         timed_selections(sel, K, budget, 1)
         log(f"warmup {w + 1}/{args.warmup} done")
@@ -334,7 +343,9 @@ def main():
         "dtype": "f32" if prec != "fp64" else "f64",
         "data": "synthetic",
         "config": {"workload": spec.name, "N_s": spec.N_s, "N_t": spec.N_t, "n_m": spec.n_m, "seed": spec.seed,
-                   "budget": budget, "precision": prec, "K_dtype": spec.k_dtype,
+                   "budget": budget, "precision": prec, "K_dtype": spec.k_dtype, "delay": delay,
+                   "downdate_variant": ["direct", "lds"][variant], "autotuned": tune,
+                   "autotuner_ms_per_pick_by_delay": [round(float(x), 4) for x in tuned] if tune else None,
                    "step": "oed_reset + oed_greedy(budget)"},
         "roofline": roofline_syrk(prof, prec, spec.name),
         "kernel_ms_per_step": {k: round(v / args.steps, 3) for k, v in prof["ms"].items()},
@@ -343,15 +354,17 @@ def main():
 
     # ---- FP64 beside it, same K
     if not args.no_fp64 and prec != "fp64":
-        sel64 = Selector(K, spec.N_s, spec.N_t, s2, precision="fp64", profile=True)
+        sel64 = Selector(K, spec.N_s, spec.N_t, s2, precision="fp64", profile=True, delay=args.delay, autotune=tune)
         sel64.profile(reset=True)
         ms64, (idx64, gain64) = timed_selections(sel64, K, budget, args.fp64_steps)
         p64 = sel64.profile(reset=True)
+        d64 = sel64.config()[0]
         if not args.no_gaps:
             gaps = top_two_gaps(sel64, K, budget)
         sel64.close()
         log(f"fp64: {ms64:.1f} ms per selection")
         result["fp64"] = {"value": round(budget / (ms64 * 1e-3), 3), "unit": "greedy steps/s",
+                          "delay": d64,
                           "ms_per_step": round(ms64, 3), "roofline": roofline_syrk(p64, "fp64", spec.name),
                           "kernel_ms_per_step": {k: round(v / args.fp64_steps, 3) for k, v in p64["ms"].items()}}
         result["mixed_vs_fp64"] = {"speedup": round(ms64 / ms, 3), **compare_picks(idx, gain, idx64, gain64)}
@@ -364,14 +377,16 @@ def main():
 
     # ---- the BF16 split-product downdate beside it, same K
     if not args.no_bf16x3 and prec == "mixed_f32" and spec.N_t <= 128 and not args.precision:
-        selb = Selector(K, spec.N_s, spec.N_t, s2, precision="mixed_bf16x3", profile=True)
+        selb = Selector(K, spec.N_s, spec.N_t, s2, precision="mixed_bf16x3", profile=True, delay=args.delay,
+                        autotune=tune)
         timed_selections(selb, K, budget, 1)
         selb.profile(reset=True)
         msb, (idxb, gainb) = timed_selections(selb, K, budget, args.steps)
         pb = selb.profile(reset=True)
+        db = selb.config()[0]
         selb.close()
         log(f"mixed_bf16x3: {msb:.1f} ms per selection")
-        result["mixed_bf16x3"] = {"value": round(budget / (msb * 1e-3), 3), "unit": "greedy steps/s",
+        result["mixed_bf16x3"] = {"value": round(budget / (msb * 1e-3), 3), "unit": "greedy steps/s", "delay": db,
                                   "ms_per_step": round(msb, 3), "roofline": roofline_syrk(pb, "mixed_bf16x3", spec.name),
                                   "kernel_ms_per_step": {k: round(v / args.steps, 3) for k, v in pb["ms"].items()},
                                   "speedup_vs_mixed_f32": round(ms / msb, 3),

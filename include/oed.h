@@ -82,6 +82,10 @@ typedef enum oed_precision {
 
 /* oed_options.flags */
 #define OED_FLAG_PROFILE 0x1u /* time every kernel with HIP events (see oed_get_profile) */
+#define OED_FLAG_AUTOTUNE 0x4u /* with delay 0: choose the delay depth and the downdate kernel by
+                                  timing one step's kernels on the packed working copy (see
+                                  oed_get_config); the choice is cached per device, precision,
+                                  block size and candidate count for the life of the process */
 
 typedef struct oed_options {
     uint32_t struct_size;       /* sizeof(oed_options); set by oed_options_init */
@@ -90,11 +94,13 @@ typedef struct oed_options {
     const int32_t *candidates;  /* host array of candidate sensors (the set C of Sec. III-A);
                                    NULL = all N_s sensors.  Copied during oed_create. */
     int32_t n_candidates;       /* length of candidates */
-    int32_t delay;              /* downdate delay depth: 1 = subtract every pick's W W^T at the
-                                   next step; 2 = hold one pick's W and subtract it together with
-                                   the next one (the gain and pick steps correct the held blocks
-                                   exactly; same picks, half the R traffic per pick); 0 = automatic
-                                   (2 for N_t <= 128, else 1).  2 with N_t > 128: OED_E_UNSUPPORTED */
+    int32_t delay;              /* downdate delay depth p, 1..4: hold up to p - 1 picks' block
+                                   columns W and subtract them together with the next one (the
+                                   gain, pick and block-column steps correct for the held ones
+                                   exactly; same picks, 1/p of the R traffic per pick).
+                                   1 = subtract every pick's W W^T at the next step; 0 = automatic
+                                   (2 for N_t <= 128, else 1).  p > 1 with N_t > 128:
+                                   OED_E_UNSUPPORTED */
     int32_t reserved[6];        /* must be 0 */
 } oed_options;
 
@@ -194,14 +200,17 @@ typedef struct oed_batch oed_batch;
 
 /* Don't capture the schedule into a HIP graph: enqueue the launches on every run. */
 #define OED_BATCH_NO_GRAPH 0x2u
-/* Downdate delay depth 1 (subtract every pick's W W^T at once) instead of the default 2 (see
-   oed_options.delay). */
-#define OED_BATCH_DELAY1 0x4u
+/* Downdate delay depth p in 1..4 (see oed_options.delay); without it the depth is 4. */
+#define OED_BATCH_DELAY(p) ((uint32_t)(p) << 8)
+/* Without OED_BATCH_DELAY: run the whole selection once per delay depth during creation and
+   keep the fastest (see oed_batch_get_config). */
+#define OED_BATCH_AUTOTUNE 0x10u
 
 /*
  * Create a batch over inst[0..n): validates every instance, allocates all device memory,
  * packs every working copy and builds the launch schedule.  flags: OED_FLAG_PROFILE (time
- * each run with HIP events), OED_BATCH_NO_GRAPH, OED_BATCH_DELAY1.  On failure *out is NULL.
+ * each run with HIP events), OED_BATCH_NO_GRAPH, OED_BATCH_DELAY(p), OED_BATCH_AUTOTUNE.  On failure
+ * *out is NULL.
  */
 OED_API oed_status oed_batch_create(oed_batch **out, const oed_instance *inst, int32_t n, int32_t precision,
                                     void *stream, uint32_t flags);
@@ -223,11 +232,22 @@ OED_API oed_status oed_batch_reset(oed_batch *b, const oed_instance *inst, int32
  * algorithmic downdate flops and bytes of one run (definitions as in oed_profile). */
 OED_API oed_status oed_batch_stats(const oed_batch *b, double *run_ms, double *syrk_flops, double *syrk_bytes);
 
+/* The delay depth the batch runs with, and with OED_BATCH_AUTOTUNE the autotuner's run time
+   for depths 1..4 (4 doubles, host; may be NULL). */
+OED_API oed_status oed_batch_get_config(const oed_batch *b, int32_t *delay, double *per_run_ms);
 OED_API oed_status oed_batch_destroy(oed_batch *b);
 OED_API const char *oed_batch_last_error(const oed_batch *b);
 
 /* Bytes of device memory the handle holds. */
 OED_API oed_status oed_device_bytes(const oed_ctx *h, int64_t *bytes);
+
+/*
+ * The configuration the handle runs with: *delay (1..4), *syrk_variant (0: per-wave global
+ * operands, 1: LDS-staged), and, if per_pick_ms is not NULL, the autotuner's estimate of the
+ * time per pick for delay depths 1..4 (4 doubles, host; 0 where not measured, all 0 without
+ * OED_FLAG_AUTOTUNE).  Any output pointer may be NULL.
+ */
+OED_API oed_status oed_get_config(const oed_ctx *h, int32_t *delay, int32_t *syrk_variant, double *per_pick_ms);
 
 /* Destroy the handle and free its device memory.  NULL is accepted. */
 OED_API oed_status oed_destroy(oed_ctx *h);

@@ -8,6 +8,7 @@ from .oed import (  # noqa: F401
     BatchSelector,
     oed_batch_create,
     oed_batch_destroy,
+    oed_batch_get_config,
     oed_batch_reset,
     oed_batch_run,
     oed_batch_stats,
@@ -20,6 +21,7 @@ from .oed import (  # noqa: F401
     oed_destroy,
     oed_device_bytes,
     oed_force,
+    oed_get_config,
     oed_get_profile,
     oed_greedy,
     oed_picks,

@@ -10,7 +10,10 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <map>
+#include <mutex>
 #include <string>
+#include <tuple>
 #include <vector>
 
 #include "../../include/oed.h"
@@ -37,14 +40,16 @@ struct oed_ctx {
     int prec = OED_PREC_FP64;
     int rtype = R_F64, wtype = W_F64;
     int syrk_variant = SYRK_LDS;
-    int delay = 1;  // 2: a pick's block column may be held and applied with the next one
+    int delay = 1;  // > 1: up to delay - 1 block columns held and subtracted with the next one
+    double tuned_ms[MAX_DELAY] = {0};  // autotuner: estimated time per pick for delay 1..MAX_DELAY
     uint32_t flags = 0;
     hipStream_t stream = nullptr;
     int device = 0;
     std::vector<int> cmap;  // local -> original sensor index (ascending)
     std::vector<int> lmap;  // original -> local (-1 = not a candidate)
     // device memory
-    void *R = nullptr, *Wb[2] = {nullptr, nullptr}, *W2b[2] = {nullptr, nullptr};  // W slots (BF16: hi, lo)
+    void *R = nullptr, *W = nullptr, *W2 = nullptr;  // `delay` W slots (BF16: hi, lo parts)
+    int64_t wslot = 0;                               // elements per W slot
     double *V = nullptr;
     double *Linv = nullptr, *gains = nullptr, *pick_gain = nullptr, *scratch_gain = nullptr,
            *scratch_pick = nullptr;
@@ -55,7 +60,7 @@ struct oed_ctx {
     int n_act = 0;     // remaining candidates
     int k = 0;         // picks made
     bool pending = false;  // the last pick's block column and downdate are not formed yet
-    int held = -1;         // W slot formed but not yet subtracted from R (delay 2), or -1
+    int nheld = 0;         // block columns formed but not yet subtracted from R (W slots 0 .. nheld-1)
     bool poisoned = false;
     std::vector<int> h_picks;   // local indices
     std::vector<double> h_gains;
@@ -135,7 +140,7 @@ void collect_profile(oed_ctx *h)
 
 void free_all(oed_ctx *h)
 {
-    void *ptrs[] = {h->R, h->Wb[0], h->Wb[1], h->W2b[0], h->W2b[1], h->V, h->Linv, h->gains, h->pick_gain, h->scratch_gain, h->scratch_pick,
+    void *ptrs[] = {h->R, h->W, h->W2, h->V, h->Linv, h->gains, h->pick_gain, h->scratch_gain, h->scratch_pick,
                     h->act[0], h->act[1], h->picks, h->state, h->dcmap};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
@@ -157,7 +162,7 @@ oed_status load_R(oed_ctx *h, const void *K)
     h->n_act = h->N_c;
     h->k = 0;
     h->pending = false;
-    h->held = -1;
+    h->nheld = 0;
     h->poisoned = false;
     h->h_picks.clear();
     h->h_gains.clear();
@@ -170,14 +175,10 @@ StepDesc desc(const oed_ctx *h)
 {
     StepDesc d{};
     d.R = h->R;
-    // the slot the next block column goes to, and the held one
-    const int ws = h->held >= 0 ? h->held ^ 1 : 0;
-    d.W = h->Wb[ws];
-    d.W2 = h->W2b[ws];
-    if (h->held >= 0) {
-        d.P = h->Wb[h->held];
-        d.P2 = h->W2b[h->held];
-    }
+    d.W = h->W;
+    d.W2 = h->W2;
+    d.wslot = h->wslot;
+    d.nheld = h->nheld;
     d.V = h->V;
     d.nw = 1;
     d.act_in = h->act[h->cur];
@@ -212,40 +213,162 @@ oed_status enqueue_syrk(oed_ctx *h, StepDesc d)
 }
 
 // Form the block column W of the last pick (Sec. III-D: the new block row of the factor) and
-// subtract the outer products from R.  With delay 2 and `full` false, a W with no held
-// predecessor is held: the gain and pick kernels correct for it, and it is subtracted together
-// with the next pick's W (one downdate of inner dimension 2 N_t, half the R traffic per pick).
-// `full` leaves R current.
+// subtract the outer products from R.  With delay p > 1 and `full` false, block columns are
+// held (W slots 0 .. nheld-1; the gain and pick kernels correct for them exactly) until p of
+// them are formed, then subtracted in one downdate of inner dimension p N_t: 1/p of the R
+// traffic per pick.  `full` leaves R current.
 oed_status advance(oed_ctx *h, bool full)
 {
     if (h->pending) {
         h->pending = false;
         if (h->n_act == 0) {
-            h->held = -1;
+            h->nheld = 0;
             return OED_OK;
         }
         StepDesc d = desc(h);
         {
             Prof pr(h, OED_K_TRSM);
-            if (d.P) HIPCHK(h, launch_vcorr(d, h->wtype, h->stream));
+            if (h->nheld > 0) HIPCHK(h, launch_vcorr(d, h->wtype, h->stream));
             HIPCHK(h, launch_trsm(d, h->rtype, h->wtype, h->stream));
         }
-        const int ws = h->held >= 0 ? h->held ^ 1 : 0;
-        if (h->held >= 0 || full || h->delay == 1) {
-            d.nw = h->held >= 0 ? 2 : 1;
-            h->held = -1;
-            return enqueue_syrk(h, d);
+        if (h->nheld + 1 < h->delay && !full) {
+            ++h->nheld;
+            return OED_OK;
         }
-        h->held = ws;
-    } else if (full && h->held >= 0) {
+        d.nw = h->nheld + 1;
+        h->nheld = 0;
+        return enqueue_syrk(h, d);
+    }
+    if (full && h->nheld > 0) {
         StepDesc d = desc(h);
-        d.W = h->Wb[h->held];
-        d.W2 = h->W2b[h->held];
-        d.P = d.P2 = nullptr;
-        h->held = -1;
+        d.nw = h->nheld;
+        d.nheld = 0;
+        h->nheld = 0;
         return enqueue_syrk(h, d);
     }
     return OED_OK;
+}
+
+// ---- autotuner (OED_FLAG_AUTOTUNE with delay 0)
+//
+// On the freshly packed working copy it times, per delay depth p = 1..MAX_DELAY, the kernels of
+// one pick: the gains and the block column with h = 0 .. p-1 block columns held, the V
+// correction for h > 0, and the downdate of p block columns; the per-pick cost is
+// t_syrk(p)/p + (1/p) sum_h (t_gain(h) + t_vcorr(h) + t_trsm(h)).  The W slots are zero while
+// the downdates are timed, so R - 0 leaves R exactly as packed; the gains, L_s^-1 and W
+// buffers it writes are overwritten by the first step.  Both downdate variants are timed at
+// p = 1.  Results are cached per (device, precision, N_tp, ceil(N_c / 32)).
+
+struct TuneKey {
+    int dev, prec, ntp, nbucket;
+    bool operator<(const TuneKey &o) const
+    {
+        return std::tie(dev, prec, ntp, nbucket) < std::tie(o.dev, o.prec, o.ntp, o.nbucket);
+    }
+};
+struct TuneVal {
+    int delay, variant;
+    double ms[MAX_DELAY];
+};
+std::mutex g_tune_mu;
+std::map<TuneKey, TuneVal> g_tune;
+
+// Milliseconds of `reps` back-to-back calls of f (the minimum over two rounds).
+template <typename F>
+hipError_t time_ms(oed_ctx *h, hipEvent_t a, hipEvent_t b, F f, double *out)
+{
+    double best = 1e300;
+    for (int round = 0; round < 2; ++round) {
+        hipError_t e = hipEventRecord(a, h->stream);
+        if (e == hipSuccess) e = f();
+        if (e == hipSuccess) e = hipEventRecord(b, h->stream);
+        if (e == hipSuccess) e = hipEventSynchronize(b);
+        float ms = 0;
+        if (e == hipSuccess) e = hipEventElapsedTime(&ms, a, b);
+        if (e != hipSuccess) return e;
+        best = std::min(best, (double)ms);
+    }
+    *out = best;
+    return hipSuccess;
+}
+
+oed_status autotune(oed_ctx *h)
+{
+    const TuneKey key{h->device, h->prec, h->N_tp, (h->N_c + 31) / 32};
+    {
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        auto it = g_tune.find(key);
+        if (it != g_tune.end()) {
+            h->delay = it->second.delay;
+            h->syrk_variant = it->second.variant;
+            std::copy(it->second.ms, it->second.ms + MAX_DELAY, h->tuned_ms);
+            return OED_OK;
+        }
+    }
+    const int64_t bs = (int64_t)h->N_tp * h->N_tp;
+    const size_t we = h->wtype == W_F64 ? 8 : h->wtype == W_F32 ? 4 : 2;
+    const size_t wbytes = (size_t)(MAX_DELAY * h->wslot) * we;
+    hipEvent_t a = nullptr, b = nullptr;
+    HIPCHK(h, hipEventCreate(&a));
+    HIPCHK(h, hipEventCreate(&b));
+    auto done = [&](oed_status st) {
+        (void)hipEventDestroy(a);
+        (void)hipEventDestroy(b);
+        return st;
+    };
+    auto zero_w = [&]() -> hipError_t {
+        hipError_t e = hipMemsetAsync(h->W, 0, wbytes, h->stream);
+        if (e == hipSuccess && h->W2) e = hipMemsetAsync(h->W2, 0, wbytes, h->stream);
+        return e;
+    };
+    hipError_t e = zero_w();
+    if (e == hipSuccess) e = hipMemsetAsync(h->Linv, 0, sizeof(double) * bs, h->stream);
+    double t_step[MAX_DELAY] = {0}, t_syrk[MAX_DELAY] = {0}, t_direct = 1e300;
+    for (int hh = 0; hh < MAX_DELAY && e == hipSuccess; ++hh) {
+        StepDesc d = desc(h);
+        d.nheld = hh;
+        double tg = 0, tt = 0;
+        e = time_ms(h, a, b, [&] { return launch_gain(d, h->rtype, h->wtype, h->stream); }, &tg);
+        if (e == hipSuccess)
+            e = time_ms(h, a, b, [&] {
+                hipError_t r = hh > 0 ? launch_vcorr(d, h->wtype, h->stream) : hipSuccess;
+                return r == hipSuccess ? launch_trsm(d, h->rtype, h->wtype, h->stream) : r;
+            }, &tt);
+        t_step[hh] = tg + tt;
+    }
+    if (e == hipSuccess) e = zero_w();
+    for (int p = 1; p <= MAX_DELAY && e == hipSuccess; ++p) {
+        StepDesc d = desc(h);
+        d.nheld = 0;
+        d.nw = p;
+        d.nitems = syrk_tiles(h->n_act, h->N_tp);
+        e = time_ms(h, a, b, [&] { return launch_syrk(d, h->rtype, h->wtype, SYRK_LDS, h->stream); }, &t_syrk[p - 1]);
+        if (e == hipSuccess && p == 1 && h->wtype != W_BF16X3)
+            e = time_ms(h, a, b, [&] { return launch_syrk(d, h->rtype, h->wtype, SYRK_DIRECT, h->stream); }, &t_direct);
+    }
+    if (e != hipSuccess) return done(fail(h, e == hipErrorOutOfMemory ? OED_E_OOM : OED_E_HIP,
+                                          std::string("autotune: ") + hipGetErrorString(e)));
+    TuneVal v{1, SYRK_LDS, {0}};
+    double best = 1e300;
+    for (int p = 1; p <= MAX_DELAY; ++p) {
+        double steps = 0;
+        for (int hh = 0; hh < p; ++hh) steps += t_step[hh];
+        const double syrk = (p == 1) ? std::min(t_syrk[0], t_direct) : t_syrk[p - 1];
+        v.ms[p - 1] = (syrk + steps) / p;
+        if (v.ms[p - 1] < best) {
+            best = v.ms[p - 1];
+            v.delay = p;
+            v.variant = (p == 1 && t_direct < t_syrk[0]) ? SYRK_DIRECT : SYRK_LDS;
+        }
+    }
+    h->delay = v.delay;
+    h->syrk_variant = v.variant;
+    std::copy(v.ms, v.ms + MAX_DELAY, h->tuned_ms);
+    {
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        g_tune[key] = v;
+    }
+    return done(OED_OK);
 }
 
 oed_status enqueue_gains(oed_ctx *h)
@@ -295,7 +418,7 @@ oed_status sync_picks(oed_ctx *h, int k0, oed_status *dev_status)
         h->k = k0 + made;
         h->n_act = h->N_c - h->k;
         h->pending = false;
-        h->held = -1;
+        h->nheld = 0;
         h->poisoned = true;
     }
     for (int q = 0; q < made; ++q) {
@@ -351,8 +474,8 @@ oed_status oed_create(oed_ctx **out, const void *K, int32_t dtype, int64_t ld, i
     if (o.precision != OED_PREC_FP64 && o.precision != OED_PREC_MIXED_F32 && o.precision != OED_PREC_MIXED_BF16X3)
         return OED_E_ARG;
     if (o.precision == OED_PREC_MIXED_BF16X3 && N_t > 128) return OED_E_UNSUPPORTED;
-    if (o.delay < 0 || o.delay > 2) return OED_E_ARG;
-    if (o.delay == 2 && N_t > REGS_MAX_NT) return OED_E_UNSUPPORTED;
+    if (o.delay < 0 || o.delay > MAX_DELAY) return OED_E_ARG;
+    if (o.delay > 1 && N_t > REGS_MAX_NT) return OED_E_UNSUPPORTED;
     for (int r : o.reserved)
         if (r != 0) return OED_E_ARG;
 
@@ -370,9 +493,10 @@ oed_status oed_create(oed_ctx **out, const void *K, int32_t dtype, int64_t ld, i
     h->rtype = o.precision == OED_PREC_FP64 ? R_F64 : R_F32;
     h->wtype = o.precision == OED_PREC_FP64 ? W_F64 : o.precision == OED_PREC_MIXED_F32 ? W_F32 : W_BF16X3;
     h->flags = o.flags;
-    // delay 0 (automatic): hold one block column whenever the register factorisations and the
-    // LDS downdate serve the block size
-    h->delay = o.delay == 0 ? (N_t <= REGS_MAX_NT ? 2 : 1) : o.delay;
+    // delay 0 (automatic): hold block columns whenever the register factorisations and the LDS
+    // downdate serve the block size
+    h->delay = o.delay == 0 ? (N_t <= REGS_MAX_NT ? MAX_DELAY : 1) : o.delay;
+    const bool tune = o.delay == 0 && (o.flags & OED_FLAG_AUTOTUNE) && N_t <= REGS_MAX_NT;
     h->stream = (hipStream_t)stream;
     h->lmap.assign(N_s, -1);
     if (o.candidates) {
@@ -401,11 +525,11 @@ oed_status oed_create(oed_ctx **out, const void *K, int32_t dtype, int64_t ld, i
         const int64_t nblk = (int64_t)h->N_c * (h->N_c + 1) / 2;
         HIPCHK(h, dmalloc(h, &h->R, (size_t)(nblk * bs) * relem(h)));
         const size_t we = h->wtype == W_F64 ? 8 : h->wtype == W_F32 ? 4 : 2;
-        for (int q = 0; q < h->delay; ++q) {
-            HIPCHK(h, dmalloc(h, &h->Wb[q], (size_t)(h->N_c * bs) * we));
-            if (h->wtype == W_BF16X3) HIPCHK(h, dmalloc(h, &h->W2b[q], (size_t)(h->N_c * bs) * 2));
-        }
-        if (h->delay == 2) HIPCHK(h, dmalloc(h, (void **)&h->V, sizeof(double) * bs));
+        h->wslot = h->N_c * bs;
+        const int slots = tune ? MAX_DELAY : h->delay;
+        HIPCHK(h, dmalloc(h, &h->W, (size_t)(slots * h->wslot) * we));
+        if (h->wtype == W_BF16X3) HIPCHK(h, dmalloc(h, &h->W2, (size_t)(slots * h->wslot) * 2));
+        if (slots > 1) HIPCHK(h, dmalloc(h, (void **)&h->V, sizeof(double) * bs * (slots - 1)));
         HIPCHK(h, dmalloc(h, (void **)&h->Linv, sizeof(double) * bs));
         HIPCHK(h, dmalloc(h, (void **)&h->gains, sizeof(double) * h->N_c));
         HIPCHK(h, dmalloc(h, (void **)&h->pick_gain, sizeof(double) * h->N_c));
@@ -424,6 +548,7 @@ oed_status oed_create(oed_ctx **out, const void *K, int32_t dtype, int64_t ld, i
         if (s2 != OED_OK) return s2;
         HIPCHK(h, hipStreamSynchronize(h->stream));
         collect_profile(h);
+        if (tune) return autotune(h);
         return OED_OK;
     };
     st = setup();
@@ -576,6 +701,15 @@ oed_status oed_get_profile(oed_ctx *h, oed_profile *out, int32_t reset)
         }
         h->syrk_flops = h->syrk_bytes = 0;
     }
+    return OED_OK;
+}
+
+oed_status oed_get_config(const oed_ctx *h, int32_t *delay, int32_t *syrk_variant, double *per_pick_ms)
+{
+    if (!h) return OED_E_ARG;
+    if (delay) *delay = h->delay;
+    if (syrk_variant) *syrk_variant = h->syrk_variant;
+    if (per_pick_ms) std::copy(h->tuned_ms, h->tuned_ms + MAX_DELAY, per_pick_ms);
     return OED_OK;
 }
 

@@ -28,7 +28,8 @@ struct Inst {
     int N_s = 0, N_t = 0, N_tp = 0, budget = 0, kdtype = 0;
     int64_t ld = 0;
     double sigma2 = 0, half_noise = 0;
-    void *R = nullptr, *W[2] = {nullptr, nullptr}, *W2[2] = {nullptr, nullptr};  // W slots (BF16: hi, lo)
+    void *R = nullptr, *W = nullptr, *W2 = nullptr;  // `delay` W slots (BF16: hi, lo parts)
+    int64_t wslot = 0;                               // elements per W slot
     double *V = nullptr;
     double *Linv = nullptr, *gains = nullptr, *pick_gain = nullptr;
     int *act[2] = {nullptr, nullptr}, *cmap = nullptr, *picks = nullptr, *state = nullptr;
@@ -62,6 +63,7 @@ struct oed_batch {
     std::vector<Inst> in;
     int prec = OED_PREC_FP64, rtype = R_F64, wtype = W_F64;
     int delay = 2;
+    double tuned_ms[MAX_DELAY] = {0};  // autotuner: eager run time for delay 1..MAX_DELAY
     uint32_t flags = 0;
     hipStream_t stream = nullptr;
     std::vector<void *> allocs;
@@ -138,21 +140,17 @@ oed_status pack_all(oed_batch *b, const oed_instance *inst)
 }
 
 // Descriptor of instance x at step k, before (gains, pick) or after (block column, downdate)
-// its k-th pick.  With delay 2 the block column of an even pick goes to slot 0 and is held; the
-// next (odd) pick's gains and pick correct for it, its block column goes to slot 1, and both are
-// subtracted in one downdate.
+// its k-th pick.  With delay p the block column of pick k goes to W slot k mod p; slots
+// 0 .. (k mod p) - 1 hold the earlier ones, and after every p-th pick all p are subtracted in
+// one downdate.
 StepDesc inst_desc(const Inst &x, int k, bool after_pick, int delay)
 {
     StepDesc d{};
     d.R = x.R;
-    const bool held = delay == 2 && (k & 1) != 0;  // pick k - 1's block column is held in slot 0
-    const int ws = held && after_pick ? 1 : 0;
-    d.W = x.W[ws];
-    d.W2 = x.W2[ws];
-    if (held) {
-        d.P = x.W[0];
-        d.P2 = x.W2[0];
-    }
+    d.W = x.W;
+    d.W2 = x.W2;
+    d.wslot = x.wslot;
+    d.nheld = k % delay;
     d.V = x.V;
     d.nw = 1;
     d.act_in = x.act[(k + (after_pick ? 1 : 0)) & 1];
@@ -210,17 +208,18 @@ void build_schedule(oed_batch *b)
                 ++p.ndesc;
             }
         b->launches.push_back(p);
-        // block column and downdate for the instances that pick again; with delay 2 an even
-        // pick's block column is held (no downdate) and an odd pick's is corrected for it
-        const bool hold = b->delay == 2 && (k & 1) == 0;
-        const bool corr = b->delay == 2 && (k & 1) == 1;
+        // block column and downdate for the instances that pick again; with delay p the
+        // block column is held unless this is the p-th pick since the last downdate
+        const bool hold = (k % b->delay) + 1 < b->delay;
+        const bool corr = k % b->delay > 0;
+        const int nw = k % b->delay + 1;
         if (corr) {
             Launch v = make_launch(L_VCORR, (int64_t)b->descs.size());
             for (const Inst &x : b->in)
                 if (x.budget > k + 1) {
                     StepDesc d = inst_desc(x, k, true, b->delay);
                     d.item0 = v.total;
-                    d.nitems = (int64_t)(x.N_tp / 16) * (x.N_tp / 16);
+                    d.nitems = (int64_t)d.nheld * (x.N_tp / 16) * (x.N_tp / 16);
                     v.total += d.nitems;
                     b->descs.push_back(d);
                     ++v.ndesc;
@@ -239,7 +238,6 @@ void build_schedule(oed_batch *b)
                 ++t.ndesc;
                 by_ntp[x.N_tp].push_back(&x);
                 if (!hold) {
-                    const int nw = corr ? 2 : 1;
                     const double nr = (double)d.n_act * x.N_t;
                     b->syrk_flops += nw * (double)x.N_t * nr * (nr + 1.0);
                     b->syrk_bytes += e * (nr * (nr + x.N_t) + nw * nr * x.N_t);
@@ -251,7 +249,7 @@ void build_schedule(oed_batch *b)
         for (auto &kv : by_ntp) {
             Launch s = make_launch(L_SYRK, (int64_t)b->descs.size());
             s.N_tp = kv.first;
-            s.nw = corr ? 2 : 1;
+            s.nw = nw;
             for (const Inst *x : kv.second) {
                 StepDesc d = inst_desc(*x, k, true, b->delay);
                 d.nw = s.nw;
@@ -288,6 +286,36 @@ oed_status enqueue_run(oed_batch *b)
     return OED_OK;
 }
 
+// Autotuner (OED_BATCH_AUTOTUNE with no delay given): runs the whole selection once per delay
+// depth p = 1..MAX_DELAY, eagerly, from freshly packed working copies, and keeps the fastest.
+// All depths give the same picks up to rounding; W slots for MAX_DELAY are allocated.
+oed_status autotune_batch(oed_batch *b, const oed_instance *inst)
+{
+    double best = 1e300;
+    int best_p = b->delay;
+    for (int p = 1; p <= MAX_DELAY; ++p) {
+        b->delay = p;
+        build_schedule(b);
+        BCHK(b, hipMemcpy(b->d_descs, b->descs.data(), sizeof(StepDesc) * b->descs.size(), hipMemcpyHostToDevice));
+        oed_status st = pack_all(b, inst);
+        if (st != OED_OK) return st;
+        BCHK(b, hipEventRecord(b->ev0, b->stream));
+        st = enqueue_run(b);
+        if (st != OED_OK) return st;
+        BCHK(b, hipEventRecord(b->ev1, b->stream));
+        BCHK(b, hipEventSynchronize(b->ev1));
+        float ms = 0;
+        BCHK(b, hipEventElapsedTime(&ms, b->ev0, b->ev1));
+        b->tuned_ms[p - 1] = ms;
+        if (ms < best) {
+            best = ms;
+            best_p = p;
+        }
+    }
+    b->delay = best_p;
+    return OED_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -301,13 +329,16 @@ oed_status oed_batch_create(oed_batch **out, const oed_instance *inst, int32_t n
     if (st != OED_OK) return st;
     if (precision != OED_PREC_FP64 && precision != OED_PREC_MIXED_F32 && precision != OED_PREC_MIXED_BF16X3)
         return OED_E_ARG;
+    if (((flags >> 8) & 0xFu) > (unsigned)MAX_DELAY) return OED_E_ARG;
     oed_batch *b = new (std::nothrow) oed_batch();
     if (!b) return OED_E_OOM;
     b->prec = precision;
     b->rtype = precision == OED_PREC_FP64 ? R_F64 : R_F32;
     b->wtype = precision == OED_PREC_FP64 ? W_F64 : precision == OED_PREC_MIXED_F32 ? W_F32 : W_BF16X3;
     b->flags = flags;
-    b->delay = (flags & OED_BATCH_DELAY1) ? 1 : 2;
+    b->delay = (int)((flags >> 8) & 0xFu);
+    const bool tune = b->delay == 0 && (flags & OED_BATCH_AUTOTUNE);
+    if (b->delay == 0) b->delay = MAX_DELAY;
     auto setup = [&]() -> oed_status {
         // the caller's K must be complete before the batch stream reads it
         BCHK(b, hipStreamSynchronize((hipStream_t)stream));
@@ -330,15 +361,14 @@ oed_status oed_batch_create(oed_batch **out, const oed_instance *inst, int32_t n
             x.half_noise = 0.5 * y.N_t * std::log(y.sigma2);
             const int64_t bs = (int64_t)x.N_tp * x.N_tp, nblk = (int64_t)x.N_s * (x.N_s + 1) / 2;
             BCHK(b, balloc(b, &x.R, (size_t)(nblk * bs) * er));
-            for (int q = 0; q < b->delay; ++q) {
-                if (b->wtype == W_BF16X3) {
-                    BCHK(b, balloc(b, &x.W[q], (size_t)(x.N_s * bs) * 2));
-                    BCHK(b, balloc(b, &x.W2[q], (size_t)(x.N_s * bs) * 2));
-                } else {
-                    BCHK(b, balloc(b, &x.W[q], (size_t)(x.N_s * bs) * er));
-                }
+            x.wslot = x.N_s * bs;
+            if (b->wtype == W_BF16X3) {
+                BCHK(b, balloc(b, &x.W, (size_t)(b->delay * x.wslot) * 2));
+                BCHK(b, balloc(b, &x.W2, (size_t)(b->delay * x.wslot) * 2));
+            } else {
+                BCHK(b, balloc(b, &x.W, (size_t)(b->delay * x.wslot) * er));
             }
-            if (b->delay == 2) BCHK(b, balloc(b, (void **)&x.V, sizeof(double) * bs));
+            if (b->delay > 1) BCHK(b, balloc(b, (void **)&x.V, sizeof(double) * bs * (b->delay - 1)));
             BCHK(b, balloc(b, (void **)&x.Linv, sizeof(double) * bs));
             BCHK(b, balloc(b, (void **)&x.gains, sizeof(double) * x.N_s));
             BCHK(b, balloc(b, (void **)&x.act[0], sizeof(int) * x.N_s));
@@ -361,8 +391,21 @@ oed_status oed_batch_create(oed_batch **out, const oed_instance *inst, int32_t n
             x.picks = ires + x.off_int;
             x.state = x.picks + x.budget;
         }
+        // descriptor array sized for the longest schedule (every delay depth the tuner may try)
+        size_t ndesc = 1;
+        for (int p = tune ? 1 : b->delay; p <= b->delay; ++p) {
+            const int keep = b->delay;
+            b->delay = p;
+            build_schedule(b);
+            ndesc = std::max(ndesc, b->descs.size());
+            b->delay = keep;
+        }
+        BCHK(b, balloc(b, (void **)&b->d_descs, sizeof(StepDesc) * ndesc));
+        if (tune) {
+            oed_status s2 = autotune_batch(b, inst);
+            if (s2 != OED_OK) return s2;
+        }
         build_schedule(b);
-        BCHK(b, balloc(b, (void **)&b->d_descs, sizeof(StepDesc) * std::max<size_t>(1, b->descs.size())));
         BCHK(b, hipMemcpy(b->d_descs, b->descs.data(), sizeof(StepDesc) * b->descs.size(), hipMemcpyHostToDevice));
         return pack_all(b, inst);
     };
@@ -373,6 +416,14 @@ oed_status oed_batch_create(oed_batch **out, const oed_instance *inst, int32_t n
         return st;
     }
     *out = b;
+    return OED_OK;
+}
+
+oed_status oed_batch_get_config(const oed_batch *b, int32_t *delay, double *per_run_ms)
+{
+    if (!b) return OED_E_ARG;
+    if (delay) *delay = b->delay;
+    if (per_run_ms) std::copy(b->tuned_ms, b->tuned_ms + MAX_DELAY, per_run_ms);
     return OED_OK;
 }
 

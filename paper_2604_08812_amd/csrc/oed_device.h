@@ -89,6 +89,11 @@ __device__ __forceinline__ int64_t tri_row(int64_t b)
     return i;
 }
 
+template <bool B>
+struct BoolC {
+    static constexpr bool value = B;
+};
+
 // Instance of a batched launch that owns work item `item`: the last descriptor with
 // item0 <= item (descriptors are sorted by item0).  -1 if no instance owns the item.
 __device__ __forceinline__ int find_instance(const StepDesc *ds, int n, int64_t item)
@@ -101,6 +106,8 @@ __device__ __forceinline__ int find_instance(const StepDesc *ds, int n, int64_t 
         else
             hi = mid - 1;
     }
+    // work-group uniform: keeps the descriptor loads scalar
+    lo = __builtin_amdgcn_readfirstlane(lo);
     return (item >= ds[lo].item0 && item < ds[lo].item0 + ds[lo].nitems) ? lo : -1;
 }
 

@@ -222,11 +222,11 @@ struct HeldProd<unsigned short> {
     }
 };
 
-// With P (the candidate's held W block; P2 its BF16 lo parts) the factored matrix is
-// R_jj - P_j P_j^T, the candidate's current Schur block.
+// With held W blocks (slots 0 .. nheld-1 of d.W, candidate offset pofs) the factored matrix is
+// R_jj - sum_h P_h,j P_h,j^T, the candidate's current Schur block.
 template <typename TR, typename TW>
 __device__ __forceinline__ bool chol_regs(const TR *__restrict__ Rb, int N_t, int nb, double *colbuf, double *piv,
-                                          double *Lout, const TW *P, const TW *P2)
+                                          double *Lout, const StepDesc &d, int64_t pofs)
 {
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     const int nbr = (N_t + 15) >> 4;
@@ -246,7 +246,9 @@ __device__ __forceinline__ bool chol_regs(const TR *__restrict__ Rb, int N_t, in
             }
         }
     }
-    if (P) {
+    for (int hp = 0; hp < d.nheld; ++hp) {
+        const TW *P = (const TW *)d.W + hp * d.wslot + pofs;
+        const TW *P2 = d.W2 ? (const TW *)d.W2 + hp * d.wslot + pofs : nullptr;
 #pragma unroll
         for (int h = 0; h < 2; ++h) {
             const int I = h ? 7 - w : w;
@@ -474,10 +476,8 @@ __device__ void gain_regs_body(const StepDesc &d, int p)
     if (d.state[ST_STATUS] != 0 || p >= d.n_act) return;
     const int i = d.act_in[p];
     const int64_t bs = (int64_t)d.N_tp * d.N_tp;
-    const TW *P = d.P ? (const TW *)d.P + i * bs : nullptr;
-    const TW *P2 = d.P2 ? (const TW *)d.P2 + i * bs : nullptr;
     const bool ok = chol_regs<TR, TW>((const TR *)d.R + blk_index(i, i) * bs, d.N_t, d.N_tp >> 4, colbuf, piv, nullptr,
-                                      P, P2);
+                                      d, i * bs);
     if (!ok) {
         if (threadIdx.x == 0) d.gains[p] = -INFINITY;
         return;
@@ -500,10 +500,8 @@ __device__ void pick_regs_body(const StepDesc &d, double *Lout)
     const int s = d.act_in[pos];
     for (int p = tid; p < d.n_act - 1; p += blockDim.x) d.act_out[p] = d.act_in[p < pos ? p : p + 1];
     const int64_t bs = (int64_t)d.N_tp * d.N_tp;
-    const TW *P = d.P ? (const TW *)d.P + s * bs : nullptr;
-    const TW *P2 = d.P2 ? (const TW *)d.P2 + s * bs : nullptr;
-    const bool ok =
-        chol_regs<TR, TW>((const TR *)d.R + blk_index(s, s) * bs, d.N_t, d.N_tp >> 4, colbuf, piv, Lout, P, P2);
+    const bool ok = chol_regs<TR, TW>((const TR *)d.R + blk_index(s, s) * bs, d.N_t, d.N_tp >> 4, colbuf, piv, Lout, d,
+                                      s * bs);
     if (!ok) {
         if (tid == 0) d.state[ST_STATUS] = 2;
         return;
@@ -660,7 +658,7 @@ static hipError_t launch_gain_t(const StepDesc &d, hipStream_t s)
     if (d.N_t <= REGS_MAX_NT) {
         hipLaunchKernelGGL((gain_regs_kernel<TR, TW>), dim3(d.n_act), dim3(256), 0, s, d);
     } else {
-        if (d.P) return hipErrorInvalidValue;
+        if (d.nheld) return hipErrorInvalidValue;
         const size_t lds = d.scratch ? 0 : gain_lds_bytes(d.N_t);
         allow_lds(gain_lds_kernel<TR>, lds);
         hipLaunchKernelGGL(gain_lds_kernel<TR>, dim3(d.n_act), dim3(256), lds, s, d);
@@ -676,7 +674,7 @@ static hipError_t launch_pick_t(const StepDesc &d, hipStream_t s)
         allow_lds(pick_regs_kernel<TR, TW>, lds);
         hipLaunchKernelGGL((pick_regs_kernel<TR, TW>), dim3(1), dim3(256), lds, s, d);
     } else {
-        if (d.P) return hipErrorInvalidValue;
+        if (d.nheld) return hipErrorInvalidValue;
         const size_t lds = d.scratch ? 0 : pick_lds_bytes(d.N_t);
         allow_lds(pick_lds_kernel<TR>, lds);
         hipLaunchKernelGGL(pick_lds_kernel<TR>, dim3(1), dim3(256), lds, s, d);

@@ -61,13 +61,18 @@ enum StateWord { ST_STATUS = 0, ST_NPICKS = 1, ST_LAST = 2, ST_WORDS = 16 };
 // One instance at one phase of one greedy step: everything a kernel needs to know.  Single
 // launches pass it by value; batched launches pass a device array sorted by item0, and every
 // work-group finds its instance by binary search.
+// Largest downdate delay depth: up to MAX_DELAY - 1 block columns held back.
+constexpr int MAX_DELAY = 4;
+
 struct StepDesc {
     void *R;               // working copy (element type by precision)
-    void *W;               // W blocks (element type by precision; BF16X3: the hi parts)
-    void *W2;              // BF16X3: the lo parts of W (same layout), else unused
-    void *P;               // held W of an earlier pick whose downdate is not yet applied, or null
-    void *P2;              // BF16X3: its lo parts
-    double *V;             // L_s^-1 P_s of the last pick s when P is held (operand order, N_tp^2)
+    void *W;               // W slots (element type by precision; BF16X3: the hi parts): slot h at
+                           // W + h * wslot elements; held block columns in slots 0 .. nheld-1, the
+                           // block column of the last pick goes to slot nheld
+    void *W2;              // BF16X3: the lo parts (same layout), else unused
+    int64_t wslot;         // elements per W slot (N_c N_tp^2)
+    double *V;             // L_s^-1 P_h,s of the last pick s for every held h (operand order, N_tp^2 each)
+    int nheld;             // number of held W (gain, pick, vcorr, trsm)
     const int *act_in;     // remaining candidates (gain, pick: before the pick; trsm, syrk: after it)
     int *act_out;          // pick: remaining candidates after the pick
     double *gains;         // gains by position in act_in
@@ -81,7 +86,7 @@ struct StepDesc {
     int N_t, N_tp;         // real and padded block size
     int step;              // pick: index of this pick
     int forced;            // pick: forced local index, or -1 for the argmax
-    int nw;                // syrk: W blocks applied (1: W; 2: W and P, inner dimension 2 N_tp)
+    int nw;                // syrk: W slots 0 .. nw-1 applied (inner dimension nw N_tp)
     int64_t item0;         // batched launches: first work item of this instance
     int64_t nitems;        // work items of this instance (gain, trsm: n_act; pick: 1; syrk: tiles)
 };
@@ -100,9 +105,10 @@ hipError_t launch_pack(const void *K, int kdtype, int64_t ld, int N_t, int N_tp,
 hipError_t launch_init_state(int *act, int n, int *state, hipStream_t s);
 
 // Single-instance launches (d.item0 = 0, d.nitems = work items).
-// Delayed downdate: while d.P holds the W of an earlier pick that R does not include yet,
-// the gain and pick kernels factor R_jj - P_j P_j^T, launch_vcorr forms V = L_s^-1 P_s for the
-// new pick s, and the block-column kernel returns W_i = R_is L_s^-T - P_i V^T.
+// Delayed downdate: while W slots 0 .. nheld-1 hold the block columns P_h of earlier picks that
+// R does not include yet, the gain and pick kernels factor R_jj - sum_h P_h,j P_h,j^T,
+// launch_vcorr forms V_h = L_s^-1 P_h,s for the new pick s, and the block-column kernel writes
+// W_i = R_is L_s^-T - sum_h P_h,i V_h^T to slot nheld.
 hipError_t launch_gain(const StepDesc &d, int rtype, int wtype, hipStream_t s);
 hipError_t launch_pick(const StepDesc &d, int rtype, int wtype, hipStream_t s);
 hipError_t launch_vcorr(const StepDesc &d, int wtype, hipStream_t s);

@@ -75,22 +75,25 @@ __device__ __forceinline__ double w_elem<unsigned short>(const unsigned short *W
     return (double)bf2f(Wh[o]) + (double)bf2f(Wl[o]);
 }
 
-// Correction of a delayed downdate: with the W of an earlier pick held back (P), the block
-// column of the new pick s is W_i = (R_is - P_i P_s^T) L_s^-T = R_is L_s^-T - P_i V^T with
-// V = L_s^-1 P_s.  One wave per 16 x 16 sub-block of V: V^T = P_s^T L_s^-T accumulated on FP64
-// MFMA lands in the accumulator order, which is V's operand order (the order of L_s^-1).
+// Correction of a delayed downdate: with the W of earlier picks held back (P_h), the block
+// column of the new pick s is W_i = (R_is - sum_h P_h,i P_h,s^T) L_s^-T
+// = R_is L_s^-T - sum_h P_h,i V_h^T with V_h = L_s^-1 P_h,s.  One wave per 16 x 16 sub-block of
+// one V_h: V_h^T = P_h,s^T L_s^-T accumulated on FP64 MFMA lands in the accumulator order, which
+// is V's operand order (the order of L_s^-1).
 template <typename TW>
 __device__ void vcorr_body(const StepDesc &d, int item)
 {
     if (d.state[ST_STATUS] != 0) return;
     const int nb = d.N_tp >> 4;
-    if (item >= nb * nb) return;
+    const int hp = item / (nb * nb);
+    if (hp >= d.nheld) return;
+    item -= hp * nb * nb;
     const int kb = item / nb, ab = item % nb;  // V^T sub-block (kb, ab) = V sub-block (ab, kb)
     const int lane = threadIdx.x & 63, g = lane >> 4, al = a_lane<double>(lane) & 15;
     const int s = d.state[ST_LAST];
     const int64_t bs = (int64_t)d.N_tp * d.N_tp;
-    const TW *Ps = (const TW *)d.P + s * bs;
-    const TW *Ps2 = d.P2 ? (const TW *)d.P2 + s * bs : nullptr;
+    const TW *Ps = (const TW *)d.W + hp * d.wslot + s * bs;
+    const TW *Ps2 = d.W2 ? (const TW *)d.W2 + hp * d.wslot + s * bs : nullptr;
     const int nbr = (d.N_t + 15) >> 4;  // rows of P_s past N_t are zero
     doublex4 acc{0.0, 0.0, 0.0, 0.0};
     for (int mq = 0; mq < nbr; ++mq) {
@@ -99,7 +102,7 @@ __device__ void vcorr_body(const StepDesc &d, int item)
         for (int s4 = 0; s4 < 4; ++s4)
             acc = mfma16(w_elem<TW>(Ps, Ps2, 16 * mq + 4 * g + s4, 16 * kb + al, nb), b[s4], acc);
     }
-    st4(d.V + ((ab * nb + kb) << 8) + lane * 4, acc);
+    st4(d.V + hp * bs + ((ab * nb + kb) << 8) + lane * 4, acc);
 }
 
 template <typename TR, typename TW>
@@ -117,8 +120,8 @@ __device__ void trsm_body(const StepDesc &d, int p)
     const int alane = a_lane<double>(lane);
     const bool below = i > s;
     const TR *Cb = R + blk_index(below ? i : s, below ? s : i) * bs;
-    TW *Wi = W + (int64_t)i * bs;
-    TW *Wi2 = (TW *)d.W2 + (int64_t)i * bs;
+    TW *Wi = W + d.nheld * d.wslot + (int64_t)i * bs;             // slot nheld
+    TW *Wi2 = (TW *)d.W2 + d.nheld * d.wslot + (int64_t)i * bs;
     for (int tb = wave; tb < nb; tb += 4) {
         for (int kg = 0; kg < nb; kg += 8) {
             const int kend = min(nb, kg + 8);
@@ -146,10 +149,11 @@ __device__ void trsm_body(const StepDesc &d, int p)
                     }
                 }
             }
-            if (d.P) {
-                // - P_i V^T: inner index over the held pick's block, V in L_s^-1's order
-                const TW *Pi = (const TW *)d.P + (int64_t)i * bs;
-                const TW *Pi2 = d.P2 ? (const TW *)d.P2 + (int64_t)i * bs : nullptr;
+            for (int hp = 0; hp < d.nheld; ++hp) {
+                // - P_h,i V_h^T: inner index over the held pick's block, V_h in L_s^-1's order
+                const TW *Pi = (const TW *)d.W + hp * d.wslot + (int64_t)i * bs;
+                const TW *Pi2 = d.W2 ? (const TW *)d.W2 + hp * d.wslot + (int64_t)i * bs : nullptr;
+                const double *Vh = d.V + hp * bs;
                 const int nbr = (d.N_t + 15) >> 4;
                 for (int q = 0; q < nbr; ++q) {
                     double b[4];
@@ -160,7 +164,7 @@ __device__ void trsm_body(const StepDesc &d, int p)
                     for (int c = 0; c < 8; ++c) {
                         const int kc = kg + c;
                         if (kc < kend) {
-                            const doublex4 a = ld4(d.V + ((kc * nb + q) << 8) + alane * 4);
+                            const doublex4 a = ld4(Vh + ((kc * nb + q) << 8) + alane * 4);
 #pragma unroll
                             for (int s4 = 0; s4 < 4; ++s4) acc[c] = mfma16(a[s4], b[s4], acc[c]);
                         }
@@ -311,15 +315,14 @@ __device__ __forceinline__ void tile_map(const StepDesc &d, int64_t P, int64_t Q
 // and is subtracted from R at the end.  FP32: the R tile is loaded into registers a few
 // blocks per slice, behind the next slice's W loads, so it streams in during the MFMAs.
 // FP64 (no registers for the tile) reads R in the epilogue.
-template <typename T, int NB, int NW>
+template <typename T, int NB>
 __device__ void syrk_lds_body(const StepDesc &d, int64_t tile)
 {
     typedef typename V4<T>::type vec;
     constexpr int N_tp = 16 * NB;
-    constexpr int NS = NB * NW;                  // 16-wide inner slices: W's, then the held P's
     constexpr bool PREFETCH_R = sizeof(T) == 4;
-    constexpr int PER = (16 + NS - 1) / NS;      // R blocks fetched per slice
-    __shared__ vec lds[2][2][8 * 64];            // [buffer][A/B][sub-block * 64 + lane]
+    constexpr int PER = (16 + NB - 1) / NB;  // R blocks fetched per slice of the last W block
+    __shared__ vec lds[2][2][8 * 64];        // [buffer][A/B][sub-block * 64 + lane]
     if (d.state[ST_STATUS] != 0) return;
     int64_t P, Q;
     if (!super_tile(tile, syrk_tile_rows(d.n_act, d.N_tp), P, Q)) return;
@@ -329,22 +332,23 @@ __device__ void syrk_lds_body(const StepDesc &d, int64_t tile)
     const int alane = a_lane<T>(lane);
     TileMap m;
     tile_map<N_tp>(d, P, Q, wave, m);
-    const T *Wl = (const T *)d.W + lane * 4;                     // this lane's element of a staged sub-block
-    const T *Pl = NW > 1 ? (const T *)d.P + lane * 4 : Wl;       // same for the held W
-    T *Rl = R + lane * 4;                                        // this lane's element of an output block
+    T *Rl = R + lane * 4;  // this lane's element of an output block
+    // W slot `slot`, at this lane's element of a staged sub-block
+    const T *W0 = (const T *)d.W + lane * 4;
+    const int64_t wslot = d.wslot;
+    auto wblk = [&](int slot) -> const T * { return W0 + slot * wslot; };
 
     vec rt[16], acc[16];
 #pragma unroll
     for (int f = 0; f < 16; ++f) acc[f] = vec{0, 0, 0, 0};
     vec sa[2], sbv[2];
+    {
+        const T *w0 = wblk(0);
 #pragma unroll
-    for (int h = 0; h < 2; ++h) {
-        sa[h] = ld4(Wl + m.wA[h]);
-        sbv[h] = ld4(Wl + m.wB[h]);
-    }
-    if (PREFETCH_R) {
-#pragma unroll
-        for (int f = 0; f < PER && f < 16; ++f) rt[f] = ld4(Rl + m.rblk[f]);
+        for (int h = 0; h < 2; ++h) {
+            sa[h] = ld4(w0 + m.wA[h]);
+            sbv[h] = ld4(w0 + m.wB[h]);
+        }
     }
 #pragma unroll
     for (int h = 0; h < 2; ++h) {
@@ -352,50 +356,58 @@ __device__ void syrk_lds_body(const StepDesc &d, int64_t tile)
         lds[0][1][(wave + 4 * h) * 64 + lane] = sbv[h];
     }
     __syncthreads();
+
+    // The NB 16-wide inner slices of one W block (cur); the slice after its last one is the
+    // first of nxt (null: none).  par: LDS buffer of its first slice.  The last block's pass
+    // also streams the R tile in (PREF): PER blocks per slice, issued after that slice's W
+    // loads, so the wait for those never waits for R.
+    auto pass = [&](auto pref, const T *cur, const T *nxt, int par) {
+        constexpr bool PREF = decltype(pref)::value;
 #pragma unroll
-    for (int q = 0; q < NS; ++q) {
-        const int buf = q & 1;
-        if (q + 1 < NS) {
-            const T *src = (q + 1) < NB ? Wl : Pl;
-            const int o = ((q + 1) % NB) << 8;
+        for (int q = 0; q < NB; ++q) {
+            const int buf = par ^ (q & 1);
+            const bool more = q + 1 < NB || nxt;
+            if (more) {
+                const T *src = q + 1 < NB ? cur + ((q + 1) << 8) : nxt;
 #pragma unroll
-            for (int h = 0; h < 2; ++h) {
-                sa[h] = ld4(src + m.wA[h] + o);
-                sbv[h] = ld4(src + m.wB[h] + o);
+                for (int h = 0; h < 2; ++h) {
+                    sa[h] = ld4(src + m.wA[h]);
+                    sbv[h] = ld4(src + m.wB[h]);
+                }
             }
-            if (PREFETCH_R) {
+            if (PREF) {
 #pragma unroll
-                for (int f = (q + 1) * PER; f < (q + 2) * PER && f < 16; ++f) rt[f] = ld4(Rl + m.rblk[f]);
+                for (int f = q * PER; f < (q + 1) * PER && f < 16; ++f) rt[f] = ld4(Rl + m.rblk[f]);
             }
+            if (m.any) {
+                vec a[4], w[4];
+#pragma unroll
+                for (int b = 0; b < 4; ++b) {
+                    a[b] = lds[buf][0][(wr * 4 + b) * 64 + alane];
+                    w[b] = lds[buf][1][(wc * 4 + b) * 64 + lane];
+                }
+#pragma unroll
+                for (int s4 = 0; s4 < 4; ++s4)
+#pragma unroll
+                    for (int b = 0; b < 4; ++b)
+#pragma unroll
+                        for (int c = 0; c < 4; ++c) acc[4 * b + c] = mfma16(a[b][s4], w[c][s4], acc[4 * b + c]);
+            }
+            if (more) {
+#pragma unroll
+                for (int h = 0; h < 2; ++h) {
+                    lds[buf ^ 1][0][(wave + 4 * h) * 64 + lane] = sa[h];
+                    lds[buf ^ 1][1][(wave + 4 * h) * 64 + lane] = sbv[h];
+                }
+            }
+            __syncthreads();
         }
-        if (m.any) {
-            vec a[4], w[4];
-#pragma unroll
-            for (int b = 0; b < 4; ++b) {
-                a[b] = lds[buf][0][(wr * 4 + b) * 64 + alane];
-                w[b] = lds[buf][1][(wc * 4 + b) * 64 + lane];
-            }
-#pragma unroll
-            for (int s4 = 0; s4 < 4; ++s4)
-#pragma unroll
-                for (int b = 0; b < 4; ++b)
-#pragma unroll
-                    for (int c = 0; c < 4; ++c) acc[4 * b + c] = mfma16(a[b][s4], w[c][s4], acc[4 * b + c]);
-        }
-        if (q + 1 < NS) {
-#pragma unroll
-            for (int h = 0; h < 2; ++h) {
-                lds[buf ^ 1][0][(wave + 4 * h) * 64 + lane] = sa[h];
-                lds[buf ^ 1][1][(wave + 4 * h) * 64 + lane] = sbv[h];
-            }
-        }
-        __syncthreads();
-    }
+    };
+    const int nw = d.nw;
+    for (int slot = 0; slot + 1 < nw; ++slot) pass(BoolC<false>(), wblk(slot), wblk(slot + 1), (slot * NB) & 1);
+    pass(BoolC<PREFETCH_R>(), wblk(nw - 1), nullptr, ((nw - 1) * NB) & 1);
+
     if (!m.any) return;
-    if (PREFETCH_R) {
-#pragma unroll
-        for (int f = NS * PER; f < 16; ++f) rt[f] = ld4(Rl + m.rblk[f]);
-    }
 #pragma unroll
     for (int f = 0; f < 16; ++f)
         if (m.ok[f]) st4(Rl + m.rblk[f], (PREFETCH_R ? rt[f] : ld4(Rl + m.rblk[f])) - acc[f]);
@@ -406,13 +418,12 @@ __device__ void syrk_lds_body(const StepDesc &d, int64_t tile)
 // hi_I lo_J^T + lo_I hi_J^T on the 16x16x32 BF16 MFMA with FP32 accumulation.  Per 32-wide
 // inner slice the work-group stages the hi and lo parts of both W panels in LDS (double
 // buffered); otherwise as syrk_lds_body.
-template <int NB32, int NW>
+template <int NB32>
 __device__ void syrk_bf16_body(const StepDesc &d, int64_t tile)
 {
     constexpr int N_tp = 32 * NB32;
-    constexpr int NS = NB32 * NW;                 // 32-wide inner slices: W's, then the held P's
-    constexpr int PER = (16 + NS - 1) / NS;       // R blocks fetched per slice
-    __shared__ u32x4 lds[2][4][8 * 64];           // [buffer][A hi, A lo, B hi, B lo][sub-block * 64 + lane]
+    constexpr int PER = (16 + NB32 - 1) / NB32;  // R blocks fetched per slice of the last W block
+    __shared__ u32x4 lds[2][4][8 * 64];          // [buffer][A hi, A lo, B hi, B lo][sub-block * 64 + lane]
     if (d.state[ST_STATUS] != 0) return;
     int64_t P, Q;
     if (!super_tile(tile, syrk_tile_rows(d.n_act, d.N_tp), P, Q)) return;
@@ -421,75 +432,84 @@ __device__ void syrk_bf16_body(const StepDesc &d, int64_t tile)
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6), wr = wave >> 1, wc = wave & 1;
     TileMap m;
     tile_map<N_tp>(d, P, Q, wave, m);  // W offsets in BF16 elements: a 16 x 32 tile is 512
-    const unsigned short *Whl = (const unsigned short *)d.W + lane * 8, *Wll = (const unsigned short *)d.W2 + lane * 8;
-    const unsigned short *Phl = NW > 1 ? (const unsigned short *)d.P + lane * 8 : Whl;
-    const unsigned short *Pll = NW > 1 ? (const unsigned short *)d.P2 + lane * 8 : Wll;
     float *Rl = R + lane * 4;
+    typedef const unsigned short *bp;
+    const bp Wh0 = (bp)d.W + lane * 8, Wl0 = (bp)d.W2 + lane * 8;
+    const int64_t wslot = d.wslot;
+    auto whi = [&](int slot) -> bp { return Wh0 + slot * wslot; };
+    auto wlo = [&](int slot) -> bp { return Wl0 + slot * wslot; };
 
     floatx4 rt[16], acc[16];
 #pragma unroll
     for (int f = 0; f < 16; ++f) acc[f] = floatx4{0, 0, 0, 0};
     u32x4 st[2][4];  // [h][A hi, A lo, B hi, B lo]
+    auto stage = [&](bp hi, bp lo) {
 #pragma unroll
-    for (int h = 0; h < 2; ++h) {
-        st[h][0] = *reinterpret_cast<const u32x4 *>(Whl + m.wA[h]);
-        st[h][1] = *reinterpret_cast<const u32x4 *>(Wll + m.wA[h]);
-        st[h][2] = *reinterpret_cast<const u32x4 *>(Whl + m.wB[h]);
-        st[h][3] = *reinterpret_cast<const u32x4 *>(Wll + m.wB[h]);
-    }
-#pragma unroll
-    for (int f = 0; f < PER && f < 16; ++f) rt[f] = ld4(Rl + m.rblk[f]);
+        for (int h = 0; h < 2; ++h) {
+            st[h][0] = *reinterpret_cast<const u32x4 *>(hi + m.wA[h]);
+            st[h][1] = *reinterpret_cast<const u32x4 *>(lo + m.wA[h]);
+            st[h][2] = *reinterpret_cast<const u32x4 *>(hi + m.wB[h]);
+            st[h][3] = *reinterpret_cast<const u32x4 *>(lo + m.wB[h]);
+        }
+    };
+    stage(whi(0), wlo(0));
 #pragma unroll
     for (int h = 0; h < 2; ++h)
 #pragma unroll
         for (int k = 0; k < 4; ++k) lds[0][k][(wave + 4 * h) * 64 + lane] = st[h][k];
     __syncthreads();
+
+    // as in syrk_lds_body, per 32-wide slice
+    auto pass = [&](auto pref, bp chi, bp clo, bp nhi, bp nlo, int par) {
+        constexpr bool PREF = decltype(pref)::value;
 #pragma unroll
-    for (int q = 0; q < NS; ++q) {
-        const int buf = q & 1;
-        if (q + 1 < NS) {
-            const unsigned short *hi = (q + 1) < NB32 ? Whl : Phl, *lo = (q + 1) < NB32 ? Wll : Pll;
-            const int64_t o = (int64_t)((q + 1) % NB32) << 9;
-#pragma unroll
-            for (int h = 0; h < 2; ++h) {
-                st[h][0] = *reinterpret_cast<const u32x4 *>(hi + m.wA[h] + o);
-                st[h][1] = *reinterpret_cast<const u32x4 *>(lo + m.wA[h] + o);
-                st[h][2] = *reinterpret_cast<const u32x4 *>(hi + m.wB[h] + o);
-                st[h][3] = *reinterpret_cast<const u32x4 *>(lo + m.wB[h] + o);
+        for (int q = 0; q < NB32; ++q) {
+            const int buf = par ^ (q & 1);
+            const bool more = q + 1 < NB32 || nhi;
+            if (more) {
+                if (q + 1 < NB32)
+                    stage(chi + ((q + 1) << 9), clo + ((q + 1) << 9));
+                else
+                    stage(nhi, nlo);
             }
+            if (PREF) {
 #pragma unroll
-            for (int f = (q + 1) * PER; f < (q + 2) * PER && f < 16; ++f) rt[f] = ld4(Rl + m.rblk[f]);
-        }
-        if (m.any) {
-            u32x4 wh[4], wl[4];
-#pragma unroll
-            for (int c = 0; c < 4; ++c) {
-                wh[c] = lds[buf][2][(wc * 4 + c) * 64 + lane];
-                wl[c] = lds[buf][3][(wc * 4 + c) * 64 + lane];
+                for (int f = q * PER; f < (q + 1) * PER && f < 16; ++f) rt[f] = ld4(Rl + m.rblk[f]);
             }
-#pragma unroll
-            for (int b = 0; b < 4; ++b) {
-                const u32x4 ah = lds[buf][0][(wr * 4 + b) * 64 + lane];
-                const u32x4 al = lds[buf][1][(wr * 4 + b) * 64 + lane];
+            if (m.any) {
+                u32x4 wh[4], wl[4];
 #pragma unroll
                 for (int c = 0; c < 4; ++c) {
-                    acc[4 * b + c] = mfma_bf16(ah, wh[c], acc[4 * b + c]);
-                    acc[4 * b + c] = mfma_bf16(ah, wl[c], acc[4 * b + c]);
-                    acc[4 * b + c] = mfma_bf16(al, wh[c], acc[4 * b + c]);
+                    wh[c] = lds[buf][2][(wc * 4 + c) * 64 + lane];
+                    wl[c] = lds[buf][3][(wc * 4 + c) * 64 + lane];
+                }
+#pragma unroll
+                for (int b = 0; b < 4; ++b) {
+                    const u32x4 ah = lds[buf][0][(wr * 4 + b) * 64 + lane];
+                    const u32x4 al = lds[buf][1][(wr * 4 + b) * 64 + lane];
+#pragma unroll
+                    for (int c = 0; c < 4; ++c) {
+                        acc[4 * b + c] = mfma_bf16(ah, wh[c], acc[4 * b + c]);
+                        acc[4 * b + c] = mfma_bf16(ah, wl[c], acc[4 * b + c]);
+                        acc[4 * b + c] = mfma_bf16(al, wh[c], acc[4 * b + c]);
+                    }
                 }
             }
-        }
-        if (q + 1 < NS) {
+            if (more) {
 #pragma unroll
-            for (int h = 0; h < 2; ++h)
+                for (int h = 0; h < 2; ++h)
 #pragma unroll
-                for (int k = 0; k < 4; ++k) lds[buf ^ 1][k][(wave + 4 * h) * 64 + lane] = st[h][k];
+                    for (int k = 0; k < 4; ++k) lds[buf ^ 1][k][(wave + 4 * h) * 64 + lane] = st[h][k];
+            }
+            __syncthreads();
         }
-        __syncthreads();
-    }
+    };
+    const int nw = d.nw;
+    for (int slot = 0; slot + 1 < nw; ++slot)
+        pass(BoolC<false>(), whi(slot), wlo(slot), whi(slot + 1), wlo(slot + 1), (slot * NB32) & 1);
+    pass(BoolC<true>(), whi(nw - 1), wlo(nw - 1), nullptr, nullptr, ((nw - 1) * NB32) & 1);
+
     if (!m.any) return;
-#pragma unroll
-    for (int f = NS * PER; f < 16; ++f) rt[f] = ld4(Rl + m.rblk[f]);
 #pragma unroll
     for (int f = 0; f < 16; ++f)
         if (m.ok[f]) st4(Rl + m.rblk[f], rt[f] - acc[f]);
@@ -533,15 +553,15 @@ __global__ void __launch_bounds__(256) syrk_direct_batched(const StepDesc *__res
     syrk_direct_body<T>(d, item - d.item0);
 }
 
-template <typename T, int NB, int NW>
+template <typename T, int NB>
 __global__ void __launch_bounds__(256, 2) syrk_lds_kernel(StepDesc d, int64_t per_xcd)
 {
     const int64_t tile = xcd_item(blockIdx.x, per_xcd);
     if (tile >= d.nitems) return;
-    syrk_lds_body<T, NB, NW>(d, tile);
+    syrk_lds_body<T, NB>(d, tile);
 }
 
-template <typename T, int NB, int NW>
+template <typename T, int NB>
 __global__ void __launch_bounds__(256, 2) syrk_lds_batched(const StepDesc *__restrict__ ds, int n, int64_t total,
                                                            int64_t per_xcd)
 {
@@ -550,18 +570,18 @@ __global__ void __launch_bounds__(256, 2) syrk_lds_batched(const StepDesc *__res
     const int i = find_instance(ds, n, item);
     if (i < 0) return;
     const StepDesc d = ds[i];
-    syrk_lds_body<T, NB, NW>(d, item - d.item0);
+    syrk_lds_body<T, NB>(d, item - d.item0);
 }
 
-template <int NB32, int NW>
+template <int NB32>
 __global__ void __launch_bounds__(256, 2) syrk_bf16_kernel(StepDesc d, int64_t per_xcd)
 {
     const int64_t tile = xcd_item(blockIdx.x, per_xcd);
     if (tile >= d.nitems) return;
-    syrk_bf16_body<NB32, NW>(d, tile);
+    syrk_bf16_body<NB32>(d, tile);
 }
 
-template <int NB32, int NW>
+template <int NB32>
 __global__ void __launch_bounds__(256, 2) syrk_bf16_batched(const StepDesc *__restrict__ ds, int n, int64_t total,
                                                             int64_t per_xcd)
 {
@@ -570,7 +590,7 @@ __global__ void __launch_bounds__(256, 2) syrk_bf16_batched(const StepDesc *__re
     const int i = find_instance(ds, n, item);
     if (i < 0) return;
     const StepDesc d = ds[i];
-    syrk_bf16_body<NB32, NW>(d, item - d.item0);
+    syrk_bf16_body<NB32>(d, item - d.item0);
 }
 
 template <typename TW>
@@ -630,11 +650,11 @@ static hipError_t launch_vcorr_t(const StepDesc *descs, const StepDesc &d, int n
     return hipGetLastError();
 }
 
-// One work-group per 16 x 16 sub-block of V (single: d.nitems ignored, (N_tp / 16)^2 groups).
+// One work-group per 16 x 16 sub-block of each V_h (single: d.nitems ignored, nheld (N_tp / 16)^2 groups).
 hipError_t launch_vcorr(const StepDesc &d, int wtype, hipStream_t s)
 {
-    if (!d.P || !d.V) return hipErrorInvalidValue;
-    const int64_t total = (int64_t)(d.N_tp / 16) * (d.N_tp / 16);
+    if (d.nheld < 1 || d.nheld >= MAX_DELAY || !d.V) return hipErrorInvalidValue;
+    const int64_t total = (int64_t)d.nheld * (d.N_tp / 16) * (d.N_tp / 16);
     if (wtype == W_F64) return launch_vcorr_t<double>(nullptr, d, 1, total, s);
     if (wtype == W_F32) return launch_vcorr_t<float>(nullptr, d, 1, total, s);
     if (wtype == W_BF16X3) return launch_vcorr_t<unsigned short>(nullptr, d, 1, total, s);
@@ -652,47 +672,37 @@ hipError_t launch_vcorr_batched(const StepDesc *descs, int n, int64_t total, int
 }
 
 // Single (descs == nullptr: d by value) or batched downdate launch over `total` tiles.
-// nw = 2 (a held W applied with the new one) needs the LDS variant.
-template <typename T, int NW>
-static hipError_t launch_syrk_lds(const StepDesc *descs, const StepDesc &d, int n, int64_t total, int nb,
-                                  hipStream_t s)
-{
-    const int64_t per_xcd = (total + 7) / 8;
-    const dim3 grid((unsigned)(per_xcd * 8)), block(256);
-    switch (nb) {
-#define OED_SYRK_CASE(NBV)                                                                                    \
-    case NBV:                                                                                                 \
-        if (descs)                                                                                            \
-            hipLaunchKernelGGL((syrk_lds_batched<T, NBV, NW>), grid, block, 0, s, descs, n, total, per_xcd);  \
-        else                                                                                                  \
-            hipLaunchKernelGGL((syrk_lds_kernel<T, NBV, NW>), grid, block, 0, s, d, per_xcd);                 \
-        break;
-        OED_SYRK_CASE(1)
-        OED_SYRK_CASE(2)
-        OED_SYRK_CASE(3)
-        OED_SYRK_CASE(4)
-        OED_SYRK_CASE(5)
-        OED_SYRK_CASE(6)
-        OED_SYRK_CASE(7)
-        OED_SYRK_CASE(8)
-#undef OED_SYRK_CASE
-    default:
-        return hipErrorInvalidValue;
-    }
-    return hipGetLastError();
-}
-
+// nw > 1 (held W applied with the new one) needs the LDS variant.
 template <typename T>
 static hipError_t launch_syrk_t(const StepDesc *descs, const StepDesc &d, int n, int64_t total, int N_tp, int nw,
                                 int variant, hipStream_t s)
 {
-    if (N_tp < 16 || N_tp % 16 != 0 || nw < 1 || nw > 2) return hipErrorInvalidValue;
+    if (N_tp < 16 || N_tp % 16 != 0 || nw < 1 || nw > MAX_DELAY) return hipErrorInvalidValue;
     const int nb = N_tp / 16;
-    if (variant == SYRK_LDS && nb <= 8)
-        return nw == 2 ? launch_syrk_lds<T, 2>(descs, d, n, total, nb, s) : launch_syrk_lds<T, 1>(descs, d, n, total, nb, s);
-    if (nw != 1) return hipErrorInvalidValue;
     const int64_t per_xcd = (total + 7) / 8;
     const dim3 grid((unsigned)(per_xcd * 8)), block(256);
+    if (variant == SYRK_LDS && nb <= 8) {
+        switch (nb) {
+#define OED_SYRK_CASE(NBV)                                                                                    \
+    case NBV:                                                                                                 \
+        if (descs)                                                                                            \
+            hipLaunchKernelGGL((syrk_lds_batched<T, NBV>), grid, block, 0, s, descs, n, total, per_xcd);      \
+        else                                                                                                  \
+            hipLaunchKernelGGL((syrk_lds_kernel<T, NBV>), grid, block, 0, s, d, per_xcd);                     \
+        break;
+            OED_SYRK_CASE(1)
+            OED_SYRK_CASE(2)
+            OED_SYRK_CASE(3)
+            OED_SYRK_CASE(4)
+            OED_SYRK_CASE(5)
+            OED_SYRK_CASE(6)
+            OED_SYRK_CASE(7)
+            OED_SYRK_CASE(8)
+#undef OED_SYRK_CASE
+        }
+        return hipGetLastError();
+    }
+    if (nw != 1) return hipErrorInvalidValue;
     if (descs)
         hipLaunchKernelGGL(syrk_direct_batched<T>, grid, block, 0, s, descs, n, total, per_xcd);
     else
@@ -701,44 +711,33 @@ static hipError_t launch_syrk_t(const StepDesc *descs, const StepDesc &d, int n,
 }
 
 // BF16 split-product downdate (single or batched).
-template <int NW>
-static hipError_t launch_syrk_bf16_t(const StepDesc *descs, const StepDesc &d, int n, int64_t total, int N_tp,
-                                     hipStream_t s)
+static hipError_t launch_syrk_bf16(const StepDesc *descs, const StepDesc &d, int n, int64_t total, int N_tp, int nw,
+                                   hipStream_t s)
 {
+    if (N_tp < 32 || N_tp % 32 != 0 || N_tp > 128 || nw < 1 || nw > MAX_DELAY) return hipErrorInvalidValue;
     const int64_t per_xcd = (total + 7) / 8;
     const dim3 grid((unsigned)(per_xcd * 8)), block(256);
     switch (N_tp / 32) {
 #define OED_BF16_CASE(V)                                                                                     \
     case V:                                                                                                  \
         if (descs)                                                                                           \
-            hipLaunchKernelGGL((syrk_bf16_batched<V, NW>), grid, block, 0, s, descs, n, total, per_xcd);     \
+            hipLaunchKernelGGL((syrk_bf16_batched<V>), grid, block, 0, s, descs, n, total, per_xcd);         \
         else                                                                                                 \
-            hipLaunchKernelGGL((syrk_bf16_kernel<V, NW>), grid, block, 0, s, d, per_xcd);                    \
+            hipLaunchKernelGGL((syrk_bf16_kernel<V>), grid, block, 0, s, d, per_xcd);                        \
         break;
         OED_BF16_CASE(1)
         OED_BF16_CASE(2)
         OED_BF16_CASE(3)
         OED_BF16_CASE(4)
 #undef OED_BF16_CASE
-    default:
-        return hipErrorInvalidValue;
     }
     return hipGetLastError();
-}
-
-static hipError_t launch_syrk_bf16(const StepDesc *descs, const StepDesc &d, int n, int64_t total, int N_tp, int nw,
-                                   hipStream_t s)
-{
-    if (N_tp < 32 || N_tp % 32 != 0 || N_tp > 128) return hipErrorInvalidValue;
-    if (nw == 1) return launch_syrk_bf16_t<1>(descs, d, n, total, N_tp, s);
-    if (nw == 2) return launch_syrk_bf16_t<2>(descs, d, n, total, N_tp, s);
-    return hipErrorInvalidValue;
 }
 
 hipError_t launch_syrk(const StepDesc &d, int rtype, int wtype, int variant, hipStream_t s)
 {
     if (d.n_act <= 0 || d.nitems <= 0) return hipSuccess;
-    if (d.nw == 2 && !d.P) return hipErrorInvalidValue;
+    if (d.nw > 1 && d.wslot <= 0) return hipErrorInvalidValue;
     if (rtype == R_F32 && wtype == W_BF16X3) return launch_syrk_bf16(nullptr, d, 1, d.nitems, d.N_tp, d.nw, s);
     if (rtype == R_F64 && wtype == W_F64) return launch_syrk_t<double>(nullptr, d, 1, d.nitems, d.N_tp, d.nw, variant, s);
     if (rtype == R_F32 && wtype == W_F32) return launch_syrk_t<float>(nullptr, d, 1, d.nitems, d.N_tp, d.nw, variant, s);

@@ -20,6 +20,7 @@ OED_OK, OED_E_ARG, OED_E_NOT_SPD, OED_E_OOM, OED_E_HIP, OED_E_STATE, OED_E_UNSUP
 OED_F64, OED_F32 = 0, 1
 PRECISIONS = {"fp64": 0, "mixed_f32": 1, "mixed_bf16x3": 2}
 OED_FLAG_PROFILE = 1
+OED_FLAG_AUTOTUNE = 4
 KERNELS = ("gain", "pick", "trsm", "syrk", "pack")
 
 
@@ -41,7 +42,7 @@ class oed_instance(ctypes.Structure):
 
 
 OED_BATCH_NO_GRAPH = 2
-OED_BATCH_DELAY1 = 4
+OED_BATCH_AUTOTUNE = 0x10
 
 
 class OedError(RuntimeError):
@@ -74,6 +75,7 @@ def library() -> ctypes.CDLL:
     L.oed_picks.argtypes = [vp, ip, dp, ip]
     L.oed_get_profile.argtypes = [vp, ctypes.POINTER(oed_profile), ctypes.c_int32]
     L.oed_device_bytes.argtypes = [vp, ctypes.POINTER(ctypes.c_int64)]
+    L.oed_get_config.argtypes = [vp, ip, ip, dp]
     L.oed_destroy.argtypes = [vp]
     L.oed_last_error.argtypes = [vp]
     L.oed_last_error.restype = ctypes.c_char_p
@@ -85,6 +87,7 @@ def library() -> ctypes.CDLL:
     L.oed_batch_reset.argtypes = [vp, ctypes.POINTER(oed_instance), ctypes.c_int32]
     L.oed_batch_stats.argtypes = [vp, dp, dp, dp]
     L.oed_batch_destroy.argtypes = [vp]
+    L.oed_batch_get_config.argtypes = [vp, ip, dp]
     L.oed_batch_last_error.argtypes = [vp]
     L.oed_batch_last_error.restype = ctypes.c_char_p
     for name in ("oed_create", "oed_reset", "oed_greedy", "oed_force", "oed_scores", "oed_schur_block", "oed_picks",
@@ -96,9 +99,10 @@ def library() -> ctypes.CDLL:
 
 
 EXPORTED = ("oed_options_init", "oed_create", "oed_reset", "oed_greedy", "oed_force", "oed_scores",
-            "oed_schur_block", "oed_picks", "oed_get_profile", "oed_device_bytes", "oed_destroy", "oed_last_error",
+            "oed_schur_block", "oed_picks", "oed_get_profile", "oed_device_bytes", "oed_get_config", "oed_destroy",
+            "oed_last_error",
             "oed_status_string", "oed_batch_create", "oed_batch_run", "oed_batch_reset", "oed_batch_stats",
-            "oed_batch_destroy", "oed_batch_last_error")
+            "oed_batch_destroy", "oed_batch_last_error", "oed_batch_get_config")
 
 
 def _status_name(s):
@@ -129,9 +133,10 @@ def _stream_handle(stream):
 
 
 # ------------------------------------------------------------------ functions with the C names
-def oed_create(K, N_s, N_t, sigma2, precision="fp64", candidates=None, profile=False, stream=None, delay=0):
+def oed_create(K, N_s, N_t, sigma2, precision="fp64", candidates=None, profile=False, stream=None, delay=0,
+               autotune=False):
     """Create a handle for the device tensor K (2-D, float64/float32, row-major, lower triangle read).
-    delay: downdate delay depth (0 automatic, 1, 2)."""
+    delay: downdate delay depth (0 automatic, 1..4); autotune: with delay 0, time the choices."""
     import torch
     L = library()
     if not isinstance(K, torch.Tensor) or not K.is_cuda or K.dim() != 2 or K.stride(1) != 1:
@@ -144,7 +149,7 @@ def oed_create(K, N_s, N_t, sigma2, precision="fp64", candidates=None, profile=F
     opt = oed_options()
     L.oed_options_init(ctypes.byref(opt))
     opt.precision = PRECISIONS[precision]
-    opt.flags = OED_FLAG_PROFILE if profile else 0
+    opt.flags = (OED_FLAG_PROFILE if profile else 0) | (OED_FLAG_AUTOTUNE if autotune else 0)
     opt.delay = int(delay)
     cand = None
     if candidates is not None:
@@ -212,6 +217,14 @@ def oed_device_bytes(h):
     return b.value
 
 
+def oed_get_config(h):
+    """(delay, syrk_variant, autotuner per-pick ms for delay 1..4)."""
+    dl, var = ctypes.c_int32(), ctypes.c_int32()
+    ms = np.zeros(4)
+    _check(h, library().oed_get_config(h, ctypes.byref(dl), ctypes.byref(var), _dp(ms)))
+    return dl.value, var.value, ms
+
+
 def oed_destroy(h):
     if h:
         library().oed_destroy(h)
@@ -239,11 +252,11 @@ def _bcheck(b, st):
         raise OedError(st, msg)
 
 
-def oed_batch_create(items, precision="fp64", profile=False, graph=True, stream=None, delay=2):
+def oed_batch_create(items, precision="fp64", profile=False, graph=True, stream=None, delay=0, autotune=False):
     arr = _instances(items)
     b = ctypes.c_void_p()
-    flags = ((OED_FLAG_PROFILE if profile else 0) | (0 if graph else OED_BATCH_NO_GRAPH) |
-             (OED_BATCH_DELAY1 if delay == 1 else 0))
+    flags = ((OED_FLAG_PROFILE if profile else 0) | (0 if graph else OED_BATCH_NO_GRAPH) | (int(delay) << 8) |
+             (OED_BATCH_AUTOTUNE if autotune else 0))
     st = library().oed_batch_create(ctypes.byref(b), arr, len(items), PRECISIONS[precision], _stream_handle(stream),
                                     flags)
     _bcheck(None, st)
@@ -276,6 +289,14 @@ def oed_batch_stats(b):
     return {"run_ms": ms.value, "syrk_flops": fl.value, "syrk_bytes": by.value}
 
 
+def oed_batch_get_config(b):
+    """(delay, autotuner run ms for delay 1..4)."""
+    dl = ctypes.c_int32()
+    ms = np.zeros(4)
+    _bcheck(b, library().oed_batch_get_config(b, ctypes.byref(dl), _dp(ms)))
+    return dl.value, ms
+
+
 def oed_batch_destroy(b):
     if b:
         library().oed_batch_destroy(b)
@@ -284,15 +305,18 @@ def oed_batch_destroy(b):
 class BatchSelector:
     """Owns one batch.  ``BatchSelector([(K, N_s, N_t, sigma2, B), ...]).run()`` -> [(idx, gain, status)]."""
 
-    def __init__(self, items, precision="fp64", profile=False, graph=True, stream=None, delay=2):
+    def __init__(self, items, precision="fp64", profile=False, graph=True, stream=None, delay=0, autotune=False):
         self.budgets = [int(it[4]) for it in items]
-        self.b = oed_batch_create(items, precision, profile, graph, stream, delay)
+        self.b = oed_batch_create(items, precision, profile, graph, stream, delay, autotune)
 
     def run(self, check=True):
         return oed_batch_run(self.b, self.budgets, check)[0]
 
     def reset(self, items):
         oed_batch_reset(self.b, items)
+
+    def config(self):
+        return oed_batch_get_config(self.b)
 
     def stats(self):
         return oed_batch_stats(self.b)
@@ -320,9 +344,9 @@ class Selector:
     """Owns one handle.  ``Selector(K, N_s, N_t, sigma2).greedy(B)`` -> (indices, gains)."""
 
     def __init__(self, K, N_s, N_t, sigma2, precision="fp64", candidates=None, profile=False, stream=None,
-                 delay=0):
+                 delay=0, autotune=False):
         self.N_s, self.N_t = int(N_s), int(N_t)
-        self.h = oed_create(K, N_s, N_t, sigma2, precision, candidates, profile, stream, delay)
+        self.h = oed_create(K, N_s, N_t, sigma2, precision, candidates, profile, stream, delay, autotune)
 
     def greedy(self, budget):
         idx, gain, _ = oed_greedy(self.h, budget)
@@ -351,6 +375,9 @@ class Selector:
 
     def device_bytes(self):
         return oed_device_bytes(self.h)
+
+    def config(self):
+        return oed_get_config(self.h)
 
     def close(self):
         if self.h:

@@ -34,7 +34,7 @@ def items(insts, dtype=torch.float64):
     return [(Kd.to(dtype), N_s, N_t, s2, B) for (_, Kd, N_s, N_t, s2, B) in insts]
 
 
-@pytest.mark.parametrize("delay", [1, 2])
+@pytest.mark.parametrize("delay", [1, 2, 4])
 @pytest.mark.parametrize("prec", ["fp64", "mixed_f32", "mixed_bf16x3"])
 def test_batch_equals_single_and_oracle(insts, prec, delay):
     from paper_2604_08812_amd import BatchSelector, Selector
@@ -83,3 +83,17 @@ def test_batch_non_pd_instance_stops_alone(insts):
     assert res[0][2] == 0 and res[1][2] == 0
     idx, gain, st = res[2]
     assert st == 2 and len(idx) == N_s - 1 and 3 not in set(idx.tolist())
+
+
+def test_batch_autotune(insts):
+    from paper_2604_08812_amd import BatchSelector
+    its = items(insts)
+    with BatchSelector(its, precision="mixed_f32", autotune=True) as t:
+        delay, ms = t.config()
+        res = t.run()
+    assert np.all(ms > 0) and delay == int(np.argmin(ms)) + 1
+    with BatchSelector(its, precision="mixed_f32", delay=delay) as f:
+        ref = f.run()
+    for (i0, g0, s0), (i1, g1, s1) in zip(ref, res):
+        assert list(i0) == list(i1) and s0 == s1 == 0
+        np.testing.assert_array_equal(g0, g1)

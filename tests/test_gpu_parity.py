@@ -51,14 +51,14 @@ def supported(prec, N_t):
     return prec != "mixed_bf16x3" or N_t <= 128
 
 
-@pytest.mark.parametrize("delay", [1, 2])
+@pytest.mark.parametrize("delay", [1, 2, 4])
 @pytest.mark.parametrize("prec", PRECS)
 @pytest.mark.parametrize("case", CASES, ids=lambda c: "x".join(map(str, c[:2])))
 def test_greedy_matches_oracle(case, prec, delay):
     N_s, N_t, n_m, seed, B = case
     if not supported(prec, N_t):
         pytest.skip("N_t > 128 has no BF16 split-product downdate")
-    if delay == 2 and N_t > 128:
+    if delay > 1 and N_t > 128:
         pytest.skip("the delayed downdate needs the register factorisations (N_t <= 128)")
     print(f"case N_s={N_s} N_t={N_t} seed={seed} B={B} prec={prec} delay={delay}", flush=True)
     K, Kd, s2 = instance(N_s, N_t, n_m, seed)
@@ -228,17 +228,52 @@ def test_errors_and_states():
         selector(Kd, N_s, N_t, s2, candidates=[1, 1, 2])
 
 
+@pytest.mark.parametrize("delay", [2, 3, 4])
 @pytest.mark.parametrize("prec", PRECS)
-def test_delay_two_matches_delay_one(prec):
-    """Holding every other block column changes the rounding only: same picks, gains equal to
-    the precision's tolerance (FP64: 1e-12)."""
+def test_delayed_downdate_matches_delay_one(prec, delay):
+    """Holding block columns back changes the rounding only: same picks, gains equal to the
+    precision's tolerance (FP64: 1e-12).  The split calls and the forced pick start with block
+    columns held; the Schur-block query applies them."""
     N_s, N_t = 48, 64
-    _, Kd, s2 = instance(N_s, N_t, 4000, 23)
+    K, Kd, s2 = instance(N_s, N_t, 4000, 23)
     with selector(Kd, N_s, N_t, s2, precision=prec, delay=1) as a, \
-            selector(Kd, N_s, N_t, s2, precision=prec, delay=2) as b:
+            selector(Kd, N_s, N_t, s2, precision=prec, delay=delay) as b:
         i1, g1 = a.greedy(20)
-        i2a, g2a = b.greedy(7)      # odd split: the next call starts with a block column held
-        i2b, g2b = b.greedy(13)
-    assert list(i1) == list(np.r_[i2a, i2b])
+        i2a, g2a = b.greedy(7)
+        i2b, g2b = b.greedy(5)
+        gf = b.force(int(i1[12]))
+        blk = b.schur_block(int(i1[13]), int(i1[14]))
+        i2c, g2c = b.greedy(7)
+    assert list(i1) == list(np.r_[i2a, i2b, [i1[12]], i2c])
     tol = 1e-12 if prec == "fp64" else RTOL[prec]
-    assert np.all(rel_err(np.r_[g2a, g2b], g1) <= tol)
+    assert np.all(rel_err(np.r_[g2a, g2b, [gf], g2c], g1) <= tol)
+    A = list(i1[:13])
+    rest = [j for j in range(N_s) if j not in A]
+    S = oracle.schur_complement(K, N_t, A, rest)
+    p, q = rest.index(int(i1[13])), rest.index(int(i1[14]))
+    ref = S[p * N_t:(p + 1) * N_t, q * N_t:(q + 1) * N_t]
+    stol = {"fp64": 1e-11, "mixed_f32": 2e-5, "mixed_bf16x3": 5e-5}[prec]
+    assert np.abs(blk - ref).max() <= stol * np.abs(S).max()
+
+
+@pytest.mark.parametrize("prec", PRECS)
+def test_autotuned_handle_selects_like_a_fixed_one(prec):
+    """The autotuner times kernels on the packed working copy with zero W: it must leave R as
+    packed, so the tuned handle gives bitwise the picks and gains of a handle created with the
+    delay it chose; the choice is the minimum of its own estimates and is cached."""
+    N_s, N_t = 70, 64
+    K, Kd, s2 = instance(N_s, N_t, 5000, 29)
+    with selector(Kd, N_s, N_t, s2, precision=prec, autotune=True) as t:
+        delay, variant, ms = t.config()
+        it, gt = t.greedy(12)
+    assert 1 <= delay <= 4 and variant in (0, 1)
+    assert np.all(ms > 0) and delay == int(np.argmin(ms)) + 1
+    with selector(Kd, N_s, N_t, s2, precision=prec, delay=delay) as f:
+        i_f, g_f = f.greedy(12)
+    assert list(it) == list(i_f)
+    np.testing.assert_array_equal(gt, g_f)
+    check_trajectory(K, N_s, N_t, s2, it, gt, RTOL[prec])
+    with selector(Kd, N_s, N_t, s2, precision=prec, autotune=True) as t2:
+        d2, v2, ms2 = t2.config()
+    assert (d2, v2) == (delay, variant)
+    np.testing.assert_array_equal(ms2, ms)
