@@ -47,6 +47,7 @@ def parse():
     ap.add_argument("--fp64-steps", type=int, default=1)
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-bf16x3", action="store_true")
+    ap.add_argument("--no-left", action="store_true", help="skip the left-looking legs")
     ap.add_argument("--no-gaps", action="store_true", help="skip the per-step top-two gap scan (FP64)")
     ap.add_argument("--delay", type=int, default=0, help="downdate delay depth (0: the library's choice)")
     ap.add_argument("--no-autotune", action="store_true",
@@ -396,6 +397,30 @@ def main():
             fd = result["mixed_bf16x3"]["vs_fp64"]["first_divergence_step"]
             if fd is not None and not args.no_gaps and fd < len(per):
                 result["mixed_bf16x3"]["vs_fp64"]["fp64_top_two_gap_at_divergence"] = per[fd]
+
+    # ---- left-looking (the order of Algorithm 1) beside it, same K
+    if not args.no_left and spec.N_t <= 128:
+        for lp in ("mixed_f32", "fp64"):
+            if lp != prec and lp != "fp64":
+                continue
+            sell = Selector(K, spec.N_s, spec.N_t, s2, precision=lp, profile=True, method="left", max_budget=budget)
+            timed_selections(sell, K, budget, 1)
+            sell.profile(reset=True)
+            nst = args.steps if lp == prec else args.fp64_steps
+            msl, (idxl, gainl) = timed_selections(sell, K, budget, nst)
+            pl = sell.profile(reset=True)
+            sell.close()
+            log(f"left-looking {lp}: {msl:.1f} ms per selection")
+            tfl = pl["syrk_flops"] / (pl["ms"]["syrk"] * 1e-3) / 1e12 if pl["ms"]["syrk"] > 0 else 0.0
+            leg = {"value": round(budget / (msl * 1e-3), 3), "unit": "greedy steps/s", "ms_per_step": round(msl, 3),
+                   "column_kernel": {"kernel": f"column_kernel<{'float' if lp != 'fp64' else 'double'}>",
+                                     "algorithmic_tflops": round(tfl, 3), "peak": PEAK_TFLOPS[lp],
+                                     "frac": round(tfl / PEAK_TFLOPS[lp], 4),
+                                     "algorithmic_flops_per_selection": pl["syrk_flops"] / nst},
+                   "kernel_ms_per_step": {k: round(v / nst, 3) for k, v in pl["ms"].items()}}
+            ref = (idx64, gain64) if "fp64" in result else (idx, gain)
+            leg["vs_fp64_right_looking" if "fp64" in result else "vs_headline"] = compare_picks(idxl, gainl, *ref)
+            result["left_looking_" + lp] = leg
 
     # ---- CPU oracle baseline on a bounded sample of the same K
     if not args.no_cpu_baseline:

@@ -101,8 +101,24 @@ typedef struct oed_options {
                                    1 = subtract every pick's W W^T at the next step; 0 = automatic
                                    (2 for N_t <= 128, else 1).  p > 1 with N_t > 128:
                                    OED_E_UNSUPPORTED */
-    int32_t reserved[6];        /* must be 0 */
+    int32_t method;             /* OED_METHOD_RIGHT_LOOKING (default) or OED_METHOD_LEFT_LOOKING */
+    int32_t max_budget;         /* left-looking: most picks the handle will make (the W history
+                                   is allocated for them); 0 = all candidates */
+    int32_t reserved[4];        /* must be 0 */
 } oed_options;
+
+/*
+ * oed_options.method.
+ *  RIGHT_LOOKING : R is the Schur complement of all remaining candidates; every pick subtracts
+ *                  its block column's outer product from all of R (the downdate).
+ *  LEFT_LOOKING  : the order of Algorithm 1 (Sec. III-D): R keeps K off the diagonal; every
+ *                  pick forms only its own block column, K_is - sum over the earlier picks'
+ *                  block columns (W history), and updates the diagonal blocks.  About 1/3 of
+ *                  the flops of RIGHT_LOOKING at 600 x 128, budget 175.  FP64 and MIXED_F32,
+ *                  N_t <= 128 (else OED_E_UNSUPPORTED); the delay option does not apply.
+ */
+#define OED_METHOD_RIGHT_LOOKING 0
+#define OED_METHOD_LEFT_LOOKING 1
 
 /* Fill *opt with the defaults (FP64, no flags, all sensors). */
 OED_API void oed_options_init(oed_options *opt);

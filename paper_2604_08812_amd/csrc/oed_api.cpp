@@ -42,6 +42,11 @@ struct oed_ctx {
     int syrk_variant = SYRK_LDS;
     int delay = 1;  // > 1: up to delay - 1 block columns held and subtracted with the next one
     double tuned_ms[MAX_DELAY] = {0};  // autotuner: estimated time per pick for delay 1..MAX_DELAY
+    // left-looking: R keeps K off the diagonal; W slot k holds pick k's block column
+    bool left = false;
+    int max_budget = 0;
+    bool diag_current = true;  // the diagonal blocks include every formed block column
+    void *C = nullptr;         // column partial sums (LEFT_SPLITS x N_c blocks, R's type)
     uint32_t flags = 0;
     hipStream_t stream = nullptr;
     int device = 0;
@@ -140,7 +145,7 @@ void collect_profile(oed_ctx *h)
 
 void free_all(oed_ctx *h)
 {
-    void *ptrs[] = {h->R, h->W, h->W2, h->V, h->Linv, h->gains, h->pick_gain, h->scratch_gain, h->scratch_pick,
+    void *ptrs[] = {h->R, h->W, h->W2, h->V, h->C, h->Linv, h->gains, h->pick_gain, h->scratch_gain, h->scratch_pick,
                     h->act[0], h->act[1], h->picks, h->state, h->dcmap};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
@@ -163,6 +168,7 @@ oed_status load_R(oed_ctx *h, const void *K)
     h->k = 0;
     h->pending = false;
     h->nheld = 0;
+    h->diag_current = true;
     h->poisoned = false;
     h->h_picks.clear();
     h->h_gains.clear();
@@ -217,8 +223,50 @@ oed_status enqueue_syrk(oed_ctx *h, StepDesc d)
 // held (W slots 0 .. nheld-1; the gain and pick kernels correct for them exactly) until p of
 // them are formed, then subtracted in one downdate of inner dimension p N_t: 1/p of the R
 // traffic per pick.  `full` leaves R current.
+// Element size of W.
+size_t welem(const oed_ctx *h) { return h->wtype == W_F64 ? 8 : h->wtype == W_F32 ? 4 : 2; }
+
+constexpr int LEFT_SPLITS = 4;
+
+// Left-looking: form the block column of the last pick s (pick k-1) from K and the k-1 earlier
+// block columns: the partial sums sum_h W_h,i W_h,s^T (column kernel, LEFT_SPLITS parts), then
+// W_i = (K_is - sums) L_s^-T into W slot k-1.  The diagonal blocks get this column at the next
+// gain launch.
+oed_status advance_left(oed_ctx *h)
+{
+    if (!h->pending) return OED_OK;
+    h->pending = false;
+    if (h->n_act == 0) return OED_OK;
+    const int hist = h->k - 1;
+    const int64_t bs = (int64_t)h->N_tp * h->N_tp;
+    StepDesc d = desc(h);
+    d.nheld = 0;
+    d.C = h->C;
+    d.cstride = (int64_t)h->N_c * bs;
+    d.nsplit = std::min(LEFT_SPLITS, hist);
+    if (hist > 0) {
+        d.nw = hist;
+        d.nitems = (int64_t)d.nsplit * syrk_tile_rows(h->n_act, h->N_tp);
+        {
+            Prof pr(h, OED_K_SYRK);
+            HIPCHK(h, launch_column(d, h->rtype, h->stream));
+        }
+        const double n = (double)h->n_act * h->N_t;
+        h->syrk_flops += 2.0 * n * h->N_t * hist * h->N_t;
+        h->syrk_bytes += (double)relem(h) * (n * hist * h->N_t + (double)hist * h->N_t * h->N_t + d.nsplit * n * h->N_t);
+    }
+    d.W = (char *)h->W + (size_t)(hist * h->wslot) * welem(h);  // output: slot k-1
+    {
+        Prof pr(h, OED_K_TRSM);
+        HIPCHK(h, launch_trsm(d, h->rtype, h->wtype, h->stream));
+    }
+    h->diag_current = false;
+    return OED_OK;
+}
+
 oed_status advance(oed_ctx *h, bool full)
 {
+    if (h->left) return advance_left(h);
     if (h->pending) {
         h->pending = false;
         if (h->n_act == 0) {
@@ -375,6 +423,13 @@ oed_status enqueue_gains(oed_ctx *h)
 {
     StepDesc d = desc(h);
     d.scratch = h->scratch_gain;
+    if (h->left && !h->diag_current) {
+        // apply the newest block column (slot k-1) to the diagonal blocks, in place
+        d.W = (char *)h->W + (size_t)((h->k - 1) * h->wslot) * welem(h);
+        d.nheld = 1;
+        d.wb = 1;
+        h->diag_current = true;
+    }
     Prof pr(h, OED_K_GAIN);
     HIPCHK(h, launch_gain(d, h->rtype, h->wtype, h->stream));
     return OED_OK;
@@ -475,6 +530,10 @@ oed_status oed_create(oed_ctx **out, const void *K, int32_t dtype, int64_t ld, i
         return OED_E_ARG;
     if (o.precision == OED_PREC_MIXED_BF16X3 && N_t > 128) return OED_E_UNSUPPORTED;
     if (o.delay < 0 || o.delay > MAX_DELAY) return OED_E_ARG;
+    if (o.method != OED_METHOD_RIGHT_LOOKING && o.method != OED_METHOD_LEFT_LOOKING) return OED_E_ARG;
+    if (o.max_budget < 0 || o.max_budget > N_s) return OED_E_ARG;
+    if (o.method == OED_METHOD_LEFT_LOOKING && (N_t > REGS_MAX_NT || o.precision == OED_PREC_MIXED_BF16X3))
+        return OED_E_UNSUPPORTED;
     if (o.delay > 1 && N_t > REGS_MAX_NT) return OED_E_UNSUPPORTED;
     for (int r : o.reserved)
         if (r != 0) return OED_E_ARG;
@@ -496,7 +555,9 @@ oed_status oed_create(oed_ctx **out, const void *K, int32_t dtype, int64_t ld, i
     // delay 0 (automatic): hold block columns whenever the register factorisations and the LDS
     // downdate serve the block size
     h->delay = o.delay == 0 ? (N_t <= REGS_MAX_NT ? MAX_DELAY : 1) : o.delay;
-    const bool tune = o.delay == 0 && (o.flags & OED_FLAG_AUTOTUNE) && N_t <= REGS_MAX_NT;
+    h->left = o.method == OED_METHOD_LEFT_LOOKING;
+    if (h->left) h->delay = 1;
+    const bool tune = !h->left && o.delay == 0 && (o.flags & OED_FLAG_AUTOTUNE) && N_t <= REGS_MAX_NT;
     h->stream = (hipStream_t)stream;
     h->lmap.assign(N_s, -1);
     if (o.candidates) {
@@ -516,6 +577,7 @@ oed_status oed_create(oed_ctx **out, const void *K, int32_t dtype, int64_t ld, i
         for (int q = 0; q < N_s; ++q) h->cmap[q] = q;
     }
     h->N_c = (int)h->cmap.size();
+    h->max_budget = (o.max_budget == 0 || o.max_budget > h->N_c) ? h->N_c : o.max_budget;
     for (int q = 0; q < h->N_c; ++q) h->lmap[h->cmap[q]] = q;
 
     oed_status st = OED_OK;
@@ -526,7 +588,8 @@ oed_status oed_create(oed_ctx **out, const void *K, int32_t dtype, int64_t ld, i
         HIPCHK(h, dmalloc(h, &h->R, (size_t)(nblk * bs) * relem(h)));
         const size_t we = h->wtype == W_F64 ? 8 : h->wtype == W_F32 ? 4 : 2;
         h->wslot = h->N_c * bs;
-        const int slots = tune ? MAX_DELAY : h->delay;
+        const int slots = h->left ? h->max_budget : tune ? MAX_DELAY : h->delay;
+        if (h->left) HIPCHK(h, dmalloc(h, &h->C, (size_t)(LEFT_SPLITS * h->N_c * bs) * relem(h)));
         HIPCHK(h, dmalloc(h, &h->W, (size_t)(slots * h->wslot) * we));
         if (h->wtype == W_BF16X3) HIPCHK(h, dmalloc(h, &h->W2, (size_t)(slots * h->wslot) * 2));
         if (slots > 1) HIPCHK(h, dmalloc(h, (void **)&h->V, sizeof(double) * bs * (slots - 1)));
@@ -578,6 +641,7 @@ oed_status oed_greedy(oed_ctx *h, int32_t budget, int32_t *idx_out, double *gain
     if (n_out) *n_out = 0;
     if (h->poisoned) return fail(h, OED_E_STATE, "handle stopped after a non-positive-definite step; reset it");
     if (budget < 0 || budget > h->n_act) return fail(h, OED_E_ARG, "budget out of range");
+    if (h->left && h->k + budget > h->max_budget) return fail(h, OED_E_ARG, "budget beyond max_budget");
     if (budget > 0 && (!idx_out || !gain_out)) return fail(h, OED_E_ARG, "NULL output array");
     const int k0 = h->k;
     for (int step = 0; step < budget; ++step) {
@@ -607,7 +671,9 @@ oed_status oed_force(oed_ctx *h, int32_t idx, double *gain_out)
     if (idx < 0 || idx >= h->N_s || h->lmap[idx] < 0 || h->picked[h->lmap[idx]])
         return fail(h, OED_E_ARG, "index is not a remaining candidate");
     const int k0 = h->k;
+    if (h->left && h->k >= h->max_budget) return fail(h, OED_E_ARG, "max_budget picks already made");
     oed_status st = advance(h, false);
+    if (st == OED_OK && h->left && !h->diag_current) st = enqueue_gains(h);
     if (st == OED_OK) st = enqueue_pick(h, h->lmap[idx]);
     if (st != OED_OK) return st;
     oed_status dev = OED_OK;
@@ -646,7 +712,10 @@ oed_status oed_schur_block(oed_ctx *h, int32_t i, int32_t j, double *out)
     int li = h->lmap[i], lj = h->lmap[j];
     if (li < 0 || lj < 0 || h->picked[li] || h->picked[lj]) return fail(h, OED_E_ARG, "not a remaining candidate");
     oed_status st = advance(h, true);
+    // left-looking: bring the diagonal blocks up to date (the gains are recomputed as a side effect)
+    if (st == OED_OK && h->left && !h->diag_current) st = enqueue_gains(h);
     if (st != OED_OK) return st;
+    const int oi = li, oj = lj;
     const bool tr = li < lj;
     if (tr) std::swap(li, lj);
     const int64_t bs = (int64_t)h->N_tp * h->N_tp;
@@ -668,6 +737,28 @@ oed_status oed_schur_block(oed_ctx *h, int32_t i, int32_t j, double *out)
             else
                 out[(size_t)t * h->N_t + u] = v;
         }
+    if (h->left && !diag) {
+        // off the diagonal R still holds K: subtract sum_k W_k,i W_k,j^T over the formed columns
+        const size_t we = welem(h);
+        std::vector<unsigned char> wi((size_t)bs * we), wj((size_t)bs * we);
+        auto wval = [&](const std::vector<unsigned char> &w, int t, int m) {
+            // element (t, m) of a block in operand order
+            const int64_t o = ((int64_t)((t >> 4) * nb + (m >> 4)) << 8) + ((((m & 15) >> 2) << 4) + (t & 15)) * 4 + (m & 3);
+            return we == 8 ? ((const double *)w.data())[o] : (double)((const float *)w.data())[o];
+        };
+        for (int kk = 0; kk < h->k; ++kk) {
+            const char *base = (const char *)h->W + (size_t)(kk * h->wslot) * we;
+            HIPCHK(h, hipMemcpyAsync(wi.data(), base + (size_t)(oi * bs) * we, wi.size(), hipMemcpyDeviceToHost, h->stream));
+            HIPCHK(h, hipMemcpyAsync(wj.data(), base + (size_t)(oj * bs) * we, wj.size(), hipMemcpyDeviceToHost, h->stream));
+            HIPCHK(h, hipStreamSynchronize(h->stream));
+            for (int t = 0; t < h->N_t; ++t)
+                for (int u = 0; u < h->N_t; ++u) {
+                    double acc = 0;
+                    for (int m = 0; m < h->N_t; ++m) acc += wval(wi, t, m) * wval(wj, u, m);
+                    out[(size_t)t * h->N_t + u] -= acc;
+                }
+        }
+    }
     return OED_OK;
 }
 

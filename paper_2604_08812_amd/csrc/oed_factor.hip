@@ -261,6 +261,22 @@ __device__ __forceinline__ bool chol_regs(const TR *__restrict__ Rb, int N_t, in
                 }
         }
     }
+    if (d.wb && d.nheld > 0) {
+        // left-looking: the diagonal block is kept current in place
+        TR *Rw = const_cast<TR *>(Rb);
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            const int I = h ? 7 - w : w;
+#pragma unroll
+            for (int J = 0; J < 8; ++J)
+                if (I < nbr && J <= I) {
+                    typename V4<TR>::type v;
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) v[r] = (TR)A[h][J][r];
+                    st4(Rw + ((I * nb + J) << 8) + lane * 4, v);
+                }
+        }
+    }
     bool ok = chol_block<0>(A, N_t, nbr, colbuf, piv, Lout);
     if (ok && nbr > 1) ok = chol_block<1>(A, N_t, nbr, colbuf, piv, Lout);
     if (ok && nbr > 2) ok = chol_block<2>(A, N_t, nbr, colbuf, piv, Lout);

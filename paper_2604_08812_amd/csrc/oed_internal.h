@@ -73,6 +73,12 @@ struct StepDesc {
     int64_t wslot;         // elements per W slot (N_c N_tp^2)
     double *V;             // L_s^-1 P_h,s of the last pick s for every held h (operand order, N_tp^2 each)
     int nheld;             // number of held W (gain, pick, vcorr, trsm)
+    int wb;                // gain: write the corrected diagonal blocks back to R (left-looking)
+    int nsplit;            // left-looking: column partial sums in C (column kernel: splits of the
+                           // W slots; trsm: C_i = R_is - sum of the nsplit partials), 0 = none
+    void *C;               // left-looking column partial sums: split q at C + q cstride elements,
+                           // candidate i's block at + i N_tp^2, accumulator order, R's type
+    int64_t cstride;
     const int *act_in;     // remaining candidates (gain, pick: before the pick; trsm, syrk: after it)
     int *act_out;          // pick: remaining candidates after the pick
     double *gains;         // gains by position in act_in
@@ -113,6 +119,9 @@ hipError_t launch_gain(const StepDesc &d, int rtype, int wtype, hipStream_t s);
 hipError_t launch_pick(const StepDesc &d, int rtype, int wtype, hipStream_t s);
 hipError_t launch_vcorr(const StepDesc &d, int wtype, hipStream_t s);
 hipError_t launch_trsm(const StepDesc &d, int rtype, int wtype, hipStream_t s);
+// Left-looking block column (Algorithm 1's order): partial sums of sum_h W_h,i W_h,s^T over the
+// d.nw W slots, split in d.nsplit parts (d.nitems = nsplit * row tiles), for every remaining i.
+hipError_t launch_column(const StepDesc &d, int rtype, hipStream_t s);
 // Downdate kernels: SYRK_DIRECT streams W operands from global memory per wave (any N_tp);
 // SYRK_LDS stages them through LDS with a software pipeline (N_tp <= 128).  W_BF16X3 always
 // runs the BF16 split-product kernel (N_tp a multiple of 32, <= 128).

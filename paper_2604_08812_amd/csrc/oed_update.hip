@@ -139,6 +139,13 @@ __device__ void trsm_body(const StepDesc &d, int p)
 #pragma unroll
                     for (int s4 = 0; s4 < 4; ++s4) b[s4] = (double)v[s4];
                 }
+                // left-looking: C_i = K_is - sum_h W_h,i W_h,s^T, the sum in nsplit partials
+                for (int sp = 0; sp < d.nsplit; ++sp) {
+                    const TR *Cp = (const TR *)d.C + sp * d.cstride + (int64_t)i * bs;
+                    const int t = 16 * tb + l16;
+#pragma unroll
+                    for (int s4 = 0; s4 < 4; ++s4) b[s4] -= (double)Cp[acc_off(t, 16 * q + 4 * g + s4, nb)];
+                }
 #pragma unroll
                 for (int c = 0; c < 8; ++c) {
                     const int kc = kg + c;
@@ -516,6 +523,123 @@ __device__ void syrk_bf16_body(const StepDesc &d, int64_t tile)
 }
 
 // ---------------------------------------------------------------------------------------------
+// Left-looking block column (the order of Algorithm 1): for the new pick s and every remaining
+// candidate i, the partial sums sum_{h in split} W_h,i W_h,s^T over the stored W slots, on MFMA
+// with the operands staged in LDS as in the downdate; one work-group per (split, 128-row tile).
+// The 128 x N_tp output tile is the rows of the remaining candidates against the N_tp rows of
+// s; partial q goes to d.C + q cstride in candidate i's block (accumulator order).
+template <typename T, int NB>
+__device__ void column_body(const StepDesc &d, int64_t item)
+{
+    typedef typename V4<T>::type vec;
+    constexpr int N_tp = 16 * NB;
+    __shared__ vec lds[2][2][8 * 64];
+    if (d.state[ST_STATUS] != 0 || d.nsplit <= 0) return;
+    const int64_t rows_t = syrk_tile_rows(d.n_act, N_tp);
+    const int split = (int)(item / rows_t);
+    const int64_t P = item % rows_t;
+    if (split >= d.nsplit) return;
+    const int h0 = (int)((int64_t)split * d.nw / d.nsplit), h1 = (int)((int64_t)(split + 1) * d.nw / d.nsplit);
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6), wr = wave >> 1, wc = wave & 1;
+    const int alane = a_lane<T>(lane);
+    const int *__restrict__ act = d.act_in;
+    const int rows = d.n_act * N_tp, last = d.n_act - 1;
+    const int s = d.state[ST_LAST];
+    const int64_t bs = (int64_t)N_tp * N_tp;
+    // staged operands: rows of the tile (A) and the rows of s (B; sub-blocks past N_tp clamped)
+    int64_t wA[2], wB[2];
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+        const int sb = wave + 4 * h;
+        const int r = (int)P * 128 + 16 * sb;
+        wA[h] = (int64_t)act[min(r / N_tp, last)] * bs + (int64_t)((r % N_tp) >> 4) * (NB * 256);
+        wB[h] = (int64_t)s * bs + (int64_t)(sb < NB ? sb : 0) * (NB * 256);
+    }
+    int64_t off[16];
+    bool ok[16];
+    bool any = false;
+#pragma unroll
+    for (int b = 0; b < 4; ++b) {
+        const int r = (int)P * 128 + wr * 64 + 16 * b;
+        const int ia = act[min(r / N_tp, last)], ta = (r % N_tp) >> 4;
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+            const int tc = wc * 4 + c;
+            const bool o = r < rows && tc < NB;
+            ok[4 * b + c] = o;
+            any |= o;
+            off[4 * b + c] = (int64_t)ia * bs + ((ta * NB + (o ? tc : 0)) << 8);
+        }
+    }
+    const T *W0 = (const T *)d.W + lane * 4;
+    const int64_t wslot = d.wslot;
+    vec acc[16];
+#pragma unroll
+    for (int f = 0; f < 16; ++f) acc[f] = vec{0, 0, 0, 0};
+    vec sa[2], sbv[2];
+    {
+        const T *w0 = W0 + h0 * wslot;
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            sa[h] = ld4(w0 + wA[h]);
+            sbv[h] = ld4(w0 + wB[h]);
+        }
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            lds[0][0][(wave + 4 * h) * 64 + lane] = sa[h];
+            lds[0][1][(wave + 4 * h) * 64 + lane] = sbv[h];
+        }
+    }
+    __syncthreads();
+    int par = 0;
+    for (int slot = h0; slot < h1; ++slot) {
+        const T *cur = W0 + slot * wslot;
+        const T *nxt = slot + 1 < h1 ? cur + wslot : nullptr;
+#pragma unroll
+        for (int q = 0; q < NB; ++q) {
+            const int buf = par ^ (q & 1);
+            const bool more = q + 1 < NB || nxt;
+            if (more) {
+                const T *src = q + 1 < NB ? cur + ((q + 1) << 8) : nxt;
+#pragma unroll
+                for (int h = 0; h < 2; ++h) {
+                    sa[h] = ld4(src + wA[h]);
+                    sbv[h] = ld4(src + wB[h]);
+                }
+            }
+            if (any) {
+                vec a[4], w[4];
+#pragma unroll
+                for (int b = 0; b < 4; ++b) {
+                    a[b] = lds[buf][0][(wr * 4 + b) * 64 + alane];
+                    w[b] = lds[buf][1][(wc * 4 + b) * 64 + lane];
+                }
+#pragma unroll
+                for (int s4 = 0; s4 < 4; ++s4)
+#pragma unroll
+                    for (int b = 0; b < 4; ++b)
+#pragma unroll
+                        for (int c = 0; c < 4; ++c) acc[4 * b + c] = mfma16(a[b][s4], w[c][s4], acc[4 * b + c]);
+            }
+            if (more) {
+#pragma unroll
+                for (int h = 0; h < 2; ++h) {
+                    lds[buf ^ 1][0][(wave + 4 * h) * 64 + lane] = sa[h];
+                    lds[buf ^ 1][1][(wave + 4 * h) * 64 + lane] = sbv[h];
+                }
+            }
+            __syncthreads();
+        }
+        par ^= NB & 1;
+    }
+    T *Cq = (T *)d.C + split * d.cstride + lane * 4;
+#pragma unroll
+    for (int f = 0; f < 16; ++f)
+        if (ok[f]) st4(Cq + off[f], acc[f]);
+}
+
+// ---------------------------------------------------------------------------------------------
 // Kernels: single instance (descriptor by value) and batched (descriptor array).
 
 template <typename TR, typename TW>
@@ -591,6 +715,14 @@ __global__ void __launch_bounds__(256, 2) syrk_bf16_batched(const StepDesc *__re
     if (i < 0) return;
     const StepDesc d = ds[i];
     syrk_bf16_body<NB32>(d, item - d.item0);
+}
+
+template <typename T, int NB>
+__global__ void __launch_bounds__(256, 2) column_kernel(StepDesc d, int64_t per_xcd)
+{
+    const int64_t item = xcd_item(blockIdx.x, per_xcd);
+    if (item >= d.nitems) return;
+    column_body<T, NB>(d, item);
 }
 
 template <typename TW>
@@ -732,6 +864,36 @@ static hipError_t launch_syrk_bf16(const StepDesc *descs, const StepDesc &d, int
 #undef OED_BF16_CASE
     }
     return hipGetLastError();
+}
+
+template <typename T>
+static hipError_t launch_column_t(const StepDesc &d, hipStream_t s)
+{
+    const int64_t per_xcd = (d.nitems + 7) / 8;
+    const dim3 grid((unsigned)(per_xcd * 8)), block(256);
+    switch (d.N_tp / 16) {
+#define OED_COL_CASE(NBV)                                                                      \
+    case NBV: hipLaunchKernelGGL((column_kernel<T, NBV>), grid, block, 0, s, d, per_xcd); break;
+        OED_COL_CASE(1)
+        OED_COL_CASE(2)
+        OED_COL_CASE(3)
+        OED_COL_CASE(4)
+        OED_COL_CASE(5)
+        OED_COL_CASE(6)
+        OED_COL_CASE(7)
+        OED_COL_CASE(8)
+#undef OED_COL_CASE
+    default:
+        return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_column(const StepDesc &d, int rtype, hipStream_t s)
+{
+    if (d.n_act <= 0 || d.nsplit <= 0 || d.nitems <= 0) return hipSuccess;
+    if (d.N_tp % 16 != 0 || d.N_tp > 128 || d.nw < d.nsplit || !d.C) return hipErrorInvalidValue;
+    return rtype == R_F64 ? launch_column_t<double>(d, s) : launch_column_t<float>(d, s);
 }
 
 hipError_t launch_syrk(const StepDesc &d, int rtype, int wtype, int variant, hipStream_t s)

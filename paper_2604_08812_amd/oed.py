@@ -27,7 +27,8 @@ KERNELS = ("gain", "pick", "trsm", "syrk", "pack")
 class oed_options(ctypes.Structure):
     _fields_ = [("struct_size", ctypes.c_uint32), ("precision", ctypes.c_int32), ("flags", ctypes.c_uint32),
                 ("candidates", ctypes.POINTER(ctypes.c_int32)), ("n_candidates", ctypes.c_int32),
-                ("delay", ctypes.c_int32), ("reserved", ctypes.c_int32 * 6)]
+                ("delay", ctypes.c_int32), ("method", ctypes.c_int32), ("max_budget", ctypes.c_int32),
+                ("reserved", ctypes.c_int32 * 4)]
 
 
 class oed_profile(ctypes.Structure):
@@ -134,9 +135,11 @@ def _stream_handle(stream):
 
 # ------------------------------------------------------------------ functions with the C names
 def oed_create(K, N_s, N_t, sigma2, precision="fp64", candidates=None, profile=False, stream=None, delay=0,
-               autotune=False):
+               autotune=False, method="right", max_budget=0):
     """Create a handle for the device tensor K (2-D, float64/float32, row-major, lower triangle read).
-    delay: downdate delay depth (0 automatic, 1..4); autotune: with delay 0, time the choices."""
+    delay: downdate delay depth (0 automatic, 1..4); autotune: with delay 0, time the choices;
+    method: "right" (downdate of all of R per pick) or "left" (only the new block column per pick);
+    max_budget: left-looking W history size (0: all candidates)."""
     import torch
     L = library()
     if not isinstance(K, torch.Tensor) or not K.is_cuda or K.dim() != 2 or K.stride(1) != 1:
@@ -151,6 +154,8 @@ def oed_create(K, N_s, N_t, sigma2, precision="fp64", candidates=None, profile=F
     opt.precision = PRECISIONS[precision]
     opt.flags = (OED_FLAG_PROFILE if profile else 0) | (OED_FLAG_AUTOTUNE if autotune else 0)
     opt.delay = int(delay)
+    opt.method = {"right": 0, "left": 1}[method]
+    opt.max_budget = int(max_budget)
     cand = None
     if candidates is not None:
         cand = np.ascontiguousarray(np.asarray(list(candidates), dtype=np.int32))
@@ -344,9 +349,10 @@ class Selector:
     """Owns one handle.  ``Selector(K, N_s, N_t, sigma2).greedy(B)`` -> (indices, gains)."""
 
     def __init__(self, K, N_s, N_t, sigma2, precision="fp64", candidates=None, profile=False, stream=None,
-                 delay=0, autotune=False):
+                 delay=0, autotune=False, method="right", max_budget=0):
         self.N_s, self.N_t = int(N_s), int(N_t)
-        self.h = oed_create(K, N_s, N_t, sigma2, precision, candidates, profile, stream, delay, autotune)
+        self.h = oed_create(K, N_s, N_t, sigma2, precision, candidates, profile, stream, delay, autotune, method,
+                            max_budget)
 
     def greedy(self, budget):
         idx, gain, _ = oed_greedy(self.h, budget)

@@ -45,6 +45,10 @@ def runs(big):
         print(f"greedy {prec} B={spec.budget}", flush=True)
         with Selector(K, spec.N_s, spec.N_t, s2, precision=prec) as sel:
             out[prec] = sel.greedy(spec.budget)
+    for prec in ("fp64", "mixed_f32"):
+        print(f"greedy left-looking {prec} B={spec.budget}", flush=True)
+        with Selector(K, spec.N_s, spec.N_t, s2, precision=prec, method="left", max_budget=spec.budget) as sel:
+            out["left_" + prec] = sel.greedy(spec.budget)
     return out
 
 
@@ -137,3 +141,22 @@ def test_subsample_100_against_oracle(big, prec):
     sub = k_sub_lower(K, spec.N_t, range(n))
     rep = check_trajectory(sub, n, spec.N_t, s2, idx, gain, RTOL[prec])
     print(f"{prec} subsample: picks {list(idx)}, max rel err {rep['max_rel_err']:.2e}")
+
+
+@pytest.mark.timeout(900)
+@pytest.mark.parametrize("prec", ["fp64", "mixed_f32"])
+def test_fullsize_left_looking(big, runs, prec):
+    """Left-looking selection at full size: the picks of the right-looking FP64 path, gains within
+    the precision's tolerance, and the telescoping identity."""
+    spec, K, s2 = big
+    i64, g64 = runs["fp64"]
+    il, gl = runs["left_" + prec]
+    div = next((k for k in range(spec.budget) if i64[k] != il[k]), None)
+    upto = spec.budget if div is None else div
+    err = rel_err(gl[:upto], g64[:upto]).max()
+    print(f"left {prec} vs right fp64: first divergence {div}, max rel gain diff {err:.2e}")
+    assert err <= RTOL[prec]
+    assert div is None or RTOL[prec] > 1e-9
+    sub = k_sub_lower(K, spec.N_t, il)
+    total = 0.5 * oracle.logdet_lapack(sub) - 0.5 * len(il) * spec.N_t * np.log(s2)
+    assert abs(gl.sum() - total) / abs(total) <= RTOL[prec]

@@ -277,3 +277,53 @@ def test_autotuned_handle_selects_like_a_fixed_one(prec):
         d2, v2, ms2 = t2.config()
     assert (d2, v2) == (delay, variant)
     np.testing.assert_array_equal(ms2, ms)
+
+
+LEFT_CASES = [c for c in CASES if c[1] <= 128]
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed_f32"])
+@pytest.mark.parametrize("case", LEFT_CASES, ids=lambda c: "x".join(map(str, c[:2])))
+def test_left_looking_matches_oracle_and_right_looking(case, prec):
+    N_s, N_t, n_m, seed, B = case
+    print(f"left-looking N_s={N_s} N_t={N_t} seed={seed} B={B} prec={prec}", flush=True)
+    K, Kd, s2 = instance(N_s, N_t, n_m, seed)
+    with selector(Kd, N_s, N_t, s2, precision=prec, method="left", max_budget=B) as sel:
+        idx, gain = sel.greedy(B)
+    rep = check_trajectory(K, N_s, N_t, s2, idx, gain, RTOL[prec])
+    print(f"  max rel gain err {rep['max_rel_err']:.2e}")
+    with selector(Kd, N_s, N_t, s2, precision=prec, delay=1) as r:
+        ir, gr = r.greedy(B)
+    assert list(idx) == list(ir) or rep["diverged_steps"]
+    if list(idx) == list(ir):
+        assert np.all(rel_err(gain, gr) <= (1e-12 if prec == "fp64" else RTOL[prec]))
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed_f32"])
+def test_left_looking_queries(prec):
+    """Forced picks, scores, Schur blocks (diagonal and off-diagonal, formed on the host from K and
+    the W history) and split calls in left-looking mode, against the oracle."""
+    N_s, N_t = 31, 48
+    K, Kd, s2 = instance(N_s, N_t, 2500, 37)
+    A = [9, 2, 30]
+    rest = [j for j in range(N_s) if j not in A]
+    tol = 1e-11 if prec == "fp64" else 2e-5
+    with selector(Kd, N_s, N_t, s2, precision=prec, method="left", max_budget=10) as sel:
+        for a in A:
+            sel.force(a)
+        g = sel.scores()
+        ref = oracle.gains(K, N_t, s2, A, rest)
+        assert np.all(rel_err(g[rest], ref) <= RTOL[prec])
+        S = oracle.schur_complement(K, N_t, A, rest)
+        scale = np.abs(S).max()
+        for (i, j) in [(1, 1), (28, 3), (3, 28), (20, 19), (29, 29), (0, 1)]:
+            blk = sel.schur_block(i, j)
+            pi, pj = rest.index(i), rest.index(j)
+            assert np.abs(blk - S[pi * N_t:(pi + 1) * N_t, pj * N_t:(pj + 1) * N_t]).max() <= tol * scale, (i, j)
+        i1, g1 = sel.greedy(4)
+        i2, g2 = sel.greedy(3)
+        with pytest.raises(Exception):
+            sel.greedy(1)      # max_budget = 10 picks made
+    ref = oracle.greedy(K, N_s, N_t, s2, 10, prefix=A)
+    assert list(ref["idx"][3:]) == list(np.r_[i1, i2])
+    assert np.all(rel_err(np.r_[g1, g2], ref["gain"][3:]) <= RTOL[prec])
