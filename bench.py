@@ -400,8 +400,8 @@ def main():
 
     # ---- left-looking (the order of Algorithm 1) beside it, same K
     if not args.no_left and spec.N_t <= 128:
-        for lp in ("mixed_f32", "fp64"):
-            if lp != prec and lp != "fp64":
+        for lp in ("mixed_f32", "mixed_bf16x3", "fp64"):
+            if lp != prec and lp != "fp64" and not (lp == "mixed_bf16x3" and prec == "mixed_f32"):
                 continue
             sell = Selector(K, spec.N_s, spec.N_t, s2, precision=lp, profile=True, method="left", max_budget=budget)
             timed_selections(sell, K, budget, 1)
@@ -413,9 +413,11 @@ def main():
             log(f"left-looking {lp}: {msl:.1f} ms per selection")
             tfl = pl["syrk_flops"] / (pl["ms"]["syrk"] * 1e-3) / 1e12 if pl["ms"]["syrk"] > 0 else 0.0
             leg = {"value": round(budget / (msl * 1e-3), 3), "unit": "greedy steps/s", "ms_per_step": round(msl, 3),
-                   "column_kernel": {"kernel": f"column_kernel<{'float' if lp != 'fp64' else 'double'}>",
+                   "column_kernel": {"kernel": {"mixed_f32": "column_kernel<float>", "fp64": "column_kernel<double>",
+                                                "mixed_bf16x3": "column_bf16_kernel"}[lp],
                                      "algorithmic_tflops": round(tfl, 3), "peak": PEAK_TFLOPS[lp],
-                                     "frac": round(tfl / PEAK_TFLOPS[lp], 4),
+                                     # the BF16 split product executes three MFMA products per one
+                                     "frac": round(tfl * (3 if lp == "mixed_bf16x3" else 1) / PEAK_TFLOPS[lp], 4),
                                      "algorithmic_flops_per_selection": pl["syrk_flops"] / nst},
                    "kernel_ms_per_step": {k: round(v / nst, 3) for k, v in pl["ms"].items()}}
             ref = (idx64, gain64) if "fp64" in result else (idx, gain)

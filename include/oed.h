@@ -114,7 +114,7 @@ typedef struct oed_options {
  *  LEFT_LOOKING  : the order of Algorithm 1 (Sec. III-D): R keeps K off the diagonal; every
  *                  pick forms only its own block column, K_is - sum over the earlier picks'
  *                  block columns (W history), and updates the diagonal blocks.  About 1/3 of
- *                  the flops of RIGHT_LOOKING at 600 x 128, budget 175.  FP64 and MIXED_F32,
+ *                  the flops of RIGHT_LOOKING at 600 x 128, budget 175.  All precisions,
  *                  N_t <= 128 (else OED_E_UNSUPPORTED); the delay option does not apply.
  */
 #define OED_METHOD_RIGHT_LOOKING 0

@@ -249,13 +249,14 @@ oed_status advance_left(oed_ctx *h)
         d.nitems = (int64_t)d.nsplit * syrk_tile_rows(h->n_act, h->N_tp);
         {
             Prof pr(h, OED_K_SYRK);
-            HIPCHK(h, launch_column(d, h->rtype, h->stream));
+            HIPCHK(h, launch_column(d, h->rtype, h->wtype, h->stream));
         }
         const double n = (double)h->n_act * h->N_t;
         h->syrk_flops += 2.0 * n * h->N_t * hist * h->N_t;
         h->syrk_bytes += (double)relem(h) * (n * hist * h->N_t + (double)hist * h->N_t * h->N_t + d.nsplit * n * h->N_t);
     }
     d.W = (char *)h->W + (size_t)(hist * h->wslot) * welem(h);  // output: slot k-1
+    if (h->W2) d.W2 = (char *)h->W2 + (size_t)(hist * h->wslot) * 2;
     {
         Prof pr(h, OED_K_TRSM);
         HIPCHK(h, launch_trsm(d, h->rtype, h->wtype, h->stream));
@@ -426,6 +427,7 @@ oed_status enqueue_gains(oed_ctx *h)
     if (h->left && !h->diag_current) {
         // apply the newest block column (slot k-1) to the diagonal blocks, in place
         d.W = (char *)h->W + (size_t)((h->k - 1) * h->wslot) * welem(h);
+        if (h->W2) d.W2 = (char *)h->W2 + (size_t)((h->k - 1) * h->wslot) * 2;
         d.nheld = 1;
         d.wb = 1;
         h->diag_current = true;
@@ -532,8 +534,7 @@ oed_status oed_create(oed_ctx **out, const void *K, int32_t dtype, int64_t ld, i
     if (o.delay < 0 || o.delay > MAX_DELAY) return OED_E_ARG;
     if (o.method != OED_METHOD_RIGHT_LOOKING && o.method != OED_METHOD_LEFT_LOOKING) return OED_E_ARG;
     if (o.max_budget < 0 || o.max_budget > N_s) return OED_E_ARG;
-    if (o.method == OED_METHOD_LEFT_LOOKING && (N_t > REGS_MAX_NT || o.precision == OED_PREC_MIXED_BF16X3))
-        return OED_E_UNSUPPORTED;
+    if (o.method == OED_METHOD_LEFT_LOOKING && N_t > REGS_MAX_NT) return OED_E_UNSUPPORTED;
     if (o.delay > 1 && N_t > REGS_MAX_NT) return OED_E_UNSUPPORTED;
     for (int r : o.reserved)
         if (r != 0) return OED_E_ARG;
@@ -740,8 +741,23 @@ oed_status oed_schur_block(oed_ctx *h, int32_t i, int32_t j, double *out)
     if (h->left && !diag) {
         // off the diagonal R still holds K: subtract sum_k W_k,i W_k,j^T over the formed columns
         const size_t we = welem(h);
-        std::vector<unsigned char> wi((size_t)bs * we), wj((size_t)bs * we);
-        auto wval = [&](const std::vector<unsigned char> &w, int t, int m) {
+        std::vector<unsigned char> wi((size_t)bs * we), wj((size_t)bs * we), wi2, wj2;
+        if (h->W2) {
+            wi2.resize(wi.size());
+            wj2.resize(wj.size());
+        }
+        auto bf = [](unsigned short x) {
+            const uint32_t u = (uint32_t)x << 16;
+            float f;
+            std::memcpy(&f, &u, 4);
+            return (double)f;
+        };
+        auto wval = [&](const std::vector<unsigned char> &w, const std::vector<unsigned char> &w2, int t, int m) {
+            if (we == 2) {  // BF16 hi + lo, 16 x 32 operand order
+                const int64_t o = ((int64_t)((t >> 4) * (nb / 2) + (m >> 5)) << 9) + ((((m & 31) >> 3) << 4) + (t & 15)) * 8 +
+                                  (m & 7);
+                return bf(((const unsigned short *)w.data())[o]) + bf(((const unsigned short *)w2.data())[o]);
+            }
             // element (t, m) of a block in operand order
             const int64_t o = ((int64_t)((t >> 4) * nb + (m >> 4)) << 8) + ((((m & 15) >> 2) << 4) + (t & 15)) * 4 + (m & 3);
             return we == 8 ? ((const double *)w.data())[o] : (double)((const float *)w.data())[o];
@@ -750,11 +766,16 @@ oed_status oed_schur_block(oed_ctx *h, int32_t i, int32_t j, double *out)
             const char *base = (const char *)h->W + (size_t)(kk * h->wslot) * we;
             HIPCHK(h, hipMemcpyAsync(wi.data(), base + (size_t)(oi * bs) * we, wi.size(), hipMemcpyDeviceToHost, h->stream));
             HIPCHK(h, hipMemcpyAsync(wj.data(), base + (size_t)(oj * bs) * we, wj.size(), hipMemcpyDeviceToHost, h->stream));
+            if (h->W2) {
+                const char *b2 = (const char *)h->W2 + (size_t)(kk * h->wslot) * 2;
+                HIPCHK(h, hipMemcpyAsync(wi2.data(), b2 + (size_t)(oi * bs) * 2, wi2.size(), hipMemcpyDeviceToHost, h->stream));
+                HIPCHK(h, hipMemcpyAsync(wj2.data(), b2 + (size_t)(oj * bs) * 2, wj2.size(), hipMemcpyDeviceToHost, h->stream));
+            }
             HIPCHK(h, hipStreamSynchronize(h->stream));
             for (int t = 0; t < h->N_t; ++t)
                 for (int u = 0; u < h->N_t; ++u) {
                     double acc = 0;
-                    for (int m = 0; m < h->N_t; ++m) acc += wval(wi, t, m) * wval(wj, u, m);
+                    for (int m = 0; m < h->N_t; ++m) acc += wval(wi, wi2, t, m) * wval(wj, wj2, u, m);
                     out[(size_t)t * h->N_t + u] -= acc;
                 }
         }

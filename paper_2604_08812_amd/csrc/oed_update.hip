@@ -639,6 +639,120 @@ __device__ void column_body(const StepDesc &d, int64_t item)
         if (ok[f]) st4(Cq + off[f], acc[f]);
 }
 
+// The same with W in BF16 hi + lo parts (32-wide slices; hi hi^T + hi lo^T + lo hi^T on the
+// 16x16x32 BF16 MFMA, FP32 accumulation).
+template <int NB32>
+__device__ void column_bf16_body(const StepDesc &d, int64_t item)
+{
+    constexpr int N_tp = 32 * NB32, NB = 2 * NB32;
+    __shared__ u32x4 lds[2][4][8 * 64];  // [buffer][A hi, A lo, B hi, B lo][sub-block * 64 + lane]
+    if (d.state[ST_STATUS] != 0 || d.nsplit <= 0) return;
+    const int64_t rows_t = syrk_tile_rows(d.n_act, N_tp);
+    const int split = (int)(item / rows_t);
+    const int64_t P = item % rows_t;
+    if (split >= d.nsplit) return;
+    const int h0 = (int)((int64_t)split * d.nw / d.nsplit), h1 = (int)((int64_t)(split + 1) * d.nw / d.nsplit);
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6), wr = wave >> 1, wc = wave & 1;
+    const int *__restrict__ act = d.act_in;
+    const int rows = d.n_act * N_tp, last = d.n_act - 1;
+    const int s = d.state[ST_LAST];
+    const int64_t bs = (int64_t)N_tp * N_tp;
+    int64_t wA[2], wB[2];
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+        const int sb = wave + 4 * h;
+        const int r = (int)P * 128 + 16 * sb;
+        wA[h] = (int64_t)act[min(r / N_tp, last)] * bs + (int64_t)((r % N_tp) >> 4) * (NB * 256);
+        wB[h] = (int64_t)s * bs + (int64_t)(sb < NB ? sb : 0) * (NB * 256);
+    }
+    int64_t off[16];
+    bool ok[16];
+    bool any = false;
+#pragma unroll
+    for (int b = 0; b < 4; ++b) {
+        const int r = (int)P * 128 + wr * 64 + 16 * b;
+        const int ia = act[min(r / N_tp, last)], ta = (r % N_tp) >> 4;
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+            const int tc = wc * 4 + c;
+            const bool o = r < rows && tc < NB;
+            ok[4 * b + c] = o;
+            any |= o;
+            off[4 * b + c] = (int64_t)ia * bs + ((ta * NB + (o ? tc : 0)) << 8);
+        }
+    }
+    typedef const unsigned short *bp;
+    const bp Wh0 = (bp)d.W + lane * 8, Wl0 = (bp)d.W2 + lane * 8;
+    const int64_t wslot = d.wslot;
+    floatx4 acc[16];
+#pragma unroll
+    for (int f = 0; f < 16; ++f) acc[f] = floatx4{0, 0, 0, 0};
+    u32x4 st[2][4];
+    auto stage = [&](bp hi, bp lo) {
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            st[h][0] = *reinterpret_cast<const u32x4 *>(hi + wA[h]);
+            st[h][1] = *reinterpret_cast<const u32x4 *>(lo + wA[h]);
+            st[h][2] = *reinterpret_cast<const u32x4 *>(hi + wB[h]);
+            st[h][3] = *reinterpret_cast<const u32x4 *>(lo + wB[h]);
+        }
+    };
+    stage(Wh0 + h0 * wslot, Wl0 + h0 * wslot);
+#pragma unroll
+    for (int h = 0; h < 2; ++h)
+#pragma unroll
+        for (int k = 0; k < 4; ++k) lds[0][k][(wave + 4 * h) * 64 + lane] = st[h][k];
+    __syncthreads();
+    int par = 0;
+    for (int slot = h0; slot < h1; ++slot) {
+        const bp chi = Wh0 + slot * wslot, clo = Wl0 + slot * wslot;
+        const bool nxt = slot + 1 < h1;
+#pragma unroll
+        for (int q = 0; q < NB32; ++q) {
+            const int buf = par ^ (q & 1);
+            const bool more = q + 1 < NB32 || nxt;
+            if (more) {
+                if (q + 1 < NB32)
+                    stage(chi + ((q + 1) << 9), clo + ((q + 1) << 9));
+                else
+                    stage(chi + wslot, clo + wslot);
+            }
+            if (any) {
+                u32x4 wh[4], wl[4];
+#pragma unroll
+                for (int c = 0; c < 4; ++c) {
+                    wh[c] = lds[buf][2][(wc * 4 + c) * 64 + lane];
+                    wl[c] = lds[buf][3][(wc * 4 + c) * 64 + lane];
+                }
+#pragma unroll
+                for (int b = 0; b < 4; ++b) {
+                    const u32x4 ah = lds[buf][0][(wr * 4 + b) * 64 + lane];
+                    const u32x4 al = lds[buf][1][(wr * 4 + b) * 64 + lane];
+#pragma unroll
+                    for (int c = 0; c < 4; ++c) {
+                        acc[4 * b + c] = mfma_bf16(ah, wh[c], acc[4 * b + c]);
+                        acc[4 * b + c] = mfma_bf16(ah, wl[c], acc[4 * b + c]);
+                        acc[4 * b + c] = mfma_bf16(al, wh[c], acc[4 * b + c]);
+                    }
+                }
+            }
+            if (more) {
+#pragma unroll
+                for (int h = 0; h < 2; ++h)
+#pragma unroll
+                    for (int k = 0; k < 4; ++k) lds[buf ^ 1][k][(wave + 4 * h) * 64 + lane] = st[h][k];
+            }
+            __syncthreads();
+        }
+        par ^= NB32 & 1;
+    }
+    float *Cq = (float *)d.C + split * d.cstride + lane * 4;
+#pragma unroll
+    for (int f = 0; f < 16; ++f)
+        if (ok[f]) st4(Cq + off[f], acc[f]);
+}
+
 // ---------------------------------------------------------------------------------------------
 // Kernels: single instance (descriptor by value) and batched (descriptor array).
 
@@ -723,6 +837,14 @@ __global__ void __launch_bounds__(256, 2) column_kernel(StepDesc d, int64_t per_
     const int64_t item = xcd_item(blockIdx.x, per_xcd);
     if (item >= d.nitems) return;
     column_body<T, NB>(d, item);
+}
+
+template <int NB32>
+__global__ void __launch_bounds__(256, 2) column_bf16_kernel(StepDesc d, int64_t per_xcd)
+{
+    const int64_t item = xcd_item(blockIdx.x, per_xcd);
+    if (item >= d.nitems) return;
+    column_bf16_body<NB32>(d, item);
 }
 
 template <typename TW>
@@ -889,10 +1011,23 @@ static hipError_t launch_column_t(const StepDesc &d, hipStream_t s)
     return hipGetLastError();
 }
 
-hipError_t launch_column(const StepDesc &d, int rtype, hipStream_t s)
+hipError_t launch_column(const StepDesc &d, int rtype, int wtype, hipStream_t s)
 {
     if (d.n_act <= 0 || d.nsplit <= 0 || d.nitems <= 0) return hipSuccess;
     if (d.N_tp % 16 != 0 || d.N_tp > 128 || d.nw < d.nsplit || !d.C) return hipErrorInvalidValue;
+    if (wtype == W_BF16X3) {
+        if (d.N_tp % 32 != 0 || !d.W2) return hipErrorInvalidValue;
+        const int64_t per_xcd = (d.nitems + 7) / 8;
+        const dim3 grid((unsigned)(per_xcd * 8)), block(256);
+        switch (d.N_tp / 32) {
+        case 1: hipLaunchKernelGGL((column_bf16_kernel<1>), grid, block, 0, s, d, per_xcd); break;
+        case 2: hipLaunchKernelGGL((column_bf16_kernel<2>), grid, block, 0, s, d, per_xcd); break;
+        case 3: hipLaunchKernelGGL((column_bf16_kernel<3>), grid, block, 0, s, d, per_xcd); break;
+        case 4: hipLaunchKernelGGL((column_bf16_kernel<4>), grid, block, 0, s, d, per_xcd); break;
+        default: return hipErrorInvalidValue;
+        }
+        return hipGetLastError();
+    }
     return rtype == R_F64 ? launch_column_t<double>(d, s) : launch_column_t<float>(d, s);
 }
 

@@ -65,8 +65,6 @@ def test_host_side_argument_validation(lib):
     assert lib.oed_create(ctypes.byref(h), fake, 0, 64, 4, 16, 1.0, None, ctypes.byref(bad)) == E_ARG
     bad.max_budget = 0
     assert lib.oed_create(ctypes.byref(h), fake, 0, 4 * 160, 4, 160, 1.0, None, ctypes.byref(bad)) == 6
-    bad.precision = 2      # left-looking: FP64 and MIXED_F32 only
-    assert lib.oed_create(ctypes.byref(h), fake, 0, 64, 4, 16, 1.0, None, ctypes.byref(bad)) == 6
     bad = oed_options()
     lib.oed_options_init(ctypes.byref(bad))
     bad.delay = 5

@@ -45,7 +45,7 @@ def runs(big):
         print(f"greedy {prec} B={spec.budget}", flush=True)
         with Selector(K, spec.N_s, spec.N_t, s2, precision=prec) as sel:
             out[prec] = sel.greedy(spec.budget)
-    for prec in ("fp64", "mixed_f32"):
+    for prec in PRECS:
         print(f"greedy left-looking {prec} B={spec.budget}", flush=True)
         with Selector(K, spec.N_s, spec.N_t, s2, precision=prec, method="left", max_budget=spec.budget) as sel:
             out["left_" + prec] = sel.greedy(spec.budget)
@@ -144,7 +144,7 @@ def test_subsample_100_against_oracle(big, prec):
 
 
 @pytest.mark.timeout(900)
-@pytest.mark.parametrize("prec", ["fp64", "mixed_f32"])
+@pytest.mark.parametrize("prec", PRECS)
 def test_fullsize_left_looking(big, runs, prec):
     """Left-looking selection at full size: the picks of the right-looking FP64 path, gains within
     the precision's tolerance, and the telescoping identity."""
