@@ -587,13 +587,13 @@ __device__ void pick_lds_body(const StepDesc &d, double *lds)
 // Kernels: single instance (descriptor by value) and batched (descriptor array).
 
 template <typename TR, typename TW>
-__global__ void __launch_bounds__(256) gain_regs_kernel(StepDesc d)
+__global__ void __launch_bounds__(256, 3) gain_regs_kernel(StepDesc d)
 {
     gain_regs_body<TR, TW>(d, blockIdx.x);
 }
 
 template <typename TR, typename TW>
-__global__ void __launch_bounds__(256) gain_regs_batched(const StepDesc *__restrict__ ds, int n)
+__global__ void __launch_bounds__(256, 3) gain_regs_batched(const StepDesc *__restrict__ ds, int n)
 {
     const int i = find_instance(ds, n, blockIdx.x);
     if (i < 0) return;
