@@ -225,12 +225,11 @@ struct HeldProd<unsigned short> {
 // With held W blocks (slots 0 .. nheld-1 of d.W, candidate offset pofs) the factored matrix is
 // R_jj - sum_h P_h,j P_h,j^T, the candidate's current Schur block.
 template <typename TR, typename TW>
-__device__ __forceinline__ bool chol_regs(const TR *__restrict__ Rb, int N_t, int nb, double *colbuf, double *piv,
-                                          double *Lout, const StepDesc &d, int64_t pofs)
+__device__ __forceinline__ void load_block(double (&A)[2][8][4], const TR *__restrict__ Rb, int N_t, int nb,
+                                           const StepDesc &d, int64_t pofs)
 {
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     const int nbr = (N_t + 15) >> 4;
-    double A[2][8][4];
 #pragma unroll
     for (int h = 0; h < 2; ++h) {
         const int I = h ? 7 - w : w;
@@ -277,6 +276,15 @@ __device__ __forceinline__ bool chol_regs(const TR *__restrict__ Rb, int N_t, in
                 }
         }
     }
+}
+
+template <typename TR, typename TW>
+__device__ __forceinline__ bool chol_regs(const TR *__restrict__ Rb, int N_t, int nb, double *colbuf, double *piv,
+                                          double *Lout, const StepDesc &d, int64_t pofs)
+{
+    const int nbr = (N_t + 15) >> 4;
+    double A[2][8][4];
+    load_block<TR, TW>(A, Rb, N_t, nb, d, pofs);
     bool ok = chol_block<0>(A, N_t, nbr, colbuf, piv, Lout);
     if (ok && nbr > 1) ok = chol_block<1>(A, N_t, nbr, colbuf, piv, Lout);
     if (ok && nbr > 2) ok = chol_block<2>(A, N_t, nbr, colbuf, piv, Lout);
@@ -289,90 +297,94 @@ __device__ __forceinline__ bool chol_regs(const TR *__restrict__ Rb, int N_t, in
     return ok;
 }
 
-// 1/2 sum_{j < n} ln piv[j] (n <= 256), the same value in every thread (fixed reduction order).
-__device__ __forceinline__ double half_sum_log(const double *piv, int n, double *red)
-{
-    const int tid = threadIdx.x, lane = tid & 63;
-    double v = tid < n ? log(piv[tid]) : 0.0;
-    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
-    if (lane == 0) red[tid >> 6] = v;
-    __syncthreads();
-    const double t = (red[0] + red[1]) + (red[2] + red[3]);
-    __syncthreads();
-    return 0.5 * t;
-}
-
-// One block row JB (16 rows) of the register-resident inverse (see inverse_regs); JB is a
-// compile-time constant so the published registers and the column range are fixed.
+// One block column JB of the factorisation with the inverse carried along: the elimination of
+// column j (row t -= (a_tj / d_j) row j, t > j) is applied to X, which starts as the identity,
+// with the same multipliers; row j of X is final at step j, so its owners publish it together
+// with column j of A and one barrier serves both.  At the end X = Lu^-1 for A = Lu D Lu^T (Lu unit
+// lower), and L^-1 = D^-1/2 X.
 template <int JB>
-__device__ __forceinline__ void inv_block(double (&X)[2][8][4], const double *Lout, int N_t, int nbr, double *rowbuf)
+__device__ __forceinline__ bool cholinv_block(double (&A)[2][8][4], double (&X)[2][8][4], int N_t, int nbr,
+                                              double *colbuf, double *rowbuf, double *piv)
 {
-    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, g = lane >> 4, l16 = lane & 15;
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6, g = lane >> 4, l16 = lane & 15;
     const int jend = min(16, N_t - 16 * JB);
     for (int jl = 0; jl < jend; ++jl) {
         const int j = 16 * JB + jl;
-        // the owners of row j (lanes of group g = jl/4, register j%4) publish all four of their
-        // rows, so no register is selected by a run-time index; readers take slot j%4
+        double *buf = colbuf + ((j & 1) << 7);
         double *rb = rowbuf + ((j & 1) << 9);
-        if (g == (jl >> 2)) {
 #pragma unroll
-            for (int h = 0; h < 2; ++h) {
-                const int I = h ? 7 - w : w;
-                if (I == JB) {
+        for (int h = 0; h < 2; ++h) {
+            const int I = h ? 7 - w : w;
+            if (l16 == jl && I < nbr && I >= JB) {
 #pragma unroll
-                    for (int J = 0; J <= JB; ++J)
+                for (int r = 0; r < 4; ++r) buf[16 * I + 4 * g + r] = A[h][JB][r];
+            }
+            // the owners of row j (group jl / 4 of block row JB) publish all four of their rows
+            if (g == (jl >> 2) && I == JB) {
 #pragma unroll
-                        for (int r = 0; r < 4; ++r) rb[(r << 7) + 16 * J + l16] = X[h][J][r];
-                }
+                for (int J = 0; J <= JB; ++J)
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) rb[(r << 7) + 16 * J + l16] = X[h][J][r];
             }
         }
         __syncthreads();
         const double *rj = rb + ((j & 3) << 7);
-        double xv[8], lv[2][4], dl[4];
+        double bu[8], bt[2][4], dv[4], xv[8];
 #pragma unroll
-        for (int J = 0; J < 8; ++J) xv[J] = rj[16 * J + l16];
+        for (int J = 0; J < 8; ++J) bu[J] = buf[16 * J + l16];
+#pragma unroll
+        for (int J = 0; J < 8; ++J) xv[J] = J <= JB ? rj[16 * J + l16] : 0.0;
 #pragma unroll
         for (int h = 0; h < 2; ++h) {
             const int I = h ? 7 - w : w;
 #pragma unroll
-            for (int r = 0; r < 4; ++r) lv[h][r] = Lout[tri(min(16 * I + 4 * g + r, N_t - 1)) + j];
+            for (int r = 0; r < 4; ++r) bt[h][r] = buf[16 * I + 4 * g + r];
         }
-        dl[0] = Lout[tri(j) + j];
-        dl[1] = dl[2] = dl[3] = 0.0;
+        dv[0] = buf[j];
+        dv[1] = dv[2] = dv[3] = 0.0;
+        pin8(bu);
         pin8(xv);
-        pin4(lv[0]);
-        pin4(lv[1]);
-        pin4(dl);
-        const double inv_ljj = 1.0 / dl[0];
+        pin4(bt[0]);
+        pin4(bt[1]);
+        pin4(dv);
+        const double dd = dv[0];
+        if (!(dd > 0.0) || !isfinite(dd)) return false;
+        if (tid == 0) piv[j] = dd;
+        const double inv_d = 1.0 / dd;
 #pragma unroll
         for (int h = 0; h < 2; ++h) {
             const int I = h ? 7 - w : w;
             if (I < nbr && I >= JB) {
-                double lt[4];
+                double wt[4];
 #pragma unroll
-                for (int r = 0; r < 4; ++r) {
-                    const int t = 16 * I + 4 * g + r;
-                    lt[r] = (t > j && t < N_t) ? lv[h][r] * inv_ljj : 0.0;
+                for (int r = 0; r < 4; ++r) wt[r] = 16 * I + 4 * g + r > j ? bt[h][r] * inv_d : 0.0;
+#pragma unroll
+                for (int J = JB; J < 8; ++J) {
+                    const double au = (16 * J + l16 > j && J <= I) ? bu[J] : 0.0;
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) A[h][J][r] = fma(-wt[r], au, A[h][J][r]);
                 }
 #pragma unroll
                 for (int J = 0; J <= JB; ++J)
 #pragma unroll
-                    for (int r = 0; r < 4; ++r) X[h][J][r] = fma(-lt[r], xv[J], X[h][J][r]);
+                    for (int r = 0; r < 4; ++r) X[h][J][r] = fma(-wt[r], xv[J], X[h][J][r]);
             }
         }
     }
+    return true;
 }
 
-// Inverse X = L^-1 of the packed lower factor in LDS, register-resident with the ownership of
-// chol_regs (rowbuf: LDS, 2 x 4 x 128 doubles).  Row-oriented elimination: row j of X, once all earlier rows have been subtracted
-// from it, equals L_jj times its final value; its owners publish it and every thread applies
-// X[t][c] -= (L[t][j] / L_jj) X[j][c] for t > j.  Rows are divided by their L_tt at the end.
-// The result goes to global memory in operand order (N_tp x N_tp, identity on the padding).
-__device__ __forceinline__ void inverse_regs(const double *Lout, int N_t, int N_tp, double *rowbuf, double *__restrict__ Linv)
+// Factor the diagonal block (with the held correction, as chol_regs) and write L^-1 in operand
+// order (N_tp x N_tp, identity on the padding) to Linv.  rowbuf: LDS, 2 x 4 x 128 doubles.
+template <typename TR, typename TW>
+__device__ __forceinline__ bool chol_inv_regs(const TR *__restrict__ Rb, int N_t, int N_tp, double *colbuf,
+                                              double *rowbuf, double *piv, const StepDesc &d, int64_t pofs,
+                                              double *__restrict__ Linv)
 {
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6, g = lane >> 4, l16 = lane & 15;
     const int nbr = (N_t + 15) >> 4, nb = N_tp >> 4;
-    double X[2][8][4];
+    double A[2][8][4], X[2][8][4];
+    load_block<TR, TW>(A, Rb, N_t, nb, d, pofs);
 #pragma unroll
     for (int h = 0; h < 2; ++h) {
         const int I = h ? 7 - w : w;
@@ -381,14 +393,16 @@ __device__ __forceinline__ void inverse_regs(const double *Lout, int N_t, int N_
 #pragma unroll
             for (int r = 0; r < 4; ++r) X[h][J][r] = (J == I && 4 * g + r == l16) ? 1.0 : 0.0;
     }
-    inv_block<0>(X, Lout, N_t, nbr, rowbuf);
-    if (nbr > 1) inv_block<1>(X, Lout, N_t, nbr, rowbuf);
-    if (nbr > 2) inv_block<2>(X, Lout, N_t, nbr, rowbuf);
-    if (nbr > 3) inv_block<3>(X, Lout, N_t, nbr, rowbuf);
-    if (nbr > 4) inv_block<4>(X, Lout, N_t, nbr, rowbuf);
-    if (nbr > 5) inv_block<5>(X, Lout, N_t, nbr, rowbuf);
-    if (nbr > 6) inv_block<6>(X, Lout, N_t, nbr, rowbuf);
-    if (nbr > 7) inv_block<7>(X, Lout, N_t, nbr, rowbuf);
+    bool ok = cholinv_block<0>(A, X, N_t, nbr, colbuf, rowbuf, piv);
+    if (ok && nbr > 1) ok = cholinv_block<1>(A, X, N_t, nbr, colbuf, rowbuf, piv);
+    if (ok && nbr > 2) ok = cholinv_block<2>(A, X, N_t, nbr, colbuf, rowbuf, piv);
+    if (ok && nbr > 3) ok = cholinv_block<3>(A, X, N_t, nbr, colbuf, rowbuf, piv);
+    if (ok && nbr > 4) ok = cholinv_block<4>(A, X, N_t, nbr, colbuf, rowbuf, piv);
+    if (ok && nbr > 5) ok = cholinv_block<5>(A, X, N_t, nbr, colbuf, rowbuf, piv);
+    if (ok && nbr > 6) ok = cholinv_block<6>(A, X, N_t, nbr, colbuf, rowbuf, piv);
+    if (ok && nbr > 7) ok = cholinv_block<7>(A, X, N_t, nbr, colbuf, rowbuf, piv);
+    __syncthreads();
+    if (!ok) return false;
     // sub-blocks outside the factored part: zero above the diagonal, identity on the padding
     for (int o = tid; o < N_tp * N_tp; o += blockDim.x) {
         const int sb = o >> 8, ww = o & 255, ln = ww >> 2, reg = ww & 3;
@@ -406,7 +420,7 @@ __device__ __forceinline__ void inverse_regs(const double *Lout, int N_t, int N_
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
                 const int t = 16 * I + 4 * g + r;
-                il[r] = t < N_t ? 1.0 / Lout[tri(t) + t] : 1.0;
+                il[r] = t < N_t ? 1.0 / sqrt(piv[t]) : 1.0;
             }
 #pragma unroll
             for (int J = 0; J < 8; ++J)
@@ -419,7 +433,22 @@ __device__ __forceinline__ void inverse_regs(const double *Lout, int N_t, int N_
                 }
         }
     }
+    return true;
 }
+
+// 1/2 sum_{j < n} ln piv[j] (n <= 256), the same value in every thread (fixed reduction order).
+__device__ __forceinline__ double half_sum_log(const double *piv, int n, double *red)
+{
+    const int tid = threadIdx.x, lane = tid & 63;
+    double v = tid < n ? log(piv[tid]) : 0.0;
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+    if (lane == 0) red[tid >> 6] = v;
+    __syncthreads();
+    const double t = (red[0] + red[1]) + (red[2] + red[3]);
+    __syncthreads();
+    return 0.5 * t;
+}
+
 
 // Argmax of the gains (exact ties -> lowest position, NaN -> -inf) or the position of a forced
 // sensor.  Returns the position (same in all threads) or -1 after setting the status word.
@@ -503,9 +532,10 @@ __device__ void gain_regs_body(const StepDesc &d, int p)
 }
 
 template <typename TR, typename TW>
-__device__ void pick_regs_body(const StepDesc &d, double *Lout)
+__device__ void pick_regs_body(const StepDesc &d)
 {
-    __shared__ double colbuf[1024];
+    __shared__ double colbuf[256];
+    __shared__ double rowbuf[1024];
     __shared__ double piv[128];
     __shared__ double red[4];
     if (d.state[ST_STATUS] != 0) return;
@@ -516,8 +546,8 @@ __device__ void pick_regs_body(const StepDesc &d, double *Lout)
     const int s = d.act_in[pos];
     for (int p = tid; p < d.n_act - 1; p += blockDim.x) d.act_out[p] = d.act_in[p < pos ? p : p + 1];
     const int64_t bs = (int64_t)d.N_tp * d.N_tp;
-    const bool ok = chol_regs<TR, TW>((const TR *)d.R + blk_index(s, s) * bs, d.N_t, d.N_tp >> 4, colbuf, piv, Lout, d,
-                                      s * bs);
+    const bool ok = chol_inv_regs<TR, TW>((const TR *)d.R + blk_index(s, s) * bs, d.N_t, d.N_tp, colbuf, rowbuf, piv, d,
+                                          s * bs, d.Linv);
     if (!ok) {
         if (tid == 0) d.state[ST_STATUS] = 2;
         return;
@@ -529,7 +559,6 @@ __device__ void pick_regs_body(const StepDesc &d, double *Lout)
         d.state[ST_NPICKS] = d.step + 1;
         d.state[ST_LAST] = s;
     }
-    inverse_regs(Lout, d.N_t, d.N_tp, colbuf, d.Linv);
 }
 
 template <typename TR>
@@ -601,21 +630,20 @@ __global__ void __launch_bounds__(256, 3) gain_regs_batched(const StepDesc *__re
     gain_regs_body<TR, TW>(d, (int)(blockIdx.x - d.item0));
 }
 
+// One work-group per pick: 512 registers per lane hold the block and its inverse.
 template <typename TR, typename TW>
-__global__ void __launch_bounds__(256) pick_regs_kernel(StepDesc d)
+__global__ void __launch_bounds__(256, 1) pick_regs_kernel(StepDesc d)
 {
-    extern __shared__ double dyn[];
-    pick_regs_body<TR, TW>(d, dyn);
+    pick_regs_body<TR, TW>(d);
 }
 
 template <typename TR, typename TW>
-__global__ void __launch_bounds__(256) pick_regs_batched(const StepDesc *__restrict__ ds, int n)
+__global__ void __launch_bounds__(256, 1) pick_regs_batched(const StepDesc *__restrict__ ds, int n)
 {
-    extern __shared__ double dyn[];
     const int i = find_instance(ds, n, blockIdx.x);
     if (i < 0) return;
     const StepDesc d = ds[i];
-    pick_regs_body<TR, TW>(d, dyn);
+    pick_regs_body<TR, TW>(d);
 }
 
 template <typename TR>
@@ -686,9 +714,7 @@ template <typename TR, typename TW>
 static hipError_t launch_pick_t(const StepDesc &d, hipStream_t s)
 {
     if (d.N_t <= REGS_MAX_NT) {
-        const size_t lds = sizeof(double) * (size_t)d.N_t * (d.N_t + 1) / 2;
-        allow_lds(pick_regs_kernel<TR, TW>, lds);
-        hipLaunchKernelGGL((pick_regs_kernel<TR, TW>), dim3(1), dim3(256), lds, s, d);
+        hipLaunchKernelGGL((pick_regs_kernel<TR, TW>), dim3(1), dim3(256), 0, s, d);
     } else {
         if (d.nheld) return hipErrorInvalidValue;
         const size_t lds = d.scratch ? 0 : pick_lds_bytes(d.N_t);
@@ -735,10 +761,9 @@ hipError_t launch_gain_batched(const StepDesc *descs, int n, int64_t total, int 
 }
 
 template <typename TR, typename TW>
-static void pick_batched_t(const StepDesc *descs, int n, size_t lds, hipStream_t s)
+static void pick_batched_t(const StepDesc *descs, int n, size_t, hipStream_t s)
 {
-    allow_lds(pick_regs_batched<TR, TW>, lds);
-    hipLaunchKernelGGL((pick_regs_batched<TR, TW>), dim3(n), dim3(256), lds, s, descs, n);
+    hipLaunchKernelGGL((pick_regs_batched<TR, TW>), dim3(n), dim3(256), 0, s, descs, n);
 }
 
 hipError_t launch_pick_batched(const StepDesc *descs, int n, int max_Nt, int rtype, int wtype, hipStream_t s)
