@@ -101,7 +101,7 @@ typedef struct oed_options {
                                    1 = subtract every pick's W W^T at the next step; 0 = automatic
                                    (2 for N_t <= 128, else 1).  p > 1 with N_t > 128:
                                    OED_E_UNSUPPORTED */
-    int32_t method;             /* OED_METHOD_RIGHT_LOOKING (default) or OED_METHOD_LEFT_LOOKING */
+    int32_t method;             /* OED_METHOD_RIGHT_LOOKING (default), _LEFT_LOOKING or _AUTO */
     int32_t max_budget;         /* left-looking: most picks the handle will make (the W history
                                    is allocated for them); 0 = all candidates */
     int32_t reserved[4];        /* must be 0 */
@@ -119,6 +119,10 @@ typedef struct oed_options {
  */
 #define OED_METHOD_RIGHT_LOOKING 0
 #define OED_METHOD_LEFT_LOOKING 1
+/* AUTO: left-looking when it needs fewer flops, i.e. for max_budget <= N_c / 2 (per pick k the
+   column costs 2 k N_t^3 per remaining candidate against (N_c - k) N_t^3 for the downdate), and
+   N_t <= 128; else right-looking. */
+#define OED_METHOD_AUTO 2
 
 /* Fill *opt with the defaults (FP64, no flags, all sensors). */
 OED_API void oed_options_init(oed_options *opt);
@@ -259,7 +263,8 @@ OED_API oed_status oed_device_bytes(const oed_ctx *h, int64_t *bytes);
 
 /*
  * The configuration the handle runs with: *delay (1..4), *syrk_variant (0: per-wave global
- * operands, 1: LDS-staged), and, if per_pick_ms is not NULL, the autotuner's estimate of the
+ * operands, 1: LDS-staged, -1: left-looking, no downdate), and, if per_pick_ms is not NULL, the
+ * autotuner's estimate of the
  * time per pick for delay depths 1..4 (4 doubles, host; 0 where not measured, all 0 without
  * OED_FLAG_AUTOTUNE).  Any output pointer may be NULL.
  */

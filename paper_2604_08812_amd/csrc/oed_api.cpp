@@ -532,7 +532,8 @@ oed_status oed_create(oed_ctx **out, const void *K, int32_t dtype, int64_t ld, i
         return OED_E_ARG;
     if (o.precision == OED_PREC_MIXED_BF16X3 && N_t > 128) return OED_E_UNSUPPORTED;
     if (o.delay < 0 || o.delay > MAX_DELAY) return OED_E_ARG;
-    if (o.method != OED_METHOD_RIGHT_LOOKING && o.method != OED_METHOD_LEFT_LOOKING) return OED_E_ARG;
+    if (o.method != OED_METHOD_RIGHT_LOOKING && o.method != OED_METHOD_LEFT_LOOKING && o.method != OED_METHOD_AUTO)
+        return OED_E_ARG;
     if (o.max_budget < 0 || o.max_budget > N_s) return OED_E_ARG;
     if (o.method == OED_METHOD_LEFT_LOOKING && N_t > REGS_MAX_NT) return OED_E_UNSUPPORTED;
     if (o.delay > 1 && N_t > REGS_MAX_NT) return OED_E_UNSUPPORTED;
@@ -556,6 +557,11 @@ oed_status oed_create(oed_ctx **out, const void *K, int32_t dtype, int64_t ld, i
     // delay 0 (automatic): hold block columns whenever the register factorisations and the LDS
     // downdate serve the block size
     h->delay = o.delay == 0 ? (N_t <= REGS_MAX_NT ? MAX_DELAY : 1) : o.delay;
+    if (o.method == OED_METHOD_AUTO) {
+        const int nc = o.candidates ? o.n_candidates : N_s;
+        const int mb = o.max_budget > 0 ? std::min(o.max_budget, nc) : nc;
+        o.method = (N_t <= REGS_MAX_NT && 2 * mb <= nc) ? OED_METHOD_LEFT_LOOKING : OED_METHOD_RIGHT_LOOKING;
+    }
     h->left = o.method == OED_METHOD_LEFT_LOOKING;
     if (h->left) h->delay = 1;
     const bool tune = !h->left && o.delay == 0 && (o.flags & OED_FLAG_AUTOTUNE) && N_t <= REGS_MAX_NT;
@@ -819,6 +825,10 @@ oed_status oed_get_profile(oed_ctx *h, oed_profile *out, int32_t reset)
 oed_status oed_get_config(const oed_ctx *h, int32_t *delay, int32_t *syrk_variant, double *per_pick_ms)
 {
     if (!h) return OED_E_ARG;
+    if (syrk_variant && h->left) {
+        *syrk_variant = -1;
+        syrk_variant = nullptr;
+    }
     if (delay) *delay = h->delay;
     if (syrk_variant) *syrk_variant = h->syrk_variant;
     if (per_pick_ms) std::copy(h->tuned_ms, h->tuned_ms + MAX_DELAY, per_pick_ms);

@@ -138,7 +138,8 @@ def oed_create(K, N_s, N_t, sigma2, precision="fp64", candidates=None, profile=F
                autotune=False, method="right", max_budget=0):
     """Create a handle for the device tensor K (2-D, float64/float32, row-major, lower triangle read).
     delay: downdate delay depth (0 automatic, 1..4); autotune: with delay 0, time the choices;
-    method: "right" (downdate of all of R per pick) or "left" (only the new block column per pick);
+    method: "right" (downdate of all of R per pick), "left" (only the new block column per pick) or
+    "auto" (left when max_budget <= half the candidates);
     max_budget: left-looking W history size (0: all candidates)."""
     import torch
     L = library()
@@ -154,7 +155,7 @@ def oed_create(K, N_s, N_t, sigma2, precision="fp64", candidates=None, profile=F
     opt.precision = PRECISIONS[precision]
     opt.flags = (OED_FLAG_PROFILE if profile else 0) | (OED_FLAG_AUTOTUNE if autotune else 0)
     opt.delay = int(delay)
-    opt.method = {"right": 0, "left": 1}[method]
+    opt.method = {"right": 0, "left": 1, "auto": 2}[method]
     opt.max_budget = int(max_budget)
     cand = None
     if candidates is not None:

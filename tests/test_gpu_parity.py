@@ -327,3 +327,17 @@ def test_left_looking_queries(prec):
     ref = oracle.greedy(K, N_s, N_t, s2, 10, prefix=A)
     assert list(ref["idx"][3:]) == list(np.r_[i1, i2])
     assert np.all(rel_err(np.r_[g1, g2], ref["gain"][3:]) <= RTOL[prec])
+
+
+def test_method_auto():
+    """AUTO takes left-looking for a budget of at most half the candidates (N_t <= 128)."""
+    N_s, N_t = 40, 32
+    K, Kd, s2 = instance(N_s, N_t, 1500, 41)
+    with selector(Kd, N_s, N_t, s2, precision="mixed_f32", method="auto", max_budget=12) as a:
+        assert a.config()[1] == -1
+        ia, ga = a.greedy(12)
+    with selector(Kd, N_s, N_t, s2, precision="mixed_f32", method="auto") as b:
+        assert b.config()[1] in (0, 1)
+        ib, gb = b.greedy(12)
+    assert list(ia) == list(ib)
+    check_trajectory(K, N_s, N_t, s2, ia, ga, RTOL["mixed_f32"])
