@@ -48,6 +48,7 @@ def parse():
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-bf16x3", action="store_true")
     ap.add_argument("--no-left", action="store_true", help="skip the left-looking legs")
+    ap.add_argument("--left", action="store_true", help="batched workload: left-looking method")
     ap.add_argument("--no-gaps", action="store_true", help="skip the per-step top-two gap scan (FP64)")
     ap.add_argument("--delay", type=int, default=0, help="downdate delay depth (0: the library's choice)")
     ap.add_argument("--no-autotune", action="store_true",
@@ -252,8 +253,9 @@ def run_batched(args):
     torch.cuda.synchronize()
     log(f"48 instances formed in {time.perf_counter() - t0:.1f} s")
     total_steps = sum(sp.budget for sp in specs)
-    tune = args.delay == 0 and not args.no_autotune
-    bs = BatchSelector(items, precision=args.precision or "mixed_f32", profile=True, delay=args.delay, autotune=tune)
+    tune = args.delay == 0 and not args.no_autotune and not args.left
+    bs = BatchSelector(items, precision=args.precision or "mixed_f32", profile=True, delay=args.delay, autotune=tune,
+                       method="left" if args.left else "right")
     delay, tuned = bs.config()
     for w in range(args.warmup):
         bs.reset(items)
@@ -278,6 +280,7 @@ def run_batched(args):
         "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
         "config": {"workload": "batched_48_uneven", "instances": len(specs), "total_picks": total_steps,
                    "precision": args.precision or "mixed_f32", "K_dtype": "f32", "delay": delay, "autotuned": tune,
+                   "method": "left-looking" if args.left else "right-looking",
                    "autotuner_run_ms_by_delay": [round(float(x), 3) for x in tuned] if tune else None,
                    "step": "oed_batch_reset + oed_batch_run"},
         "roofline": {"kernel": "whole batched run (graph)", "bound": "hbm", "achieved": round(gbs, 1),

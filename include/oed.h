@@ -225,11 +225,14 @@ typedef struct oed_batch oed_batch;
 /* Without OED_BATCH_DELAY: run the whole selection once per delay depth during creation and
    keep the fastest (see oed_batch_get_config). */
 #define OED_BATCH_AUTOTUNE 0x10u
+/* Left-looking method for every instance (see OED_METHOD_LEFT_LOOKING; no delay, no autotuner). */
+#define OED_BATCH_LEFT_LOOKING 0x20u
 
 /*
  * Create a batch over inst[0..n): validates every instance, allocates all device memory,
  * packs every working copy and builds the launch schedule.  flags: OED_FLAG_PROFILE (time
- * each run with HIP events), OED_BATCH_NO_GRAPH, OED_BATCH_DELAY(p), OED_BATCH_AUTOTUNE.  On failure
+ * each run with HIP events), OED_BATCH_NO_GRAPH, OED_BATCH_DELAY(p), OED_BATCH_AUTOTUNE,
+ * OED_BATCH_LEFT_LOOKING.  On failure
  * *out is NULL.
  */
 OED_API oed_status oed_batch_create(oed_batch **out, const oed_instance *inst, int32_t n, int32_t precision,

@@ -31,12 +31,15 @@ struct Inst {
     void *R = nullptr, *W = nullptr, *W2 = nullptr;  // `delay` W slots (BF16: hi, lo parts)
     int64_t wslot = 0;                               // elements per W slot
     double *V = nullptr;
+    void *C = nullptr;  // left-looking column partial sums (LEFT_SPLITS x N_s blocks, R's type)
     double *Linv = nullptr, *gains = nullptr, *pick_gain = nullptr;
     int *act[2] = {nullptr, nullptr}, *cmap = nullptr, *picks = nullptr, *state = nullptr;
     size_t off_gain = 0, off_int = 0;  // offsets of this instance's results in the results block
 };
 
-enum LaunchKind { L_INIT, L_GAIN, L_PICK, L_VCORR, L_TRSM, L_SYRK };
+enum LaunchKind { L_INIT, L_GAIN, L_PICK, L_VCORR, L_TRSM, L_SYRK, L_COLUMN };
+
+constexpr int LEFT_SPLITS = 4;
 
 struct Launch {
     int kind = L_INIT;
@@ -63,6 +66,7 @@ struct oed_batch {
     std::vector<Inst> in;
     int prec = OED_PREC_FP64, rtype = R_F64, wtype = W_F64;
     int delay = 2;
+    bool left = false;  // left-looking: W slot k holds pick k's block column
     double tuned_ms[MAX_DELAY] = {0};  // autotuner: eager run time for delay 1..MAX_DELAY
     uint32_t flags = 0;
     hipStream_t stream = nullptr;
@@ -169,12 +173,117 @@ StepDesc inst_desc(const Inst &x, int k, bool after_pick, int delay)
     return d;
 }
 
+// Left-looking descriptor of instance x at step k.  Before the pick (gains) the newest block
+// column, slot k - 1, is applied to the diagonal blocks in place; after the pick the column kernel
+// sums slots 0 .. k-1 and the block column of pick k goes to slot k.
+StepDesc inst_desc_left(const oed_batch *b, const Inst &x, int k, bool after_pick)
+{
+    StepDesc d = inst_desc(x, k, after_pick, 1);
+    const size_t we = b->wtype == W_F64 ? 8 : b->wtype == W_F32 ? 4 : 2;
+    const int64_t bs = (int64_t)x.N_tp * x.N_tp;
+    d.nheld = 0;
+    if (!after_pick) {
+        if (k >= 1) {
+            d.W = (char *)x.W + (size_t)((k - 1) * x.wslot) * we;
+            if (x.W2) d.W2 = (char *)x.W2 + (size_t)((k - 1) * x.wslot) * 2;
+            d.nheld = 1;
+            d.wb = 1;
+        }
+        return d;
+    }
+    d.C = x.C;
+    d.cstride = (int64_t)x.N_s * bs;
+    d.nsplit = std::min(LEFT_SPLITS, k);
+    d.nw = k;
+    return d;
+}
+
+// Output slot k of the block-column launch after pick k (left-looking).
+void left_out_slot(const oed_batch *b, const Inst &x, int k, StepDesc &d)
+{
+    const size_t we = b->wtype == W_F64 ? 8 : b->wtype == W_F32 ? 4 : 2;
+    d.W = (char *)x.W + (size_t)(k * x.wslot) * we;
+    if (x.W2) d.W2 = (char *)x.W2 + (size_t)(k * x.wslot) * 2;
+}
+
+void build_schedule_left(oed_batch *b)
+{
+    const double e = b->rtype == R_F64 ? 8.0 : 4.0;
+    int maxB = 0;
+    for (size_t i = 0; i < b->in.size(); ++i) {
+        maxB = std::max(maxB, b->in[i].budget);
+        Launch L = make_launch(L_INIT, 0);
+        L.inst = (int)i;
+        b->launches.push_back(L);
+    }
+    for (int k = 0; k < maxB; ++k) {
+        Launch g = make_launch(L_GAIN, (int64_t)b->descs.size());
+        for (const Inst &x : b->in)
+            if (x.budget > k) {
+                StepDesc d = inst_desc_left(b, x, k, false);
+                d.item0 = g.total;
+                d.nitems = d.n_act;
+                g.total += d.nitems;
+                b->descs.push_back(d);
+                ++g.ndesc;
+            }
+        b->launches.push_back(g);
+        Launch p = make_launch(L_PICK, (int64_t)b->descs.size());
+        for (const Inst &x : b->in)
+            if (x.budget > k) {
+                StepDesc d = inst_desc_left(b, x, k, false);
+                d.nheld = 0;
+                d.wb = 0;
+                d.item0 = p.total;
+                d.nitems = 1;
+                p.total += 1;
+                p.max_Nt = std::max(p.max_Nt, x.N_t);
+                b->descs.push_back(d);
+                ++p.ndesc;
+            }
+        b->launches.push_back(p);
+        // block column of pick k for the instances that pick again
+        std::map<int, std::vector<const Inst *>> by_ntp;
+        for (const Inst &x : b->in)
+            if (x.budget > k + 1 && k >= 1) by_ntp[x.N_tp].push_back(&x);
+        for (auto &kv : by_ntp) {
+            Launch c = make_launch(L_COLUMN, (int64_t)b->descs.size());
+            c.N_tp = kv.first;
+            for (const Inst *x : kv.second) {
+                StepDesc d = inst_desc_left(b, *x, k, true);
+                d.item0 = c.total;
+                d.nitems = (int64_t)d.nsplit * syrk_tile_rows(d.n_act, d.N_tp);
+                c.total += d.nitems;
+                b->descs.push_back(d);
+                ++c.ndesc;
+                const double n = (double)d.n_act * x->N_t;
+                b->syrk_flops += 2.0 * n * x->N_t * k * x->N_t;
+                b->syrk_bytes += e * (n * k * x->N_t + (double)k * x->N_t * x->N_t + d.nsplit * n * x->N_t);
+            }
+            b->launches.push_back(c);
+        }
+        Launch t = make_launch(L_TRSM, (int64_t)b->descs.size());
+        for (const Inst &x : b->in)
+            if (x.budget > k + 1) {
+                StepDesc d = inst_desc_left(b, x, k, true);
+                left_out_slot(b, x, k, d);
+                d.item0 = t.total;
+                d.nitems = d.n_act;
+                t.total += d.nitems;
+                b->descs.push_back(d);
+                ++t.ndesc;
+            }
+        if (t.ndesc) b->launches.push_back(t);
+    }
+}
+
 // Build the descriptor array and the launch list of one run.
 void build_schedule(oed_batch *b)
 {
     b->descs.clear();
     b->launches.clear();
     b->syrk_flops = b->syrk_bytes = 0;
+    if (b->left) return build_schedule_left(b);
     const double e = b->rtype == R_F64 ? 8.0 : 4.0;
     int maxB = 0;
     for (size_t i = 0; i < b->in.size(); ++i) {
@@ -277,6 +386,9 @@ oed_status enqueue_run(oed_batch *b)
         case L_GAIN: BCHK(b, launch_gain_batched(d, L.ndesc, L.total, b->rtype, b->wtype, b->stream)); break;
         case L_PICK: BCHK(b, launch_pick_batched(d, L.ndesc, L.max_Nt, b->rtype, b->wtype, b->stream)); break;
         case L_VCORR: BCHK(b, launch_vcorr_batched(d, L.ndesc, L.total, b->wtype, b->stream)); break;
+        case L_COLUMN:
+            BCHK(b, launch_column_batched(d, L.ndesc, L.total, L.N_tp, b->rtype, b->wtype, b->stream));
+            break;
         case L_TRSM: BCHK(b, launch_trsm_batched(d, L.ndesc, L.total, b->rtype, b->wtype, b->stream)); break;
         case L_SYRK:
             BCHK(b, launch_syrk_batched(d, L.ndesc, L.total, L.N_tp, L.nw, b->rtype, b->wtype, SYRK_LDS, b->stream));
@@ -337,8 +449,10 @@ oed_status oed_batch_create(oed_batch **out, const oed_instance *inst, int32_t n
     b->wtype = precision == OED_PREC_FP64 ? W_F64 : precision == OED_PREC_MIXED_F32 ? W_F32 : W_BF16X3;
     b->flags = flags;
     b->delay = (int)((flags >> 8) & 0xFu);
-    const bool tune = b->delay == 0 && (flags & OED_BATCH_AUTOTUNE);
+    b->left = (flags & OED_BATCH_LEFT_LOOKING) != 0;
+    const bool tune = !b->left && b->delay == 0 && (flags & OED_BATCH_AUTOTUNE);
     if (b->delay == 0) b->delay = MAX_DELAY;
+    if (b->left) b->delay = 1;
     auto setup = [&]() -> oed_status {
         // the caller's K must be complete before the batch stream reads it
         BCHK(b, hipStreamSynchronize((hipStream_t)stream));
@@ -362,13 +476,15 @@ oed_status oed_batch_create(oed_batch **out, const oed_instance *inst, int32_t n
             const int64_t bs = (int64_t)x.N_tp * x.N_tp, nblk = (int64_t)x.N_s * (x.N_s + 1) / 2;
             BCHK(b, balloc(b, &x.R, (size_t)(nblk * bs) * er));
             x.wslot = x.N_s * bs;
+            const int slots = b->left ? x.budget : b->delay;
             if (b->wtype == W_BF16X3) {
-                BCHK(b, balloc(b, &x.W, (size_t)(b->delay * x.wslot) * 2));
-                BCHK(b, balloc(b, &x.W2, (size_t)(b->delay * x.wslot) * 2));
+                BCHK(b, balloc(b, &x.W, (size_t)(slots * x.wslot) * 2));
+                BCHK(b, balloc(b, &x.W2, (size_t)(slots * x.wslot) * 2));
             } else {
-                BCHK(b, balloc(b, &x.W, (size_t)(b->delay * x.wslot) * er));
+                BCHK(b, balloc(b, &x.W, (size_t)(slots * x.wslot) * er));
             }
             if (b->delay > 1) BCHK(b, balloc(b, (void **)&x.V, sizeof(double) * bs * (b->delay - 1)));
+            if (b->left) BCHK(b, balloc(b, &x.C, (size_t)(LEFT_SPLITS * x.N_s * bs) * er));
             BCHK(b, balloc(b, (void **)&x.Linv, sizeof(double) * bs));
             BCHK(b, balloc(b, (void **)&x.gains, sizeof(double) * x.N_s));
             BCHK(b, balloc(b, (void **)&x.act[0], sizeof(int) * x.N_s));

@@ -122,6 +122,9 @@ hipError_t launch_trsm(const StepDesc &d, int rtype, int wtype, hipStream_t s);
 // Left-looking block column (Algorithm 1's order): partial sums of sum_h W_h,i W_h,s^T over the
 // d.nw W slots, split in d.nsplit parts (d.nitems = nsplit * row tiles), for every remaining i.
 hipError_t launch_column(const StepDesc &d, int rtype, int wtype, hipStream_t s);
+// Batched: one common N_tp per launch; each descriptor's nitems = nsplit * its row tiles.
+hipError_t launch_column_batched(const StepDesc *descs, int n, int64_t total, int N_tp, int rtype, int wtype,
+                                 hipStream_t s);
 // Downdate kernels: SYRK_DIRECT streams W operands from global memory per wave (any N_tp);
 // SYRK_LDS stages them through LDS with a software pipeline (N_tp <= 128).  W_BF16X3 always
 // runs the BF16 split-product kernel (N_tp a multiple of 32, <= 128).

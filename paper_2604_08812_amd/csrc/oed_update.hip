@@ -847,6 +847,30 @@ __global__ void __launch_bounds__(256, 2) column_bf16_kernel(StepDesc d, int64_t
     column_bf16_body<NB32>(d, item);
 }
 
+template <typename T, int NB>
+__global__ void __launch_bounds__(256, 2) column_batched(const StepDesc *__restrict__ ds, int n, int64_t total,
+                                                         int64_t per_xcd)
+{
+    const int64_t item = xcd_item(blockIdx.x, per_xcd);
+    if (item >= total) return;
+    const int i = find_instance(ds, n, item);
+    if (i < 0) return;
+    const StepDesc d = ds[i];
+    column_body<T, NB>(d, item - d.item0);
+}
+
+template <int NB32>
+__global__ void __launch_bounds__(256, 2) column_bf16_batched(const StepDesc *__restrict__ ds, int n, int64_t total,
+                                                              int64_t per_xcd)
+{
+    const int64_t item = xcd_item(blockIdx.x, per_xcd);
+    if (item >= total) return;
+    const int i = find_instance(ds, n, item);
+    if (i < 0) return;
+    const StepDesc d = ds[i];
+    column_bf16_body<NB32>(d, item - d.item0);
+}
+
 template <typename TW>
 __global__ void __launch_bounds__(64) vcorr_kernel(StepDesc d)
 {
@@ -1029,6 +1053,46 @@ hipError_t launch_column(const StepDesc &d, int rtype, int wtype, hipStream_t s)
         return hipGetLastError();
     }
     return rtype == R_F64 ? launch_column_t<double>(d, s) : launch_column_t<float>(d, s);
+}
+
+hipError_t launch_column_batched(const StepDesc *descs, int n, int64_t total, int N_tp, int rtype, int wtype,
+                                 hipStream_t s)
+{
+    if (n <= 0 || total <= 0) return hipSuccess;
+    if (N_tp % 16 != 0 || N_tp > 128) return hipErrorInvalidValue;
+    const int64_t per_xcd = (total + 7) / 8;
+    const dim3 grid((unsigned)(per_xcd * 8)), block(256);
+    if (wtype == W_BF16X3) {
+        switch (N_tp / 32) {
+        case 1: hipLaunchKernelGGL((column_bf16_batched<1>), grid, block, 0, s, descs, n, total, per_xcd); break;
+        case 2: hipLaunchKernelGGL((column_bf16_batched<2>), grid, block, 0, s, descs, n, total, per_xcd); break;
+        case 3: hipLaunchKernelGGL((column_bf16_batched<3>), grid, block, 0, s, descs, n, total, per_xcd); break;
+        case 4: hipLaunchKernelGGL((column_bf16_batched<4>), grid, block, 0, s, descs, n, total, per_xcd); break;
+        default: return hipErrorInvalidValue;
+        }
+        return hipGetLastError();
+    }
+    switch (N_tp / 16) {
+#define OED_COLB_CASE(NBV)                                                                                         \
+    case NBV:                                                                                                      \
+        if (rtype == R_F64)                                                                                        \
+            hipLaunchKernelGGL((column_batched<double, NBV>), grid, block, 0, s, descs, n, total, per_xcd);        \
+        else                                                                                                       \
+            hipLaunchKernelGGL((column_batched<float, NBV>), grid, block, 0, s, descs, n, total, per_xcd);         \
+        break;
+        OED_COLB_CASE(1)
+        OED_COLB_CASE(2)
+        OED_COLB_CASE(3)
+        OED_COLB_CASE(4)
+        OED_COLB_CASE(5)
+        OED_COLB_CASE(6)
+        OED_COLB_CASE(7)
+        OED_COLB_CASE(8)
+#undef OED_COLB_CASE
+    default:
+        return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
 }
 
 hipError_t launch_syrk(const StepDesc &d, int rtype, int wtype, int variant, hipStream_t s)

@@ -44,6 +44,7 @@ class oed_instance(ctypes.Structure):
 
 OED_BATCH_NO_GRAPH = 2
 OED_BATCH_AUTOTUNE = 0x10
+OED_BATCH_LEFT_LOOKING = 0x20
 
 
 class OedError(RuntimeError):
@@ -258,11 +259,12 @@ def _bcheck(b, st):
         raise OedError(st, msg)
 
 
-def oed_batch_create(items, precision="fp64", profile=False, graph=True, stream=None, delay=0, autotune=False):
+def oed_batch_create(items, precision="fp64", profile=False, graph=True, stream=None, delay=0, autotune=False,
+                     method="right"):
     arr = _instances(items)
     b = ctypes.c_void_p()
     flags = ((OED_FLAG_PROFILE if profile else 0) | (0 if graph else OED_BATCH_NO_GRAPH) | (int(delay) << 8) |
-             (OED_BATCH_AUTOTUNE if autotune else 0))
+             (OED_BATCH_AUTOTUNE if autotune else 0) | (OED_BATCH_LEFT_LOOKING if method == "left" else 0))
     st = library().oed_batch_create(ctypes.byref(b), arr, len(items), PRECISIONS[precision], _stream_handle(stream),
                                     flags)
     _bcheck(None, st)
@@ -311,9 +313,10 @@ def oed_batch_destroy(b):
 class BatchSelector:
     """Owns one batch.  ``BatchSelector([(K, N_s, N_t, sigma2, B), ...]).run()`` -> [(idx, gain, status)]."""
 
-    def __init__(self, items, precision="fp64", profile=False, graph=True, stream=None, delay=0, autotune=False):
+    def __init__(self, items, precision="fp64", profile=False, graph=True, stream=None, delay=0, autotune=False,
+                 method="right"):
         self.budgets = [int(it[4]) for it in items]
-        self.b = oed_batch_create(items, precision, profile, graph, stream, delay, autotune)
+        self.b = oed_batch_create(items, precision, profile, graph, stream, delay, autotune, method)
 
     def run(self, check=True):
         return oed_batch_run(self.b, self.budgets, check)[0]

@@ -97,3 +97,25 @@ def test_batch_autotune(insts):
     for (i0, g0, s0), (i1, g1, s1) in zip(ref, res):
         assert list(i0) == list(i1) and s0 == s1 == 0
         np.testing.assert_array_equal(g0, g1)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed_f32", "mixed_bf16x3"])
+def test_batch_left_looking(insts, prec):
+    """Batched left-looking: each instance bitwise equal to a left-looking handle of its own, and
+    to the oracle within tolerance; graph replays equal."""
+    from paper_2604_08812_amd import BatchSelector, Selector
+    its = items(insts)
+    with BatchSelector(its, precision=prec, method="left") as bs:
+        res = bs.run()
+        bs.reset(its)
+        res2 = bs.run()
+    for q, (K, Kd, N_s, N_t, s2, B) in enumerate(insts):
+        idx, gain, st = res[q]
+        assert st == 0 and len(idx) == B
+        assert list(idx) == list(res2[q][0])
+        np.testing.assert_array_equal(gain, res2[q][1])
+        with Selector(Kd, N_s, N_t, s2, precision=prec, method="left", max_budget=B) as sel:
+            i1, g1 = sel.greedy(B)
+        assert list(idx) == list(i1), q
+        np.testing.assert_array_equal(gain, g1)
+        check_trajectory(K, N_s, N_t, s2, idx, gain, RTOL[prec])
