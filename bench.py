@@ -289,6 +289,23 @@ def run_batched(args):
                      "syrk_tflops_over_run": round(st["syrk_flops"] / (run_ms * 1e-3) / 1e12, 3)},
         "graph_run_ms": round(run_ms, 3),
     }
+    if not args.left and not args.no_left:
+        # the same designs left-looking (only each pick's block column formed), beside it
+        bl = BatchSelector(items, precision=args.precision or "mixed_f32", profile=True, method="left")
+        bl.reset(items)
+        bl.run()
+        tl = []
+        for s_ in range(args.steps):
+            bl.reset(items)
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            bl.run()
+            torch.cuda.synchronize()
+            tl.append(time.perf_counter() - t1)
+        bl.close()
+        msl = 1e3 * sum(tl) / len(tl)
+        result["left_looking"] = {"value": round(total_steps / (msl * 1e-3), 3), "unit": "greedy steps/s",
+                                  "ms_per_run": round(msl, 3), "note": "oed_batch_run only (reset outside the timing)"}
     print(json.dumps(result), flush=True)
 
 
