@@ -322,14 +322,16 @@ __device__ __forceinline__ void tile_map(const StepDesc &d, int64_t P, int64_t Q
 // and is subtracted from R at the end.  FP32: the R tile is loaded into registers a few
 // blocks per slice, behind the next slice's W loads, so it streams in during the MFMAs.
 // FP64 (no registers for the tile) reads R in the epilogue.
-template <typename T, int NB>
+template <typename T, int NB, int KS>
 __device__ void syrk_lds_body(const StepDesc &d, int64_t tile)
 {
+    // KS consecutive 16-wide inner slices are staged per barrier (NB % KS == 0)
     typedef typename V4<T>::type vec;
     constexpr int N_tp = 16 * NB;
+    constexpr int NST = NB / KS;              // stages per W block
     constexpr bool PREFETCH_R = sizeof(T) == 4;
-    constexpr int PER = (16 + NB - 1) / NB;  // R blocks fetched per slice of the last W block
-    __shared__ vec lds[2][2][8 * 64];        // [buffer][A/B][sub-block * 64 + lane]
+    constexpr int PER = (16 + NST - 1) / NST;  // R blocks fetched per stage of the last W block
+    __shared__ vec lds[2][2][KS][8 * 64];      // [buffer][A/B][slice][sub-block * 64 + lane]
     if (d.state[ST_STATUS] != 0) return;
     int64_t P, Q;
     if (!super_tile(tile, syrk_tile_rows(d.n_act, d.N_tp), P, Q)) return;
@@ -348,71 +350,68 @@ __device__ void syrk_lds_body(const StepDesc &d, int64_t tile)
     vec rt[16], acc[16];
 #pragma unroll
     for (int f = 0; f < 16; ++f) acc[f] = vec{0, 0, 0, 0};
-    vec sa[2], sbv[2];
-    {
-        const T *w0 = wblk(0);
+    vec sa[KS][2], sbv[KS][2];
+    auto stage = [&](const T *src) {
 #pragma unroll
-        for (int h = 0; h < 2; ++h) {
-            sa[h] = ld4(w0 + m.wA[h]);
-            sbv[h] = ld4(w0 + m.wB[h]);
-        }
-    }
+        for (int k = 0; k < KS; ++k)
 #pragma unroll
-    for (int h = 0; h < 2; ++h) {
-        lds[0][0][(wave + 4 * h) * 64 + lane] = sa[h];
-        lds[0][1][(wave + 4 * h) * 64 + lane] = sbv[h];
-    }
+            for (int h = 0; h < 2; ++h) {
+                sa[k][h] = ld4(src + (k << 8) + m.wA[h]);
+                sbv[k][h] = ld4(src + (k << 8) + m.wB[h]);
+            }
+    };
+    auto put = [&](int buf) {
+#pragma unroll
+        for (int k = 0; k < KS; ++k)
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+                lds[buf][0][k][(wave + 4 * h) * 64 + lane] = sa[k][h];
+                lds[buf][1][k][(wave + 4 * h) * 64 + lane] = sbv[k][h];
+            }
+    };
+    stage(wblk(0));
+    put(0);
     __syncthreads();
 
-    // The NB 16-wide inner slices of one W block (cur); the slice after its last one is the
-    // first of nxt (null: none).  par: LDS buffer of its first slice.  The last block's pass
-    // also streams the R tile in (PREF): PER blocks per slice, issued after that slice's W
-    // loads, so the wait for those never waits for R.
+    // The NST stages of one W block (cur); the stage after its last one is the first of nxt
+    // (null: none).  par: LDS buffer of its first stage.  The last block's pass also streams
+    // the R tile in (PREF): PER blocks per stage, issued after that stage's W loads, so the
+    // wait for those never waits for R.
     auto pass = [&](auto pref, const T *cur, const T *nxt, int par) {
         constexpr bool PREF = decltype(pref)::value;
 #pragma unroll
-        for (int q = 0; q < NB; ++q) {
+        for (int q = 0; q < NST; ++q) {
             const int buf = par ^ (q & 1);
-            const bool more = q + 1 < NB || nxt;
-            if (more) {
-                const T *src = q + 1 < NB ? cur + ((q + 1) << 8) : nxt;
-#pragma unroll
-                for (int h = 0; h < 2; ++h) {
-                    sa[h] = ld4(src + m.wA[h]);
-                    sbv[h] = ld4(src + m.wB[h]);
-                }
-            }
+            const bool more = q + 1 < NST || nxt;
+            if (more) stage(q + 1 < NST ? cur + (((q + 1) * KS) << 8) : nxt);
             if (PREF) {
 #pragma unroll
                 for (int f = q * PER; f < (q + 1) * PER && f < 16; ++f) rt[f] = ld4(Rl + m.rblk[f]);
             }
             if (m.any) {
-                vec a[4], w[4];
 #pragma unroll
-                for (int b = 0; b < 4; ++b) {
-                    a[b] = lds[buf][0][(wr * 4 + b) * 64 + alane];
-                    w[b] = lds[buf][1][(wc * 4 + b) * 64 + lane];
-                }
+                for (int k = 0; k < KS; ++k) {
+                    vec a[4], w[4];
 #pragma unroll
-                for (int s4 = 0; s4 < 4; ++s4)
+                    for (int b = 0; b < 4; ++b) {
+                        a[b] = lds[buf][0][k][(wr * 4 + b) * 64 + alane];
+                        w[b] = lds[buf][1][k][(wc * 4 + b) * 64 + lane];
+                    }
 #pragma unroll
-                    for (int b = 0; b < 4; ++b)
+                    for (int s4 = 0; s4 < 4; ++s4)
 #pragma unroll
-                        for (int c = 0; c < 4; ++c) acc[4 * b + c] = mfma16(a[b][s4], w[c][s4], acc[4 * b + c]);
-            }
-            if (more) {
+                        for (int b = 0; b < 4; ++b)
 #pragma unroll
-                for (int h = 0; h < 2; ++h) {
-                    lds[buf ^ 1][0][(wave + 4 * h) * 64 + lane] = sa[h];
-                    lds[buf ^ 1][1][(wave + 4 * h) * 64 + lane] = sbv[h];
+                            for (int c = 0; c < 4; ++c) acc[4 * b + c] = mfma16(a[b][s4], w[c][s4], acc[4 * b + c]);
                 }
             }
+            if (more) put(buf ^ 1);
             __syncthreads();
         }
     };
     const int nw = d.nw;
-    for (int slot = 0; slot + 1 < nw; ++slot) pass(BoolC<false>(), wblk(slot), wblk(slot + 1), (slot * NB) & 1);
-    pass(BoolC<PREFETCH_R>(), wblk(nw - 1), nullptr, ((nw - 1) * NB) & 1);
+    for (int slot = 0; slot + 1 < nw; ++slot) pass(BoolC<false>(), wblk(slot), wblk(slot + 1), (slot * NST) & 1);
+    pass(BoolC<PREFETCH_R>(), wblk(nw - 1), nullptr, ((nw - 1) * NST) & 1);
 
     if (!m.any) return;
 #pragma unroll
@@ -791,15 +790,15 @@ __global__ void __launch_bounds__(256) syrk_direct_batched(const StepDesc *__res
     syrk_direct_body<T>(d, item - d.item0);
 }
 
-template <typename T, int NB>
+template <typename T, int NB, int KS>
 __global__ void __launch_bounds__(256, 2) syrk_lds_kernel(StepDesc d, int64_t per_xcd)
 {
     const int64_t tile = xcd_item(blockIdx.x, per_xcd);
     if (tile >= d.nitems) return;
-    syrk_lds_body<T, NB>(d, tile);
+    syrk_lds_body<T, NB, KS>(d, tile);
 }
 
-template <typename T, int NB>
+template <typename T, int NB, int KS>
 __global__ void __launch_bounds__(256, 2) syrk_lds_batched(const StepDesc *__restrict__ ds, int n, int64_t total,
                                                            int64_t per_xcd)
 {
@@ -808,7 +807,7 @@ __global__ void __launch_bounds__(256, 2) syrk_lds_batched(const StepDesc *__res
     const int i = find_instance(ds, n, item);
     if (i < 0) return;
     const StepDesc d = ds[i];
-    syrk_lds_body<T, NB>(d, item - d.item0);
+    syrk_lds_body<T, NB, KS>(d, item - d.item0);
 }
 
 template <int NB32>
@@ -961,13 +960,16 @@ static hipError_t launch_syrk_t(const StepDesc *descs, const StepDesc &d, int n,
     const dim3 grid((unsigned)(per_xcd * 8)), block(256);
     if (variant == SYRK_LDS && nb <= 8) {
         switch (nb) {
+// One 16-wide slice per barrier (two, KS = 2, measured 5% slower for FP32 at 600 x 128)
 #define OED_SYRK_CASE(NBV)                                                                                    \
-    case NBV:                                                                                                 \
+    case NBV: {                                                                                               \
+        constexpr int KSV = 1;                                                                                \
         if (descs)                                                                                            \
-            hipLaunchKernelGGL((syrk_lds_batched<T, NBV>), grid, block, 0, s, descs, n, total, per_xcd);      \
+            hipLaunchKernelGGL((syrk_lds_batched<T, NBV, KSV>), grid, block, 0, s, descs, n, total, per_xcd); \
         else                                                                                                  \
-            hipLaunchKernelGGL((syrk_lds_kernel<T, NBV>), grid, block, 0, s, d, per_xcd);                     \
-        break;
+            hipLaunchKernelGGL((syrk_lds_kernel<T, NBV, KSV>), grid, block, 0, s, d, per_xcd);                \
+        break;                                                                                                \
+    }
             OED_SYRK_CASE(1)
             OED_SYRK_CASE(2)
             OED_SYRK_CASE(3)
