@@ -53,9 +53,9 @@ def lib():
         ip = ctypes.POINTER(ctypes.c_int)
         L.oedo_chol_logdet.argtypes = [dp, ctypes.c_int64, dp]
         L.oedo_subset_logdet.argtypes = [dp, ctypes.c_int64, ctypes.c_int, ip, ctypes.c_int, dp]
-        L.oedo_gains.argtypes = [dp, ctypes.c_int64, ctypes.c_int, ctypes.c_double, ip, ctypes.c_int,
+        L.oedo_gains.argtypes = [dp, ctypes.c_int64, ctypes.c_int, ctypes.c_double, dp, ip, ctypes.c_int,
                                  ip, ctypes.c_int, dp, ctypes.c_int]
-        L.oedo_greedy.argtypes = [dp, ctypes.c_int64, ctypes.c_int, ctypes.c_double, ip, ctypes.c_int,
+        L.oedo_greedy.argtypes = [dp, ctypes.c_int64, ctypes.c_int, ctypes.c_double, dp, ip, ctypes.c_int,
                                   ip, ctypes.c_int, ctypes.c_int, ip, dp, dp, ip, dp, ip, ctypes.c_int]
         _lib = L
     return _lib
@@ -73,6 +73,8 @@ def _as_K(K):
 
 
 def _dp(a):
+    if a is None:
+        return None
     return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
 
 
@@ -103,26 +105,37 @@ def subset_logdet(K, N_t, S):
     return None if rc != 0 else out.value
 
 
-def objective(K, N_t, sigma2, S):
-    """f(S) = 1/2 logdet(sigma^-2 K_SS)."""
+def objective(K, N_t, sigma2, S, noise_hld=None):
+    """f(S) = 1/2 logdet K_SS - sum_{j in S} h_j, h_j = (N_t/2) ln sigma2 (isotropic noise) or
+    noise_hld[j] (1/2 logdet of sensor j's noise covariance block)."""
     ld = subset_logdet(K, N_t, S)
-    return None if ld is None else 0.5 * ld - 0.5 * len(S) * N_t * math.log(sigma2)
+    if ld is None:
+        return None
+    if noise_hld is None:
+        return 0.5 * ld - 0.5 * len(S) * N_t * math.log(sigma2)
+    return 0.5 * ld - float(sum(noise_hld[j] for j in S))
 
 
-def gains(K, N_t, sigma2, A, cands, threads=None):
-    """Scores of ``cands`` at the greedy step that follows the ordered prefix A."""
+def _hld(noise_hld):
+    return None if noise_hld is None else np.ascontiguousarray(np.asarray(noise_hld, dtype=np.float64))
+
+
+def gains(K, N_t, sigma2, A, cands, threads=None, noise_hld=None):
+    """Scores of ``cands`` at the greedy step that follows the ordered prefix A (noise_hld: per
+    sensor 1/2 logdet of its noise covariance block; None = isotropic sigma2)."""
     K = _as_K(K)
     A = _ints(A)
     c = _ints(cands)
+    h = _hld(noise_hld)
     g = np.empty(len(c), dtype=np.float64)
-    rc = lib().oedo_gains(_dp(K), K.shape[1], N_t, float(sigma2), _ip(A), len(A), _ip(c), len(c),
+    rc = lib().oedo_gains(_dp(K), K.shape[1], N_t, float(sigma2), _dp(h), _ip(A), len(A), _ip(c), len(c),
                           _dp(g), threads or default_threads())
     if rc != 0:
         raise OracleError(rc)
     return g
 
 
-def greedy(K, N_s, N_t, sigma2, B, candidates=None, prefix=None, threads=None, raise_on_error=True):
+def greedy(K, N_s, N_t, sigma2, B, candidates=None, prefix=None, threads=None, raise_on_error=True, noise_hld=None):
     """Greedy selection of B sensors.
 
     Returns a dict with ``idx`` (picked sensors, pick order), ``gain`` (their
@@ -141,7 +154,10 @@ def greedy(K, N_s, N_t, sigma2, B, candidates=None, prefix=None, threads=None, r
     best = np.full(B, -1, dtype=np.int32)
     best_gain = np.full(B, np.nan)
     n = ctypes.c_int()
-    rc = lib().oedo_greedy(_dp(K), K.shape[1], N_t, float(sigma2), _ip(cand), len(cand), _ip(pre),
+    h = _hld(noise_hld)
+    if h is not None and len(h) < N_s:
+        raise ValueError("noise_hld needs one entry per sensor")
+    rc = lib().oedo_greedy(_dp(K), K.shape[1], N_t, float(sigma2), _dp(h), _ip(cand), len(cand), _ip(pre),
                            len(pre), int(B), _ip(idx), _dp(gain), _dp(gap), _ip(best), _dp(best_gain),
                            ctypes.byref(n),
                            threads or default_threads())

@@ -108,11 +108,14 @@ int oedo_subset_logdet(const double *K, int64_t ld, int N_t, const int *S, int n
 
 /*
  * Scores of the candidates cand[0..nc) given the ordered prefix A[0..nA):
- * gains[c] = 1/2 [logdet K_{A u cand[c]} - logdet K_A] - (N_t/2) ln sigma2,
- * or -inf when the factorisation of K_{A u cand[c]} fails.
+ * gains[c] = 1/2 [logdet K_{A u cand[c]} - logdet K_A] - h[cand[c]],
+ * or -inf when the factorisation of K_{A u cand[c]} fails.  h[j] is 1/2 logdet of sensor j's
+ * noise covariance block: with sensors whose noise is independent of each other the noise term of
+ * the computable objective (Sec. III-C) is the sum of these over the selected set.  hld == NULL:
+ * isotropic noise, h[j] = (N_t/2) ln sigma2 for every sensor.
  */
-int oedo_gains(const double *K, int64_t ld, int N_t, double sigma2, const int *A, int nA,
-               const int *cand, int nc, double *gains, int nthreads)
+int oedo_gains(const double *K, int64_t ld, int N_t, double sigma2, const double *hld, const int *A,
+               int nA, const int *cand, int nc, double *gains, int nthreads)
 {
     if (!K || N_t <= 0 || !(sigma2 > 0.0) || nA < 0 || nc < 0)
         return ORC_ARG;
@@ -149,7 +152,7 @@ int oedo_gains(const double *K, int64_t ld, int N_t, double sigma2, const int *A
                 gather_subset(K, ld, N_t, S, nA + 1, M);
                 double ld_Aj;
                 if (oedo_chol_logdet(M, n, &ld_Aj) == 0)
-                    gains[c] = 0.5 * (ld_Aj - ld_A) - noise;
+                    gains[c] = 0.5 * (ld_Aj - ld_A) - (hld ? hld[cand[c]] : noise);
                 else
                     gains[c] = -INFINITY;
             }
@@ -173,8 +176,8 @@ int oedo_gains(const double *K, int64_t ld, int N_t, double sigma2, const int *A
  *               step and its score (differs from idx_out[k] only when forced);
  *               either pointer may be NULL.
  */
-int oedo_greedy(const double *K, int64_t ld, int N_t, double sigma2, const int *cand, int nc,
-                const int *prefix, int nprefix, int B, int *idx_out, double *gain_out,
+int oedo_greedy(const double *K, int64_t ld, int N_t, double sigma2, const double *hld, const int *cand,
+                int nc, const int *prefix, int nprefix, int B, int *idx_out, double *gain_out,
                 double *gap_out, int *best_out, double *bestgain_out, int *n_out, int nthreads)
 {
     *n_out = 0;
@@ -199,7 +202,7 @@ int oedo_greedy(const double *K, int64_t ld, int N_t, double sigma2, const int *
         }
     int npool = nc, status = ORC_OK;
     for (int k = 0; k < B; ++k) {
-        int rc = oedo_gains(K, ld, N_t, sigma2, A, k, pool, npool, g, nthreads);
+        int rc = oedo_gains(K, ld, N_t, sigma2, hld, A, k, pool, npool, g, nthreads);
         if (rc != ORC_OK) {
             status = rc;
             break;

@@ -329,3 +329,82 @@ def test_small_fp64_config_properties():
         oracle.symmetrize_lower(K)[np.ix_(oracle.block_index(16, res["idx"]),
                                           oracle.block_index(16, res["idx"]))] / s2)
     assert abs(g.sum() - total) <= 1e-10 * abs(total)
+
+
+# --------------------------------------------------------------------------- per-sensor noise
+def sensor_noise_instance(rng, N_s, N_t, n_m=None):
+    """K = F F^T / n_m + blockdiag(D_j), D_j a random SPD noise covariance per sensor; returns K,
+    the blocks D_j and h_j = 1/2 logdet D_j (from eigenvalues)."""
+    N_d = N_s * N_t
+    n_m = n_m or 2 * N_d
+    F = rng.standard_normal((N_d, n_m)) * (1.0 + np.arange(n_m)) ** -0.25
+    G = F @ F.T / n_m
+    scale = float(np.mean(np.diag(G)))
+    K = G.copy()
+    D, h = [], np.empty(N_s)
+    for j in range(N_s):
+        Q = rng.standard_normal((N_t, N_t))
+        Dj = scale * (0.01 * 10 ** rng.uniform(-1, 1)) * (np.eye(N_t) + 0.3 * Q @ Q.T / N_t)
+        K[j * N_t:(j + 1) * N_t, j * N_t:(j + 1) * N_t] += Dj
+        D.append(Dj)
+        h[j] = 0.5 * float(np.sum(np.log(np.linalg.eigvalsh(Dj))))
+    return K, D, h
+
+
+def test_sensor_noise_greedy_matches_brute_force():
+    """f(S) = 1/2 logdet K_S - sum_{j in S} h_j, the computable objective with independent
+    per-sensor noise: the oracle follows the greedy trajectory of the brute-force value table."""
+    rng = np.random.default_rng(11)
+    N_s, N_t, B = 8, 3, 4
+    K, _, h = sensor_noise_instance(rng, N_s, N_t)
+    table = {(): 0.0}
+    for k in range(1, B + 1):
+        for S in itertools.combinations(range(N_s), k):
+            idx = oracle.block_index(N_t, S)
+            sign, ld = np.linalg.slogdet(K[np.ix_(idx, idx)])
+            table[S] = 0.5 * ld - float(sum(h[list(S)]))
+    A, g, _ = greedy_from_table(table, N_s, B)
+    res = oracle.greedy(K, N_s, N_t, 1.0, B, noise_hld=h)
+    assert list(res["idx"]) == A
+    np.testing.assert_allclose(res["gain"], g, rtol=1e-11, atol=1e-11)
+
+
+def test_sensor_noise_block_diagonal_is_single_sensor_information():
+    """With no coupling between sensors each gain is the single sensor's information
+    1/2 logdet(I + D^-1 P) = 1/2 sum ln(1 + lambda_i) (generalised eigenvalues of (P, D)), whatever
+    was picked before; picks are the top blocks (ties to the lowest index).  A candidate subset
+    checks that h is taken by sensor index."""
+    rng = np.random.default_rng(12)
+    N_s, N_t, B = 9, 4, 5
+    K = np.zeros((N_s * N_t, N_s * N_t))
+    info, h = np.empty(N_s), np.empty(N_s)
+    for j in range(N_s):
+        X = rng.standard_normal((N_t, 2 * N_t))
+        P = X @ X.T / (2 * N_t) * 10 ** rng.uniform(-1, 1)
+        Dj = np.diag(10 ** rng.uniform(-2, 0, N_t))
+        K[j * N_t:(j + 1) * N_t, j * N_t:(j + 1) * N_t] = P + Dj
+        lam = scipy.linalg.eigh(P, Dj, eigvals_only=True)
+        info[j] = 0.5 * float(np.sum(np.log1p(lam)))
+        h[j] = 0.5 * float(np.sum(np.log(np.diag(Dj))))
+    cand = [8, 1, 5, 3, 0, 7]
+    res = oracle.greedy(K, N_s, N_t, 1.0, B, candidates=cand, noise_hld=h)
+    order = sorted(cand, key=lambda j: (-info[j], j))[:B]
+    assert list(res["idx"]) == order
+    np.testing.assert_allclose(res["gain"], info[order], rtol=1e-10)
+
+
+def test_sensor_noise_telescoping_and_isotropic_special_case():
+    rng = np.random.default_rng(13)
+    N_s, N_t, B = 12, 4, 7
+    K, _, h = sensor_noise_instance(rng, N_s, N_t)
+    res = oracle.greedy(K, N_s, N_t, 1.0, B, noise_hld=h)
+    A = list(res["idx"])
+    idx = oracle.block_index(N_t, A)
+    total = 0.5 * oracle.logdet_lapack(K[np.ix_(idx, idx)]) - float(sum(h[A]))
+    assert abs(res["gain"].sum() - total) <= 1e-10 * abs(total)
+    # equal noise blocks s2 I: identical to the isotropic objective
+    K2, s2 = rand_spd_instance(rng, N_s, N_t)
+    iso = oracle.greedy(K2, N_s, N_t, s2, B)
+    eq = oracle.greedy(K2, N_s, N_t, 1.0, B, noise_hld=np.full(N_s, 0.5 * N_t * math.log(s2)))
+    assert list(iso["idx"]) == list(eq["idx"])
+    np.testing.assert_allclose(iso["gain"], eq["gain"], rtol=1e-13, atol=1e-13)
