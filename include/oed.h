@@ -104,6 +104,13 @@ typedef struct oed_options {
     int32_t method;             /* OED_METHOD_RIGHT_LOOKING (default), _LEFT_LOOKING or _AUTO */
     int32_t max_budget;         /* left-looking: most picks the handle will make (the W history
                                    is allocated for them); 0 = all candidates */
+    const double *noise_half_logdet; /* host array, one per sensor (length N_s): h_j = 1/2 logdet of
+                                   sensor j's noise covariance block, for noise independent between
+                                   sensors (the computable objective of Sec. III-C with a
+                                   block-diagonal noise covariance; K must include that noise).  A
+                                   candidate then scores 1/2 logdet S_j - h_j.  NULL = isotropic
+                                   noise sigma2: h_j = (N_t/2) ln sigma2.  Copied during oed_create;
+                                   non-finite entries: OED_E_ARG. */
     int32_t reserved[4];        /* must be 0 */
 } oed_options;
 

@@ -13,6 +13,7 @@ from .synth import (  # noqa: F401
     f_tile,
     make_K,
     make_K_lower_panels,
+    make_K_sensor_noise,
     k_sub_lower,
 )
 from .configs import CONFIGS, batched_instance_specs, Spec  # noqa: F401

@@ -80,6 +80,27 @@ def make_K(N_s: int, N_t: int, n_m: int, seed: int, c: float = 0.01, device="cpu
     return G.to(dtype), sigma2
 
 
+def make_K_sensor_noise(N_s: int, N_t: int, n_m: int, seed: int, c_lo: float = 1e-3, c_hi: float = 1e-1,
+                        device="cpu", dtype=torch.float64):
+    """K = F F^T / n_m + diag(sigma_j^2) with a noise variance per sensor (independent,
+    uncorrelated noise of uneven instruments): sigma_j^2 = c_j mean diag(F F^T / n_m), c_j
+    log-uniform in [c_lo, c_hi] from ``numpy.random.default_rng(seed)``.  Returns
+    ``(K, sigma2_per_sensor)`` (the latter a numpy array of length N_s).
+    """
+    import numpy as np
+    N_d = N_s * N_t
+    G = torch.zeros((N_d, N_d), dtype=torch.float64, device=device)
+    for cb in range(math.ceil(n_m / TILE)):
+        Fc = f_column_chunk(seed, N_d, n_m, cb, device)
+        G.addmm_(Fc, Fc.t())
+    G /= n_m
+    scale = float(G.diagonal().mean().item())
+    c = 10.0 ** np.random.default_rng(seed).uniform(np.log10(c_lo), np.log10(c_hi), N_s)
+    var = scale * c
+    G.diagonal().add_(torch.from_numpy(np.repeat(var, N_t)).to(device))
+    return G.to(dtype), var
+
+
 def make_K_lower_panels(N_s: int, N_t: int, n_m: int, seed: int, c: float = 0.01,
                         device="cuda", dtype=torch.float64, panel: int = 12800,
                         progress=None):

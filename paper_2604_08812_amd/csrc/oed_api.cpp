@@ -47,6 +47,7 @@ struct oed_ctx {
     int max_budget = 0;
     bool diag_current = true;  // the diagonal blocks include every formed block column
     void *C = nullptr;         // column partial sums (LEFT_SPLITS x N_c blocks, R's type)
+    double *noise_h = nullptr; // per-sensor noise terms by local index (device), or null
     uint32_t flags = 0;
     hipStream_t stream = nullptr;
     int device = 0;
@@ -145,7 +146,7 @@ void collect_profile(oed_ctx *h)
 
 void free_all(oed_ctx *h)
 {
-    void *ptrs[] = {h->R, h->W, h->W2, h->V, h->C, h->Linv, h->gains, h->pick_gain, h->scratch_gain, h->scratch_pick,
+    void *ptrs[] = {h->R, h->W, h->W2, h->V, h->C, h->noise_h, h->Linv, h->gains, h->pick_gain, h->scratch_gain, h->scratch_pick,
                     h->act[0], h->act[1], h->picks, h->state, h->dcmap};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
@@ -195,6 +196,7 @@ StepDesc desc(const oed_ctx *h)
     d.picks = h->picks;
     d.pick_gain = h->pick_gain;
     d.half_noise = h->half_noise;
+    d.noise_h = h->noise_h;
     d.n_act = h->n_act;
     d.N_t = h->N_t;
     d.N_tp = h->N_tp;
@@ -584,6 +586,17 @@ oed_status oed_create(oed_ctx **out, const void *K, int32_t dtype, int64_t ld, i
         for (int q = 0; q < N_s; ++q) h->cmap[q] = q;
     }
     h->N_c = (int)h->cmap.size();
+    std::vector<double> hloc;
+    if (o.noise_half_logdet) {
+        hloc.resize(h->N_c);
+        for (int q = 0; q < h->N_c; ++q) {
+            hloc[q] = o.noise_half_logdet[h->cmap[q]];
+            if (!std::isfinite(hloc[q])) {
+                delete h;
+                return OED_E_ARG;
+            }
+        }
+    }
     h->max_budget = (o.max_budget == 0 || o.max_budget > h->N_c) ? h->N_c : o.max_budget;
     for (int q = 0; q < h->N_c; ++q) h->lmap[h->cmap[q]] = q;
 
@@ -614,6 +627,10 @@ oed_status oed_create(oed_ctx **out, const void *K, int32_t dtype, int64_t ld, i
         if (h->N_t > REGS_MAX_NT && pick_lds_bytes(h->N_t) == 0)
             HIPCHK(h, dmalloc(h, (void **)&h->scratch_pick, sizeof(double) * tri * 2));
         HIPCHK(h, hipMemcpyAsync(h->dcmap, h->cmap.data(), sizeof(int) * h->N_c, hipMemcpyHostToDevice, h->stream));
+        if (!hloc.empty()) {
+            HIPCHK(h, dmalloc(h, (void **)&h->noise_h, sizeof(double) * h->N_c));
+            HIPCHK(h, hipMemcpyAsync(h->noise_h, hloc.data(), sizeof(double) * h->N_c, hipMemcpyHostToDevice, h->stream));
+        }
         oed_status s2 = load_R(h, K);
         if (s2 != OED_OK) return s2;
         HIPCHK(h, hipStreamSynchronize(h->stream));

@@ -528,7 +528,7 @@ __device__ void gain_regs_body(const StepDesc &d, int p)
         return;
     }
     const double ls = half_sum_log(piv, d.N_t, red);
-    if (threadIdx.x == 0) d.gains[p] = ls - d.half_noise;
+    if (threadIdx.x == 0) d.gains[p] = ls - (d.noise_h ? d.noise_h[i] : d.half_noise);
 }
 
 template <typename TR, typename TW>
@@ -555,7 +555,7 @@ __device__ void pick_regs_body(const StepDesc &d)
     const double ls = half_sum_log(piv, d.N_t, red);
     if (tid == 0) {
         d.picks[d.step] = s;
-        d.pick_gain[d.step] = d.forced < 0 ? g : ls - d.half_noise;
+        d.pick_gain[d.step] = d.forced < 0 ? g : ls - (d.noise_h ? d.noise_h[s] : d.half_noise);
         d.state[ST_NPICKS] = d.step + 1;
         d.state[ST_LAST] = s;
     }
@@ -569,7 +569,7 @@ __device__ void gain_lds_body(const StepDesc &d, int p, double *lds)
     const int i = d.act_in[p];
     load_diag_block((const TR *)d.R + blk_index(i, i) * (int64_t)d.N_tp * d.N_tp, d.N_t, d.N_tp, A);
     const double ls = chol_packed(A, d.N_t);
-    if (threadIdx.x == 0) d.gains[p] = (ls == -INFINITY) ? -INFINITY : ls - d.half_noise;
+    if (threadIdx.x == 0) d.gains[p] = (ls == -INFINITY) ? -INFINITY : ls - (d.noise_h ? d.noise_h[i] : d.half_noise);
 }
 
 template <typename TR>
@@ -593,7 +593,7 @@ __device__ void pick_lds_body(const StepDesc &d, double *lds)
     }
     if (tid == 0) {
         d.picks[d.step] = s;
-        d.pick_gain[d.step] = d.forced < 0 ? g : ls - d.half_noise;
+        d.pick_gain[d.step] = d.forced < 0 ? g : ls - (d.noise_h ? d.noise_h[s] : d.half_noise);
         d.state[ST_NPICKS] = d.step + 1;
         d.state[ST_LAST] = s;
     }

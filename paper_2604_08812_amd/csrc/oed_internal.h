@@ -87,7 +87,8 @@ struct StepDesc {
     int *picks;            // local index of every pick
     double *pick_gain;     // gain of every pick
     double *scratch;       // global scratch of the LDS factorisation kernels (N_t > REGS_MAX_NT)
-    double half_noise;     // (N_t / 2) ln sigma^2
+    double half_noise;     // (N_t / 2) ln sigma^2 (isotropic noise)
+    const double *noise_h; // per-sensor noise term h_j by local candidate index, or null: half_noise
     int n_act;             // number of entries of act_in
     int N_t, N_tp;         // real and padded block size
     int step;              // pick: index of this pick

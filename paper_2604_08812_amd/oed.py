@@ -28,7 +28,7 @@ class oed_options(ctypes.Structure):
     _fields_ = [("struct_size", ctypes.c_uint32), ("precision", ctypes.c_int32), ("flags", ctypes.c_uint32),
                 ("candidates", ctypes.POINTER(ctypes.c_int32)), ("n_candidates", ctypes.c_int32),
                 ("delay", ctypes.c_int32), ("method", ctypes.c_int32), ("max_budget", ctypes.c_int32),
-                ("reserved", ctypes.c_int32 * 4)]
+                ("noise_half_logdet", ctypes.POINTER(ctypes.c_double)), ("reserved", ctypes.c_int32 * 4)]
 
 
 class oed_profile(ctypes.Structure):
@@ -136,12 +136,13 @@ def _stream_handle(stream):
 
 # ------------------------------------------------------------------ functions with the C names
 def oed_create(K, N_s, N_t, sigma2, precision="fp64", candidates=None, profile=False, stream=None, delay=0,
-               autotune=False, method="right", max_budget=0):
+               autotune=False, method="right", max_budget=0, noise_half_logdet=None):
     """Create a handle for the device tensor K (2-D, float64/float32, row-major, lower triangle read).
     delay: downdate delay depth (0 automatic, 1..4); autotune: with delay 0, time the choices;
     method: "right" (downdate of all of R per pick), "left" (only the new block column per pick) or
     "auto" (left when max_budget <= half the candidates);
-    max_budget: left-looking W history size (0: all candidates)."""
+    max_budget: left-looking W history size (0: all candidates); noise_half_logdet: per-sensor
+    1/2 logdet of the noise covariance blocks (None: isotropic sigma2)."""
     import torch
     L = library()
     if not isinstance(K, torch.Tensor) or not K.is_cuda or K.dim() != 2 or K.stride(1) != 1:
@@ -158,6 +159,12 @@ def oed_create(K, N_s, N_t, sigma2, precision="fp64", candidates=None, profile=F
     opt.delay = int(delay)
     opt.method = {"right": 0, "left": 1, "auto": 2}[method]
     opt.max_budget = int(max_budget)
+    hld = None
+    if noise_half_logdet is not None:
+        hld = np.ascontiguousarray(np.asarray(noise_half_logdet, dtype=np.float64))
+        if hld.shape != (int(N_s),):
+            raise ValueError("noise_half_logdet needs one entry per sensor")
+        opt.noise_half_logdet = _dp(hld)
     cand = None
     if candidates is not None:
         cand = np.ascontiguousarray(np.asarray(list(candidates), dtype=np.int32))
@@ -353,10 +360,10 @@ class Selector:
     """Owns one handle.  ``Selector(K, N_s, N_t, sigma2).greedy(B)`` -> (indices, gains)."""
 
     def __init__(self, K, N_s, N_t, sigma2, precision="fp64", candidates=None, profile=False, stream=None,
-                 delay=0, autotune=False, method="right", max_budget=0):
+                 delay=0, autotune=False, method="right", max_budget=0, noise_half_logdet=None):
         self.N_s, self.N_t = int(N_s), int(N_t)
         self.h = oed_create(K, N_s, N_t, sigma2, precision, candidates, profile, stream, delay, autotune, method,
-                            max_budget)
+                            max_budget, noise_half_logdet)
 
     def greedy(self, budget):
         idx, gain, _ = oed_greedy(self.h, budget)

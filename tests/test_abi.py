@@ -67,6 +67,11 @@ def test_host_side_argument_validation(lib):
     assert lib.oed_create(ctypes.byref(h), fake, 0, 4 * 160, 4, 160, 1.0, None, ctypes.byref(bad)) == 6
     bad = oed_options()
     lib.oed_options_init(ctypes.byref(bad))
+    hn = (ctypes.c_double * 4)(0.0, float("nan"), 1.0, 2.0)   # non-finite per-sensor noise term
+    bad.noise_half_logdet = ctypes.cast(hn, ctypes.POINTER(ctypes.c_double))
+    assert lib.oed_create(ctypes.byref(h), fake, 0, 64, 4, 16, 1.0, None, ctypes.byref(bad)) == E_ARG
+    bad = oed_options()
+    lib.oed_options_init(ctypes.byref(bad))
     bad.delay = 5
     assert lib.oed_create(ctypes.byref(h), fake, 0, 64, 4, 16, 1.0, None, ctypes.byref(bad)) == E_ARG
     bad = oed_options()

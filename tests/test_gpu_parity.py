@@ -341,3 +341,23 @@ def test_method_auto():
         ib, gb = b.greedy(12)
     assert list(ia) == list(ib)
     check_trajectory(K, N_s, N_t, s2, ia, ga, RTOL["mixed_f32"])
+
+
+@pytest.mark.parametrize("method,delay", [("right", 1), ("right", 4), ("left", 0)])
+@pytest.mark.parametrize("prec", PRECS)
+def test_per_sensor_noise(prec, method, delay):
+    """Noise variances differing by sensor (100x range): gains 1/2 logdet S_j - h_j with
+    h_j = (N_t/2) ln sigma_j^2, against the oracle with the same per-sensor terms."""
+    from oed_inputs import make_K_sensor_noise
+    N_s, N_t, B = 36, 32, 10
+    K, var = make_K_sensor_noise(N_s, N_t, 2000, 51)
+    h = 0.5 * N_t * np.log(var)
+    with selector(K.to(DEV), N_s, N_t, 1.0, precision=prec, method=method, delay=delay,
+                  noise_half_logdet=h) as sel:
+        idx, gain = sel.greedy(B)
+    ref = oracle.greedy(K.numpy(), N_s, N_t, 1.0, B, noise_hld=h)
+    div = next((k for k in range(B) if idx[k] != ref["idx"][k]), None)
+    upto = B if div is None else div
+    assert np.all(rel_err(gain[:upto], ref["gain"][:upto]) <= RTOL[prec])
+    if div is not None:
+        assert ref["gap"][div] <= 2 * RTOL[prec] * max(1.0, abs(ref["gain"][div])), (div, ref["gap"][div])
