@@ -526,7 +526,8 @@ __device__ void syrk_bf16_body(const StepDesc &d, int64_t tile)
 // candidate i, the partial sums sum_{h in split} W_h,i W_h,s^T over the stored W slots, on MFMA
 // with the operands staged in LDS as in the downdate; one work-group per (split, 128-row tile).
 // The 128 x N_tp output tile is the rows of the remaining candidates against the N_tp rows of
-// s; partial q goes to d.C + q cstride in candidate i's block (accumulator order).
+// s; wave w computes rows 32w .. 32w + 31 against all N_tp columns (no idle MFMAs for N_tp < 128).
+// Partial q goes to d.C + q cstride in candidate i's block (accumulator order).
 template <typename T, int NB>
 __device__ void column_body(const StepDesc &d, int64_t item)
 {
@@ -540,7 +541,7 @@ __device__ void column_body(const StepDesc &d, int64_t item)
     if (split >= d.nsplit) return;
     const int h0 = (int)((int64_t)split * d.nw / d.nsplit), h1 = (int)((int64_t)(split + 1) * d.nw / d.nsplit);
     const int tid = threadIdx.x, lane = tid & 63;
-    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6), wr = wave >> 1, wc = wave & 1;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int alane = a_lane<T>(lane);
     const int *__restrict__ act = d.act_in;
     const int rows = d.n_act * N_tp, last = d.n_act - 1;
@@ -555,27 +556,22 @@ __device__ void column_body(const StepDesc &d, int64_t item)
         wA[h] = (int64_t)act[min(r / N_tp, last)] * bs + (int64_t)((r % N_tp) >> 4) * (NB * 256);
         wB[h] = (int64_t)s * bs + (int64_t)(sb < NB ? sb : 0) * (NB * 256);
     }
-    int64_t off[16];
-    bool ok[16];
-    bool any = false;
+    int64_t off[2];
+    bool ok[2];
 #pragma unroll
-    for (int b = 0; b < 4; ++b) {
-        const int r = (int)P * 128 + wr * 64 + 16 * b;
-        const int ia = act[min(r / N_tp, last)], ta = (r % N_tp) >> 4;
-#pragma unroll
-        for (int c = 0; c < 4; ++c) {
-            const int tc = wc * 4 + c;
-            const bool o = r < rows && tc < NB;
-            ok[4 * b + c] = o;
-            any |= o;
-            off[4 * b + c] = (int64_t)ia * bs + ((ta * NB + (o ? tc : 0)) << 8);
-        }
+    for (int b = 0; b < 2; ++b) {
+        const int r = (int)P * 128 + wave * 32 + 16 * b;
+        ok[b] = r < rows;
+        off[b] = (int64_t)act[min(r / N_tp, last)] * bs + ((((r % N_tp) >> 4) * NB) << 8);
     }
+    const bool any = ok[0];
     const T *W0 = (const T *)d.W + lane * 4;
     const int64_t wslot = d.wslot;
-    vec acc[16];
+    vec acc[2][NB];
 #pragma unroll
-    for (int f = 0; f < 16; ++f) acc[f] = vec{0, 0, 0, 0};
+    for (int b = 0; b < 2; ++b)
+#pragma unroll
+        for (int c = 0; c < NB; ++c) acc[b][c] = vec{0, 0, 0, 0};
     vec sa[2], sbv[2];
     {
         const T *w0 = W0 + h0 * wslot;
@@ -608,18 +604,17 @@ __device__ void column_body(const StepDesc &d, int64_t item)
                 }
             }
             if (any) {
-                vec a[4], w[4];
+                vec a[2], w[NB];
 #pragma unroll
-                for (int b = 0; b < 4; ++b) {
-                    a[b] = lds[buf][0][(wr * 4 + b) * 64 + alane];
-                    w[b] = lds[buf][1][(wc * 4 + b) * 64 + lane];
-                }
+                for (int b = 0; b < 2; ++b) a[b] = lds[buf][0][(2 * wave + b) * 64 + alane];
+#pragma unroll
+                for (int c = 0; c < NB; ++c) w[c] = lds[buf][1][c * 64 + lane];
 #pragma unroll
                 for (int s4 = 0; s4 < 4; ++s4)
 #pragma unroll
-                    for (int b = 0; b < 4; ++b)
+                    for (int b = 0; b < 2; ++b)
 #pragma unroll
-                        for (int c = 0; c < 4; ++c) acc[4 * b + c] = mfma16(a[b][s4], w[c][s4], acc[4 * b + c]);
+                        for (int c = 0; c < NB; ++c) acc[b][c] = mfma16(a[b][s4], w[c][s4], acc[b][c]);
             }
             if (more) {
 #pragma unroll
@@ -634,8 +629,11 @@ __device__ void column_body(const StepDesc &d, int64_t item)
     }
     T *Cq = (T *)d.C + split * d.cstride + lane * 4;
 #pragma unroll
-    for (int f = 0; f < 16; ++f)
-        if (ok[f]) st4(Cq + off[f], acc[f]);
+    for (int b = 0; b < 2; ++b)
+        if (ok[b]) {
+#pragma unroll
+            for (int c = 0; c < NB; ++c) st4(Cq + off[b] + (c << 8), acc[b][c]);
+        }
 }
 
 // The same with W in BF16 hi + lo parts (32-wide slices; hi hi^T + hi lo^T + lo hi^T on the
@@ -652,7 +650,7 @@ __device__ void column_bf16_body(const StepDesc &d, int64_t item)
     if (split >= d.nsplit) return;
     const int h0 = (int)((int64_t)split * d.nw / d.nsplit), h1 = (int)((int64_t)(split + 1) * d.nw / d.nsplit);
     const int tid = threadIdx.x, lane = tid & 63;
-    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6), wr = wave >> 1, wc = wave & 1;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int *__restrict__ act = d.act_in;
     const int rows = d.n_act * N_tp, last = d.n_act - 1;
     const int s = d.state[ST_LAST];
@@ -665,28 +663,23 @@ __device__ void column_bf16_body(const StepDesc &d, int64_t item)
         wA[h] = (int64_t)act[min(r / N_tp, last)] * bs + (int64_t)((r % N_tp) >> 4) * (NB * 256);
         wB[h] = (int64_t)s * bs + (int64_t)(sb < NB ? sb : 0) * (NB * 256);
     }
-    int64_t off[16];
-    bool ok[16];
-    bool any = false;
+    int64_t off[2];
+    bool ok[2];
 #pragma unroll
-    for (int b = 0; b < 4; ++b) {
-        const int r = (int)P * 128 + wr * 64 + 16 * b;
-        const int ia = act[min(r / N_tp, last)], ta = (r % N_tp) >> 4;
-#pragma unroll
-        for (int c = 0; c < 4; ++c) {
-            const int tc = wc * 4 + c;
-            const bool o = r < rows && tc < NB;
-            ok[4 * b + c] = o;
-            any |= o;
-            off[4 * b + c] = (int64_t)ia * bs + ((ta * NB + (o ? tc : 0)) << 8);
-        }
+    for (int b = 0; b < 2; ++b) {
+        const int r = (int)P * 128 + wave * 32 + 16 * b;
+        ok[b] = r < rows;
+        off[b] = (int64_t)act[min(r / N_tp, last)] * bs + ((((r % N_tp) >> 4) * NB) << 8);
     }
+    const bool any = ok[0];
     typedef const unsigned short *bp;
     const bp Wh0 = (bp)d.W + lane * 8, Wl0 = (bp)d.W2 + lane * 8;
     const int64_t wslot = d.wslot;
-    floatx4 acc[16];
+    floatx4 acc[2][NB];
 #pragma unroll
-    for (int f = 0; f < 16; ++f) acc[f] = floatx4{0, 0, 0, 0};
+    for (int b = 0; b < 2; ++b)
+#pragma unroll
+        for (int c = 0; c < NB; ++c) acc[b][c] = floatx4{0, 0, 0, 0};
     u32x4 st[2][4];
     auto stage = [&](bp hi, bp lo) {
 #pragma unroll
@@ -718,21 +711,20 @@ __device__ void column_bf16_body(const StepDesc &d, int64_t item)
                     stage(chi + wslot, clo + wslot);
             }
             if (any) {
-                u32x4 wh[4], wl[4];
+                u32x4 ah[2], al[2];
 #pragma unroll
-                for (int c = 0; c < 4; ++c) {
-                    wh[c] = lds[buf][2][(wc * 4 + c) * 64 + lane];
-                    wl[c] = lds[buf][3][(wc * 4 + c) * 64 + lane];
+                for (int b = 0; b < 2; ++b) {
+                    ah[b] = lds[buf][0][(2 * wave + b) * 64 + lane];
+                    al[b] = lds[buf][1][(2 * wave + b) * 64 + lane];
                 }
 #pragma unroll
-                for (int b = 0; b < 4; ++b) {
-                    const u32x4 ah = lds[buf][0][(wr * 4 + b) * 64 + lane];
-                    const u32x4 al = lds[buf][1][(wr * 4 + b) * 64 + lane];
+                for (int c = 0; c < NB; ++c) {
+                    const u32x4 wh = lds[buf][2][c * 64 + lane], wl = lds[buf][3][c * 64 + lane];
 #pragma unroll
-                    for (int c = 0; c < 4; ++c) {
-                        acc[4 * b + c] = mfma_bf16(ah, wh[c], acc[4 * b + c]);
-                        acc[4 * b + c] = mfma_bf16(ah, wl[c], acc[4 * b + c]);
-                        acc[4 * b + c] = mfma_bf16(al, wh[c], acc[4 * b + c]);
+                    for (int b = 0; b < 2; ++b) {
+                        acc[b][c] = mfma_bf16(ah[b], wh, acc[b][c]);
+                        acc[b][c] = mfma_bf16(ah[b], wl, acc[b][c]);
+                        acc[b][c] = mfma_bf16(al[b], wh, acc[b][c]);
                     }
                 }
             }
@@ -748,8 +740,11 @@ __device__ void column_bf16_body(const StepDesc &d, int64_t item)
     }
     float *Cq = (float *)d.C + split * d.cstride + lane * 4;
 #pragma unroll
-    for (int f = 0; f < 16; ++f)
-        if (ok[f]) st4(Cq + off[f], acc[f]);
+    for (int b = 0; b < 2; ++b)
+        if (ok[b]) {
+#pragma unroll
+            for (int c = 0; c < NB; ++c) st4(Cq + off[b] + (c << 8), acc[b][c]);
+        }
 }
 
 // ---------------------------------------------------------------------------------------------
