@@ -268,6 +268,56 @@ OED_API oed_status oed_batch_get_config(const oed_batch *b, int32_t *delay, doub
 OED_API oed_status oed_batch_destroy(oed_batch *b);
 OED_API const char *oed_batch_last_error(const oed_batch *b);
 
+/* ---------------------------------------------------------------------------------------------
+ * Design evaluation: the objective of given sensor sets, as in the comparison of the greedy
+ * design with random and uniformly spaced ones (Sec. IV-E, Fig. 5).  For a design
+ * S = (s_0, ..., s_{B-1}) of distinct sensors and isotropic noise (Sec. III-C),
+ *     f(S) = 1/2 logdet(sigma^-2 K_SS) = sum_k t_k,  t_k = 1/2 logdet(S_k) - (N_t/2) ln sigma^2,
+ * where S_k is the Schur complement of K's block s_k given s_0 .. s_{k-1} (chain rule of the
+ * determinant, the recursion of Algorithm 1, Sec. III-D).  t_k is the gain the greedy would
+ * credit s_k after conditioning on s_0 .. s_{k-1}, so the greedy design in its pick order
+ * reproduces the greedy gains term by term.  f(S) does not depend on the order; the terms do.
+ * Each design runs as a selection whose k-th pick is forced to s_k (a blocked right-looking
+ * Cholesky of K_SS with the pick, block-column and downdate kernels; no gain scoring), and up
+ * to `batch` designs run together in one batched launch sequence (a HIP graph unless
+ * OED_BATCH_NO_GRAPH).
+ */
+typedef struct oed_eval oed_eval;
+
+/*
+ * Evaluator of designs of B sensors (1 <= B <= N_s) over K (device, dtype OED_F64 or OED_F32,
+ * row-major, ld >= N_s*N_t, lower triangle read; it must stay valid and unchanged for the life
+ * of the evaluator, since every run packs from it).  N_t <= 128.  max_batch: designs per batched
+ * launch sequence; 0 = as many as fit in half the free device memory, at most 64.  precision:
+ * oed_precision (downdate type; the block factorisations are FP64).  flags: OED_FLAG_PROFILE,
+ * OED_BATCH_NO_GRAPH, OED_BATCH_DELAY(p); anything else is OED_E_ARG.  Allocates all device
+ * memory of the evaluator.  On failure *out is NULL.
+ */
+OED_API oed_status oed_eval_create(oed_eval **out, const void *K_dev, int32_t dtype, int64_t ld, int32_t N_s,
+                                   int32_t N_t, double sigma2, int32_t B, int32_t max_batch, int32_t precision,
+                                   void *stream, uint32_t flags);
+
+/*
+ * Evaluate n designs: designs (host) holds design r at designs[r*B .. r*B+B), each entry a
+ * sensor in [0, N_s), no sensor twice in a design (else OED_E_ARG and nothing runs).  Outputs
+ * (host): obj_out[r] = f(S_r); terms_out (may be NULL) [r*B + k] = t_k of design r.  A design
+ * whose Schur block is not positive definite gets obj NaN (terms NaN from that block on), the
+ * others are still evaluated, and the call returns OED_E_NOT_SPD.  Designs run in chunks of the
+ * evaluator's batch size; a short last chunk costs a full one.  Synchronises the creation stream
+ * first, then runs on the evaluator's own stream and returns when the results are on the host.
+ */
+OED_API oed_status oed_eval_run(oed_eval *e, const int32_t *designs, int32_t n, double *obj_out,
+                                double *terms_out);
+
+/* Of the last oed_eval_run: *run_ms, milliseconds of its launch sequences (HIP events; needs
+ * OED_FLAG_PROFILE, else 0); *syrk_flops, algorithmic downdate flops executed (definition as in
+ * oed_profile, all executed instances); *executed, instances executed (n rounded up to chunks);
+ * *batch, designs per chunk.  Any output pointer may be NULL. */
+OED_API oed_status oed_eval_stats(const oed_eval *e, double *run_ms, double *syrk_flops, int64_t *executed,
+                                  int32_t *batch);
+OED_API oed_status oed_eval_destroy(oed_eval *e);
+OED_API const char *oed_eval_last_error(const oed_eval *e);
+
 /* Bytes of device memory the handle holds. */
 OED_API oed_status oed_device_bytes(const oed_ctx *h, int64_t *bytes);
 

@@ -6,6 +6,11 @@ The selection runs in liboed.so (HIP kernels behind the C ABI of
 from .oed import (  # noqa: F401
     EXPORTED,
     BatchSelector,
+    Evaluator,
+    oed_eval_create,
+    oed_eval_destroy,
+    oed_eval_run,
+    oed_eval_stats,
     oed_batch_create,
     oed_batch_destroy,
     oed_batch_get_config,

@@ -67,6 +67,7 @@ struct oed_batch {
     int prec = OED_PREC_FP64, rtype = R_F64, wtype = W_F64;
     int delay = 2;
     bool left = false;  // left-looking: W slot k holds pick k's block column
+    bool eval = false;  // design evaluation: pick k is candidate k, no gain scoring
     double tuned_ms[MAX_DELAY] = {0};  // autotuner: eager run time for delay 1..MAX_DELAY
     uint32_t flags = 0;
     hipStream_t stream = nullptr;
@@ -293,22 +294,25 @@ void build_schedule(oed_batch *b)
         b->launches.push_back(L);
     }
     for (int k = 0; k < maxB; ++k) {
-        // gains and pick of step k
-        Launch g = make_launch(L_GAIN, (int64_t)b->descs.size());
-        for (const Inst &x : b->in)
-            if (x.budget > k) {
-                StepDesc d = inst_desc(x, k, false, b->delay);
-                d.item0 = g.total;
-                d.nitems = d.n_act;
-                g.total += d.nitems;
-                b->descs.push_back(d);
-                ++g.ndesc;
-            }
-        b->launches.push_back(g);
+        // gains and pick of step k (design evaluation: no gains, the pick is candidate k)
+        if (!b->eval) {
+            Launch g = make_launch(L_GAIN, (int64_t)b->descs.size());
+            for (const Inst &x : b->in)
+                if (x.budget > k) {
+                    StepDesc d = inst_desc(x, k, false, b->delay);
+                    d.item0 = g.total;
+                    d.nitems = d.n_act;
+                    g.total += d.nitems;
+                    b->descs.push_back(d);
+                    ++g.ndesc;
+                }
+            b->launches.push_back(g);
+        }
         Launch p = make_launch(L_PICK, (int64_t)b->descs.size());
         for (const Inst &x : b->in)
             if (x.budget > k) {
                 StepDesc d = inst_desc(x, k, false, b->delay);
+                if (b->eval) d.forced = k;
                 d.item0 = p.total;
                 d.nitems = 1;
                 p.total += 1;
@@ -432,8 +436,10 @@ oed_status autotune_batch(oed_batch *b, const oed_instance *inst)
 
 extern "C" {
 
-oed_status oed_batch_create(oed_batch **out, const oed_instance *inst, int32_t n, int32_t precision, void *stream,
-                            uint32_t flags)
+// Batch creation; eval: design evaluation (pick k forced to candidate k, no gains, nothing
+// packed: the caller sets every instance's candidate map and packs before each run).
+static oed_status create_batch(oed_batch **out, const oed_instance *inst, int32_t n, int32_t precision,
+                               void *stream, uint32_t flags, bool eval)
 {
     if (!out) return OED_E_ARG;
     *out = nullptr;
@@ -450,6 +456,7 @@ oed_status oed_batch_create(oed_batch **out, const oed_instance *inst, int32_t n
     b->flags = flags;
     b->delay = (int)((flags >> 8) & 0xFu);
     b->left = (flags & OED_BATCH_LEFT_LOOKING) != 0;
+    b->eval = eval;
     const bool tune = !b->left && b->delay == 0 && (flags & OED_BATCH_AUTOTUNE);
     if (b->delay == 0) b->delay = MAX_DELAY;
     if (b->left) b->delay = 1;
@@ -523,7 +530,7 @@ oed_status oed_batch_create(oed_batch **out, const oed_instance *inst, int32_t n
         }
         build_schedule(b);
         BCHK(b, hipMemcpy(b->d_descs, b->descs.data(), sizeof(StepDesc) * b->descs.size(), hipMemcpyHostToDevice));
-        return pack_all(b, inst);
+        return eval ? OED_OK : pack_all(b, inst);
     };
     st = setup();
     if (st != OED_OK) {
@@ -533,6 +540,12 @@ oed_status oed_batch_create(oed_batch **out, const oed_instance *inst, int32_t n
     }
     *out = b;
     return OED_OK;
+}
+
+oed_status oed_batch_create(oed_batch **out, const oed_instance *inst, int32_t n, int32_t precision, void *stream,
+                            uint32_t flags)
+{
+    return create_batch(out, inst, n, precision, stream, flags, false);
 }
 
 oed_status oed_batch_get_config(const oed_batch *b, int32_t *delay, double *per_run_ms)
@@ -630,5 +643,171 @@ oed_status oed_batch_destroy(oed_batch *b)
 }
 
 const char *oed_batch_last_error(const oed_batch *b) { return b ? b->err.c_str() : "null batch"; }
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------------------------
+// Design evaluation: every design is one instance of an evaluation batch whose candidates are
+// the design's sensors in the given order and whose k-th pick is forced to candidate k, so the
+// pick kernel factors the Schur complement of s_k given s_0 .. s_{k-1} and records its term;
+// the block-column and downdate launches are the selection's.  The batch (its memory, schedule
+// and graph) is built once; a run fills the candidate maps, packs and replays it per chunk.
+
+struct oed_eval {
+    oed_batch *b = nullptr;
+    std::vector<oed_instance> inst;  // nb copies of (K, N_t, B candidates, budget B)
+    hipStream_t caller = nullptr;
+    int N_s = 0, N_t = 0, B = 0, nb = 0;
+    double last_ms = 0, syrk_flops = 0;
+    int64_t executed = 0;
+    std::string err;
+};
+
+namespace {
+
+oed_status efail(oed_eval *e, oed_status st, const std::string &msg)
+{
+    if (e) e->err = msg;
+    return st;
+}
+
+// Device bytes of one evaluation instance (working copy, W slots, V, L^-1 and small arrays).
+size_t eval_inst_bytes(int B, int N_t, int precision, int delay)
+{
+    const bool bf = precision == OED_PREC_MIXED_BF16X3;
+    const size_t er = precision == OED_PREC_FP64 ? 8 : 4, ew = bf ? 4 : er;
+    const size_t N_tp = bf ? (N_t + 31) / 32 * 32 : (N_t + 15) / 16 * 16, bs = N_tp * N_tp;
+    return (size_t)B * (B + 1) / 2 * bs * er + (size_t)delay * B * bs * ew + (size_t)delay * bs * 8 +
+           (size_t)B * 64 + 4096;
+}
+
+}  // namespace
+
+extern "C" {
+
+oed_status oed_eval_create(oed_eval **out, const void *K_dev, int32_t dtype, int64_t ld, int32_t N_s, int32_t N_t,
+                           double sigma2, int32_t B, int32_t max_batch, int32_t precision, void *stream,
+                           uint32_t flags)
+{
+    if (!out) return OED_E_ARG;
+    *out = nullptr;
+    if (!K_dev || (dtype != OED_F64 && dtype != OED_F32) || N_s < 1 || N_t < 1 || ld < (int64_t)N_s * N_t ||
+        !(sigma2 > 0.0) || !std::isfinite(sigma2) || B < 1 || B > N_s || max_batch < 0)
+        return OED_E_ARG;
+    if (precision != OED_PREC_FP64 && precision != OED_PREC_MIXED_F32 && precision != OED_PREC_MIXED_BF16X3)
+        return OED_E_ARG;
+    if (flags & ~(uint32_t)(OED_FLAG_PROFILE | OED_BATCH_NO_GRAPH | 0xF00u)) return OED_E_ARG;
+    const int delay = (int)((flags >> 8) & 0xFu);
+    if (delay > MAX_DELAY) return OED_E_ARG;
+    if (N_t > REGS_MAX_NT) return OED_E_UNSUPPORTED;
+    int nb = max_batch;
+    if (nb == 0) {
+        size_t fr = 0, tot = 0;
+        if (hipMemGetInfo(&fr, &tot) != hipSuccess) return OED_E_HIP;
+        const size_t per = eval_inst_bytes(B, N_t, precision, delay ? delay : MAX_DELAY);
+        nb = (int)std::max<size_t>(1, std::min<size_t>(64, fr / 2 / per));
+    }
+    oed_eval *e = new (std::nothrow) oed_eval();
+    if (!e) return OED_E_OOM;
+    e->N_s = N_s;
+    e->N_t = N_t;
+    e->B = B;
+    e->nb = nb;
+    e->caller = (hipStream_t)stream;
+    oed_instance x{};
+    x.K_dev = K_dev;
+    x.dtype = dtype;
+    x.N_s = B;
+    x.N_t = N_t;
+    x.budget = B;
+    x.ld = ld;
+    x.sigma2 = sigma2;
+    e->inst.assign(nb, x);
+    const oed_status st = create_batch(&e->b, e->inst.data(), nb, precision, stream, flags, true);
+    if (st != OED_OK) {
+        delete e;
+        return st;
+    }
+    *out = e;
+    return OED_OK;
+}
+
+oed_status oed_eval_run(oed_eval *e, const int32_t *designs, int32_t n, double *obj_out, double *terms_out)
+{
+    if (!e) return OED_E_ARG;
+    if (n < 0 || (n > 0 && (!designs || !obj_out))) return efail(e, OED_E_ARG, "bad arguments");
+    const int B = e->B, nb = e->nb;
+    std::vector<char> seen(e->N_s);
+    for (int64_t r = 0; r < n; ++r) {
+        std::fill(seen.begin(), seen.end(), 0);
+        for (int k = 0; k < B; ++k) {
+            const int32_t s = designs[r * B + k];
+            if (s < 0 || s >= e->N_s || seen[s])
+                return efail(e, OED_E_ARG, "design " + std::to_string(r) + ": sensor out of range or repeated");
+            seen[s] = 1;
+        }
+    }
+    oed_batch *b = e->b;
+    if (hipStreamSynchronize(e->caller) != hipSuccess) return efail(e, OED_E_HIP, "caller stream");
+    std::vector<int32_t> idx((size_t)nb * B), made(nb), stat(nb);
+    std::vector<double> g((size_t)nb * B);
+    e->last_ms = 0;
+    e->syrk_flops = 0;
+    e->executed = 0;
+    oed_status worst = OED_OK;
+    for (int64_t c0 = 0; c0 < n; c0 += nb) {
+        const int cnt = (int)std::min<int64_t>(nb, n - c0);
+        // a short last chunk repeats its last design in the unused instances
+        for (int i = 0; i < nb; ++i) {
+            const int32_t *S = designs + (size_t)(c0 + std::min(i, cnt - 1)) * B;
+            if (hipMemcpy(b->in[i].cmap, S, sizeof(int32_t) * B, hipMemcpyHostToDevice) != hipSuccess)
+                return efail(e, OED_E_HIP, "candidate map upload");
+        }
+        oed_status st = pack_all(b, e->inst.data());
+        if (st != OED_OK) return efail(e, st, b->err);
+        st = oed_batch_run(b, idx.data(), g.data(), made.data(), stat.data());
+        if (st != OED_OK && st != OED_E_NOT_SPD) return efail(e, st, b->err);
+        e->last_ms += b->last_ms;
+        e->syrk_flops += b->syrk_flops;
+        e->executed += nb;
+        for (int i = 0; i < cnt; ++i) {
+            const size_t r = (size_t)(c0 + i);
+            bool ok = stat[i] == OED_OK && made[i] == B;
+            double sum = 0.0;
+            for (int k = 0; k < B; ++k) {
+                const bool have = k < made[i] && idx[(size_t)i * B + k] == k;
+                ok = ok && have;
+                const double t = have ? g[(size_t)i * B + k] : NAN;
+                sum += t;
+                if (terms_out) terms_out[r * B + k] = t;
+            }
+            obj_out[r] = ok ? sum : NAN;
+            if (!ok) worst = OED_E_NOT_SPD;
+        }
+    }
+    if (worst != OED_OK)
+        return efail(e, worst, "a design has a Schur block that is not positive definite: its objective is NaN");
+    return OED_OK;
+}
+
+oed_status oed_eval_stats(const oed_eval *e, double *run_ms, double *syrk_flops, int64_t *executed, int32_t *batch)
+{
+    if (!e) return OED_E_ARG;
+    if (run_ms) *run_ms = e->last_ms;
+    if (syrk_flops) *syrk_flops = e->syrk_flops;
+    if (executed) *executed = e->executed;
+    if (batch) *batch = e->nb;
+    return OED_OK;
+}
+
+oed_status oed_eval_destroy(oed_eval *e)
+{
+    if (!e) return OED_OK;
+    (void)oed_batch_destroy(e->b);
+    delete e;
+    return OED_OK;
+}
+
+const char *oed_eval_last_error(const oed_eval *e) { return e ? e->err.c_str() : "null evaluator"; }
 
 }  // extern "C"

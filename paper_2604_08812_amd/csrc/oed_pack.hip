@@ -7,6 +7,8 @@ namespace oed {
 
 // ---------------------------------------------------------------------------------------------
 // Pack the candidate part of K's lower triangle into R (padded, packed, accumulator order).
+// Candidate i is sensor cmap[i]; the map need not be increasing (blocks above K's diagonal are
+// read as the transpose of the block below it).
 // One thread per (block, sub-block, lane): it writes the lane's 4 elements with one vector store.
 template <typename TK, typename TR>
 __global__ void __launch_bounds__(256) pack_kernel(const TK *__restrict__ K, int64_t ld, int N_t, int N_tp,
@@ -34,9 +36,12 @@ __global__ void __launch_bounds__(256) pack_kernel(const TK *__restrict__ K, int
             double x;
             if (t < N_t && u < N_t) {
                 int64_t row, col;
-                if (i != j) {
+                if (ci > cj) {
                     row = ci * N_t + t;
                     col = cj * N_t + u;
+                } else if (ci < cj) {  // block (ci, cj) lies above K's diagonal: its transpose
+                    row = cj * N_t + u;
+                    col = ci * N_t + t;
                 } else {
                     row = ci * N_t + (t >= u ? t : u);
                     col = ci * N_t + (t >= u ? u : t);

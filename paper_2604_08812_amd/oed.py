@@ -92,9 +92,18 @@ def library() -> ctypes.CDLL:
     L.oed_batch_get_config.argtypes = [vp, ip, dp]
     L.oed_batch_last_error.argtypes = [vp]
     L.oed_batch_last_error.restype = ctypes.c_char_p
+    L.oed_eval_create.argtypes = [ctypes.POINTER(vp), vp, ctypes.c_int32, ctypes.c_int64, ctypes.c_int32,
+                                  ctypes.c_int32, ctypes.c_double, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, vp,
+                                  ctypes.c_uint32]
+    L.oed_eval_run.argtypes = [vp, ip, ctypes.c_int32, dp, dp]
+    L.oed_eval_stats.argtypes = [vp, dp, dp, ctypes.POINTER(ctypes.c_int64), ip]
+    L.oed_eval_destroy.argtypes = [vp]
+    L.oed_eval_last_error.argtypes = [vp]
+    L.oed_eval_last_error.restype = ctypes.c_char_p
     for name in ("oed_create", "oed_reset", "oed_greedy", "oed_force", "oed_scores", "oed_schur_block", "oed_picks",
                  "oed_get_profile", "oed_device_bytes", "oed_destroy", "oed_batch_create", "oed_batch_run",
-                 "oed_batch_reset", "oed_batch_stats", "oed_batch_destroy"):
+                 "oed_batch_reset", "oed_batch_stats", "oed_batch_destroy", "oed_batch_get_config", "oed_get_config",
+                 "oed_eval_create", "oed_eval_run", "oed_eval_stats", "oed_eval_destroy"):
         getattr(L, name).restype = ctypes.c_int32
     _lib = L
     return L
@@ -104,7 +113,8 @@ EXPORTED = ("oed_options_init", "oed_create", "oed_reset", "oed_greedy", "oed_fo
             "oed_schur_block", "oed_picks", "oed_get_profile", "oed_device_bytes", "oed_get_config", "oed_destroy",
             "oed_last_error",
             "oed_status_string", "oed_batch_create", "oed_batch_run", "oed_batch_reset", "oed_batch_stats",
-            "oed_batch_destroy", "oed_batch_last_error", "oed_batch_get_config")
+            "oed_batch_destroy", "oed_batch_last_error", "oed_batch_get_config", "oed_eval_create", "oed_eval_run",
+            "oed_eval_stats", "oed_eval_destroy", "oed_eval_last_error")
 
 
 def _status_name(s):
@@ -341,6 +351,91 @@ class BatchSelector:
         if self.b:
             oed_batch_destroy(self.b)
             self.b = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def _echeck(e, st):
+    if st != OED_OK:
+        msg = library().oed_eval_last_error(e).decode() if e else ""
+        raise OedError(st, msg)
+
+
+def oed_eval_create(K, N_s, N_t, sigma2, B, max_batch=0, precision="fp64", profile=False, graph=True, stream=None,
+                    delay=0):
+    import torch
+    if not isinstance(K, torch.Tensor) or not K.is_cuda or K.dim() != 2 or K.stride(1) != 1:
+        raise ValueError("K must be a 2-D row-major device tensor")
+    if K.shape[0] < N_s * N_t or K.shape[1] < N_s * N_t:
+        raise ValueError("K must have at least N_s*N_t rows and columns")
+    dt = {torch.float64: OED_F64, torch.float32: OED_F32}.get(K.dtype)
+    if dt is None:
+        raise ValueError("K must be float64 or float32")
+    e = ctypes.c_void_p()
+    flags = (OED_FLAG_PROFILE if profile else 0) | (0 if graph else OED_BATCH_NO_GRAPH) | (int(delay) << 8)
+    st = library().oed_eval_create(ctypes.byref(e), ctypes.c_void_p(K.data_ptr()), dt, K.stride(0), int(N_s),
+                                   int(N_t), float(sigma2), int(B), int(max_batch), PRECISIONS[precision],
+                                   _stream_handle(stream), flags)
+    _echeck(None, st)
+    return e
+
+
+def oed_eval_run(e, designs, check=True):
+    """designs: (n, B) int array.  Returns (objectives (n,), terms (n, B), status)."""
+    d = np.ascontiguousarray(designs, dtype=np.int32)
+    if d.ndim != 2:
+        raise ValueError("designs must be a 2-D (n, B) array")
+    n, B = d.shape
+    obj = np.empty(max(n, 1))
+    terms = np.empty((max(n, 1), B))
+    st = library().oed_eval_run(e, _ip(d), n, _dp(obj), _dp(terms))
+    if check:
+        _echeck(e, st)
+    return obj[:n].copy(), terms[:n].copy(), st
+
+
+def oed_eval_stats(e):
+    ms, fl = ctypes.c_double(), ctypes.c_double()
+    ex, nb = ctypes.c_int64(), ctypes.c_int32()
+    _echeck(e, library().oed_eval_stats(e, ctypes.byref(ms), ctypes.byref(fl), ctypes.byref(ex), ctypes.byref(nb)))
+    return {"run_ms": ms.value, "syrk_flops": fl.value, "executed": ex.value, "batch": nb.value}
+
+
+def oed_eval_destroy(e):
+    if e:
+        library().oed_eval_destroy(e)
+
+
+class Evaluator:
+    """Objective f(S) = 1/2 logdet(sigma^-2 K_SS) of given designs of B sensors:
+    ``Evaluator(K, N_s, N_t, sigma2, B).run(designs)`` -> (objectives, per-block terms)."""
+
+    def __init__(self, K, N_s, N_t, sigma2, B, max_batch=0, precision="fp64", profile=False, graph=True,
+                 stream=None, delay=0):
+        self.B = int(B)
+        self.e = oed_eval_create(K, N_s, N_t, sigma2, B, max_batch, precision, profile, graph, stream, delay)
+
+    def run(self, designs, check=True):
+        obj, terms, _ = oed_eval_run(self.e, designs, check)
+        return obj, terms
+
+    def stats(self):
+        return oed_eval_stats(self.e)
+
+    def close(self):
+        if self.e:
+            oed_eval_destroy(self.e)
+            self.e = None
 
     def __enter__(self):
         return self

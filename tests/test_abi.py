@@ -115,3 +115,25 @@ def test_batch_host_side_validation(lib):
     assert lib.oed_batch_create(ctypes.byref(b), arr, 1, 9, None, 0) == 1   # no such precision
     assert not b.value
     assert lib.oed_batch_destroy(None) == 0
+
+
+def test_eval_host_side_validation(lib):
+    e = ctypes.c_void_p()
+    fake = ctypes.c_void_p(0x1000)  # never dereferenced: validation fails before any device call
+    E_ARG, E_UNSUPPORTED = 1, 6
+    #            K     dtype ld   N_s N_t sigma2 B  batch prec stream flags
+    good = [fake, 0, 128, 8, 16, 1.0, 4, 2, 1, None, 0]
+    for pos, val, code in ((0, None, E_ARG), (1, 5, E_ARG), (2, 127, E_ARG), (3, 0, E_ARG), (5, 0.0, E_ARG),
+                           (5, float("inf"), E_ARG), (6, 0, E_ARG), (6, 9, E_ARG), (7, -1, E_ARG), (8, 7, E_ARG),
+                           (10, 0x10, E_ARG), (10, 0x20, E_ARG), (10, 5 << 8, E_ARG)):
+        args = list(good)
+        args[pos] = val
+        assert lib.oed_eval_create(ctypes.byref(e), *args) == code, (pos, val)
+        assert not e.value
+    big = [fake, 0, 2 * 160, 2, 160, 1.0, 1, 1, 1, None, 0]
+    assert lib.oed_eval_create(ctypes.byref(e), *big) == E_UNSUPPORTED
+    assert lib.oed_eval_create(None, *good) == E_ARG
+    assert lib.oed_eval_destroy(None) == 0
+    assert lib.oed_eval_run(None, None, 0, None, None) == E_ARG
+    assert lib.oed_eval_stats(None, None, None, None, None) == E_ARG
+    assert lib.oed_eval_last_error(None) == b"null evaluator"

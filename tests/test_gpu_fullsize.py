@@ -160,3 +160,42 @@ def test_fullsize_left_looking(big, runs, prec):
     sub = k_sub_lower(K, spec.N_t, il)
     total = 0.5 * oracle.logdet_lapack(sub) - 0.5 * len(il) * spec.N_t * np.log(s2)
     assert abs(gl.sum() - total) / abs(total) <= RTOL[prec]
+
+
+@pytest.fixture(scope="module")
+def eval_designs(big, runs):
+    """The FP64 greedy design in pick order, one random design and the uniformly spaced one, all
+    of B = 175 sensors, with the oracle's objective of the last two (LAPACK Cholesky of the
+    22,400^2 K_SS)."""
+    spec, K, s2 = big
+    B = spec.budget
+    rng = np.random.default_rng(5)
+    rand = rng.permutation(spec.N_s)[:B]
+    unif = np.round(np.linspace(0, spec.N_s - 1, B)).astype(np.int64)
+    ref = []
+    for S in (rand, unif):
+        sub = k_sub_lower(K, spec.N_t, S)
+        ref.append(0.5 * oracle.logdet_lapack(sub) - 0.5 * B * spec.N_t * np.log(s2))
+        del sub
+    designs = np.stack([runs["fp64"][0], rand, unif]).astype(np.int32)
+    return designs, ref
+
+
+@pytest.mark.timeout(900)
+@pytest.mark.parametrize("prec", PRECS)
+def test_fullsize_design_evaluation(big, runs, eval_designs, prec):
+    from paper_2604_08812_amd import Evaluator
+    spec, K, s2 = big
+    designs, ref = eval_designs
+    print(f"design evaluation {prec}: 3 designs of {spec.budget} sensors", flush=True)
+    with Evaluator(K, spec.N_s, spec.N_t, s2, spec.budget, max_batch=2, precision=prec) as ev:
+        obj, terms = ev.run(designs)
+    i_g, g_g = runs[prec]
+    same = next((k for k in range(spec.budget) if i_g[k] != designs[0][k]), spec.budget)
+    err_g = rel_err(terms[0][:same], g_g[:same]).max()
+    err_r = rel_err(obj[1:], np.asarray(ref)).max()
+    print(f"{prec}: greedy terms vs gains over {same} steps {err_g:.2e}; random/uniform objective "
+          f"{obj[1]:.10e}/{obj[2]:.10e} vs {ref[0]:.10e}/{ref[1]:.10e}, rel {err_r:.2e}")
+    assert err_g <= RTOL[prec]
+    assert err_r <= RTOL[prec]
+    assert obj[0] > obj[1] and obj[0] > obj[2]
