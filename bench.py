@@ -53,6 +53,9 @@ def parse():
     ap.add_argument("--delay", type=int, default=0, help="downdate delay depth (0: the library's choice)")
     ap.add_argument("--no-autotune", action="store_true",
                     help="with --delay 0, take the library's fixed default instead of its autotuner")
+    ap.add_argument("--no-eval", action="store_true", help="skip the design-evaluation leg")
+    ap.add_argument("--eval-designs", type=int, default=64,
+                    help="designs of the evaluation leg: the greedy one, the uniform one and random ones")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-budget", type=int, default=16, help="picks of the oracle sample")
     ap.add_argument("--cpu-sensors", type=int, default=100)
@@ -232,6 +235,41 @@ def per_step_diff(gain, gain_ref, upto):
         return None
     d = np.abs(gain[:upto] - gain_ref[:upto]) / np.maximum(1, np.abs(gain_ref[:upto]))
     return {"max": float(d.max()), "median": float(np.median(d)), "p90": float(np.quantile(d, 0.9))}
+
+
+def design_evaluation(K, spec, s2, prec, budget, idx, gain, n):
+    """Objective of the greedy design (pick order), the uniformly spaced one and n - 2 random
+    ones of the same size, in batched launch sequences of n/2 designs; a warm-up run captures
+    the graph, the second run is timed."""
+    import numpy as np
+    import torch
+    from paper_2604_08812_amd import Evaluator
+    rng = np.random.default_rng(5)
+    unif = np.round(np.linspace(0, spec.N_s - 1, budget)).astype(np.int32)
+    rand = [rng.permutation(spec.N_s)[:budget] for _ in range(n - 2)]
+    designs = np.stack([np.asarray(idx, dtype=np.int32), unif] + rand).astype(np.int32)
+    nb = (n + 1) // 2
+    with Evaluator(K, spec.N_s, spec.N_t, s2, budget, max_batch=nb, precision=prec, profile=True) as ev:
+        ev.run(designs)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        obj, terms = ev.run(designs)
+        wall = time.perf_counter() - t0
+        st = ev.stats()
+    r = obj[2:]
+    mu, sd = float(r.mean()), float(r.std(ddof=1))
+    log(f"design evaluation: {n} designs of {budget} in {wall:.2f} s; greedy {obj[0]:.6f}, uniform {obj[1]:.6f}, "
+        f"random mean {mu:.6f} sd {sd:.3e} max {r.max():.6f}")
+    return {"value": round(n / wall, 3), "unit": "designs/s", "designs": n, "B": budget, "precision": prec,
+            "batch": st["batch"], "ms_per_design": round(wall * 1e3 / n, 3),
+            "graph_ms": round(st["run_ms"], 3),
+            "downdate_tflops_over_run": round(st["syrk_flops"] / (st["run_ms"] * 1e-3) / 1e12, 3)
+            if st["run_ms"] > 0 else None,
+            "greedy_objective": float(obj[0]), "uniform_objective": float(obj[1]),
+            "random_mean": mu, "random_sd": sd, "random_max": float(r.max()),
+            "greedy_z_score": round((float(obj[0]) - mu) / sd, 3) if sd > 0 else None,
+            "greedy_above_best_random_in_sd": round((float(obj[0]) - float(r.max())) / sd, 3) if sd > 0 else None,
+            "greedy_terms_vs_gains_max_rel": float(np.max(np.abs(terms[0] - gain) / np.maximum(1, np.abs(gain))))}
 
 
 def run_batched(args):
@@ -443,6 +481,10 @@ def main():
             ref = (idx64, gain64) if "fp64" in result else (idx, gain)
             leg["vs_fp64_right_looking" if "fp64" in result else "vs_headline"] = compare_picks(idxl, gainl, *ref)
             result["left_looking_" + lp] = leg
+
+    # ---- design evaluation: the greedy design against random and uniformly spaced ones
+    if not args.no_eval and spec.N_t <= 128 and args.eval_designs >= 3:
+        result["design_evaluation"] = design_evaluation(K, spec, s2, prec, budget, idx, gain, args.eval_designs)
 
     # ---- CPU oracle baseline on a bounded sample of the same K
     if not args.no_cpu_baseline:
