@@ -86,6 +86,12 @@ typedef enum oed_precision {
                                   timing one step's kernels on the packed working copy (see
                                   oed_get_config); the choice is cached per device, precision,
                                   block size and candidate count for the life of the process */
+#define OED_FLAG_DEFER_PACK 0x8u /* create without K (K_dev must be NULL; dtype and ld are ignored):
+                                    the working copy is filled block row by block row with
+                                    oed_pack_rows before the first step, so that K never has to
+                                    be resident in full beside it (600 sensors x 420 observations,
+                                    the paper's shape: the FP32 working copy takes 135 GB, a full
+                                    FP32 K another 254 GB).  Not with OED_FLAG_AUTOTUNE. */
 
 typedef struct oed_options {
     uint32_t struct_size;       /* sizeof(oed_options); set by oed_options_init */
@@ -149,9 +155,29 @@ OED_API oed_status oed_create(oed_ctx **out, const void *K_dev, int32_t dtype, i
 
 /*
  * Reload the working copy from K_dev (same dtype, ld and shape as at creation)
- * and forget all picks.  Allocates nothing.
+ * and forget all picks.  Allocates nothing.  For a handle created with
+ * OED_FLAG_DEFER_PACK, K_dev must be NULL: the picks are forgotten and every
+ * block row must be packed again with oed_pack_rows.
  */
 OED_API oed_status oed_reset(oed_ctx *h, const void *K_dev);
+
+/*
+ * Pack the block rows of sensors sensor0 .. sensor0 + n_sensors - 1 into the
+ * working copy of a handle created with OED_FLAG_DEFER_PACK (Sec. III-F keeps
+ * K out of device memory and fetches its blocks as needed; here the caller
+ * forms K panel by panel and frees each panel after this call).  K_rows
+ * (device, dtype OED_F64 or OED_F32, row-major, leading dimension ld) holds
+ * rows sensor0*N_t .. (sensor0 + n_sensors)*N_t - 1 of K, row r at
+ * K_rows + (r - sensor0*N_t)*ld, with at least the columns
+ * 0 .. (sensor0 + n_sensors)*N_t - 1 (ld >= that width); only column <= row is
+ * read.  Sensors that are not candidates are skipped; packing a row twice
+ * overwrites it.  Only before the first pick (after creation or a reset).
+ * The greedy, force, scores and Schur-block calls return OED_E_STATE until
+ * every candidate's block row has been packed.  Synchronises the handle's
+ * stream before returning, so the caller may free K_rows afterwards.
+ */
+OED_API oed_status oed_pack_rows(oed_ctx *h, const void *K_rows, int32_t dtype, int64_t ld, int32_t sensor0,
+                                 int32_t n_sensors);
 
 /*
  * Run `budget` more greedy steps (Sec. III-D): each step scores all remaining

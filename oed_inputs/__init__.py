@@ -11,6 +11,8 @@ from .synth import (  # noqa: F401
     TILE,
     tile_seed,
     f_tile,
+    f_matrix,
+    k_row_panels,
     make_K,
     make_K_lower_panels,
     make_K_sensor_noise,

@@ -38,6 +38,10 @@ CONFIGS = {
                           notes="same K as fp64_600x128; R in FP32"),
     "large_1500x96": Spec("large_1500x96", 1500, 96, 40000, 2, 175, precision="mixed_f32",
                           k_dtype="f32"),
+    # the paper's shape: K (252,000^2) is never whole on the GPU; F (40 GB FP32) stays resident and
+    # K's row panels are formed one GEMM at a time and packed into the working copy (135 GB FP32)
+    "paper_600x420": Spec("paper_600x420", 600, 420, 40000, 3, 175, precision="mixed_f32", k_dtype="f32",
+                          notes="F resident, K formed and packed by row panels"),
 }
 
 

@@ -130,6 +130,40 @@ def make_K_lower_panels(N_s: int, N_t: int, n_m: int, seed: int, c: float = 0.01
     return K, sigma2
 
 
+def f_matrix(N_d: int, n_m: int, seed: int, device="cuda", dtype=torch.float32, progress=None):
+    """F itself (``N_d x n_m``), drawn by column tile in FP64 as above and stored in ``dtype``, with
+    the FP64 mean of ``diag(F F^T) / n_m`` taken from the FP64 draws (the noise scale).
+    Returns ``(F, scale)``; ``sigma^2 = c * scale``.  For K too large to be formed whole: its row
+    panels come from ``k_row_panels``."""
+    F = torch.empty((N_d, n_m), dtype=dtype, device=device)
+    sq = torch.zeros(N_d, dtype=torch.float64, device=device)
+    n_cb = math.ceil(n_m / TILE)
+    for cb in range(n_cb):
+        Fc = f_column_chunk(seed, N_d, n_m, cb, device)
+        sq += (Fc * Fc).sum(1)
+        F[:, cb * TILE:cb * TILE + Fc.shape[1]] = Fc.to(dtype)
+        del Fc
+        if progress is not None:
+            progress(cb + 1, n_cb)
+    return F, float(sq.mean().item()) / n_m
+
+
+def k_row_panels(F: torch.Tensor, N_s: int, N_t: int, sigma2: float, panel_sensors: int):
+    """Row panels of ``K = F F^T / n_m + sigma^2 I`` in F's dtype, one GEMM each: yields
+    ``(sensor0, n, P)`` with ``P`` = rows ``sensor0*N_t .. (sensor0+n)*N_t - 1`` of K and its
+    columns ``0 .. (sensor0+n)*N_t - 1`` (the panel's lower block triangle and diagonal blocks).
+    Each panel is a new tensor; drop it before taking the next to keep one in memory."""
+    n_m = F.shape[1]
+    for s0 in range(0, N_s, panel_sensors):
+        n = min(panel_sensors, N_s - s0)
+        r0, r1 = s0 * N_t, (s0 + n) * N_t
+        P = torch.matmul(F[r0:r1], F[:r1].t())
+        P.mul_(1.0 / n_m)
+        P[:, r0:r1].diagonal().add_(sigma2)
+        yield s0, n, P
+        del P
+
+
 def k_sub_lower(K: torch.Tensor, N_t: int, sensors) -> "numpy.ndarray":
     """Dense FP64 host copy of the block sub-matrix of K for the ordered sensor list,
     every element taken from K's lower triangle (K may live on the GPU)."""

@@ -29,6 +29,7 @@ from .oed import (  # noqa: F401
     oed_get_config,
     oed_get_profile,
     oed_greedy,
+    oed_pack_rows,
     oed_picks,
     oed_reset,
     oed_schur_block,

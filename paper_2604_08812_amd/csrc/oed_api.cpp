@@ -68,6 +68,10 @@ struct oed_ctx {
     bool pending = false;  // the last pick's block column and downdate are not formed yet
     int nheld = 0;         // block columns formed but not yet subtracted from R (W slots 0 .. nheld-1)
     bool poisoned = false;
+    // OED_FLAG_DEFER_PACK: block rows filled by oed_pack_rows; steps need all of them
+    bool deferred = false;
+    std::vector<char> row_packed;  // by local index
+    int unpacked = 0;
     std::vector<int> h_picks;   // local indices
     std::vector<double> h_gains;
     std::vector<char> picked;  // by local index
@@ -157,12 +161,9 @@ void free_all(oed_ctx *h)
     h->ev_pool.clear();
 }
 
-oed_status load_R(oed_ctx *h, const void *K)
+// Forget all picks: fresh active list and state words (the working copy is untouched).
+oed_status reset_state(oed_ctx *h)
 {
-    {
-        Prof pr(h, OED_K_PACK);
-        HIPCHK(h, launch_pack(K, h->kdtype, h->ld, h->N_t, h->N_tp, h->dcmap, h->N_c, h->R, h->rtype, h->stream));
-    }
     HIPCHK(h, launch_init_state(h->act[0], h->N_c, h->state, h->stream));
     h->cur = 0;
     h->n_act = h->N_c;
@@ -174,6 +175,24 @@ oed_status load_R(oed_ctx *h, const void *K)
     h->h_picks.clear();
     h->h_gains.clear();
     h->picked.assign(h->N_c, 0);
+    return OED_OK;
+}
+
+oed_status load_R(oed_ctx *h, const void *K)
+{
+    {
+        Prof pr(h, OED_K_PACK);
+        HIPCHK(h, launch_pack(K, h->kdtype, h->ld, h->N_t, h->N_tp, h->dcmap, h->N_c, h->R, h->rtype, h->stream));
+    }
+    return reset_state(h);
+}
+
+// Steps need every candidate's block row in the working copy.
+oed_status need_packed(oed_ctx *h)
+{
+    if (h->deferred && h->unpacked > 0)
+        return fail(h, OED_E_STATE,
+                    std::to_string(h->unpacked) + " candidate block rows not packed yet (oed_pack_rows)");
     return OED_OK;
 }
 
@@ -527,7 +546,14 @@ oed_status oed_create(oed_ctx **out, const void *K, int32_t dtype, int64_t ld, i
         if (opt->struct_size != sizeof(oed_options)) return OED_E_ARG;
         o = *opt;
     }
-    if (!K || (dtype != OED_F64 && dtype != OED_F32) || N_s < 1 || N_t < 1 || N_t > 4096 ||
+    const bool deferred = (o.flags & OED_FLAG_DEFER_PACK) != 0;
+    if (deferred) {
+        // no K: dtype and ld are not used
+        if (K || (o.flags & OED_FLAG_AUTOTUNE)) return OED_E_ARG;
+        dtype = OED_F64;
+        ld = (int64_t)N_s * N_t;
+    }
+    if ((!K && !deferred) || (dtype != OED_F64 && dtype != OED_F32) || N_s < 1 || N_t < 1 || N_t > 4096 ||
         ld < (int64_t)N_s * N_t || !(sigma2 > 0.0) || !std::isfinite(sigma2))
         return OED_E_ARG;
     if (o.precision != OED_PREC_FP64 && o.precision != OED_PREC_MIXED_F32 && o.precision != OED_PREC_MIXED_BF16X3)
@@ -631,7 +657,12 @@ oed_status oed_create(oed_ctx **out, const void *K, int32_t dtype, int64_t ld, i
             HIPCHK(h, dmalloc(h, (void **)&h->noise_h, sizeof(double) * h->N_c));
             HIPCHK(h, hipMemcpyAsync(h->noise_h, hloc.data(), sizeof(double) * h->N_c, hipMemcpyHostToDevice, h->stream));
         }
-        oed_status s2 = load_R(h, K);
+        h->deferred = deferred;
+        if (deferred) {
+            h->row_packed.assign(h->N_c, 0);
+            h->unpacked = h->N_c;
+        }
+        oed_status s2 = deferred ? reset_state(h) : load_R(h, K);
         if (s2 != OED_OK) return s2;
         HIPCHK(h, hipStreamSynchronize(h->stream));
         collect_profile(h);
@@ -651,6 +682,15 @@ oed_status oed_create(oed_ctx **out, const void *K, int32_t dtype, int64_t ld, i
 oed_status oed_reset(oed_ctx *h, const void *K)
 {
     if (!h) return OED_E_ARG;
+    if (h->deferred) {
+        if (K) return fail(h, OED_E_ARG, "deferred packing: reset with K = NULL and pack the rows again");
+        h->row_packed.assign(h->N_c, 0);
+        h->unpacked = h->N_c;
+        oed_status st = reset_state(h);
+        if (st != OED_OK) return st;
+        HIPCHK(h, hipStreamSynchronize(h->stream));
+        return OED_OK;
+    }
     if (!K) return fail(h, OED_E_ARG, "K is NULL");
     oed_status st = load_R(h, K);
     if (st != OED_OK) return st;
@@ -659,10 +699,42 @@ oed_status oed_reset(oed_ctx *h, const void *K)
     return OED_OK;
 }
 
+oed_status oed_pack_rows(oed_ctx *h, const void *K_rows, int32_t dtype, int64_t ld, int32_t sensor0,
+                         int32_t n_sensors)
+{
+    if (!h) return OED_E_ARG;
+    if (!h->deferred) return fail(h, OED_E_STATE, "handle was not created with OED_FLAG_DEFER_PACK");
+    if (h->k > 0 || h->pending) return fail(h, OED_E_STATE, "picks made: reset the handle before packing");
+    if (!K_rows || (dtype != OED_F64 && dtype != OED_F32) || sensor0 < 0 || n_sensors < 1 ||
+        (int64_t)sensor0 + n_sensors > h->N_s || ld < ((int64_t)sensor0 + n_sensors) * h->N_t)
+        return fail(h, OED_E_ARG, "bad panel");
+    // candidates are ascending, so the panel's candidates are local indices i0 .. i1-1 and every
+    // block (i, j <= i) lies in the panel's lower block triangle
+    const int i0 = (int)(std::lower_bound(h->cmap.begin(), h->cmap.end(), sensor0) - h->cmap.begin());
+    const int i1 = (int)(std::lower_bound(h->cmap.begin(), h->cmap.end(), sensor0 + n_sensors) - h->cmap.begin());
+    if (i1 > i0) {
+        {
+            Prof pr(h, OED_K_PACK);
+            HIPCHK(h, launch_pack_range(K_rows, dtype, ld, (int64_t)sensor0 * h->N_t, h->N_t, h->N_tp, h->dcmap,
+                                        blk_index(i0, 0), blk_index(i1, 0) - blk_index(i0, 0), h->R, h->rtype,
+                                        h->stream));
+        }
+        HIPCHK(h, hipStreamSynchronize(h->stream));
+        collect_profile(h);
+        for (int i = i0; i < i1; ++i)
+            if (!h->row_packed[i]) {
+                h->row_packed[i] = 1;
+                --h->unpacked;
+            }
+    }
+    return OED_OK;
+}
+
 oed_status oed_greedy(oed_ctx *h, int32_t budget, int32_t *idx_out, double *gain_out, int32_t *n_out)
 {
     if (!h) return OED_E_ARG;
     if (n_out) *n_out = 0;
+    if (need_packed(h) != OED_OK) return OED_E_STATE;
     if (h->poisoned) return fail(h, OED_E_STATE, "handle stopped after a non-positive-definite step; reset it");
     if (budget < 0 || budget > h->n_act) return fail(h, OED_E_ARG, "budget out of range");
     if (h->left && h->k + budget > h->max_budget) return fail(h, OED_E_ARG, "budget beyond max_budget");
@@ -692,6 +764,7 @@ oed_status oed_force(oed_ctx *h, int32_t idx, double *gain_out)
 {
     if (!h) return OED_E_ARG;
     if (h->poisoned) return fail(h, OED_E_STATE, "handle stopped; reset it");
+    if (need_packed(h) != OED_OK) return OED_E_STATE;
     if (idx < 0 || idx >= h->N_s || h->lmap[idx] < 0 || h->picked[h->lmap[idx]])
         return fail(h, OED_E_ARG, "index is not a remaining candidate");
     const int k0 = h->k;
@@ -713,6 +786,7 @@ oed_status oed_scores(oed_ctx *h, double *out)
 {
     if (!h || !out) return OED_E_ARG;
     if (h->poisoned) return fail(h, OED_E_STATE, "handle stopped; reset it");
+    if (need_packed(h) != OED_OK) return OED_E_STATE;
     for (int q = 0; q < h->N_s; ++q) out[q] = -INFINITY;
     if (h->n_act == 0) return OED_OK;
     oed_status st = advance(h, false);
@@ -732,6 +806,7 @@ oed_status oed_schur_block(oed_ctx *h, int32_t i, int32_t j, double *out)
 {
     if (!h || !out) return OED_E_ARG;
     if (h->poisoned) return fail(h, OED_E_STATE, "handle stopped; reset it");
+    if (need_packed(h) != OED_OK) return OED_E_STATE;
     if (i < 0 || j < 0 || i >= h->N_s || j >= h->N_s) return fail(h, OED_E_ARG, "index out of range");
     int li = h->lmap[i], lj = h->lmap[j];
     if (li < 0 || lj < 0 || h->picked[li] || h->picked[lj]) return fail(h, OED_E_ARG, "not a remaining candidate");
@@ -847,7 +922,9 @@ oed_status oed_get_config(const oed_ctx *h, int32_t *delay, int32_t *syrk_varian
         syrk_variant = nullptr;
     }
     if (delay) *delay = h->delay;
-    if (syrk_variant) *syrk_variant = h->syrk_variant;
+    // the LDS-staged FP32/FP64 downdate serves N_tp <= 128; beyond it the per-wave kernel runs
+    if (syrk_variant)
+        *syrk_variant = (h->wtype != W_BF16X3 && h->N_tp > 128) ? (int32_t)SYRK_DIRECT : h->syrk_variant;
     if (per_pick_ms) std::copy(h->tuned_ms, h->tuned_ms + MAX_DELAY, per_pick_ms);
     return OED_OK;
 }

@@ -109,6 +109,10 @@ __host__ __device__ inline int64_t syrk_tiles(int n_act, int N_tp)
 
 hipError_t launch_pack(const void *K, int kdtype, int64_t ld, int N_t, int N_tp, const int *cmap, int N_c,
                        void *R, int rtype, hipStream_t s);
+// Blocks b0 .. b0 + nblocks - 1 of R only, K's row r read at K + (r - row0) ld: the block rows of
+// consecutive candidates from a panel of K's rows.
+hipError_t launch_pack_range(const void *K, int kdtype, int64_t ld, int64_t row0, int N_t, int N_tp,
+                             const int *cmap, int64_t b0, int64_t nblocks, void *R, int rtype, hipStream_t s);
 hipError_t launch_init_state(int *act, int n, int *state, hipStream_t s);
 
 // Single-instance launches (d.item0 = 0, d.nitems = work items).

@@ -10,10 +10,11 @@ namespace oed {
 // Candidate i is sensor cmap[i]; the map need not be increasing (blocks above K's diagonal are
 // read as the transpose of the block below it).
 // One thread per (block, sub-block, lane): it writes the lane's 4 elements with one vector store.
+// Blocks b0 .. b0 + nblocks - 1 of R are packed; K's row r is read at K + (r - row0) ld.
 template <typename TK, typename TR>
-__global__ void __launch_bounds__(256) pack_kernel(const TK *__restrict__ K, int64_t ld, int N_t, int N_tp,
-                                                   const int *__restrict__ cmap, int64_t nblocks,
-                                                   TR *__restrict__ R)
+__global__ void __launch_bounds__(256) pack_kernel(const TK *__restrict__ K, int64_t ld, int64_t row0, int N_t,
+                                                   int N_tp, const int *__restrict__ cmap, int64_t b0,
+                                                   int64_t nblocks, TR *__restrict__ R)
 {
     const int nb = N_tp >> 4;
     const int64_t per_block = (int64_t)nb * nb * 64;
@@ -21,8 +22,8 @@ __global__ void __launch_bounds__(256) pack_kernel(const TK *__restrict__ K, int
     const int64_t bs = (int64_t)N_tp * N_tp;
     for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total;
          e += (int64_t)gridDim.x * blockDim.x) {
-        const int64_t b = e / per_block;
-        const int rem = (int)(e - b * per_block);
+        const int64_t b = b0 + e / per_block;
+        const int rem = (int)(e - (b - b0) * per_block);
         const int sb = rem >> 6, lane = rem & 63;
         const int64_t i = tri_row(b), j = b - i * (i + 1) / 2;
         const int tb = sb / nb, ub = sb - tb * nb;
@@ -46,7 +47,7 @@ __global__ void __launch_bounds__(256) pack_kernel(const TK *__restrict__ K, int
                     row = ci * N_t + (t >= u ? t : u);
                     col = ci * N_t + (t >= u ? u : t);
                 }
-                x = (double)K[row * ld + col];
+                x = (double)K[(row - row0) * ld + col];
             } else {
                 x = (i == j && t == u) ? 1.0 : 0.0;
             }
@@ -63,25 +64,31 @@ __global__ void init_state_kernel(int *act, int n, int *state)
     if (p < ST_WORDS) state[p] = 0;
 }
 
+hipError_t launch_pack_range(const void *K, int kdtype, int64_t ld, int64_t row0, int N_t, int N_tp,
+                             const int *cmap, int64_t b0, int64_t nblocks, void *R, int rtype, hipStream_t s)
+{
+    if (nblocks <= 0) return hipSuccess;
+    const int64_t threads = nblocks * (N_tp / 16) * (N_tp / 16) * 64;
+    const int64_t grid = std::min<int64_t>((threads + 255) / 256, 1 << 20);
+#define OED_PACK(TK, TR)                                                                                         \
+    hipLaunchKernelGGL((pack_kernel<TK, TR>), dim3(grid), dim3(256), 0, s, (const TK *)K, ld, row0, N_t, N_tp, cmap, \
+                       b0, nblocks, (TR *)R)
+    if (kdtype == 0 && rtype == R_F64)
+        OED_PACK(double, double);
+    else if (kdtype == 0 && rtype == R_F32)
+        OED_PACK(double, float);
+    else if (kdtype == 1 && rtype == R_F64)
+        OED_PACK(float, double);
+    else
+        OED_PACK(float, float);
+#undef OED_PACK
+    return hipGetLastError();
+}
+
 hipError_t launch_pack(const void *K, int kdtype, int64_t ld, int N_t, int N_tp, const int *cmap, int N_c,
                        void *R, int rtype, hipStream_t s)
 {
-    const int64_t nblocks = (int64_t)N_c * (N_c + 1) / 2;
-    const int64_t threads = nblocks * (N_tp / 16) * (N_tp / 16) * 64;
-    const int64_t grid = std::min<int64_t>((threads + 255) / 256, 1 << 20);
-    if (kdtype == 0 && rtype == R_F64)
-        hipLaunchKernelGGL((pack_kernel<double, double>), dim3(grid), dim3(256), 0, s, (const double *)K, ld, N_t, N_tp,
-                           cmap, nblocks, (double *)R);
-    else if (kdtype == 0 && rtype == R_F32)
-        hipLaunchKernelGGL((pack_kernel<double, float>), dim3(grid), dim3(256), 0, s, (const double *)K, ld, N_t, N_tp,
-                           cmap, nblocks, (float *)R);
-    else if (kdtype == 1 && rtype == R_F64)
-        hipLaunchKernelGGL((pack_kernel<float, double>), dim3(grid), dim3(256), 0, s, (const float *)K, ld, N_t, N_tp,
-                           cmap, nblocks, (double *)R);
-    else
-        hipLaunchKernelGGL((pack_kernel<float, float>), dim3(grid), dim3(256), 0, s, (const float *)K, ld, N_t, N_tp,
-                           cmap, nblocks, (float *)R);
-    return hipGetLastError();
+    return launch_pack_range(K, kdtype, ld, 0, N_t, N_tp, cmap, 0, (int64_t)N_c * (N_c + 1) / 2, R, rtype, s);
 }
 
 hipError_t launch_init_state(int *act, int n, int *state, hipStream_t s)

@@ -21,6 +21,7 @@ OED_F64, OED_F32 = 0, 1
 PRECISIONS = {"fp64": 0, "mixed_f32": 1, "mixed_bf16x3": 2}
 OED_FLAG_PROFILE = 1
 OED_FLAG_AUTOTUNE = 4
+OED_FLAG_DEFER_PACK = 8
 KERNELS = ("gain", "pick", "trsm", "syrk", "pack")
 
 
@@ -70,6 +71,7 @@ def library() -> ctypes.CDLL:
     L.oed_create.argtypes = [ctypes.POINTER(vp), vp, ctypes.c_int32, ctypes.c_int64, ctypes.c_int32, ctypes.c_int32,
                              ctypes.c_double, vp, ctypes.POINTER(oed_options)]
     L.oed_reset.argtypes = [vp, vp]
+    L.oed_pack_rows.argtypes = [vp, vp, ctypes.c_int32, ctypes.c_int64, ctypes.c_int32, ctypes.c_int32]
     L.oed_greedy.argtypes = [vp, ctypes.c_int32, ip, dp, ip]
     L.oed_force.argtypes = [vp, ctypes.c_int32, dp]
     L.oed_scores.argtypes = [vp, dp]
@@ -100,7 +102,7 @@ def library() -> ctypes.CDLL:
     L.oed_eval_destroy.argtypes = [vp]
     L.oed_eval_last_error.argtypes = [vp]
     L.oed_eval_last_error.restype = ctypes.c_char_p
-    for name in ("oed_create", "oed_reset", "oed_greedy", "oed_force", "oed_scores", "oed_schur_block", "oed_picks",
+    for name in ("oed_create", "oed_reset", "oed_pack_rows", "oed_greedy", "oed_force", "oed_scores", "oed_schur_block", "oed_picks",
                  "oed_get_profile", "oed_device_bytes", "oed_destroy", "oed_batch_create", "oed_batch_run",
                  "oed_batch_reset", "oed_batch_stats", "oed_batch_destroy", "oed_batch_get_config", "oed_get_config",
                  "oed_eval_create", "oed_eval_run", "oed_eval_stats", "oed_eval_destroy"):
@@ -109,7 +111,7 @@ def library() -> ctypes.CDLL:
     return L
 
 
-EXPORTED = ("oed_options_init", "oed_create", "oed_reset", "oed_greedy", "oed_force", "oed_scores",
+EXPORTED = ("oed_options_init", "oed_create", "oed_reset", "oed_pack_rows", "oed_greedy", "oed_force", "oed_scores",
             "oed_schur_block", "oed_picks", "oed_get_profile", "oed_device_bytes", "oed_get_config", "oed_destroy",
             "oed_last_error",
             "oed_status_string", "oed_batch_create", "oed_batch_run", "oed_batch_reset", "oed_batch_stats",
@@ -152,20 +154,26 @@ def oed_create(K, N_s, N_t, sigma2, precision="fp64", candidates=None, profile=F
     method: "right" (downdate of all of R per pick), "left" (only the new block column per pick) or
     "auto" (left when max_budget <= half the candidates);
     max_budget: left-looking W history size (0: all candidates); noise_half_logdet: per-sensor
-    1/2 logdet of the noise covariance blocks (None: isotropic sigma2)."""
+    1/2 logdet of the noise covariance blocks (None: isotropic sigma2).
+    K = None: deferred packing (OED_FLAG_DEFER_PACK), the rows come through oed_pack_rows."""
     import torch
     L = library()
-    if not isinstance(K, torch.Tensor) or not K.is_cuda or K.dim() != 2 or K.stride(1) != 1:
-        raise ValueError("K must be a 2-D row-major device tensor")
-    dtype = {torch.float64: OED_F64, torch.float32: OED_F32}.get(K.dtype)
-    if dtype is None:
-        raise ValueError("K must be float64 or float32")
-    if K.shape[0] < N_s * N_t or K.shape[1] < N_s * N_t:
-        raise ValueError("K must have at least N_s*N_t rows and columns")
+    if K is None:
+        dtype, ld, kp = OED_F64, int(N_s) * int(N_t), None
+    else:
+        if not isinstance(K, torch.Tensor) or not K.is_cuda or K.dim() != 2 or K.stride(1) != 1:
+            raise ValueError("K must be a 2-D row-major device tensor")
+        dtype = {torch.float64: OED_F64, torch.float32: OED_F32}.get(K.dtype)
+        if dtype is None:
+            raise ValueError("K must be float64 or float32")
+        if K.shape[0] < N_s * N_t or K.shape[1] < N_s * N_t:
+            raise ValueError("K must have at least N_s*N_t rows and columns")
+        ld, kp = K.stride(0), ctypes.c_void_p(K.data_ptr())
     opt = oed_options()
     L.oed_options_init(ctypes.byref(opt))
     opt.precision = PRECISIONS[precision]
-    opt.flags = (OED_FLAG_PROFILE if profile else 0) | (OED_FLAG_AUTOTUNE if autotune else 0)
+    opt.flags = ((OED_FLAG_PROFILE if profile else 0) | (OED_FLAG_AUTOTUNE if autotune else 0) |
+                 (OED_FLAG_DEFER_PACK if K is None else 0))
     opt.delay = int(delay)
     opt.method = {"right": 0, "left": 1, "auto": 2}[method]
     opt.max_budget = int(max_budget)
@@ -181,14 +189,30 @@ def oed_create(K, N_s, N_t, sigma2, precision="fp64", candidates=None, profile=F
         opt.candidates = _ip(cand)
         opt.n_candidates = len(cand)
     h = ctypes.c_void_p()
-    st = L.oed_create(ctypes.byref(h), ctypes.c_void_p(K.data_ptr()), dtype, K.stride(0), int(N_s), int(N_t),
-                      float(sigma2), _stream_handle(stream), ctypes.byref(opt))
+    st = L.oed_create(ctypes.byref(h), kp, dtype, ld, int(N_s), int(N_t), float(sigma2), _stream_handle(stream),
+                      ctypes.byref(opt))
     _check(None, st)
     return h
 
 
 def oed_reset(h, K):
-    _check(h, library().oed_reset(h, ctypes.c_void_p(K.data_ptr())))
+    """K = None: a deferred-packing handle forgets its picks and its packed rows."""
+    _check(h, library().oed_reset(h, None if K is None else ctypes.c_void_p(K.data_ptr())))
+
+
+def oed_pack_rows(h, K_rows, sensor0, n_sensors, N_t):
+    """Pack the block rows of sensors sensor0 .. sensor0+n_sensors-1 from the device tensor K_rows
+    (their rows of K, at least (sensor0+n_sensors)*N_t columns, row-major)."""
+    import torch
+    if not isinstance(K_rows, torch.Tensor) or not K_rows.is_cuda or K_rows.dim() != 2 or K_rows.stride(1) != 1:
+        raise ValueError("K_rows must be a 2-D row-major device tensor")
+    dtype = {torch.float64: OED_F64, torch.float32: OED_F32}.get(K_rows.dtype)
+    if dtype is None:
+        raise ValueError("K_rows must be float64 or float32")
+    if K_rows.shape[0] < n_sensors * N_t or K_rows.shape[1] < (sensor0 + n_sensors) * N_t:
+        raise ValueError("K_rows is smaller than the panel")
+    _check(h, library().oed_pack_rows(h, ctypes.c_void_p(K_rows.data_ptr()), dtype, K_rows.stride(0),
+                                      int(sensor0), int(n_sensors)))
 
 
 def oed_greedy(h, budget, check=True):
@@ -463,6 +487,9 @@ class Selector:
     def greedy(self, budget):
         idx, gain, _ = oed_greedy(self.h, budget)
         return idx, gain
+
+    def pack_rows(self, K_rows, sensor0, n_sensors):
+        oed_pack_rows(self.h, K_rows, sensor0, n_sensors, self.N_t)
 
     def greedy_status(self, budget):
         return oed_greedy(self.h, budget, check=False)

@@ -137,3 +137,20 @@ def test_eval_host_side_validation(lib):
     assert lib.oed_eval_run(None, None, 0, None, None) == E_ARG
     assert lib.oed_eval_stats(None, None, None, None, None) == E_ARG
     assert lib.oed_eval_last_error(None) == b"null evaluator"
+
+
+def test_deferred_pack_host_side_validation(lib):
+    from paper_2604_08812_amd.oed import OED_FLAG_AUTOTUNE, OED_FLAG_DEFER_PACK, oed_options
+    h = ctypes.c_void_p()
+    fake = ctypes.c_void_p(0x1000)  # never dereferenced
+    opt = oed_options()
+    lib.oed_options_init(ctypes.byref(opt))
+    opt.flags = OED_FLAG_DEFER_PACK
+    # deferred packing takes no K, and cannot autotune (nothing packed to time on)
+    assert lib.oed_create(ctypes.byref(h), fake, 0, 64, 4, 16, 1.0, None, ctypes.byref(opt)) == 1
+    opt.flags = OED_FLAG_DEFER_PACK | OED_FLAG_AUTOTUNE
+    assert lib.oed_create(ctypes.byref(h), None, 0, 64, 4, 16, 1.0, None, ctypes.byref(opt)) == 1
+    opt.flags = OED_FLAG_DEFER_PACK
+    assert lib.oed_create(ctypes.byref(h), None, 0, 64, 4, 16, 0.0, None, ctypes.byref(opt)) == 1
+    assert not h.value
+    assert lib.oed_pack_rows(None, fake, 0, 64, 0, 1) == 1

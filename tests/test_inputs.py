@@ -48,3 +48,26 @@ def test_config_table():
         assert 40 <= s.N_s <= 400 and s.N_t in (16, 32, 64)
         assert 1e-3 <= s.c <= 1e-1 and s.budget == s.N_s // 4 and s.n_m == 2 * s.N_d
     assert specs == batched_instance_specs()
+
+
+def test_row_panels_are_the_lower_block_triangle_of_K():
+    """k_row_panels (K formed by row panels from a resident F) gives exactly the rows and
+    columns of K = F F^T / n_m + sigma^2 I that the panel covers, and f_matrix draws the F of
+    make_K (same seed, same noise scale)."""
+    import torch
+    from oed_inputs import f_matrix, k_row_panels
+    N_s, N_t, n_m = 7, 5, 300
+    F, scale = f_matrix(N_s * N_t, n_m, 4, device="cpu", dtype=torch.float64)
+    K = F @ F.t() / n_m
+    assert abs(scale - K.diagonal().mean().item()) < 1e-12
+    s2 = 0.01 * scale
+    K.diagonal().add_(s2)
+    seen = []
+    for s0, n, P in k_row_panels(F, N_s, N_t, s2, 3):
+        r0, r1 = s0 * N_t, (s0 + n) * N_t
+        assert P.shape == (r1 - r0, r1)
+        assert torch.allclose(P, K[r0:r1, :r1], rtol=0, atol=1e-13)
+        seen.append((s0, n))
+    assert seen == [(0, 3), (3, 3), (6, 1)]
+    Kref, s2ref = make_K(N_s, N_t, n_m, seed=4)
+    assert torch.allclose(Kref, K, rtol=0, atol=1e-12) and abs(s2ref - s2) <= 1e-14 * s2
