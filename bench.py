@@ -334,7 +334,7 @@ def run_paper_shape(args):
                    "delay": delay, "downdate_variant": ["direct", "lds"][variant],
                    "step": "oed_greedy(budget) on the packed working copy"},
         "roofline": {**roofline_syrk(prof, "mixed_f32", spec.name),
-                     "kernel": "syrk_direct_kernel<float>" if variant == 0 else SYRK_KERNEL["mixed_f32"]},
+                     "kernel": "syrk_direct_kernel<float>" if variant == 0 else "syrk_lds_rt_kernel<float>"},
         "kernel_ms_per_step": {k: round(v / args.steps, 3) for k, v in prof["ms"].items()},
         "pack_s_per_fill": round(sum(pack_s) / len(pack_s), 3),
         "device_bytes_of_handle": dev_bytes,

@@ -922,9 +922,7 @@ oed_status oed_get_config(const oed_ctx *h, int32_t *delay, int32_t *syrk_varian
         syrk_variant = nullptr;
     }
     if (delay) *delay = h->delay;
-    // the LDS-staged FP32/FP64 downdate serves N_tp <= 128; beyond it the per-wave kernel runs
-    if (syrk_variant)
-        *syrk_variant = (h->wtype != W_BF16X3 && h->N_tp > 128) ? (int32_t)SYRK_DIRECT : h->syrk_variant;
+    if (syrk_variant) *syrk_variant = h->syrk_variant;
     if (per_pick_ms) std::copy(h->tuned_ms, h->tuned_ms + MAX_DELAY, per_pick_ms);
     return OED_OK;
 }

@@ -281,10 +281,10 @@ struct TileMap {
     bool any;
 };
 
-template <int N_tp>
-__device__ __forceinline__ void tile_map(const StepDesc &d, int64_t P, int64_t Q, int wave, TileMap &m)
+__device__ __forceinline__ void tile_map_n(const StepDesc &d, const int N_tp, int64_t P, int64_t Q, int wave,
+                                           TileMap &m)
 {
-    constexpr int NB = N_tp / 16;
+    const int NB = N_tp / 16;
     const int *__restrict__ act = d.act_in;
     const int rows = d.n_act * N_tp, last = d.n_act - 1;
     const int64_t bs = (int64_t)N_tp * N_tp;
@@ -311,6 +311,12 @@ __device__ __forceinline__ void tile_map(const StepDesc &d, int64_t P, int64_t Q
             m.rblk[4 * b + c] = o ? blk_index(ia, ja) * bs + ((ta * NB + tc) << 8) : 0;
         }
     }
+}
+
+template <int N_tp>
+__device__ __forceinline__ void tile_map(const StepDesc &d, int64_t P, int64_t Q, int wave, TileMap &m)
+{
+    tile_map_n(d, N_tp, P, Q, wave, m);
 }
 
 // ---------------------------------------------------------------------------------------------
@@ -412,6 +418,106 @@ __device__ void syrk_lds_body(const StepDesc &d, int64_t tile)
     const int nw = d.nw;
     for (int slot = 0; slot + 1 < nw; ++slot) pass(BoolC<false>(), wblk(slot), wblk(slot + 1), (slot * NST) & 1);
     pass(BoolC<PREFETCH_R>(), wblk(nw - 1), nullptr, ((nw - 1) * NST) & 1);
+
+    if (!m.any) return;
+#pragma unroll
+    for (int f = 0; f < 16; ++f)
+        if (m.ok[f]) st4(Rl + m.rblk[f], (PREFETCH_R ? rt[f] : ld4(Rl + m.rblk[f])) - acc[f]);
+}
+
+// ---------------------------------------------------------------------------------------------
+// Downdate for N_tp = 16 nb > 128 (runtime block size, nb > RT_TAIL): the LDS-staged,
+// double-buffered tile of syrk_lds_body with a runtime slice loop.  The last RT_TAIL slices of
+// the last W slot are unrolled so that the FP32 kernel streams the R tile in there, two blocks
+// per slice, behind the slice's W loads.
+constexpr int RT_TAIL = 8;
+
+template <typename T>
+__device__ void syrk_lds_rt_body(const StepDesc &d, int64_t tile)
+{
+    typedef typename V4<T>::type vec;
+    constexpr bool PREFETCH_R = sizeof(T) == 4;
+    __shared__ vec lds[2][2][8 * 64];  // [buffer][A/B][sub-block * 64 + lane]
+    if (d.state[ST_STATUS] != 0) return;
+    int64_t P, Q;
+    if (!super_tile(tile, syrk_tile_rows(d.n_act, d.N_tp), P, Q)) return;
+    const int nb = d.N_tp >> 4;
+    T *__restrict__ R = (T *)d.R;
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6), wr = wave >> 1, wc = wave & 1;
+    const int alane = a_lane<T>(lane);
+    TileMap m;
+    tile_map_n(d, d.N_tp, P, Q, wave, m);
+    T *Rl = R + lane * 4;
+    const T *W0 = (const T *)d.W + lane * 4;
+    const int64_t wslot = d.wslot;
+
+    vec rt[16], acc[16];
+#pragma unroll
+    for (int f = 0; f < 16; ++f) acc[f] = vec{0, 0, 0, 0};
+    vec sa[2], sbv[2];
+    auto stage = [&](const T *src) {
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            sa[h] = ld4(src + m.wA[h]);
+            sbv[h] = ld4(src + m.wB[h]);
+        }
+    };
+    auto put = [&](int buf) {
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            lds[buf][0][(wave + 4 * h) * 64 + lane] = sa[h];
+            lds[buf][1][(wave + 4 * h) * 64 + lane] = sbv[h];
+        }
+    };
+    auto mma = [&](int buf) {
+        if (!m.any) return;
+        vec a[4], w[4];
+#pragma unroll
+        for (int b = 0; b < 4; ++b) {
+            a[b] = lds[buf][0][(wr * 4 + b) * 64 + alane];
+            w[b] = lds[buf][1][(wc * 4 + b) * 64 + lane];
+        }
+#pragma unroll
+        for (int s4 = 0; s4 < 4; ++s4)
+#pragma unroll
+            for (int b = 0; b < 4; ++b)
+#pragma unroll
+                for (int c = 0; c < 4; ++c) acc[4 * b + c] = mfma16(a[b][s4], w[c][s4], acc[4 * b + c]);
+    };
+    stage(W0);
+    put(0);
+    __syncthreads();
+    int buf = 0;
+    const int nw = d.nw;
+    for (int slot = 0; slot < nw; ++slot) {
+        const T *cur = W0 + slot * wslot;
+        const bool last = slot + 1 == nw;
+        // slice q of a staged sub-block row sits 256 q elements after its slice 0
+        const int body = last ? nb - RT_TAIL : nb;
+        for (int q = 0; q < body; ++q) {
+            stage(q + 1 < nb ? cur + ((q + 1) << 8) : cur + wslot);
+            mma(buf);
+            put(buf ^ 1);
+            __syncthreads();
+            buf ^= 1;
+        }
+        if (last) {
+#pragma unroll
+            for (int t = 0; t < RT_TAIL; ++t) {
+                const bool more = t + 1 < RT_TAIL;
+                if (more) stage(cur + ((nb - RT_TAIL + t + 1) << 8));
+                if (PREFETCH_R) {
+                    rt[2 * t] = ld4(Rl + m.rblk[2 * t]);
+                    rt[2 * t + 1] = ld4(Rl + m.rblk[2 * t + 1]);
+                }
+                mma(buf);
+                if (more) put(buf ^ 1);
+                __syncthreads();
+                buf ^= 1;
+            }
+        }
+    }
 
     if (!m.any) return;
 #pragma unroll
@@ -785,6 +891,14 @@ __global__ void __launch_bounds__(256) syrk_direct_batched(const StepDesc *__res
     syrk_direct_body<T>(d, item - d.item0);
 }
 
+template <typename T>
+__global__ void __launch_bounds__(256, 2) syrk_lds_rt_kernel(StepDesc d, int64_t per_xcd)
+{
+    const int64_t tile = xcd_item(blockIdx.x, per_xcd);
+    if (tile >= d.nitems) return;
+    syrk_lds_rt_body<T>(d, tile);
+}
+
 template <typename T, int NB, int KS>
 __global__ void __launch_bounds__(256, 2) syrk_lds_kernel(StepDesc d, int64_t per_xcd)
 {
@@ -975,6 +1089,11 @@ static hipError_t launch_syrk_t(const StepDesc *descs, const StepDesc &d, int n,
             OED_SYRK_CASE(8)
 #undef OED_SYRK_CASE
         }
+        return hipGetLastError();
+    }
+    // single instances only: batches hold N_t <= 128
+    if (variant == SYRK_LDS && nb > RT_TAIL && !descs) {
+        hipLaunchKernelGGL(syrk_lds_rt_kernel<T>, grid, block, 0, s, d, per_xcd);
         return hipGetLastError();
     }
     if (nw != 1) return hipErrorInvalidValue;

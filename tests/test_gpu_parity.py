@@ -40,6 +40,8 @@ CASES = [
     (50, 1, 200, 7, 30),     # N_t = 1 padded to 16
     (17, 48, 2000, 8, 9),
     (9, 160, 2000, 9, 5),    # N_t > 128: factorisations in global scratch
+    (12, 144, 2500, 10, 6),  # N_tp = 144: the smallest block of the runtime-size LDS downdate
+    (5, 420, 3000, 11, 4),   # the paper's block size, padded to 432
 ]
 
 
