@@ -297,6 +297,198 @@ __device__ __forceinline__ bool chol_regs(const TR *__restrict__ Rb, int N_t, in
     return ok;
 }
 
+// ---------------------------------------------------------------------------------------------
+// Blocked register Cholesky on FP64 MFMA for N_t <= 128 (the gain kernel).  Upper form:
+// A = U^T U, block by block, with A held as its upper 16x16 blocks (I, C), I <= C, in the
+// accumulator order (lane l, g = l/16 holds elements (4g + r, l % 16), r = 0..3).  Wave w
+// owns block columns C in {w, 7 - w}.  Step p:
+//   (a) the owner of column p factors A_pp = U_pp^T U_pp inside one wave and publishes
+//       Y = U_pp^-1 through LDS (one barrier);
+//   (b) every owner of a column C > p forms U_pC = U_pp^-T A_pC on the MFMA (the B operand is
+//       the register block itself) and publishes it (one barrier);
+//   (c) every owner updates its blocks A_IC -= U_pI^T U_pC, p < I <= C (MFMA).
+// In this form every product takes its B operand in the accumulator order and its A operand
+// from an accumulator-order block read at the permuted lane a_lane() (see mfma16 / a_lane),
+// so no operand is ever transposed.  The stored lower blocks of R are read transposed.
+
+// In-wave factorisation of one 16x16 diagonal block M (accumulator order) by symmetric
+// elimination, carrying X = L_u^-1 along (M = L_u D L_u^T, L_u unit lower): then
+// U^-T = D^-1/2 X and Y = U^-1 has Y[a][b] = X[b][a] / sqrt(d_b).  Writes Y in the accumulator
+// order to ylds (256 doubles) and the pivots d_j to piv[0..15] (LDS, lane 0).  Returns false,
+// uniformly over the wave, at a pivot that is not > 0 or not finite.
+__device__ __forceinline__ bool chol16_inv(doublex4 M, double *ylds, double *piv)
+{
+    const int lane = threadIdx.x & 63, g = lane >> 4, c = lane & 15;
+    doublex4 X;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) X[r] = (4 * g + r == c) ? 1.0 : 0.0;
+    // a run-time loop keeps the code small (it is instantiated once per block column)
+#pragma unroll 1
+    for (int j = 0; j < 16; ++j) {
+        const int jg = j >> 2, jr = j & 3;
+        // the pivot and row j of the eliminated block (row j: lanes of group jg, register jr);
+        // column j of the lane's own rows 4g + r sits in lane 16 g + j by symmetry
+        const double mj = M[jr], xj = X[jr];
+        const double d = __shfl(mj, jg * 16 + j);
+        if (!(d > 0.0) || !isfinite(d)) return false;
+        if (lane == 0) piv[j] = d;
+        const double inv = 1.0 / d;
+        const double mjc = __shfl(mj, jg * 16 + c);
+        const double xjc = __shfl(xj, jg * 16 + c);
+        double mja[4];
+#pragma unroll
+        for (int r = 0; r < 4; ++r) mja[r] = __shfl(M[r], g * 16 + j);
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+            if (4 * g + r > j) {
+                const double m = mja[r] * inv;
+                if (c > j) M[r] = fma(-m, mjc, M[r]);
+                X[r] = fma(-m, xjc, X[r]);
+            }
+    }
+    // the pivots went to LDS from lane 0; the wave's LDS accesses complete in order
+    __builtin_amdgcn_wave_barrier();
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        const int x = 4 * g + r;
+        ylds[((((c >> 2) << 4) + x) << 2) + (c & 3)] = X[r] / sqrt(piv[x]);
+    }
+    return true;
+}
+
+// The register blocks of one wave: block column C0 = w (<= 3) keeps blocks I = 0..3 (those
+// with I <= C0 are used), block column C1 = 7 - w (>= 4) keeps blocks I = 0..7.  ub() maps
+// (h, I) to them; with h and I compile-time constants the selection is static.
+struct UBlocks {
+    doublex4 c0[4], c1[8];
+};
+__device__ __forceinline__ doublex4 &ub(UBlocks &A, int h, int I) { return h ? A.c1[I & 7] : A.c0[I & 3]; }
+
+// Load the candidate's current Schur block as upper blocks: block (I, C) of the upper form is
+// the transpose of the stored lower block (C, I); with held W blocks (slots 0 .. nheld-1 at
+// candidate offset pofs) their products P_I P_C^T are subtracted, and with d.wb the corrected
+// block is written back (left-looking).
+template <typename TR, typename TW>
+__device__ __forceinline__ void load_upper(UBlocks &A, const TR *__restrict__ Rb, int nbr, int nb, const StepDesc &d,
+                                           int64_t pofs)
+{
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, g = lane >> 4, c = lane & 15;
+    // element (4g + r, c) of upper (I, C) = element (c, 4g + r) of lower (C, I)
+    const int tofs = ((((c >> 2) << 4) + 4 * g) << 2) + (c & 3);
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+        const int C = h ? 7 - w : w;
+#pragma unroll
+        for (int I = 0; I < (h ? 8 : 4); ++I) {
+            if (C < nbr && I <= C) {
+                const TR *blk = Rb + ((C * nb + I) << 8) + tofs;
+#pragma unroll
+                for (int r = 0; r < 4; ++r) ub(A, h, I)[r] = (double)blk[4 * r];
+            } else {
+                ub(A, h, I) = doublex4{0.0, 0.0, 0.0, 0.0};
+            }
+        }
+    }
+    for (int hp = 0; hp < d.nheld; ++hp) {
+        const TW *P = (const TW *)d.W + hp * d.wslot + pofs;
+        const TW *P2 = d.W2 ? (const TW *)d.W2 + hp * d.wslot + pofs : nullptr;
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            const int C = h ? 7 - w : w;
+#pragma unroll
+            for (int I = 0; I < (h ? 8 : 4); ++I)
+                if (C < nbr && I <= C) {
+                    const auto q = HeldProd<TW>::run(P, P2, I, C, nb, nbr, lane);
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) ub(A, h, I)[r] -= (double)q[r];
+                }
+        }
+    }
+    if (d.wb && d.nheld > 0) {
+        TR *Rw = const_cast<TR *>(Rb);
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            const int C = h ? 7 - w : w;
+#pragma unroll
+            for (int I = 0; I < (h ? 8 : 4); ++I)
+                if (C < nbr && I <= C) {
+                    TR *blk = Rw + ((C * nb + I) << 8) + tofs;
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) blk[4 * r] = (TR)ub(A, h, I)[r];
+                }
+        }
+    }
+}
+
+// Step p of the blocked factorisation (p is a compile-time constant, so that every register
+// block is addressed statically).  Returns false (uniformly) at a failed pivot.
+template <int p>
+__device__ __forceinline__ bool chol_mfma_step(UBlocks &A, int nbr, double *piv, doublex4 (*Ls)[8][64], int *sfail)
+{
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int al = a_lane<double>(lane);
+    const int C0 = w, C1 = 7 - w;
+    constexpr int buf = p & 1, hp = p < 4 ? 0 : 1;  // column p is a C0 column iff p <= 3
+    // (a) the owner of block column p
+    if ((hp ? C1 : C0) == p) {
+        const bool ok = chol16_inv(ub(A, hp, p), (double *)Ls[buf][p], piv + 16 * p);
+        if (lane == 0) sfail[buf] = ok ? 0 : 1;
+    }
+    __syncthreads();
+    if (sfail[buf]) return false;
+    // (b) U_pC = U_pp^-T A_pC for the owned columns C > p
+    const doublex4 y = Ls[buf][p][al];
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+        const int C = h ? C1 : C0;
+        if ((h || p < 4) && C > p && C < nbr) {
+            doublex4 acc{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+            for (int s4 = 0; s4 < 4; ++s4) acc = mfma16(y[s4], ub(A, h, p)[s4], acc);
+            ub(A, h, p) = acc;
+            Ls[buf][C][lane] = acc;
+        }
+    }
+    __syncthreads();
+    // (c) A_IC -= U_pI^T U_pC for p < I <= C
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+        const int C = h ? C1 : C0;
+        if ((h || p < 4) && C > p && C < nbr) {
+#pragma unroll
+            for (int I = p + 1; I < (h ? 8 : 4); ++I)
+                if (I <= C) {
+                    const doublex4 u = Ls[buf][I][al];
+#pragma unroll
+                    for (int s4 = 0; s4 < 4; ++s4) ub(A, h, I) = mfma16(-u[s4], ub(A, h, p)[s4], ub(A, h, I));
+                }
+        }
+    }
+    return true;
+}
+
+// The blocked factorisation; pivots d_j go to piv[0 .. 16 nbr).  Returns false (uniformly) at
+// a pivot that is not > 0 or not finite.
+template <typename TR, typename TW>
+__device__ __forceinline__ bool chol_mfma(const TR *__restrict__ Rb, int N_t, int nb, double *piv, const StepDesc &d,
+                                          int64_t pofs)
+{
+    __shared__ doublex4 Ls[2][8][64];  // [step parity][block column][lane]
+    __shared__ int sfail[2];
+    const int nbr = (N_t + 15) >> 4;
+    UBlocks A;
+    load_upper<TR, TW>(A, Rb, nbr, nb, d, pofs);
+    if (!chol_mfma_step<0>(A, nbr, piv, Ls, sfail)) return false;
+    if (nbr > 1 && !chol_mfma_step<1>(A, nbr, piv, Ls, sfail)) return false;
+    if (nbr > 2 && !chol_mfma_step<2>(A, nbr, piv, Ls, sfail)) return false;
+    if (nbr > 3 && !chol_mfma_step<3>(A, nbr, piv, Ls, sfail)) return false;
+    if (nbr > 4 && !chol_mfma_step<4>(A, nbr, piv, Ls, sfail)) return false;
+    if (nbr > 5 && !chol_mfma_step<5>(A, nbr, piv, Ls, sfail)) return false;
+    if (nbr > 6 && !chol_mfma_step<6>(A, nbr, piv, Ls, sfail)) return false;
+    if (nbr > 7 && !chol_mfma_step<7>(A, nbr, piv, Ls, sfail)) return false;
+    return true;
+}
+
 // One block column JB of the factorisation with the inverse carried along: the elimination of
 // column j (row t -= (a_tj / d_j) row j, t > j) is applied to X, which starts as the identity,
 // with the same multipliers; row j of X is final at step j, so its owners publish it together
@@ -515,14 +707,12 @@ __device__ __forceinline__ int select_winner(const int *__restrict__ act_in, int
 template <typename TR, typename TW>
 __device__ void gain_regs_body(const StepDesc &d, int p)
 {
-    __shared__ double colbuf[256];
     __shared__ double piv[128];
     __shared__ double red[4];
     if (d.state[ST_STATUS] != 0 || p >= d.n_act) return;
     const int i = d.act_in[p];
     const int64_t bs = (int64_t)d.N_tp * d.N_tp;
-    const bool ok = chol_regs<TR, TW>((const TR *)d.R + blk_index(i, i) * bs, d.N_t, d.N_tp >> 4, colbuf, piv, nullptr,
-                                      d, i * bs);
+    const bool ok = chol_mfma<TR, TW>((const TR *)d.R + blk_index(i, i) * bs, d.N_t, d.N_tp >> 4, piv, d, i * bs);
     if (!ok) {
         if (threadIdx.x == 0) d.gains[p] = -INFINITY;
         return;
