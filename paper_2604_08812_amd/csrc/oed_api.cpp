@@ -647,11 +647,9 @@ oed_status oed_create(oed_ctx **out, const void *K, int32_t dtype, int64_t ld, i
         HIPCHK(h, dmalloc(h, (void **)&h->picks, sizeof(int) * h->N_c));
         HIPCHK(h, dmalloc(h, (void **)&h->state, sizeof(int) * ST_WORDS));
         HIPCHK(h, dmalloc(h, (void **)&h->dcmap, sizeof(int) * h->N_c));
-        const int64_t tri = (int64_t)h->N_t * (h->N_t + 1) / 2;
-        if (h->N_t > REGS_MAX_NT && gain_lds_bytes(h->N_t) == 0)
-            HIPCHK(h, dmalloc(h, (void **)&h->scratch_gain, sizeof(double) * tri * h->N_c));
-        if (h->N_t > REGS_MAX_NT && pick_lds_bytes(h->N_t) == 0)
-            HIPCHK(h, dmalloc(h, (void **)&h->scratch_pick, sizeof(double) * tri * 2));
+        const size_t sg = gain_scratch_doubles(h->N_t, h->N_tp, h->N_c), sp = pick_scratch_doubles(h->N_t, h->N_tp);
+        if (sg) HIPCHK(h, dmalloc(h, (void **)&h->scratch_gain, sizeof(double) * sg));
+        if (sp) HIPCHK(h, dmalloc(h, (void **)&h->scratch_pick, sizeof(double) * sp));
         HIPCHK(h, hipMemcpyAsync(h->dcmap, h->cmap.data(), sizeof(int) * h->N_c, hipMemcpyHostToDevice, h->stream));
         if (!hloc.empty()) {
             HIPCHK(h, dmalloc(h, (void **)&h->noise_h, sizeof(double) * h->N_c));

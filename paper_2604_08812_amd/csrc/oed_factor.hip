@@ -329,22 +329,26 @@ __device__ __forceinline__ bool chol16_inv(doublex4 M, double *ylds, double *piv
         // the pivot and row j of the eliminated block (row j: lanes of group jg, register jr);
         // column j of the lane's own rows 4g + r sits in lane 16 g + j by symmetry
         const double mj = M[jr], xj = X[jr];
-        const double d = __shfl(mj, jg * 16 + j);
+        const int src = jg * 16 + j;  // wave-uniform
+        const double d = __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(mj), src),
+                                          __builtin_amdgcn_readlane(__double2loint(mj), src));
         if (!(d > 0.0) || !isfinite(d)) return false;
         if (lane == 0) piv[j] = d;
-        const double inv = 1.0 / d;
-        const double mjc = __shfl(mj, jg * 16 + c);
+        // 1/d from the hardware reciprocal and two Newton steps (within an ulp or two)
+        double inv = __builtin_amdgcn_rcp(d);
+        inv = fma(inv, fma(-d, inv, 1.0), inv);
+        inv = fma(inv, fma(-d, inv, 1.0), inv);
+        const double mjc = c > j ? __shfl(mj, jg * 16 + c) : 0.0;
         const double xjc = __shfl(xj, jg * 16 + c);
         double mja[4];
 #pragma unroll
         for (int r = 0; r < 4; ++r) mja[r] = __shfl(M[r], g * 16 + j);
 #pragma unroll
-        for (int r = 0; r < 4; ++r)
-            if (4 * g + r > j) {
-                const double m = mja[r] * inv;
-                if (c > j) M[r] = fma(-m, mjc, M[r]);
-                X[r] = fma(-m, xjc, X[r]);
-            }
+        for (int r = 0; r < 4; ++r) {
+            const double m = 4 * g + r > j ? mja[r] * inv : 0.0;
+            M[r] = fma(-m, mjc, M[r]);
+            X[r] = fma(-m, xjc, X[r]);
+        }
     }
     // the pivots went to LDS from lane 0; the wave's LDS accesses complete in order
     __builtin_amdgcn_wave_barrier();
@@ -803,6 +807,194 @@ __device__ void pick_lds_body(const StepDesc &d, double *lds)
 }
 
 // ---------------------------------------------------------------------------------------------
+// Blocked factorisation in global scratch for 128 < N_t <= 16 BLK_MAX_NB (one work-group per
+// block; the block is too large for registers or LDS).  The same upper form as chol_mfma: the
+// upper 16x16 blocks (I, C), I <= C < nbr, in FP64 accumulator order, block (I, C) at
+// S + 256 (C (C + 1) / 2 + I).  Step p: wave p % 4 factors A_pp in-wave (chol16_inv) and
+// publishes U_pp^-1; the row blocks U_pC = U_pp^-T A_pC are formed and published through LDS;
+// the trailing blocks A_IC -= U_pI^T U_pC are updated in place.  Traffic per block: about
+// nbr^3 / 3 block reads and writes (13 MB at N_t = 420), against nbr^3 16^3 / 6 element
+// reads and writes for an unblocked factorisation.
+
+__device__ __forceinline__ int64_t ublk(int I, int C) { return ((int64_t)C * (C + 1) / 2 + I) << 8; }
+
+// Copy the candidate's diagonal block of R (lower blocks, TR) into S as upper FP64 blocks.
+template <typename TR>
+__device__ void load_upper_global(const TR *__restrict__ Rb, int nb, int nbr, double *__restrict__ S)
+{
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, g = lane >> 4, c = lane & 15;
+    const int tofs = ((((c >> 2) << 4) + 4 * g) << 2) + (c & 3);
+    for (int C = w; C < nbr; C += 4)
+        for (int I = 0; I <= C; ++I) {
+            const TR *blk = Rb + ((C * nb + I) << 8) + tofs;
+            doublex4 v;
+#pragma unroll
+            for (int r = 0; r < 4; ++r) v[r] = (double)blk[4 * r];
+            st4(S + ublk(I, C) + lane * 4, v);
+        }
+}
+
+// The factorisation of the upper blocks in S (whole work-group).  Ub: LDS, (nbr + 1) x 64
+// doublex4 (row blocks of the step, then U_pp^-1).  With Yg, U_pp^-1 of every diagonal block is
+// also kept there (block p at Yg + 256 p).  Pivots to piv (16 nbr).  Returns false (uniformly) at
+// a pivot that is not > 0 or not finite.
+__device__ bool chol_blocked(double *__restrict__ S, int nbr, double *piv, double *__restrict__ Yg,
+                             doublex4 *Ub, int *sfail)
+{
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int al = a_lane<double>(lane);
+    doublex4 *Yl = Ub + nbr * 64;
+    for (int p = 0; p < nbr; ++p) {
+        if (w == (p & 3)) {
+            const bool ok = chol16_inv(ld4(S + ublk(p, p) + lane * 4), (double *)Yl, piv + 16 * p);
+            if (lane == 0) *sfail = ok ? 0 : 1;
+        }
+        __syncthreads();
+        if (*sfail) return false;
+        const doublex4 y = Yl[al];
+        if (Yg && w == 0) st4(Yg + ((int64_t)p << 8) + lane * 4, Yl[lane]);
+        for (int C = p + 1 + w; C < nbr; C += 4) {
+            const doublex4 a = ld4(S + ublk(p, C) + lane * 4);
+            doublex4 acc{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+            for (int s4 = 0; s4 < 4; ++s4) acc = mfma16(y[s4], a[s4], acc);
+            st4(S + ublk(p, C) + lane * 4, acc);
+            Ub[C * 64 + lane] = acc;
+        }
+        __syncthreads();
+        for (int C = p + 1 + w; C < nbr; C += 4) {
+            const doublex4 b = Ub[C * 64 + lane];
+            for (int I = p + 1; I <= C; ++I) {
+                const doublex4 u = Ub[I * 64 + al];
+                doublex4 acc = ld4(S + ublk(I, C) + lane * 4);
+#pragma unroll
+                for (int s4 = 0; s4 < 4; ++s4) acc = mfma16(-u[s4], b[s4], acc);
+                st4(S + ublk(I, C) + lane * 4, acc);
+            }
+        }
+        // the next step's owner reads its updated diagonal block, and Ub is rewritten
+        __syncthreads();
+    }
+    return true;
+}
+
+// 1/2 sum_{j < n} ln piv[j] for any n (whole work-group, fixed reduction order).
+__device__ double half_sum_log_any(const double *piv, int n, double *red)
+{
+    const int tid = threadIdx.x, lane = tid & 63;
+    double v = 0.0;
+    for (int t = tid; t < n; t += blockDim.x) v += log(piv[t]);
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+    if (lane == 0) red[tid >> 6] = v;
+    __syncthreads();
+    const double t = (red[0] + red[1]) + (red[2] + red[3]);
+    __syncthreads();
+    return 0.5 * t;
+}
+
+constexpr int BLK_MAX_NB = 64;  // the blocked path serves N_tp <= 1024
+
+// Dynamic LDS of the blocked kernels: Ub ((nbr + 1) blocks) and the pivots.
+__host__ __device__ inline size_t blocked_lds_bytes(int nbr)
+{
+    return (size_t)(nbr + 1) * 64 * sizeof(doublex4) + (size_t)16 * nbr * sizeof(double);
+}
+
+template <typename TR>
+__device__ void gain_blocked_body(const StepDesc &d, int p, unsigned char *dyn)
+{
+    __shared__ double red[4];
+    __shared__ int sfail;
+    if (d.state[ST_STATUS] != 0 || p >= d.n_act) return;
+    const int nbr = d.N_tp >> 4;
+    doublex4 *Ub = (doublex4 *)dyn;
+    double *piv = (double *)(Ub + (nbr + 1) * 64);
+    const int64_t nblk = (int64_t)nbr * (nbr + 1) / 2;
+    double *S = d.scratch + p * (nblk << 8);
+    const int i = d.act_in[p];
+    load_upper_global((const TR *)d.R + blk_index(i, i) * (int64_t)d.N_tp * d.N_tp, nbr, nbr, S);
+    __syncthreads();
+    if (!chol_blocked(S, nbr, piv, nullptr, Ub, &sfail)) {
+        if (threadIdx.x == 0) d.gains[p] = -INFINITY;
+        return;
+    }
+    const double ls = half_sum_log_any(piv, d.N_t, red);
+    if (threadIdx.x == 0) d.gains[p] = ls - (d.noise_h ? d.noise_h[i] : d.half_noise);
+}
+
+// Pick: the winner's factorisation as in the gain kernel, then Z = L^-1 = U^-T by block
+// columns q (wave q % 4, no barriers): Z_qq = (U_qq^-1)^T and, down the column,
+// Z_pq = -(U_pp^-1)^T sum_{r = q}^{p-1} U_rp^T Z_rq; Z is written to Linv in the operand order.
+// Scratch: S (nblk blocks), U_pp^-1 (nbr blocks), Z (nblk lower blocks, (p, q) at p(p+1)/2 + q).
+template <typename TR>
+__device__ void pick_blocked_body(const StepDesc &d, unsigned char *dyn)
+{
+    __shared__ double red[4];
+    __shared__ int sfail;
+    if (d.state[ST_STATUS] != 0) return;
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6, g = lane >> 4, c = lane & 15;
+    const int al = a_lane<double>(lane);
+    double g_sel = 0.0;
+    const int pos = select_winner(d.act_in, d.n_act, d.gains, d.forced, d.state, &g_sel);
+    if (pos < 0) return;
+    const int s = d.act_in[pos];
+    for (int q = tid; q < d.n_act - 1; q += blockDim.x) d.act_out[q] = d.act_in[q < pos ? q : q + 1];
+    const int nbr = d.N_tp >> 4;
+    doublex4 *Ub = (doublex4 *)dyn;
+    double *piv = (double *)(Ub + (nbr + 1) * 64);
+    const int64_t nblk = (int64_t)nbr * (nbr + 1) / 2;
+    double *S = d.scratch, *Yg = S + (nblk << 8), *Z = Yg + ((int64_t)nbr << 8);
+    load_upper_global((const TR *)d.R + blk_index(s, s) * (int64_t)d.N_tp * d.N_tp, nbr, nbr, S);
+    __syncthreads();
+    if (!chol_blocked(S, nbr, piv, Yg, Ub, &sfail)) {
+        if (tid == 0) d.state[ST_STATUS] = 2;
+        return;
+    }
+    const double ls = half_sum_log_any(piv, d.N_t, red);
+    if (tid == 0) {
+        d.picks[d.step] = s;
+        d.pick_gain[d.step] = d.forced < 0 ? g_sel : ls - (d.noise_h ? d.noise_h[s] : d.half_noise);
+        d.state[ST_NPICKS] = d.step + 1;
+        d.state[ST_LAST] = s;
+    }
+    // element (4g + r, c) of a block's transpose sits at tofs + 4r of the block
+    const int tofs = ((((c >> 2) << 4) + 4 * g) << 2) + (c & 3);
+    auto zblk = [](int P, int Q) -> int64_t { return ((int64_t)P * (P + 1) / 2 + Q) << 8; };
+    for (int q = w; q < nbr; q += 4) {
+        doublex4 zqq;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) zqq[r] = Yg[((int64_t)q << 8) + tofs + 4 * r];
+        st4(Z + zblk(q, q) + lane * 4, zqq);
+        for (int P = q + 1; P < nbr; ++P) {
+            doublex4 t{0.0, 0.0, 0.0, 0.0};
+            for (int r = q; r < P; ++r) {
+                const doublex4 u = ld4(S + ublk(r, P) + al * 4);
+                const doublex4 z = ld4(Z + zblk(r, q) + lane * 4);
+#pragma unroll
+                for (int s4 = 0; s4 < 4; ++s4) t = mfma16(u[s4], z[s4], t);
+            }
+            const doublex4 y = ld4(Yg + ((int64_t)P << 8) + al * 4);
+            doublex4 zpq{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+            for (int s4 = 0; s4 < 4; ++s4) zpq = mfma16(-y[s4], t[s4], zpq);
+            st4(Z + zblk(P, q) + lane * 4, zpq);
+        }
+    }
+    __syncthreads();
+    // Linv: lower blocks (P, Q) from Z, the operand order; blocks above the diagonal are zero
+    const int nb = nbr;
+    for (int b = w; b < nbr * nbr; b += 4) {
+        const int P = b / nbr, Q = b - P * nbr;
+        doublex4 v{0.0, 0.0, 0.0, 0.0};
+        if (Q <= P) v = ld4(Z + zblk(P, Q) + lane * 4);
+        // element (16P + 4g + r, 16Q + c) of L^-1 -> operand position (t, k)
+        double *dst = d.Linv + ((int64_t)(P * nb + Q) << 8) + tofs;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) dst[4 * r] = v[r];
+    }
+}
+
+// ---------------------------------------------------------------------------------------------
 // Kernels: single instance (descriptor by value) and batched (descriptor array).
 
 template <typename TR, typename TW>
@@ -837,6 +1029,20 @@ __global__ void __launch_bounds__(256, 1) pick_regs_batched(const StepDesc *__re
 }
 
 template <typename TR>
+__global__ void __launch_bounds__(256) gain_blocked_kernel(StepDesc d)
+{
+    extern __shared__ double dyn[];
+    gain_blocked_body<TR>(d, blockIdx.x, (unsigned char *)dyn);
+}
+
+template <typename TR>
+__global__ void __launch_bounds__(256) pick_blocked_kernel(StepDesc d)
+{
+    extern __shared__ double dyn[];
+    pick_blocked_body<TR>(d, (unsigned char *)dyn);
+}
+
+template <typename TR>
 __global__ void __launch_bounds__(256) gain_lds_kernel(StepDesc d)
 {
     extern __shared__ double dyn[];
@@ -867,6 +1073,22 @@ static int max_lds()
     return g_max_lds;
 }
 
+size_t gain_scratch_doubles(int N_t, int N_tp, int N_c)
+{
+    if (N_t <= REGS_MAX_NT) return 0;
+    const size_t nbr = N_tp / 16;
+    if (nbr <= (size_t)BLK_MAX_NB) return nbr * (nbr + 1) / 2 * 256 * N_c;
+    return gain_lds_bytes(N_t) ? 0 : (size_t)N_t * (N_t + 1) / 2 * N_c;
+}
+
+size_t pick_scratch_doubles(int N_t, int N_tp)
+{
+    if (N_t <= REGS_MAX_NT) return 0;
+    const size_t nbr = N_tp / 16;
+    if (nbr <= (size_t)BLK_MAX_NB) return (nbr * (nbr + 1) + nbr) * 256;
+    return pick_lds_bytes(N_t) ? 0 : (size_t)N_t * (N_t + 1);
+}
+
 size_t gain_lds_bytes(int N_t)
 {
     const size_t b = sizeof(double) * (size_t)N_t * (N_t + 1) / 2;
@@ -891,6 +1113,11 @@ static hipError_t launch_gain_t(const StepDesc &d, hipStream_t s)
     if (d.n_act <= 0) return hipSuccess;
     if (d.N_t <= REGS_MAX_NT) {
         hipLaunchKernelGGL((gain_regs_kernel<TR, TW>), dim3(d.n_act), dim3(256), 0, s, d);
+    } else if (d.N_tp <= 16 * BLK_MAX_NB) {
+        if (d.nheld || !d.scratch) return hipErrorInvalidValue;
+        const size_t lds = blocked_lds_bytes(d.N_tp >> 4);
+        allow_lds(gain_blocked_kernel<TR>, lds);
+        hipLaunchKernelGGL(gain_blocked_kernel<TR>, dim3(d.n_act), dim3(256), lds, s, d);
     } else {
         if (d.nheld) return hipErrorInvalidValue;
         const size_t lds = d.scratch ? 0 : gain_lds_bytes(d.N_t);
@@ -905,6 +1132,11 @@ static hipError_t launch_pick_t(const StepDesc &d, hipStream_t s)
 {
     if (d.N_t <= REGS_MAX_NT) {
         hipLaunchKernelGGL((pick_regs_kernel<TR, TW>), dim3(1), dim3(256), 0, s, d);
+    } else if (d.N_tp <= 16 * BLK_MAX_NB) {
+        if (d.nheld || !d.scratch) return hipErrorInvalidValue;
+        const size_t lds = blocked_lds_bytes(d.N_tp >> 4);
+        allow_lds(pick_blocked_kernel<TR>, lds);
+        hipLaunchKernelGGL(pick_blocked_kernel<TR>, dim3(1), dim3(256), lds, s, d);
     } else {
         if (d.nheld) return hipErrorInvalidValue;
         const size_t lds = d.scratch ? 0 : pick_lds_bytes(d.N_t);

@@ -151,6 +151,11 @@ hipError_t launch_syrk_batched(const StepDesc *descs, int n, int64_t total, int 
 // LDS / global-scratch kernels run.
 constexpr int REGS_MAX_NT = 128;
 
+// Global scratch (doubles) the factorisation kernels of a block size need: the gain kernel for
+// N_c candidates and the pick kernel (0: none).
+size_t gain_scratch_doubles(int N_t, int N_tp, int N_c);
+size_t pick_scratch_doubles(int N_t, int N_tp);
+
 // Bytes of dynamic LDS the LDS factorisation kernels need (0 = use global scratch).
 size_t gain_lds_bytes(int N_t);
 size_t pick_lds_bytes(int N_t);
