@@ -325,9 +325,10 @@ __device__ __forceinline__ void tile_map(const StepDesc &d, int64_t P, int64_t Q
 // rows) and B panel (tile columns) of W into LDS once (double-buffered, one barrier per
 // slice) and every wave reads its operands from there; the next slice's global loads are in
 // flight while the current slice's MFMAs run.  The product W_I W_J^T accumulates from zero
-// and is subtracted from R at the end.  FP32: the R tile is loaded into registers a few
-// blocks per slice, behind the next slice's W loads, so it streams in during the MFMAs.
-// FP64 (no registers for the tile) reads R in the epilogue.
+// and is subtracted from R at the end, which reads the R tile in the epilogue: with p W slots
+// per launch the tile's MFMA work is p times longer than its R traffic, and without a register
+// copy of the tile the FP32 kernel fits three work-groups per CU, whose MFMAs cover each
+// other's epilogues (streaming R into registers during the last slot measured slower there).
 template <typename T, int NB, int KS>
 __device__ void syrk_lds_body(const StepDesc &d, int64_t tile)
 {
@@ -335,8 +336,6 @@ __device__ void syrk_lds_body(const StepDesc &d, int64_t tile)
     typedef typename V4<T>::type vec;
     constexpr int N_tp = 16 * NB;
     constexpr int NST = NB / KS;              // stages per W block
-    constexpr bool PREFETCH_R = sizeof(T) == 4;
-    constexpr int PER = (16 + NST - 1) / NST;  // R blocks fetched per stage of the last W block
     __shared__ vec lds[2][2][KS][8 * 64];      // [buffer][A/B][slice][sub-block * 64 + lane]
     if (d.state[ST_STATUS] != 0) return;
     int64_t P, Q;
@@ -353,7 +352,7 @@ __device__ void syrk_lds_body(const StepDesc &d, int64_t tile)
     const int64_t wslot = d.wslot;
     auto wblk = [&](int slot) -> const T * { return W0 + slot * wslot; };
 
-    vec rt[16], acc[16];
+    vec acc[16];
 #pragma unroll
     for (int f = 0; f < 16; ++f) acc[f] = vec{0, 0, 0, 0};
     vec sa[KS][2], sbv[KS][2];
@@ -380,20 +379,13 @@ __device__ void syrk_lds_body(const StepDesc &d, int64_t tile)
     __syncthreads();
 
     // The NST stages of one W block (cur); the stage after its last one is the first of nxt
-    // (null: none).  par: LDS buffer of its first stage.  The last block's pass also streams
-    // the R tile in (PREF): PER blocks per stage, issued after that stage's W loads, so the
-    // wait for those never waits for R.
-    auto pass = [&](auto pref, const T *cur, const T *nxt, int par) {
-        constexpr bool PREF = decltype(pref)::value;
+    // (null: none).  par: LDS buffer of its first stage.
+    auto pass = [&](const T *cur, const T *nxt, int par) {
 #pragma unroll
         for (int q = 0; q < NST; ++q) {
             const int buf = par ^ (q & 1);
             const bool more = q + 1 < NST || nxt;
             if (more) stage(q + 1 < NST ? cur + (((q + 1) * KS) << 8) : nxt);
-            if (PREF) {
-#pragma unroll
-                for (int f = q * PER; f < (q + 1) * PER && f < 16; ++f) rt[f] = ld4(Rl + m.rblk[f]);
-            }
             if (m.any) {
 #pragma unroll
                 for (int k = 0; k < KS; ++k) {
@@ -416,13 +408,22 @@ __device__ void syrk_lds_body(const StepDesc &d, int64_t tile)
         }
     };
     const int nw = d.nw;
-    for (int slot = 0; slot + 1 < nw; ++slot) pass(BoolC<false>(), wblk(slot), wblk(slot + 1), (slot * NST) & 1);
-    pass(BoolC<PREFETCH_R>(), wblk(nw - 1), nullptr, ((nw - 1) * NST) & 1);
+    for (int slot = 0; slot + 1 < nw; ++slot) pass(wblk(slot), wblk(slot + 1), (slot * NST) & 1);
+    pass(wblk(nw - 1), nullptr, ((nw - 1) * NST) & 1);
 
     if (!m.any) return;
+    // the tile's loads in flight together, all 16 in FP32, four at a time in FP64 (registers);
+    // blocks outside the triangle read a valid address and are not stored
+    constexpr int GR = sizeof(T) == 4 ? 16 : 4;
 #pragma unroll
-    for (int f = 0; f < 16; ++f)
-        if (m.ok[f]) st4(Rl + m.rblk[f], (PREFETCH_R ? rt[f] : ld4(Rl + m.rblk[f])) - acc[f]);
+    for (int f0 = 0; f0 < 16; f0 += GR) {
+        vec rt[GR];
+#pragma unroll
+        for (int f = 0; f < GR; ++f) rt[f] = ld4(Rl + m.rblk[f0 + f]);
+#pragma unroll
+        for (int f = 0; f < GR; ++f)
+            if (m.ok[f0 + f]) st4(Rl + m.rblk[f0 + f], rt[f] - acc[f0 + f]);
+    }
 }
 
 // ---------------------------------------------------------------------------------------------
@@ -900,7 +901,7 @@ __global__ void __launch_bounds__(256, 2) syrk_lds_rt_kernel(StepDesc d, int64_t
 }
 
 template <typename T, int NB, int KS>
-__global__ void __launch_bounds__(256, 2) syrk_lds_kernel(StepDesc d, int64_t per_xcd)
+__global__ void __launch_bounds__(256, (sizeof(T) == 4 ? 3 : 2)) syrk_lds_kernel(StepDesc d, int64_t per_xcd)
 {
     const int64_t tile = xcd_item(blockIdx.x, per_xcd);
     if (tile >= d.nitems) return;
