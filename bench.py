@@ -294,24 +294,24 @@ def run_paper_shape(args):
     sel = Selector(None, spec.N_s, spec.N_t, s2, precision="mixed_f32", profile=True)
     delay, variant, _ = sel.config()
 
-    def pack():
+    def pack(target):
         t = time.perf_counter()
         for s0, n, P in k_row_panels(F, spec.N_s, spec.N_t, s2, 56):
-            sel.pack_rows(P, s0, n)
+            target.pack_rows(P, s0, n)
             del P
         torch.cuda.synchronize()
         return time.perf_counter() - t
 
     pack_s = []
     for w in range(args.warmup):
-        pack_s.append(pack())
+        pack_s.append(pack(sel))
         sel.greedy(budget)
         sel.reset(None)
         log(f"warmup {w + 1}/{args.warmup} done")
     ms_list = []
     sel.profile(reset=True)
     for st in range(args.steps):
-        pack_s.append(pack())
+        pack_s.append(pack(sel))
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         idx, gain = sel.greedy(budget)
@@ -324,6 +324,34 @@ def run_paper_shape(args):
     dev_bytes = sel.device_bytes()
     sel.close()
     ms = sum(ms_list) / len(ms_list)
+    left = None
+    if not args.no_left:
+        # left-looking (Algorithm 1's order) on the same K: pack, free F (the W history needs
+        # the room), one timed selection
+        sell = Selector(None, spec.N_s, spec.N_t, s2, precision="mixed_f32", profile=True, method="left",
+                        max_budget=budget)
+        pack_l = pack(sell)
+        del F
+        torch.cuda.empty_cache()
+        F = None
+        torch.cuda.synchronize()
+        sell.profile(reset=True)
+        t0 = time.perf_counter()
+        il, gl = sell.greedy(budget)
+        torch.cuda.synchronize()
+        msl = (time.perf_counter() - t0) * 1e3
+        pl = sell.profile(reset=True)
+        devl = sell.device_bytes()
+        sell.close()
+        log(f"left-looking: {msl:.1f} ms per selection")
+        tfl = pl["syrk_flops"] / (pl["ms"]["syrk"] * 1e-3) / 1e12 if pl["ms"]["syrk"] > 0 else 0.0
+        left = {"value": round(budget / (msl * 1e-3), 3), "unit": "greedy steps/s", "ms_per_step": round(msl, 3),
+                "column_kernel": {"kernel": "column_rt_kernel<float>", "algorithmic_tflops": round(tfl, 3),
+                                  "peak": PEAK_TFLOPS["mixed_f32"], "frac": round(tfl / PEAK_TFLOPS["mixed_f32"], 4),
+                                  "algorithmic_flops_per_selection": pl["syrk_flops"]},
+                "kernel_ms_per_step": {k: round(v, 3) for k, v in pl["ms"].items()},
+                "pack_s": round(pack_l, 3), "device_bytes_of_handle": devl,
+                "vs_right_looking": compare_picks(il, gl, idx, gain)}
     result = {
         "metric": "greedy steps/s + SYRK TFLOP/s (% MFMA peak), mixed vs FP64, same picks",
         "value": round(budget / (ms * 1e-3), 3), "unit": "greedy steps/s", "n_gpus": 1, "steps": args.steps,
@@ -340,6 +368,8 @@ def run_paper_shape(args):
         "device_bytes_of_handle": dev_bytes,
         "picks_head": [int(x) for x in idx[:10]], "gain_first_last": [float(gain[0]), float(gain[-1])],
     }
+    if left is not None:
+        result["left_looking_mixed_f32"] = left
     del F
     print(json.dumps(result), flush=True)
 

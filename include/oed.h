@@ -127,14 +127,15 @@ typedef struct oed_options {
  *  LEFT_LOOKING  : the order of Algorithm 1 (Sec. III-D): R keeps K off the diagonal; every
  *                  pick forms only its own block column, K_is - sum over the earlier picks'
  *                  block columns (W history), and updates the diagonal blocks.  About 1/3 of
- *                  the flops of RIGHT_LOOKING at 600 x 128, budget 175.  All precisions,
- *                  N_t <= 128 (else OED_E_UNSUPPORTED); the delay option does not apply.
+ *                  the flops of RIGHT_LOOKING at 600 x 128, budget 175.  FP64 and
+ *                  MIXED_F32 for N_t <= 1024, MIXED_BF16X3 for N_t <= 128 (else
+ *                  OED_E_UNSUPPORTED); the delay option does not apply.
  */
 #define OED_METHOD_RIGHT_LOOKING 0
 #define OED_METHOD_LEFT_LOOKING 1
 /* AUTO: left-looking when it needs fewer flops, i.e. for max_budget <= N_c / 2 (per pick k the
    column costs 2 k N_t^3 per remaining candidate against (N_c - k) N_t^3 for the downdate), and
-   N_t <= 128; else right-looking. */
+   N_t <= 1024; else right-looking. */
 #define OED_METHOD_AUTO 2
 
 /* Fill *opt with the defaults (FP64, no flags, all sensors). */

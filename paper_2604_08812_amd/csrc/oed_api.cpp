@@ -563,7 +563,8 @@ oed_status oed_create(oed_ctx **out, const void *K, int32_t dtype, int64_t ld, i
     if (o.method != OED_METHOD_RIGHT_LOOKING && o.method != OED_METHOD_LEFT_LOOKING && o.method != OED_METHOD_AUTO)
         return OED_E_ARG;
     if (o.max_budget < 0 || o.max_budget > N_s) return OED_E_ARG;
-    if (o.method == OED_METHOD_LEFT_LOOKING && N_t > REGS_MAX_NT) return OED_E_UNSUPPORTED;
+    // left-looking needs the diagonal-block update of the register or blocked gain kernels
+    if (o.method == OED_METHOD_LEFT_LOOKING && N_t > BLK_MAX_NTP) return OED_E_UNSUPPORTED;
     if (o.delay > 1 && N_t > REGS_MAX_NT) return OED_E_UNSUPPORTED;
     for (int r : o.reserved)
         if (r != 0) return OED_E_ARG;
@@ -588,7 +589,7 @@ oed_status oed_create(oed_ctx **out, const void *K, int32_t dtype, int64_t ld, i
     if (o.method == OED_METHOD_AUTO) {
         const int nc = o.candidates ? o.n_candidates : N_s;
         const int mb = o.max_budget > 0 ? std::min(o.max_budget, nc) : nc;
-        o.method = (N_t <= REGS_MAX_NT && 2 * mb <= nc) ? OED_METHOD_LEFT_LOOKING : OED_METHOD_RIGHT_LOOKING;
+        o.method = (N_t <= BLK_MAX_NTP && 2 * mb <= nc) ? OED_METHOD_LEFT_LOOKING : OED_METHOD_RIGHT_LOOKING;
     }
     h->left = o.method == OED_METHOD_LEFT_LOOKING;
     if (h->left) h->delay = 1;

@@ -819,8 +819,12 @@ __device__ void pick_lds_body(const StepDesc &d, double *lds)
 __device__ __forceinline__ int64_t ublk(int I, int C) { return ((int64_t)C * (C + 1) / 2 + I) << 8; }
 
 // Copy the candidate's diagonal block of R (lower blocks, TR) into S as upper FP64 blocks.
+// With held W blocks (slots 0 .. d.nheld-1 at candidate offset pofs, same element type as R)
+// their products P_I P_C^T are subtracted, and with d.wb the corrected block is written back
+// to R (left-looking: the newest block column applied to the diagonal block in place).
 template <typename TR>
-__device__ void load_upper_global(const TR *__restrict__ Rb, int nb, int nbr, double *__restrict__ S)
+__device__ void load_upper_global(const TR *__restrict__ Rb, int nb, int nbr, double *__restrict__ S,
+                                  const StepDesc &d, int64_t pofs)
 {
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, g = lane >> 4, c = lane & 15;
     const int tofs = ((((c >> 2) << 4) + 4 * g) << 2) + (c & 3);
@@ -830,6 +834,17 @@ __device__ void load_upper_global(const TR *__restrict__ Rb, int nb, int nbr, do
             doublex4 v;
 #pragma unroll
             for (int r = 0; r < 4; ++r) v[r] = (double)blk[4 * r];
+            for (int hp = 0; hp < d.nheld; ++hp) {
+                const TR *Pw = (const TR *)d.W + hp * d.wslot + pofs;
+                const auto q = HeldProd<TR>::run(Pw, nullptr, I, C, nb, nbr, lane);
+#pragma unroll
+                for (int r = 0; r < 4; ++r) v[r] -= (double)q[r];
+            }
+            if (d.wb && d.nheld > 0) {
+                TR *wblk = const_cast<TR *>(blk);
+#pragma unroll
+                for (int r = 0; r < 4; ++r) wblk[4 * r] = (TR)v[r];
+            }
             st4(S + ublk(I, C) + lane * 4, v);
         }
 }
@@ -892,7 +907,7 @@ __device__ double half_sum_log_any(const double *piv, int n, double *red)
     return 0.5 * t;
 }
 
-constexpr int BLK_MAX_NB = 64;  // the blocked path serves N_tp <= 1024
+constexpr int BLK_MAX_NB = BLK_MAX_NTP / 16;
 
 // Dynamic LDS of the blocked kernels: Ub ((nbr + 1) blocks) and the pivots.
 __host__ __device__ inline size_t blocked_lds_bytes(int nbr)
@@ -912,7 +927,8 @@ __device__ void gain_blocked_body(const StepDesc &d, int p, unsigned char *dyn)
     const int64_t nblk = (int64_t)nbr * (nbr + 1) / 2;
     double *S = d.scratch + p * (nblk << 8);
     const int i = d.act_in[p];
-    load_upper_global((const TR *)d.R + blk_index(i, i) * (int64_t)d.N_tp * d.N_tp, nbr, nbr, S);
+    const int64_t bs = (int64_t)d.N_tp * d.N_tp;
+    load_upper_global((const TR *)d.R + blk_index(i, i) * bs, nbr, nbr, S, d, i * bs);
     __syncthreads();
     if (!chol_blocked(S, nbr, piv, nullptr, Ub, &sfail)) {
         if (threadIdx.x == 0) d.gains[p] = -INFINITY;
@@ -944,7 +960,8 @@ __device__ void pick_blocked_body(const StepDesc &d, unsigned char *dyn)
     double *piv = (double *)(Ub + (nbr + 1) * 64);
     const int64_t nblk = (int64_t)nbr * (nbr + 1) / 2;
     double *S = d.scratch, *Yg = S + (nblk << 8), *Z = Yg + ((int64_t)nbr << 8);
-    load_upper_global((const TR *)d.R + blk_index(s, s) * (int64_t)d.N_tp * d.N_tp, nbr, nbr, S);
+    const int64_t bs = (int64_t)d.N_tp * d.N_tp;
+    load_upper_global((const TR *)d.R + blk_index(s, s) * bs, nbr, nbr, S, d, s * bs);
     __syncthreads();
     if (!chol_blocked(S, nbr, piv, Yg, Ub, &sfail)) {
         if (tid == 0) d.state[ST_STATUS] = 2;
@@ -1114,7 +1131,7 @@ static hipError_t launch_gain_t(const StepDesc &d, hipStream_t s)
     if (d.N_t <= REGS_MAX_NT) {
         hipLaunchKernelGGL((gain_regs_kernel<TR, TW>), dim3(d.n_act), dim3(256), 0, s, d);
     } else if (d.N_tp <= 16 * BLK_MAX_NB) {
-        if (d.nheld || !d.scratch) return hipErrorInvalidValue;
+        if (!d.scratch || (d.nheld && sizeof(TW) != sizeof(TR))) return hipErrorInvalidValue;
         const size_t lds = blocked_lds_bytes(d.N_tp >> 4);
         allow_lds(gain_blocked_kernel<TR>, lds);
         hipLaunchKernelGGL(gain_blocked_kernel<TR>, dim3(d.n_act), dim3(256), lds, s, d);

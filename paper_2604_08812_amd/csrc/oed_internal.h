@@ -150,6 +150,9 @@ hipError_t launch_syrk_batched(const StepDesc *descs, int n, int64_t total, int 
 // Largest N_t handled by the register-resident factorisation kernels; beyond it the
 // LDS / global-scratch kernels run.
 constexpr int REGS_MAX_NT = 128;
+// Largest padded block size of the blocked global-scratch factorisation kernels (and of the
+// left-looking method beyond REGS_MAX_NT); larger blocks fall back to element-wise kernels.
+constexpr int BLK_MAX_NTP = 1024;
 
 // Global scratch (doubles) the factorisation kernels of a block size need: the gain kernel for
 // N_c candidates and the pick kernel (0: none).

@@ -743,6 +743,111 @@ __device__ void column_body(const StepDesc &d, int64_t item)
         }
 }
 
+// Left-looking block column for N_tp = 16 nb > 128: as column_body, with a run-time slice
+// loop and the N_tp columns of the pick taken in chunks of 128 (eight sub-blocks), the chunk
+// being the fastest index of the work item (split, row tile, chunk), so that the work-groups of
+// one row tile run together and share its rows of W in L2.
+template <typename T>
+__device__ void column_rt_body(const StepDesc &d, int64_t item)
+{
+    typedef typename V4<T>::type vec;
+    __shared__ vec lds[2][2][8 * 64];
+    if (d.state[ST_STATUS] != 0 || d.nsplit <= 0) return;
+    const int N_tp = d.N_tp, nb = N_tp >> 4, nchunk = (nb + 7) >> 3;
+    const int64_t rows_t = syrk_tile_rows(d.n_act, N_tp);
+    const int64_t per_split = rows_t * nchunk;
+    const int split = (int)(item / per_split);
+    const int64_t rem = item - split * per_split;
+    const int64_t P = rem / nchunk;
+    const int cc = (int)(rem - P * nchunk);
+    if (split >= d.nsplit) return;
+    const int h0 = (int)((int64_t)split * d.nw / d.nsplit), h1 = (int)((int64_t)(split + 1) * d.nw / d.nsplit);
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int alane = a_lane<T>(lane);
+    const int *__restrict__ act = d.act_in;
+    const int rows = d.n_act * N_tp, last = d.n_act - 1;
+    const int s = d.state[ST_LAST];
+    const int64_t bs = (int64_t)N_tp * N_tp;
+    const int ncol = min(8, nb - 8 * cc);
+    // staged operands: rows of the tile (A) and the chunk's rows of s (B; past nb clamped)
+    int64_t wA[2], wB[2];
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+        const int sb = wave + 4 * h;
+        const int r = (int)P * 128 + 16 * sb;
+        wA[h] = (int64_t)act[min(r / N_tp, last)] * bs + (int64_t)((r % N_tp) >> 4) * (nb * 256);
+        const int sbB = 8 * cc + sb;
+        wB[h] = (int64_t)s * bs + (int64_t)(sbB < nb ? sbB : 0) * (nb * 256);
+    }
+    int64_t off[2];
+    bool ok[2];
+#pragma unroll
+    for (int b = 0; b < 2; ++b) {
+        const int r = (int)P * 128 + wave * 32 + 16 * b;
+        ok[b] = r < rows;
+        off[b] = (int64_t)act[min(r / N_tp, last)] * bs + ((((r % N_tp) >> 4) * nb + 8 * cc) << 8);
+    }
+    const bool any = ok[0];
+    const T *W0 = (const T *)d.W + lane * 4;
+    const int64_t wslot = d.wslot;
+    vec acc[2][8];
+#pragma unroll
+    for (int b = 0; b < 2; ++b)
+#pragma unroll
+        for (int c = 0; c < 8; ++c) acc[b][c] = vec{0, 0, 0, 0};
+    vec sa[2], sbv[2];
+    auto stage = [&](const T *src) {
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            sa[h] = ld4(src + wA[h]);
+            sbv[h] = ld4(src + wB[h]);
+        }
+    };
+    auto put = [&](int buf) {
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            lds[buf][0][(wave + 4 * h) * 64 + lane] = sa[h];
+            lds[buf][1][(wave + 4 * h) * 64 + lane] = sbv[h];
+        }
+    };
+    stage(W0 + h0 * wslot);
+    put(0);
+    __syncthreads();
+    int buf = 0;
+    for (int slot = h0; slot < h1; ++slot) {
+        const T *cur = W0 + slot * wslot;
+        for (int q = 0; q < nb; ++q) {
+            const bool more = q + 1 < nb || slot + 1 < h1;
+            if (more) stage(q + 1 < nb ? cur + ((q + 1) << 8) : cur + wslot);
+            if (any) {
+                vec a[2], w[8];
+#pragma unroll
+                for (int b = 0; b < 2; ++b) a[b] = lds[buf][0][(2 * wave + b) * 64 + alane];
+#pragma unroll
+                for (int c = 0; c < 8; ++c) w[c] = lds[buf][1][c * 64 + lane];
+#pragma unroll
+                for (int s4 = 0; s4 < 4; ++s4)
+#pragma unroll
+                    for (int b = 0; b < 2; ++b)
+#pragma unroll
+                        for (int c = 0; c < 8; ++c) acc[b][c] = mfma16(a[b][s4], w[c][s4], acc[b][c]);
+            }
+            if (more) put(buf ^ 1);
+            __syncthreads();
+            buf ^= 1;
+        }
+    }
+    T *Cq = (T *)d.C + split * d.cstride + lane * 4;
+#pragma unroll
+    for (int b = 0; b < 2; ++b)
+        if (ok[b]) {
+#pragma unroll
+            for (int c = 0; c < 8; ++c)
+                if (c < ncol) st4(Cq + off[b] + (c << 8), acc[b][c]);
+        }
+}
+
 // The same with W in BF16 hi + lo parts (32-wide slices; hi hi^T + hi lo^T + lo hi^T on the
 // 16x16x32 BF16 MFMA, FP32 accumulation).
 template <int NB32>
@@ -946,6 +1051,15 @@ __global__ void __launch_bounds__(256, 2) column_kernel(StepDesc d, int64_t per_
     const int64_t item = xcd_item(blockIdx.x, per_xcd);
     if (item >= d.nitems) return;
     column_body<T, NB>(d, item);
+}
+
+// d.nitems here counts (split, row tile, column chunk) items
+template <typename T>
+__global__ void __launch_bounds__(256, 2) column_rt_kernel(StepDesc d, int64_t per_xcd)
+{
+    const int64_t item = xcd_item(blockIdx.x, per_xcd);
+    if (item >= d.nitems) return;
+    column_rt_body<T>(d, item);
 }
 
 template <int NB32>
@@ -1155,7 +1269,20 @@ static hipError_t launch_column_t(const StepDesc &d, hipStream_t s)
 hipError_t launch_column(const StepDesc &d, int rtype, int wtype, hipStream_t s)
 {
     if (d.n_act <= 0 || d.nsplit <= 0 || d.nitems <= 0) return hipSuccess;
-    if (d.N_tp % 16 != 0 || d.N_tp > 128 || d.nw < d.nsplit || !d.C) return hipErrorInvalidValue;
+    if (d.N_tp % 16 != 0 || d.nw < d.nsplit || !d.C) return hipErrorInvalidValue;
+    if (d.N_tp > 128) {
+        if (wtype == W_BF16X3) return hipErrorInvalidValue;
+        // one item per (split, row tile, 128-column chunk of the pick)
+        StepDesc e = d;
+        e.nitems = d.nitems * ((d.N_tp / 16 + 7) / 8);
+        const int64_t per_xcd = (e.nitems + 7) / 8;
+        const dim3 grid((unsigned)(per_xcd * 8)), block(256);
+        if (rtype == R_F64)
+            hipLaunchKernelGGL(column_rt_kernel<double>, grid, block, 0, s, e, per_xcd);
+        else
+            hipLaunchKernelGGL(column_rt_kernel<float>, grid, block, 0, s, e, per_xcd);
+        return hipGetLastError();
+    }
     if (wtype == W_BF16X3) {
         if (d.N_tp % 32 != 0 || !d.W2) return hipErrorInvalidValue;
         const int64_t per_xcd = (d.nitems + 7) / 8;

@@ -63,8 +63,8 @@ def test_host_side_argument_validation(lib):
     bad.method = 1
     bad.max_budget = 5     # > N_s
     assert lib.oed_create(ctypes.byref(h), fake, 0, 64, 4, 16, 1.0, None, ctypes.byref(bad)) == E_ARG
-    bad.max_budget = 0
-    assert lib.oed_create(ctypes.byref(h), fake, 0, 4 * 160, 4, 160, 1.0, None, ctypes.byref(bad)) == 6
+    bad.max_budget = 0     # left-looking serves N_t <= 1024
+    assert lib.oed_create(ctypes.byref(h), fake, 0, 2 * 1025, 2, 1025, 1.0, None, ctypes.byref(bad)) == 6
     bad = oed_options()
     lib.oed_options_init(ctypes.byref(bad))
     hn = (ctypes.c_double * 4)(0.0, float("nan"), 1.0, 2.0)   # non-finite per-sensor noise term

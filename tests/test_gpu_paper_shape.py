@@ -5,7 +5,8 @@ packing.
 
 Sampled outputs against the oracle: the scores of sampled candidates at steps 0, 1 and 2 (each
 the log-determinant of a Schur complement given the GPU's own picks), the telescoping identity over
-the first picks, and each pick's oracle score against the sampled ones.  The oracle's K entries
+the first picks, and each pick's oracle score against the sampled ones; the left-looking method
+must then pick the same sensors with the same gains.  The oracle's K entries
 are formed in FP64 from the same F; the GPU's are the FP32 GEMM of it (relative difference ~1e-7,
 far inside the mixed tolerance).
 """
@@ -80,3 +81,13 @@ def test_paper_shape_first_steps_against_oracle(paper):
     Ks = k_sub(F, N_t, spec.n_m, s2, picks)
     total = oracle.objective(Ks, N_t, s2, list(range(STEPS)))
     assert abs(sum(gains) - total) <= rtol * abs(total)
+    # the left-looking method (column GEMM over 128-column chunks of the pick, diagonal blocks
+    # kept current by the blocked gain kernel) picks the same sensors with the same gains
+    with Selector(None, N_s, N_t, s2, precision="mixed_f32", method="left", max_budget=STEPS) as sel:
+        for s0, n, P in k_row_panels(F, N_s, N_t, s2, 56):
+            sel.pack_rows(P, s0, n)
+            del P
+        il, gl = sel.greedy(STEPS)
+    print(f"left-looking: picks {list(il)} gains {list(gl)}", flush=True)
+    assert list(il) == picks
+    assert np.all(rel_err(gl, np.array(gains)) <= rtol)
