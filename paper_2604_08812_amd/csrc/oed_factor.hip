@@ -1,8 +1,9 @@
 // FP64 factorisation kernels of one greedy step: the gains of all remaining candidates (a
 // Cholesky of every diagonal block R_jj, i.e. of every matrix M_j of Algorithm 1, Sec. III-D),
 // and the pick (argmax with lowest-index ties, active-list update, factor of the winner and
-// its inverse).  Register-resident kernels serve N_t <= REGS_MAX_NT; LDS (or global-scratch)
-// kernels serve larger blocks.
+// its inverse).  Blocked factorisations on the FP64 MFMA serve N_t <= REGS_MAX_NT (register
+// resident) and N_tp <= BLK_MAX_NTP (global scratch); element-wise LDS or global-scratch kernels
+// serve larger blocks.
 #include <algorithm>
 
 #include "oed_device.h"
@@ -75,96 +76,8 @@ __device__ void tri_inverse(const double *L, double *X, int n)
 }
 
 // ---------------------------------------------------------------------------------------------
-// Makes loaded values opaque to the optimiser, so that loads followed by a mask are not turned
-// back into one load under a branch each (which serialises the LDS round trips of a column
-// step): all loads of a step are issued, then pinned together (one wait), then masked.
-__device__ __forceinline__ void pin8(double (&x)[8])
-{
-    __asm__ volatile("" : "+v"(x[0]), "+v"(x[1]), "+v"(x[2]), "+v"(x[3]), "+v"(x[4]), "+v"(x[5]), "+v"(x[6]),
-                     "+v"(x[7]));
-}
-__device__ __forceinline__ void pin4(double (&x)[4])
-{
-    __asm__ volatile("" : "+v"(x[0]), "+v"(x[1]), "+v"(x[2]), "+v"(x[3]));
-}
-
 // Register-resident FP64 factorisations for N_t <= 128 (work-group of 256 threads).
 //
-// Ownership: thread (wave w, lane l, g = l/16) holds the 16x16 sub-block rows I in {w, 7-w}
-// (so every wave gets the same share of the lower triangle) and, in sub-block (I, J), J <= I,
-// the four accumulator-order elements (16I + 4g + r, 16J + l%16), r = 0..3 -- the same order
-// R is stored in, so a diagonal block is loaded with one vector access per sub-block.
-//
-// One block column JB (16 columns) of the register-resident Cholesky.  JB is a compile-time
-// constant, so the owners' register A[h][JB] and the column masks need no run-time selection.
-template <int JB>
-__device__ __forceinline__ bool chol_block(double (&A)[2][8][4], int N_t, int nbr, double *colbuf, double *piv,
-                                           double *Lout)
-{
-    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6, g = lane >> 4, l16 = lane & 15;
-    const int jend = min(16, N_t - 16 * JB);
-    for (int jl = 0; jl < jend; ++jl) {
-        const int j = 16 * JB + jl;
-        double *buf = colbuf + ((j & 1) << 7);
-        if (l16 == jl) {
-#pragma unroll
-            for (int h = 0; h < 2; ++h) {
-                const int I = h ? 7 - w : w;
-                if (I < nbr && I >= JB) {
-#pragma unroll
-                    for (int r = 0; r < 4; ++r) buf[16 * I + 4 * g + r] = A[h][JB][r];
-                }
-            }
-        }
-        __syncthreads();
-        // every LDS read of the step is issued before the first use (one wait)
-        double bu[8], bt[2][4], dv[4];
-#pragma unroll
-        for (int J = 0; J < 8; ++J) bu[J] = buf[16 * J + l16];
-#pragma unroll
-        for (int h = 0; h < 2; ++h) {
-            const int I = h ? 7 - w : w;
-#pragma unroll
-            for (int r = 0; r < 4; ++r) bt[h][r] = buf[16 * I + 4 * g + r];
-        }
-        dv[0] = buf[j];
-        dv[1] = dv[2] = dv[3] = 0.0;
-        pin8(bu);
-        pin4(bt[0]);
-        pin4(bt[1]);
-        pin4(dv);
-        const double d = dv[0];
-        if (!(d > 0.0) || !isfinite(d)) return false;
-        if (tid == 0) piv[j] = d;
-        if (Lout) {
-            const double l = sqrt(d), il = 1.0 / l;
-            for (int t = j + tid; t < N_t; t += blockDim.x) Lout[tri(t) + j] = t == j ? l : buf[t] * il;
-        }
-        const double inv_d = 1.0 / d;
-#pragma unroll
-        for (int h = 0; h < 2; ++h) {
-            const int I = h ? 7 - w : w;
-            if (I < nbr && I >= JB) {
-                double wt[4];
-#pragma unroll
-                for (int r = 0; r < 4; ++r) wt[r] = 16 * I + 4 * g + r > j ? bt[h][r] * inv_d : 0.0;
-                // sub-blocks left of column j are final; above the diagonal (J > I) au = 0
-#pragma unroll
-                for (int J = JB; J < 8; ++J) {
-                    const double au = (16 * J + l16 > j && J <= I) ? bu[J] : 0.0;
-#pragma unroll
-                    for (int r = 0; r < 4; ++r) A[h][J][r] = fma(-wt[r], au, A[h][J][r]);
-                }
-            }
-        }
-    }
-    return true;
-}
-
-// Right-looking Cholesky, one barrier per column j: the owners of column j publish it
-// (unscaled, a_t = A[t][j]) in a double-buffered LDS vector; every thread then reads the pivot
-// d = a_j and applies A[t][u] -= a_t a_u / d to the elements it owns with t, u > j.  The
-// pivots are kept; sum_t ln L_tt = 1/2 sum_j ln d_j.  With Lout, L is also written (packed).
 // Product P_I P_J^T of sub-block rows I and J of one candidate's held W block (the W of an
 // earlier pick that R does not include yet), over its first nk 16-wide inner blocks (the rest
 // is padding, zero), in the 16x16 accumulator order of R: element (4g + r, l % 16) of lane l,
@@ -222,83 +135,8 @@ struct HeldProd<unsigned short> {
     }
 };
 
-// With held W blocks (slots 0 .. nheld-1 of d.W, candidate offset pofs) the factored matrix is
-// R_jj - sum_h P_h,j P_h,j^T, the candidate's current Schur block.
-template <typename TR, typename TW>
-__device__ __forceinline__ void load_block(double (&A)[2][8][4], const TR *__restrict__ Rb, int N_t, int nb,
-                                           const StepDesc &d, int64_t pofs)
-{
-    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-    const int nbr = (N_t + 15) >> 4;
-#pragma unroll
-    for (int h = 0; h < 2; ++h) {
-        const int I = h ? 7 - w : w;
-#pragma unroll
-        for (int J = 0; J < 8; ++J) {
-            if (I < nbr && J <= I) {
-                const typename V4<TR>::type v = ld4(Rb + ((I * nb + J) << 8) + lane * 4);
-#pragma unroll
-                for (int r = 0; r < 4; ++r) A[h][J][r] = (double)v[r];
-            } else {
-#pragma unroll
-                for (int r = 0; r < 4; ++r) A[h][J][r] = 0.0;
-            }
-        }
-    }
-    for (int hp = 0; hp < d.nheld; ++hp) {
-        const TW *P = (const TW *)d.W + hp * d.wslot + pofs;
-        const TW *P2 = d.W2 ? (const TW *)d.W2 + hp * d.wslot + pofs : nullptr;
-#pragma unroll
-        for (int h = 0; h < 2; ++h) {
-            const int I = h ? 7 - w : w;
-#pragma unroll
-            for (int J = 0; J < 8; ++J)
-                if (I < nbr && J <= I) {
-                    const auto c = HeldProd<TW>::run(P, P2, I, J, nb, nbr, lane);
-#pragma unroll
-                    for (int r = 0; r < 4; ++r) A[h][J][r] -= (double)c[r];
-                }
-        }
-    }
-    if (d.wb && d.nheld > 0) {
-        // left-looking: the diagonal block is kept current in place
-        TR *Rw = const_cast<TR *>(Rb);
-#pragma unroll
-        for (int h = 0; h < 2; ++h) {
-            const int I = h ? 7 - w : w;
-#pragma unroll
-            for (int J = 0; J < 8; ++J)
-                if (I < nbr && J <= I) {
-                    typename V4<TR>::type v;
-#pragma unroll
-                    for (int r = 0; r < 4; ++r) v[r] = (TR)A[h][J][r];
-                    st4(Rw + ((I * nb + J) << 8) + lane * 4, v);
-                }
-        }
-    }
-}
-
-template <typename TR, typename TW>
-__device__ __forceinline__ bool chol_regs(const TR *__restrict__ Rb, int N_t, int nb, double *colbuf, double *piv,
-                                          double *Lout, const StepDesc &d, int64_t pofs)
-{
-    const int nbr = (N_t + 15) >> 4;
-    double A[2][8][4];
-    load_block<TR, TW>(A, Rb, N_t, nb, d, pofs);
-    bool ok = chol_block<0>(A, N_t, nbr, colbuf, piv, Lout);
-    if (ok && nbr > 1) ok = chol_block<1>(A, N_t, nbr, colbuf, piv, Lout);
-    if (ok && nbr > 2) ok = chol_block<2>(A, N_t, nbr, colbuf, piv, Lout);
-    if (ok && nbr > 3) ok = chol_block<3>(A, N_t, nbr, colbuf, piv, Lout);
-    if (ok && nbr > 4) ok = chol_block<4>(A, N_t, nbr, colbuf, piv, Lout);
-    if (ok && nbr > 5) ok = chol_block<5>(A, N_t, nbr, colbuf, piv, Lout);
-    if (ok && nbr > 6) ok = chol_block<6>(A, N_t, nbr, colbuf, piv, Lout);
-    if (ok && nbr > 7) ok = chol_block<7>(A, N_t, nbr, colbuf, piv, Lout);
-    __syncthreads();
-    return ok;
-}
-
 // ---------------------------------------------------------------------------------------------
-// Blocked register Cholesky on FP64 MFMA for N_t <= 128 (the gain kernel).  Upper form:
+// Blocked register Cholesky on FP64 MFMA for N_t <= 128 (gains and picks).  Upper form:
 // A = U^T U, block by block, with A held as its upper 16x16 blocks (I, C), I <= C, in the
 // accumulator order (lane l, g = l/16 holds elements (4g + r, l % 16), r = 0..3).  Wave w
 // owns block columns C in {w, 7 - w}.  Step p:
@@ -427,7 +265,8 @@ __device__ __forceinline__ void load_upper(UBlocks &A, const TR *__restrict__ Rb
 // Step p of the blocked factorisation (p is a compile-time constant, so that every register
 // block is addressed statically).  Returns false (uniformly) at a failed pivot.
 template <int p>
-__device__ __forceinline__ bool chol_mfma_step(UBlocks &A, int nbr, double *piv, doublex4 (*Ls)[8][64], int *sfail)
+__device__ __forceinline__ bool chol_mfma_step(UBlocks &A, int nbr, double *piv, doublex4 (*Ls)[8][64], int *sfail,
+                                               doublex4 (*Ysave)[64])
 {
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     const int al = a_lane<double>(lane);
@@ -440,6 +279,7 @@ __device__ __forceinline__ bool chol_mfma_step(UBlocks &A, int nbr, double *piv,
     }
     __syncthreads();
     if (sfail[buf]) return false;
+    if (Ysave && (hp ? C1 : C0) == p) Ysave[p][lane] = Ls[buf][p][lane];
     // (b) U_pC = U_pp^-T A_pC for the owned columns C > p
     const doublex4 y = Ls[buf][p][al];
 #pragma unroll
@@ -471,162 +311,112 @@ __device__ __forceinline__ bool chol_mfma_step(UBlocks &A, int nbr, double *piv,
     return true;
 }
 
-// The blocked factorisation; pivots d_j go to piv[0 .. 16 nbr).  Returns false (uniformly) at
-// a pivot that is not > 0 or not finite.
+// The blocked factorisation of the register blocks A (loaded by load_upper); pivots d_j go to
+// piv[0 .. 16 nbr), and with Ysave (LDS, 8 blocks) U_pp^-1 of every diagonal block is kept.
+// On return A holds the off-diagonal blocks U_IC, I < C, of U.  Returns false (uniformly) at a
+// pivot that is not > 0 or not finite.
+__device__ __forceinline__ bool chol_mfma_regs(UBlocks &A, int nbr, double *piv, doublex4 (*Ysave)[64])
+{
+    __shared__ doublex4 Ls[2][8][64];  // [step parity][block column][lane]
+    __shared__ int sfail[2];
+    if (!chol_mfma_step<0>(A, nbr, piv, Ls, sfail, Ysave)) return false;
+    if (nbr > 1 && !chol_mfma_step<1>(A, nbr, piv, Ls, sfail, Ysave)) return false;
+    if (nbr > 2 && !chol_mfma_step<2>(A, nbr, piv, Ls, sfail, Ysave)) return false;
+    if (nbr > 3 && !chol_mfma_step<3>(A, nbr, piv, Ls, sfail, Ysave)) return false;
+    if (nbr > 4 && !chol_mfma_step<4>(A, nbr, piv, Ls, sfail, Ysave)) return false;
+    if (nbr > 5 && !chol_mfma_step<5>(A, nbr, piv, Ls, sfail, Ysave)) return false;
+    if (nbr > 6 && !chol_mfma_step<6>(A, nbr, piv, Ls, sfail, Ysave)) return false;
+    if (nbr > 7 && !chol_mfma_step<7>(A, nbr, piv, Ls, sfail, Ysave)) return false;
+    return true;
+}
+
+// The gain kernel's factorisation: pivots only.
 template <typename TR, typename TW>
 __device__ __forceinline__ bool chol_mfma(const TR *__restrict__ Rb, int N_t, int nb, double *piv, const StepDesc &d,
                                           int64_t pofs)
 {
-    __shared__ doublex4 Ls[2][8][64];  // [step parity][block column][lane]
-    __shared__ int sfail[2];
     const int nbr = (N_t + 15) >> 4;
     UBlocks A;
     load_upper<TR, TW>(A, Rb, nbr, nb, d, pofs);
-    if (!chol_mfma_step<0>(A, nbr, piv, Ls, sfail)) return false;
-    if (nbr > 1 && !chol_mfma_step<1>(A, nbr, piv, Ls, sfail)) return false;
-    if (nbr > 2 && !chol_mfma_step<2>(A, nbr, piv, Ls, sfail)) return false;
-    if (nbr > 3 && !chol_mfma_step<3>(A, nbr, piv, Ls, sfail)) return false;
-    if (nbr > 4 && !chol_mfma_step<4>(A, nbr, piv, Ls, sfail)) return false;
-    if (nbr > 5 && !chol_mfma_step<5>(A, nbr, piv, Ls, sfail)) return false;
-    if (nbr > 6 && !chol_mfma_step<6>(A, nbr, piv, Ls, sfail)) return false;
-    if (nbr > 7 && !chol_mfma_step<7>(A, nbr, piv, Ls, sfail)) return false;
-    return true;
+    return chol_mfma_regs(A, nbr, piv, nullptr);
 }
 
-// One block column JB of the factorisation with the inverse carried along: the elimination of
-// column j (row t -= (a_tj / d_j) row j, t > j) is applied to X, which starts as the identity,
-// with the same multipliers; row j of X is final at step j, so its owners publish it together
-// with column j of A and one barrier serves both.  At the end X = Lu^-1 for A = Lu D Lu^T (Lu unit
-// lower), and L^-1 = D^-1/2 X.
-template <int JB>
-__device__ __forceinline__ bool cholinv_block(double (&A)[2][8][4], double (&X)[2][8][4], int N_t, int nbr,
-                                              double *colbuf, double *rowbuf, double *piv)
+// The pick's factor and inverse for N_t <= 128: the register factorisation above (keeping every
+// U_pp^-1), the off-diagonal blocks of U published to LDS, then Z = L^-1 = U^-T by block columns
+// in registers (wave w: columns w and 7 - w), Z_qq = (U_qq^-1)^T and down the column
+// Z_pq = -(U_pp^-1)^T sum_{r = q}^{p-1} U_rp^T Z_rq, and Z written to Linv in the operand order.
+// Blocks of Linv outside the factored part: zero above the diagonal, identity on the padding.
+template <typename TR, typename TW>
+__device__ __forceinline__ bool chol_inv_mfma(const TR *__restrict__ Rb, int N_t, int N_tp, double *piv,
+                                              const StepDesc &d, int64_t pofs, double *__restrict__ Linv)
 {
-    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6, g = lane >> 4, l16 = lane & 15;
-    const int jend = min(16, N_t - 16 * JB);
-    for (int jl = 0; jl < jend; ++jl) {
-        const int j = 16 * JB + jl;
-        double *buf = colbuf + ((j & 1) << 7);
-        double *rb = rowbuf + ((j & 1) << 9);
+    __shared__ doublex4 Y[8][64];    // U_pp^-1
+    __shared__ doublex4 Uo[28][64];  // U_rp, r < p, at p (p - 1) / 2 + r
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6, g = lane >> 4, c = lane & 15;
+    const int al = a_lane<double>(lane);
+    const int nbr = (N_t + 15) >> 4, nb = N_tp >> 4;
+    {
+        UBlocks A;
+        load_upper<TR, TW>(A, Rb, nbr, nb, d, pofs);
+        if (!chol_mfma_regs(A, nbr, piv, Y)) return false;
 #pragma unroll
         for (int h = 0; h < 2; ++h) {
-            const int I = h ? 7 - w : w;
-            if (l16 == jl && I < nbr && I >= JB) {
+            const int C = h ? 7 - w : w;
 #pragma unroll
-                for (int r = 0; r < 4; ++r) buf[16 * I + 4 * g + r] = A[h][JB][r];
-            }
-            // the owners of row j (group jl / 4 of block row JB) publish all four of their rows
-            if (g == (jl >> 2) && I == JB) {
-#pragma unroll
-                for (int J = 0; J <= JB; ++J)
-#pragma unroll
-                    for (int r = 0; r < 4; ++r) rb[(r << 7) + 16 * J + l16] = X[h][J][r];
-            }
-        }
-        __syncthreads();
-        const double *rj = rb + ((j & 3) << 7);
-        double bu[8], bt[2][4], dv[4], xv[8];
-#pragma unroll
-        for (int J = 0; J < 8; ++J) bu[J] = buf[16 * J + l16];
-#pragma unroll
-        for (int J = 0; J < 8; ++J) xv[J] = J <= JB ? rj[16 * J + l16] : 0.0;
-#pragma unroll
-        for (int h = 0; h < 2; ++h) {
-            const int I = h ? 7 - w : w;
-#pragma unroll
-            for (int r = 0; r < 4; ++r) bt[h][r] = buf[16 * I + 4 * g + r];
-        }
-        dv[0] = buf[j];
-        dv[1] = dv[2] = dv[3] = 0.0;
-        pin8(bu);
-        pin8(xv);
-        pin4(bt[0]);
-        pin4(bt[1]);
-        pin4(dv);
-        const double dd = dv[0];
-        if (!(dd > 0.0) || !isfinite(dd)) return false;
-        if (tid == 0) piv[j] = dd;
-        const double inv_d = 1.0 / dd;
-#pragma unroll
-        for (int h = 0; h < 2; ++h) {
-            const int I = h ? 7 - w : w;
-            if (I < nbr && I >= JB) {
-                double wt[4];
-#pragma unroll
-                for (int r = 0; r < 4; ++r) wt[r] = 16 * I + 4 * g + r > j ? bt[h][r] * inv_d : 0.0;
-#pragma unroll
-                for (int J = JB; J < 8; ++J) {
-                    const double au = (16 * J + l16 > j && J <= I) ? bu[J] : 0.0;
-#pragma unroll
-                    for (int r = 0; r < 4; ++r) A[h][J][r] = fma(-wt[r], au, A[h][J][r]);
-                }
-#pragma unroll
-                for (int J = 0; J <= JB; ++J)
-#pragma unroll
-                    for (int r = 0; r < 4; ++r) X[h][J][r] = fma(-wt[r], xv[J], X[h][J][r]);
-            }
+            for (int I = 0; I < (h ? 8 : 4); ++I)
+                if (I < C && C < nbr) Uo[C * (C - 1) / 2 + I][lane] = ub(A, h, I);
         }
     }
-    return true;
-}
-
-// Factor the diagonal block (with the held correction, as chol_regs) and write L^-1 in operand
-// order (N_tp x N_tp, identity on the padding) to Linv.  rowbuf: LDS, 2 x 4 x 128 doubles.
-template <typename TR, typename TW>
-__device__ __forceinline__ bool chol_inv_regs(const TR *__restrict__ Rb, int N_t, int N_tp, double *colbuf,
-                                              double *rowbuf, double *piv, const StepDesc &d, int64_t pofs,
-                                              double *__restrict__ Linv)
-{
-    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6, g = lane >> 4, l16 = lane & 15;
-    const int nbr = (N_t + 15) >> 4, nb = N_tp >> 4;
-    double A[2][8][4], X[2][8][4];
-    load_block<TR, TW>(A, Rb, N_t, nb, d, pofs);
+    __syncthreads();
+    // element (4g + r, c) of a block's transpose sits at tofs + 4r of the block (accumulator order)
+    const int tofs = ((((c >> 2) << 4) + 4 * g) << 2) + (c & 3);
+    // Z column q0 = w keeps blocks P = 0..7 (those with P >= q0 used), q1 = 7 - w blocks P = 4..7
+    doublex4 z0[8], z1[4];
+    auto zb = [&](int h, int P) -> doublex4 & { return h ? z1[(P - 4) & 3] : z0[P & 7]; };
 #pragma unroll
     for (int h = 0; h < 2; ++h) {
-        const int I = h ? 7 - w : w;
+        const int q = h ? 7 - w : w;
+        if (q >= nbr) continue;
+        // Z_qq = (U_qq^-1)^T: the transpose of Y_q, read through LDS
+        const double *Yq = (const double *)Y[q];
+        doublex4 t;
 #pragma unroll
-        for (int J = 0; J < 8; ++J)
+        for (int r = 0; r < 4; ++r) t[r] = Yq[tofs + 4 * r];
 #pragma unroll
-            for (int r = 0; r < 4; ++r) X[h][J][r] = (J == I && 4 * g + r == l16) ? 1.0 : 0.0;
+        for (int P = (h ? 4 : 0); P < 8; ++P)
+            if (P == q) zb(h, P) = t;
+#pragma unroll
+        for (int P = (h ? 4 : 0); P < 8; ++P) {
+            if (P <= q || P >= nbr) continue;
+            doublex4 acc{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+            for (int r = (h ? 4 : 0); r < 8; ++r) {
+                if (r < q || r >= P) continue;
+                const doublex4 u = Uo[P * (P - 1) / 2 + r][al];
+#pragma unroll
+                for (int s4 = 0; s4 < 4; ++s4) acc = mfma16(u[s4], zb(h, r)[s4], acc);
+            }
+            const doublex4 y = Y[P][al];
+            doublex4 z{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+            for (int s4 = 0; s4 < 4; ++s4) z = mfma16(-y[s4], acc[s4], z);
+            zb(h, P) = z;
+        }
+        // Z_Pq to Linv: element (16P + 4g + r, 16q + c) in the operand order
+#pragma unroll
+        for (int P = (h ? 4 : 0); P < 8; ++P) {
+            if (P < q || P >= nbr) continue;
+            double *dst = Linv + ((P * nb + q) << 8) + tofs;
+#pragma unroll
+            for (int r = 0; r < 4; ++r) dst[4 * r] = zb(h, P)[r];
+        }
     }
-    bool ok = cholinv_block<0>(A, X, N_t, nbr, colbuf, rowbuf, piv);
-    if (ok && nbr > 1) ok = cholinv_block<1>(A, X, N_t, nbr, colbuf, rowbuf, piv);
-    if (ok && nbr > 2) ok = cholinv_block<2>(A, X, N_t, nbr, colbuf, rowbuf, piv);
-    if (ok && nbr > 3) ok = cholinv_block<3>(A, X, N_t, nbr, colbuf, rowbuf, piv);
-    if (ok && nbr > 4) ok = cholinv_block<4>(A, X, N_t, nbr, colbuf, rowbuf, piv);
-    if (ok && nbr > 5) ok = cholinv_block<5>(A, X, N_t, nbr, colbuf, rowbuf, piv);
-    if (ok && nbr > 6) ok = cholinv_block<6>(A, X, N_t, nbr, colbuf, rowbuf, piv);
-    if (ok && nbr > 7) ok = cholinv_block<7>(A, X, N_t, nbr, colbuf, rowbuf, piv);
-    __syncthreads();
-    if (!ok) return false;
-    // sub-blocks outside the factored part: zero above the diagonal, identity on the padding
     for (int o = tid; o < N_tp * N_tp; o += blockDim.x) {
         const int sb = o >> 8, ww = o & 255, ln = ww >> 2, reg = ww & 3;
         const int I = sb / nb, J = sb % nb;
         if (I >= nbr || J >= nbr || J > I) {
             const int k = I * 16 + (ln & 15), kp = J * 16 + ((ln >> 4) << 2) + reg;
             Linv[o] = k == kp ? 1.0 : 0.0;
-        }
-    }
-#pragma unroll
-    for (int h = 0; h < 2; ++h) {
-        const int I = h ? 7 - w : w;
-        if (I < nbr) {
-            double il[4];
-#pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                const int t = 16 * I + 4 * g + r;
-                il[r] = t < N_t ? 1.0 / sqrt(piv[t]) : 1.0;
-            }
-#pragma unroll
-            for (int J = 0; J < 8; ++J)
-                if (J <= I) {
-#pragma unroll
-                    for (int r = 0; r < 4; ++r) {
-                        const int t = 4 * g + r, c = l16;  // row / column inside sub-block (I, J)
-                        Linv[((I * nb + J) << 8) + ((((c >> 2) << 4) + t) << 2) + (c & 3)] = X[h][J][r] * il[r];
-                    }
-                }
         }
     }
     return true;
@@ -728,8 +518,6 @@ __device__ void gain_regs_body(const StepDesc &d, int p)
 template <typename TR, typename TW>
 __device__ void pick_regs_body(const StepDesc &d)
 {
-    __shared__ double colbuf[256];
-    __shared__ double rowbuf[1024];
     __shared__ double piv[128];
     __shared__ double red[4];
     if (d.state[ST_STATUS] != 0) return;
@@ -740,8 +528,8 @@ __device__ void pick_regs_body(const StepDesc &d)
     const int s = d.act_in[pos];
     for (int p = tid; p < d.n_act - 1; p += blockDim.x) d.act_out[p] = d.act_in[p < pos ? p : p + 1];
     const int64_t bs = (int64_t)d.N_tp * d.N_tp;
-    const bool ok = chol_inv_regs<TR, TW>((const TR *)d.R + blk_index(s, s) * bs, d.N_t, d.N_tp, colbuf, rowbuf, piv, d,
-                                          s * bs, d.Linv);
+    const bool ok = chol_inv_mfma<TR, TW>((const TR *)d.R + blk_index(s, s) * bs, d.N_t, d.N_tp, piv, d, s * bs,
+                                          d.Linv);
     if (!ok) {
         if (tid == 0) d.state[ST_STATUS] = 2;
         return;
