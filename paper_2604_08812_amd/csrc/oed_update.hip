@@ -192,6 +192,114 @@ __device__ void trsm_body(const StepDesc &d, int p)
     }
 }
 
+// The block column for N_tp = 16 NB <= 128 (single launches): as trsm_body with the slice loops
+// unrolled and both sub-block rows of a wave (w and w + 4) carried together, so that every
+// L_s^-1 (or V_h) block loaded from L2 feeds the MFMAs of both rows and the loads of later
+// slices are issued ahead of the current slice's MFMAs.
+template <typename TR, typename TW, int NB>
+__device__ void trsm_nb_body(const StepDesc &d, int p)
+{
+    if (d.state[ST_STATUS] != 0 || p >= d.n_act) return;
+    constexpr int nb = NB;
+    constexpr int64_t bs = 256 * NB * NB;
+    const TR *__restrict__ R = (const TR *)d.R;
+    const double *__restrict__ Linv = d.Linv;
+    const int i = d.act_in[p], s = d.state[ST_LAST];
+    const int lane = threadIdx.x & 63, g = lane >> 4, l16 = lane & 15;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int alane = a_lane<double>(lane);
+    const bool below = i > s;
+    const TR *Cb = R + blk_index(below ? i : s, below ? s : i) * bs;
+    TW *Wi = (TW *)d.W + d.nheld * d.wslot + (int64_t)i * bs;  // slot nheld
+    TW *Wi2 = (TW *)d.W2 + d.nheld * d.wslot + (int64_t)i * bs;
+    bool has[2];
+    int tb[2];
+#pragma unroll
+    for (int rr = 0; rr < 2; ++rr) {
+        tb[rr] = wave + 4 * rr;
+        has[rr] = tb[rr] < nb;
+    }
+    if (!has[0]) return;
+    doublex4 acc[2][NB];
+#pragma unroll
+    for (int rr = 0; rr < 2; ++rr)
+#pragma unroll
+        for (int c = 0; c < NB; ++c) acc[rr][c] = doublex4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int q = 0; q < NB; ++q) {
+        double b[2][4];
+#pragma unroll
+        for (int rr = 0; rr < 2; ++rr) {
+            if (!has[rr]) continue;
+            const int t = 16 * tb[rr] + l16;
+            if (below) {
+#pragma unroll
+                for (int s4 = 0; s4 < 4; ++s4) b[rr][s4] = (double)Cb[acc_off(t, 16 * q + 4 * g + s4, nb)];
+            } else {
+                const typename V4<TR>::type v = ld4(Cb + acc_off(16 * q + 4 * g, 16 * tb[rr] + l16, nb));
+#pragma unroll
+                for (int s4 = 0; s4 < 4; ++s4) b[rr][s4] = (double)v[s4];
+            }
+            // left-looking: C_i = K_is - sum_h W_h,i W_h,s^T, the sum in nsplit partials
+            for (int sp = 0; sp < d.nsplit; ++sp) {
+                const TR *Cp = (const TR *)d.C + sp * d.cstride + (int64_t)i * bs;
+#pragma unroll
+                for (int s4 = 0; s4 < 4; ++s4) b[rr][s4] -= (double)Cp[acc_off(t, 16 * q + 4 * g + s4, nb)];
+            }
+        }
+#pragma unroll
+        for (int c = q; c < NB; ++c) {
+            const doublex4 a = ld4(Linv + ((c * nb + q) << 8) + alane * 4);
+#pragma unroll
+            for (int rr = 0; rr < 2; ++rr)
+                if (has[rr]) {
+#pragma unroll
+                    for (int s4 = 0; s4 < 4; ++s4) acc[rr][c] = mfma16(a[s4], b[rr][s4], acc[rr][c]);
+                }
+        }
+    }
+    const int nbr = (d.N_t + 15) >> 4;
+    for (int hp = 0; hp < d.nheld; ++hp) {
+        // - P_h,i V_h^T: inner index over the held pick's block, V_h in L_s^-1's order
+        const TW *Pi = (const TW *)d.W + hp * d.wslot + (int64_t)i * bs;
+        const TW *Pi2 = d.W2 ? (const TW *)d.W2 + hp * d.wslot + (int64_t)i * bs : nullptr;
+        const double *Vh = d.V + hp * bs;
+#pragma unroll
+        for (int q = 0; q < NB; ++q) {
+            if (q >= nbr) break;
+            double b[2][4];
+#pragma unroll
+            for (int rr = 0; rr < 2; ++rr) {
+                if (!has[rr]) continue;
+                w_row4<TW>(Pi, Pi2, tb[rr], q, nb, lane, b[rr]);
+#pragma unroll
+                for (int s4 = 0; s4 < 4; ++s4) b[rr][s4] = -b[rr][s4];
+            }
+#pragma unroll
+            for (int c = 0; c < NB; ++c) {
+                const doublex4 a = ld4(Vh + ((c * nb + q) << 8) + alane * 4);
+#pragma unroll
+                for (int rr = 0; rr < 2; ++rr)
+                    if (has[rr]) {
+#pragma unroll
+                        for (int s4 = 0; s4 < 4; ++s4) acc[rr][c] = mfma16(a[s4], b[rr][s4], acc[rr][c]);
+                    }
+            }
+        }
+    }
+#pragma unroll
+    for (int rr = 0; rr < 2; ++rr)
+        if (has[rr]) {
+#pragma unroll
+            for (int c = 0; c < NB; ++c) {
+                if constexpr (sizeof(TW) == 2)
+                    store_w_bf16(Wi, Wi2, tb[rr], c, nb >> 1, lane, acc[rr][c]);
+                else
+                    store_w(Wi, ((int64_t)(tb[rr] * nb + c) << 8) + lane * 4, acc[rr][c]);
+            }
+        }
+}
+
 // ---------------------------------------------------------------------------------------------
 // Downdate R_IJ -= W_I W_J^T over 128 x 128 tiles of the remaining rows, lower triangle only.
 // Four waves per tile, each a 64 x 64 quarter = 4 x 4 MFMA 16x16 blocks.  Tiles are handed
@@ -968,6 +1076,12 @@ __global__ void __launch_bounds__(256) trsm_kernel(StepDesc d)
     trsm_body<TR, TW>(d, blockIdx.x);
 }
 
+template <typename TR, typename TW, int NB>
+__global__ void __launch_bounds__(256, 2) trsm_nb_kernel(StepDesc d)
+{
+    trsm_nb_body<TR, TW, NB>(d, blockIdx.x);
+}
+
 template <typename TR, typename TW>
 __global__ void __launch_bounds__(256) trsm_batched(const StepDesc *__restrict__ ds, int n)
 {
@@ -1115,6 +1229,24 @@ __global__ void __launch_bounds__(64) vcorr_batched(const StepDesc *__restrict__
 template <typename TR, typename TW>
 static hipError_t launch_trsm_t(const StepDesc *descs, const StepDesc &d, int n, int64_t total, hipStream_t s)
 {
+    if (!descs && d.N_tp <= 128) {
+        const dim3 grid((unsigned)total), block(256);
+        switch (d.N_tp / 16) {
+#define OED_TRSM_CASE(NBV) \
+    case NBV: hipLaunchKernelGGL((trsm_nb_kernel<TR, TW, NBV>), grid, block, 0, s, d); break;
+            OED_TRSM_CASE(1)
+            OED_TRSM_CASE(2)
+            OED_TRSM_CASE(3)
+            OED_TRSM_CASE(4)
+            OED_TRSM_CASE(5)
+            OED_TRSM_CASE(6)
+            OED_TRSM_CASE(7)
+            OED_TRSM_CASE(8)
+#undef OED_TRSM_CASE
+        default: return hipErrorInvalidValue;
+        }
+        return hipGetLastError();
+    }
     if (descs)
         hipLaunchKernelGGL((trsm_batched<TR, TW>), dim3((unsigned)total), dim3(256), 0, s, descs, n);
     else
