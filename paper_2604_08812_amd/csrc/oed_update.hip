@@ -535,17 +535,16 @@ __device__ void syrk_lds_body(const StepDesc &d, int64_t tile)
 }
 
 // ---------------------------------------------------------------------------------------------
-// Downdate for N_tp = 16 nb > 128 (runtime block size, nb > RT_TAIL): the LDS-staged,
-// double-buffered tile of syrk_lds_body with a runtime slice loop.  The last RT_TAIL slices of
-// the last W slot are unrolled so that the FP32 kernel streams the R tile in there, two blocks
-// per slice, behind the slice's W loads.
-constexpr int RT_TAIL = 8;
+// Downdate for N_tp = 16 nb > 128 (runtime block size): the LDS-staged, double-buffered tile of
+// syrk_lds_body with a run-time slice loop; R is read in the epilogue, as there (the K extent of
+// N_tp > 128 is long against the tile's R traffic, and the kernel then fits four work-groups
+// per CU, which cover each other's epilogues).
+constexpr int RT_MIN_NB = 9;
 
 template <typename T>
 __device__ void syrk_lds_rt_body(const StepDesc &d, int64_t tile)
 {
     typedef typename V4<T>::type vec;
-    constexpr bool PREFETCH_R = sizeof(T) == 4;
     __shared__ vec lds[2][2][8 * 64];  // [buffer][A/B][sub-block * 64 + lane]
     if (d.state[ST_STATUS] != 0) return;
     int64_t P, Q;
@@ -561,7 +560,7 @@ __device__ void syrk_lds_rt_body(const StepDesc &d, int64_t tile)
     const T *W0 = (const T *)d.W + lane * 4;
     const int64_t wslot = d.wslot;
 
-    vec rt[16], acc[16];
+    vec acc[16];
 #pragma unroll
     for (int f = 0; f < 16; ++f) acc[f] = vec{0, 0, 0, 0};
     vec sa[2], sbv[2];
@@ -603,35 +602,28 @@ __device__ void syrk_lds_rt_body(const StepDesc &d, int64_t tile)
         const T *cur = W0 + slot * wslot;
         const bool last = slot + 1 == nw;
         // slice q of a staged sub-block row sits 256 q elements after its slice 0
-        const int body = last ? nb - RT_TAIL : nb;
-        for (int q = 0; q < body; ++q) {
-            stage(q + 1 < nb ? cur + ((q + 1) << 8) : cur + wslot);
+        for (int q = 0; q < nb; ++q) {
+            const bool more = q + 1 < nb || !last;
+            if (more) stage(q + 1 < nb ? cur + ((q + 1) << 8) : cur + wslot);
             mma(buf);
-            put(buf ^ 1);
+            if (more) put(buf ^ 1);
             __syncthreads();
             buf ^= 1;
-        }
-        if (last) {
-#pragma unroll
-            for (int t = 0; t < RT_TAIL; ++t) {
-                const bool more = t + 1 < RT_TAIL;
-                if (more) stage(cur + ((nb - RT_TAIL + t + 1) << 8));
-                if (PREFETCH_R) {
-                    rt[2 * t] = ld4(Rl + m.rblk[2 * t]);
-                    rt[2 * t + 1] = ld4(Rl + m.rblk[2 * t + 1]);
-                }
-                mma(buf);
-                if (more) put(buf ^ 1);
-                __syncthreads();
-                buf ^= 1;
-            }
         }
     }
 
     if (!m.any) return;
+    // the tile's loads four at a time (more would cost the fourth work-group per CU in FP32)
+    constexpr int GR = 4;
 #pragma unroll
-    for (int f = 0; f < 16; ++f)
-        if (m.ok[f]) st4(Rl + m.rblk[f], (PREFETCH_R ? rt[f] : ld4(Rl + m.rblk[f])) - acc[f]);
+    for (int f0 = 0; f0 < 16; f0 += GR) {
+        vec rt[GR];
+#pragma unroll
+        for (int f = 0; f < GR; ++f) rt[f] = ld4(Rl + m.rblk[f0 + f]);
+#pragma unroll
+        for (int f = 0; f < GR; ++f)
+            if (m.ok[f0 + f]) st4(Rl + m.rblk[f0 + f], rt[f] - acc[f0 + f]);
+    }
 }
 
 // ---------------------------------------------------------------------------------------------
@@ -1112,7 +1104,7 @@ __global__ void __launch_bounds__(256) syrk_direct_batched(const StepDesc *__res
 }
 
 template <typename T>
-__global__ void __launch_bounds__(256, 2) syrk_lds_rt_kernel(StepDesc d, int64_t per_xcd)
+__global__ void __launch_bounds__(256, (sizeof(T) == 4 ? 3 : 2)) syrk_lds_rt_kernel(StepDesc d, int64_t per_xcd)
 {
     const int64_t tile = xcd_item(blockIdx.x, per_xcd);
     if (tile >= d.nitems) return;
@@ -1339,7 +1331,7 @@ static hipError_t launch_syrk_t(const StepDesc *descs, const StepDesc &d, int n,
         return hipGetLastError();
     }
     // single instances only: batches hold N_t <= 128
-    if (variant == SYRK_LDS && nb > RT_TAIL && !descs) {
+    if (variant == SYRK_LDS && nb >= RT_MIN_NB && !descs) {
         hipLaunchKernelGGL(syrk_lds_rt_kernel<T>, grid, block, 0, s, d, per_xcd);
         return hipGetLastError();
     }
