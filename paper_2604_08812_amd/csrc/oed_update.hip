@@ -1161,7 +1161,7 @@ __global__ void __launch_bounds__(256, 2) column_kernel(StepDesc d, int64_t per_
 
 // d.nitems here counts (split, row tile, column chunk) items
 template <typename T>
-__global__ void __launch_bounds__(256, 2) column_rt_kernel(StepDesc d, int64_t per_xcd)
+__global__ void __launch_bounds__(256, (sizeof(T) == 4 ? 4 : 2)) column_rt_kernel(StepDesc d, int64_t per_xcd)
 {
     const int64_t item = xcd_item(blockIdx.x, per_xcd);
     if (item >= d.nitems) return;
