@@ -76,6 +76,20 @@ __device__ __forceinline__ void st4(T *p, typename V4<T>::type v)
     *reinterpret_cast<typename V4<T>::type *>(p) = v;
 }
 
+// Streaming (non-temporal) vector access: the downdate reads and writes each block of R once per
+// launch, and marking those accesses streaming keeps them from evicting the W panels that the
+// tiles of an XCD share in its L2.
+template <typename T>
+__device__ __forceinline__ typename V4<T>::type ld4_stream(const T *p)
+{
+    return __builtin_nontemporal_load(reinterpret_cast<const typename V4<T>::type *>(p));
+}
+template <typename T>
+__device__ __forceinline__ void st4_stream(T *p, typename V4<T>::type v)
+{
+    __builtin_nontemporal_store(v, reinterpret_cast<typename V4<T>::type *>(p));
+}
+
 // Row of the packed lower triangle: element (t, u), u <= t, at tri(t) + u.
 __device__ __forceinline__ int tri(int t) { return t * (t + 1) / 2; }
 

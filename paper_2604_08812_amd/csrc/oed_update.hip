@@ -527,10 +527,10 @@ __device__ void syrk_lds_body(const StepDesc &d, int64_t tile)
     for (int f0 = 0; f0 < 16; f0 += GR) {
         vec rt[GR];
 #pragma unroll
-        for (int f = 0; f < GR; ++f) rt[f] = ld4(Rl + m.rblk[f0 + f]);
+        for (int f = 0; f < GR; ++f) rt[f] = ld4_stream(Rl + m.rblk[f0 + f]);
 #pragma unroll
         for (int f = 0; f < GR; ++f)
-            if (m.ok[f0 + f]) st4(Rl + m.rblk[f0 + f], rt[f] - acc[f0 + f]);
+            if (m.ok[f0 + f]) st4_stream(Rl + m.rblk[f0 + f], rt[f] - acc[f0 + f]);
     }
 }
 
@@ -619,10 +619,10 @@ __device__ void syrk_lds_rt_body(const StepDesc &d, int64_t tile)
     for (int f0 = 0; f0 < 16; f0 += GR) {
         vec rt[GR];
 #pragma unroll
-        for (int f = 0; f < GR; ++f) rt[f] = ld4(Rl + m.rblk[f0 + f]);
+        for (int f = 0; f < GR; ++f) rt[f] = ld4_stream(Rl + m.rblk[f0 + f]);
 #pragma unroll
         for (int f = 0; f < GR; ++f)
-            if (m.ok[f0 + f]) st4(Rl + m.rblk[f0 + f], rt[f] - acc[f0 + f]);
+            if (m.ok[f0 + f]) st4_stream(Rl + m.rblk[f0 + f], rt[f] - acc[f0 + f]);
     }
 }
 
@@ -687,7 +687,7 @@ __device__ void syrk_bf16_body(const StepDesc &d, int64_t tile)
             }
             if (PREF) {
 #pragma unroll
-                for (int f = q * PER; f < (q + 1) * PER && f < 16; ++f) rt[f] = ld4(Rl + m.rblk[f]);
+                for (int f = q * PER; f < (q + 1) * PER && f < 16; ++f) rt[f] = ld4_stream(Rl + m.rblk[f]);
             }
             if (m.any) {
                 u32x4 wh[4], wl[4];
@@ -725,7 +725,7 @@ __device__ void syrk_bf16_body(const StepDesc &d, int64_t tile)
     if (!m.any) return;
 #pragma unroll
     for (int f = 0; f < 16; ++f)
-        if (m.ok[f]) st4(Rl + m.rblk[f], rt[f] - acc[f]);
+        if (m.ok[f]) st4_stream(Rl + m.rblk[f], rt[f] - acc[f]);
 }
 
 // ---------------------------------------------------------------------------------------------
