@@ -81,6 +81,9 @@ typedef enum oed_precision {
 } oed_precision;
 
 /* oed_options.flags */
+/* Deepest downdate delay (oed_options.delay, OED_BATCH_DELAY). */
+#define OED_MAX_DELAY 8
+
 #define OED_FLAG_PROFILE 0x1u /* time every kernel with HIP events (see oed_get_profile) */
 #define OED_FLAG_AUTOTUNE 0x4u /* with delay 0: choose the delay depth and the downdate kernel by
                                   timing one step's kernels on the packed working copy (see
@@ -100,12 +103,13 @@ typedef struct oed_options {
     const int32_t *candidates;  /* host array of candidate sensors (the set C of Sec. III-A);
                                    NULL = all N_s sensors.  Copied during oed_create. */
     int32_t n_candidates;       /* length of candidates */
-    int32_t delay;              /* downdate delay depth p, 1..4: hold up to p - 1 picks' block
-                                   columns W and subtract them together with the next one (the
-                                   gain, pick and block-column steps correct for the held ones
-                                   exactly; same picks, 1/p of the R traffic per pick).
+    int32_t delay;              /* downdate delay depth p, 1..OED_MAX_DELAY: hold up to p - 1
+                                   picks' block columns W and subtract them together with the next
+                                   one (the gain, pick and block-column steps correct for the held
+                                   ones exactly; same picks, 1/p of the R traffic per pick).
                                    1 = subtract every pick's W W^T at the next step; 0 = automatic
-                                   (2 for N_t <= 128, else 1).  p > 1 with N_t > 128:
+                                   (with OED_FLAG_AUTOTUNE the autotuner's choice, else 4, for
+                                   N_t <= 128; 1 otherwise).  p > 1 with N_t > 128:
                                    OED_E_UNSUPPORTED */
     int32_t method;             /* OED_METHOD_RIGHT_LOOKING (default), _LEFT_LOOKING or _AUTO */
     int32_t max_budget;         /* left-looking: most picks the handle will make (the W history
@@ -254,7 +258,8 @@ typedef struct oed_batch oed_batch;
 
 /* Don't capture the schedule into a HIP graph: enqueue the launches on every run. */
 #define OED_BATCH_NO_GRAPH 0x2u
-/* Downdate delay depth p in 1..4 (see oed_options.delay); without it the depth is 4. */
+/* Downdate delay depth p in 1..OED_MAX_DELAY (see oed_options.delay); without it the depth is 4,
+   or the autotuner's choice with OED_BATCH_AUTOTUNE. */
 #define OED_BATCH_DELAY(p) ((uint32_t)(p) << 8)
 /* Without OED_BATCH_DELAY: run the whole selection once per delay depth during creation and
    keep the fastest (see oed_batch_get_config). */
@@ -290,7 +295,7 @@ OED_API oed_status oed_batch_reset(oed_batch *b, const oed_instance *inst, int32
 OED_API oed_status oed_batch_stats(const oed_batch *b, double *run_ms, double *syrk_flops, double *syrk_bytes);
 
 /* The delay depth the batch runs with, and with OED_BATCH_AUTOTUNE the autotuner's run time
-   for depths 1..4 (4 doubles, host; may be NULL). */
+   for depths 1..OED_MAX_DELAY (OED_MAX_DELAY doubles, host; may be NULL). */
 OED_API oed_status oed_batch_get_config(const oed_batch *b, int32_t *delay, double *per_run_ms);
 OED_API oed_status oed_batch_destroy(oed_batch *b);
 OED_API const char *oed_batch_last_error(const oed_batch *b);
@@ -349,11 +354,11 @@ OED_API const char *oed_eval_last_error(const oed_eval *e);
 OED_API oed_status oed_device_bytes(const oed_ctx *h, int64_t *bytes);
 
 /*
- * The configuration the handle runs with: *delay (1..4), *syrk_variant (0: per-wave global
- * operands, 1: LDS-staged, -1: left-looking, no downdate), and, if per_pick_ms is not NULL, the
- * autotuner's estimate of the
- * time per pick for delay depths 1..4 (4 doubles, host; 0 where not measured, all 0 without
- * OED_FLAG_AUTOTUNE).  Any output pointer may be NULL.
+ * The configuration the handle runs with: *delay (1..OED_MAX_DELAY), *syrk_variant (0: per-wave
+ * global operands, 1: LDS-staged, -1: left-looking, no downdate), and, if per_pick_ms is not
+ * NULL, the autotuner's estimate of the time per pick for delay depths 1..OED_MAX_DELAY
+ * (OED_MAX_DELAY doubles, host; 0 where not measured, all 0 without OED_FLAG_AUTOTUNE).  Any
+ * output pointer may be NULL.
  */
 OED_API oed_status oed_get_config(const oed_ctx *h, int32_t *delay, int32_t *syrk_variant, double *per_pick_ms);
 

@@ -585,7 +585,7 @@ oed_status oed_create(oed_ctx **out, const void *K, int32_t dtype, int64_t ld, i
     h->flags = o.flags;
     // delay 0 (automatic): hold block columns whenever the register factorisations and the LDS
     // downdate serve the block size
-    h->delay = o.delay == 0 ? (N_t <= REGS_MAX_NT ? MAX_DELAY : 1) : o.delay;
+    h->delay = o.delay == 0 ? (N_t <= REGS_MAX_NT ? DEFAULT_DELAY : 1) : o.delay;
     if (o.method == OED_METHOD_AUTO) {
         const int nc = o.candidates ? o.n_candidates : N_s;
         const int mb = o.max_budget > 0 ? std::min(o.max_budget, nc) : nc;

@@ -458,8 +458,10 @@ static oed_status create_batch(oed_batch **out, const oed_instance *inst, int32_
     b->left = (flags & OED_BATCH_LEFT_LOOKING) != 0;
     b->eval = eval;
     const bool tune = !b->left && b->delay == 0 && (flags & OED_BATCH_AUTOTUNE);
-    if (b->delay == 0) b->delay = MAX_DELAY;
+    if (b->delay == 0) b->delay = DEFAULT_DELAY;
     if (b->left) b->delay = 1;
+    // W slots and held-column buffers for the deepest delay the batch may run with
+    const int max_p = tune ? MAX_DELAY : b->delay;
     auto setup = [&]() -> oed_status {
         // the caller's K must be complete before the batch stream reads it
         BCHK(b, hipStreamSynchronize((hipStream_t)stream));
@@ -483,14 +485,14 @@ static oed_status create_batch(oed_batch **out, const oed_instance *inst, int32_
             const int64_t bs = (int64_t)x.N_tp * x.N_tp, nblk = (int64_t)x.N_s * (x.N_s + 1) / 2;
             BCHK(b, balloc(b, &x.R, (size_t)(nblk * bs) * er));
             x.wslot = x.N_s * bs;
-            const int slots = b->left ? x.budget : b->delay;
+            const int slots = b->left ? x.budget : max_p;
             if (b->wtype == W_BF16X3) {
                 BCHK(b, balloc(b, &x.W, (size_t)(slots * x.wslot) * 2));
                 BCHK(b, balloc(b, &x.W2, (size_t)(slots * x.wslot) * 2));
             } else {
                 BCHK(b, balloc(b, &x.W, (size_t)(slots * x.wslot) * er));
             }
-            if (b->delay > 1) BCHK(b, balloc(b, (void **)&x.V, sizeof(double) * bs * (b->delay - 1)));
+            if (max_p > 1) BCHK(b, balloc(b, (void **)&x.V, sizeof(double) * bs * (max_p - 1)));
             if (b->left) BCHK(b, balloc(b, &x.C, (size_t)(LEFT_SPLITS * x.N_s * bs) * er));
             BCHK(b, balloc(b, (void **)&x.Linv, sizeof(double) * bs));
             BCHK(b, balloc(b, (void **)&x.gains, sizeof(double) * x.N_s));
@@ -516,7 +518,7 @@ static oed_status create_batch(oed_batch **out, const oed_instance *inst, int32_
         }
         // descriptor array sized for the longest schedule (every delay depth the tuner may try)
         size_t ndesc = 1;
-        for (int p = tune ? 1 : b->delay; p <= b->delay; ++p) {
+        for (int p = tune ? 1 : b->delay; p <= max_p; ++p) {
             const int keep = b->delay;
             b->delay = p;
             build_schedule(b);
@@ -704,7 +706,7 @@ oed_status oed_eval_create(oed_eval **out, const void *K_dev, int32_t dtype, int
     if (nb == 0) {
         size_t fr = 0, tot = 0;
         if (hipMemGetInfo(&fr, &tot) != hipSuccess) return OED_E_HIP;
-        const size_t per = eval_inst_bytes(B, N_t, precision, delay ? delay : MAX_DELAY);
+        const size_t per = eval_inst_bytes(B, N_t, precision, delay ? delay : DEFAULT_DELAY);
         nb = (int)std::max<size_t>(1, std::min<size_t>(64, fr / 2 / per));
     }
     oed_eval *e = new (std::nothrow) oed_eval();

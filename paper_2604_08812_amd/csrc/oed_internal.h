@@ -61,8 +61,10 @@ enum StateWord { ST_STATUS = 0, ST_NPICKS = 1, ST_LAST = 2, ST_WORDS = 16 };
 // One instance at one phase of one greedy step: everything a kernel needs to know.  Single
 // launches pass it by value; batched launches pass a device array sorted by item0, and every
 // work-group finds its instance by binary search.
-// Largest downdate delay depth: up to MAX_DELAY - 1 block columns held back.
-constexpr int MAX_DELAY = 4;
+// Largest downdate delay depth: up to MAX_DELAY - 1 block columns held back; DEFAULT_DELAY is the
+// depth taken when none is given and the autotuner is not asked for.
+constexpr int MAX_DELAY = 8;  // OED_MAX_DELAY of the C ABI
+constexpr int DEFAULT_DELAY = 4;
 
 struct StepDesc {
     void *R;               // working copy (element type by precision)

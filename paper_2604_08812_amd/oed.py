@@ -22,6 +22,7 @@ PRECISIONS = {"fp64": 0, "mixed_f32": 1, "mixed_bf16x3": 2}
 OED_FLAG_PROFILE = 1
 OED_FLAG_AUTOTUNE = 4
 OED_FLAG_DEFER_PACK = 8
+OED_MAX_DELAY = 8
 KERNELS = ("gain", "pick", "trsm", "syrk", "pack")
 
 
@@ -150,7 +151,7 @@ def _stream_handle(stream):
 def oed_create(K, N_s, N_t, sigma2, precision="fp64", candidates=None, profile=False, stream=None, delay=0,
                autotune=False, method="right", max_budget=0, noise_half_logdet=None):
     """Create a handle for the device tensor K (2-D, float64/float32, row-major, lower triangle read).
-    delay: downdate delay depth (0 automatic, 1..4); autotune: with delay 0, time the choices;
+    delay: downdate delay depth (0 automatic, 1..OED_MAX_DELAY); autotune: with delay 0, time the choices;
     method: "right" (downdate of all of R per pick), "left" (only the new block column per pick) or
     "auto" (left when max_budget <= half the candidates);
     max_budget: left-looking W history size (0: all candidates); noise_half_logdet: per-sensor
@@ -266,9 +267,9 @@ def oed_device_bytes(h):
 
 
 def oed_get_config(h):
-    """(delay, syrk_variant, autotuner per-pick ms for delay 1..4)."""
+    """(delay, syrk_variant, autotuner per-pick ms for delay 1..OED_MAX_DELAY)."""
     dl, var = ctypes.c_int32(), ctypes.c_int32()
-    ms = np.zeros(4)
+    ms = np.zeros(OED_MAX_DELAY)
     _check(h, library().oed_get_config(h, ctypes.byref(dl), ctypes.byref(var), _dp(ms)))
     return dl.value, var.value, ms
 
@@ -339,9 +340,9 @@ def oed_batch_stats(b):
 
 
 def oed_batch_get_config(b):
-    """(delay, autotuner run ms for delay 1..4)."""
+    """(delay, autotuner run ms for delay 1..OED_MAX_DELAY)."""
     dl = ctypes.c_int32()
-    ms = np.zeros(4)
+    ms = np.zeros(OED_MAX_DELAY)
     _bcheck(b, library().oed_batch_get_config(b, ctypes.byref(dl), _dp(ms)))
     return dl.value, ms
 

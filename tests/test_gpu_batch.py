@@ -34,7 +34,7 @@ def items(insts, dtype=torch.float64):
     return [(Kd.to(dtype), N_s, N_t, s2, B) for (_, Kd, N_s, N_t, s2, B) in insts]
 
 
-@pytest.mark.parametrize("delay", [1, 2, 4])
+@pytest.mark.parametrize("delay", [1, 2, 4, 8])
 @pytest.mark.parametrize("prec", ["fp64", "mixed_f32", "mixed_bf16x3"])
 def test_batch_equals_single_and_oracle(insts, prec, delay):
     from paper_2604_08812_amd import BatchSelector, Selector

@@ -53,7 +53,7 @@ def supported(prec, N_t):
     return prec != "mixed_bf16x3" or N_t <= 128
 
 
-@pytest.mark.parametrize("delay", [1, 2, 4])
+@pytest.mark.parametrize("delay", [1, 2, 4, 8])
 @pytest.mark.parametrize("prec", PRECS)
 @pytest.mark.parametrize("case", CASES, ids=lambda c: "x".join(map(str, c[:2])))
 def test_greedy_matches_oracle(case, prec, delay):
