@@ -425,12 +425,16 @@ oed_status autotune(oed_ctx *h)
         for (int hh = 0; hh < p; ++hh) steps += t_step[hh];
         const double syrk = (p == 1) ? std::min(t_syrk[0], t_direct) : t_syrk[p - 1];
         v.ms[p - 1] = (syrk + steps) / p;
-        if (v.ms[p - 1] < best) {
-            best = v.ms[p - 1];
+        best = std::min(best, v.ms[p - 1]);
+    }
+    // the shallowest depth within 0.5% of the best estimate: the estimate takes the held-column
+    // corrections at the first step's size only, and a deeper delay gains less than it adds there
+    for (int p = 1; p <= MAX_DELAY; ++p)
+        if (v.ms[p - 1] <= 1.005 * best) {
             v.delay = p;
             v.variant = (p == 1 && t_direct < t_syrk[0]) ? SYRK_DIRECT : SYRK_LDS;
+            break;
         }
-    }
     h->delay = v.delay;
     h->syrk_variant = v.variant;
     std::copy(v.ms, v.ms + MAX_DELAY, h->tuned_ms);

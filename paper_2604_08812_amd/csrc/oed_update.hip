@@ -225,6 +225,81 @@ __device__ void trsm_nb_body(const StepDesc &d, int p)
     for (int rr = 0; rr < 2; ++rr)
 #pragma unroll
         for (int c = 0; c < NB; ++c) acc[rr][c] = doublex4{0.0, 0.0, 0.0, 0.0};
+    // - sum_h P_h,i V_h^T (held block columns).  Mixed paths: on the FP32 MFMA (P is FP32, or
+    // BF16 hi + lo, exact in FP32; V_h rounded to FP32) -- the precision the downdate itself
+    // would have subtracted these columns in -- accumulated separately and added in FP64.
+    const int nbr = (d.N_t + 15) >> 4;
+    if constexpr (sizeof(TR) == 4) {
+        floatx4 hacc[2][NB];
+#pragma unroll
+        for (int rr = 0; rr < 2; ++rr)
+#pragma unroll
+            for (int c = 0; c < NB; ++c) hacc[rr][c] = floatx4{0.f, 0.f, 0.f, 0.f};
+        for (int hp = 0; hp < d.nheld; ++hp) {
+            const TW *Pi = (const TW *)d.W + hp * d.wslot + (int64_t)i * bs;
+            const TW *Pi2 = d.W2 ? (const TW *)d.W2 + hp * d.wslot + (int64_t)i * bs : nullptr;
+            const double *Vh = d.V + hp * bs;
+#pragma unroll
+            for (int q = 0; q < NB; ++q) {
+                if (q >= nbr) break;
+                float b[2][4];
+#pragma unroll
+                for (int rr = 0; rr < 2; ++rr) {
+                    if (!has[rr]) continue;
+                    double v[4];
+                    w_row4<TW>(Pi, Pi2, tb[rr], q, nb, lane, v);
+#pragma unroll
+                    for (int s4 = 0; s4 < 4; ++s4) b[rr][s4] = (float)-v[s4];
+                }
+#pragma unroll
+                for (int c = 0; c < NB; ++c) {
+                    // the FP32 MFMA takes its A operand in the natural lane order
+                    const doublex4 a = ld4(Vh + ((c * nb + q) << 8) + lane * 4);
+#pragma unroll
+                    for (int rr = 0; rr < 2; ++rr)
+                        if (has[rr]) {
+#pragma unroll
+                            for (int s4 = 0; s4 < 4; ++s4) hacc[rr][c] = mfma16((float)a[s4], b[rr][s4], hacc[rr][c]);
+                        }
+                }
+            }
+        }
+#pragma unroll
+        for (int rr = 0; rr < 2; ++rr)
+#pragma unroll
+            for (int c = 0; c < NB; ++c)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) acc[rr][c][r] = (double)hacc[rr][c][r];
+    } else {
+        for (int hp = 0; hp < d.nheld; ++hp) {
+            // - P_h,i V_h^T: inner index over the held pick's block, V_h in L_s^-1's order
+            const TW *Pi = (const TW *)d.W + hp * d.wslot + (int64_t)i * bs;
+            const TW *Pi2 = d.W2 ? (const TW *)d.W2 + hp * d.wslot + (int64_t)i * bs : nullptr;
+            const double *Vh = d.V + hp * bs;
+#pragma unroll
+            for (int q = 0; q < NB; ++q) {
+                if (q >= nbr) break;
+                double b[2][4];
+#pragma unroll
+                for (int rr = 0; rr < 2; ++rr) {
+                    if (!has[rr]) continue;
+                    w_row4<TW>(Pi, Pi2, tb[rr], q, nb, lane, b[rr]);
+#pragma unroll
+                    for (int s4 = 0; s4 < 4; ++s4) b[rr][s4] = -b[rr][s4];
+                }
+#pragma unroll
+                for (int c = 0; c < NB; ++c) {
+                    const doublex4 a = ld4(Vh + ((c * nb + q) << 8) + alane * 4);
+#pragma unroll
+                    for (int rr = 0; rr < 2; ++rr)
+                        if (has[rr]) {
+#pragma unroll
+                            for (int s4 = 0; s4 < 4; ++s4) acc[rr][c] = mfma16(a[s4], b[rr][s4], acc[rr][c]);
+                        }
+                }
+            }
+        }
+    }
 #pragma unroll
     for (int q = 0; q < NB; ++q) {
         double b[2][4];
@@ -256,35 +331,6 @@ __device__ void trsm_nb_body(const StepDesc &d, int p)
 #pragma unroll
                     for (int s4 = 0; s4 < 4; ++s4) acc[rr][c] = mfma16(a[s4], b[rr][s4], acc[rr][c]);
                 }
-        }
-    }
-    const int nbr = (d.N_t + 15) >> 4;
-    for (int hp = 0; hp < d.nheld; ++hp) {
-        // - P_h,i V_h^T: inner index over the held pick's block, V_h in L_s^-1's order
-        const TW *Pi = (const TW *)d.W + hp * d.wslot + (int64_t)i * bs;
-        const TW *Pi2 = d.W2 ? (const TW *)d.W2 + hp * d.wslot + (int64_t)i * bs : nullptr;
-        const double *Vh = d.V + hp * bs;
-#pragma unroll
-        for (int q = 0; q < NB; ++q) {
-            if (q >= nbr) break;
-            double b[2][4];
-#pragma unroll
-            for (int rr = 0; rr < 2; ++rr) {
-                if (!has[rr]) continue;
-                w_row4<TW>(Pi, Pi2, tb[rr], q, nb, lane, b[rr]);
-#pragma unroll
-                for (int s4 = 0; s4 < 4; ++s4) b[rr][s4] = -b[rr][s4];
-            }
-#pragma unroll
-            for (int c = 0; c < NB; ++c) {
-                const doublex4 a = ld4(Vh + ((c * nb + q) << 8) + alane * 4);
-#pragma unroll
-                for (int rr = 0; rr < 2; ++rr)
-                    if (has[rr]) {
-#pragma unroll
-                        for (int s4 = 0; s4 < 4; ++s4) acc[rr][c] = mfma16(a[s4], b[rr][s4], acc[rr][c]);
-                    }
-            }
         }
     }
 #pragma unroll
