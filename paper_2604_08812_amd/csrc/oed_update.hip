@@ -128,6 +128,63 @@ __device__ void trsm_body(const StepDesc &d, int p)
             doublex4 acc[8];
 #pragma unroll
             for (int c = 0; c < 8; ++c) acc[c] = doublex4{0.0, 0.0, 0.0, 0.0};
+            // - sum_h P_h,i V_h^T first (held block columns; inner index over the held pick's
+            // block, V_h in L_s^-1's order).  Mixed paths: on the FP32 MFMA (P is FP32, or BF16
+            // hi + lo, exact in FP32; V_h rounded to FP32), the precision in which the downdate
+            // would have subtracted them, then carried on in FP64.
+            const int nbr = (d.N_t + 15) >> 4;
+            if constexpr (sizeof(TR) == 4) {
+                floatx4 hacc[8];
+#pragma unroll
+                for (int c = 0; c < 8; ++c) hacc[c] = floatx4{0.f, 0.f, 0.f, 0.f};
+                for (int hp = 0; hp < d.nheld; ++hp) {
+                    const TW *Pi = (const TW *)d.W + hp * d.wslot + (int64_t)i * bs;
+                    const TW *Pi2 = d.W2 ? (const TW *)d.W2 + hp * d.wslot + (int64_t)i * bs : nullptr;
+                    const double *Vh = d.V + hp * bs;
+                    for (int q = 0; q < nbr; ++q) {
+                        double v[4];
+                        w_row4<TW>(Pi, Pi2, tb, q, nb, lane, v);
+                        float b[4];
+#pragma unroll
+                        for (int s4 = 0; s4 < 4; ++s4) b[s4] = (float)-v[s4];
+#pragma unroll
+                        for (int c = 0; c < 8; ++c) {
+                            const int kc = kg + c;
+                            if (kc < kend) {
+                                // the FP32 MFMA takes its A operand in the natural lane order
+                                const doublex4 a = ld4(Vh + ((kc * nb + q) << 8) + lane * 4);
+#pragma unroll
+                                for (int s4 = 0; s4 < 4; ++s4) hacc[c] = mfma16((float)a[s4], b[s4], hacc[c]);
+                            }
+                        }
+                    }
+                }
+#pragma unroll
+                for (int c = 0; c < 8; ++c)
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) acc[c][r] = (double)hacc[c][r];
+            } else {
+                for (int hp = 0; hp < d.nheld; ++hp) {
+                    const TW *Pi = (const TW *)d.W + hp * d.wslot + (int64_t)i * bs;
+                    const TW *Pi2 = d.W2 ? (const TW *)d.W2 + hp * d.wslot + (int64_t)i * bs : nullptr;
+                    const double *Vh = d.V + hp * bs;
+                    for (int q = 0; q < nbr; ++q) {
+                        double b[4];
+                        w_row4<TW>(Pi, Pi2, tb, q, nb, lane, b);
+#pragma unroll
+                        for (int s4 = 0; s4 < 4; ++s4) b[s4] = -b[s4];
+#pragma unroll
+                        for (int c = 0; c < 8; ++c) {
+                            const int kc = kg + c;
+                            if (kc < kend) {
+                                const doublex4 a = ld4(Vh + ((kc * nb + q) << 8) + alane * 4);
+#pragma unroll
+                                for (int s4 = 0; s4 < 4; ++s4) acc[c] = mfma16(a[s4], b[s4], acc[c]);
+                            }
+                        }
+                    }
+                }
+            }
             for (int q = 0; q < kend; ++q) {
                 double b[4];
                 if (below) {
@@ -153,28 +210,6 @@ __device__ void trsm_body(const StepDesc &d, int p)
                         const doublex4 a = ld4(Linv + ((kc * nb + q) << 8) + alane * 4);
 #pragma unroll
                         for (int s4 = 0; s4 < 4; ++s4) acc[c] = mfma16(a[s4], b[s4], acc[c]);
-                    }
-                }
-            }
-            for (int hp = 0; hp < d.nheld; ++hp) {
-                // - P_h,i V_h^T: inner index over the held pick's block, V_h in L_s^-1's order
-                const TW *Pi = (const TW *)d.W + hp * d.wslot + (int64_t)i * bs;
-                const TW *Pi2 = d.W2 ? (const TW *)d.W2 + hp * d.wslot + (int64_t)i * bs : nullptr;
-                const double *Vh = d.V + hp * bs;
-                const int nbr = (d.N_t + 15) >> 4;
-                for (int q = 0; q < nbr; ++q) {
-                    double b[4];
-                    w_row4<TW>(Pi, Pi2, tb, q, nb, lane, b);
-#pragma unroll
-                    for (int s4 = 0; s4 < 4; ++s4) b[s4] = -b[s4];
-#pragma unroll
-                    for (int c = 0; c < 8; ++c) {
-                        const int kc = kg + c;
-                        if (kc < kend) {
-                            const doublex4 a = ld4(Vh + ((kc * nb + q) << 8) + alane * 4);
-#pragma unroll
-                            for (int s4 = 0; s4 < 4; ++s4) acc[c] = mfma16(a[s4], b[s4], acc[c]);
-                        }
                     }
                 }
             }
