@@ -43,7 +43,9 @@ def runs(big):
     out = {}
     for prec in PRECS:
         print(f"greedy {prec} B={spec.budget}", flush=True)
-        with Selector(K, spec.N_s, spec.N_t, s2, precision=prec) as sel:
+        # autotuned delay, as the benchmark runs it
+        with Selector(K, spec.N_s, spec.N_t, s2, precision=prec, autotune=True) as sel:
+            print(f"  delay {sel.config()[0]}", flush=True)
             out[prec] = sel.greedy(spec.budget)
     for prec in PRECS:
         print(f"greedy left-looking {prec} B={spec.budget}", flush=True)
