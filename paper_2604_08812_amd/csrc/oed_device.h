@@ -108,6 +108,14 @@ struct BoolC {
     static constexpr bool value = B;
 };
 
+// A wave-uniform element of a device array, kept in a scalar register.  Where the array's address
+// itself comes from memory (a batched launch's descriptor) the compiler reads it with a vector load;
+// without this every address derived from the value would occupy vector registers.
+__device__ __forceinline__ int uniform_at(const int *__restrict__ p, int k)
+{
+    return __builtin_amdgcn_readfirstlane(p[k]);
+}
+
 // Instance of a batched launch that owns work item `item`: the last descriptor with
 // item0 <= item (descriptors are sorted by item0).  -1 if no instance owns the item.
 __device__ __forceinline__ int find_instance(const StepDesc *ds, int n, int64_t item)

@@ -504,7 +504,7 @@ __device__ void gain_regs_body(const StepDesc &d, int p)
     __shared__ double piv[128];
     __shared__ double red[4];
     if (d.state[ST_STATUS] != 0 || p >= d.n_act) return;
-    const int i = d.act_in[p];
+    const int i = uniform_at(d.act_in, p);
     const int64_t bs = (int64_t)d.N_tp * d.N_tp;
     const bool ok = chol_mfma<TR, TW>((const TR *)d.R + blk_index(i, i) * bs, d.N_t, d.N_tp >> 4, piv, d, i * bs);
     if (!ok) {
@@ -548,7 +548,7 @@ __device__ void gain_lds_body(const StepDesc &d, int p, double *lds)
 {
     if (d.state[ST_STATUS] != 0 || p >= d.n_act) return;
     double *A = d.scratch ? d.scratch + (int64_t)p * tri(d.N_t) : lds;
-    const int i = d.act_in[p];
+    const int i = uniform_at(d.act_in, p);
     load_diag_block((const TR *)d.R + blk_index(i, i) * (int64_t)d.N_tp * d.N_tp, d.N_t, d.N_tp, A);
     const double ls = chol_packed(A, d.N_t);
     if (threadIdx.x == 0) d.gains[p] = (ls == -INFINITY) ? -INFINITY : ls - (d.noise_h ? d.noise_h[i] : d.half_noise);
@@ -714,7 +714,7 @@ __device__ void gain_blocked_body(const StepDesc &d, int p, unsigned char *dyn)
     double *piv = (double *)(Ub + (nbr + 1) * 64);
     const int64_t nblk = (int64_t)nbr * (nbr + 1) / 2;
     double *S = d.scratch + p * (nblk << 8);
-    const int i = d.act_in[p];
+    const int i = uniform_at(d.act_in, p);
     const int64_t bs = (int64_t)d.N_tp * d.N_tp;
     load_upper_global((const TR *)d.R + blk_index(i, i) * bs, nbr, nbr, S, d, i * bs);
     __syncthreads();

@@ -90,7 +90,7 @@ __device__ void vcorr_body(const StepDesc &d, int item)
     item -= hp * nb * nb;
     const int kb = item / nb, ab = item % nb;  // V^T sub-block (kb, ab) = V sub-block (ab, kb)
     const int lane = threadIdx.x & 63, g = lane >> 4, al = a_lane<double>(lane) & 15;
-    const int s = d.state[ST_LAST];
+    const int s = uniform_at(d.state, ST_LAST);
     const int64_t bs = (int64_t)d.N_tp * d.N_tp;
     const TW *Ps = (const TW *)d.W + hp * d.wslot + s * bs;
     const TW *Ps2 = d.W2 ? (const TW *)d.W2 + hp * d.wslot + s * bs : nullptr;
@@ -481,7 +481,7 @@ __device__ __forceinline__ void tile_map_n(const StepDesc &d, const int N_tp, in
     for (int h = 0; h < 2; ++h) {
         const int sb = wave + 4 * h;
         const int r = (int)P * 128 + 16 * sb, c = (int)Q * 128 + 16 * sb;
-        const int ia = act[min(r / N_tp, last)], ja = act[min(c / N_tp, last)];
+        const int ia = uniform_at(act, min(r / N_tp, last)), ja = uniform_at(act, min(c / N_tp, last));
         m.wA[h] = (int64_t)ia * bs + (int64_t)((r % N_tp) >> 4) * (NB * 256);
         m.wB[h] = (int64_t)ja * bs + (int64_t)((c % N_tp) >> 4) * (NB * 256);
     }
@@ -489,11 +489,11 @@ __device__ __forceinline__ void tile_map_n(const StepDesc &d, const int N_tp, in
 #pragma unroll
     for (int b = 0; b < 4; ++b) {
         const int r = (int)P * 128 + (wave >> 1) * 64 + 16 * b;
-        const int ia = act[min(r / N_tp, last)], ta = (r % N_tp) >> 4;
+        const int ia = uniform_at(act, min(r / N_tp, last)), ta = (r % N_tp) >> 4;
 #pragma unroll
         for (int c = 0; c < 4; ++c) {
             const int cc = (int)Q * 128 + (wave & 1) * 64 + 16 * c;
-            const int ja = act[min(cc / N_tp, last)], tc = (cc % N_tp) >> 4;
+            const int ja = uniform_at(act, min(cc / N_tp, last)), tc = (cc % N_tp) >> 4;
             const bool o = r < rows && cc < rows && ia >= ja;
             m.ok[4 * b + c] = o;
             m.any |= o;
@@ -833,7 +833,7 @@ __device__ void column_body(const StepDesc &d, int64_t item)
     const int alane = a_lane<T>(lane);
     const int *__restrict__ act = d.act_in;
     const int rows = d.n_act * N_tp, last = d.n_act - 1;
-    const int s = d.state[ST_LAST];
+    const int s = uniform_at(d.state, ST_LAST);
     const int64_t bs = (int64_t)N_tp * N_tp;
     // staged operands: rows of the tile (A) and the rows of s (B; sub-blocks past N_tp clamped)
     int64_t wA[2], wB[2];
@@ -841,7 +841,7 @@ __device__ void column_body(const StepDesc &d, int64_t item)
     for (int h = 0; h < 2; ++h) {
         const int sb = wave + 4 * h;
         const int r = (int)P * 128 + 16 * sb;
-        wA[h] = (int64_t)act[min(r / N_tp, last)] * bs + (int64_t)((r % N_tp) >> 4) * (NB * 256);
+        wA[h] = (int64_t)uniform_at(act, min(r / N_tp, last)) * bs + (int64_t)((r % N_tp) >> 4) * (NB * 256);
         wB[h] = (int64_t)s * bs + (int64_t)(sb < NB ? sb : 0) * (NB * 256);
     }
     int64_t off[2];
@@ -850,7 +850,7 @@ __device__ void column_body(const StepDesc &d, int64_t item)
     for (int b = 0; b < 2; ++b) {
         const int r = (int)P * 128 + wave * 32 + 16 * b;
         ok[b] = r < rows;
-        off[b] = (int64_t)act[min(r / N_tp, last)] * bs + ((((r % N_tp) >> 4) * NB) << 8);
+        off[b] = (int64_t)uniform_at(act, min(r / N_tp, last)) * bs + ((((r % N_tp) >> 4) * NB) << 8);
     }
     const bool any = ok[0];
     const T *W0 = (const T *)d.W + lane * 4;
@@ -948,7 +948,7 @@ __device__ void column_rt_body(const StepDesc &d, int64_t item)
     const int alane = a_lane<T>(lane);
     const int *__restrict__ act = d.act_in;
     const int rows = d.n_act * N_tp, last = d.n_act - 1;
-    const int s = d.state[ST_LAST];
+    const int s = uniform_at(d.state, ST_LAST);
     const int64_t bs = (int64_t)N_tp * N_tp;
     const int ncol = min(8, nb - 8 * cc);
     // staged operands: rows of the tile (A) and the chunk's rows of s (B; past nb clamped)
@@ -957,7 +957,7 @@ __device__ void column_rt_body(const StepDesc &d, int64_t item)
     for (int h = 0; h < 2; ++h) {
         const int sb = wave + 4 * h;
         const int r = (int)P * 128 + 16 * sb;
-        wA[h] = (int64_t)act[min(r / N_tp, last)] * bs + (int64_t)((r % N_tp) >> 4) * (nb * 256);
+        wA[h] = (int64_t)uniform_at(act, min(r / N_tp, last)) * bs + (int64_t)((r % N_tp) >> 4) * (nb * 256);
         const int sbB = 8 * cc + sb;
         wB[h] = (int64_t)s * bs + (int64_t)(sbB < nb ? sbB : 0) * (nb * 256);
     }
@@ -967,7 +967,7 @@ __device__ void column_rt_body(const StepDesc &d, int64_t item)
     for (int b = 0; b < 2; ++b) {
         const int r = (int)P * 128 + wave * 32 + 16 * b;
         ok[b] = r < rows;
-        off[b] = (int64_t)act[min(r / N_tp, last)] * bs + ((((r % N_tp) >> 4) * nb + 8 * cc) << 8);
+        off[b] = (int64_t)uniform_at(act, min(r / N_tp, last)) * bs + ((((r % N_tp) >> 4) * nb + 8 * cc) << 8);
     }
     const bool any = ok[0];
     const T *W0 = (const T *)d.W + lane * 4;
@@ -1046,14 +1046,14 @@ __device__ void column_bf16_body(const StepDesc &d, int64_t item)
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int *__restrict__ act = d.act_in;
     const int rows = d.n_act * N_tp, last = d.n_act - 1;
-    const int s = d.state[ST_LAST];
+    const int s = uniform_at(d.state, ST_LAST);
     const int64_t bs = (int64_t)N_tp * N_tp;
     int64_t wA[2], wB[2];
 #pragma unroll
     for (int h = 0; h < 2; ++h) {
         const int sb = wave + 4 * h;
         const int r = (int)P * 128 + 16 * sb;
-        wA[h] = (int64_t)act[min(r / N_tp, last)] * bs + (int64_t)((r % N_tp) >> 4) * (NB * 256);
+        wA[h] = (int64_t)uniform_at(act, min(r / N_tp, last)) * bs + (int64_t)((r % N_tp) >> 4) * (NB * 256);
         wB[h] = (int64_t)s * bs + (int64_t)(sb < NB ? sb : 0) * (NB * 256);
     }
     int64_t off[2];
@@ -1062,7 +1062,7 @@ __device__ void column_bf16_body(const StepDesc &d, int64_t item)
     for (int b = 0; b < 2; ++b) {
         const int r = (int)P * 128 + wave * 32 + 16 * b;
         ok[b] = r < rows;
-        off[b] = (int64_t)act[min(r / N_tp, last)] * bs + ((((r % N_tp) >> 4) * NB) << 8);
+        off[b] = (int64_t)uniform_at(act, min(r / N_tp, last)) * bs + ((((r % N_tp) >> 4) * NB) << 8);
     }
     const bool any = ok[0];
     typedef const unsigned short *bp;
