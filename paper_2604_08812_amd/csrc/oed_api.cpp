@@ -324,7 +324,9 @@ oed_status advance(oed_ctx *h, bool full)
 // On the freshly packed working copy it times, per delay depth p = 1..MAX_DELAY, the kernels of
 // one pick: the gains and the block column with h = 0 .. p-1 block columns held, the V
 // correction for h > 0, and the downdate of p block columns; the per-pick cost is
-// t_syrk(p)/p + (1/p) sum_h (t_gain(h) + t_vcorr(h) + t_trsm(h)).  The W slots are zero while
+// t_syrk(p)/p + (1/p) sum_h (t_gain(h) + t_vcorr(h) + t_trsm(h)), taken at the first step's
+// candidate count and at half of it (the leading half of the active list) and averaged; the
+// choice is the least estimate (the shallowest on ties).  The W slots are zero while
 // the downdates are timed, so R - 0 leaves R exactly as packed; the gains, L_s^-1 and W
 // buffers it writes are overwritten by the first step.  Both downdate variants are timed at
 // p = 1.  Results are cached per (device, precision, N_tp, ceil(N_c / 32)).
@@ -343,12 +345,12 @@ struct TuneVal {
 std::mutex g_tune_mu;
 std::map<TuneKey, TuneVal> g_tune;
 
-// Milliseconds of `reps` back-to-back calls of f (the minimum over two rounds).
+// Milliseconds of one call of f (the minimum over three rounds).
 template <typename F>
 hipError_t time_ms(oed_ctx *h, hipEvent_t a, hipEvent_t b, F f, double *out)
 {
     double best = 1e300;
-    for (int round = 0; round < 2; ++round) {
+    for (int round = 0; round < 3; ++round) {
         hipError_t e = hipEventRecord(a, h->stream);
         if (e == hipSuccess) e = f();
         if (e == hipSuccess) e = hipEventRecord(b, h->stream);
@@ -393,46 +395,61 @@ oed_status autotune(oed_ctx *h)
     };
     hipError_t e = zero_w();
     if (e == hipSuccess) e = hipMemsetAsync(h->Linv, 0, sizeof(double) * bs, h->stream);
-    double t_step[MAX_DELAY] = {0}, t_syrk[MAX_DELAY] = {0}, t_direct = 1e300;
-    for (int hh = 0; hh < MAX_DELAY && e == hipSuccess; ++hh) {
-        StepDesc d = desc(h);
-        d.nheld = hh;
-        double tg = 0, tt = 0;
-        e = time_ms(h, a, b, [&] { return launch_gain(d, h->rtype, h->wtype, h->stream); }, &tg);
-        if (e == hipSuccess)
-            e = time_ms(h, a, b, [&] {
-                hipError_t r = hh > 0 ? launch_vcorr(d, h->wtype, h->stream) : hipSuccess;
-                return r == hipSuccess ? launch_trsm(d, h->rtype, h->wtype, h->stream) : r;
-            }, &tt);
-        t_step[hh] = tg + tt;
-    }
-    if (e == hipSuccess) e = zero_w();
-    for (int p = 1; p <= MAX_DELAY && e == hipSuccess; ++p) {
-        StepDesc d = desc(h);
-        d.nheld = 0;
-        d.nw = p;
-        d.nitems = syrk_tiles(h->n_act, h->N_tp);
-        e = time_ms(h, a, b, [&] { return launch_syrk(d, h->rtype, h->wtype, SYRK_LDS, h->stream); }, &t_syrk[p - 1]);
-        if (e == hipSuccess && p == 1 && h->wtype != W_BF16X3)
-            e = time_ms(h, a, b, [&] { return launch_syrk(d, h->rtype, h->wtype, SYRK_DIRECT, h->stream); }, &t_direct);
+    // the per-pick estimates at the first step's size n and at n / 2, averaged: the run's later
+    // steps work on fewer candidates, where each launch's fixed cost weighs more
+    double t_step[2][MAX_DELAY] = {{0}}, t_syrk[2][MAX_DELAY] = {{0}}, t_direct[2] = {1e300, 1e300};
+    const int n_at[2] = {h->n_act, std::max(1, h->n_act / 2)};
+    for (int z = 0; z < 2 && e == hipSuccess; ++z) {
+        for (int hh = 0; hh < MAX_DELAY && e == hipSuccess; ++hh) {
+            StepDesc d = desc(h);
+            d.n_act = n_at[z];
+            d.nitems = n_at[z];
+            d.nheld = hh;
+            double tg = 0, tt = 0;
+            e = time_ms(h, a, b, [&] { return launch_gain(d, h->rtype, h->wtype, h->stream); }, &tg);
+            if (e == hipSuccess)
+                e = time_ms(h, a, b, [&] {
+                    hipError_t r = hh > 0 ? launch_vcorr(d, h->wtype, h->stream) : hipSuccess;
+                    return r == hipSuccess ? launch_trsm(d, h->rtype, h->wtype, h->stream) : r;
+                }, &tt);
+            t_step[z][hh] = tg + tt;
+        }
+        if (e == hipSuccess) e = zero_w();
+        for (int p = 1; p <= MAX_DELAY && e == hipSuccess; ++p) {
+            StepDesc d = desc(h);
+            d.n_act = n_at[z];
+            d.nheld = 0;
+            d.nw = p;
+            d.nitems = syrk_tiles(n_at[z], h->N_tp);
+            e = time_ms(h, a, b, [&] { return launch_syrk(d, h->rtype, h->wtype, SYRK_LDS, h->stream); },
+                        &t_syrk[z][p - 1]);
+            if (e == hipSuccess && p == 1 && h->wtype != W_BF16X3)
+                e = time_ms(h, a, b, [&] { return launch_syrk(d, h->rtype, h->wtype, SYRK_DIRECT, h->stream); },
+                            &t_direct[z]);
+        }
     }
     if (e != hipSuccess) return done(fail(h, e == hipErrorOutOfMemory ? OED_E_OOM : OED_E_HIP,
                                           std::string("autotune: ") + hipGetErrorString(e)));
     TuneVal v{1, SYRK_LDS, {0}};
+    const bool direct = t_direct[0] + t_direct[1] < t_syrk[0][0] + t_syrk[1][0];
     double best = 1e300;
     for (int p = 1; p <= MAX_DELAY; ++p) {
-        double steps = 0;
-        for (int hh = 0; hh < p; ++hh) steps += t_step[hh];
-        const double syrk = (p == 1) ? std::min(t_syrk[0], t_direct) : t_syrk[p - 1];
-        v.ms[p - 1] = (syrk + steps) / p;
+        double sum = 0;
+        for (int z = 0; z < 2; ++z) {
+            double steps = 0;
+            for (int hh = 0; hh < p; ++hh) steps += t_step[z][hh];
+            const double syrk = (p == 1 && direct) ? t_direct[z] : t_syrk[z][p - 1];
+            sum += (syrk + steps) / p;
+        }
+        v.ms[p - 1] = 0.5 * sum;
         best = std::min(best, v.ms[p - 1]);
     }
-    // the shallowest depth within 0.5% of the best estimate: the estimate takes the held-column
-    // corrections at the first step's size only, and a deeper delay gains less than it adds there
+    // the least estimate, the shallowest depth on ties (a margin towards shallower depths chose
+    // delay 3 at 600 x 128 FP32, measured 1.5% slower than 4)
     for (int p = 1; p <= MAX_DELAY; ++p)
-        if (v.ms[p - 1] <= 1.005 * best) {
+        if (v.ms[p - 1] <= best) {
             v.delay = p;
-            v.variant = (p == 1 && t_direct < t_syrk[0]) ? SYRK_DIRECT : SYRK_LDS;
+            v.variant = (p == 1 && direct) ? SYRK_DIRECT : SYRK_LDS;
             break;
         }
     h->delay = v.delay;
