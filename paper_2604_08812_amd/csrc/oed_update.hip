@@ -525,6 +525,7 @@ __device__ void syrk_lds_body(const StepDesc &d, int64_t tile)
     typedef typename V4<T>::type vec;
     constexpr int N_tp = 16 * NB;
     constexpr int NST = NB / KS;              // stages per W block
+    constexpr bool FLAT = sizeof(T) == 4;     // FP32: the slice's MFMAs without a branch
     __shared__ vec lds[2][2][KS][8 * 64];      // [buffer][A/B][slice][sub-block * 64 + lane]
     if (d.state[ST_STATUS] != 0) return;
     int64_t P, Q;
@@ -575,7 +576,12 @@ __device__ void syrk_lds_body(const StepDesc &d, int64_t tile)
             const int buf = par ^ (q & 1);
             const bool more = q + 1 < NST || nxt;
             if (more) stage(q + 1 < NST ? cur + (((q + 1) * KS) << 8) : nxt);
-            if (m.any) {
+            // FP32: the MFMAs run unconditionally (a wave with no output block in the triangle
+            // computes products it never stores), so that each slice is one basic block and the
+            // scheduling barrier keeps the next slice's loads ahead of them instead of sunk below
+            // (2.4% faster at 600 x 128).  FP64 keeps the branch: there the same form spills.
+            if constexpr (FLAT) __builtin_amdgcn_sched_barrier(0);
+            if (FLAT || m.any) {
 #pragma unroll
                 for (int k = 0; k < KS; ++k) {
                     vec a[4], w[4];
@@ -770,7 +776,9 @@ __device__ void syrk_bf16_body(const StepDesc &d, int64_t tile)
 #pragma unroll
                 for (int f = q * PER; f < (q + 1) * PER && f < 16; ++f) rt[f] = ld4_stream(Rl + m.rblk[f]);
             }
-            if (m.any) {
+            // as in the FP32 downdate: the MFMAs without a branch, the loads kept ahead of them
+            __builtin_amdgcn_sched_barrier(0);
+            {
                 u32x4 wh[4], wl[4];
 #pragma unroll
                 for (int c = 0; c < 4; ++c) {
