@@ -74,7 +74,7 @@ def timed_selections(sel, K, budget, steps):
     return (time.perf_counter() - t0) * 1e3 / steps, out
 
 
-def roofline_syrk(prof, prec, workload=None):
+def roofline_syrk(prof, prec, workload=None, delay=None):
     """The downdate R -= W W^T: algorithmic flops (2 per multiply-add of the lower-triangle
     blocks) over its summed HIP-event time.  The BF16 split product executes three MFMA
     products per algorithmic one; its fraction is taken of the BF16 peak on the executed
@@ -91,7 +91,7 @@ def roofline_syrk(prof, prec, workload=None):
         "peak": PEAK_TFLOPS[prec],
         "unit": "TFLOP/s",
         "frac": round(executed / PEAK_TFLOPS[prec], 4),
-        "traffic": counted_traffic(workload, prec, SYRK_KERNEL[prec]) if workload else None,
+        "traffic": counted_traffic(workload, prec, SYRK_KERNEL[prec], delay) if workload else None,
         "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
         "algorithmic_bytes_per_launch": round(prof["syrk_bytes"] / n),
         "avg_launch_ms": round(ms / n, 4),
@@ -144,9 +144,10 @@ def source_digest():
     return h.hexdigest()
 
 
-def counted_traffic(workload, prec, kernel_name):
-    """HBM bytes per launch of the downdate from the committed rocprofv3 FETCH_SIZE / WRITE_SIZE
-    summary (scaled by the copy calibration), or None when absent or taken on other source."""
+def counted_traffic(workload, prec, kernel_name, delay):
+    """HBM bytes per launch of the downdate at this delay depth (W slots per launch) from the
+    committed rocprofv3 FETCH_SIZE / WRITE_SIZE summary (scaled by the copy calibration), or None
+    when absent, taken at another depth or on other source."""
     path = os.path.join(ROOT, "profiles", f"syrk_hbm_traffic_{workload}.json")
     try:
         with open(path) as fh:
@@ -156,7 +157,8 @@ def counted_traffic(workload, prec, kernel_name):
     ent = rec.get("kernels", {}).get(prec)
     if not ent or ent.get("source_sha256") != source_digest() or ent.get("kernel") != kernel_name:
         return None
-    return ent.get("hbm_bytes_per_launch")
+    at = ent.get("by_delay", {}).get(str(delay))
+    return at.get("hbm_bytes_per_launch") if at else None
 
 
 def naive_flops(n, N_t, budget):
@@ -375,7 +377,7 @@ def run_paper_shape(args):
                    "budget": budget, "precision": "mixed_f32", "K_dtype": "f32 (row panels, never whole)",
                    "delay": delay, "downdate_variant": ["direct", "lds"][variant],
                    "step": "oed_greedy(budget) on the packed working copy"},
-        "roofline": {**roofline_syrk(prof, "mixed_f32", spec.name),
+        "roofline": {**roofline_syrk(prof, "mixed_f32", spec.name, delay),
                      "kernel": "syrk_direct_kernel<float>" if variant == 0 else "syrk_lds_rt_kernel<float>"},
         "kernel_ms_per_step": {k: round(v / args.steps, 3) for k, v in prof["ms"].items()},
         "pack_s_per_fill": round(sum(pack_s) / len(pack_s), 3),
@@ -525,7 +527,7 @@ def main():
                    "downdate_variant": ["direct", "lds"][variant], "autotuned": tune,
                    "autotuner_ms_per_pick_by_delay": [round(float(x), 4) for x in tuned] if tune else None,
                    "step": "oed_reset + oed_greedy(budget)"},
-        "roofline": roofline_syrk(prof, prec, spec.name),
+        "roofline": roofline_syrk(prof, prec, spec.name, delay),
         "kernel_ms_per_step": {k: round(v / args.steps, 3) for k, v in prof["ms"].items()},
         "paper_context": PAPER_CONTEXT,
     }
@@ -544,7 +546,7 @@ def main():
         log(f"fp64: {ms64:.1f} ms per selection")
         result["fp64"] = {"value": round(budget / (ms64 * 1e-3), 3), "unit": "greedy steps/s",
                           "delay": d64,
-                          "ms_per_step": round(ms64, 3), "roofline": roofline_syrk(p64, "fp64", spec.name),
+                          "ms_per_step": round(ms64, 3), "roofline": roofline_syrk(p64, "fp64", spec.name, d64),
                           "kernel_ms_per_step": {k: round(v / args.fp64_steps, 3) for k, v in p64["ms"].items()}}
         result["mixed_vs_fp64"] = {"speedup": round(ms64 / ms, 3), **compare_picks(idx, gain, idx64, gain64)}
         if not args.no_gaps:
@@ -566,7 +568,7 @@ def main():
         selb.close()
         log(f"mixed_bf16x3: {msb:.1f} ms per selection")
         result["mixed_bf16x3"] = {"value": round(budget / (msb * 1e-3), 3), "unit": "greedy steps/s", "delay": db,
-                                  "ms_per_step": round(msb, 3), "roofline": roofline_syrk(pb, "mixed_bf16x3", spec.name),
+                                  "ms_per_step": round(msb, 3), "roofline": roofline_syrk(pb, "mixed_bf16x3", spec.name, db),
                                   "kernel_ms_per_step": {k: round(v / args.steps, 3) for k, v in pb["ms"].items()},
                                   "speedup_vs_mixed_f32": round(ms / msb, 3),
                                   "vs_mixed_f32": compare_picks(idxb, gainb, idx, gain)}
