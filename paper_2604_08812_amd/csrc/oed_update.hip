@@ -899,7 +899,9 @@ __device__ void column_body(const StepDesc &d, int64_t item)
                     sbv[h] = ld4(src + wB[h]);
                 }
             }
-            if (any) {
+            // FP32: the MFMAs without a branch, the loads kept ahead of them (as in the downdate)
+            if constexpr (sizeof(T) == 4) __builtin_amdgcn_sched_barrier(0);
+            if (sizeof(T) == 4 || any) {
                 vec a[2], w[NB];
 #pragma unroll
                 for (int b = 0; b < 2; ++b) a[b] = lds[buf][0][(2 * wave + b) * 64 + alane];
