@@ -95,7 +95,7 @@ def test_greedy_matches_brute_force(N_s, N_t, B, seed):
     assert list(res["idx"]) == A_ref
     np.testing.assert_allclose(res["gain"], g_ref, rtol=1e-11, atol=1e-12)
     np.testing.assert_allclose(res["gap"], gaps, rtol=1e-8, atol=1e-10)
-    # (1 - 1/e) guarantee for monotone submodular maximisation (Sec. III-G)
+    # (1 - 1/e) guarantee for monotone submodular maximisation (Sec. III-H)
     opt = max(v for S, v in table.items() if len(S) == B)
     assert table[tuple(sorted(A_ref))] >= (1.0 - 1.0 / math.e) * opt - 1e-12
 
@@ -408,3 +408,70 @@ def test_sensor_noise_telescoping_and_isotropic_special_case():
     eq = oracle.greedy(K2, N_s, N_t, 1.0, B, noise_hld=np.full(N_s, 0.5 * N_t * math.log(s2)))
     assert list(iso["idx"]) == list(eq["idx"])
     np.testing.assert_allclose(iso["gain"], eq["gain"], rtol=1e-13, atol=1e-13)
+
+
+# --------------------------------------------------------------------------- objective f(S)
+@pytest.mark.parametrize("N_s,N_t,B,seed", [(6, 1, 3, 20), (7, 2, 3, 21), (8, 3, 4, 22)])
+def test_objective_matches_lu_table_for_every_subset(N_s, N_t, B, seed):
+    """f(S) = 1/2 logdet(sigma^-2 K_SS) (Sec. III-C, isotropic noise) for every subset of up to B
+    sensors, against numpy's LU-based slogdet; the value does not depend on the order of S."""
+    rng = np.random.default_rng(seed)
+    K, s2 = rand_spd_instance(rng, N_s, N_t)
+    assert abs(math.log(s2)) > 1.0  # the noise term is far from zero, so its count and sign matter
+    table = brute_force_table(K, N_s, N_t, s2, B)
+    assert oracle.objective(K, N_t, s2, []) == 0.0
+    for S, ref in table.items():
+        if not S:
+            continue
+        got = oracle.objective(K, N_t, s2, list(S))
+        assert abs(got - ref) <= 1e-12 * max(1.0, abs(ref)), (S, got, ref)
+        rev = oracle.objective(K, N_t, s2, list(S)[::-1])
+        assert abs(rev - ref) <= 1e-12 * max(1.0, abs(ref)), (S, rev, ref)
+
+
+def test_objective_is_sum_of_greedy_gains():
+    """Telescoping: the gains of the greedy trajectory add up to f(A_B), isotropic and per-sensor."""
+    K, s2 = _config0_like(14)
+    N_s, N_t, B = 24, 8, 9
+    res = oracle.greedy(K, N_s, N_t, s2, B)
+    for k in range(1, B + 1):
+        f = oracle.objective(K, N_t, s2, list(res["idx"][:k]))
+        assert abs(f - res["gain"][:k].sum()) <= 1e-11 * max(1.0, abs(f)), k
+    rng = np.random.default_rng(15)
+    Kn, _, h = sensor_noise_instance(rng, 12, 4)
+    rn = oracle.greedy(Kn, 12, 4, 1.0, 6, noise_hld=h)
+    f = oracle.objective(Kn, 4, 1.0, list(rn["idx"]), noise_hld=h)
+    assert abs(f - rn["gain"].sum()) <= 1e-11 * max(1.0, abs(f))
+
+
+def test_objective_parameter_space_and_generalised_eigenvalues():
+    """With K = F F^T / n_m + D (D block-diagonal, the noise covariance of sensors independent of each
+    other), the computable objective f(S) = 1/2 logdet K_SS - sum_{j in S} 1/2 logdet D_j equals the
+    expected information gain in the parameter space, 1/2 logdet(I + F_S^T D_S^-1 F_S / n_m)
+    (Sylvester's determinant identity), and 1/2 sum ln(lambda) over the generalised eigenvalues of
+    (K_SS, D_SS).  Isotropic D = sigma^2 I is checked the same way."""
+    rng = np.random.default_rng(16)
+    N_s, N_t, n_m = 7, 3, 40
+    N_d = N_s * N_t
+    F = rng.standard_normal((N_d, n_m)) * (1.0 + np.arange(n_m)) ** -0.25
+    D = np.zeros((N_d, N_d))
+    h = np.empty(N_s)
+    for j in range(N_s):
+        Q = rng.standard_normal((N_t, N_t))
+        Dj = 0.02 * 10 ** rng.uniform(-1, 1) * (np.eye(N_t) + 0.3 * Q @ Q.T / N_t)
+        D[j * N_t:(j + 1) * N_t, j * N_t:(j + 1) * N_t] = Dj
+        h[j] = 0.5 * float(np.sum(np.log(np.linalg.eigvalsh(Dj))))
+    K = F @ F.T / n_m + D
+    s2 = 0.013
+    Kiso = F @ F.T / n_m + s2 * np.eye(N_d)
+    for S in ([3], [0, 5], [6, 1, 4], [2, 0, 6, 3, 5]):
+        idx = oracle.block_index(N_t, S)
+        FS, DS = F[idx], D[np.ix_(idx, idx)]
+        eig = 0.5 * np.linalg.slogdet(np.eye(n_m) + FS.T @ np.linalg.solve(DS, FS) / n_m)[1]
+        lam = scipy.linalg.eigh(K[np.ix_(idx, idx)], DS, eigvals_only=True)
+        got = oracle.objective(K, N_t, 1.0, S, noise_hld=h)
+        assert abs(got - eig) <= 1e-11 * max(1.0, abs(eig)), (S, got, eig)
+        assert abs(got - 0.5 * float(np.sum(np.log(lam)))) <= 1e-11 * max(1.0, abs(eig)), S
+        eig_iso = 0.5 * np.linalg.slogdet(np.eye(n_m) + FS.T @ FS / (n_m * s2))[1]
+        got_iso = oracle.objective(Kiso, N_t, s2, S)
+        assert abs(got_iso - eig_iso) <= 1e-11 * max(1.0, abs(eig_iso)), (S, got_iso, eig_iso)
