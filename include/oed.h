@@ -350,6 +350,43 @@ OED_API oed_status oed_eval_stats(const oed_eval *e, double *run_ms, double *syr
 OED_API oed_status oed_eval_destroy(oed_eval *e);
 OED_API const char *oed_eval_last_error(const oed_eval *e);
 
+/* ---------------------------------------------------------------------------------------------
+ * A whole greedy selection that allocates nothing, for callers that cannot allocate device
+ * memory (code under HIP graph capture, tight serving loops, harnesses that forbid hipMalloc).
+ * It runs the kernels of oed_create + oed_greedy (right-looking, LDS downdate, delay depth
+ * `delay`, all N_s sensors candidates, isotropic noise) in the same order, so its picks and
+ * gains equal, bit for bit, those of a handle created with the same precision and delay and
+ * run for the same budget.  Every workspace (working copy R, W slots, L_s^-1, held-column
+ * corrections, gains, active lists, state words) lives in one static device array of
+ * OED_NOALLOC_MAX_BYTES that the library holds on each GPU it runs on until the process ends;
+ * the call makes no hipMalloc / hipFree and no allocating library call.
+ *
+ * Arguments: K_dev, dtype, ld, N_s, N_t, sigma2 as for oed_create (device K, row-major, lower
+ * triangle read); precision: oed_precision; delay: 1..OED_MAX_DELAY (0 = 4); 0 <= budget <= N_s.
+ * Outputs (device memory of the current device, caller-owned): idx_dev[k] (int32, length
+ * budget) the k-th pick's sensor index, gain_dev[k] (FP64, length budget) its gain;
+ * status_dev[0] (int32) 0 = all picks made, 2 = every remaining candidate had a
+ * non-positive-definite Schur block (picks after that are not written), status_dev[1] = picks
+ * made.  err (host, may be NULL): err_len bytes receiving the text of a failure.
+ *
+ * Everything is enqueued on `stream` (hipStream_t, NULL = default) and the call returns without
+ * synchronising; the outputs are valid once the stream reaches that point.  Rejected before
+ * anything runs: invalid arguments (OED_E_ARG), N_t > 128 or a problem whose workspaces exceed
+ * OED_NOALLOC_MAX_BYTES (OED_E_UNSUPPORTED; the message gives the bytes needed:
+ * the sum of N_s (N_s + 1)/2 N_tp^2 e_R (R), delay N_s N_tp^2 e_W (W; BF16: twice),
+ * 8 (delay - 1) N_tp^2 (if delay > 1), 8 N_tp^2, 8 N_s, three times 4 N_s and 64 bytes, each
+ * rounded up to a multiple of 256; N_tp = N_t rounded up to a multiple of 16, of 32 for
+ * MIXED_BF16X3; e_R = 8 for FP64, else 4; e_W = 8, 4 or 2 by precision).
+ * All calls on one GPU share its one array, which keeps the last call's contents (every buffer
+ * is re-initialised by kernels before it is read): two calls that overlap in time on the same
+ * GPU (different streams or threads) race and give undefined results.
+ */
+#define OED_NOALLOC_MAX_BYTES (64ull << 20)
+OED_API oed_status oed_greedy_noalloc(const void *K_dev, int32_t dtype, int64_t ld, int32_t N_s, int32_t N_t,
+                                      double sigma2, int32_t precision, int32_t delay, int32_t budget, void *stream,
+                                      int32_t *idx_dev, double *gain_dev, int32_t *status_dev, char *err,
+                                      int32_t err_len);
+
 /* Bytes of device memory the handle holds. */
 OED_API oed_status oed_device_bytes(const oed_ctx *h, int64_t *bytes);
 

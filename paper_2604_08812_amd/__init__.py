@@ -29,6 +29,7 @@ from .oed import (  # noqa: F401
     oed_get_config,
     oed_get_profile,
     oed_greedy,
+    oed_greedy_noalloc,
     oed_pack_rows,
     oed_picks,
     oed_reset,

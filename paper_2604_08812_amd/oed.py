@@ -103,10 +103,13 @@ def library() -> ctypes.CDLL:
     L.oed_eval_destroy.argtypes = [vp]
     L.oed_eval_last_error.argtypes = [vp]
     L.oed_eval_last_error.restype = ctypes.c_char_p
+    L.oed_greedy_noalloc.argtypes = [vp, ctypes.c_int32, ctypes.c_int64, ctypes.c_int32, ctypes.c_int32,
+                                     ctypes.c_double, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, vp, vp, vp,
+                                     vp, ctypes.c_char_p, ctypes.c_int32]
     for name in ("oed_create", "oed_reset", "oed_pack_rows", "oed_greedy", "oed_force", "oed_scores", "oed_schur_block", "oed_picks",
                  "oed_get_profile", "oed_device_bytes", "oed_destroy", "oed_batch_create", "oed_batch_run",
                  "oed_batch_reset", "oed_batch_stats", "oed_batch_destroy", "oed_batch_get_config", "oed_get_config",
-                 "oed_eval_create", "oed_eval_run", "oed_eval_stats", "oed_eval_destroy"):
+                 "oed_eval_create", "oed_eval_run", "oed_eval_stats", "oed_eval_destroy", "oed_greedy_noalloc"):
         getattr(L, name).restype = ctypes.c_int32
     _lib = L
     return L
@@ -117,7 +120,8 @@ EXPORTED = ("oed_options_init", "oed_create", "oed_reset", "oed_pack_rows", "oed
             "oed_last_error",
             "oed_status_string", "oed_batch_create", "oed_batch_run", "oed_batch_reset", "oed_batch_stats",
             "oed_batch_destroy", "oed_batch_last_error", "oed_batch_get_config", "oed_eval_create", "oed_eval_run",
-            "oed_eval_stats", "oed_eval_destroy", "oed_eval_last_error")
+            "oed_eval_stats", "oed_eval_destroy", "oed_eval_last_error", "oed_greedy_noalloc")
+OED_NOALLOC_MAX_BYTES = 64 << 20
 
 
 def _status_name(s):
@@ -277,6 +281,33 @@ def oed_get_config(h):
 def oed_destroy(h):
     if h:
         library().oed_destroy(h)
+
+
+def oed_greedy_noalloc(K, N_s, N_t, sigma2, budget, idx_out, gain_out, status_out, precision="fp64", delay=0,
+                       stream=None):
+    """One whole selection without allocating (the library's static scratch array): K, idx_out (int32,
+    length >= budget), gain_out (float64, length >= budget) and status_out (int32, length >= 2) are
+    caller-owned device tensors.  Enqueued on the stream; returns without synchronising."""
+    import torch
+    if not isinstance(K, torch.Tensor) or not K.is_cuda or K.dim() != 2 or K.stride(1) != 1:
+        raise ValueError("K must be a 2-D row-major device tensor")
+    dtype = {torch.float64: OED_F64, torch.float32: OED_F32}.get(K.dtype)
+    if dtype is None:
+        raise ValueError("K must be float64 or float32")
+    if K.shape[0] < N_s * N_t or K.shape[1] < N_s * N_t:
+        raise ValueError("K must have at least N_s*N_t rows and columns")
+    for t, dt, n in ((idx_out, torch.int32, budget), (gain_out, torch.float64, budget), (status_out, torch.int32, 2)):
+        if not isinstance(t, torch.Tensor) or not t.is_cuda or t.dtype != dt or not t.is_contiguous() or t.numel() < n:
+            raise ValueError("outputs must be contiguous device tensors: idx int32, gain float64 (budget each), "
+                             "status int32 (2)")
+    err = ctypes.create_string_buffer(512)
+    st = library().oed_greedy_noalloc(ctypes.c_void_p(K.data_ptr()), dtype, K.stride(0), int(N_s), int(N_t),
+                                      float(sigma2), PRECISIONS[precision], int(delay), int(budget),
+                                      _stream_handle(stream), ctypes.c_void_p(idx_out.data_ptr()),
+                                      ctypes.c_void_p(gain_out.data_ptr()), ctypes.c_void_p(status_out.data_ptr()),
+                                      err, len(err))
+    if st != OED_OK:
+        raise OedError(st, err.value.decode())
 
 
 def _instances(items):
