@@ -308,7 +308,7 @@ def run_paper_shape(args):
     torch.cuda.synchronize()
     log(f"F {spec.N_d} x {spec.n_m} formed in {time.perf_counter() - t0:.1f} s, sigma2={s2:.6e}")
     sel = Selector(None, spec.N_s, spec.N_t, s2, precision="mixed_f32", profile=True)
-    delay, variant, _ = sel.config()
+    delay, variant, _, tiles = sel.config()
 
     def pack(target):
         t = time.perf_counter()
@@ -391,6 +391,56 @@ def run_paper_shape(args):
     print(json.dumps(result), flush=True)
 
 
+def batched_checks(specs, items, res, prec, delay, method, args):
+    """The timed batch's picks and gains against a single handle per instance (same kernels and
+    delay: equal bit for bit), and the oracle on a bounded sample: the instances with N_t <= 32,
+    each restricted to its first min(N_s, 100) sensors with budget min(N_s, 100) // 4, selected
+    by the GPU as one batch and by the oracle instance by instance (timed: the cpu_baseline)."""
+    import numpy as np
+
+    import oracle
+    from oed_inputs import k_sub_lower
+    from paper_2604_08812_amd import BatchSelector, Selector
+    same, worst = 0, 0.0
+    for (K, N_s, N_t, s2, B), (idx, gain, stt) in zip(items, res):
+        kw = {"method": "left", "max_budget": B} if method == "left" else {"delay": delay}
+        with Selector(K, N_s, N_t, s2, precision=prec, **kw) as sel:
+            i1, g1 = sel.greedy(B)
+        if stt == 0 and list(idx) == list(i1):
+            same += 1
+            worst = max(worst, float(np.max(np.abs(gain - g1) / np.maximum(1.0, np.abs(g1)))))
+    out = {"batch_vs_single_handles": {"instances_with_equal_picks": same, "instances": len(items),
+                                       "max_rel_gain_diff": worst}}
+    if args.no_cpu_baseline:
+        return out
+    sample = [(q, min(sp.N_s, 100)) for q, sp in enumerate(specs) if sp.N_t <= 32]
+    sub_items = [(items[q][0], n, specs[q].N_t, items[q][3], n // 4) for q, n in sample]
+    kw = {"method": "left"} if method == "left" else {"delay": delay}
+    with BatchSelector(sub_items, precision=prec, **kw) as sb:
+        gres = sb.run()
+    threads = oracle.default_threads()
+    agree, gerr, secs, flops = 0, 0.0, 0.0, 0.0
+    for (q, n), (idx, gain, _) in zip(sample, gres):
+        sp = specs[q]
+        sub = k_sub_lower(items[q][0], sp.N_t, range(n))
+        t0 = time.perf_counter()
+        ref = oracle.greedy(sub, n, sp.N_t, items[q][3], n // 4, threads=threads)
+        secs += time.perf_counter() - t0
+        flops += naive_flops(n, sp.N_t, n // 4)
+        if list(ref["idx"]) == list(idx):
+            agree += 1
+            gerr = max(gerr, float(np.max(np.abs(gain - ref["gain"]) / np.maximum(1.0, np.abs(ref["gain"])))))
+    steps = sum(n // 4 for _, n in sample)
+    out["cpu_baseline"] = {
+        "value": round(steps / secs, 4), "unit": "greedy steps/s", "cores": threads, "kind": "oracle",
+        "sample": f"the {len(sample)} instances with N_t <= 32, each on its first min(N_s, 100) sensors with "
+                  f"budget min(N_s, 100) // 4 ({steps} picks), {secs:.1f} s",
+        "seconds": round(secs, 2), "oracle_gflops": round(flops / secs / 1e9, 2), "cpu_model": cpu_model(),
+        "gpu_same_sample_instances_with_equal_picks": agree, "gpu_same_sample_instances": len(sample),
+        "gpu_same_sample_max_rel_gain_err": gerr}
+    return out
+
+
 def run_batched(args):
     """The 48 uneven designs (seeds 100+i), FP32 K, mixed precision, one graph launch per run."""
     import torch
@@ -413,22 +463,25 @@ def run_batched(args):
     tune = args.delay == 0 and not args.no_autotune and not args.left
     bs = BatchSelector(items, precision=args.precision or "mixed_f32", profile=True, delay=args.delay, autotune=tune,
                        method="left" if args.left else "right")
-    delay, tuned = bs.config()
+    delay, tuned, tiles = bs.config()
     for w in range(args.warmup):
         bs.reset(items)
         bs.run()
     ms_list = []
+    res = None
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for s in range(args.steps):
         bs.reset(items)
-        bs.run()
+        res = bs.run()
         ms_list.append(bs.stats()["run_ms"])
     torch.cuda.synchronize()
     ms = (time.perf_counter() - t0) * 1e3 / args.steps
     st = bs.stats()
     run_ms = sum(ms_list) / len(ms_list)
     bs.close()
+    prec = args.precision or "mixed_f32"
+    checks = batched_checks(specs, items, res, prec, delay, "left" if args.left else "right", args)
     gbs = st["syrk_bytes"] / (run_ms * 1e-3) / 1e9
     result = {
         "metric": "greedy steps/s + SYRK TFLOP/s (% MFMA peak), mixed vs FP64, same picks",
@@ -436,7 +489,8 @@ def run_batched(args):
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms, 3), "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
         "config": {"workload": "batched_48_uneven", "instances": len(specs), "total_picks": total_steps,
-                   "precision": args.precision or "mixed_f32", "K_dtype": "f32", "delay": delay, "autotuned": tune,
+                   "precision": args.precision or "mixed_f32", "K_dtype": "f32", "delay": delay, "tile_order": tiles,
+                   "autotuned": tune,
                    "method": "left-looking" if args.left else "right-looking",
                    "autotuner_run_ms_by_delay": [round(float(x), 3) for x in tuned] if tune else None,
                    "step": "oed_batch_reset + oed_batch_run"},
@@ -445,6 +499,7 @@ def run_batched(args):
                      "note": "algorithmic downdate bytes / whole-run time (gains, picks and W included in the time)",
                      "syrk_tflops_over_run": round(st["syrk_flops"] / (run_ms * 1e-3) / 1e12, 3)},
         "graph_run_ms": round(run_ms, 3),
+        **checks,
     }
     if not args.left and not args.no_left:
         # the same designs left-looking (only each pick's block column formed), beside it
@@ -501,7 +556,7 @@ def main():
     # ---- headline path
     tune = args.delay == 0 and not args.no_autotune
     sel = Selector(K, spec.N_s, spec.N_t, s2, precision=prec, profile=True, delay=args.delay, autotune=tune)
-    delay, variant, tuned = sel.config()
+    delay, variant, tuned, tiles = sel.config()
     for w in range(args.warmup):
         timed_selections(sel, K, budget, 1)
         log(f"warmup {w + 1}/{args.warmup} done")
@@ -524,7 +579,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": spec.name, "N_s": spec.N_s, "N_t": spec.N_t, "n_m": spec.n_m, "seed": spec.seed,
                    "budget": budget, "precision": prec, "K_dtype": spec.k_dtype, "delay": delay,
-                   "downdate_variant": ["direct", "lds"][variant], "autotuned": tune,
+                   "downdate_variant": ["direct", "lds"][variant], "tile_order": tiles, "autotuned": tune,
                    "autotuner_ms_per_pick_by_delay": [round(float(x), 4) for x in tuned] if tune else None,
                    "step": "oed_reset + oed_greedy(budget)"},
         "roofline": roofline_syrk(prof, prec, spec.name, delay),

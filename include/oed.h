@@ -121,8 +121,34 @@ typedef struct oed_options {
                                    candidate then scores 1/2 logdet S_j - h_j.  NULL = isotropic
                                    noise sigma2: h_j = (N_t/2) ln sigma2.  Copied during oed_create;
                                    non-finite entries: OED_E_ARG. */
-    int32_t reserved[4];        /* must be 0 */
+    const char *tune_cache;     /* path of a text file the autotuner (OED_FLAG_AUTOTUNE) reads its
+                                   choice from and appends a newly tuned one to, keyed by the GPU's
+                                   name, precision, block size, candidate count / 32 and method;
+                                   NULL = keep choices in the process only.  An unreadable or
+                                   unwritable file is ignored (the tuner then times as usual). */
+    int64_t max_device_bytes;   /* 0 = no limit; else oed_create returns OED_E_OOM, before any
+                                   allocation or other HIP call, when the handle would hold more
+                                   device memory than this (oed_last_error(NULL) gives the bytes) */
+    int32_t tile_order;         /* downdate tile order, OED_TILES_*: 0 = automatic (the autotuner's
+                                   choice with OED_FLAG_AUTOTUNE, else OED_TILES_COL4) */
+    int32_t debug_fail_step;    /* test hook for the error paths: k >= 1 makes the k-th pick after
+                                   creation (or the last reset) fail once with OED_E_HIP on the
+                                   host, before anything of that step is enqueued; 0 = off */
+    int32_t reserved[2];        /* must be 0 */
 } oed_options;
+
+/*
+ * oed_options.tile_order: the order in which the downdate's 128 x 128 tiles of the lower
+ * triangle are handed out (one contiguous share per XCD).  Tiles are grouped in b x b
+ * super-tiles swept band by band; COL orders run down each super-tile's columns, so the tiles
+ * sharing a column panel of W are consecutive and the band's b row panels stay in the XCD's L2;
+ * ROW8 runs along the rows of 8 x 8 super-tiles.  The order changes only speed, never results.
+ */
+#define OED_TILES_AUTO 0
+#define OED_TILES_ROW8 1
+#define OED_TILES_COL8 2
+#define OED_TILES_COL4 3
+#define OED_TILES_COL2 4
 
 /*
  * oed_options.method.
@@ -214,7 +240,10 @@ OED_API oed_status oed_scores(oed_ctx *h, double *gains_out);
 /*
  * Block (i, j) of the current Schur complement of the remaining candidates
  * (both i and j remaining candidates), in FP64, unpadded, row-major N_t x N_t
- * into host memory out.  Any order of i, j is accepted (R is symmetric).
+ * into host memory out.  Any order of i, j is accepted (R is symmetric).  The
+ * block is formed on the device (left-looking: the stored K block minus the
+ * formed block columns' products) and copied to the host; a diagnostic query,
+ * not part of the greedy loop.
  */
 OED_API oed_status oed_schur_block(oed_ctx *h, int32_t i, int32_t j, double *out);
 
@@ -264,14 +293,17 @@ typedef struct oed_batch oed_batch;
 /* Without OED_BATCH_DELAY: run the whole selection once per delay depth during creation and
    keep the fastest (see oed_batch_get_config). */
 #define OED_BATCH_AUTOTUNE 0x10u
+/* Downdate tile order o (OED_TILES_*, see oed_options.tile_order); without it OED_TILES_COL4, or
+   the autotuner's choice with OED_BATCH_AUTOTUNE. */
+#define OED_BATCH_TILES(o) ((uint32_t)(o) << 12)
 /* Left-looking method for every instance (see OED_METHOD_LEFT_LOOKING; no delay, no autotuner). */
 #define OED_BATCH_LEFT_LOOKING 0x20u
 
 /*
  * Create a batch over inst[0..n): validates every instance, allocates all device memory,
  * packs every working copy and builds the launch schedule.  flags: OED_FLAG_PROFILE (time
- * each run with HIP events), OED_BATCH_NO_GRAPH, OED_BATCH_DELAY(p), OED_BATCH_AUTOTUNE,
- * OED_BATCH_LEFT_LOOKING.  On failure
+ * each run with HIP events), OED_BATCH_NO_GRAPH, OED_BATCH_DELAY(p), OED_BATCH_TILES(o),
+ * OED_BATCH_AUTOTUNE, OED_BATCH_LEFT_LOOKING.  On failure
  * *out is NULL.
  */
 OED_API oed_status oed_batch_create(oed_batch **out, const oed_instance *inst, int32_t n, int32_t precision,
@@ -287,16 +319,21 @@ OED_API oed_status oed_batch_create(oed_batch **out, const oed_instance *inst, i
 OED_API oed_status oed_batch_run(oed_batch *b, int32_t *idx_out, double *gain_out, int32_t *n_out,
                                  int32_t *status_out);
 
-/* Reload every working copy from inst[] (same shapes as at creation); allocates nothing. */
+/* Reload every working copy from inst[] (same shapes, dtypes and leading dimensions as at
+ * creation, else OED_E_ARG); allocates nothing.  The packing is ordered after all work enqueued
+ * so far on the stream given at creation (where the caller may still be writing K), and the call
+ * returns once it is done, so K may be changed or freed afterwards. */
 OED_API oed_status oed_batch_reset(oed_batch *b, const oed_instance *inst, int32_t n);
 
 /* Milliseconds of the last run (HIP events around it; needs OED_FLAG_PROFILE), and the
  * algorithmic downdate flops and bytes of one run (definitions as in oed_profile). */
 OED_API oed_status oed_batch_stats(const oed_batch *b, double *run_ms, double *syrk_flops, double *syrk_bytes);
 
-/* The delay depth the batch runs with, and with OED_BATCH_AUTOTUNE the autotuner's run time
-   for depths 1..OED_MAX_DELAY (OED_MAX_DELAY doubles, host; may be NULL). */
-OED_API oed_status oed_batch_get_config(const oed_batch *b, int32_t *delay, double *per_run_ms);
+/* The delay depth and the downdate tile order (OED_TILES_*) the batch runs with, and with
+   OED_BATCH_AUTOTUNE the autotuner's run time for depths 1..OED_MAX_DELAY in the default tile
+   order (OED_MAX_DELAY doubles, host); the tuner then also tries the other orders at the chosen
+   depth.  Any output pointer may be NULL. */
+OED_API oed_status oed_batch_get_config(const oed_batch *b, int32_t *delay, int32_t *tile_order, double *per_run_ms);
 OED_API oed_status oed_batch_destroy(oed_batch *b);
 OED_API const char *oed_batch_last_error(const oed_batch *b);
 
@@ -392,17 +429,20 @@ OED_API oed_status oed_device_bytes(const oed_ctx *h, int64_t *bytes);
 
 /*
  * The configuration the handle runs with: *delay (1..OED_MAX_DELAY), *syrk_variant (0: per-wave
- * global operands, 1: LDS-staged, -1: left-looking, no downdate), and, if per_pick_ms is not
- * NULL, the autotuner's estimate of the time per pick for delay depths 1..OED_MAX_DELAY
- * (OED_MAX_DELAY doubles, host; 0 where not measured, all 0 without OED_FLAG_AUTOTUNE).  Any
- * output pointer may be NULL.
+ * global operands, 1: LDS-staged, -1: left-looking, no downdate), *tile_order (OED_TILES_*: the
+ * downdate's tile order, chosen by the autotuner unless given), and, if per_pick_ms is not NULL,
+ * the autotuner's estimate of the time per pick for delay depths 1..OED_MAX_DELAY (OED_MAX_DELAY
+ * doubles, host; 0 where not measured, all 0 without OED_FLAG_AUTOTUNE).  Any output pointer may
+ * be NULL.
  */
-OED_API oed_status oed_get_config(const oed_ctx *h, int32_t *delay, int32_t *syrk_variant, double *per_pick_ms);
+OED_API oed_status oed_get_config(const oed_ctx *h, int32_t *delay, int32_t *syrk_variant, int32_t *tile_order,
+                                  double *per_pick_ms);
 
 /* Destroy the handle and free its device memory.  NULL is accepted. */
 OED_API oed_status oed_destroy(oed_ctx *h);
 
-/* Text of the handle's last error ("" if none; a static string for NULL). */
+/* Text of the handle's last error ("" if none).  For NULL: the text of the last failed
+ * oed_create on the calling thread ("" if none). */
 OED_API const char *oed_last_error(const oed_ctx *h);
 
 /* Name of a status code. */

@@ -40,6 +40,7 @@ struct oed_ctx {
     int prec = OED_PREC_FP64;
     int rtype = R_F64, wtype = W_F64;
     int syrk_variant = SYRK_LDS;
+    int stl = STL_COL4;  // downdate super-tile order (see super_tile())
     int delay = 1;  // > 1: up to delay - 1 block columns held and subtracted with the next one
     double tuned_ms[MAX_DELAY] = {0};  // autotuner: estimated time per pick for delay 1..MAX_DELAY
     // left-looking: R keeps K off the diagonal; W slot k holds pick k's block column
@@ -49,6 +50,8 @@ struct oed_ctx {
     void *C = nullptr;         // column partial sums (LEFT_SPLITS x N_c blocks, R's type)
     double *noise_h = nullptr; // per-sensor noise terms by local index (device), or null
     uint32_t flags = 0;
+    std::string tune_cache;  // autotuner cache file ("" = in-process only)
+    int fail_step = 0;       // test hook: the fail_step-th pick since creation / reset fails once
     hipStream_t stream = nullptr;
     int device = 0;
     std::vector<int> cmap;  // local -> original sensor index (ascending)
@@ -85,6 +88,9 @@ struct oed_ctx {
 };
 
 namespace {
+
+// Text of the calling thread's last failed oed_create (oed_last_error(NULL)).
+thread_local std::string g_create_err;
 
 oed_status fail(oed_ctx *h, oed_status st, const std::string &msg)
 {
@@ -207,6 +213,7 @@ StepDesc desc(const oed_ctx *h)
     d.nheld = h->nheld;
     d.V = h->V;
     d.nw = 1;
+    d.stl = h->stl;
     d.act_in = h->act[h->cur];
     d.act_out = h->act[h->cur ^ 1];
     d.gains = h->gains;
@@ -228,7 +235,7 @@ StepDesc desc(const oed_ctx *h)
 
 oed_status enqueue_syrk(oed_ctx *h, StepDesc d)
 {
-    d.nitems = syrk_tiles(h->n_act, h->N_tp);
+    d.nitems = syrk_tiles(h->n_act, h->N_tp, h->stl);
     {
         Prof pr(h, OED_K_SYRK);
         HIPCHK(h, launch_syrk(d, h->rtype, h->wtype, h->syrk_variant, h->stream));
@@ -323,13 +330,19 @@ oed_status advance(oed_ctx *h, bool full)
 //
 // On the freshly packed working copy it times, per delay depth p = 1..MAX_DELAY, the kernels of
 // one pick: the gains and the block column with h = 0 .. p-1 block columns held, the V
-// correction for h > 0, and the downdate of p block columns; the per-pick cost is
-// t_syrk(p)/p + (1/p) sum_h (t_gain(h) + t_vcorr(h) + t_trsm(h)), taken at the first step's
-// candidate count and at half of it (the leading half of the active list) and averaged; the
-// choice is the least estimate (the shallowest on ties).  The W slots are zero while
-// the downdates are timed, so R - 0 leaves R exactly as packed; the gains, L_s^-1 and W
-// buffers it writes are overwritten by the first step.  Both downdate variants are timed at
-// p = 1.  Results are cached per (device, precision, N_tp, ceil(N_c / 32)).
+// correction for h > 0, and the downdate of p block columns in every tile order of TUNE_ORDERS
+// (both downdate variants at p = 1, in the default order); the per-pick cost is
+// min over orders of t_syrk(p)/p + (1/p) sum_h (t_gain(h) + t_vcorr(h) + t_trsm(h)), taken at the
+// first step's candidate count and at half of it (the leading half of the active list) and
+// averaged; the choice is the least estimate (the shallowest depth on ties).  The W slots are
+// zero while the downdates are timed, so R - 0 leaves R exactly as packed; the gains, L_s^-1 and
+// W buffers it writes are overwritten by the first step.  Results are cached per (device,
+// precision, N_tp, ceil(N_c / 32)) in the process and, with oed_options.tune_cache, in a text file
+// keyed by the GPU's architecture name and compute-unit count instead of the device index; a
+// matching line of the file takes precedence over the process's cache.
+
+constexpr int TUNE_ORDERS[] = {STL_COL4, STL_COL8, STL_ROW8};
+constexpr int N_TUNE_ORDERS = sizeof(TUNE_ORDERS) / sizeof(TUNE_ORDERS[0]);
 
 struct TuneKey {
     int dev, prec, ntp, nbucket;
@@ -339,11 +352,75 @@ struct TuneKey {
     }
 };
 struct TuneVal {
-    int delay, variant;
+    int delay, variant, stl;
     double ms[MAX_DELAY];
 };
 std::mutex g_tune_mu;
 std::map<TuneKey, TuneVal> g_tune;
+
+// The tune-cache line of a handle's shape on its GPU: "oedtune1 <arch> <CUs> <precision> <N_tp>
+// <candidates/32>" followed by "<delay> <variant> <tile code> <ms per pick for delay 1..8>".
+std::string tune_cache_key(const oed_ctx *h)
+{
+    hipDeviceProp_t prop;
+    std::string arch = "unknown";
+    int cus = 0;
+    if (hipGetDeviceProperties(&prop, h->device) == hipSuccess) {
+        arch = prop.gcnArchName;
+        cus = prop.multiProcessorCount;
+    }
+    for (char &c : arch)
+        if (c == ' ') c = '_';
+    return "oedtune1 " + arch + " " + std::to_string(cus) + " " + std::to_string(h->prec) + " " +
+           std::to_string(h->N_tp) + " " + std::to_string((h->N_c + 31) / 32);
+}
+
+bool tune_cache_read(const oed_ctx *h, const std::string &key, TuneVal &v)
+{
+    FILE *f = std::fopen(h->tune_cache.c_str(), "r");
+    if (!f) return false;
+    char line[1024];
+    bool found = false;
+    while (std::fgets(line, sizeof(line), f)) {
+        std::string ln(line);
+        if (ln.compare(0, key.size(), key) != 0 || ln.size() <= key.size() || ln[key.size()] != ' ') continue;
+        TuneVal t{};
+        const char *p = ln.c_str() + key.size();
+        int used = 0;
+        if (std::sscanf(p, " %d %d %d%n", &t.delay, &t.variant, &t.stl, &used) != 3) continue;
+        p += used;
+        bool ok = t.delay >= 1 && t.delay <= MAX_DELAY && (t.variant == SYRK_DIRECT || t.variant == SYRK_LDS);
+        for (int q = 0; q < MAX_DELAY && ok; ++q) {
+            if (std::sscanf(p, " %lf%n", &t.ms[q], &used) != 1) ok = false;
+            p += used;
+        }
+        ok = ok && std::find(TUNE_ORDERS, TUNE_ORDERS + N_TUNE_ORDERS, t.stl) != TUNE_ORDERS + N_TUNE_ORDERS;
+        if (ok) {
+            v = t;  // the last matching line wins
+            found = true;
+        }
+    }
+    std::fclose(f);
+    return found;
+}
+
+void tune_cache_append(const oed_ctx *h, const std::string &key, const TuneVal &v)
+{
+    FILE *f = std::fopen(h->tune_cache.c_str(), "a");
+    if (!f) return;
+    std::fprintf(f, "%s %d %d %d", key.c_str(), v.delay, v.variant, v.stl);
+    for (int q = 0; q < MAX_DELAY; ++q) std::fprintf(f, " %.6g", v.ms[q]);
+    std::fprintf(f, "\n");
+    std::fclose(f);
+}
+
+void tune_apply(oed_ctx *h, const TuneVal &v)
+{
+    h->delay = v.delay;
+    h->syrk_variant = v.variant;
+    h->stl = v.stl;
+    std::copy(v.ms, v.ms + MAX_DELAY, h->tuned_ms);
+}
 
 // Milliseconds of one call of f (the minimum over three rounds).
 template <typename F>
@@ -367,13 +444,23 @@ hipError_t time_ms(oed_ctx *h, hipEvent_t a, hipEvent_t b, F f, double *out)
 oed_status autotune(oed_ctx *h)
 {
     const TuneKey key{h->device, h->prec, h->N_tp, (h->N_c + 31) / 32};
+    // the cache file first (it outlives the process), then the process's own choices
+    const std::string ckey = h->tune_cache.empty() ? std::string() : tune_cache_key(h);
+    if (!ckey.empty()) {
+        TuneVal v;
+        if (tune_cache_read(h, ckey, v)) {
+            tune_apply(h, v);
+            std::lock_guard<std::mutex> lk(g_tune_mu);
+            g_tune[key] = v;
+            return OED_OK;
+        }
+    }
     {
         std::lock_guard<std::mutex> lk(g_tune_mu);
         auto it = g_tune.find(key);
         if (it != g_tune.end()) {
-            h->delay = it->second.delay;
-            h->syrk_variant = it->second.variant;
-            std::copy(it->second.ms, it->second.ms + MAX_DELAY, h->tuned_ms);
+            tune_apply(h, it->second);
+            if (!ckey.empty()) tune_cache_append(h, ckey, it->second);
             return OED_OK;
         }
     }
@@ -397,7 +484,7 @@ oed_status autotune(oed_ctx *h)
     if (e == hipSuccess) e = hipMemsetAsync(h->Linv, 0, sizeof(double) * bs, h->stream);
     // the per-pick estimates at the first step's size n and at n / 2, averaged: the run's later
     // steps work on fewer candidates, where each launch's fixed cost weighs more
-    double t_step[2][MAX_DELAY] = {{0}}, t_syrk[2][MAX_DELAY] = {{0}}, t_direct[2] = {1e300, 1e300};
+    double t_step[2][MAX_DELAY] = {{0}}, t_syrk[2][MAX_DELAY][N_TUNE_ORDERS] = {}, t_direct[2] = {1e300, 1e300};
     const int n_at[2] = {h->n_act, std::max(1, h->n_act / 2)};
     for (int z = 0; z < 2 && e == hipSuccess; ++z) {
         for (int hh = 0; hh < MAX_DELAY && e == hipSuccess; ++hh) {
@@ -416,29 +503,42 @@ oed_status autotune(oed_ctx *h)
         }
         if (e == hipSuccess) e = zero_w();
         for (int p = 1; p <= MAX_DELAY && e == hipSuccess; ++p) {
-            StepDesc d = desc(h);
-            d.n_act = n_at[z];
-            d.nheld = 0;
-            d.nw = p;
-            d.nitems = syrk_tiles(n_at[z], h->N_tp);
-            e = time_ms(h, a, b, [&] { return launch_syrk(d, h->rtype, h->wtype, SYRK_LDS, h->stream); },
-                        &t_syrk[z][p - 1]);
-            if (e == hipSuccess && p == 1 && h->wtype != W_BF16X3)
-                e = time_ms(h, a, b, [&] { return launch_syrk(d, h->rtype, h->wtype, SYRK_DIRECT, h->stream); },
-                            &t_direct[z]);
+            for (int o = 0; o < N_TUNE_ORDERS && e == hipSuccess; ++o) {
+                StepDesc d = desc(h);
+                d.n_act = n_at[z];
+                d.nheld = 0;
+                d.nw = p;
+                d.stl = TUNE_ORDERS[o];
+                d.nitems = syrk_tiles(n_at[z], h->N_tp, d.stl);
+                e = time_ms(h, a, b, [&] { return launch_syrk(d, h->rtype, h->wtype, SYRK_LDS, h->stream); },
+                            &t_syrk[z][p - 1][o]);
+                if (e == hipSuccess && p == 1 && o == 0 && h->wtype != W_BF16X3)
+                    e = time_ms(h, a, b, [&] { return launch_syrk(d, h->rtype, h->wtype, SYRK_DIRECT, h->stream); },
+                                &t_direct[z]);
+            }
         }
     }
     if (e != hipSuccess) return done(fail(h, e == hipErrorOutOfMemory ? OED_E_OOM : OED_E_HIP,
                                           std::string("autotune: ") + hipGetErrorString(e)));
-    TuneVal v{1, SYRK_LDS, {0}};
-    const bool direct = t_direct[0] + t_direct[1] < t_syrk[0][0] + t_syrk[1][0];
+    TuneVal v{1, SYRK_LDS, TUNE_ORDERS[0], {0}};
+    int best_o[MAX_DELAY] = {0};
     double best = 1e300;
     for (int p = 1; p <= MAX_DELAY; ++p) {
+        // the tile order with the least downdate time over both sizes
+        double tbest = 1e300;
+        for (int o = 0; o < N_TUNE_ORDERS; ++o) {
+            const double t = t_syrk[0][p - 1][o] + t_syrk[1][p - 1][o];
+            if (t < tbest) {
+                tbest = t;
+                best_o[p - 1] = o;
+            }
+        }
+        const bool direct = p == 1 && t_direct[0] + t_direct[1] < tbest;
         double sum = 0;
         for (int z = 0; z < 2; ++z) {
             double steps = 0;
             for (int hh = 0; hh < p; ++hh) steps += t_step[z][hh];
-            const double syrk = (p == 1 && direct) ? t_direct[z] : t_syrk[z][p - 1];
+            const double syrk = direct ? t_direct[z] : t_syrk[z][p - 1][best_o[p - 1]];
             sum += (syrk + steps) / p;
         }
         v.ms[p - 1] = 0.5 * sum;
@@ -449,16 +549,18 @@ oed_status autotune(oed_ctx *h)
     for (int p = 1; p <= MAX_DELAY; ++p)
         if (v.ms[p - 1] <= best) {
             v.delay = p;
-            v.variant = (p == 1 && direct) ? SYRK_DIRECT : SYRK_LDS;
+            v.stl = TUNE_ORDERS[best_o[p - 1]];
+            v.variant = (p == 1 && t_direct[0] + t_direct[1] < t_syrk[0][0][best_o[0]] + t_syrk[1][0][best_o[0]])
+                            ? SYRK_DIRECT : SYRK_LDS;
+            if (v.variant == SYRK_DIRECT) v.stl = TUNE_ORDERS[0];
             break;
         }
-    h->delay = v.delay;
-    h->syrk_variant = v.variant;
-    std::copy(v.ms, v.ms + MAX_DELAY, h->tuned_ms);
+    tune_apply(h, v);
     {
         std::lock_guard<std::mutex> lk(g_tune_mu);
         g_tune[key] = v;
     }
+    if (!ckey.empty()) tune_cache_append(h, ckey, v);
     return done(OED_OK);
 }
 
@@ -528,6 +630,40 @@ oed_status sync_picks(oed_ctx *h, int k0, oed_status *dev_status)
     return OED_OK;
 }
 
+// The debug_fail_step hook: the fail_step-th pick since creation or the last reset fails once,
+// on the host, before anything of it is enqueued.
+oed_status step_hook(oed_ctx *h)
+{
+    if (h->fail_step > 0 && h->k + 1 == h->fail_step) {
+        h->fail_step = 0;
+        return fail(h, OED_E_HIP, "injected failure before pick " + std::to_string(h->k + 1) +
+                                      " (oed_options.debug_fail_step)");
+    }
+    return OED_OK;
+}
+
+// A step failed before or while it was enqueued: wait for what was enqueued before it, hand back
+// the picks it made (if the outputs are given), and stop the handle until oed_reset.  The first
+// failure's status and text are kept.
+oed_status stop_after_failure(oed_ctx *h, oed_status st, int k0, int32_t *idx_out, double *gain_out, int32_t *n_out)
+{
+    const std::string msg = h->err;
+    // the failing step's pick was not enqueued: the mirror counts only launched picks
+    oed_status dev = OED_OK;
+    if (sync_picks(h, k0, &dev) == OED_OK && idx_out && gain_out) {
+        const int made = (int)h->h_picks.size() - k0;
+        for (int q = 0; q < made; ++q) {
+            idx_out[q] = h->cmap[h->h_picks[k0 + q]];
+            gain_out[q] = h->h_gains[k0 + q];
+        }
+        if (n_out) *n_out = made;
+    }
+    h->poisoned = true;
+    h->pending = false;
+    h->err = msg;
+    return st;
+}
+
 }  // namespace
 
 extern "C" {
@@ -554,44 +690,53 @@ const char *oed_status_string(int32_t s)
     }
 }
 
-const char *oed_last_error(const oed_ctx *h) { return h ? h->err.c_str() : "null handle"; }
+const char *oed_last_error(const oed_ctx *h) { return h ? h->err.c_str() : g_create_err.c_str(); }
 
 oed_status oed_create(oed_ctx **out, const void *K, int32_t dtype, int64_t ld, int32_t N_s, int32_t N_t,
                       double sigma2, void *stream, const oed_options *opt)
 {
-    if (!out) return OED_E_ARG;
+    g_create_err.clear();
+    auto cfail = [](oed_status st, const std::string &msg) {
+        g_create_err = msg;
+        return st;
+    };
+    if (!out) return cfail(OED_E_ARG, "out is NULL");
     *out = nullptr;
     oed_options o;
     oed_options_init(&o);
     if (opt) {
-        if (opt->struct_size != sizeof(oed_options)) return OED_E_ARG;
+        if (opt->struct_size != sizeof(oed_options)) return cfail(OED_E_ARG, "oed_options.struct_size mismatch");
         o = *opt;
     }
     const bool deferred = (o.flags & OED_FLAG_DEFER_PACK) != 0;
     if (deferred) {
         // no K: dtype and ld are not used
-        if (K || (o.flags & OED_FLAG_AUTOTUNE)) return OED_E_ARG;
+        if (K || (o.flags & OED_FLAG_AUTOTUNE)) return cfail(OED_E_ARG, "deferred packing takes no K and no autotuner");
         dtype = OED_F64;
         ld = (int64_t)N_s * N_t;
     }
     if ((!K && !deferred) || (dtype != OED_F64 && dtype != OED_F32) || N_s < 1 || N_t < 1 || N_t > 4096 ||
         ld < (int64_t)N_s * N_t || !(sigma2 > 0.0) || !std::isfinite(sigma2))
-        return OED_E_ARG;
+        return cfail(OED_E_ARG, "bad K, dtype, shape, leading dimension or sigma2");
     if (o.precision != OED_PREC_FP64 && o.precision != OED_PREC_MIXED_F32 && o.precision != OED_PREC_MIXED_BF16X3)
-        return OED_E_ARG;
-    if (o.precision == OED_PREC_MIXED_BF16X3 && N_t > 128) return OED_E_UNSUPPORTED;
-    if (o.delay < 0 || o.delay > MAX_DELAY) return OED_E_ARG;
+        return cfail(OED_E_ARG, "unknown precision");
+    if (o.precision == OED_PREC_MIXED_BF16X3 && N_t > 128)
+        return cfail(OED_E_UNSUPPORTED, "the BF16 split product serves N_t <= 128");
+    if (o.delay < 0 || o.delay > MAX_DELAY) return cfail(OED_E_ARG, "delay out of range");
     if (o.method != OED_METHOD_RIGHT_LOOKING && o.method != OED_METHOD_LEFT_LOOKING && o.method != OED_METHOD_AUTO)
-        return OED_E_ARG;
-    if (o.max_budget < 0 || o.max_budget > N_s) return OED_E_ARG;
+        return cfail(OED_E_ARG, "unknown method");
+    if (o.max_budget < 0 || o.max_budget > N_s) return cfail(OED_E_ARG, "max_budget out of range");
     // left-looking needs the diagonal-block update of the register or blocked gain kernels
-    if (o.method == OED_METHOD_LEFT_LOOKING && N_t > BLK_MAX_NTP) return OED_E_UNSUPPORTED;
-    if (o.delay > 1 && N_t > REGS_MAX_NT) return OED_E_UNSUPPORTED;
+    if (o.method == OED_METHOD_LEFT_LOOKING && N_t > BLK_MAX_NTP)
+        return cfail(OED_E_UNSUPPORTED, "the left-looking method serves N_t <= 1024");
+    if (o.delay > 1 && N_t > REGS_MAX_NT) return cfail(OED_E_UNSUPPORTED, "delay > 1 needs N_t <= 128");
+    if (o.tile_order < OED_TILES_AUTO || o.tile_order > OED_TILES_COL2) return cfail(OED_E_ARG, "unknown tile order");
+    if (o.max_device_bytes < 0 || o.debug_fail_step < 0) return cfail(OED_E_ARG, "negative limit or hook step");
     for (int r : o.reserved)
-        if (r != 0) return OED_E_ARG;
+        if (r != 0) return cfail(OED_E_ARG, "reserved option fields must be 0");
 
     oed_ctx *h = new (std::nothrow) oed_ctx();
-    if (!h) return OED_E_OOM;
+    if (!h) return cfail(OED_E_OOM, "host allocation of the handle failed");
     h->N_s = N_s;
     h->N_t = N_t;
     // the BF16 operands hold 32 inner indices per lane group of four
@@ -604,6 +749,10 @@ oed_status oed_create(oed_ctx **out, const void *K, int32_t dtype, int64_t ld, i
     h->rtype = o.precision == OED_PREC_FP64 ? R_F64 : R_F32;
     h->wtype = o.precision == OED_PREC_FP64 ? W_F64 : o.precision == OED_PREC_MIXED_F32 ? W_F32 : W_BF16X3;
     h->flags = o.flags;
+    h->fail_step = o.debug_fail_step;
+    if (o.tune_cache) h->tune_cache = o.tune_cache;
+    static const int stl_of[] = {STL_COL4, STL_ROW8, STL_COL8, STL_COL4, STL_COL2};
+    h->stl = stl_of[o.tile_order];
     // delay 0 (automatic): hold block columns whenever the register factorisations and the LDS
     // downdate serve the block size
     h->delay = o.delay == 0 ? (N_t <= REGS_MAX_NT ? DEFAULT_DELAY : 1) : o.delay;
@@ -614,20 +763,22 @@ oed_status oed_create(oed_ctx **out, const void *K, int32_t dtype, int64_t ld, i
     }
     h->left = o.method == OED_METHOD_LEFT_LOOKING;
     if (h->left) h->delay = 1;
+    // the autotuner chooses the depth and, unless one is given, the tile order
     const bool tune = !h->left && o.delay == 0 && (o.flags & OED_FLAG_AUTOTUNE) && N_t <= REGS_MAX_NT;
+    const bool tune_tiles = tune && o.tile_order == OED_TILES_AUTO;
     h->stream = (hipStream_t)stream;
     h->lmap.assign(N_s, -1);
     if (o.candidates) {
         if (o.n_candidates < 1 || o.n_candidates > N_s) {
             delete h;
-            return OED_E_ARG;
+            return cfail(OED_E_ARG, "n_candidates out of range");
         }
         h->cmap.assign(o.candidates, o.candidates + o.n_candidates);
         std::sort(h->cmap.begin(), h->cmap.end());
         for (size_t q = 0; q < h->cmap.size(); ++q)
             if (h->cmap[q] < 0 || h->cmap[q] >= N_s || (q > 0 && h->cmap[q] == h->cmap[q - 1])) {
                 delete h;
-                return OED_E_ARG;
+                return cfail(OED_E_ARG, "candidate out of range or repeated");
             }
     } else {
         h->cmap.resize(N_s);
@@ -641,42 +792,58 @@ oed_status oed_create(oed_ctx **out, const void *K, int32_t dtype, int64_t ld, i
             hloc[q] = o.noise_half_logdet[h->cmap[q]];
             if (!std::isfinite(hloc[q])) {
                 delete h;
-                return OED_E_ARG;
+                return cfail(OED_E_ARG, "non-finite noise_half_logdet entry");
             }
         }
     }
     h->max_budget = (o.max_budget == 0 || o.max_budget > h->N_c) ? h->N_c : o.max_budget;
     for (int q = 0; q < h->N_c; ++q) h->lmap[h->cmap[q]] = q;
 
+    // every device buffer of the handle, sized before anything is allocated
+    const int64_t bs = (int64_t)h->N_tp * h->N_tp;
+    const int64_t nblk = (int64_t)h->N_c * (h->N_c + 1) / 2;
+    const size_t we = h->wtype == W_F64 ? 8 : h->wtype == W_F32 ? 4 : 2;
+    h->wslot = h->N_c * bs;
+    const int slots = h->left ? h->max_budget : tune ? MAX_DELAY : h->delay;
+    const size_t sg = gain_scratch_doubles(h->N_t, h->N_tp, h->N_c), sp = pick_scratch_doubles(h->N_t, h->N_tp);
+    struct Buf {
+        void **ptr;
+        size_t bytes;
+    };
+    const Buf bufs[] = {
+        {&h->R, (size_t)(nblk * bs) * relem(h)},
+        {&h->C, h->left ? (size_t)(LEFT_SPLITS * h->N_c * bs) * relem(h) : 0},
+        {&h->W, (size_t)(slots * h->wslot) * we},
+        {&h->W2, h->wtype == W_BF16X3 ? (size_t)(slots * h->wslot) * 2 : 0},
+        {(void **)&h->V, slots > 1 ? sizeof(double) * bs * (slots - 1) : 0},
+        {(void **)&h->Linv, sizeof(double) * bs},
+        {(void **)&h->gains, sizeof(double) * h->N_c},
+        {(void **)&h->pick_gain, sizeof(double) * h->N_c},
+        {(void **)&h->act[0], sizeof(int) * h->N_c},
+        {(void **)&h->act[1], sizeof(int) * h->N_c},
+        {(void **)&h->picks, sizeof(int) * h->N_c},
+        {(void **)&h->state, sizeof(int) * ST_WORDS},
+        {(void **)&h->dcmap, sizeof(int) * h->N_c},
+        {(void **)&h->scratch_gain, sizeof(double) * sg},
+        {(void **)&h->scratch_pick, sizeof(double) * sp},
+        {(void **)&h->noise_h, hloc.empty() ? 0 : sizeof(double) * h->N_c},
+    };
+    int64_t need = 0;
+    for (const Buf &b : bufs) need += (int64_t)b.bytes;
+    if (o.max_device_bytes > 0 && need > o.max_device_bytes) {
+        delete h;
+        return cfail(OED_E_OOM, "the handle needs " + std::to_string(need) + " bytes of device memory, more than "
+                                "max_device_bytes = " + std::to_string(o.max_device_bytes));
+    }
+
     oed_status st = OED_OK;
     auto setup = [&]() -> oed_status {
         HIPCHK(h, hipGetDevice(&h->device));
-        const int64_t bs = (int64_t)h->N_tp * h->N_tp;
-        const int64_t nblk = (int64_t)h->N_c * (h->N_c + 1) / 2;
-        HIPCHK(h, dmalloc(h, &h->R, (size_t)(nblk * bs) * relem(h)));
-        const size_t we = h->wtype == W_F64 ? 8 : h->wtype == W_F32 ? 4 : 2;
-        h->wslot = h->N_c * bs;
-        const int slots = h->left ? h->max_budget : tune ? MAX_DELAY : h->delay;
-        if (h->left) HIPCHK(h, dmalloc(h, &h->C, (size_t)(LEFT_SPLITS * h->N_c * bs) * relem(h)));
-        HIPCHK(h, dmalloc(h, &h->W, (size_t)(slots * h->wslot) * we));
-        if (h->wtype == W_BF16X3) HIPCHK(h, dmalloc(h, &h->W2, (size_t)(slots * h->wslot) * 2));
-        if (slots > 1) HIPCHK(h, dmalloc(h, (void **)&h->V, sizeof(double) * bs * (slots - 1)));
-        HIPCHK(h, dmalloc(h, (void **)&h->Linv, sizeof(double) * bs));
-        HIPCHK(h, dmalloc(h, (void **)&h->gains, sizeof(double) * h->N_c));
-        HIPCHK(h, dmalloc(h, (void **)&h->pick_gain, sizeof(double) * h->N_c));
-        HIPCHK(h, dmalloc(h, (void **)&h->act[0], sizeof(int) * h->N_c));
-        HIPCHK(h, dmalloc(h, (void **)&h->act[1], sizeof(int) * h->N_c));
-        HIPCHK(h, dmalloc(h, (void **)&h->picks, sizeof(int) * h->N_c));
-        HIPCHK(h, dmalloc(h, (void **)&h->state, sizeof(int) * ST_WORDS));
-        HIPCHK(h, dmalloc(h, (void **)&h->dcmap, sizeof(int) * h->N_c));
-        const size_t sg = gain_scratch_doubles(h->N_t, h->N_tp, h->N_c), sp = pick_scratch_doubles(h->N_t, h->N_tp);
-        if (sg) HIPCHK(h, dmalloc(h, (void **)&h->scratch_gain, sizeof(double) * sg));
-        if (sp) HIPCHK(h, dmalloc(h, (void **)&h->scratch_pick, sizeof(double) * sp));
+        for (const Buf &b : bufs)
+            if (b.bytes) HIPCHK(h, dmalloc(h, b.ptr, b.bytes));
         HIPCHK(h, hipMemcpyAsync(h->dcmap, h->cmap.data(), sizeof(int) * h->N_c, hipMemcpyHostToDevice, h->stream));
-        if (!hloc.empty()) {
-            HIPCHK(h, dmalloc(h, (void **)&h->noise_h, sizeof(double) * h->N_c));
+        if (!hloc.empty())
             HIPCHK(h, hipMemcpyAsync(h->noise_h, hloc.data(), sizeof(double) * h->N_c, hipMemcpyHostToDevice, h->stream));
-        }
         h->deferred = deferred;
         if (deferred) {
             h->row_packed.assign(h->N_c, 0);
@@ -686,11 +853,17 @@ oed_status oed_create(oed_ctx **out, const void *K, int32_t dtype, int64_t ld, i
         if (s2 != OED_OK) return s2;
         HIPCHK(h, hipStreamSynchronize(h->stream));
         collect_profile(h);
-        if (tune) return autotune(h);
+        if (tune) {
+            const int keep_stl = h->stl;
+            s2 = autotune(h);
+            if (!tune_tiles) h->stl = keep_stl;
+            return s2;
+        }
         return OED_OK;
     };
     st = setup();
     if (st != OED_OK) {
+        g_create_err = h->err;
         free_all(h);
         delete h;
         return st;
@@ -761,10 +934,11 @@ oed_status oed_greedy(oed_ctx *h, int32_t budget, int32_t *idx_out, double *gain
     if (budget > 0 && (!idx_out || !gain_out)) return fail(h, OED_E_ARG, "NULL output array");
     const int k0 = h->k;
     for (int step = 0; step < budget; ++step) {
-        oed_status st = advance(h, false);
+        oed_status st = step_hook(h);
+        if (st == OED_OK) st = advance(h, false);
         if (st == OED_OK) st = enqueue_gains(h);
         if (st == OED_OK) st = enqueue_pick(h, -1);
-        if (st != OED_OK) return st;
+        if (st != OED_OK) return stop_after_failure(h, st, k0, idx_out, gain_out, n_out);
     }
     oed_status dev = OED_OK;
     oed_status st = sync_picks(h, k0, &dev);
@@ -789,7 +963,9 @@ oed_status oed_force(oed_ctx *h, int32_t idx, double *gain_out)
         return fail(h, OED_E_ARG, "index is not a remaining candidate");
     const int k0 = h->k;
     if (h->left && h->k >= h->max_budget) return fail(h, OED_E_ARG, "max_budget picks already made");
-    oed_status st = advance(h, false);
+    oed_status st = step_hook(h);
+    if (st != OED_OK) return stop_after_failure(h, st, k0, nullptr, nullptr, nullptr);
+    st = advance(h, false);
     if (st == OED_OK && h->left && !h->diag_current) st = enqueue_gains(h);
     if (st == OED_OK) st = enqueue_pick(h, h->lmap[idx]);
     if (st != OED_OK) return st;
@@ -834,70 +1010,16 @@ oed_status oed_schur_block(oed_ctx *h, int32_t i, int32_t j, double *out)
     // left-looking: bring the diagonal blocks up to date (the gains are recomputed as a side effect)
     if (st == OED_OK && h->left && !h->diag_current) st = enqueue_gains(h);
     if (st != OED_OK) return st;
-    const int oi = li, oj = lj;
     const bool tr = li < lj;
     if (tr) std::swap(li, lj);
-    const int64_t bs = (int64_t)h->N_tp * h->N_tp;
-    const size_t e = relem(h);
-    std::vector<unsigned char> raw((size_t)bs * e);
-    HIPCHK(h, hipMemcpyAsync(raw.data(), (const char *)h->R + (size_t)(blk_index(li, lj) * bs) * e, raw.size(),
-                             hipMemcpyDeviceToHost, h->stream));
+    // the block is formed on the device into the L_s^-1 buffer (N_tp^2 >= N_t^2 doubles), which no
+    // step needs between here and the next pick: the last pick's block column is formed above
+    const int nsub = (h->left && li != lj) ? h->k : 0;
+    HIPCHK(h, launch_schur_block(h->R, h->rtype, h->W, h->W2, h->wtype, h->wslot, nsub, li, lj, tr ? 1 : 0, h->N_t,
+                                 h->N_tp, h->Linv, h->stream));
+    HIPCHK(h, hipMemcpyAsync(out, h->Linv, sizeof(double) * h->N_t * h->N_t, hipMemcpyDeviceToHost, h->stream));
     HIPCHK(h, hipStreamSynchronize(h->stream));
     collect_profile(h);
-    const int nb = h->N_tp / 16;
-    const bool diag = li == lj;
-    for (int t = 0; t < h->N_t; ++t)
-        for (int u = 0; u < h->N_t; ++u) {
-            // a diagonal block is current on its lower triangle only: mirror it
-            const int o = (diag && u > t) ? acc_off(u, t, nb) : acc_off(t, u, nb);
-            const double v = e == 8 ? ((const double *)raw.data())[o] : (double)((const float *)raw.data())[o];
-            if (tr)
-                out[(size_t)u * h->N_t + t] = v;
-            else
-                out[(size_t)t * h->N_t + u] = v;
-        }
-    if (h->left && !diag) {
-        // off the diagonal R still holds K: subtract sum_k W_k,i W_k,j^T over the formed columns
-        const size_t we = welem(h);
-        std::vector<unsigned char> wi((size_t)bs * we), wj((size_t)bs * we), wi2, wj2;
-        if (h->W2) {
-            wi2.resize(wi.size());
-            wj2.resize(wj.size());
-        }
-        auto bf = [](unsigned short x) {
-            const uint32_t u = (uint32_t)x << 16;
-            float f;
-            std::memcpy(&f, &u, 4);
-            return (double)f;
-        };
-        auto wval = [&](const std::vector<unsigned char> &w, const std::vector<unsigned char> &w2, int t, int m) {
-            if (we == 2) {  // BF16 hi + lo, 16 x 32 operand order
-                const int64_t o = ((int64_t)((t >> 4) * (nb / 2) + (m >> 5)) << 9) + ((((m & 31) >> 3) << 4) + (t & 15)) * 8 +
-                                  (m & 7);
-                return bf(((const unsigned short *)w.data())[o]) + bf(((const unsigned short *)w2.data())[o]);
-            }
-            // element (t, m) of a block in operand order
-            const int64_t o = ((int64_t)((t >> 4) * nb + (m >> 4)) << 8) + ((((m & 15) >> 2) << 4) + (t & 15)) * 4 + (m & 3);
-            return we == 8 ? ((const double *)w.data())[o] : (double)((const float *)w.data())[o];
-        };
-        for (int kk = 0; kk < h->k; ++kk) {
-            const char *base = (const char *)h->W + (size_t)(kk * h->wslot) * we;
-            HIPCHK(h, hipMemcpyAsync(wi.data(), base + (size_t)(oi * bs) * we, wi.size(), hipMemcpyDeviceToHost, h->stream));
-            HIPCHK(h, hipMemcpyAsync(wj.data(), base + (size_t)(oj * bs) * we, wj.size(), hipMemcpyDeviceToHost, h->stream));
-            if (h->W2) {
-                const char *b2 = (const char *)h->W2 + (size_t)(kk * h->wslot) * 2;
-                HIPCHK(h, hipMemcpyAsync(wi2.data(), b2 + (size_t)(oi * bs) * 2, wi2.size(), hipMemcpyDeviceToHost, h->stream));
-                HIPCHK(h, hipMemcpyAsync(wj2.data(), b2 + (size_t)(oj * bs) * 2, wj2.size(), hipMemcpyDeviceToHost, h->stream));
-            }
-            HIPCHK(h, hipStreamSynchronize(h->stream));
-            for (int t = 0; t < h->N_t; ++t)
-                for (int u = 0; u < h->N_t; ++u) {
-                    double acc = 0;
-                    for (int m = 0; m < h->N_t; ++m) acc += wval(wi, wi2, t, m) * wval(wj, wj2, u, m);
-                    out[(size_t)t * h->N_t + u] -= acc;
-                }
-        }
-    }
     return OED_OK;
 }
 
@@ -934,7 +1056,8 @@ oed_status oed_get_profile(oed_ctx *h, oed_profile *out, int32_t reset)
     return OED_OK;
 }
 
-oed_status oed_get_config(const oed_ctx *h, int32_t *delay, int32_t *syrk_variant, double *per_pick_ms)
+oed_status oed_get_config(const oed_ctx *h, int32_t *delay, int32_t *syrk_variant, int32_t *tile_order,
+                          double *per_pick_ms)
 {
     if (!h) return OED_E_ARG;
     if (syrk_variant && h->left) {
@@ -943,6 +1066,9 @@ oed_status oed_get_config(const oed_ctx *h, int32_t *delay, int32_t *syrk_varian
     }
     if (delay) *delay = h->delay;
     if (syrk_variant) *syrk_variant = h->syrk_variant;
+    if (tile_order)
+        *tile_order = h->stl == STL_ROW8 ? OED_TILES_ROW8 : h->stl == STL_COL8 ? OED_TILES_COL8
+                      : h->stl == STL_COL4 ? OED_TILES_COL4 : OED_TILES_COL2;
     if (per_pick_ms) std::copy(h->tuned_ms, h->tuned_ms + MAX_DELAY, per_pick_ms);
     return OED_OK;
 }

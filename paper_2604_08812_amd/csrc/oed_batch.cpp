@@ -66,11 +66,14 @@ struct oed_batch {
     std::vector<Inst> in;
     int prec = OED_PREC_FP64, rtype = R_F64, wtype = W_F64;
     int delay = 2;
+    int stl = STL_COL4;  // downdate tile order (see super_tile())
     bool left = false;  // left-looking: W slot k holds pick k's block column
     bool eval = false;  // design evaluation: pick k is candidate k, no gain scoring
-    double tuned_ms[MAX_DELAY] = {0};  // autotuner: eager run time for delay 1..MAX_DELAY
+    double tuned_ms[MAX_DELAY] = {0};  // autotuner: eager run time for delay 1..MAX_DELAY (default order)
     uint32_t flags = 0;
-    hipStream_t stream = nullptr;
+    hipStream_t stream = nullptr;  // the batch's own stream (graph capture and replay)
+    hipStream_t caller = nullptr;  // the stream given at creation: K is complete in its order
+    hipEvent_t ev_in = nullptr;    // recorded on `caller` before every pack
     std::vector<void *> allocs;
     char *results = nullptr;  // [gains of all picks (double)][picks + state words (int)]
     size_t results_bytes = 0, n_gain = 0;
@@ -116,6 +119,7 @@ void bfree(oed_batch *b)
     b->allocs.clear();
     if (b->ev0) (void)hipEventDestroy(b->ev0);
     if (b->ev1) (void)hipEventDestroy(b->ev1);
+    if (b->ev_in) (void)hipEventDestroy(b->ev_in);
     if (b->stream) (void)hipStreamDestroy(b->stream);
 }
 
@@ -133,8 +137,12 @@ oed_status check_instances(const oed_instance *inst, int32_t n)
     return OED_OK;
 }
 
+// Pack every working copy from inst[].K_dev on the batch stream, ordered after everything enqueued
+// so far on the creation stream (where the caller wrote K), and wait for it.
 oed_status pack_all(oed_batch *b, const oed_instance *inst)
 {
+    BCHK(b, hipEventRecord(b->ev_in, b->caller));
+    BCHK(b, hipStreamWaitEvent(b->stream, b->ev_in, 0));
     for (size_t i = 0; i < b->in.size(); ++i) {
         const Inst &x = b->in[i];
         BCHK(b, launch_pack(inst[i].K_dev, x.kdtype, x.ld, x.N_t, x.N_tp, x.cmap, x.N_s, x.R, b->rtype, b->stream));
@@ -148,9 +156,10 @@ oed_status pack_all(oed_batch *b, const oed_instance *inst)
 // its k-th pick.  With delay p the block column of pick k goes to W slot k mod p; slots
 // 0 .. (k mod p) - 1 hold the earlier ones, and after every p-th pick all p are subtracted in
 // one downdate.
-StepDesc inst_desc(const Inst &x, int k, bool after_pick, int delay)
+StepDesc inst_desc(const Inst &x, int k, bool after_pick, int delay, int stl = STL_COL4)
 {
     StepDesc d{};
+    d.stl = stl;
     d.R = x.R;
     d.W = x.W;
     d.W2 = x.W2;
@@ -364,10 +373,10 @@ void build_schedule(oed_batch *b)
             s.N_tp = kv.first;
             s.nw = nw;
             for (const Inst *x : kv.second) {
-                StepDesc d = inst_desc(*x, k, true, b->delay);
+                StepDesc d = inst_desc(*x, k, true, b->delay, b->stl);
                 d.nw = s.nw;
                 d.item0 = s.total;
-                d.nitems = syrk_tiles(d.n_act, d.N_tp);
+                d.nitems = syrk_tiles(d.n_act, d.N_tp, b->stl);
                 s.total += d.nitems;
                 b->descs.push_back(d);
                 ++s.ndesc;
@@ -405,12 +414,9 @@ oed_status enqueue_run(oed_batch *b)
 // Autotuner (OED_BATCH_AUTOTUNE with no delay given): runs the whole selection once per delay
 // depth p = 1..MAX_DELAY, eagerly, from freshly packed working copies, and keeps the fastest.
 // All depths give the same picks up to rounding; W slots for MAX_DELAY are allocated.
-oed_status autotune_batch(oed_batch *b, const oed_instance *inst)
+oed_status autotune_batch(oed_batch *b, const oed_instance *inst, bool tiles)
 {
-    double best = 1e300;
-    int best_p = b->delay;
-    for (int p = 1; p <= MAX_DELAY; ++p) {
-        b->delay = p;
+    auto timed_run = [&](double *out) -> oed_status {
         build_schedule(b);
         BCHK(b, hipMemcpy(b->d_descs, b->descs.data(), sizeof(StepDesc) * b->descs.size(), hipMemcpyHostToDevice));
         oed_status st = pack_all(b, inst);
@@ -422,13 +428,36 @@ oed_status autotune_batch(oed_batch *b, const oed_instance *inst)
         BCHK(b, hipEventSynchronize(b->ev1));
         float ms = 0;
         BCHK(b, hipEventElapsedTime(&ms, b->ev0, b->ev1));
-        b->tuned_ms[p - 1] = ms;
-        if (ms < best) {
-            best = ms;
+        *out = ms;
+        return OED_OK;
+    };
+    double best = 1e300;
+    int best_p = b->delay;
+    for (int p = 1; p <= MAX_DELAY; ++p) {
+        b->delay = p;
+        oed_status st = timed_run(&b->tuned_ms[p - 1]);
+        if (st != OED_OK) return st;
+        if (b->tuned_ms[p - 1] < best) {
+            best = b->tuned_ms[p - 1];
             best_p = p;
         }
     }
     b->delay = best_p;
+    if (!tiles) return OED_OK;
+    // the other tile orders at the chosen depth
+    const int orders[] = {STL_COL8, STL_ROW8};
+    int best_stl = b->stl;
+    for (int o : orders) {
+        b->stl = o;
+        double ms = 0;
+        oed_status st = timed_run(&ms);
+        if (st != OED_OK) return st;
+        if (ms < best) {
+            best = ms;
+            best_stl = o;
+        }
+    }
+    b->stl = best_stl;
     return OED_OK;
 }
 
@@ -448,6 +477,8 @@ static oed_status create_batch(oed_batch **out, const oed_instance *inst, int32_
     if (precision != OED_PREC_FP64 && precision != OED_PREC_MIXED_F32 && precision != OED_PREC_MIXED_BF16X3)
         return OED_E_ARG;
     if (((flags >> 8) & 0xFu) > (unsigned)MAX_DELAY) return OED_E_ARG;
+    const unsigned tiles = (flags >> 12) & 0xFu;
+    if (tiles > OED_TILES_COL2) return OED_E_ARG;
     oed_batch *b = new (std::nothrow) oed_batch();
     if (!b) return OED_E_OOM;
     b->prec = precision;
@@ -458,16 +489,20 @@ static oed_status create_batch(oed_batch **out, const oed_instance *inst, int32_
     b->left = (flags & OED_BATCH_LEFT_LOOKING) != 0;
     b->eval = eval;
     const bool tune = !b->left && b->delay == 0 && (flags & OED_BATCH_AUTOTUNE);
+    static const int stl_of[] = {STL_COL4, STL_ROW8, STL_COL8, STL_COL4, STL_COL2};
+    b->stl = stl_of[tiles];
     if (b->delay == 0) b->delay = DEFAULT_DELAY;
     if (b->left) b->delay = 1;
     // W slots and held-column buffers for the deepest delay the batch may run with
     const int max_p = tune ? MAX_DELAY : b->delay;
     auto setup = [&]() -> oed_status {
         // the caller's K must be complete before the batch stream reads it
-        BCHK(b, hipStreamSynchronize((hipStream_t)stream));
+        b->caller = (hipStream_t)stream;
+        BCHK(b, hipStreamSynchronize(b->caller));
         BCHK(b, hipStreamCreateWithFlags(&b->stream, hipStreamNonBlocking));
         BCHK(b, hipEventCreate(&b->ev0));
         BCHK(b, hipEventCreate(&b->ev1));
+        BCHK(b, hipEventCreateWithFlags(&b->ev_in, hipEventDisableTiming));
         const size_t er = b->rtype == R_F64 ? 8 : 4;
         size_t n_gain = 0, n_int = 0;
         b->in.resize(n);
@@ -527,7 +562,7 @@ static oed_status create_batch(oed_batch **out, const oed_instance *inst, int32_
         }
         BCHK(b, balloc(b, (void **)&b->d_descs, sizeof(StepDesc) * ndesc));
         if (tune) {
-            oed_status s2 = autotune_batch(b, inst);
+            oed_status s2 = autotune_batch(b, inst, !eval && tiles == OED_TILES_AUTO);
             if (s2 != OED_OK) return s2;
         }
         build_schedule(b);
@@ -550,10 +585,13 @@ oed_status oed_batch_create(oed_batch **out, const oed_instance *inst, int32_t n
     return create_batch(out, inst, n, precision, stream, flags, false);
 }
 
-oed_status oed_batch_get_config(const oed_batch *b, int32_t *delay, double *per_run_ms)
+oed_status oed_batch_get_config(const oed_batch *b, int32_t *delay, int32_t *tile_order, double *per_run_ms)
 {
     if (!b) return OED_E_ARG;
     if (delay) *delay = b->delay;
+    if (tile_order)
+        *tile_order = b->stl == STL_ROW8 ? OED_TILES_ROW8 : b->stl == STL_COL8 ? OED_TILES_COL8
+                      : b->stl == STL_COL4 ? OED_TILES_COL4 : OED_TILES_COL2;
     if (per_run_ms) std::copy(b->tuned_ms, b->tuned_ms + MAX_DELAY, per_run_ms);
     return OED_OK;
 }

@@ -134,17 +134,22 @@ __device__ __forceinline__ int find_instance(const StepDesc *ds, int n, int64_t 
 }
 
 // Downdate tile order: the 128 x 128 tiles (P, Q), Q <= P, of the lower triangle are grouped
-// in super-tiles of 8 x 8 tiles, taken in lower-triangular order; a super-tile holds 64 slots,
-// row-major.  The 64 work-groups an XCD runs at a time then share 8 row panels and 8 column
-// panels of W (1 MB at N_tp = 128) in that XCD's L2 instead of sweeping all of W.
+// in super-tiles of b x b tiles (b = 2^(stl & 7), 8 for stl & 7 == 0), taken in lower-triangular
+// order, so that super-tile row SP (a band of b tile rows) is swept column after column.  Inside
+// a super-tile the b^2 slots run down the columns (the b tiles that share a column panel of W
+// are consecutive, and the band's b row panels are reused by every super-tile of the band) or,
+// with stl & 8, along the rows.  The work-groups an XCD runs at a time then share a few row and
+// column panels of W in that XCD's L2 instead of sweeping all of W.
 // Returns false for slots outside the triangle or past the last tile row T.
-__device__ __forceinline__ bool super_tile(int64_t slot, int64_t T, int64_t &P, int64_t &Q)
+__device__ __forceinline__ bool super_tile(int64_t slot, int64_t T, int stl, int64_t &P, int64_t &Q)
 {
     if (slot < 0) return false;
-    const int64_t st = slot >> 6, r = slot & 63;
+    const int lb = (stl & 7) ? (stl & 7) : 3;
+    const int64_t st = slot >> (2 * lb), r = slot & ((1 << (2 * lb)) - 1);
     const int64_t SP = tri_row(st), SQ = st - SP * (SP + 1) / 2;
-    P = SP * 8 + (r >> 3);
-    Q = SQ * 8 + (r & 7);
+    const int64_t lo = r & ((1 << lb) - 1), hi = r >> lb;
+    P = (SP << lb) + ((stl & 8) ? hi : lo);
+    Q = (SQ << lb) + ((stl & 8) ? lo : hi);
     return P < T && Q <= P;
 }
 

@@ -96,18 +96,27 @@ struct StepDesc {
     int step;              // pick: index of this pick
     int forced;            // pick: forced local index, or -1 for the argmax
     int nw;                // syrk: W slots 0 .. nw-1 applied (inner dimension nw N_tp)
+    int stl;               // syrk: super-tile code of the tile order (see super_tile(); 0 = 8 x 8)
     int64_t item0;         // batched launches: first work item of this instance
     int64_t nitems;        // work items of this instance (gain, trsm: n_act; pick: 1; syrk: tiles)
 };
 
 // Work items (tile slots) of the downdate over n remaining candidates: 128 x 128 tiles of the
-// lower triangle, grouped in 8 x 8 super-tiles of 64 slots each (see super_tile()).
+// lower triangle, grouped in b x b super-tiles of b^2 slots each, b = 2^(stl & 7) (8 for 0; see
+// super_tile()).
 __host__ __device__ inline int64_t syrk_tile_rows(int n_act, int N_tp) { return ((int64_t)n_act * N_tp + 127) / 128; }
-__host__ __device__ inline int64_t syrk_tiles(int n_act, int N_tp)
+__host__ __device__ inline int64_t syrk_tiles(int n_act, int N_tp, int stl)
 {
-    const int64_t ST = (syrk_tile_rows(n_act, N_tp) + 7) / 8;
-    return 64 * (ST * (ST + 1) / 2);
+    const int lb = (stl & 7) ? (stl & 7) : 3;
+    const int64_t b = (int64_t)1 << lb;
+    const int64_t ST = (syrk_tile_rows(n_act, N_tp) + b - 1) / b;
+    return b * b * (ST * (ST + 1) / 2);
 }
+// Super-tile codes (StepDesc::stl): edge 2^(code & 7) tiles, code & 8 = row-major inside.
+constexpr int STL_ROW8 = 8 | 3;  // 8 x 8, row-major: the order of the first downdate kernels
+constexpr int STL_COL4 = 2;      // 4 x 4, down the columns
+constexpr int STL_COL8 = 3;      // 8 x 8, down the columns
+constexpr int STL_COL2 = 1;      // 2 x 2, down the columns
 
 hipError_t launch_pack(const void *K, int kdtype, int64_t ld, int N_t, int N_tp, const int *cmap, int N_c,
                        void *R, int rtype, hipStream_t s);
@@ -137,6 +146,11 @@ hipError_t launch_column_batched(const StepDesc *descs, int n, int64_t total, in
 // runs the BF16 split-product kernel (N_tp a multiple of 32, <= 128).
 enum SyrkVariant { SYRK_DIRECT = 0, SYRK_LDS = 1, SYRK_NVARIANTS = 2 };
 hipError_t launch_syrk(const StepDesc &d, int rtype, int wtype, int variant, hipStream_t s);
+
+// Block (li, lj), li >= lj, of the current Schur complement into out (device, N_t x N_t FP64
+// row-major; tr: its transpose), subtracting the nsub W slots R does not include.
+hipError_t launch_schur_block(const void *R, int rtype, const void *W, const void *W2, int wtype, int64_t wslot,
+                              int nsub, int li, int lj, int tr, int N_t, int N_tp, double *out, hipStream_t s);
 
 // Batched launches over n instances (descs: device array sorted by item0, total work items).
 // The register factorisation kernels serve all of them (max_Nt <= REGS_MAX_NT); a batched

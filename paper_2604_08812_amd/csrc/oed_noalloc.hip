@@ -155,6 +155,7 @@ OED_API oed_status oed_greedy_noalloc(const void *K_dev, int32_t dtype, int64_t 
     d.N_t = N_t;
     d.N_tp = N_tp;
     d.forced = -1;
+    d.stl = STL_COL4;  // the handle's default tile order
 
     // the greedy loop of oed_greedy: the block column of pick k and, every `delay` picks, the
     // downdate of the held columns are enqueued at the start of step k + 1
@@ -176,7 +177,7 @@ OED_API oed_status oed_greedy_noalloc(const void *K_dev, int32_t dtype, int64_t 
             } else {
                 StepDesc u = d;
                 u.nw = nheld + 1;
-                u.nitems = syrk_tiles(n_act, N_tp);
+                u.nitems = syrk_tiles(n_act, N_tp, u.stl);
                 NA_CHK(launch_syrk(u, rtype, wtype, SYRK_LDS, s));
                 nheld = 0;
             }

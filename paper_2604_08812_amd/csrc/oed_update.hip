@@ -396,7 +396,7 @@ __device__ void syrk_direct_body(const StepDesc &d, int64_t tile)
     const int *__restrict__ act = d.act_in;
     const int n_act = d.n_act, N_tp = d.N_tp;
     int64_t P, Q;
-    if (!super_tile(tile, syrk_tile_rows(d.n_act, d.N_tp), P, Q)) return;
+    if (!super_tile(tile, syrk_tile_rows(d.n_act, d.N_tp), d.stl, P, Q)) return;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, wr = wave >> 1, wc = wave & 1;
     const int alane = a_lane<T>(lane);
     const int nb = N_tp >> 4;
@@ -529,7 +529,7 @@ __device__ void syrk_lds_body(const StepDesc &d, int64_t tile)
     __shared__ vec lds[2][2][KS][8 * 64];      // [buffer][A/B][slice][sub-block * 64 + lane]
     if (d.state[ST_STATUS] != 0) return;
     int64_t P, Q;
-    if (!super_tile(tile, syrk_tile_rows(d.n_act, d.N_tp), P, Q)) return;
+    if (!super_tile(tile, syrk_tile_rows(d.n_act, d.N_tp), d.stl, P, Q)) return;
     T *__restrict__ R = (T *)d.R;
     const int tid = threadIdx.x, lane = tid & 63;
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6), wr = wave >> 1, wc = wave & 1;
@@ -635,7 +635,7 @@ __device__ void syrk_lds_rt_body(const StepDesc &d, int64_t tile)
     __shared__ vec lds[2][2][8 * 64];  // [buffer][A/B][sub-block * 64 + lane]
     if (d.state[ST_STATUS] != 0) return;
     int64_t P, Q;
-    if (!super_tile(tile, syrk_tile_rows(d.n_act, d.N_tp), P, Q)) return;
+    if (!super_tile(tile, syrk_tile_rows(d.n_act, d.N_tp), d.stl, P, Q)) return;
     const int nb = d.N_tp >> 4;
     T *__restrict__ R = (T *)d.R;
     const int tid = threadIdx.x, lane = tid & 63;
@@ -726,7 +726,7 @@ __device__ void syrk_bf16_body(const StepDesc &d, int64_t tile)
     __shared__ u32x4 lds[2][4][8 * 64];          // [buffer][A hi, A lo, B hi, B lo][sub-block * 64 + lane]
     if (d.state[ST_STATUS] != 0) return;
     int64_t P, Q;
-    if (!super_tile(tile, syrk_tile_rows(d.n_act, d.N_tp), P, Q)) return;
+    if (!super_tile(tile, syrk_tile_rows(d.n_act, d.N_tp), d.stl, P, Q)) return;
     float *__restrict__ R = (float *)d.R;
     const int tid = threadIdx.x, lane = tid & 63;
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6), wr = wave >> 1, wc = wave & 1;
@@ -1304,6 +1304,56 @@ __global__ void __launch_bounds__(64) vcorr_batched(const StepDesc *__restrict__
     if (i < 0) return;
     const StepDesc d = ds[i];
     vcorr_body<TW>(d, (int)(blockIdx.x - d.item0));
+}
+
+// ---------------------------------------------------------------------------------------------
+// Query: block (li, lj) of the current Schur complement, unpadded FP64 row-major N_t x N_t, from
+// R's stored lower block (li >= lj; with tr the transpose is returned, on the diagonal the lower
+// triangle is mirrored) minus sum_k W_k,li W_k,lj^T over the nsub W slots that R does not include
+// (left-looking: every formed block column; right-looking: none).  One thread per element.
+template <typename TR, typename TW>
+__global__ void __launch_bounds__(256) schur_block_kernel(const TR *__restrict__ R, const TW *__restrict__ W,
+                                                          const TW *__restrict__ W2, int64_t wslot, int nsub, int li,
+                                                          int lj, int tr, int N_t, int N_tp, double *__restrict__ out)
+{
+    const int e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= N_t * N_t) return;
+    const int a = e / N_t, b = e - a * N_t;      // element (a, b) of the returned block
+    const int t = tr ? b : a, u = tr ? a : b;    // element (t, u) of stored block (li, lj)
+    const int nb = N_tp >> 4;
+    const int64_t bs = (int64_t)N_tp * N_tp;
+    const TR *Rb = R + blk_index(li, lj) * bs;
+    // a diagonal block is current on its lower triangle only
+    const int o = (li == lj && u > t) ? acc_off(u, t, nb) : acc_off(t, u, nb);
+    double v = (double)Rb[o];
+    for (int k = 0; k < nsub; ++k) {
+        const TW *Wi = W + k * wslot + (int64_t)li * bs, *Wj = W + k * wslot + (int64_t)lj * bs;
+        const TW *Wi2 = W2 ? W2 + k * wslot + (int64_t)li * bs : nullptr;
+        const TW *Wj2 = W2 ? W2 + k * wslot + (int64_t)lj * bs : nullptr;
+        double acc = 0.0;
+        for (int m = 0; m < N_t; ++m) acc += w_elem<TW>(Wi, Wi2, t, m, nb) * w_elem<TW>(Wj, Wj2, u, m, nb);
+        v -= acc;
+    }
+    out[e] = v;
+}
+
+hipError_t launch_schur_block(const void *R, int rtype, const void *W, const void *W2, int wtype, int64_t wslot,
+                              int nsub, int li, int lj, int tr, int N_t, int N_tp, double *out, hipStream_t s)
+{
+    const dim3 grid((unsigned)((N_t * N_t + 255) / 256)), block(256);
+#define OED_SCHUR(TR, TW)                                                                                       \
+    hipLaunchKernelGGL((schur_block_kernel<TR, TW>), grid, block, 0, s, (const TR *)R, (const TW *)W,              \
+                       (const TW *)W2, wslot, nsub, li, lj, tr, N_t, N_tp, out)
+    if (rtype == R_F64 && wtype == W_F64)
+        OED_SCHUR(double, double);
+    else if (rtype == R_F32 && wtype == W_F32)
+        OED_SCHUR(float, float);
+    else if (rtype == R_F32 && wtype == W_BF16X3)
+        OED_SCHUR(float, unsigned short);
+    else
+        return hipErrorInvalidValue;
+#undef OED_SCHUR
+    return hipGetLastError();
 }
 
 // ---------------------------------------------------------------------------------------------

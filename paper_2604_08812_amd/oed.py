@@ -30,7 +30,12 @@ class oed_options(ctypes.Structure):
     _fields_ = [("struct_size", ctypes.c_uint32), ("precision", ctypes.c_int32), ("flags", ctypes.c_uint32),
                 ("candidates", ctypes.POINTER(ctypes.c_int32)), ("n_candidates", ctypes.c_int32),
                 ("delay", ctypes.c_int32), ("method", ctypes.c_int32), ("max_budget", ctypes.c_int32),
-                ("noise_half_logdet", ctypes.POINTER(ctypes.c_double)), ("reserved", ctypes.c_int32 * 4)]
+                ("noise_half_logdet", ctypes.POINTER(ctypes.c_double)), ("tune_cache", ctypes.c_char_p),
+                ("max_device_bytes", ctypes.c_int64), ("tile_order", ctypes.c_int32),
+                ("debug_fail_step", ctypes.c_int32), ("reserved", ctypes.c_int32 * 2)]
+
+
+TILE_ORDERS = {"auto": 0, "row8": 1, "col8": 2, "col4": 3, "col2": 4}
 
 
 class oed_profile(ctypes.Structure):
@@ -80,7 +85,7 @@ def library() -> ctypes.CDLL:
     L.oed_picks.argtypes = [vp, ip, dp, ip]
     L.oed_get_profile.argtypes = [vp, ctypes.POINTER(oed_profile), ctypes.c_int32]
     L.oed_device_bytes.argtypes = [vp, ctypes.POINTER(ctypes.c_int64)]
-    L.oed_get_config.argtypes = [vp, ip, ip, dp]
+    L.oed_get_config.argtypes = [vp, ip, ip, ip, dp]
     L.oed_destroy.argtypes = [vp]
     L.oed_last_error.argtypes = [vp]
     L.oed_last_error.restype = ctypes.c_char_p
@@ -92,7 +97,7 @@ def library() -> ctypes.CDLL:
     L.oed_batch_reset.argtypes = [vp, ctypes.POINTER(oed_instance), ctypes.c_int32]
     L.oed_batch_stats.argtypes = [vp, dp, dp, dp]
     L.oed_batch_destroy.argtypes = [vp]
-    L.oed_batch_get_config.argtypes = [vp, ip, dp]
+    L.oed_batch_get_config.argtypes = [vp, ip, ip, dp]
     L.oed_batch_last_error.argtypes = [vp]
     L.oed_batch_last_error.restype = ctypes.c_char_p
     L.oed_eval_create.argtypes = [ctypes.POINTER(vp), vp, ctypes.c_int32, ctypes.c_int64, ctypes.c_int32,
@@ -153,13 +158,17 @@ def _stream_handle(stream):
 
 # ------------------------------------------------------------------ functions with the C names
 def oed_create(K, N_s, N_t, sigma2, precision="fp64", candidates=None, profile=False, stream=None, delay=0,
-               autotune=False, method="right", max_budget=0, noise_half_logdet=None):
+               autotune=False, method="right", max_budget=0, noise_half_logdet=None, tile_order="auto",
+               tune_cache=None, max_device_bytes=0, debug_fail_step=0):
     """Create a handle for the device tensor K (2-D, float64/float32, row-major, lower triangle read).
     delay: downdate delay depth (0 automatic, 1..OED_MAX_DELAY); autotune: with delay 0, time the choices;
     method: "right" (downdate of all of R per pick), "left" (only the new block column per pick) or
     "auto" (left when max_budget <= half the candidates);
     max_budget: left-looking W history size (0: all candidates); noise_half_logdet: per-sensor
-    1/2 logdet of the noise covariance blocks (None: isotropic sigma2).
+    1/2 logdet of the noise covariance blocks (None: isotropic sigma2); tile_order: the downdate's
+    tile order ("auto", "row8", "col8", "col4", "col2"); tune_cache: autotuner cache file path;
+    max_device_bytes: fail with OED_E_OOM instead of holding more (0: no limit); debug_fail_step:
+    make that pick fail once (error-path tests).
     K = None: deferred packing (OED_FLAG_DEFER_PACK), the rows come through oed_pack_rows."""
     import torch
     L = library()
@@ -182,6 +191,13 @@ def oed_create(K, N_s, N_t, sigma2, precision="fp64", candidates=None, profile=F
     opt.delay = int(delay)
     opt.method = {"right": 0, "left": 1, "auto": 2}[method]
     opt.max_budget = int(max_budget)
+    opt.tile_order = TILE_ORDERS[tile_order]
+    cache = None
+    if tune_cache is not None:
+        cache = os.fsencode(os.fspath(tune_cache))
+        opt.tune_cache = cache
+    opt.max_device_bytes = int(max_device_bytes)
+    opt.debug_fail_step = int(debug_fail_step)
     hld = None
     if noise_half_logdet is not None:
         hld = np.ascontiguousarray(np.asarray(noise_half_logdet, dtype=np.float64))
@@ -196,12 +212,30 @@ def oed_create(K, N_s, N_t, sigma2, precision="fp64", candidates=None, profile=F
     h = ctypes.c_void_p()
     st = L.oed_create(ctypes.byref(h), kp, dtype, ld, int(N_s), int(N_t), float(sigma2), _stream_handle(stream),
                       ctypes.byref(opt))
-    _check(None, st)
+    if st != OED_OK:
+        raise OedError(st, L.oed_last_error(None).decode())
+    # what oed_reset must be given again: the C side reuses the dtype and leading dimension of K
+    _K_SIG[h.value] = None if K is None else _k_signature(K)
     return h
 
 
+_K_SIG = {}
+
+
+def _k_signature(K):
+    return (K.dtype, K.stride(0), K.stride(1), tuple(K.shape), K.device)
+
+
 def oed_reset(h, K):
-    """K = None: a deferred-packing handle forgets its picks and its packed rows."""
+    """K = None: a deferred-packing handle forgets its picks and its packed rows.  Otherwise K must be a
+    device tensor of the dtype, strides, shape and device the handle was created with."""
+    import torch
+    if K is not None:
+        if not isinstance(K, torch.Tensor) or not K.is_cuda:
+            raise ValueError("K must be a device tensor")
+        want = _K_SIG.get(h.value if isinstance(h, ctypes.c_void_p) else h)
+        if want is not None and _k_signature(K) != want:
+            raise ValueError(f"K (dtype, strides, shape, device) {_k_signature(K)} differs from creation {want}")
     _check(h, library().oed_reset(h, None if K is None else ctypes.c_void_p(K.data_ptr())))
 
 
@@ -271,15 +305,17 @@ def oed_device_bytes(h):
 
 
 def oed_get_config(h):
-    """(delay, syrk_variant, autotuner per-pick ms for delay 1..OED_MAX_DELAY)."""
-    dl, var = ctypes.c_int32(), ctypes.c_int32()
+    """(delay, syrk_variant, autotuner per-pick ms for delay 1..OED_MAX_DELAY, tile order name)."""
+    dl, var, to = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
     ms = np.zeros(OED_MAX_DELAY)
-    _check(h, library().oed_get_config(h, ctypes.byref(dl), ctypes.byref(var), _dp(ms)))
-    return dl.value, var.value, ms
+    _check(h, library().oed_get_config(h, ctypes.byref(dl), ctypes.byref(var), ctypes.byref(to), _dp(ms)))
+    names = {v: k for k, v in TILE_ORDERS.items()}
+    return dl.value, var.value, ms, names.get(to.value, str(to.value))
 
 
 def oed_destroy(h):
     if h:
+        _K_SIG.pop(h.value if isinstance(h, ctypes.c_void_p) else h, None)
         library().oed_destroy(h)
 
 
@@ -333,11 +369,12 @@ def _bcheck(b, st):
 
 
 def oed_batch_create(items, precision="fp64", profile=False, graph=True, stream=None, delay=0, autotune=False,
-                     method="right"):
+                     method="right", tile_order="auto"):
     arr = _instances(items)
     b = ctypes.c_void_p()
     flags = ((OED_FLAG_PROFILE if profile else 0) | (0 if graph else OED_BATCH_NO_GRAPH) | (int(delay) << 8) |
-             (OED_BATCH_AUTOTUNE if autotune else 0) | (OED_BATCH_LEFT_LOOKING if method == "left" else 0))
+             (OED_BATCH_AUTOTUNE if autotune else 0) | (OED_BATCH_LEFT_LOOKING if method == "left" else 0) |
+             (TILE_ORDERS[tile_order] << 12))
     st = library().oed_batch_create(ctypes.byref(b), arr, len(items), PRECISIONS[precision], _stream_handle(stream),
                                     flags)
     _bcheck(None, st)
@@ -371,11 +408,12 @@ def oed_batch_stats(b):
 
 
 def oed_batch_get_config(b):
-    """(delay, autotuner run ms for delay 1..OED_MAX_DELAY)."""
-    dl = ctypes.c_int32()
+    """(delay, autotuner run ms for delay 1..OED_MAX_DELAY, tile order name)."""
+    dl, to = ctypes.c_int32(), ctypes.c_int32()
     ms = np.zeros(OED_MAX_DELAY)
-    _bcheck(b, library().oed_batch_get_config(b, ctypes.byref(dl), _dp(ms)))
-    return dl.value, ms
+    _bcheck(b, library().oed_batch_get_config(b, ctypes.byref(dl), ctypes.byref(to), _dp(ms)))
+    names = {v: k for k, v in TILE_ORDERS.items()}
+    return dl.value, ms, names.get(to.value, str(to.value))
 
 
 def oed_batch_destroy(b):
@@ -387,9 +425,9 @@ class BatchSelector:
     """Owns one batch.  ``BatchSelector([(K, N_s, N_t, sigma2, B), ...]).run()`` -> [(idx, gain, status)]."""
 
     def __init__(self, items, precision="fp64", profile=False, graph=True, stream=None, delay=0, autotune=False,
-                 method="right"):
+                 method="right", tile_order="auto"):
         self.budgets = [int(it[4]) for it in items]
-        self.b = oed_batch_create(items, precision, profile, graph, stream, delay, autotune, method)
+        self.b = oed_batch_create(items, precision, profile, graph, stream, delay, autotune, method, tile_order)
 
     def run(self, check=True):
         return oed_batch_run(self.b, self.budgets, check)[0]
@@ -511,10 +549,12 @@ class Selector:
     """Owns one handle.  ``Selector(K, N_s, N_t, sigma2).greedy(B)`` -> (indices, gains)."""
 
     def __init__(self, K, N_s, N_t, sigma2, precision="fp64", candidates=None, profile=False, stream=None,
-                 delay=0, autotune=False, method="right", max_budget=0, noise_half_logdet=None):
+                 delay=0, autotune=False, method="right", max_budget=0, noise_half_logdet=None, tile_order="auto",
+                 tune_cache=None, max_device_bytes=0, debug_fail_step=0):
         self.N_s, self.N_t = int(N_s), int(N_t)
         self.h = oed_create(K, N_s, N_t, sigma2, precision, candidates, profile, stream, delay, autotune, method,
-                            max_budget, noise_half_logdet)
+                            max_budget, noise_half_logdet, tile_order, tune_cache, max_device_bytes,
+                            debug_fail_step)
 
     def greedy(self, budget):
         idx, gain, _ = oed_greedy(self.h, budget)

@@ -15,20 +15,53 @@ def rel_err(a, b):
     return np.abs(a - b) / np.maximum(1.0, np.abs(b))
 
 
-def check_trajectory(K, N_s, N_t, s2, gpu_idx, gpu_gain, rtol, candidates=None):
+# Achieved-error regression bounds on the seeded benchmark instances (not the parity tolerance,
+# which stays RTOL): per-step gain difference of a mixed path to the FP64 path before any
+# divergence.  They sit about two orders of magnitude above what the paths achieve, so a
+# precision regression fails them long before it reaches RTOL.
+REGRESSION = {"mixed_f32": 1e-6, "mixed_bf16x3": 1e-5}
+
+
+def check_trajectory(K, N_s, N_t, s2, gpu_idx, gpu_gain, rtol, candidates=None, cache=None, progress=None):
     """Compare a GPU trajectory with the oracle replaying the GPU's own prefix.
 
     At every step the oracle scores all remaining candidates given the GPU's
-    picks so far.  The GPU's pick must be the oracle's pick, except where the
-    oracle's score of the GPU's pick is within tau = 2*rtol*max(|g_best|, 1) of
-    the oracle's best score (a near-tie the precision cannot resolve).  The
-    GPU's gains must match the oracle's scores of the same picks within rtol.
-    Returns a dict with the per-step report.
+    picks so far (from-scratch factorisations, ``oracle.gains``); its pick is the
+    first strictly largest score in ascending candidate order.  The GPU's pick
+    must be the oracle's pick, except where the oracle's score of the GPU's pick
+    is within tau = 2*rtol*max(|g_best|, 1) of the oracle's best score (a
+    near-tie the precision cannot resolve).  The GPU's gains must match the
+    oracle's scores of the same picks within rtol.  Returns a dict with the
+    per-step report.  cache: a dict the caller keeps for one K (the replay of a
+    step depends only on K, the sizes and the prefix, so paths with the same
+    picks share it).  progress: print a line per step (long replays).
     """
     B = len(gpu_idx)
-    ref = oracle.greedy(K, N_s, N_t, s2, B, candidates=candidates, prefix=list(gpu_idx))
-    assert len(ref["idx"]) == B
-    assert list(ref["idx"]) == list(gpu_idx)
+    cands = list(range(N_s)) if candidates is None else sorted(int(c) for c in candidates)
+    ref = {"idx": [], "gain": [], "best": [], "best_gain": []}
+    picked = []
+    for k in range(B):
+        key = (N_s, N_t, s2, tuple(cands), tuple(int(i) for i in gpu_idx[:k]))
+        step = cache.get(key) if cache is not None else None
+        if step is None:
+            rest = [c for c in cands if c not in picked]
+            g = oracle.gains(K, N_t, s2, picked, rest)
+            g = np.where(np.isnan(g), -np.inf, g)
+            step = (rest, g)
+            if cache is not None:
+                cache[key] = step
+        rest, g = step
+        j = int(gpu_idx[k])
+        assert j in rest, f"step {k}: GPU pick {j} is not a remaining candidate"
+        bpos = int(np.argmax(g))          # the first maximum: lowest index on exact ties
+        ref["idx"].append(j)
+        ref["gain"].append(float(g[rest.index(j)]))
+        ref["best"].append(rest[bpos])
+        ref["best_gain"].append(float(g[bpos]))
+        picked.append(j)
+        if progress:
+            print(f"  {progress} oracle step {k}: {len(rest)} candidates, pick {j}", flush=True)
+    ref = {k: np.asarray(v) for k, v in ref.items()}
     err = rel_err(gpu_gain, ref["gain"])
     diverged = [k for k in range(B) if ref["best"][k] != gpu_idx[k]]
     for k in diverged:

@@ -88,7 +88,8 @@ def test_host_side_argument_validation(lib):
     assert lib.oed_greedy(None, 1, None, None, None) == E_ARG
     assert lib.oed_destroy(None) == 0
     assert lib.oed_status_string(2) == b"OED_E_NOT_SPD"
-    assert lib.oed_last_error(None) == b"null handle"
+    # NULL handle: the text of the thread's last failed oed_create
+    assert lib.oed_last_error(None) == b"candidate out of range or repeated"
 
 
 def test_binding_fails_loudly_without_library(monkeypatch, tmp_path):
@@ -154,3 +155,34 @@ def test_deferred_pack_host_side_validation(lib):
     assert lib.oed_create(ctypes.byref(h), None, 0, 64, 4, 16, 0.0, None, ctypes.byref(opt)) == 1
     assert not h.value
     assert lib.oed_pack_rows(None, fake, 0, 64, 0, 1) == 1
+
+
+def test_options_layout_and_create_errors_without_a_gpu(lib):
+    """The options struct the binding builds has the C size; a device-memory limit below what the
+    handle needs is OED_E_OOM before any HIP call, with the bytes in oed_last_error(NULL); bad tile
+    orders, negative limits and hook steps are OED_E_ARG with a message."""
+    from paper_2604_08812_amd.oed import oed_options
+    opt = oed_options()
+    lib.oed_options_init(ctypes.byref(opt))
+    assert opt.struct_size == ctypes.sizeof(oed_options)
+    assert opt.tile_order == 0 and opt.max_device_bytes == 0 and opt.debug_fail_step == 0 and not opt.tune_cache
+    h = ctypes.c_void_p()
+    fake = ctypes.c_void_p(0x1000)  # never dereferenced: every call below fails before any HIP call
+    opt.max_device_bytes = 1000
+    # 4 sensors x 16, FP64: R alone is 10 blocks of 16^2 doubles = 20,480 bytes
+    assert lib.oed_create(ctypes.byref(h), fake, 0, 64, 4, 16, 1.0, None, ctypes.byref(opt)) == 3
+    msg = lib.oed_last_error(None).decode()
+    assert "max_device_bytes = 1000" in msg and "needs" in msg and not h.value
+    opt.max_device_bytes = -1
+    assert lib.oed_create(ctypes.byref(h), fake, 0, 64, 4, 16, 1.0, None, ctypes.byref(opt)) == 1
+    opt.max_device_bytes = 0
+    opt.tile_order = 9
+    assert lib.oed_create(ctypes.byref(h), fake, 0, 64, 4, 16, 1.0, None, ctypes.byref(opt)) == 1
+    assert "tile order" in lib.oed_last_error(None).decode()
+    opt.tile_order = 0
+    opt.debug_fail_step = -2
+    assert lib.oed_create(ctypes.byref(h), fake, 0, 64, 4, 16, 1.0, None, ctypes.byref(opt)) == 1
+    opt.debug_fail_step = 0
+    opt.reserved[1] = 1
+    assert lib.oed_create(ctypes.byref(h), fake, 0, 64, 4, 16, 1.0, None, ctypes.byref(opt)) == 1
+    assert "reserved" in lib.oed_last_error(None).decode()

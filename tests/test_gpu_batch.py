@@ -89,7 +89,7 @@ def test_batch_autotune(insts):
     from paper_2604_08812_amd import BatchSelector
     its = items(insts)
     with BatchSelector(its, precision="mixed_f32", autotune=True) as t:
-        delay, ms = t.config()
+        delay, ms, _ = t.config()
         res = t.run()
     assert np.all(ms > 0) and delay == int(np.argmin(ms)) + 1
     with BatchSelector(its, precision="mixed_f32", delay=delay) as f:
@@ -119,3 +119,31 @@ def test_batch_left_looking(insts, prec):
         assert list(idx) == list(i1), q
         np.testing.assert_array_equal(gain, g1)
         check_trajectory(K, N_s, N_t, s2, idx, gain, RTOL[prec])
+
+
+def test_batch_reset_is_ordered_after_the_caller_stream(insts):
+    """K rewritten on the creation (torch) stream, behind a long matrix product, and oed_batch_reset
+    called at once with no host synchronisation: the pack must see the rewritten K."""
+    from paper_2604_08812_amd import BatchSelector
+    alt = []
+    for (N_s, N_t, n_m, seed, c, B) in SPECS:
+        K, s2 = make_K(N_s, N_t, n_m, seed + 1000, c)
+        alt.append((K.to(DEV), N_s, N_t, s2, B))
+    with BatchSelector(alt, precision="mixed_f32") as ref_bs:
+        ref = ref_bs.run()
+    # working buffers that start as the original K and are overwritten with the alternative ones
+    work = [(Kd.clone(), N_s, N_t, s2a, B) for (_, Kd, N_s, N_t, _, B), (_, _, _, s2a, _) in zip(insts, alt)]
+    with BatchSelector(work, precision="mixed_f32") as bs:
+        bs.run()
+        a = torch.randn(8192, 8192, device=DEV)
+        torch.cuda.synchronize()
+        for _ in range(6):
+            a = a @ a
+            a = a / a.norm()
+        for (Kw, *_), (Ka, *_) in zip(work, alt):
+            Kw.copy_(Ka)
+        bs.reset(work)
+        res = bs.run()
+    for (i0, g0, s0), (i1, g1, s1) in zip(ref, res):
+        assert s0 == s1 == 0 and list(i0) == list(i1)
+        np.testing.assert_array_equal(g0, g1)

@@ -17,7 +17,7 @@ import torch
 
 import oracle
 from oed_inputs import CONFIGS, k_sub_lower, make_K_lower_panels
-from parity import RTOL, check_trajectory, rel_err
+from parity import REGRESSION, RTOL, check_trajectory, rel_err
 
 pytestmark = pytest.mark.gpu
 
@@ -122,6 +122,12 @@ def test_fullsize_mixed_vs_fp64(big, runs, prec):
     err = rel_err(g32[:upto], g64[:upto]).max()
     print(f"{prec} vs fp64: first divergence {div}, max rel gain diff before it {err:.2e}")
     assert err <= RTOL[prec]
+    # regression bounds at the achieved level: FP32 picks every FP64 pick on this instance (its
+    # smallest FP64 top-two gap, 6.2e-8 relative, is several times its gain error), and both mixed
+    # paths stay within REGRESSION of FP64 before any divergence
+    assert err <= REGRESSION[prec], f"{prec}: gain difference to FP64 {err:.2e} > {REGRESSION[prec]}"
+    if prec == "mixed_f32":
+        assert div is None, f"mixed FP32 left the FP64 picks at step {div}"
     if div is not None:
         # a divergence must be a near-tie at that step for the FP64 scores
         from paper_2604_08812_amd import Selector
@@ -132,16 +138,22 @@ def test_fullsize_mixed_vs_fp64(big, runs, prec):
         assert g[i64[div]] - g[i32[div]] <= 2 * RTOL[prec] * abs(g[i64[div]])
 
 
+_SUB_CACHE = {}
+
+
 @pytest.mark.timeout(900)
 @pytest.mark.parametrize("prec", PRECS)
 def test_subsample_100_against_oracle(big, prec):
+    """Sensors 0..99 of the same K (its leading 12,800^2 block), budget 29 (175 scaled to 100 of
+    600 sensors), replayed in full by the oracle."""
     from paper_2604_08812_amd import Selector
     spec, K, s2 = big
-    n, B = 100, 8
+    n, B = 100, 29
     with Selector(K, spec.N_s, spec.N_t, s2, precision=prec, candidates=range(n)) as sel:
         idx, gain = sel.greedy(B)
     sub = k_sub_lower(K, spec.N_t, range(n))
-    rep = check_trajectory(sub, n, spec.N_t, s2, idx, gain, RTOL[prec])
+    rep = check_trajectory(sub, n, spec.N_t, s2, idx, gain, RTOL[prec], cache=_SUB_CACHE,
+                           progress="600x128 " + prec)
     print(f"{prec} subsample: picks {list(idx)}, max rel err {rep['max_rel_err']:.2e}")
 
 

@@ -267,7 +267,7 @@ def test_autotuned_handle_selects_like_a_fixed_one(prec):
     N_s, N_t = 70, 64
     K, Kd, s2 = instance(N_s, N_t, 5000, 29)
     with selector(Kd, N_s, N_t, s2, precision=prec, autotune=True) as t:
-        delay, variant, ms = t.config()
+        delay, variant, ms, _ = t.config()
         it, gt = t.greedy(12)
     assert 1 <= delay <= 8 and variant in (0, 1)
     assert np.all(ms > 0) and delay == int(np.argmin(ms)) + 1
@@ -277,7 +277,7 @@ def test_autotuned_handle_selects_like_a_fixed_one(prec):
     np.testing.assert_array_equal(gt, g_f)
     check_trajectory(K, N_s, N_t, s2, it, gt, RTOL[prec])
     with selector(Kd, N_s, N_t, s2, precision=prec, autotune=True) as t2:
-        d2, v2, ms2 = t2.config()
+        d2, v2, ms2, _ = t2.config()
     assert (d2, v2) == (delay, variant)
     np.testing.assert_array_equal(ms2, ms)
 
@@ -366,3 +366,89 @@ def test_per_sensor_noise(prec, method, delay):
     assert np.all(rel_err(gain[:upto], ref["gain"][:upto]) <= RTOL[prec])
     if div is not None:
         assert ref["gap"][div] <= 2 * RTOL[prec] * max(1.0, abs(ref["gain"][div])), (div, ref["gap"][div])
+
+
+@pytest.mark.parametrize("prec", PRECS)
+def test_every_tile_order_gives_the_same_selection(prec):
+    """The downdate's tile order changes which work-group computes a tile, never the arithmetic:
+    at each delay every order gives bitwise the picks and gains of the others, on a ragged
+    instance whose tile rows are not a multiple of any super-tile edge, and the oracle agrees."""
+    N_s, N_t, B = 83, 48, 14   # 3,984 rows: 32 tile rows, the last one partial
+    K, Kd, s2 = instance(N_s, N_t, 6000, 31)
+    for delay in (1, 4, 7):
+        outs = []
+        for order in ("col4", "row8", "col8", "col2"):
+            print(f"tile order {order} delay {delay} {prec}", flush=True)
+            with selector(Kd, N_s, N_t, s2, precision=prec, delay=delay, tile_order=order) as sel:
+                assert sel.config()[3] == order
+                outs.append(sel.greedy(B))
+        for i1, g1 in outs[1:]:
+            assert list(i1) == list(outs[0][0])
+            np.testing.assert_array_equal(g1, outs[0][1])
+        check_trajectory(K, N_s, N_t, s2, outs[0][0], outs[0][1], RTOL[prec])
+
+
+def test_tune_cache_file_round_trip(tmp_path):
+    """With a tune-cache file the tuner appends its choice; a line edited in the file is what the
+    next tuned handle of that shape takes (the file takes precedence over the process's cache)."""
+    N_s, N_t = 37, 80
+    K, Kd, s2 = instance(N_s, N_t, 4000, 33)
+    path = tmp_path / "oed_tune.txt"
+    with selector(Kd, N_s, N_t, s2, precision="mixed_f32", autotune=True, tune_cache=str(path)) as t:
+        delay, variant, ms, order = t.config()
+        i0, g0 = t.greedy(9)
+    lines = path.read_text().splitlines()
+    assert len(lines) == 1 and lines[0].startswith("oedtune1 ")
+    f = lines[0].split()
+    assert int(f[6]) == delay and int(f[7]) == variant
+    f[6], f[7], f[8] = "2", "1", "3"          # delay 2, LDS downdate, 8 x 8 down the columns
+    path.write_text(" ".join(f) + "\n")
+    with selector(Kd, N_s, N_t, s2, precision="mixed_f32", autotune=True, tune_cache=str(path)) as t2:
+        d2, v2, _, o2 = t2.config()
+        i2, g2 = t2.greedy(9)
+    assert (d2, v2, o2) == (2, 1, "col8")
+    with selector(Kd, N_s, N_t, s2, precision="mixed_f32", delay=2) as f2:
+        i3, g3 = f2.greedy(9)
+    assert list(i2) == list(i3) and list(i0) == list(i3)
+    np.testing.assert_array_equal(g2, g3)
+
+
+@pytest.mark.parametrize("method", ["right", "left"])
+def test_injected_failure_stops_cleanly(method):
+    """debug_fail_step = 5: the fifth pick fails once on the host before anything of it is
+    enqueued.  The call returns OED_E_HIP with the picks made before it, the handle then refuses
+    steps until it is reset, the reset selection equals a clean one, and destroying the handle
+    returns all of its device memory."""
+    from paper_2604_08812_amd import OedError
+    N_s, N_t, B = 30, 32, 10
+    K, Kd, s2 = instance(N_s, N_t, 3000, 35)
+    kw = {"method": method, "max_budget": B} if method == "left" else {"delay": 3}
+    with selector(Kd, N_s, N_t, s2, precision="mixed_f32", **kw) as clean:
+        ic, gc = clean.greedy(B)
+        need = clean.device_bytes()
+    torch.cuda.synchronize()
+    free0 = torch.cuda.mem_get_info()[0]
+    sel = selector(Kd, N_s, N_t, s2, precision="mixed_f32", debug_fail_step=5, **kw)
+    assert sel.device_bytes() == need
+    idx, gain, st = sel.greedy_status(B)
+    assert st == 4 and len(idx) == 4
+    assert list(idx) == list(ic[:4])
+    np.testing.assert_array_equal(gain, gc[:4])
+    from paper_2604_08812_amd import library
+    assert "injected failure before pick 5" in library().oed_last_error(sel.h).decode()
+    with pytest.raises(OedError):
+        sel.greedy(1)
+    with pytest.raises(OedError):
+        sel.force(int(ic[5]))
+    sel.reset(Kd)
+    i2, g2 = sel.greedy(B)
+    assert list(i2) == list(ic)
+    np.testing.assert_array_equal(g2, gc)
+    sel.close()
+    torch.cuda.synchronize()
+    assert torch.cuda.mem_get_info()[0] == free0
+    # a limit of exactly what the handle holds is accepted; one byte less is OED_E_OOM
+    selector(Kd, N_s, N_t, s2, precision="mixed_f32", max_device_bytes=need, **kw).close()
+    with pytest.raises(OedError) as ei:
+        selector(Kd, N_s, N_t, s2, precision="mixed_f32", max_device_bytes=need - 1, **kw)
+    assert ei.value.status == 3 and str(need) in str(ei.value)

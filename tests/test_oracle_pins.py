@@ -475,3 +475,24 @@ def test_objective_parameter_space_and_generalised_eigenvalues():
         eig_iso = 0.5 * np.linalg.slogdet(np.eye(n_m) + FS.T @ FS / (n_m * s2))[1]
         got_iso = oracle.objective(Kiso, N_t, s2, S)
         assert abs(got_iso - eig_iso) <= 1e-11 * max(1.0, abs(eig_iso)), (S, got_iso, eig_iso)
+
+
+def test_step_replay_helper_matches_the_oracle_greedy():
+    """The GPU tests replay a trajectory step by step with oracle.gains; on the oracle's own picks
+    that replay must reproduce oracle.greedy exactly (picks, gains, its own argmax), with and
+    without a candidate subset, and a planted wrong pick must be reported."""
+    import sys
+    sys.path.insert(0, os.path.dirname(__file__))
+    from parity import check_trajectory
+    N_s, N_t, B = 12, 3, 6
+    K, s2 = make_K(N_s, N_t, 60, 77)
+    K = K.numpy()
+    for cand in (None, [0, 2, 3, 5, 7, 8, 10, 11]):
+        ref = oracle.greedy(K, N_s, N_t, s2, B, candidates=cand)
+        rep = check_trajectory(K, N_s, N_t, s2, ref["idx"], ref["gain"], 1e-12, candidates=cand)
+        assert list(rep["ref"]["best"]) == list(ref["idx"]) and rep["diverged_steps"] == []
+        np.testing.assert_array_equal(rep["ref"]["gain"], ref["gain"])
+    bad = list(ref["idx"])
+    bad[2], bad[3] = bad[3], bad[2]   # not a near-tie: the replay must reject it
+    with pytest.raises(AssertionError):
+        check_trajectory(K, N_s, N_t, s2, bad, ref["gain"], 1e-12, candidates=cand)
