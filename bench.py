@@ -49,6 +49,9 @@ def parse():
     ap.add_argument("--no-bf16x3", action="store_true")
     ap.add_argument("--no-left", action="store_true", help="skip the left-looking legs")
     ap.add_argument("--left", action="store_true", help="batched workload: left-looking method")
+    ap.add_argument("--branches", type=int, default=0,
+                    help="batched workload: concurrent launch sequences (0: the library's choice)")
+    ap.add_argument("--no-graph", action="store_true", help="batched workload: enqueue every run eagerly")
     ap.add_argument("--no-gaps", action="store_true", help="skip the per-step top-two gap scan (FP64)")
     ap.add_argument("--delay", type=int, default=0, help="downdate delay depth (0: the library's choice)")
     ap.add_argument("--no-autotune", action="store_true",
@@ -462,8 +465,8 @@ def run_batched(args):
     total_steps = sum(sp.budget for sp in specs)
     tune = args.delay == 0 and not args.no_autotune and not args.left
     bs = BatchSelector(items, precision=args.precision or "mixed_f32", profile=True, delay=args.delay, autotune=tune,
-                       method="left" if args.left else "right")
-    delay, tuned, tiles = bs.config()
+                       method="left" if args.left else "right", branches=args.branches, graph=not args.no_graph)
+    delay, tuned, tiles, branches = bs.config()
     for w in range(args.warmup):
         bs.reset(items)
         bs.run()
@@ -490,7 +493,7 @@ def run_batched(args):
         "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
         "config": {"workload": "batched_48_uneven", "instances": len(specs), "total_picks": total_steps,
                    "precision": args.precision or "mixed_f32", "K_dtype": "f32", "delay": delay, "tile_order": tiles,
-                   "autotuned": tune,
+                   "branches": branches, "graph": not args.no_graph, "autotuned": tune,
                    "method": "left-looking" if args.left else "right-looking",
                    "autotuner_run_ms_by_delay": [round(float(x), 3) for x in tuned] if tune else None,
                    "step": "oed_batch_reset + oed_batch_run"},

@@ -296,6 +296,14 @@ typedef struct oed_batch oed_batch;
 /* Downdate tile order o (OED_TILES_*, see oed_options.tile_order); without it OED_TILES_COL4, or
    the autotuner's choice with OED_BATCH_AUTOTUNE. */
 #define OED_BATCH_TILES(o) ((uint32_t)(o) << 12)
+/* Run the instances as g independent launch sequences (1 <= g <= OED_BATCH_MAX_BRANCHES): the
+   instances are split into g groups of about equal downdate work, each group's launches go to a
+   stream of its own, forked from and joined into the batch's stream (captured as parallel
+   branches of the one graph), so one group's latency-bound steps overlap another's downdates.
+   Without it: 4 (at most the number of instances), or with OED_BATCH_AUTOTUNE the tuner's choice.
+   Results do not depend on g. */
+#define OED_BATCH_MAX_BRANCHES 4
+#define OED_BATCH_BRANCHES(g) ((uint32_t)(g) << 16)
 /* Left-looking method for every instance (see OED_METHOD_LEFT_LOOKING; no delay, no autotuner). */
 #define OED_BATCH_LEFT_LOOKING 0x20u
 
@@ -329,11 +337,13 @@ OED_API oed_status oed_batch_reset(oed_batch *b, const oed_instance *inst, int32
  * algorithmic downdate flops and bytes of one run (definitions as in oed_profile). */
 OED_API oed_status oed_batch_stats(const oed_batch *b, double *run_ms, double *syrk_flops, double *syrk_bytes);
 
-/* The delay depth and the downdate tile order (OED_TILES_*) the batch runs with, and with
-   OED_BATCH_AUTOTUNE the autotuner's run time for depths 1..OED_MAX_DELAY in the default tile
-   order (OED_MAX_DELAY doubles, host); the tuner then also tries the other orders at the chosen
-   depth.  Any output pointer may be NULL. */
-OED_API oed_status oed_batch_get_config(const oed_batch *b, int32_t *delay, int32_t *tile_order, double *per_run_ms);
+/* The delay depth, the downdate tile order (OED_TILES_*) and the number of launch sequences the
+   batch runs with, and with OED_BATCH_AUTOTUNE the autotuner's run time for depths
+   1..OED_MAX_DELAY in the default tile order and one sequence (OED_MAX_DELAY doubles, host); the
+   tuner then tries the other orders and sequence counts at the chosen depth.  Any output pointer
+   may be NULL. */
+OED_API oed_status oed_batch_get_config(const oed_batch *b, int32_t *delay, int32_t *tile_order, int32_t *branches,
+                                        double *per_run_ms);
 OED_API oed_status oed_batch_destroy(oed_batch *b);
 OED_API const char *oed_batch_last_error(const oed_batch *b);
 
@@ -411,7 +421,8 @@ OED_API const char *oed_eval_last_error(const oed_eval *e);
  * anything runs: invalid arguments (OED_E_ARG), N_t > 128 or a problem whose workspaces exceed
  * OED_NOALLOC_MAX_BYTES (OED_E_UNSUPPORTED; the message gives the bytes needed:
  * the sum of N_s (N_s + 1)/2 N_tp^2 e_R (R), delay N_s N_tp^2 e_W (W; BF16: twice),
- * 8 (delay - 1) N_tp^2 (if delay > 1), 8 N_tp^2, 8 N_s, three times 4 N_s and 64 bytes, each
+ * 8 (delay - 1) N_tp^2 (if delay > 1), 8 N_tp^2, 8 N_s, 73,728 N_s (the factor cache of the
+ * pick), three times 4 N_s and 64 bytes, each
  * rounded up to a multiple of 256; N_tp = N_t rounded up to a multiple of 16, of 32 for
  * MIXED_BF16X3; e_R = 8 for FP64, else 4; e_W = 8, 4 or 2 by precision).
  * All calls on one GPU share its one array, which keeps the last call's contents (every buffer

@@ -47,6 +47,11 @@ struct oed_ctx {
     bool left = false;
     int max_budget = 0;
     bool diag_current = true;  // the diagonal blocks include every formed block column
+    // right-looking, N_t <= REGS_MAX_NT: the diagonal blocks are kept current eagerly (the gain
+    // kernel subtracts the newest block column from them and writes them back) and the downdate
+    // skips them, so the gains never carry the held columns
+    bool eager = false;
+    int newest = -1;  // W slot of the block column the diagonal blocks do not include yet
     void *C = nullptr;         // column partial sums (LEFT_SPLITS x N_c blocks, R's type)
     double *noise_h = nullptr; // per-sensor noise terms by local index (device), or null
     uint32_t flags = 0;
@@ -61,7 +66,7 @@ struct oed_ctx {
     int64_t wslot = 0;                               // elements per W slot
     double *V = nullptr;
     double *Linv = nullptr, *gains = nullptr, *pick_gain = nullptr, *scratch_gain = nullptr,
-           *scratch_pick = nullptr;
+           *scratch_pick = nullptr, *fcache = nullptr;
     int *act[2] = {nullptr, nullptr}, *picks = nullptr, *state = nullptr, *dcmap = nullptr;
     int64_t dev_bytes = 0;
     // host mirror of the selection
@@ -157,7 +162,7 @@ void collect_profile(oed_ctx *h)
 void free_all(oed_ctx *h)
 {
     void *ptrs[] = {h->R, h->W, h->W2, h->V, h->C, h->noise_h, h->Linv, h->gains, h->pick_gain, h->scratch_gain, h->scratch_pick,
-                    h->act[0], h->act[1], h->picks, h->state, h->dcmap};
+                    h->fcache, h->act[0], h->act[1], h->picks, h->state, h->dcmap};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
     for (auto &e : h->ev_pool) {
@@ -177,6 +182,7 @@ oed_status reset_state(oed_ctx *h)
     h->pending = false;
     h->nheld = 0;
     h->diag_current = true;
+    h->newest = -1;
     h->poisoned = false;
     h->h_picks.clear();
     h->h_gains.clear();
@@ -218,6 +224,7 @@ StepDesc desc(const oed_ctx *h)
     d.act_out = h->act[h->cur ^ 1];
     d.gains = h->gains;
     d.Linv = h->Linv;
+    d.fcache = h->fcache;
     d.state = h->state;
     d.picks = h->picks;
     d.pick_gain = h->pick_gain;
@@ -236,6 +243,7 @@ StepDesc desc(const oed_ctx *h)
 oed_status enqueue_syrk(oed_ctx *h, StepDesc d)
 {
     d.nitems = syrk_tiles(h->n_act, h->N_tp, h->stl);
+    d.skipdiag = h->eager ? 1 : 0;
     {
         Prof pr(h, OED_K_SYRK);
         HIPCHK(h, launch_syrk(d, h->rtype, h->wtype, h->syrk_variant, h->stream));
@@ -307,6 +315,10 @@ oed_status advance(oed_ctx *h, bool full)
             Prof pr(h, OED_K_TRSM);
             if (h->nheld > 0) HIPCHK(h, launch_vcorr(d, h->wtype, h->stream));
             HIPCHK(h, launch_trsm(d, h->rtype, h->wtype, h->stream));
+        }
+        if (h->eager) {
+            h->newest = h->nheld;  // the next gain launch applies it to the diagonal blocks
+            h->diag_current = false;
         }
         if (h->nheld + 1 < h->delay && !full) {
             ++h->nheld;
@@ -492,8 +504,15 @@ oed_status autotune(oed_ctx *h)
             d.n_act = n_at[z];
             d.nitems = n_at[z];
             d.nheld = hh;
+            // eager diagonal: the gain launch applies only the newest column and writes it back
+            // (the W slots are zero, so R stays exactly as packed)
+            StepDesc dg = d;
+            if (h->eager) {
+                dg.nheld = hh > 0 ? 1 : 0;
+                dg.wb = dg.nheld;
+            }
             double tg = 0, tt = 0;
-            e = time_ms(h, a, b, [&] { return launch_gain(d, h->rtype, h->wtype, h->stream); }, &tg);
+            e = time_ms(h, a, b, [&] { return launch_gain(dg, h->rtype, h->wtype, h->stream); }, &tg);
             if (e == hipSuccess)
                 e = time_ms(h, a, b, [&] {
                     hipError_t r = hh > 0 ? launch_vcorr(d, h->wtype, h->stream) : hipSuccess;
@@ -509,6 +528,7 @@ oed_status autotune(oed_ctx *h)
                 d.nheld = 0;
                 d.nw = p;
                 d.stl = TUNE_ORDERS[o];
+                d.skipdiag = h->eager ? 1 : 0;
                 d.nitems = syrk_tiles(n_at[z], h->N_tp, d.stl);
                 e = time_ms(h, a, b, [&] { return launch_syrk(d, h->rtype, h->wtype, SYRK_LDS, h->stream); },
                             &t_syrk[z][p - 1][o]);
@@ -568,7 +588,17 @@ oed_status enqueue_gains(oed_ctx *h)
 {
     StepDesc d = desc(h);
     d.scratch = h->scratch_gain;
-    if (h->left && !h->diag_current) {
+    if (h->eager) {
+        // the diagonal blocks include every column but the newest one: apply it and write back
+        d.nheld = 0;
+        if (!h->diag_current && h->newest >= 0) {
+            d.W = (char *)h->W + (size_t)(h->newest * h->wslot) * welem(h);
+            if (h->W2) d.W2 = (char *)h->W2 + (size_t)(h->newest * h->wslot) * 2;
+            d.nheld = 1;
+            d.wb = 1;
+        }
+        h->diag_current = true;
+    } else if (h->left && !h->diag_current) {
         // apply the newest block column (slot k-1) to the diagonal blocks, in place
         d.W = (char *)h->W + (size_t)((h->k - 1) * h->wslot) * welem(h);
         if (h->W2) d.W2 = (char *)h->W2 + (size_t)((h->k - 1) * h->wslot) * 2;
@@ -585,6 +615,7 @@ oed_status enqueue_pick(oed_ctx *h, int forced_local)
 {
     StepDesc d = desc(h);
     d.scratch = h->scratch_pick;
+    if (h->eager) d.nheld = 0;  // the winner's diagonal block is current
     d.forced = forced_local;
     d.nitems = 1;
     {
@@ -763,6 +794,7 @@ oed_status oed_create(oed_ctx **out, const void *K, int32_t dtype, int64_t ld, i
     }
     h->left = o.method == OED_METHOD_LEFT_LOOKING;
     if (h->left) h->delay = 1;
+    h->eager = !h->left && N_t <= REGS_MAX_NT;
     // the autotuner chooses the depth and, unless one is given, the tile order
     const bool tune = !h->left && o.delay == 0 && (o.flags & OED_FLAG_AUTOTUNE) && N_t <= REGS_MAX_NT;
     const bool tune_tiles = tune && o.tile_order == OED_TILES_AUTO;
@@ -826,6 +858,7 @@ oed_status oed_create(oed_ctx **out, const void *K, int32_t dtype, int64_t ld, i
         {(void **)&h->dcmap, sizeof(int) * h->N_c},
         {(void **)&h->scratch_gain, sizeof(double) * sg},
         {(void **)&h->scratch_pick, sizeof(double) * sp},
+        {(void **)&h->fcache, h->N_t <= REGS_MAX_NT ? sizeof(double) * 256 * FCACHE_BLOCKS * h->N_c : 0},
         {(void **)&h->noise_h, hloc.empty() ? 0 : sizeof(double) * h->N_c},
     };
     int64_t need = 0;
@@ -966,7 +999,7 @@ oed_status oed_force(oed_ctx *h, int32_t idx, double *gain_out)
     oed_status st = step_hook(h);
     if (st != OED_OK) return stop_after_failure(h, st, k0, nullptr, nullptr, nullptr);
     st = advance(h, false);
-    if (st == OED_OK && h->left && !h->diag_current) st = enqueue_gains(h);
+    if (st == OED_OK && (h->left || h->eager) && !h->diag_current) st = enqueue_gains(h);
     if (st == OED_OK) st = enqueue_pick(h, h->lmap[idx]);
     if (st != OED_OK) return st;
     oed_status dev = OED_OK;
@@ -1007,8 +1040,8 @@ oed_status oed_schur_block(oed_ctx *h, int32_t i, int32_t j, double *out)
     int li = h->lmap[i], lj = h->lmap[j];
     if (li < 0 || lj < 0 || h->picked[li] || h->picked[lj]) return fail(h, OED_E_ARG, "not a remaining candidate");
     oed_status st = advance(h, true);
-    // left-looking: bring the diagonal blocks up to date (the gains are recomputed as a side effect)
-    if (st == OED_OK && h->left && !h->diag_current) st = enqueue_gains(h);
+    // bring the diagonal blocks up to date (the gains are recomputed as a side effect)
+    if (st == OED_OK && (h->left || h->eager) && !h->diag_current) st = enqueue_gains(h);
     if (st != OED_OK) return st;
     const bool tr = li < lj;
     if (tr) std::swap(li, lj);

@@ -32,9 +32,10 @@ struct Inst {
     int64_t wslot = 0;                               // elements per W slot
     double *V = nullptr;
     void *C = nullptr;  // left-looking column partial sums (LEFT_SPLITS x N_s blocks, R's type)
-    double *Linv = nullptr, *gains = nullptr, *pick_gain = nullptr;
+    double *Linv = nullptr, *gains = nullptr, *pick_gain = nullptr, *fcache = nullptr;
     int *act[2] = {nullptr, nullptr}, *cmap = nullptr, *picks = nullptr, *state = nullptr;
     size_t off_gain = 0, off_int = 0;  // offsets of this instance's results in the results block
+    int branch = 0;                    // launch sequence (stream) the instance runs in
 };
 
 enum LaunchKind { L_INIT, L_GAIN, L_PICK, L_VCORR, L_TRSM, L_SYRK, L_COLUMN };
@@ -50,6 +51,7 @@ struct Launch {
     int N_tp = 0;        // L_SYRK
     int nw = 1;          // L_SYRK
     int max_Nt = 0;      // L_PICK
+    int branch = 0;      // launch sequence (stream) of the launch
 };
 
 Launch make_launch(int kind, int64_t desc0)
@@ -74,6 +76,13 @@ struct oed_batch {
     hipStream_t stream = nullptr;  // the batch's own stream (graph capture and replay)
     hipStream_t caller = nullptr;  // the stream given at creation: K is complete in its order
     hipEvent_t ev_in = nullptr;    // recorded on `caller` before every pack
+    // independent launch sequences: instances split into nbranch groups of about equal work, each
+    // group's launches on a stream of its own (branch 0: `stream`), forked from and joined into
+    // `stream`, so one group's latency-bound steps overlap another's downdates
+    int nbranch = 1;
+    std::vector<hipStream_t> bstream;  // branches 1 .. nbranch-1
+    hipEvent_t ev_fork = nullptr;
+    std::vector<hipEvent_t> ev_join;
     std::vector<void *> allocs;
     char *results = nullptr;  // [gains of all picks (double)][picks + state words (int)]
     size_t results_bytes = 0, n_gain = 0;
@@ -120,6 +129,11 @@ void bfree(oed_batch *b)
     if (b->ev0) (void)hipEventDestroy(b->ev0);
     if (b->ev1) (void)hipEventDestroy(b->ev1);
     if (b->ev_in) (void)hipEventDestroy(b->ev_in);
+    if (b->ev_fork) (void)hipEventDestroy(b->ev_fork);
+    for (hipEvent_t e : b->ev_join)
+        if (e) (void)hipEventDestroy(e);
+    for (hipStream_t t : b->bstream)
+        if (t) (void)hipStreamDestroy(t);
     if (b->stream) (void)hipStreamDestroy(b->stream);
 }
 
@@ -171,6 +185,7 @@ StepDesc inst_desc(const Inst &x, int k, bool after_pick, int delay, int stl = S
     d.act_out = x.act[(k + 1) & 1];
     d.gains = x.gains;
     d.Linv = x.Linv;
+    d.fcache = x.fcache;
     d.state = x.state;
     d.picks = x.picks;
     d.pick_gain = x.pick_gain;
@@ -216,20 +231,22 @@ void left_out_slot(const oed_batch *b, const Inst &x, int k, StepDesc &d)
     if (x.W2) d.W2 = (char *)x.W2 + (size_t)(k * x.wslot) * 2;
 }
 
-void build_schedule_left(oed_batch *b)
+void build_branch_left(oed_batch *b, int br)
 {
     const double e = b->rtype == R_F64 ? 8.0 : 4.0;
     int maxB = 0;
     for (size_t i = 0; i < b->in.size(); ++i) {
+        if (b->in[i].branch != br) continue;
         maxB = std::max(maxB, b->in[i].budget);
         Launch L = make_launch(L_INIT, 0);
         L.inst = (int)i;
         b->launches.push_back(L);
     }
+    auto mine = [&](const Inst &x) { return x.branch == br; };
     for (int k = 0; k < maxB; ++k) {
         Launch g = make_launch(L_GAIN, (int64_t)b->descs.size());
         for (const Inst &x : b->in)
-            if (x.budget > k) {
+            if (mine(x) && x.budget > k) {
                 StepDesc d = inst_desc_left(b, x, k, false);
                 d.item0 = g.total;
                 d.nitems = d.n_act;
@@ -240,7 +257,7 @@ void build_schedule_left(oed_batch *b)
         b->launches.push_back(g);
         Launch p = make_launch(L_PICK, (int64_t)b->descs.size());
         for (const Inst &x : b->in)
-            if (x.budget > k) {
+            if (mine(x) && x.budget > k) {
                 StepDesc d = inst_desc_left(b, x, k, false);
                 d.nheld = 0;
                 d.wb = 0;
@@ -255,7 +272,7 @@ void build_schedule_left(oed_batch *b)
         // block column of pick k for the instances that pick again
         std::map<int, std::vector<const Inst *>> by_ntp;
         for (const Inst &x : b->in)
-            if (x.budget > k + 1 && k >= 1) by_ntp[x.N_tp].push_back(&x);
+            if (mine(x) && x.budget > k + 1 && k >= 1) by_ntp[x.N_tp].push_back(&x);
         for (auto &kv : by_ntp) {
             Launch c = make_launch(L_COLUMN, (int64_t)b->descs.size());
             c.N_tp = kv.first;
@@ -274,7 +291,7 @@ void build_schedule_left(oed_batch *b)
         }
         Launch t = make_launch(L_TRSM, (int64_t)b->descs.size());
         for (const Inst &x : b->in)
-            if (x.budget > k + 1) {
+            if (mine(x) && x.budget > k + 1) {
                 StepDesc d = inst_desc_left(b, x, k, true);
                 left_out_slot(b, x, k, d);
                 d.item0 = t.total;
@@ -287,28 +304,37 @@ void build_schedule_left(oed_batch *b)
     }
 }
 
-// Build the descriptor array and the launch list of one run.
-void build_schedule(oed_batch *b)
+// The descriptors and launches of branch br (the instances with x.branch == br).
+void build_branch(oed_batch *b, int br)
 {
-    b->descs.clear();
-    b->launches.clear();
-    b->syrk_flops = b->syrk_bytes = 0;
-    if (b->left) return build_schedule_left(b);
     const double e = b->rtype == R_F64 ? 8.0 : 4.0;
     int maxB = 0;
     for (size_t i = 0; i < b->in.size(); ++i) {
+        if (b->in[i].branch != br) continue;
         maxB = std::max(maxB, b->in[i].budget);
         Launch L = make_launch(L_INIT, 0);
         L.inst = (int)i;
         b->launches.push_back(L);
     }
+    auto mine = [&](const Inst &x) { return x.branch == br; };
     for (int k = 0; k < maxB; ++k) {
         // gains and pick of step k (design evaluation: no gains, the pick is candidate k)
         if (!b->eval) {
             Launch g = make_launch(L_GAIN, (int64_t)b->descs.size());
             for (const Inst &x : b->in)
-                if (x.budget > k) {
+                if (mine(x) && x.budget > k) {
                     StepDesc d = inst_desc(x, k, false, b->delay);
+                    // eager diagonal: apply the newest block column (pick k - 1, slot (k - 1) mod
+                    // delay) to the diagonal blocks and write them back; the rest are included
+                    d.nheld = 0;
+                    if (k >= 1) {
+                        const size_t we = b->wtype == W_F64 ? 8 : b->wtype == W_F32 ? 4 : 2;
+                        const int slot = (k - 1) % b->delay;
+                        d.W = (char *)x.W + (size_t)(slot * x.wslot) * we;
+                        if (x.W2) d.W2 = (char *)x.W2 + (size_t)(slot * x.wslot) * 2;
+                        d.nheld = 1;
+                        d.wb = 1;
+                    }
                     d.item0 = g.total;
                     d.nitems = d.n_act;
                     g.total += d.nitems;
@@ -319,9 +345,12 @@ void build_schedule(oed_batch *b)
         }
         Launch p = make_launch(L_PICK, (int64_t)b->descs.size());
         for (const Inst &x : b->in)
-            if (x.budget > k) {
+            if (mine(x) && x.budget > k) {
                 StepDesc d = inst_desc(x, k, false, b->delay);
-                if (b->eval) d.forced = k;
+                if (b->eval)
+                    d.forced = k;  // no gain launches: the pick applies the held columns itself
+                else
+                    d.nheld = 0;   // the winner's diagonal block is current
                 d.item0 = p.total;
                 d.nitems = 1;
                 p.total += 1;
@@ -338,7 +367,7 @@ void build_schedule(oed_batch *b)
         if (corr) {
             Launch v = make_launch(L_VCORR, (int64_t)b->descs.size());
             for (const Inst &x : b->in)
-                if (x.budget > k + 1) {
+                if (mine(x) && x.budget > k + 1) {
                     StepDesc d = inst_desc(x, k, true, b->delay);
                     d.item0 = v.total;
                     d.nitems = (int64_t)d.nheld * (x.N_tp / 16) * (x.N_tp / 16);
@@ -351,7 +380,7 @@ void build_schedule(oed_batch *b)
         Launch t = make_launch(L_TRSM, (int64_t)b->descs.size());
         std::map<int, std::vector<const Inst *>> by_ntp;
         for (const Inst &x : b->in)
-            if (x.budget > k + 1) {
+            if (mine(x) && x.budget > k + 1) {
                 StepDesc d = inst_desc(x, k, true, b->delay);
                 d.item0 = t.total;
                 d.nitems = d.n_act;
@@ -375,6 +404,7 @@ void build_schedule(oed_batch *b)
             for (const Inst *x : kv.second) {
                 StepDesc d = inst_desc(*x, k, true, b->delay, b->stl);
                 d.nw = s.nw;
+                d.skipdiag = b->eval ? 0 : 1;  // kept current by the gain launches
                 d.item0 = s.total;
                 d.nitems = syrk_tiles(d.n_act, d.N_tp, b->stl);
                 s.total += d.nitems;
@@ -386,35 +416,89 @@ void build_schedule(oed_batch *b)
     }
 }
 
+// Build the descriptor array and the launch list of one run: branch after branch, each launch
+// tagged with its branch.
+void build_schedule(oed_batch *b)
+{
+    b->descs.clear();
+    b->launches.clear();
+    b->syrk_flops = b->syrk_bytes = 0;
+    for (int br = 0; br < b->nbranch; ++br) {
+        const size_t l0 = b->launches.size();
+        if (b->left)
+            build_branch_left(b, br);
+        else
+            build_branch(b, br);
+        for (size_t l = l0; l < b->launches.size(); ++l) b->launches[l].branch = br;
+    }
+}
+
 oed_status enqueue_run(oed_batch *b)
 {
+    // fork: every branch starts after what `stream` holds (the packs); join at the end
+    if (b->nbranch > 1) {
+        BCHK(b, hipEventRecord(b->ev_fork, b->stream));
+        for (int br = 1; br < b->nbranch; ++br) BCHK(b, hipStreamWaitEvent(b->bstream[br - 1], b->ev_fork, 0));
+    }
     for (const Launch &L : b->launches) {
         const StepDesc *d = b->d_descs + L.desc0;
+        const hipStream_t stream = L.branch == 0 ? b->stream : b->bstream[L.branch - 1];
         switch (L.kind) {
         case L_INIT: {
             const Inst &x = b->in[L.inst];
-            BCHK(b, launch_init_state(x.act[0], x.N_s, x.state, b->stream));
+            BCHK(b, launch_init_state(x.act[0], x.N_s, x.state, stream));
             break;
         }
-        case L_GAIN: BCHK(b, launch_gain_batched(d, L.ndesc, L.total, b->rtype, b->wtype, b->stream)); break;
-        case L_PICK: BCHK(b, launch_pick_batched(d, L.ndesc, L.max_Nt, b->rtype, b->wtype, b->stream)); break;
-        case L_VCORR: BCHK(b, launch_vcorr_batched(d, L.ndesc, L.total, b->wtype, b->stream)); break;
+        case L_GAIN: BCHK(b, launch_gain_batched(d, L.ndesc, L.total, b->rtype, b->wtype, stream)); break;
+        case L_PICK: BCHK(b, launch_pick_batched(d, L.ndesc, L.max_Nt, b->rtype, b->wtype, stream)); break;
+        case L_VCORR: BCHK(b, launch_vcorr_batched(d, L.ndesc, L.total, b->wtype, stream)); break;
         case L_COLUMN:
-            BCHK(b, launch_column_batched(d, L.ndesc, L.total, L.N_tp, b->rtype, b->wtype, b->stream));
+            BCHK(b, launch_column_batched(d, L.ndesc, L.total, L.N_tp, b->rtype, b->wtype, stream));
             break;
-        case L_TRSM: BCHK(b, launch_trsm_batched(d, L.ndesc, L.total, b->rtype, b->wtype, b->stream)); break;
+        case L_TRSM: BCHK(b, launch_trsm_batched(d, L.ndesc, L.total, b->rtype, b->wtype, stream)); break;
         case L_SYRK:
-            BCHK(b, launch_syrk_batched(d, L.ndesc, L.total, L.N_tp, L.nw, b->rtype, b->wtype, SYRK_LDS, b->stream));
+            BCHK(b, launch_syrk_batched(d, L.ndesc, L.total, L.N_tp, L.nw, b->rtype, b->wtype, SYRK_LDS, stream));
             break;
+        }
+    }
+    if (b->nbranch > 1) {
+        for (int br = 1; br < b->nbranch; ++br) {
+            BCHK(b, hipEventRecord(b->ev_join[br - 1], b->bstream[br - 1]));
+            BCHK(b, hipStreamWaitEvent(b->stream, b->ev_join[br - 1], 0));
         }
     }
     return OED_OK;
 }
 
+// Split the instances into b->nbranch groups of about equal work: largest first, each to the
+// group with the least work so far (ties to the lowest group); work = the downdate flops of the
+// whole selection, sum over the steps of N_t n^2 (n = remaining rows).
+void assign_branches(oed_batch *b)
+{
+    const int n = (int)b->in.size();
+    std::vector<double> cost(n, 0.0);
+    for (int i = 0; i < n; ++i) {
+        const Inst &x = b->in[i];
+        for (int k = 0; k < x.budget; ++k) {
+            const double r = (double)(x.N_s - k) * x.N_t;
+            cost[i] += x.N_t * r * r;
+        }
+    }
+    std::vector<int> order(n);
+    for (int i = 0; i < n; ++i) order[i] = i;
+    std::stable_sort(order.begin(), order.end(), [&](int a, int c) { return cost[a] > cost[c]; });
+    std::vector<double> load(b->nbranch, 0.0);
+    for (int i : order) {
+        const int br = (int)(std::min_element(load.begin(), load.end()) - load.begin());
+        b->in[i].branch = br;
+        load[br] += cost[i];
+    }
+}
+
 // Autotuner (OED_BATCH_AUTOTUNE with no delay given): runs the whole selection once per delay
 // depth p = 1..MAX_DELAY, eagerly, from freshly packed working copies, and keeps the fastest.
 // All depths give the same picks up to rounding; W slots for MAX_DELAY are allocated.
-oed_status autotune_batch(oed_batch *b, const oed_instance *inst, bool tiles)
+oed_status autotune_batch(oed_batch *b, const oed_instance *inst, bool tiles, bool branches)
 {
     auto timed_run = [&](double *out) -> oed_status {
         build_schedule(b);
@@ -458,6 +542,25 @@ oed_status autotune_batch(oed_batch *b, const oed_instance *inst, bool tiles)
         }
     }
     b->stl = best_stl;
+    if (!branches) return OED_OK;
+    // 1 .. the most branches the streams were made for, at the chosen depth and order
+    int best_br = b->nbranch;
+    for (int nb = 1; nb <= (int)b->bstream.size() + 1; ++nb) {
+        if (nb == b->nbranch) continue;
+        const int keep = b->nbranch;
+        b->nbranch = nb;
+        assign_branches(b);
+        double ms = 0;
+        oed_status st = timed_run(&ms);
+        if (st != OED_OK) return st;
+        if (ms < best) {
+            best = ms;
+            best_br = nb;
+        }
+        b->nbranch = keep;
+    }
+    b->nbranch = best_br;
+    assign_branches(b);
     return OED_OK;
 }
 
@@ -479,6 +582,8 @@ static oed_status create_batch(oed_batch **out, const oed_instance *inst, int32_
     if (((flags >> 8) & 0xFu) > (unsigned)MAX_DELAY) return OED_E_ARG;
     const unsigned tiles = (flags >> 12) & 0xFu;
     if (tiles > OED_TILES_COL2) return OED_E_ARG;
+    const unsigned branches = (flags >> 16) & 0xFu;
+    if (branches > OED_BATCH_MAX_BRANCHES) return OED_E_ARG;
     oed_batch *b = new (std::nothrow) oed_batch();
     if (!b) return OED_E_OOM;
     b->prec = precision;
@@ -491,6 +596,8 @@ static oed_status create_batch(oed_batch **out, const oed_instance *inst, int32_
     const bool tune = !b->left && b->delay == 0 && (flags & OED_BATCH_AUTOTUNE);
     static const int stl_of[] = {STL_COL4, STL_ROW8, STL_COL8, STL_COL4, STL_COL2};
     b->stl = stl_of[tiles];
+    b->nbranch = std::min<int>(n, branches == 0 ? DEFAULT_BRANCHES : (int)branches);
+    const bool tune_br = tune && !eval && branches == 0;
     if (b->delay == 0) b->delay = DEFAULT_DELAY;
     if (b->left) b->delay = 1;
     // W slots and held-column buffers for the deepest delay the batch may run with
@@ -503,6 +610,15 @@ static oed_status create_batch(oed_batch **out, const oed_instance *inst, int32_
         BCHK(b, hipEventCreate(&b->ev0));
         BCHK(b, hipEventCreate(&b->ev1));
         BCHK(b, hipEventCreateWithFlags(&b->ev_in, hipEventDisableTiming));
+        // streams and events for the most branches the batch may run with
+        const int max_br = std::min<int>(n, tune_br ? OED_BATCH_MAX_BRANCHES : (int)b->nbranch);
+        BCHK(b, hipEventCreateWithFlags(&b->ev_fork, hipEventDisableTiming));
+        b->bstream.assign(std::max(0, max_br - 1), nullptr);
+        b->ev_join.assign(std::max(0, max_br - 1), nullptr);
+        for (int q = 0; q + 1 < max_br; ++q) {
+            BCHK(b, hipStreamCreateWithFlags(&b->bstream[q], hipStreamNonBlocking));
+            BCHK(b, hipEventCreateWithFlags(&b->ev_join[q], hipEventDisableTiming));
+        }
         const size_t er = b->rtype == R_F64 ? 8 : 4;
         size_t n_gain = 0, n_int = 0;
         b->in.resize(n);
@@ -531,6 +647,7 @@ static oed_status create_batch(oed_batch **out, const oed_instance *inst, int32_
             if (b->left) BCHK(b, balloc(b, &x.C, (size_t)(LEFT_SPLITS * x.N_s * bs) * er));
             BCHK(b, balloc(b, (void **)&x.Linv, sizeof(double) * bs));
             BCHK(b, balloc(b, (void **)&x.gains, sizeof(double) * x.N_s));
+            if (!eval) BCHK(b, balloc(b, (void **)&x.fcache, sizeof(double) * 256 * FCACHE_BLOCKS * x.N_s));
             BCHK(b, balloc(b, (void **)&x.act[0], sizeof(int) * x.N_s));
             BCHK(b, balloc(b, (void **)&x.act[1], sizeof(int) * x.N_s));
             BCHK(b, balloc(b, (void **)&x.cmap, sizeof(int) * x.N_s));
@@ -543,6 +660,7 @@ static oed_status create_batch(oed_batch **out, const oed_instance *inst, int32_
             n_int += x.budget + ST_WORDS;
         }
         b->n_gain = n_gain;
+        assign_branches(b);
         b->results_bytes = sizeof(double) * n_gain + sizeof(int) * n_int;
         BCHK(b, balloc(b, (void **)&b->results, b->results_bytes));
         int *ires = (int *)(b->results + sizeof(double) * n_gain);
@@ -554,15 +672,21 @@ static oed_status create_batch(oed_batch **out, const oed_instance *inst, int32_
         // descriptor array sized for the longest schedule (every delay depth the tuner may try)
         size_t ndesc = 1;
         for (int p = tune ? 1 : b->delay; p <= max_p; ++p) {
-            const int keep = b->delay;
+            const int keep = b->delay, keep_br = b->nbranch;
             b->delay = p;
-            build_schedule(b);
-            ndesc = std::max(ndesc, b->descs.size());
+            for (int nb = 1; nb <= (int)b->bstream.size() + 1; ++nb) {
+                b->nbranch = nb;
+                assign_branches(b);
+                build_schedule(b);
+                ndesc = std::max(ndesc, b->descs.size());
+            }
             b->delay = keep;
+            b->nbranch = keep_br;
+            assign_branches(b);
         }
         BCHK(b, balloc(b, (void **)&b->d_descs, sizeof(StepDesc) * ndesc));
         if (tune) {
-            oed_status s2 = autotune_batch(b, inst, !eval && tiles == OED_TILES_AUTO);
+            oed_status s2 = autotune_batch(b, inst, !eval && tiles == OED_TILES_AUTO, tune_br);
             if (s2 != OED_OK) return s2;
         }
         build_schedule(b);
@@ -585,10 +709,12 @@ oed_status oed_batch_create(oed_batch **out, const oed_instance *inst, int32_t n
     return create_batch(out, inst, n, precision, stream, flags, false);
 }
 
-oed_status oed_batch_get_config(const oed_batch *b, int32_t *delay, int32_t *tile_order, double *per_run_ms)
+oed_status oed_batch_get_config(const oed_batch *b, int32_t *delay, int32_t *tile_order, int32_t *branches,
+                                double *per_run_ms)
 {
     if (!b) return OED_E_ARG;
     if (delay) *delay = b->delay;
+    if (branches) *branches = b->nbranch;
     if (tile_order)
         *tile_order = b->stl == STL_ROW8 ? OED_TILES_ROW8 : b->stl == STL_COL8 ? OED_TILES_COL8
                       : b->stl == STL_COL4 ? OED_TILES_COL4 : OED_TILES_COL2;

@@ -330,44 +330,45 @@ __device__ __forceinline__ bool chol_mfma_regs(UBlocks &A, int nbr, double *piv,
     return true;
 }
 
-// The gain kernel's factorisation: pivots only.
+// Blocks of a candidate's factor kept by the gain kernel for the pick (FCACHE_BLOCKS of 256
+// doubles, lane-major doublex4 per block): slot p < 8 holds U_pp^-1, slot 8 + C (C - 1) / 2 + I
+// holds the off-diagonal block U_IC, I < C.  Only blocks with C < ceil(N_t / 16) are written.
+constexpr int FCACHE_UO = 8;
+
+// The gain kernel's factorisation: the pivots, and with fc (the candidate's factor-cache slots,
+// global memory) U_pp^-1 and the off-diagonal blocks of U for the pick.
 template <typename TR, typename TW>
 __device__ __forceinline__ bool chol_mfma(const TR *__restrict__ Rb, int N_t, int nb, double *piv, const StepDesc &d,
-                                          int64_t pofs)
+                                          int64_t pofs, doublex4 (*fc)[64])
 {
     const int nbr = (N_t + 15) >> 4;
     UBlocks A;
     load_upper<TR, TW>(A, Rb, nbr, nb, d, pofs);
-    return chol_mfma_regs(A, nbr, piv, nullptr);
-}
-
-// The pick's factor and inverse for N_t <= 128: the register factorisation above (keeping every
-// U_pp^-1), the off-diagonal blocks of U published to LDS, then Z = L^-1 = U^-T by block columns
-// in registers (wave w: columns w and 7 - w), Z_qq = (U_qq^-1)^T and down the column
-// Z_pq = -(U_pp^-1)^T sum_{r = q}^{p-1} U_rp^T Z_rq, and Z written to Linv in the operand order.
-// Blocks of Linv outside the factored part: zero above the diagonal, identity on the padding.
-template <typename TR, typename TW>
-__device__ __forceinline__ bool chol_inv_mfma(const TR *__restrict__ Rb, int N_t, int N_tp, double *piv,
-                                              const StepDesc &d, int64_t pofs, double *__restrict__ Linv)
-{
-    __shared__ doublex4 Y[8][64];    // U_pp^-1
-    __shared__ doublex4 Uo[28][64];  // U_rp, r < p, at p (p - 1) / 2 + r
-    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6, g = lane >> 4, c = lane & 15;
-    const int al = a_lane<double>(lane);
-    const int nbr = (N_t + 15) >> 4, nb = N_tp >> 4;
-    {
-        UBlocks A;
-        load_upper<TR, TW>(A, Rb, nbr, nb, d, pofs);
-        if (!chol_mfma_regs(A, nbr, piv, Y)) return false;
+    if (!chol_mfma_regs(A, nbr, piv, fc)) return false;
+    if (fc) {
+        const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
 #pragma unroll
         for (int h = 0; h < 2; ++h) {
             const int C = h ? 7 - w : w;
 #pragma unroll
             for (int I = 0; I < (h ? 8 : 4); ++I)
-                if (I < C && C < nbr) Uo[C * (C - 1) / 2 + I][lane] = ub(A, h, I);
+                if (I < C && C < nbr) fc[FCACHE_UO + C * (C - 1) / 2 + I][lane] = ub(A, h, I);
         }
     }
-    __syncthreads();
+    return true;
+}
+
+
+// The inverse Z = L^-1 = U^-T of a factor held in LDS (Y: U_pp^-1, Uo: U_rp at p (p - 1) / 2 + r), by
+// block columns in registers (wave w: columns w and 7 - w), Z_qq = (U_qq^-1)^T and down the column
+// Z_pq = -(U_pp^-1)^T sum_{r = q}^{p-1} U_rp^T Z_rq, written to Linv in the operand order.  Blocks of
+// Linv outside the factored part: zero above the diagonal, identity on the padding.
+__device__ __forceinline__ void inv_from_lds(const doublex4 (*Y)[64], const doublex4 (*Uo)[64], int N_t, int N_tp,
+                                             double *__restrict__ Linv)
+{
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6, g = lane >> 4, c = lane & 15;
+    const int al = a_lane<double>(lane);
+    const int nbr = (N_t + 15) >> 4, nb = N_tp >> 4;
     // element (4g + r, c) of a block's transpose sits at tofs + 4r of the block (accumulator order)
     const int tofs = ((((c >> 2) << 4) + 4 * g) << 2) + (c & 3);
     // Z column q0 = w keeps blocks P = 0..7 (those with P >= q0 used), q1 = 7 - w blocks P = 4..7
@@ -419,6 +420,32 @@ __device__ __forceinline__ bool chol_inv_mfma(const TR *__restrict__ Rb, int N_t
             Linv[o] = k == kp ? 1.0 : 0.0;
         }
     }
+}
+
+// The pick's factor and inverse for N_t <= 128: the register factorisation above (keeping every
+// U_pp^-1), the off-diagonal blocks of U published to LDS, then the inverse (inv_from_lds).
+template <typename TR, typename TW>
+__device__ __forceinline__ bool chol_inv_mfma(const TR *__restrict__ Rb, int N_t, int N_tp, double *piv,
+                                              const StepDesc &d, int64_t pofs, double *__restrict__ Linv,
+                                              doublex4 (*Y)[64], doublex4 (*Uo)[64])
+{
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    const int nbr = (N_t + 15) >> 4, nb = N_tp >> 4;
+    {
+        UBlocks A;
+        load_upper<TR, TW>(A, Rb, nbr, nb, d, pofs);
+        if (!chol_mfma_regs(A, nbr, piv, Y)) return false;
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            const int C = h ? 7 - w : w;
+#pragma unroll
+            for (int I = 0; I < (h ? 8 : 4); ++I)
+                if (I < C && C < nbr) Uo[C * (C - 1) / 2 + I][lane] = ub(A, h, I);
+        }
+    }
+    (void)tid;
+    __syncthreads();
+    inv_from_lds(Y, Uo, N_t, N_tp, Linv);
     return true;
 }
 
@@ -506,7 +533,8 @@ __device__ void gain_regs_body(const StepDesc &d, int p)
     if (d.state[ST_STATUS] != 0 || p >= d.n_act) return;
     const int i = uniform_at(d.act_in, p);
     const int64_t bs = (int64_t)d.N_tp * d.N_tp;
-    const bool ok = chol_mfma<TR, TW>((const TR *)d.R + blk_index(i, i) * bs, d.N_t, d.N_tp >> 4, piv, d, i * bs);
+    doublex4(*fc)[64] = d.fcache ? (doublex4(*)[64])(d.fcache + (int64_t)i * (FCACHE_BLOCKS * 256)) : nullptr;
+    const bool ok = chol_mfma<TR, TW>((const TR *)d.R + blk_index(i, i) * bs, d.N_t, d.N_tp >> 4, piv, d, i * bs, fc);
     if (!ok) {
         if (threadIdx.x == 0) d.gains[p] = -INFINITY;
         return;
@@ -520,6 +548,8 @@ __device__ void pick_regs_body(const StepDesc &d)
 {
     __shared__ double piv[128];
     __shared__ double red[4];
+    __shared__ doublex4 Y[8][64];    // U_pp^-1
+    __shared__ doublex4 Uo[28][64];  // U_rp, r < p, at p (p - 1) / 2 + r
     if (d.state[ST_STATUS] != 0) return;
     const int tid = threadIdx.x;
     double g = 0.0;
@@ -527,9 +557,34 @@ __device__ void pick_regs_body(const StepDesc &d)
     if (pos < 0) return;
     const int s = d.act_in[pos];
     for (int p = tid; p < d.n_act - 1; p += blockDim.x) d.act_out[p] = d.act_in[p < pos ? p : p + 1];
+    if (d.fcache && d.forced < 0) {
+        // the gain kernel of this step factored the winner's block: its U_pp^-1 and off-diagonal
+        // blocks of U are in the factor cache, and only the inverse is left to form
+        const int nbr = (d.N_t + 15) >> 4;
+        const doublex4 *fc = (const doublex4 *)(d.fcache + (int64_t)s * (FCACHE_BLOCKS * 256));
+        for (int o = tid; o < 36 * 64; o += blockDim.x) {
+            const int blk = o >> 6, ln = o & 63;
+            const bool used = blk < FCACHE_UO ? blk < nbr : (blk - FCACHE_UO) < nbr * (nbr - 1) / 2;
+            if (!used) continue;
+            const doublex4 v = fc[o];
+            if (blk < FCACHE_UO)
+                Y[blk][ln] = v;
+            else
+                Uo[blk - FCACHE_UO][ln] = v;
+        }
+        __syncthreads();
+        inv_from_lds(Y, Uo, d.N_t, d.N_tp, d.Linv);
+        if (tid == 0) {
+            d.picks[d.step] = s;
+            d.pick_gain[d.step] = g;
+            d.state[ST_NPICKS] = d.step + 1;
+            d.state[ST_LAST] = s;
+        }
+        return;
+    }
     const int64_t bs = (int64_t)d.N_tp * d.N_tp;
     const bool ok = chol_inv_mfma<TR, TW>((const TR *)d.R + blk_index(s, s) * bs, d.N_t, d.N_tp, piv, d, s * bs,
-                                          d.Linv);
+                                          d.Linv, Y, Uo);
     if (!ok) {
         if (tid == 0) d.state[ST_STATUS] = 2;
         return;

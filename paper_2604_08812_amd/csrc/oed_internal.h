@@ -65,6 +65,8 @@ enum StateWord { ST_STATUS = 0, ST_NPICKS = 1, ST_LAST = 2, ST_WORDS = 16 };
 // depth taken when none is given and the autotuner is not asked for.
 constexpr int MAX_DELAY = 8;  // OED_MAX_DELAY of the C ABI
 constexpr int DEFAULT_DELAY = 4;
+// Concurrent launch sequences of a batch when none is given (OED_BATCH_BRANCHES).
+constexpr int DEFAULT_BRANCHES = 4;
 
 struct StepDesc {
     void *R;               // working copy (element type by precision)
@@ -89,6 +91,9 @@ struct StepDesc {
     int *picks;            // local index of every pick
     double *pick_gain;     // gain of every pick
     double *scratch;       // global scratch of the LDS factorisation kernels (N_t > REGS_MAX_NT)
+    double *fcache;        // N_t <= REGS_MAX_NT: per candidate (local index) FCACHE_BLOCKS blocks of 256
+                           // doubles, the factor the gain kernel found, for the pick of the same step;
+                           // null: the pick factors the winner itself
     double half_noise;     // (N_t / 2) ln sigma^2 (isotropic noise)
     const double *noise_h; // per-sensor noise term h_j by local candidate index, or null: half_noise
     int n_act;             // number of entries of act_in
@@ -97,6 +102,7 @@ struct StepDesc {
     int forced;            // pick: forced local index, or -1 for the argmax
     int nw;                // syrk: W slots 0 .. nw-1 applied (inner dimension nw N_tp)
     int stl;               // syrk: super-tile code of the tile order (see super_tile(); 0 = 8 x 8)
+    int skipdiag;          // syrk: leave the diagonal blocks alone (kept current by the gain kernel)
     int64_t item0;         // batched launches: first work item of this instance
     int64_t nitems;        // work items of this instance (gain, trsm: n_act; pick: 1; syrk: tiles)
 };
@@ -166,6 +172,9 @@ hipError_t launch_syrk_batched(const StepDesc *descs, int n, int64_t total, int 
 // Largest N_t handled by the register-resident factorisation kernels; beyond it the
 // LDS / global-scratch kernels run.
 constexpr int REGS_MAX_NT = 128;
+// Blocks of 16 x 16 doubles the factor cache keeps per candidate: U_pp^-1 for the 8 diagonal
+// blocks and the 28 off-diagonal blocks of U (N_t <= REGS_MAX_NT).
+constexpr int FCACHE_BLOCKS = 36;
 // Largest padded block size of the blocked global-scratch factorisation kernels (and of the
 // left-looking method beyond REGS_MAX_NT); larger blocks fall back to element-wise kernels.
 constexpr int BLK_MAX_NTP = 1024;

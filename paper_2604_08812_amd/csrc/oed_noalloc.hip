@@ -1,7 +1,7 @@
 // oed_greedy_noalloc: a whole greedy selection that allocates nothing (declaration and contract in
 // include/oed.h).  The working copy R, the W slots, L_s^-1, the held-column corrections, the
 // gains, the active lists and the state words live in one file-scope device array, `scratch`,
-// of OED_NOALLOC_MAX_BYTES; the kernels are those of oed_create / oed_greedy (right-looking,
+// of OED_NOALLOC_MAX_BYTES (the factor cache of the pick too); the kernels are those of oed_create / oed_greedy (right-looking,
 // fixed delay depth, LDS downdate), launched in the same order, so the picks and gains are
 // bitwise those of a handle created with the same precision and delay.
 //
@@ -43,7 +43,7 @@ int64_t align256(int64_t b) { return (b + 255) / 256 * 256; }
 
 // Byte offsets of the buffers inside the scratch array (each 256-byte aligned).
 struct Layout {
-    int64_t R, W, W2, V, Linv, gains, act0, act1, cmap, state, total;
+    int64_t R, W, W2, V, Linv, gains, fcache, act0, act1, cmap, state, total;
 };
 
 Layout layout(int N, int N_tp, int prec, int delay)
@@ -64,6 +64,7 @@ Layout layout(int N, int N_tp, int prec, int delay)
     L.V = delay > 1 ? take((int64_t)(delay - 1) * bs * 8) : -1;
     L.Linv = take(bs * 8);
     L.gains = take((int64_t)N * 8);
+    L.fcache = take((int64_t)N * FCACHE_BLOCKS * 256 * 8);
     L.act0 = take((int64_t)N * 4);
     L.act1 = take((int64_t)N * 4);
     L.cmap = take((int64_t)N * 4);
@@ -148,6 +149,7 @@ OED_API oed_status oed_greedy_noalloc(const void *K_dev, int32_t dtype, int64_t 
     d.V = L.V >= 0 ? (double *)(base + L.V) : nullptr;
     d.gains = (double *)(base + L.gains);
     d.Linv = (double *)(base + L.Linv);
+    d.fcache = (double *)(base + L.fcache);
     d.state = state;
     d.picks = idx_dev;       // all sensors are candidates: local index = sensor index
     d.pick_gain = gain_dev;
@@ -159,8 +161,9 @@ OED_API oed_status oed_greedy_noalloc(const void *K_dev, int32_t dtype, int64_t 
 
     // the greedy loop of oed_greedy: the block column of pick k and, every `delay` picks, the
     // downdate of the held columns are enqueued at the start of step k + 1
-    int cur = 0, n_act = N_s, nheld = 0;
+    int cur = 0, n_act = N_s, nheld = 0, newest = -1;
     bool pending = false;
+    const int64_t wel = wtype == W_F64 ? 8 : wtype == W_F32 ? 4 : 2;
     for (int k = 0; k < budget; ++k) {
         d.act_in = act[cur];
         d.act_out = act[cur ^ 1];
@@ -169,24 +172,39 @@ OED_API oed_status oed_greedy_noalloc(const void *K_dev, int32_t dtype, int64_t 
         d.nw = 1;
         d.nheld = nheld;
         d.step = k;
+        newest = -1;
         if (pending) {
             if (nheld > 0) NA_CHK(launch_vcorr(d, wtype, s));
             NA_CHK(launch_trsm(d, rtype, wtype, s));
+            newest = nheld;
             if (nheld + 1 < delay) {
                 ++nheld;
             } else {
                 StepDesc u = d;
                 u.nw = nheld + 1;
                 u.nitems = syrk_tiles(n_act, N_tp, u.stl);
+                u.skipdiag = 1;
                 NA_CHK(launch_syrk(u, rtype, wtype, SYRK_LDS, s));
                 nheld = 0;
             }
             d.nheld = nheld;
         }
-        d.nitems = n_act;
-        NA_CHK(launch_gain(d, rtype, wtype, s));
-        d.nitems = 1;
-        NA_CHK(launch_pick(d, rtype, wtype, s));
+        // as the handle: the gain launch applies the newest block column to the diagonal blocks
+        // and writes them back, and the pick finds the winner's diagonal block current
+        StepDesc g = d;
+        g.nitems = n_act;
+        g.nheld = 0;
+        if (newest >= 0) {
+            g.W = (char *)d.W + newest * d.wslot * wel;
+            if (d.W2) g.W2 = (char *)d.W2 + newest * d.wslot * 2;
+            g.nheld = 1;
+            g.wb = 1;
+        }
+        NA_CHK(launch_gain(g, rtype, wtype, s));
+        StepDesc pk = d;
+        pk.nitems = 1;
+        pk.nheld = 0;
+        NA_CHK(launch_pick(pk, rtype, wtype, s));
         cur ^= 1;
         --n_act;
         pending = true;

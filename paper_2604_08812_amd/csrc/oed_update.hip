@@ -420,7 +420,7 @@ __device__ void syrk_direct_body(const StepDesc &d, int64_t tile)
 #pragma unroll
     for (int b = 0; b < 4; ++b)
 #pragma unroll
-        for (int c = 0; c < 4; ++c) any |= vr[b] && vc[c] && ia[b] >= ja[c];
+        for (int c = 0; c < 4; ++c) any |= vr[b] && vc[c] && ia[b] >= ja[c] && !(d.skipdiag && ia[b] == ja[c]);
     if (!any) return;
 
     vec acc[4][4];
@@ -428,7 +428,7 @@ __device__ void syrk_direct_body(const StepDesc &d, int64_t tile)
     for (int b = 0; b < 4; ++b)
 #pragma unroll
         for (int c = 0; c < 4; ++c) {
-            if (vr[b] && vc[c] && ia[b] >= ja[c])
+            if (vr[b] && vc[c] && ia[b] >= ja[c] && !(d.skipdiag && ia[b] == ja[c]))
                 acc[b][c] = ld4(R + blk_index(ia[b], ja[c]) * bs + ((ta[b] * nb + tc[c]) << 8) + lane * 4);
             else
                 acc[b][c] = vec{0, 0, 0, 0};
@@ -451,7 +451,7 @@ __device__ void syrk_direct_body(const StepDesc &d, int64_t tile)
     for (int b = 0; b < 4; ++b)
 #pragma unroll
         for (int c = 0; c < 4; ++c)
-            if (vr[b] && vc[c] && ia[b] >= ja[c])
+            if (vr[b] && vc[c] && ia[b] >= ja[c] && !(d.skipdiag && ia[b] == ja[c]))
                 st4(R + blk_index(ia[b], ja[c]) * bs + ((ta[b] * nb + tc[c]) << 8) + lane * 4, acc[b][c]);
 }
 
@@ -494,7 +494,7 @@ __device__ __forceinline__ void tile_map_n(const StepDesc &d, const int N_tp, in
         for (int c = 0; c < 4; ++c) {
             const int cc = (int)Q * 128 + (wave & 1) * 64 + 16 * c;
             const int ja = uniform_at(act, min(cc / N_tp, last)), tc = (cc % N_tp) >> 4;
-            const bool o = r < rows && cc < rows && ia >= ja;
+            const bool o = r < rows && cc < rows && ia >= ja && !(d.skipdiag && ia == ja);
             m.ok[4 * b + c] = o;
             m.any |= o;
             m.rblk[4 * b + c] = o ? blk_index(ia, ja) * bs + ((ta * NB + tc) << 8) : 0;

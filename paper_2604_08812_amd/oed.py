@@ -97,7 +97,7 @@ def library() -> ctypes.CDLL:
     L.oed_batch_reset.argtypes = [vp, ctypes.POINTER(oed_instance), ctypes.c_int32]
     L.oed_batch_stats.argtypes = [vp, dp, dp, dp]
     L.oed_batch_destroy.argtypes = [vp]
-    L.oed_batch_get_config.argtypes = [vp, ip, ip, dp]
+    L.oed_batch_get_config.argtypes = [vp, ip, ip, ip, dp]
     L.oed_batch_last_error.argtypes = [vp]
     L.oed_batch_last_error.restype = ctypes.c_char_p
     L.oed_eval_create.argtypes = [ctypes.POINTER(vp), vp, ctypes.c_int32, ctypes.c_int64, ctypes.c_int32,
@@ -369,12 +369,12 @@ def _bcheck(b, st):
 
 
 def oed_batch_create(items, precision="fp64", profile=False, graph=True, stream=None, delay=0, autotune=False,
-                     method="right", tile_order="auto"):
+                     method="right", tile_order="auto", branches=0):
     arr = _instances(items)
     b = ctypes.c_void_p()
     flags = ((OED_FLAG_PROFILE if profile else 0) | (0 if graph else OED_BATCH_NO_GRAPH) | (int(delay) << 8) |
              (OED_BATCH_AUTOTUNE if autotune else 0) | (OED_BATCH_LEFT_LOOKING if method == "left" else 0) |
-             (TILE_ORDERS[tile_order] << 12))
+             (TILE_ORDERS[tile_order] << 12) | (int(branches) << 16))
     st = library().oed_batch_create(ctypes.byref(b), arr, len(items), PRECISIONS[precision], _stream_handle(stream),
                                     flags)
     _bcheck(None, st)
@@ -408,12 +408,12 @@ def oed_batch_stats(b):
 
 
 def oed_batch_get_config(b):
-    """(delay, autotuner run ms for delay 1..OED_MAX_DELAY, tile order name)."""
-    dl, to = ctypes.c_int32(), ctypes.c_int32()
+    """(delay, autotuner run ms for delay 1..OED_MAX_DELAY, tile order name, launch sequences)."""
+    dl, to, nb = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
     ms = np.zeros(OED_MAX_DELAY)
-    _bcheck(b, library().oed_batch_get_config(b, ctypes.byref(dl), ctypes.byref(to), _dp(ms)))
+    _bcheck(b, library().oed_batch_get_config(b, ctypes.byref(dl), ctypes.byref(to), ctypes.byref(nb), _dp(ms)))
     names = {v: k for k, v in TILE_ORDERS.items()}
-    return dl.value, ms, names.get(to.value, str(to.value))
+    return dl.value, ms, names.get(to.value, str(to.value)), nb.value
 
 
 def oed_batch_destroy(b):
@@ -425,9 +425,10 @@ class BatchSelector:
     """Owns one batch.  ``BatchSelector([(K, N_s, N_t, sigma2, B), ...]).run()`` -> [(idx, gain, status)]."""
 
     def __init__(self, items, precision="fp64", profile=False, graph=True, stream=None, delay=0, autotune=False,
-                 method="right", tile_order="auto"):
+                 method="right", tile_order="auto", branches=0):
         self.budgets = [int(it[4]) for it in items]
-        self.b = oed_batch_create(items, precision, profile, graph, stream, delay, autotune, method, tile_order)
+        self.b = oed_batch_create(items, precision, profile, graph, stream, delay, autotune, method, tile_order,
+                                  branches)
 
     def run(self, check=True):
         return oed_batch_run(self.b, self.budgets, check)[0]

@@ -89,7 +89,7 @@ def test_batch_autotune(insts):
     from paper_2604_08812_amd import BatchSelector
     its = items(insts)
     with BatchSelector(its, precision="mixed_f32", autotune=True) as t:
-        delay, ms, _ = t.config()
+        delay, ms, _, _ = t.config()
         res = t.run()
     assert np.all(ms > 0) and delay == int(np.argmin(ms)) + 1
     with BatchSelector(its, precision="mixed_f32", delay=delay) as f:
@@ -147,3 +147,25 @@ def test_batch_reset_is_ordered_after_the_caller_stream(insts):
     for (i0, g0, s0), (i1, g1, s1) in zip(ref, res):
         assert s0 == s1 == 0 and list(i0) == list(i1)
         np.testing.assert_array_equal(g0, g1)
+
+
+@pytest.mark.parametrize("graph", [True, False])
+@pytest.mark.parametrize("method", ["right", "left"])
+def test_branches_give_the_same_selection(insts, method, graph):
+    """Splitting the batch into concurrent launch sequences (forked streams, parallel graph branches)
+    changes nothing: every branch count gives bitwise the picks and gains of one sequence, on
+    repeated runs."""
+    from paper_2604_08812_amd import BatchSelector
+    its = items(insts, torch.float32)
+    with BatchSelector(its, precision="mixed_f32", method=method, branches=1) as one:
+        ref = one.run()
+    for nb in (2, 3, 4):
+        with BatchSelector(its, precision="mixed_f32", method=method, branches=nb, graph=graph) as bs:
+            assert bs.config()[3] == nb
+            for rep in range(2):
+                res = bs.run()
+                for (i0, g0, s0), (i1, g1, s1) in zip(ref, res):
+                    assert s0 == s1 == 0 and list(i0) == list(i1)
+                    np.testing.assert_array_equal(g0, g1)
+                torch.cuda.synchronize()
+                bs.reset(its)
