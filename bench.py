@@ -378,7 +378,7 @@ def run_paper_shape(args):
         "vs_baseline": None, "dtype": "f32", "data": "synthetic",
         "config": {"workload": spec.name, "N_s": spec.N_s, "N_t": spec.N_t, "n_m": spec.n_m, "seed": spec.seed,
                    "budget": budget, "precision": "mixed_f32", "K_dtype": "f32 (row panels, never whole)",
-                   "delay": delay, "downdate_variant": ["direct", "lds"][variant],
+                   "delay": delay, "downdate_variant": ["direct", "lds", "lds256"][variant],
                    "step": "oed_greedy(budget) on the packed working copy"},
         "roofline": {**roofline_syrk(prof, "mixed_f32", spec.name, delay),
                      "kernel": "syrk_direct_kernel<float>" if variant == 0 else "syrk_lds_rt_kernel<float>"},
@@ -582,7 +582,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": spec.name, "N_s": spec.N_s, "N_t": spec.N_t, "n_m": spec.n_m, "seed": spec.seed,
                    "budget": budget, "precision": prec, "K_dtype": spec.k_dtype, "delay": delay,
-                   "downdate_variant": ["direct", "lds"][variant], "tile_order": tiles, "autotuned": tune,
+                   "downdate_variant": ["direct", "lds", "lds256"][variant], "tile_order": tiles, "autotuned": tune,
                    "autotuner_ms_per_pick_by_delay": [round(float(x), 4) for x in tuned] if tune else None,
                    "step": "oed_reset + oed_greedy(budget)"},
         "roofline": roofline_syrk(prof, prec, spec.name, delay),

@@ -134,7 +134,11 @@ typedef struct oed_options {
     int32_t debug_fail_step;    /* test hook for the error paths: k >= 1 makes the k-th pick after
                                    creation (or the last reset) fail once with OED_E_HIP on the
                                    host, before anything of that step is enqueued; 0 = off */
-    int32_t reserved[2];        /* must be 0 */
+    int32_t tile_size;          /* downdate work-group tile: 128 (128 x 128, four waves), 256 (256 x 256,
+                                   eight waves; MIXED_BF16X3 only, else OED_E_UNSUPPORTED) or 0 =
+                                   automatic (the autotuner's choice with OED_FLAG_AUTOTUNE, else
+                                   128) */
+    int32_t reserved[1];        /* must be 0 */
 } oed_options;
 
 /*
@@ -440,7 +444,8 @@ OED_API oed_status oed_device_bytes(const oed_ctx *h, int64_t *bytes);
 
 /*
  * The configuration the handle runs with: *delay (1..OED_MAX_DELAY), *syrk_variant (0: per-wave
- * global operands, 1: LDS-staged, -1: left-looking, no downdate), *tile_order (OED_TILES_*: the
+ * global operands, 1: LDS-staged 128 x 128 tiles, 2: LDS-staged 256 x 256 tiles, -1: left-looking,
+ * no downdate), *tile_order (OED_TILES_*: the
  * downdate's tile order, chosen by the autotuner unless given), and, if per_pick_ms is not NULL,
  * the autotuner's estimate of the time per pick for delay depths 1..OED_MAX_DELAY (OED_MAX_DELAY
  * doubles, host; 0 where not measured, all 0 without OED_FLAG_AUTOTUNE).  Any output pointer may

@@ -40,6 +40,7 @@ struct oed_ctx {
     int prec = OED_PREC_FP64;
     int rtype = R_F64, wtype = W_F64;
     int syrk_variant = SYRK_LDS;
+    int fixed_variant = -1;  // oed_options.tile_size: the downdate kernel the tuner must keep (-1: free)
     int stl = STL_COL4;  // downdate super-tile order (see super_tile())
     int delay = 1;  // > 1: up to delay - 1 block columns held and subtracted with the next one
     double tuned_ms[MAX_DELAY] = {0};  // autotuner: estimated time per pick for delay 1..MAX_DELAY
@@ -242,7 +243,7 @@ StepDesc desc(const oed_ctx *h)
 
 oed_status enqueue_syrk(oed_ctx *h, StepDesc d)
 {
-    d.nitems = syrk_tiles(h->n_act, h->N_tp, h->stl);
+    d.nitems = syrk_items(h->syrk_variant, h->n_act, h->N_tp, h->stl);
     d.skipdiag = h->eager ? 1 : 0;
     {
         Prof pr(h, OED_K_SYRK);
@@ -401,7 +402,9 @@ bool tune_cache_read(const oed_ctx *h, const std::string &key, TuneVal &v)
         int used = 0;
         if (std::sscanf(p, " %d %d %d%n", &t.delay, &t.variant, &t.stl, &used) != 3) continue;
         p += used;
-        bool ok = t.delay >= 1 && t.delay <= MAX_DELAY && (t.variant == SYRK_DIRECT || t.variant == SYRK_LDS);
+        bool ok = t.delay >= 1 && t.delay <= MAX_DELAY &&
+                  (t.variant == SYRK_DIRECT || t.variant == SYRK_LDS ||
+                   (t.variant == SYRK_BIG && h->wtype == W_BF16X3));
         for (int q = 0; q < MAX_DELAY && ok; ++q) {
             if (std::sscanf(p, " %lf%n", &t.ms[q], &used) != 1) ok = false;
             p += used;
@@ -496,7 +499,15 @@ oed_status autotune(oed_ctx *h)
     if (e == hipSuccess) e = hipMemsetAsync(h->Linv, 0, sizeof(double) * bs, h->stream);
     // the per-pick estimates at the first step's size n and at n / 2, averaged: the run's later
     // steps work on fewer candidates, where each launch's fixed cost weighs more
-    double t_step[2][MAX_DELAY] = {{0}}, t_syrk[2][MAX_DELAY][N_TUNE_ORDERS] = {}, t_direct[2] = {1e300, 1e300};
+    // downdate kernels tried: the 128 x 128 LDS tile, and for the BF16 split product the 256 x 256 one
+    // (unless oed_options.tile_size fixed one of them)
+    int variants[2] = {SYRK_LDS, SYRK_BIG};
+    int nvar = h->wtype == W_BF16X3 ? 2 : 1;
+    if (h->fixed_variant >= 0) {
+        variants[0] = h->fixed_variant;
+        nvar = 1;
+    }
+    double t_step[2][MAX_DELAY] = {{0}}, t_syrk[2][MAX_DELAY][N_TUNE_ORDERS][2] = {}, t_direct[2] = {1e300, 1e300};
     const int n_at[2] = {h->n_act, std::max(1, h->n_act / 2)};
     for (int z = 0; z < 2 && e == hipSuccess; ++z) {
         for (int hh = 0; hh < MAX_DELAY && e == hipSuccess; ++hh) {
@@ -522,43 +533,50 @@ oed_status autotune(oed_ctx *h)
         }
         if (e == hipSuccess) e = zero_w();
         for (int p = 1; p <= MAX_DELAY && e == hipSuccess; ++p) {
-            for (int o = 0; o < N_TUNE_ORDERS && e == hipSuccess; ++o) {
-                StepDesc d = desc(h);
-                d.n_act = n_at[z];
-                d.nheld = 0;
-                d.nw = p;
-                d.stl = TUNE_ORDERS[o];
-                d.skipdiag = h->eager ? 1 : 0;
-                d.nitems = syrk_tiles(n_at[z], h->N_tp, d.stl);
-                e = time_ms(h, a, b, [&] { return launch_syrk(d, h->rtype, h->wtype, SYRK_LDS, h->stream); },
-                            &t_syrk[z][p - 1][o]);
-                if (e == hipSuccess && p == 1 && o == 0 && h->wtype != W_BF16X3)
-                    e = time_ms(h, a, b, [&] { return launch_syrk(d, h->rtype, h->wtype, SYRK_DIRECT, h->stream); },
-                                &t_direct[z]);
-            }
+            for (int o = 0; o < N_TUNE_ORDERS && e == hipSuccess; ++o)
+                for (int v = 0; v < nvar && e == hipSuccess; ++v) {
+                    StepDesc d = desc(h);
+                    d.n_act = n_at[z];
+                    d.nheld = 0;
+                    d.nw = p;
+                    d.stl = TUNE_ORDERS[o];
+                    d.skipdiag = h->eager ? 1 : 0;
+                    d.nitems = syrk_items(variants[v], n_at[z], h->N_tp, d.stl);
+                    e = time_ms(h, a, b, [&] { return launch_syrk(d, h->rtype, h->wtype, variants[v], h->stream); },
+                                &t_syrk[z][p - 1][o][v]);
+                    if (e == hipSuccess && p == 1 && o == 0 && v == 0 && h->wtype != W_BF16X3 && h->fixed_variant < 0) {
+                        d.nitems = syrk_tiles(n_at[z], h->N_tp, d.stl);
+                        e = time_ms(h, a, b, [&] { return launch_syrk(d, h->rtype, h->wtype, SYRK_DIRECT, h->stream); },
+                                    &t_direct[z]);
+                    }
+                }
         }
     }
     if (e != hipSuccess) return done(fail(h, e == hipErrorOutOfMemory ? OED_E_OOM : OED_E_HIP,
                                           std::string("autotune: ") + hipGetErrorString(e)));
-    TuneVal v{1, SYRK_LDS, TUNE_ORDERS[0], {0}};
-    int best_o[MAX_DELAY] = {0};
+    TuneVal v{1, variants[0], TUNE_ORDERS[0], {0}};
+    int best_o[MAX_DELAY] = {0}, best_v[MAX_DELAY] = {0};
+    bool direct_at1 = false;
     double best = 1e300;
     for (int p = 1; p <= MAX_DELAY; ++p) {
-        // the tile order with the least downdate time over both sizes
+        // the tile order and kernel with the least downdate time over both sizes
         double tbest = 1e300;
-        for (int o = 0; o < N_TUNE_ORDERS; ++o) {
-            const double t = t_syrk[0][p - 1][o] + t_syrk[1][p - 1][o];
-            if (t < tbest) {
-                tbest = t;
-                best_o[p - 1] = o;
+        for (int o = 0; o < N_TUNE_ORDERS; ++o)
+            for (int vv = 0; vv < nvar; ++vv) {
+                const double t = t_syrk[0][p - 1][o][vv] + t_syrk[1][p - 1][o][vv];
+                if (t < tbest) {
+                    tbest = t;
+                    best_o[p - 1] = o;
+                    best_v[p - 1] = vv;
+                }
             }
-        }
         const bool direct = p == 1 && t_direct[0] + t_direct[1] < tbest;
+        if (p == 1) direct_at1 = direct;
         double sum = 0;
         for (int z = 0; z < 2; ++z) {
             double steps = 0;
             for (int hh = 0; hh < p; ++hh) steps += t_step[z][hh];
-            const double syrk = direct ? t_direct[z] : t_syrk[z][p - 1][best_o[p - 1]];
+            const double syrk = direct ? t_direct[z] : t_syrk[z][p - 1][best_o[p - 1]][best_v[p - 1]];
             sum += (syrk + steps) / p;
         }
         v.ms[p - 1] = 0.5 * sum;
@@ -570,9 +588,11 @@ oed_status autotune(oed_ctx *h)
         if (v.ms[p - 1] <= best) {
             v.delay = p;
             v.stl = TUNE_ORDERS[best_o[p - 1]];
-            v.variant = (p == 1 && t_direct[0] + t_direct[1] < t_syrk[0][0][best_o[0]] + t_syrk[1][0][best_o[0]])
-                            ? SYRK_DIRECT : SYRK_LDS;
-            if (v.variant == SYRK_DIRECT) v.stl = TUNE_ORDERS[0];
+            v.variant = variants[best_v[p - 1]];
+            if (p == 1 && direct_at1) {
+                v.variant = SYRK_DIRECT;
+                v.stl = TUNE_ORDERS[0];
+            }
             break;
         }
     tune_apply(h, v);
@@ -763,6 +783,9 @@ oed_status oed_create(oed_ctx **out, const void *K, int32_t dtype, int64_t ld, i
     if (o.delay > 1 && N_t > REGS_MAX_NT) return cfail(OED_E_UNSUPPORTED, "delay > 1 needs N_t <= 128");
     if (o.tile_order < OED_TILES_AUTO || o.tile_order > OED_TILES_COL2) return cfail(OED_E_ARG, "unknown tile order");
     if (o.max_device_bytes < 0 || o.debug_fail_step < 0) return cfail(OED_E_ARG, "negative limit or hook step");
+    if (o.tile_size != 0 && o.tile_size != 128 && o.tile_size != 256) return cfail(OED_E_ARG, "tile_size: 0, 128 or 256");
+    if (o.tile_size == 256 && o.precision != OED_PREC_MIXED_BF16X3)
+        return cfail(OED_E_UNSUPPORTED, "256 x 256 downdate tiles serve the BF16 split product only");
     for (int r : o.reserved)
         if (r != 0) return cfail(OED_E_ARG, "reserved option fields must be 0");
 
@@ -784,6 +807,12 @@ oed_status oed_create(oed_ctx **out, const void *K, int32_t dtype, int64_t ld, i
     if (o.tune_cache) h->tune_cache = o.tune_cache;
     static const int stl_of[] = {STL_COL4, STL_ROW8, STL_COL8, STL_COL4, STL_COL2};
     h->stl = stl_of[o.tile_order];
+    // downdate kernel: 128 x 128 tiles, or (BF16 split product) 256 x 256, which the autotuner weighs
+    // against it; without the tuner 128 x 128 (faster at 600 x 128: 11.6 against 15.3 ms per launch at
+    // delay 7)
+    if (o.tile_size == 128) h->fixed_variant = SYRK_LDS;
+    if (o.tile_size == 256) h->fixed_variant = SYRK_BIG;
+    h->syrk_variant = o.tile_size == 256 ? SYRK_BIG : SYRK_LDS;
     // delay 0 (automatic): hold block columns whenever the register factorisations and the LDS
     // downdate serve the block size
     h->delay = o.delay == 0 ? (N_t <= REGS_MAX_NT ? DEFAULT_DELAY : 1) : o.delay;
@@ -890,6 +919,7 @@ oed_status oed_create(oed_ctx **out, const void *K, int32_t dtype, int64_t ld, i
             const int keep_stl = h->stl;
             s2 = autotune(h);
             if (!tune_tiles) h->stl = keep_stl;
+            if (h->fixed_variant >= 0) h->syrk_variant = h->fixed_variant;
             return s2;
         }
         return OED_OK;

@@ -118,6 +118,20 @@ __host__ __device__ inline int64_t syrk_tiles(int n_act, int N_tp, int stl)
     const int64_t ST = (syrk_tile_rows(n_act, N_tp) + b - 1) / b;
     return b * b * (ST * (ST + 1) / 2);
 }
+// The same over 256 x 256 tiles (SYRK_BIG).
+__host__ __device__ inline int64_t syrk_tiles_big(int n_act, int N_tp, int stl)
+{
+    const int lb = (stl & 7) ? (stl & 7) : 3;
+    const int64_t b = (int64_t)1 << lb;
+    const int64_t T = ((int64_t)n_act * N_tp + 255) / 256;
+    const int64_t ST = (T + b - 1) / b;
+    return b * b * (ST * (ST + 1) / 2);
+}
+// Work items of a downdate launch of the given variant.
+__host__ __device__ inline int64_t syrk_items(int variant, int n_act, int N_tp, int stl)
+{
+    return variant == 2 ? syrk_tiles_big(n_act, N_tp, stl) : syrk_tiles(n_act, N_tp, stl);
+}
 // Super-tile codes (StepDesc::stl): edge 2^(code & 7) tiles, code & 8 = row-major inside.
 constexpr int STL_ROW8 = 8 | 3;  // 8 x 8, row-major: the order of the first downdate kernels
 constexpr int STL_COL4 = 2;      // 4 x 4, down the columns
@@ -150,7 +164,9 @@ hipError_t launch_column_batched(const StepDesc *descs, int n, int64_t total, in
 // Downdate kernels: SYRK_DIRECT streams W operands from global memory per wave (any N_tp);
 // SYRK_LDS stages them through LDS with a software pipeline (N_tp <= 128).  W_BF16X3 always
 // runs the BF16 split-product kernel (N_tp a multiple of 32, <= 128).
-enum SyrkVariant { SYRK_DIRECT = 0, SYRK_LDS = 1, SYRK_NVARIANTS = 2 };
+// SYRK_BIG: 256 x 256 tiles, eight waves (the BF16 split product only; its work items are
+// syrk_tiles_big()).
+enum SyrkVariant { SYRK_DIRECT = 0, SYRK_LDS = 1, SYRK_BIG = 2, SYRK_NVARIANTS = 3 };
 hipError_t launch_syrk(const StepDesc &d, int rtype, int wtype, int variant, hipStream_t s);
 
 // Block (li, lj), li >= lj, of the current Schur complement into out (device, N_t x N_t FP64

@@ -818,6 +818,137 @@ __device__ void syrk_bf16_body(const StepDesc &d, int64_t tile)
 }
 
 // ---------------------------------------------------------------------------------------------
+// The BF16 split-product downdate over 256 x 256 tiles (SYRK_BIG): eight waves, wave w computes
+// rows 64 (w / 2) .. + 63 of the tile against columns 128 (w % 2) .. + 127, 4 x 8 blocks of 16 x 16.
+// Per 32-wide inner slice the work-group stages the 256-row A and B panels, hi and lo parts, in LDS
+// (double buffered, 128 KB of dynamic LDS: one work-group per CU, two waves per SIMD).  Against the
+// 128 x 128 tile of syrk_bf16_body every staged operand feeds twice the MFMAs, which halves the W
+// traffic from L2 and the LDS reads per flop (that kernel reads about as many LDS bytes as its
+// MFMAs can consume).  Tiles run in the super-tile order of d.stl over 256-row tiles.
+constexpr int BIG_TILE = 256;
+constexpr size_t BIG_LDS_BYTES = 2 * 4 * 16 * 64 * sizeof(u32x4);
+
+template <int NB32>
+__device__ void syrk_bf16_big_body(const StepDesc &d, int64_t tile, u32x4 *lds)
+{
+    constexpr int N_tp = 32 * NB32, NB = N_tp / 16;
+    constexpr int64_t bs = (int64_t)N_tp * N_tp;
+    if (d.state[ST_STATUS] != 0) return;
+    const int rows = d.n_act * N_tp, last = d.n_act - 1;
+    int64_t P, Q;
+    if (!super_tile(tile, (rows + BIG_TILE - 1) / BIG_TILE, d.stl, P, Q)) return;
+    const int *__restrict__ act = d.act_in;
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6), wr = wave >> 1, wc = wave & 1;
+    // the wave stages sub-block rows `wave` and `wave + 8` of both panels (slice 0 offsets)
+    int64_t wA[2], wB[2];
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+        const int sb = wave + 8 * h;
+        const int r = (int)P * BIG_TILE + 16 * sb, c = (int)Q * BIG_TILE + 16 * sb;
+        const int ia = uniform_at(act, min(r / N_tp, last)), ja = uniform_at(act, min(c / N_tp, last));
+        wA[h] = ia * bs + (int64_t)((r % N_tp) >> 4) * (NB * 256);
+        wB[h] = ja * bs + (int64_t)((c % N_tp) >> 4) * (NB * 256);
+    }
+    typedef const unsigned short *bp;
+    const bp Wh0 = (bp)d.W + lane * 8, Wl0 = (bp)d.W2 + lane * 8;
+    const int64_t wslot = d.wslot;
+    auto L = [&](int buf, int part, int sb) -> u32x4 * { return lds + ((((buf << 2) + part) << 4) + sb) * 64; };
+
+    floatx4 acc[4][8];
+#pragma unroll
+    for (int b = 0; b < 4; ++b)
+#pragma unroll
+        for (int c = 0; c < 8; ++c) acc[b][c] = floatx4{0, 0, 0, 0};
+    u32x4 st[2][4];  // [h][A hi, A lo, B hi, B lo]
+    auto stage = [&](bp hi, bp lo) {
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            st[h][0] = *reinterpret_cast<const u32x4 *>(hi + wA[h]);
+            st[h][1] = *reinterpret_cast<const u32x4 *>(lo + wA[h]);
+            st[h][2] = *reinterpret_cast<const u32x4 *>(hi + wB[h]);
+            st[h][3] = *reinterpret_cast<const u32x4 *>(lo + wB[h]);
+        }
+    };
+    auto put = [&](int buf) {
+#pragma unroll
+        for (int h = 0; h < 2; ++h)
+#pragma unroll
+            for (int k = 0; k < 4; ++k) L(buf, k, wave + 8 * h)[lane] = st[h][k];
+    };
+    stage(Wh0, Wl0);
+    put(0);
+    __syncthreads();
+
+    const int nw = d.nw;
+    int buf = 0;
+    for (int slot = 0; slot < nw; ++slot) {
+        const bp chi = Wh0 + slot * wslot, clo = Wl0 + slot * wslot;
+#pragma unroll
+        for (int q = 0; q < NB32; ++q) {
+            const bool more = q + 1 < NB32 || slot + 1 < nw;
+            if (more) {
+                if (q + 1 < NB32)
+                    stage(chi + ((q + 1) << 9), clo + ((q + 1) << 9));
+                else
+                    stage(chi + wslot, clo + wslot);
+            }
+            // the slice's MFMAs without a branch, the next slice's loads kept ahead of them
+            __builtin_amdgcn_sched_barrier(0);
+            {
+                u32x4 ah[4], al[4];
+#pragma unroll
+                for (int b = 0; b < 4; ++b) {
+                    ah[b] = L(buf, 0, wr * 4 + b)[lane];
+                    al[b] = L(buf, 1, wr * 4 + b)[lane];
+                }
+#pragma unroll
+                for (int c = 0; c < 8; ++c) {
+                    const u32x4 bh = L(buf, 2, wc * 8 + c)[lane];
+                    const u32x4 bl = L(buf, 3, wc * 8 + c)[lane];
+                    // the three products of a block pair four MFMAs apart
+#pragma unroll
+                    for (int b = 0; b < 4; ++b) acc[b][c] = mfma_bf16(ah[b], bh, acc[b][c]);
+#pragma unroll
+                    for (int b = 0; b < 4; ++b) acc[b][c] = mfma_bf16(ah[b], bl, acc[b][c]);
+#pragma unroll
+                    for (int b = 0; b < 4; ++b) acc[b][c] = mfma_bf16(al[b], bh, acc[b][c]);
+                }
+            }
+            if (more) put(buf ^ 1);
+            __syncthreads();
+            buf ^= 1;
+        }
+    }
+
+    // epilogue: R -= acc on the wave's blocks in the lower triangle, eight loads in flight at a time
+    float *__restrict__ Rl = (float *)d.R + lane * 4;
+#pragma unroll
+    for (int b = 0; b < 4; ++b) {
+        const int r = (int)P * BIG_TILE + wr * 64 + 16 * b;
+        const int ia = uniform_at(act, min(r / N_tp, last)), ta = (r % N_tp) >> 4;
+        int64_t off[8];
+        bool ok[8];
+        bool any = false;
+#pragma unroll
+        for (int c = 0; c < 8; ++c) {
+            const int cc = (int)Q * BIG_TILE + wc * 128 + 16 * c;
+            const int ja = uniform_at(act, min(cc / N_tp, last)), tc = (cc % N_tp) >> 4;
+            ok[c] = r < rows && cc < rows && ia >= ja && !(d.skipdiag && ia == ja);
+            off[c] = ok[c] ? blk_index(ia, ja) * bs + ((ta * NB + tc) << 8) : 0;
+            any |= ok[c];
+        }
+        if (!any) continue;
+        floatx4 rt[8];
+#pragma unroll
+        for (int c = 0; c < 8; ++c) rt[c] = ld4_stream(Rl + off[c]);
+#pragma unroll
+        for (int c = 0; c < 8; ++c)
+            if (ok[c]) st4_stream(Rl + off[c], rt[c] - acc[b][c]);
+    }
+}
+
+// ---------------------------------------------------------------------------------------------
 // Left-looking block column (the order of Algorithm 1): for the new pick s and every remaining
 // candidate i, the partial sums sum_{h in split} W_h,i W_h,s^T over the stored W slots, on MFMA
 // with the operands staged in LDS as in the downdate; one work-group per (split, 128-row tile).
@@ -1242,6 +1373,28 @@ __global__ void __launch_bounds__(256, 2) syrk_bf16_batched(const StepDesc *__re
     syrk_bf16_body<NB32>(d, item - d.item0);
 }
 
+template <int NB32>
+__global__ void __launch_bounds__(512, 1) syrk_bf16_big_kernel(StepDesc d, int64_t per_xcd)
+{
+    extern __shared__ u32x4 big_lds[];
+    const int64_t tile = xcd_item(blockIdx.x, per_xcd);
+    if (tile >= d.nitems) return;
+    syrk_bf16_big_body<NB32>(d, tile, big_lds);
+}
+
+template <int NB32>
+__global__ void __launch_bounds__(512, 1) syrk_bf16_big_batched(const StepDesc *__restrict__ ds, int n, int64_t total,
+                                                                int64_t per_xcd)
+{
+    extern __shared__ u32x4 big_lds[];
+    const int64_t item = xcd_item(blockIdx.x, per_xcd);
+    if (item >= total) return;
+    const int i = find_instance(ds, n, item);
+    if (i < 0) return;
+    const StepDesc d = ds[i];
+    syrk_bf16_big_body<NB32>(d, item - d.item0, big_lds);
+}
+
 template <typename T, int NB>
 __global__ void __launch_bounds__(256, 2) column_kernel(StepDesc d, int64_t per_xcd)
 {
@@ -1485,11 +1638,38 @@ static hipError_t launch_syrk_t(const StepDesc *descs, const StepDesc &d, int n,
 }
 
 // BF16 split-product downdate (single or batched).
+template <typename K>
+static void allow_big_lds(K kernel)
+{
+    (void)hipFuncSetAttribute((const void *)kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)BIG_LDS_BYTES);
+}
+
 static hipError_t launch_syrk_bf16(const StepDesc *descs, const StepDesc &d, int n, int64_t total, int N_tp, int nw,
-                                   hipStream_t s)
+                                   int variant, hipStream_t s)
 {
     if (N_tp < 32 || N_tp % 32 != 0 || N_tp > 128 || nw < 1 || nw > MAX_DELAY) return hipErrorInvalidValue;
     const int64_t per_xcd = (total + 7) / 8;
+    if (variant == SYRK_BIG) {
+        const dim3 grid((unsigned)(per_xcd * 8)), block(512);
+        switch (N_tp / 32) {
+#define OED_BF16_BIG_CASE(V)                                                                                       \
+    case V:                                                                                                        \
+        if (descs) {                                                                                               \
+            allow_big_lds(syrk_bf16_big_batched<V>);                                                               \
+            hipLaunchKernelGGL((syrk_bf16_big_batched<V>), grid, block, BIG_LDS_BYTES, s, descs, n, total, per_xcd); \
+        } else {                                                                                                   \
+            allow_big_lds(syrk_bf16_big_kernel<V>);                                                                \
+            hipLaunchKernelGGL((syrk_bf16_big_kernel<V>), grid, block, BIG_LDS_BYTES, s, d, per_xcd);              \
+        }                                                                                                          \
+        break;
+            OED_BF16_BIG_CASE(1)
+            OED_BF16_BIG_CASE(2)
+            OED_BF16_BIG_CASE(3)
+            OED_BF16_BIG_CASE(4)
+#undef OED_BF16_BIG_CASE
+        }
+        return hipGetLastError();
+    }
     const dim3 grid((unsigned)(per_xcd * 8)), block(256);
     switch (N_tp / 32) {
 #define OED_BF16_CASE(V)                                                                                     \
@@ -1608,7 +1788,7 @@ hipError_t launch_syrk(const StepDesc &d, int rtype, int wtype, int variant, hip
 {
     if (d.n_act <= 0 || d.nitems <= 0) return hipSuccess;
     if (d.nw > 1 && d.wslot <= 0) return hipErrorInvalidValue;
-    if (rtype == R_F32 && wtype == W_BF16X3) return launch_syrk_bf16(nullptr, d, 1, d.nitems, d.N_tp, d.nw, s);
+    if (rtype == R_F32 && wtype == W_BF16X3) return launch_syrk_bf16(nullptr, d, 1, d.nitems, d.N_tp, d.nw, variant, s);
     if (rtype == R_F64 && wtype == W_F64) return launch_syrk_t<double>(nullptr, d, 1, d.nitems, d.N_tp, d.nw, variant, s);
     if (rtype == R_F32 && wtype == W_F32) return launch_syrk_t<float>(nullptr, d, 1, d.nitems, d.N_tp, d.nw, variant, s);
     return hipErrorInvalidValue;
@@ -1619,7 +1799,7 @@ hipError_t launch_syrk_batched(const StepDesc *descs, int n, int64_t total, int 
 {
     if (n <= 0 || total <= 0) return hipSuccess;
     StepDesc none{};
-    if (rtype == R_F32 && wtype == W_BF16X3) return launch_syrk_bf16(descs, none, n, total, N_tp, nw, s);
+    if (rtype == R_F32 && wtype == W_BF16X3) return launch_syrk_bf16(descs, none, n, total, N_tp, nw, variant, s);
     if (rtype == R_F64 && wtype == W_F64) return launch_syrk_t<double>(descs, none, n, total, N_tp, nw, variant, s);
     if (rtype == R_F32 && wtype == W_F32) return launch_syrk_t<float>(descs, none, n, total, N_tp, nw, variant, s);
     return hipErrorInvalidValue;

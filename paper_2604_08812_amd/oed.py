@@ -32,7 +32,7 @@ class oed_options(ctypes.Structure):
                 ("delay", ctypes.c_int32), ("method", ctypes.c_int32), ("max_budget", ctypes.c_int32),
                 ("noise_half_logdet", ctypes.POINTER(ctypes.c_double)), ("tune_cache", ctypes.c_char_p),
                 ("max_device_bytes", ctypes.c_int64), ("tile_order", ctypes.c_int32),
-                ("debug_fail_step", ctypes.c_int32), ("reserved", ctypes.c_int32 * 2)]
+                ("debug_fail_step", ctypes.c_int32), ("tile_size", ctypes.c_int32), ("reserved", ctypes.c_int32 * 1)]
 
 
 TILE_ORDERS = {"auto": 0, "row8": 1, "col8": 2, "col4": 3, "col2": 4}
@@ -159,7 +159,7 @@ def _stream_handle(stream):
 # ------------------------------------------------------------------ functions with the C names
 def oed_create(K, N_s, N_t, sigma2, precision="fp64", candidates=None, profile=False, stream=None, delay=0,
                autotune=False, method="right", max_budget=0, noise_half_logdet=None, tile_order="auto",
-               tune_cache=None, max_device_bytes=0, debug_fail_step=0):
+               tune_cache=None, max_device_bytes=0, debug_fail_step=0, tile_size=0):
     """Create a handle for the device tensor K (2-D, float64/float32, row-major, lower triangle read).
     delay: downdate delay depth (0 automatic, 1..OED_MAX_DELAY); autotune: with delay 0, time the choices;
     method: "right" (downdate of all of R per pick), "left" (only the new block column per pick) or
@@ -168,7 +168,7 @@ def oed_create(K, N_s, N_t, sigma2, precision="fp64", candidates=None, profile=F
     1/2 logdet of the noise covariance blocks (None: isotropic sigma2); tile_order: the downdate's
     tile order ("auto", "row8", "col8", "col4", "col2"); tune_cache: autotuner cache file path;
     max_device_bytes: fail with OED_E_OOM instead of holding more (0: no limit); debug_fail_step:
-    make that pick fail once (error-path tests).
+    make that pick fail once (error-path tests); tile_size: downdate tile 128 or 256 (0: automatic).
     K = None: deferred packing (OED_FLAG_DEFER_PACK), the rows come through oed_pack_rows."""
     import torch
     L = library()
@@ -198,6 +198,7 @@ def oed_create(K, N_s, N_t, sigma2, precision="fp64", candidates=None, profile=F
         opt.tune_cache = cache
     opt.max_device_bytes = int(max_device_bytes)
     opt.debug_fail_step = int(debug_fail_step)
+    opt.tile_size = int(tile_size)
     hld = None
     if noise_half_logdet is not None:
         hld = np.ascontiguousarray(np.asarray(noise_half_logdet, dtype=np.float64))
@@ -551,11 +552,11 @@ class Selector:
 
     def __init__(self, K, N_s, N_t, sigma2, precision="fp64", candidates=None, profile=False, stream=None,
                  delay=0, autotune=False, method="right", max_budget=0, noise_half_logdet=None, tile_order="auto",
-                 tune_cache=None, max_device_bytes=0, debug_fail_step=0):
+                 tune_cache=None, max_device_bytes=0, debug_fail_step=0, tile_size=0):
         self.N_s, self.N_t = int(N_s), int(N_t)
         self.h = oed_create(K, N_s, N_t, sigma2, precision, candidates, profile, stream, delay, autotune, method,
                             max_budget, noise_half_logdet, tile_order, tune_cache, max_device_bytes,
-                            debug_fail_step)
+                            debug_fail_step, tile_size)
 
     def greedy(self, budget):
         idx, gain, _ = oed_greedy(self.h, budget)

@@ -183,6 +183,11 @@ def test_options_layout_and_create_errors_without_a_gpu(lib):
     opt.debug_fail_step = -2
     assert lib.oed_create(ctypes.byref(h), fake, 0, 64, 4, 16, 1.0, None, ctypes.byref(opt)) == 1
     opt.debug_fail_step = 0
-    opt.reserved[1] = 1
+    opt.tile_size = 64
+    assert lib.oed_create(ctypes.byref(h), fake, 0, 64, 4, 16, 1.0, None, ctypes.byref(opt)) == 1
+    opt.tile_size = 256      # 256 x 256 downdate tiles: the BF16 split product only
+    assert lib.oed_create(ctypes.byref(h), fake, 0, 64, 4, 16, 1.0, None, ctypes.byref(opt)) == 6
+    opt.tile_size = 0
+    opt.reserved[0] = 1
     assert lib.oed_create(ctypes.byref(h), fake, 0, 64, 4, 16, 1.0, None, ctypes.byref(opt)) == 1
     assert "reserved" in lib.oed_last_error(None).decode()

@@ -452,3 +452,24 @@ def test_injected_failure_stops_cleanly(method):
     with pytest.raises(OedError) as ei:
         selector(Kd, N_s, N_t, s2, precision="mixed_f32", max_device_bytes=need - 1, **kw)
     assert ei.value.status == 3 and str(need) in str(ei.value)
+
+
+@pytest.mark.parametrize("N_t", [32, 48, 96, 128])
+def test_bf16_big_tiles_equal_the_128_tiles(N_t):
+    """The BF16 split-product downdate over 256 x 256 tiles (eight waves) accumulates every element
+    in the order of the 128 x 128 kernel (slot, slice, then hi hi, hi lo, lo hi), so the selections
+    are bitwise equal, at several delays and on ragged instances (the tile rows end mid-tile and, for
+    N_t = 48 and 96, mid-block), and agree with the oracle."""
+    N_s, B = {32: (61, 12), 48: (45, 10), 96: (27, 8), 128: (23, 8)}[N_t]
+    K, Kd, s2 = instance(N_s, N_t, 5000, 40 + N_t)
+    for delay in (1, 3, 8):
+        print(f"bf16 big tiles N_t={N_t} delay={delay}", flush=True)
+        with selector(Kd, N_s, N_t, s2, precision="mixed_bf16x3", delay=delay, tile_size=128) as a:
+            assert a.config()[1] == 1
+            ia, ga = a.greedy(B)
+        with selector(Kd, N_s, N_t, s2, precision="mixed_bf16x3", delay=delay, tile_size=256) as b:
+            assert b.config()[1] == 2
+            ib, gb = b.greedy(B)
+        assert list(ia) == list(ib)
+        np.testing.assert_array_equal(ga, gb)
+    check_trajectory(K, N_s, N_t, s2, ib, gb, RTOL["mixed_bf16x3"])
