@@ -343,18 +343,19 @@ oed_status advance(oed_ctx *h, bool full)
 //
 // On the freshly packed working copy it times, per delay depth p = 1..MAX_DELAY, the kernels of
 // one pick: the gains and the block column with h = 0 .. p-1 block columns held, the V
-// correction for h > 0, and the downdate of p block columns in every tile order of TUNE_ORDERS
-// (both downdate variants at p = 1, in the default order); the per-pick cost is
-// min over orders of t_syrk(p)/p + (1/p) sum_h (t_gain(h) + t_vcorr(h) + t_trsm(h)), taken at the
+// correction for h > 0, and the downdate of p block columns with each downdate kernel in the first
+// tile order (the per-wave kernel too at p = 1); the per-pick cost is
+// t_syrk(p)/p + (1/p) sum_h (t_gain(h) + t_vcorr(h) + t_trsm(h)), taken at the
 // first step's candidate count and at half of it (the leading half of the active list) and
-// averaged; the choice is the least estimate (the shallowest depth on ties).  The W slots are
+// averaged; the choice is the least estimate (the shallowest depth on ties), after which the other
+// tile orders of TUNE_ORDERS are timed at that depth and the fastest kept.  The W slots are
 // zero while the downdates are timed, so R - 0 leaves R exactly as packed; the gains, L_s^-1 and
 // W buffers it writes are overwritten by the first step.  Results are cached per (device,
 // precision, N_tp, ceil(N_c / 32)) in the process and, with oed_options.tune_cache, in a text file
 // keyed by the GPU's architecture name and compute-unit count instead of the device index; a
 // matching line of the file takes precedence over the process's cache.
 
-constexpr int TUNE_ORDERS[] = {STL_COL4, STL_COL8, STL_ROW8};
+constexpr int TUNE_ORDERS[] = {STL_COL4, STL_COL8, STL_COL2, STL_ROW8};
 constexpr int N_TUNE_ORDERS = sizeof(TUNE_ORDERS) / sizeof(TUNE_ORDERS[0]);
 
 struct TuneKey {
@@ -509,6 +510,21 @@ oed_status autotune(oed_ctx *h)
     }
     double t_step[2][MAX_DELAY] = {{0}}, t_syrk[2][MAX_DELAY][N_TUNE_ORDERS][2] = {}, t_direct[2] = {1e300, 1e300};
     const int n_at[2] = {h->n_act, std::max(1, h->n_act / 2)};
+    auto syrk_desc = [&](int p, int o, int z) {
+        StepDesc d = desc(h);
+        d.n_act = n_at[z];
+        d.nheld = 0;
+        d.nw = p;
+        d.stl = TUNE_ORDERS[o];
+        d.skipdiag = h->eager ? 1 : 0;
+        return d;
+    };
+    // the downdate of p zero W slots (R - 0 leaves R as packed) in tile order o with kernel v
+    auto time_syrk = [&](int p, int o, int v, int z, double *out) {
+        StepDesc d = syrk_desc(p, o, z);
+        d.nitems = syrk_items(variants[v], n_at[z], h->N_tp, d.stl);
+        return time_ms(h, a, b, [&] { return launch_syrk(d, h->rtype, h->wtype, variants[v], h->stream); }, out);
+    };
     for (int z = 0; z < 2 && e == hipSuccess; ++z) {
         for (int hh = 0; hh < MAX_DELAY && e == hipSuccess; ++hh) {
             StepDesc d = desc(h);
@@ -532,54 +548,46 @@ oed_status autotune(oed_ctx *h)
             t_step[z][hh] = tg + tt;
         }
         if (e == hipSuccess) e = zero_w();
-        for (int p = 1; p <= MAX_DELAY && e == hipSuccess; ++p) {
-            for (int o = 0; o < N_TUNE_ORDERS && e == hipSuccess; ++o)
-                for (int v = 0; v < nvar && e == hipSuccess; ++v) {
-                    StepDesc d = desc(h);
-                    d.n_act = n_at[z];
-                    d.nheld = 0;
-                    d.nw = p;
-                    d.stl = TUNE_ORDERS[o];
-                    d.skipdiag = h->eager ? 1 : 0;
-                    d.nitems = syrk_items(variants[v], n_at[z], h->N_tp, d.stl);
-                    e = time_ms(h, a, b, [&] { return launch_syrk(d, h->rtype, h->wtype, variants[v], h->stream); },
-                                &t_syrk[z][p - 1][o][v]);
-                    if (e == hipSuccess && p == 1 && o == 0 && v == 0 && h->wtype != W_BF16X3 && h->fixed_variant < 0) {
-                        d.nitems = syrk_tiles(n_at[z], h->N_tp, d.stl);
-                        e = time_ms(h, a, b, [&] { return launch_syrk(d, h->rtype, h->wtype, SYRK_DIRECT, h->stream); },
-                                    &t_direct[z]);
-                    }
+        // phase 1: every depth in the first tile order, every downdate kernel
+        for (int p = 1; p <= MAX_DELAY && e == hipSuccess; ++p)
+            for (int v = 0; v < nvar && e == hipSuccess; ++v) {
+                e = time_syrk(p, 0, v, z, &t_syrk[z][p - 1][0][v]);
+                if (e == hipSuccess && p == 1 && v == 0 && h->wtype != W_BF16X3 && h->fixed_variant < 0) {
+                    StepDesc d = syrk_desc(p, 0, z);
+                    d.nitems = syrk_tiles(n_at[z], h->N_tp, d.stl);
+                    e = time_ms(h, a, b, [&] { return launch_syrk(d, h->rtype, h->wtype, SYRK_DIRECT, h->stream); },
+                                &t_direct[z]);
                 }
-        }
+            }
     }
     if (e != hipSuccess) return done(fail(h, e == hipErrorOutOfMemory ? OED_E_OOM : OED_E_HIP,
                                           std::string("autotune: ") + hipGetErrorString(e)));
     TuneVal v{1, variants[0], TUNE_ORDERS[0], {0}};
-    int best_o[MAX_DELAY] = {0}, best_v[MAX_DELAY] = {0};
+    int best_v[MAX_DELAY] = {0};
     bool direct_at1 = false;
     double best = 1e300;
-    for (int p = 1; p <= MAX_DELAY; ++p) {
-        // the tile order and kernel with the least downdate time over both sizes
-        double tbest = 1e300;
-        for (int o = 0; o < N_TUNE_ORDERS; ++o)
-            for (int vv = 0; vv < nvar; ++vv) {
-                const double t = t_syrk[0][p - 1][o][vv] + t_syrk[1][p - 1][o][vv];
-                if (t < tbest) {
-                    tbest = t;
-                    best_o[p - 1] = o;
-                    best_v[p - 1] = vv;
-                }
-            }
-        const bool direct = p == 1 && t_direct[0] + t_direct[1] < tbest;
-        if (p == 1) direct_at1 = direct;
+    auto estimate = [&](int p, double syrk0, double syrk1) {
         double sum = 0;
         for (int z = 0; z < 2; ++z) {
             double steps = 0;
             for (int hh = 0; hh < p; ++hh) steps += t_step[z][hh];
-            const double syrk = direct ? t_direct[z] : t_syrk[z][p - 1][best_o[p - 1]][best_v[p - 1]];
-            sum += (syrk + steps) / p;
+            sum += ((z ? syrk1 : syrk0) + steps) / p;
         }
-        v.ms[p - 1] = 0.5 * sum;
+        return 0.5 * sum;
+    };
+    for (int p = 1; p <= MAX_DELAY; ++p) {
+        double tbest = 1e300;
+        for (int vv = 0; vv < nvar; ++vv) {
+            const double t = t_syrk[0][p - 1][0][vv] + t_syrk[1][p - 1][0][vv];
+            if (t < tbest) {
+                tbest = t;
+                best_v[p - 1] = vv;
+            }
+        }
+        const bool direct = p == 1 && t_direct[0] + t_direct[1] < tbest;
+        if (p == 1) direct_at1 = direct;
+        v.ms[p - 1] = direct ? estimate(p, t_direct[0], t_direct[1])
+                             : estimate(p, t_syrk[0][p - 1][0][best_v[p - 1]], t_syrk[1][p - 1][0][best_v[p - 1]]);
         best = std::min(best, v.ms[p - 1]);
     }
     // the least estimate, the shallowest depth on ties (a margin towards shallower depths chose
@@ -587,14 +595,28 @@ oed_status autotune(oed_ctx *h)
     for (int p = 1; p <= MAX_DELAY; ++p)
         if (v.ms[p - 1] <= best) {
             v.delay = p;
-            v.stl = TUNE_ORDERS[best_o[p - 1]];
             v.variant = variants[best_v[p - 1]];
-            if (p == 1 && direct_at1) {
-                v.variant = SYRK_DIRECT;
-                v.stl = TUNE_ORDERS[0];
-            }
+            if (p == 1 && direct_at1) v.variant = SYRK_DIRECT;
             break;
         }
+    // phase 2: the other tile orders at the chosen depth and kernel
+    if (v.variant != SYRK_DIRECT) {
+        const int p = v.delay, vv = best_v[p - 1];
+        double tbest = t_syrk[0][p - 1][0][vv] + t_syrk[1][p - 1][0][vv];
+        for (int o = 1; o < N_TUNE_ORDERS && e == hipSuccess; ++o) {
+            for (int z = 0; z < 2 && e == hipSuccess; ++z) e = time_syrk(p, o, vv, z, &t_syrk[z][p - 1][o][vv]);
+            const double t = t_syrk[0][p - 1][o][vv] + t_syrk[1][p - 1][o][vv];
+            // another order only when it is clearly faster (the timings of one launch scatter by
+            // about 0.5%; at 600 x 128 the first order was the fastest over whole selections)
+            if (e == hipSuccess && t < 0.99 * tbest) {
+                tbest = t;
+                v.stl = TUNE_ORDERS[o];
+                v.ms[p - 1] = estimate(p, t_syrk[0][p - 1][o][vv], t_syrk[1][p - 1][o][vv]);
+            }
+        }
+        if (e != hipSuccess) return done(fail(h, e == hipErrorOutOfMemory ? OED_E_OOM : OED_E_HIP,
+                                              std::string("autotune: ") + hipGetErrorString(e)));
+    }
     tune_apply(h, v);
     {
         std::lock_guard<std::mutex> lk(g_tune_mu);

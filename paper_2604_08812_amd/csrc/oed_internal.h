@@ -75,7 +75,8 @@ struct StepDesc {
                            // block column of the last pick goes to slot nheld
     void *W2;              // BF16X3: the lo parts (same layout), else unused
     int64_t wslot;         // elements per W slot (N_c N_tp^2)
-    double *V;             // L_s^-1 P_h,s of the last pick s for every held h (operand order, N_tp^2 each)
+    double *V;             // L_s^-1 P_h,s of the last pick s for every held h (operand order, N_tp^2 each;
+                           // FP64, stored as FP32 in the mixed paths, which apply it on the FP32 MFMA)
     int nheld;             // number of held W (gain, pick, vcorr, trsm)
     int wb;                // gain: write the corrected diagonal blocks back to R (left-looking)
     int nsplit;            // left-looking: column partial sums in C (column kernel: splits of the

@@ -102,7 +102,16 @@ __device__ void vcorr_body(const StepDesc &d, int item)
         for (int s4 = 0; s4 < 4; ++s4)
             acc = mfma16(w_elem<TW>(Ps, Ps2, 16 * mq + 4 * g + s4, 16 * kb + al, nb), b[s4], acc);
     }
-    st4(d.V + hp * bs + ((ab * nb + kb) << 8) + lane * 4, acc);
+    if constexpr (sizeof(TW) == 8) {
+        st4(d.V + hp * bs + ((ab * nb + kb) << 8) + lane * 4, acc);
+    } else {
+        // the mixed paths apply V_h on the FP32 MFMA: keep it rounded to FP32 (the block column
+        // kernel reads half the bytes and converts nothing)
+        floatx4 v;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) v[r] = (float)acc[r];
+        st4((float *)d.V + hp * bs + ((ab * nb + kb) << 8) + lane * 4, v);
+    }
 }
 
 template <typename TR, typename TW>
@@ -140,7 +149,7 @@ __device__ void trsm_body(const StepDesc &d, int p)
                 for (int hp = 0; hp < d.nheld; ++hp) {
                     const TW *Pi = (const TW *)d.W + hp * d.wslot + (int64_t)i * bs;
                     const TW *Pi2 = d.W2 ? (const TW *)d.W2 + hp * d.wslot + (int64_t)i * bs : nullptr;
-                    const double *Vh = d.V + hp * bs;
+                    const float *Vh = (const float *)d.V + hp * bs;
                     for (int q = 0; q < nbr; ++q) {
                         double v[4];
                         w_row4<TW>(Pi, Pi2, tb, q, nb, lane, v);
@@ -152,9 +161,9 @@ __device__ void trsm_body(const StepDesc &d, int p)
                             const int kc = kg + c;
                             if (kc < kend) {
                                 // the FP32 MFMA takes its A operand in the natural lane order
-                                const doublex4 a = ld4(Vh + ((kc * nb + q) << 8) + lane * 4);
+                                const floatx4 a = ld4(Vh + ((kc * nb + q) << 8) + lane * 4);
 #pragma unroll
-                                for (int s4 = 0; s4 < 4; ++s4) hacc[c] = mfma16((float)a[s4], b[s4], hacc[c]);
+                                for (int s4 = 0; s4 < 4; ++s4) hacc[c] = mfma16(a[s4], b[s4], hacc[c]);
                             }
                         }
                     }
@@ -273,7 +282,7 @@ __device__ void trsm_nb_body(const StepDesc &d, int p)
         for (int hp = 0; hp < d.nheld; ++hp) {
             const TW *Pi = (const TW *)d.W + hp * d.wslot + (int64_t)i * bs;
             const TW *Pi2 = d.W2 ? (const TW *)d.W2 + hp * d.wslot + (int64_t)i * bs : nullptr;
-            const double *Vh = d.V + hp * bs;
+            const float *Vh = (const float *)d.V + hp * bs;
 #pragma unroll
             for (int q = 0; q < NB; ++q) {
                 if (q >= nbr) break;
@@ -289,12 +298,12 @@ __device__ void trsm_nb_body(const StepDesc &d, int p)
 #pragma unroll
                 for (int c = 0; c < NB; ++c) {
                     // the FP32 MFMA takes its A operand in the natural lane order
-                    const doublex4 a = ld4(Vh + ((c * nb + q) << 8) + lane * 4);
+                    const floatx4 a = ld4(Vh + ((c * nb + q) << 8) + lane * 4);
 #pragma unroll
                     for (int rr = 0; rr < 2; ++rr)
                         if (has[rr]) {
 #pragma unroll
-                            for (int s4 = 0; s4 < 4; ++s4) hacc[rr][c] = mfma16((float)a[s4], b[rr][s4], hacc[rr][c]);
+                            for (int s4 = 0; s4 < 4; ++s4) hacc[rr][c] = mfma16(a[s4], b[rr][s4], hacc[rr][c]);
                         }
                 }
             }

@@ -72,7 +72,7 @@ def test_host_side_argument_validation(lib):
     assert lib.oed_create(ctypes.byref(h), fake, 0, 64, 4, 16, 1.0, None, ctypes.byref(bad)) == E_ARG
     bad = oed_options()
     lib.oed_options_init(ctypes.byref(bad))
-    bad.delay = 9
+    bad.delay = 13
     assert lib.oed_create(ctypes.byref(h), fake, 0, 64, 4, 16, 1.0, None, ctypes.byref(bad)) == E_ARG
     bad = oed_options()
     lib.oed_options_init(ctypes.byref(bad))
@@ -126,7 +126,7 @@ def test_eval_host_side_validation(lib):
     good = [fake, 0, 128, 8, 16, 1.0, 4, 2, 1, None, 0]
     for pos, val, code in ((0, None, E_ARG), (1, 5, E_ARG), (2, 127, E_ARG), (3, 0, E_ARG), (5, 0.0, E_ARG),
                            (5, float("inf"), E_ARG), (6, 0, E_ARG), (6, 9, E_ARG), (7, -1, E_ARG), (8, 7, E_ARG),
-                           (10, 0x10, E_ARG), (10, 0x20, E_ARG), (10, 9 << 8, E_ARG)):
+                           (10, 0x10, E_ARG), (10, 0x20, E_ARG), (10, 13 << 8, E_ARG)):
         args = list(good)
         args[pos] = val
         assert lib.oed_eval_create(ctypes.byref(e), *args) == code, (pos, val)

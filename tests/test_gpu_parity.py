@@ -269,7 +269,7 @@ def test_autotuned_handle_selects_like_a_fixed_one(prec):
     with selector(Kd, N_s, N_t, s2, precision=prec, autotune=True) as t:
         delay, variant, ms, _ = t.config()
         it, gt = t.greedy(12)
-    assert 1 <= delay <= 8 and variant in (0, 1)
+    assert 1 <= delay <= 8 and variant in (0, 1, 2)
     assert np.all(ms > 0) and delay == int(np.argmin(ms)) + 1
     with selector(Kd, N_s, N_t, s2, precision=prec, delay=delay) as f:
         i_f, g_f = f.greedy(12)

@@ -70,7 +70,7 @@ def test_noalloc_rejects_what_it_cannot_hold():
     assert call(4, 16, s2=0.0) == 1
     assert call(4, 16, s2=float("nan")) == 1
     assert call(4, 16, prec=7) == 1
-    assert call(4, 16, delay=9) == 1
+    assert call(4, 16, delay=13) == 1
     assert call(4, 16, budget=5) == 1
     assert call(4, 16, dtype=3) == 1
     assert L.oed_greedy_noalloc(None, 0, 64, 4, 16, 1.0, 0, 4, 1, None, fake, fake, fake, err, len(err)) == 1
