@@ -54,6 +54,10 @@ def parse():
     ap.add_argument("--no-graph", action="store_true", help="batched workload: enqueue every run eagerly")
     ap.add_argument("--no-gaps", action="store_true", help="skip the per-step top-two gap scan (FP64)")
     ap.add_argument("--delay", type=int, default=0, help="downdate delay depth (0: the library's choice)")
+    ap.add_argument("--tile-order", default="auto", choices=["auto", "row8", "col8", "col4", "col2"],
+                    help="downdate tile order (auto: the autotuner's choice, else the library default)")
+    ap.add_argument("--tile-size", type=int, default=0, choices=[0, 128, 256],
+                    help="BF16 split-product downdate tile edge (0: the autotuner's choice)")
     ap.add_argument("--no-autotune", action="store_true",
                     help="with --delay 0, take the library's fixed default instead of its autotuner")
     ap.add_argument("--no-eval", action="store_true", help="skip the design-evaluation leg")
@@ -77,24 +81,35 @@ def timed_selections(sel, K, budget, steps):
     return (time.perf_counter() - t0) * 1e3 / steps, out
 
 
-def roofline_syrk(prof, prec, workload=None, delay=None):
+def syrk_kernel_name(prec, variant=1):
+    """The downdate kernel a handle launches: variant 0 the direct kernel (delay 1), 1 the LDS kernel of
+    128 x 128 tiles, 2 the BF16 split-product kernel of 256 x 256 tiles."""
+    if variant == 0:
+        return "syrk_direct_kernel<double>" if prec == "fp64" else "syrk_direct_kernel<float>"
+    if variant == 2:
+        return "syrk_bf16_big_kernel"
+    return SYRK_KERNEL[prec]
+
+
+def roofline_syrk(prof, prec, workload=None, delay=None, variant=1):
     """The downdate R -= W W^T: algorithmic flops (2 per multiply-add of the lower-triangle
     blocks) over its summed HIP-event time.  The BF16 split product executes three MFMA
     products per algorithmic one; its fraction is taken of the BF16 peak on the executed
     flops, and the HBM view (algorithmic bytes / time) is given beside it."""
+    kname = syrk_kernel_name(prec, variant)
     ms = prof["ms"]["syrk"]
     n = max(1, prof["launches"]["syrk"])
     tflops = prof["syrk_flops"] / (ms * 1e-3) / 1e12 if ms > 0 else 0.0
     gbs = prof["syrk_bytes"] / (ms * 1e-3) / 1e9 if ms > 0 else 0.0
     executed = tflops * (3 if prec == "mixed_bf16x3" else 1)
     out = {
-        "kernel": SYRK_KERNEL[prec],
+        "kernel": kname,
         "bound": "mfma",
         "achieved": round(executed, 3),
         "peak": PEAK_TFLOPS[prec],
         "unit": "TFLOP/s",
         "frac": round(executed / PEAK_TFLOPS[prec], 4),
-        "traffic": counted_traffic(workload, prec, SYRK_KERNEL[prec], delay) if workload else None,
+        "traffic": counted_traffic(workload, prec, kname, delay) if workload else None,
         "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
         "algorithmic_bytes_per_launch": round(prof["syrk_bytes"] / n),
         "avg_launch_ms": round(ms / n, 4),
@@ -465,7 +480,8 @@ def run_batched(args):
     total_steps = sum(sp.budget for sp in specs)
     tune = args.delay == 0 and not args.no_autotune and not args.left
     bs = BatchSelector(items, precision=args.precision or "mixed_f32", profile=True, delay=args.delay, autotune=tune,
-                       method="left" if args.left else "right", branches=args.branches, graph=not args.no_graph)
+                       method="left" if args.left else "right", branches=args.branches, graph=not args.no_graph,
+                       tile_order=args.tile_order)
     delay, tuned, tiles, branches = bs.config()
     for w in range(args.warmup):
         bs.reset(items)
@@ -558,7 +574,10 @@ def main():
 
     # ---- headline path
     tune = args.delay == 0 and not args.no_autotune
-    sel = Selector(K, spec.N_s, spec.N_t, s2, precision=prec, profile=True, delay=args.delay, autotune=tune)
+    tiles_kw = {"tile_order": args.tile_order}
+    bf16_kw = {**tiles_kw, "tile_size": args.tile_size}
+    sel = Selector(K, spec.N_s, spec.N_t, s2, precision=prec, profile=True, delay=args.delay, autotune=tune,
+                   **(bf16_kw if prec == "mixed_bf16x3" else tiles_kw))
     delay, variant, tuned, tiles = sel.config()
     for w in range(args.warmup):
         timed_selections(sel, K, budget, 1)
@@ -585,7 +604,7 @@ def main():
                    "downdate_variant": ["direct", "lds", "lds256"][variant], "tile_order": tiles, "autotuned": tune,
                    "autotuner_ms_per_pick_by_delay": [round(float(x), 4) for x in tuned] if tune else None,
                    "step": "oed_reset + oed_greedy(budget)"},
-        "roofline": roofline_syrk(prof, prec, spec.name, delay),
+        "roofline": roofline_syrk(prof, prec, spec.name, delay, variant),
         "kernel_ms_per_step": {k: round(v / args.steps, 3) for k, v in prof["ms"].items()},
         "paper_context": PAPER_CONTEXT,
     }
@@ -593,18 +612,19 @@ def main():
 
     # ---- FP64 beside it, same K
     if not args.no_fp64 and prec != "fp64":
-        sel64 = Selector(K, spec.N_s, spec.N_t, s2, precision="fp64", profile=True, delay=args.delay, autotune=tune)
+        sel64 = Selector(K, spec.N_s, spec.N_t, s2, precision="fp64", profile=True, delay=args.delay, autotune=tune,
+                         **tiles_kw)
         sel64.profile(reset=True)
         ms64, (idx64, gain64) = timed_selections(sel64, K, budget, args.fp64_steps)
         p64 = sel64.profile(reset=True)
-        d64 = sel64.config()[0]
+        d64, v64, _, o64 = sel64.config()
         if not args.no_gaps:
             gaps = top_two_gaps(sel64, K, budget)
         sel64.close()
         log(f"fp64: {ms64:.1f} ms per selection")
         result["fp64"] = {"value": round(budget / (ms64 * 1e-3), 3), "unit": "greedy steps/s",
-                          "delay": d64,
-                          "ms_per_step": round(ms64, 3), "roofline": roofline_syrk(p64, "fp64", spec.name, d64),
+                          "delay": d64, "tile_order": o64,
+                          "ms_per_step": round(ms64, 3), "roofline": roofline_syrk(p64, "fp64", spec.name, d64, v64),
                           "kernel_ms_per_step": {k: round(v / args.fp64_steps, 3) for k, v in p64["ms"].items()}}
         result["mixed_vs_fp64"] = {"speedup": round(ms64 / ms, 3), **compare_picks(idx, gain, idx64, gain64)}
         if not args.no_gaps:
@@ -617,16 +637,18 @@ def main():
     # ---- the BF16 split-product downdate beside it, same K
     if not args.no_bf16x3 and prec == "mixed_f32" and spec.N_t <= 128 and not args.precision:
         selb = Selector(K, spec.N_s, spec.N_t, s2, precision="mixed_bf16x3", profile=True, delay=args.delay,
-                        autotune=tune)
+                        autotune=tune, **bf16_kw)
         timed_selections(selb, K, budget, 1)
         selb.profile(reset=True)
         msb, (idxb, gainb) = timed_selections(selb, K, budget, args.steps)
         pb = selb.profile(reset=True)
-        db = selb.config()[0]
+        db, vb, _, ob = selb.config()
         selb.close()
         log(f"mixed_bf16x3: {msb:.1f} ms per selection")
         result["mixed_bf16x3"] = {"value": round(budget / (msb * 1e-3), 3), "unit": "greedy steps/s", "delay": db,
-                                  "ms_per_step": round(msb, 3), "roofline": roofline_syrk(pb, "mixed_bf16x3", spec.name, db),
+                                  "downdate_variant": ["direct", "lds", "lds256"][vb], "tile_order": ob,
+                                  "ms_per_step": round(msb, 3),
+                                  "roofline": roofline_syrk(pb, "mixed_bf16x3", spec.name, db, vb),
                                   "kernel_ms_per_step": {k: round(v / args.steps, 3) for k, v in pb["ms"].items()},
                                   "speedup_vs_mixed_f32": round(ms / msb, 3),
                                   "vs_mixed_f32": compare_picks(idxb, gainb, idx, gain)}
