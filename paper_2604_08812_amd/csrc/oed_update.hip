@@ -1,6 +1,8 @@
 // Update kernels of one greedy step: the block column W = R[:, s] L_s^-T of the winner s (the
 // new block row of the factor in Algorithm 1, Sec. III-D) and the Schur-complement downdate
 // R -= W W^T on the lower triangle of the remaining rows, on MFMA.
+#include <type_traits>
+
 #include "oed_device.h"
 
 namespace oed {
@@ -236,158 +238,220 @@ __device__ void trsm_body(const StepDesc &d, int p)
     }
 }
 
-// The block column for N_tp = 16 NB <= 128 (single launches): as trsm_body with the slice loops
-// unrolled and both sub-block rows of a wave (w and w + 4) carried together, so that every
-// L_s^-1 (or V_h) block loaded from L2 feeds the MFMAs of both rows and the loads of later
-// slices are issued ahead of the current slice's MFMAs.
-template <typename TR, typename TW, int NB>
+// The block column for N_tp = 16 NB <= 128 (single launches): one work-group of NB waves per
+// remaining row i, wave w computing sub-block row tb = w of W_i (all NB sub-blocks of it).  The
+// operands every wave needs -- V_h of the held columns and L_s^-1 -- pass through LDS one
+// 16-column slice at a time, double-buffered: while the waves multiply slice j, the next slice is
+// on its way from L2, and so are the wave's own rows of P_h,i (or of R_is and the left-looking
+// partial sums) for it.  Slices: (h, q) for every held column h and 16-column block q of P_h,i,
+// then q = 0 .. NB-1 of L_s^-1 (only the sub-blocks c >= q of its lower triangle).  Every
+// accumulator sees the products of trsm_body in the same order, so W is bitwise the same.
+constexpr int TRSM_MAX_SPLITS = 4;  // left-looking partial sums the kernel reads (LEFT_SPLITS)
+
+// A row block of a held W (P_h,i), four consecutive inner indices per lane, as loaded: FP32 or
+// FP64 one vector, BF16 the hi and lo parts (w_row4 without the conversion, so that the load can
+// be issued a slice ahead and waited for only where it is used).
+template <typename TW>
+struct PRaw {
+    typename V4<TW>::type x;
+    __device__ __forceinline__ void load(const TW *Wb, const TW *, int tb, int q, int nb, int lane)
+    {
+        x = ld4(Wb + ((int64_t)(tb * nb + q) << 8) + lane * 4);
+    }
+    __device__ __forceinline__ double get(int r) const { return (double)x[r]; }
+};
+template <>
+struct PRaw<unsigned short> {
+    u16x4 h, l;
+    __device__ __forceinline__ void load(const unsigned short *Wh, const unsigned short *Wl, int tb, int q, int nb,
+                                         int lane)
+    {
+        const int g = lane >> 4, l16 = lane & 15;
+        const int64_t off = ((int64_t)(tb * (nb >> 1) + (q >> 1)) << 9) +
+                            (((((q & 1) << 1) + (g >> 1)) << 4) + l16) * 8 + 4 * (g & 1);
+        h = *reinterpret_cast<const u16x4 *>(Wh + off);
+        l = *reinterpret_cast<const u16x4 *>(Wl + off);
+    }
+    __device__ __forceinline__ double get(int r) const { return (double)bf2f(h[r]) + (double)bf2f(l[r]); }
+};
+
+template <typename TR, typename TW, int NB, bool LEFT>
 __device__ void trsm_nb_body(const StepDesc &d, int p)
 {
     if (d.state[ST_STATUS] != 0 || p >= d.n_act) return;
+    constexpr int MS = LEFT ? TRSM_MAX_SPLITS : 0;  // partial sums read (left-looking only)
+    using VE = typename std::conditional<sizeof(TR) == 4, float, double>::type;  // V's element
     constexpr int nb = NB;
+    constexpr int NT = 64 * NB;                 // threads
     constexpr int64_t bs = 256 * NB * NB;
+    __shared__ __align__(16) double sbuf[2][NB * 256];  // one slice: NB sub-blocks of 256
     const TR *__restrict__ R = (const TR *)d.R;
-    const double *__restrict__ Linv = d.Linv;
     const int i = d.act_in[p], s = d.state[ST_LAST];
     const int lane = threadIdx.x & 63, g = lane >> 4, l16 = lane & 15;
-    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int tb = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int alane = a_lane<double>(lane);
     const bool below = i > s;
     const TR *Cb = R + blk_index(below ? i : s, below ? s : i) * bs;
-    TW *Wi = (TW *)d.W + d.nheld * d.wslot + (int64_t)i * bs;  // slot nheld
-    TW *Wi2 = (TW *)d.W2 + d.nheld * d.wslot + (int64_t)i * bs;
-    bool has[2];
-    int tb[2];
+    const int nbr = (d.N_t + 15) >> 4;          // rows of P past N_t are zero
+    const int nheld = d.nheld, nsplit = min(d.nsplit, MS);
+    const int nhs = nheld * nbr;                // held slices
+    const int nsl = nhs + NB;                   // all slices
+    const int t = 16 * tb + l16;
+
+    // the shared operand of slice j in 16-byte chunks: chunk ch of a slice whose sub-blocks
+    // c0 .. NB-1 are staged lands at LDS byte c0 * 256 * eb + 16 ch (eb: element bytes)
+    u32x4 stg[2];
+    auto fetch_shared = [&](int j) {
+        const bool held = j < nhs;
+        const int q = held ? j % nbr : j - nhs;
+        const int c0 = held ? 0 : q, eb = held ? (int)sizeof(VE) : 8, cpb = 16 * eb;
+        const char *src = held ? (const char *)((const VE *)d.V + (j / nbr) * bs + (q << 8))
+                               : (const char *)(d.Linv + (q << 8));
+        const int nch = (NB - c0) * cpb;
 #pragma unroll
-    for (int rr = 0; rr < 2; ++rr) {
-        tb[rr] = wave + 4 * rr;
-        has[rr] = tb[rr] < nb;
-    }
-    if (!has[0]) return;
-    doublex4 acc[2][NB];
-#pragma unroll
-    for (int rr = 0; rr < 2; ++rr)
-#pragma unroll
-        for (int c = 0; c < NB; ++c) acc[rr][c] = doublex4{0.0, 0.0, 0.0, 0.0};
-    // - sum_h P_h,i V_h^T (held block columns).  Mixed paths: on the FP32 MFMA (P is FP32, or
-    // BF16 hi + lo, exact in FP32; V_h rounded to FP32) -- the precision the downdate itself
-    // would have subtracted these columns in -- accumulated separately and added in FP64.
-    const int nbr = (d.N_t + 15) >> 4;
-    if constexpr (sizeof(TR) == 4) {
-        floatx4 hacc[2][NB];
-#pragma unroll
-        for (int rr = 0; rr < 2; ++rr)
-#pragma unroll
-            for (int c = 0; c < NB; ++c) hacc[rr][c] = floatx4{0.f, 0.f, 0.f, 0.f};
-        for (int hp = 0; hp < d.nheld; ++hp) {
-            const TW *Pi = (const TW *)d.W + hp * d.wslot + (int64_t)i * bs;
-            const TW *Pi2 = d.W2 ? (const TW *)d.W2 + hp * d.wslot + (int64_t)i * bs : nullptr;
-            const float *Vh = (const float *)d.V + hp * bs;
-#pragma unroll
-            for (int q = 0; q < NB; ++q) {
-                if (q >= nbr) break;
-                float b[2][4];
-#pragma unroll
-                for (int rr = 0; rr < 2; ++rr) {
-                    if (!has[rr]) continue;
-                    double v[4];
-                    w_row4<TW>(Pi, Pi2, tb[rr], q, nb, lane, v);
-#pragma unroll
-                    for (int s4 = 0; s4 < 4; ++s4) b[rr][s4] = (float)-v[s4];
-                }
-#pragma unroll
-                for (int c = 0; c < NB; ++c) {
-                    // the FP32 MFMA takes its A operand in the natural lane order
-                    const floatx4 a = ld4(Vh + ((c * nb + q) << 8) + lane * 4);
-#pragma unroll
-                    for (int rr = 0; rr < 2; ++rr)
-                        if (has[rr]) {
-#pragma unroll
-                            for (int s4 = 0; s4 < 4; ++s4) hacc[rr][c] = mfma16(a[s4], b[rr][s4], hacc[rr][c]);
-                        }
-                }
+        for (int r = 0; r < 2; ++r) {
+            const int ch = (int)threadIdx.x + r * NT;
+            if (ch < nch) {
+                const int c = c0 + ch / cpb, off = ch % cpb;
+                stg[r] = *reinterpret_cast<const u32x4 *>(src + ((int64_t)c * nb << 8) * eb + off * 16);
             }
         }
+    };
+    auto store_shared = [&](int j, int buf) {
+        const bool held = j < nhs;
+        const int c0 = held ? 0 : j - nhs, eb = held ? (int)sizeof(VE) : 8, cpb = 16 * eb;
+        const int nch = (NB - c0) * cpb;
 #pragma unroll
-        for (int rr = 0; rr < 2; ++rr)
-#pragma unroll
-            for (int c = 0; c < NB; ++c)
-#pragma unroll
-                for (int r = 0; r < 4; ++r) acc[rr][c][r] = (double)hacc[rr][c][r];
-    } else {
-        for (int hp = 0; hp < d.nheld; ++hp) {
-            // - P_h,i V_h^T: inner index over the held pick's block, V_h in L_s^-1's order
+        for (int r = 0; r < 2; ++r) {
+            const int ch = (int)threadIdx.x + r * NT;
+            if (ch < nch) *reinterpret_cast<u32x4 *>((char *)sbuf[buf] + c0 * 256 * eb + ch * 16) = stg[r];
+        }
+    };
+    // the wave's own operand of slice j, as loaded: row block tb of P_h,i (held slices), or of
+    // R_is and of the left-looking partial sums (slices of L_s^-1)
+    PRaw<TW> pr;
+    TR cr[1 + MS][4];
+    auto fetch_own = [&](int j) {
+        if (j < nhs) {
+            const int hp = j / nbr, q = j % nbr;
             const TW *Pi = (const TW *)d.W + hp * d.wslot + (int64_t)i * bs;
             const TW *Pi2 = d.W2 ? (const TW *)d.W2 + hp * d.wslot + (int64_t)i * bs : nullptr;
-            const double *Vh = d.V + hp * bs;
-#pragma unroll
-            for (int q = 0; q < NB; ++q) {
-                if (q >= nbr) break;
-                double b[2][4];
-#pragma unroll
-                for (int rr = 0; rr < 2; ++rr) {
-                    if (!has[rr]) continue;
-                    w_row4<TW>(Pi, Pi2, tb[rr], q, nb, lane, b[rr]);
-#pragma unroll
-                    for (int s4 = 0; s4 < 4; ++s4) b[rr][s4] = -b[rr][s4];
-                }
-#pragma unroll
-                for (int c = 0; c < NB; ++c) {
-                    const doublex4 a = ld4(Vh + ((c * nb + q) << 8) + alane * 4);
-#pragma unroll
-                    for (int rr = 0; rr < 2; ++rr)
-                        if (has[rr]) {
-#pragma unroll
-                            for (int s4 = 0; s4 < 4; ++s4) acc[rr][c] = mfma16(a[s4], b[rr][s4], acc[rr][c]);
-                        }
-                }
-            }
-        }
-    }
-#pragma unroll
-    for (int q = 0; q < NB; ++q) {
-        double b[2][4];
-#pragma unroll
-        for (int rr = 0; rr < 2; ++rr) {
-            if (!has[rr]) continue;
-            const int t = 16 * tb[rr] + l16;
+            pr.load(Pi, Pi2, tb, q, nb, lane);
+        } else {
+            const int q = j - nhs;
             if (below) {
 #pragma unroll
-                for (int s4 = 0; s4 < 4; ++s4) b[rr][s4] = (double)Cb[acc_off(t, 16 * q + 4 * g + s4, nb)];
+                for (int s4 = 0; s4 < 4; ++s4) cr[0][s4] = Cb[acc_off(t, 16 * q + 4 * g + s4, nb)];
             } else {
-                const typename V4<TR>::type v = ld4(Cb + acc_off(16 * q + 4 * g, 16 * tb[rr] + l16, nb));
+                const typename V4<TR>::type v = ld4(Cb + acc_off(16 * q + 4 * g, t, nb));
 #pragma unroll
-                for (int s4 = 0; s4 < 4; ++s4) b[rr][s4] = (double)v[s4];
+                for (int s4 = 0; s4 < 4; ++s4) cr[0][s4] = v[s4];
             }
-            // left-looking: C_i = K_is - sum_h W_h,i W_h,s^T, the sum in nsplit partials
-            for (int sp = 0; sp < d.nsplit; ++sp) {
-                const TR *Cp = (const TR *)d.C + sp * d.cstride + (int64_t)i * bs;
 #pragma unroll
-                for (int s4 = 0; s4 < 4; ++s4) b[rr][s4] -= (double)Cp[acc_off(t, 16 * q + 4 * g + s4, nb)];
-            }
-        }
+            for (int sp = 0; sp < MS; ++sp)
+                if (sp < nsplit) {
+                    const TR *Cp = (const TR *)d.C + sp * d.cstride + (int64_t)i * bs;
 #pragma unroll
-        for (int c = q; c < NB; ++c) {
-            const doublex4 a = ld4(Linv + ((c * nb + q) << 8) + alane * 4);
-#pragma unroll
-            for (int rr = 0; rr < 2; ++rr)
-                if (has[rr]) {
-#pragma unroll
-                    for (int s4 = 0; s4 < 4; ++s4) acc[rr][c] = mfma16(a[s4], b[rr][s4], acc[rr][c]);
+                    for (int s4 = 0; s4 < 4; ++s4) cr[1 + sp][s4] = Cp[acc_off(t, 16 * q + 4 * g + s4, nb)];
                 }
         }
-    }
+    };
+    // after the multiplications of slice j: the next slice into the other buffer
+    auto advance = [&](int j) {
+        if (j + 1 < nsl) {
+            store_shared(j + 1, (j + 1) & 1);
+            __syncthreads();
+        }
+    };
+
+    fetch_shared(0);
+    fetch_own(0);
+    store_shared(0, 0);
+    __syncthreads();
+
+    doublex4 acc[NB];
+    if constexpr (sizeof(TR) == 4) {
+        // - sum_h P_h,i V_h^T on the FP32 MFMA (P is FP32, or BF16 hi + lo, exact in FP32; V_h
+        // rounded to FP32) -- the precision the downdate itself would have subtracted these
+        // columns in -- accumulated apart and carried on in FP64
+        floatx4 hacc[NB];
 #pragma unroll
-    for (int rr = 0; rr < 2; ++rr)
-        if (has[rr]) {
+        for (int c = 0; c < NB; ++c) hacc[c] = floatx4{0.f, 0.f, 0.f, 0.f};
+        for (int j = 0; j < nhs; ++j) {
+            float b[4];
+#pragma unroll
+            for (int s4 = 0; s4 < 4; ++s4) b[s4] = (float)-pr.get(s4);
+            fetch_shared(j + 1);
+            fetch_own(j + 1);
+            const float *Vs = (const float *)sbuf[j & 1];
 #pragma unroll
             for (int c = 0; c < NB; ++c) {
-                if constexpr (sizeof(TW) == 2)
-                    store_w_bf16(Wi, Wi2, tb[rr], c, nb >> 1, lane, acc[rr][c]);
-                else
-                    store_w(Wi, ((int64_t)(tb[rr] * nb + c) << 8) + lane * 4, acc[rr][c]);
+                // the FP32 MFMA takes its A operand in the natural lane order
+                const floatx4 a = ld4(Vs + (c << 8) + lane * 4);
+#pragma unroll
+                for (int s4 = 0; s4 < 4; ++s4) hacc[c] = mfma16(a[s4], b[s4], hacc[c]);
+            }
+            advance(j);
+        }
+#pragma unroll
+        for (int c = 0; c < NB; ++c)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) acc[c][r] = (double)hacc[c][r];
+    } else {
+#pragma unroll
+        for (int c = 0; c < NB; ++c) acc[c] = doublex4{0.0, 0.0, 0.0, 0.0};
+        for (int j = 0; j < nhs; ++j) {
+            double b[4];
+#pragma unroll
+            for (int s4 = 0; s4 < 4; ++s4) b[s4] = -pr.get(s4);
+            fetch_shared(j + 1);
+            fetch_own(j + 1);
+            const double *Vs = sbuf[j & 1];
+#pragma unroll
+            for (int c = 0; c < NB; ++c) {
+                const doublex4 a = ld4(Vs + (c << 8) + alane * 4);
+#pragma unroll
+                for (int s4 = 0; s4 < 4; ++s4) acc[c] = mfma16(a[s4], b[s4], acc[c]);
+            }
+            advance(j);
+        }
+    }
+    // + C_i L_s^-T, C_i = R_is (right-looking) or K_is - sum_h W_h,i W_h,s^T (left-looking, the sum
+    // in nsplit partials)
+    for (int q = 0; q < NB; ++q) {
+        const int j = nhs + q;
+        double b[4];
+#pragma unroll
+        for (int s4 = 0; s4 < 4; ++s4) {
+            b[s4] = (double)cr[0][s4];
+#pragma unroll
+            for (int sp = 0; sp < MS; ++sp)
+                if (sp < nsplit) b[s4] -= (double)cr[1 + sp][s4];
+        }
+        if (j + 1 < nsl) {
+            fetch_shared(j + 1);
+            fetch_own(j + 1);
+        }
+        const double *Ls = sbuf[j & 1];
+#pragma unroll
+        for (int c = 0; c < NB; ++c) {
+            if (c >= q) {
+                const doublex4 a = ld4(Ls + (c << 8) + alane * 4);
+#pragma unroll
+                for (int s4 = 0; s4 < 4; ++s4) acc[c] = mfma16(a[s4], b[s4], acc[c]);
             }
         }
+        advance(j);
+    }
+    TW *Wi = (TW *)d.W + nheld * d.wslot + (int64_t)i * bs;  // slot nheld
+    TW *Wi2 = (TW *)d.W2 + nheld * d.wslot + (int64_t)i * bs;
+#pragma unroll
+    for (int c = 0; c < NB; ++c) {
+        if constexpr (sizeof(TW) == 2)
+            store_w_bf16(Wi, Wi2, tb, c, nb >> 1, lane, acc[c]);
+        else
+            store_w(Wi, ((int64_t)(tb * nb + c) << 8) + lane * 4, acc[c]);
+    }
 }
 
 // ---------------------------------------------------------------------------------------------
@@ -1299,10 +1363,10 @@ __global__ void __launch_bounds__(256) trsm_kernel(StepDesc d)
     trsm_body<TR, TW>(d, blockIdx.x);
 }
 
-template <typename TR, typename TW, int NB>
-__global__ void __launch_bounds__(256, 2) trsm_nb_kernel(StepDesc d)
+template <typename TR, typename TW, int NB, bool LEFT>
+__global__ void __launch_bounds__(64 * NB, (LEFT && sizeof(TR) == 8) ? 2 : 4) trsm_nb_kernel(StepDesc d)
 {
-    trsm_nb_body<TR, TW, NB>(d, blockIdx.x);
+    trsm_nb_body<TR, TW, NB, LEFT>(d, blockIdx.x);
 }
 
 template <typename TR, typename TW>
@@ -1525,10 +1589,16 @@ template <typename TR, typename TW>
 static hipError_t launch_trsm_t(const StepDesc *descs, const StepDesc &d, int n, int64_t total, hipStream_t s)
 {
     if (!descs && d.N_tp <= 128) {
-        const dim3 grid((unsigned)total), block(256);
+        if (d.nsplit > TRSM_MAX_SPLITS) return hipErrorInvalidValue;
+        const dim3 grid((unsigned)total), block(d.N_tp * 4);
         switch (d.N_tp / 16) {
-#define OED_TRSM_CASE(NBV) \
-    case NBV: hipLaunchKernelGGL((trsm_nb_kernel<TR, TW, NBV>), grid, block, 0, s, d); break;
+#define OED_TRSM_CASE(NBV)                                                                        \
+    case NBV:                                                                                     \
+        if (d.nsplit > 0)                                                                         \
+            hipLaunchKernelGGL((trsm_nb_kernel<TR, TW, NBV, true>), grid, block, 0, s, d);        \
+        else                                                                                      \
+            hipLaunchKernelGGL((trsm_nb_kernel<TR, TW, NBV, false>), grid, block, 0, s, d);       \
+        break;
             OED_TRSM_CASE(1)
             OED_TRSM_CASE(2)
             OED_TRSM_CASE(3)
