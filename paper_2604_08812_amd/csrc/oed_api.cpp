@@ -269,6 +269,11 @@ constexpr int LEFT_SPLITS = 4;
 // block columns: the partial sums sum_h W_h,i W_h,s^T (column kernel, LEFT_SPLITS parts), then
 // W_i = (K_is - sums) L_s^-T into W slot k-1.  The diagonal blocks get this column at the next
 // gain launch.
+// The block column kernel applies the new column to the diagonal blocks itself (single launches,
+// N_tp <= 128) wherever they are kept current step by step: the eager right-looking path and the
+// left-looking method.  The gain launch then factors them as they are.
+bool fuse_diag(const oed_ctx *h) { return (h->eager || h->left) && h->N_tp <= 128; }
+
 oed_status advance_left(oed_ctx *h)
 {
     if (!h->pending) return OED_OK;
@@ -294,11 +299,12 @@ oed_status advance_left(oed_ctx *h)
     }
     d.W = (char *)h->W + (size_t)(hist * h->wslot) * welem(h);  // output: slot k-1
     if (h->W2) d.W2 = (char *)h->W2 + (size_t)(hist * h->wslot) * 2;
+    d.diag = fuse_diag(h) ? 1 : 0;  // the new column applied to the diagonal blocks there and then
     {
         Prof pr(h, OED_K_TRSM);
         HIPCHK(h, launch_trsm(d, h->rtype, h->wtype, h->stream));
     }
-    h->diag_current = false;
+    h->diag_current = d.diag != 0;
     return OED_OK;
 }
 
@@ -312,12 +318,14 @@ oed_status advance(oed_ctx *h, bool full)
             return OED_OK;
         }
         StepDesc d = desc(h);
+        d.diag = fuse_diag(h) ? 1 : 0;
         {
             Prof pr(h, OED_K_TRSM);
             if (h->nheld > 0) HIPCHK(h, launch_vcorr(d, h->wtype, h->stream));
             HIPCHK(h, launch_trsm(d, h->rtype, h->wtype, h->stream));
         }
-        if (h->eager) {
+        d.diag = 0;
+        if (h->eager && !fuse_diag(h)) {
             h->newest = h->nheld;  // the next gain launch applies it to the diagonal blocks
             h->diag_current = false;
         }
@@ -531,12 +539,17 @@ oed_status autotune(oed_ctx *h)
             d.n_act = n_at[z];
             d.nitems = n_at[z];
             d.nheld = hh;
-            // eager diagonal: the gain launch applies only the newest column and writes it back
-            // (the W slots are zero, so R stays exactly as packed)
+            // eager diagonal: the block column kernel applies the new column to the diagonal blocks
+            // and the gain launch factors them as they are (the W slots and L_s^-1 are zero, so R
+            // stays exactly as packed)
             StepDesc dg = d;
             if (h->eager) {
-                dg.nheld = hh > 0 ? 1 : 0;
-                dg.wb = dg.nheld;
+                dg.nheld = 0;
+                d.diag = fuse_diag(h) ? 1 : 0;
+                if (!d.diag) {
+                    dg.nheld = hh > 0 ? 1 : 0;
+                    dg.wb = dg.nheld;
+                }
             }
             double tg = 0, tt = 0;
             e = time_ms(h, a, b, [&] { return launch_gain(dg, h->rtype, h->wtype, h->stream); }, &tg);

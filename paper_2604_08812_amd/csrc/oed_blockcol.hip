@@ -275,6 +275,105 @@ struct PRaw<unsigned short> {
     __device__ __forceinline__ double get(int r) const { return (double)bf2f(h[r]) + (double)bf2f(l[r]); }
 };
 
+// D_ii -= W_i W_i^T on candidate i's own diagonal block: the update the gain kernel makes when it
+// applies the newest block column (HeldProd over the nbr inner blocks, then
+// R = (TR)((double)R - (double)q)), made here from the W_i the work-group has just formed.  The
+// rounded W_i (as stored) is staged in LDS, wave w takes the lower blocks (C, I), I <= C < nbr,
+// numbered w, w + NB, ..., and forms each as q^T = P_C P_I^T: the same products in the same order
+// as the gain kernel's q = P_I P_C^T (the MFMA's operands swapped, each product commutes), which
+// lands in R's storage order, so the block is read and written with vector accesses.  FP64 stages
+// the inner blocks four at a time (64 KB of LDS).
+template <typename TR, typename TW, int NB>
+struct DiagStage {
+    static constexpr int KH = sizeof(TW) == 8 ? (NB < 4 ? NB : 4) : NB;  // inner blocks per stage
+};
+
+template <typename TR, typename TW, int NB>
+__device__ __forceinline__ void diag_update(TR *__restrict__ Rd, const doublex4 (&acc)[NB], int nbr, int tb,
+                                            int lane, char *lds)
+{
+    using VR = typename V4<TR>::type;
+    constexpr int KH = DiagStage<TR, TW, NB>::KH;
+    constexpr int PERW = (NB * (NB + 1) / 2 + NB - 1) / NB;
+    const int nblk = nbr * (nbr + 1) / 2;
+    const int al = a_lane<double>(lane);
+    // the blocks of this wave and their current values, loaded first (their latency is covered
+    // by the staging and the products); a slot past the last block reads block 0 and is not stored
+    int bc[PERW], bi[PERW];
+    VR rv[PERW];
+#pragma unroll
+    for (int u = 0; u < PERW; ++u) {
+        const int b = tb + u * NB;
+        const int bb = b < nblk ? b : 0;
+        bc[u] = (int)tri_row(bb);
+        bi[u] = bb - bc[u] * (bc[u] + 1) / 2;
+        rv[u] = ld4(Rd + ((bc[u] * NB + bi[u]) << 8) + lane * 4);
+    }
+    typedef typename std::conditional<sizeof(TW) == 8, doublex4, floatx4>::type QV;
+    QV q[PERW];
+#pragma unroll
+    for (int u = 0; u < PERW; ++u) q[u] = QV{0, 0, 0, 0};
+#pragma unroll
+    for (int k0 = 0; k0 < NB; k0 += KH) {
+        __syncthreads();  // the LDS is free (the slices of the block column, or the previous stage)
+        // the wave's row block tb of W_i, rounded as stored, inner blocks k0 .. k0 + KH - 1
+        if constexpr (sizeof(TW) == 2) {
+            unsigned short *Lh = (unsigned short *)lds, *Ll = Lh + NB * NB * 256;
+#pragma unroll
+            for (int c = 0; c < NB; ++c) store_w_bf16(Lh, Ll, tb, c, NB >> 1, lane, acc[c]);
+        } else {
+            TW *L = (TW *)lds;
+#pragma unroll
+            for (int c = 0; c < KH; ++c)
+                if (k0 + c < NB) store_w(L, ((int64_t)(tb * KH + c) << 8) + lane * 4, acc[k0 + c]);
+        }
+        __syncthreads();
+#pragma unroll
+        for (int u = 0; u < PERW; ++u) {
+            if (tb + u * NB >= nblk) break;
+            const int C = bc[u], I = bi[u];
+            if constexpr (sizeof(TW) == 2) {
+                const unsigned short *Lh = (const unsigned short *)lds, *Ll = Lh + NB * NB * 256;
+                constexpr int N32 = NB / 2;
+                const int n32 = (nbr + 1) >> 1;
+#pragma unroll
+                for (int kc = 0; kc < (N32 > 0 ? N32 : 1); ++kc)
+                    if (kc < n32) {
+                        const int oc = ((C * N32 + kc) << 9) + lane * 8, oi = ((I * N32 + kc) << 9) + lane * 8;
+                        const u32x4 ch = *reinterpret_cast<const u32x4 *>(Lh + oc);
+                        const u32x4 cl = *reinterpret_cast<const u32x4 *>(Ll + oc);
+                        const u32x4 ih = *reinterpret_cast<const u32x4 *>(Lh + oi);
+                        const u32x4 il = *reinterpret_cast<const u32x4 *>(Ll + oi);
+                        // hi_I hi_C + hi_I lo_C + lo_I hi_C, in that order
+                        q[u] = mfma_bf16(ch, ih, q[u]);
+                        q[u] = mfma_bf16(cl, ih, q[u]);
+                        q[u] = mfma_bf16(ch, il, q[u]);
+                    }
+            } else {
+                const TW *L = (const TW *)lds;
+#pragma unroll
+                for (int c = 0; c < KH; ++c)
+                    if (k0 + c < nbr) {
+                        // FP64: the A operand's rows at the permuted lane, as everywhere
+                        const typename V4<TW>::type a =
+                            ld4(L + ((C * KH + c) << 8) + (sizeof(TW) == 8 ? al : lane) * 4);
+                        const typename V4<TW>::type b = ld4(L + ((I * KH + c) << 8) + lane * 4);
+#pragma unroll
+                        for (int s4 = 0; s4 < 4; ++s4) q[u] = mfma16(a[s4], b[s4], q[u]);
+                    }
+            }
+        }
+    }
+#pragma unroll
+    for (int u = 0; u < PERW; ++u) {
+        if (tb + u * NB >= nblk) break;
+        VR v;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) v[r] = (TR)((double)rv[u][r] - (double)q[u][r]);
+        st4(Rd + ((bc[u] * NB + bi[u]) << 8) + lane * 4, v);
+    }
+}
+
 template <typename TR, typename TW, int NB, bool LEFT>
 __device__ void trsm_nb_body(const StepDesc &d, int p)
 {
@@ -284,7 +383,12 @@ __device__ void trsm_nb_body(const StepDesc &d, int p)
     constexpr int nb = NB;
     constexpr int NT = 64 * NB;                 // threads
     constexpr int64_t bs = 256 * NB * NB;
-    __shared__ __align__(16) double sbuf[2][NB * 256];  // one slice: NB sub-blocks of 256
+    // the slice buffers (2 x NB sub-blocks of 256 doubles), and after the slices the staged W_i of
+    // the diagonal update (NB^2 sub-blocks of FP32 / BF16 hi + lo, or NB x 4 of FP64)
+    constexpr int SLICE_D = 2 * NB * 256;                                             // doubles
+    constexpr int STAGE_D = sizeof(TW) == 8 ? NB * DiagStage<TR, TW, NB>::KH * 256 : NB * NB * 128;
+    __shared__ __align__(16) double lds_all[SLICE_D > STAGE_D ? SLICE_D : STAGE_D];
+    double(*sbuf)[NB * 256] = reinterpret_cast<double(*)[NB * 256]>(lds_all);
     const TR *__restrict__ R = (const TR *)d.R;
     const int i = d.act_in[p], s = d.state[ST_LAST];
     const int lane = threadIdx.x & 63, g = lane >> 4, l16 = lane & 15;
@@ -452,6 +556,7 @@ __device__ void trsm_nb_body(const StepDesc &d, int p)
         else
             store_w(Wi, ((int64_t)(tb * nb + c) << 8) + lane * 4, acc[c]);
     }
+    if (d.diag) diag_update<TR, TW, NB>((TR *)d.R + blk_index(i, i) * bs, acc, nbr, tb, lane, (char *)lds_all);
 }
 
 // ---------------------------------------------------------------------------------------------
@@ -549,6 +654,8 @@ hipError_t launch_schur_block(const void *R, int rtype, const void *W, const voi
 template <typename TR, typename TW>
 static hipError_t launch_trsm_t(const StepDesc *descs, const StepDesc &d, int n, int64_t total, hipStream_t s)
 {
+    // the in-place diagonal update exists in the single-launch kernel only
+    if (d.diag && (descs || d.N_tp > 128)) return hipErrorInvalidValue;
     if (!descs && d.N_tp <= 128) {
         if (d.nsplit > TRSM_MAX_SPLITS) return hipErrorInvalidValue;
         const dim3 grid((unsigned)total), block(d.N_tp * 4);

@@ -247,6 +247,8 @@ __device__ __forceinline__ void load_upper(UBlocks &A, const TR *__restrict__ Rb
         }
     }
     if (d.wb && d.nheld > 0) {
+        // the corrected blocks as stored: the factorisation below takes the rounded value too,
+        // as it would after the block column kernel's in-place update (trsm with d.diag)
         TR *Rw = const_cast<TR *>(Rb);
 #pragma unroll
         for (int h = 0; h < 2; ++h) {
@@ -256,7 +258,11 @@ __device__ __forceinline__ void load_upper(UBlocks &A, const TR *__restrict__ Rb
                 if (C < nbr && I <= C) {
                     TR *blk = Rw + ((C * nb + I) << 8) + tofs;
 #pragma unroll
-                    for (int r = 0; r < 4; ++r) blk[4 * r] = (TR)ub(A, h, I)[r];
+                    for (int r = 0; r < 4; ++r) {
+                        const TR v = (TR)ub(A, h, I)[r];
+                        blk[4 * r] = v;
+                        ub(A, h, I)[r] = (double)v;
+                    }
                 }
         }
     }

@@ -103,7 +103,10 @@ struct StepDesc {
     int forced;            // pick: forced local index, or -1 for the argmax
     int nw;                // syrk: W slots 0 .. nw-1 applied (inner dimension nw N_tp)
     int stl;               // syrk: super-tile code of the tile order (see super_tile(); 0 = 8 x 8)
-    int skipdiag;          // syrk: leave the diagonal blocks alone (kept current by the gain kernel)
+    int skipdiag;          // syrk: leave the diagonal blocks alone (kept current by the gain or
+                           // block column kernel)
+    int diag;              // trsm (N_tp <= 128, single launches): also subtract the new block column
+                           // from every remaining diagonal block, D_ii -= W_i W_i^T, in place
     int64_t item0;         // batched launches: first work item of this instance
     int64_t nitems;        // work items of this instance (gain, trsm: n_act; pick: 1; syrk: tiles)
 };

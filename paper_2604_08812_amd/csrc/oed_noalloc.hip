@@ -161,9 +161,8 @@ OED_API oed_status oed_greedy_noalloc(const void *K_dev, int32_t dtype, int64_t 
 
     // the greedy loop of oed_greedy: the block column of pick k and, every `delay` picks, the
     // downdate of the held columns are enqueued at the start of step k + 1
-    int cur = 0, n_act = N_s, nheld = 0, newest = -1;
+    int cur = 0, n_act = N_s, nheld = 0;
     bool pending = false;
-    const int64_t wel = wtype == W_F64 ? 8 : wtype == W_F32 ? 4 : 2;
     for (int k = 0; k < budget; ++k) {
         d.act_in = act[cur];
         d.act_out = act[cur ^ 1];
@@ -172,11 +171,13 @@ OED_API oed_status oed_greedy_noalloc(const void *K_dev, int32_t dtype, int64_t 
         d.nw = 1;
         d.nheld = nheld;
         d.step = k;
-        newest = -1;
         if (pending) {
             if (nheld > 0) NA_CHK(launch_vcorr(d, wtype, s));
-            NA_CHK(launch_trsm(d, rtype, wtype, s));
-            newest = nheld;
+            // as the handle: the block column kernel also applies the new column to the diagonal
+            // blocks, so the gain launch factors them as they are
+            StepDesc t = d;
+            t.diag = 1;
+            NA_CHK(launch_trsm(t, rtype, wtype, s));
             if (nheld + 1 < delay) {
                 ++nheld;
             } else {
@@ -189,17 +190,10 @@ OED_API oed_status oed_greedy_noalloc(const void *K_dev, int32_t dtype, int64_t 
             }
             d.nheld = nheld;
         }
-        // as the handle: the gain launch applies the newest block column to the diagonal blocks
-        // and writes them back, and the pick finds the winner's diagonal block current
+        // the pick finds the winner's diagonal block current too
         StepDesc g = d;
         g.nitems = n_act;
         g.nheld = 0;
-        if (newest >= 0) {
-            g.W = (char *)d.W + newest * d.wslot * wel;
-            if (d.W2) g.W2 = (char *)d.W2 + newest * d.wslot * 2;
-            g.nheld = 1;
-            g.wb = 1;
-        }
         NA_CHK(launch_gain(g, rtype, wtype, s));
         StepDesc pk = d;
         pk.nitems = 1;
