@@ -325,7 +325,7 @@ def run_paper_shape(args):
     s2 = spec.c * scale
     torch.cuda.synchronize()
     log(f"F {spec.N_d} x {spec.n_m} formed in {time.perf_counter() - t0:.1f} s, sigma2={s2:.6e}")
-    sel = Selector(None, spec.N_s, spec.N_t, s2, precision="mixed_f32", profile=True)
+    sel = Selector(None, spec.N_s, spec.N_t, s2, precision="mixed_f32", profile=True, delay=args.delay)
     delay, variant, _, tiles = sel.config()
 
     def pack(target):

@@ -109,8 +109,9 @@ typedef struct oed_options {
                                    ones exactly; same picks, 1/p of the R traffic per pick).
                                    1 = subtract every pick's W W^T at the next step; 0 = automatic
                                    (with OED_FLAG_AUTOTUNE the autotuner's choice, else 4, for
-                                   N_t <= 128; 1 otherwise).  p > 1 with N_t > 128:
-                                   OED_E_UNSUPPORTED */
+                                   N_t <= 128; 1 otherwise).  With 128 < N_t <= 1024 a depth p > 1
+                                   is taken as given (the gain and pick kernels then apply the held
+                                   columns themselves); p > 1 with N_t > 1024: OED_E_UNSUPPORTED */
     int32_t method;             /* OED_METHOD_RIGHT_LOOKING (default), _LEFT_LOOKING or _AUTO */
     int32_t max_budget;         /* left-looking: most picks the handle will make (the W history
                                    is allocated for them); 0 = all candidates */

@@ -11,7 +11,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "liboed.so")
 OBJDIR = os.path.join(HERE, "_build")
-SOURCES = ["oed_pack.hip", "oed_factor.hip", "oed_blockcol.hip", "oed_update.hip", "oed_api.cpp", "oed_batch.cpp", "oed_noalloc.hip"]
+SOURCES = ["oed_pack.hip", "oed_factor.hip", "oed_blockcol.hip", "oed_column.hip", "oed_update.hip", "oed_api.cpp", "oed_batch.cpp", "oed_noalloc.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 FLAGS = [

@@ -809,13 +809,14 @@ oed_status oed_create(oed_ctx **out, const void *K, int32_t dtype, int64_t ld, i
     if (o.precision == OED_PREC_MIXED_BF16X3 && N_t > 128)
         return cfail(OED_E_UNSUPPORTED, "the BF16 split product serves N_t <= 128");
     if (o.delay < 0 || o.delay > MAX_DELAY) return cfail(OED_E_ARG, "delay out of range");
+    // held block columns need the register or blocked factorisations (they apply them on the fly)
+    if (o.delay > 1 && N_t > BLK_MAX_NTP) return cfail(OED_E_UNSUPPORTED, "delay > 1 needs N_t <= 1024");
     if (o.method != OED_METHOD_RIGHT_LOOKING && o.method != OED_METHOD_LEFT_LOOKING && o.method != OED_METHOD_AUTO)
         return cfail(OED_E_ARG, "unknown method");
     if (o.max_budget < 0 || o.max_budget > N_s) return cfail(OED_E_ARG, "max_budget out of range");
     // left-looking needs the diagonal-block update of the register or blocked gain kernels
     if (o.method == OED_METHOD_LEFT_LOOKING && N_t > BLK_MAX_NTP)
         return cfail(OED_E_UNSUPPORTED, "the left-looking method serves N_t <= 1024");
-    if (o.delay > 1 && N_t > REGS_MAX_NT) return cfail(OED_E_UNSUPPORTED, "delay > 1 needs N_t <= 128");
     if (o.tile_order < OED_TILES_AUTO || o.tile_order > OED_TILES_COL2) return cfail(OED_E_ARG, "unknown tile order");
     if (o.max_device_bytes < 0 || o.debug_fail_step < 0) return cfail(OED_E_ARG, "negative limit or hook step");
     if (o.tile_size != 0 && o.tile_size != 128 && o.tile_size != 256) return cfail(OED_E_ARG, "tile_size: 0, 128 or 256");

@@ -209,10 +209,11 @@ __device__ void trsm_body(const StepDesc &d, int p)
                 }
                 // left-looking: C_i = K_is - sum_h W_h,i W_h,s^T, the sum in nsplit partials
                 for (int sp = 0; sp < d.nsplit; ++sp) {
+                    // transposed sub-block (q, tb): the lane's four pick rows in one vector
                     const TR *Cp = (const TR *)d.C + sp * d.cstride + (int64_t)i * bs;
-                    const int t = 16 * tb + l16;
+                    const typename V4<TR>::type v = ld4(Cp + ((q * nb + tb) << 8) + lane * 4);
 #pragma unroll
-                    for (int s4 = 0; s4 < 4; ++s4) b[s4] -= (double)Cp[acc_off(t, 16 * q + 4 * g + s4, nb)];
+                    for (int s4 = 0; s4 < 4; ++s4) b[s4] -= (double)v[s4];
                 }
 #pragma unroll
                 for (int c = 0; c < 8; ++c) {
@@ -312,8 +313,6 @@ __device__ __forceinline__ void diag_update(TR *__restrict__ Rd, const doublex4 
     typedef typename std::conditional<sizeof(TW) == 8, doublex4, floatx4>::type QV;
     QV q[PERW];
 #pragma unroll
-    for (int u = 0; u < PERW; ++u) q[u] = QV{0, 0, 0, 0};
-#pragma unroll
     for (int k0 = 0; k0 < NB; k0 += KH) {
         __syncthreads();  // the LDS is free (the slices of the block column, or the previous stage)
         // the wave's row block tb of W_i, rounded as stored, inner blocks k0 .. k0 + KH - 1
@@ -328,6 +327,11 @@ __device__ __forceinline__ void diag_update(TR *__restrict__ Rd, const doublex4 
                 if (k0 + c < NB) store_w(L, ((int64_t)(tb * KH + c) << 8) + lane * 4, acc[k0 + c]);
         }
         __syncthreads();
+        if (k0 == 0) {
+            // the products start here, after the wave's W_i went to LDS (fewer live registers)
+#pragma unroll
+            for (int u = 0; u < PERW; ++u) q[u] = QV{0, 0, 0, 0};
+        }
 #pragma unroll
         for (int u = 0; u < PERW; ++u) {
             if (tb + u * NB >= nblk) break;
@@ -397,7 +401,9 @@ __device__ void trsm_nb_body(const StepDesc &d, int p)
     const bool below = i > s;
     const TR *Cb = R + blk_index(below ? i : s, below ? s : i) * bs;
     const int nbr = (d.N_t + 15) >> 4;          // rows of P past N_t are zero
-    const int nheld = d.nheld, nsplit = min(d.nsplit, MS);
+    // left-looking runs hold no block column back; the FP32 variant has its held-slice loop compiled
+    // out (that spills less there; for the BF16 variant keeping it does)
+    const int nheld = (LEFT && sizeof(TW) == 4) ? 0 : d.nheld, nsplit = min(d.nsplit, MS);
     const int nhs = nheld * nbr;                // held slices
     const int nsl = nhs + NB;                   // all slices
     const int t = 16 * tb + l16;
@@ -454,9 +460,11 @@ __device__ void trsm_nb_body(const StepDesc &d, int p)
 #pragma unroll
             for (int sp = 0; sp < MS; ++sp)
                 if (sp < nsplit) {
+                    // transposed sub-block (q, tb): the lane's four pick rows in one vector
                     const TR *Cp = (const TR *)d.C + sp * d.cstride + (int64_t)i * bs;
+                    const typename V4<TR>::type v = ld4(Cp + ((q * nb + tb) << 8) + lane * 4);
 #pragma unroll
-                    for (int s4 = 0; s4 < 4; ++s4) cr[1 + sp][s4] = Cp[acc_off(t, 16 * q + 4 * g + s4, nb)];
+                    for (int s4 = 0; s4 < 4; ++s4) cr[1 + sp][s4] = v[s4];
                 }
         }
     };

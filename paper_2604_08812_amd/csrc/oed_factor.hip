@@ -272,7 +272,7 @@ __device__ __forceinline__ void load_upper(UBlocks &A, const TR *__restrict__ Rb
 // block is addressed statically).  Returns false (uniformly) at a failed pivot.
 template <int p>
 __device__ __forceinline__ bool chol_mfma_step(UBlocks &A, int nbr, double *piv, doublex4 (*Ls)[8][64], int *sfail,
-                                               doublex4 (*Ysave)[64])
+                                               doublex4 (*Ysave)[64], doublex4 (*Usave)[64])
 {
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     const int al = a_lane<double>(lane);
@@ -297,6 +297,9 @@ __device__ __forceinline__ bool chol_mfma_step(UBlocks &A, int nbr, double *piv,
             for (int s4 = 0; s4 < 4; ++s4) acc = mfma16(y[s4], ub(A, h, p)[s4], acc);
             ub(A, h, p) = acc;
             Ls[buf][C][lane] = acc;
+            // U_pC is final: kept for the pick as soon as it is formed, so the factor cache's stores
+            // spread over the factorisation instead of trailing it
+            if (Usave) Usave[C * (C - 1) / 2 + p][lane] = acc;
         }
     }
     __syncthreads();
@@ -318,21 +321,22 @@ __device__ __forceinline__ bool chol_mfma_step(UBlocks &A, int nbr, double *piv,
 }
 
 // The blocked factorisation of the register blocks A (loaded by load_upper); pivots d_j go to
-// piv[0 .. 16 nbr), and with Ysave (LDS, 8 blocks) U_pp^-1 of every diagonal block is kept.
-// On return A holds the off-diagonal blocks U_IC, I < C, of U.  Returns false (uniformly) at a
-// pivot that is not > 0 or not finite.
-__device__ __forceinline__ bool chol_mfma_regs(UBlocks &A, int nbr, double *piv, doublex4 (*Ysave)[64])
+// piv[0 .. 16 nbr), with Ysave (8 blocks) U_pp^-1 of every diagonal block is kept and with Usave
+// (block (I, C) at C (C - 1) / 2 + I) every off-diagonal block U_IC, I < C.  On return A holds the
+// off-diagonal blocks of U.  Returns false (uniformly) at a pivot that is not > 0 or not finite.
+__device__ __forceinline__ bool chol_mfma_regs(UBlocks &A, int nbr, double *piv, doublex4 (*Ysave)[64],
+                                               doublex4 (*Usave)[64])
 {
     __shared__ doublex4 Ls[2][8][64];  // [step parity][block column][lane]
     __shared__ int sfail[2];
-    if (!chol_mfma_step<0>(A, nbr, piv, Ls, sfail, Ysave)) return false;
-    if (nbr > 1 && !chol_mfma_step<1>(A, nbr, piv, Ls, sfail, Ysave)) return false;
-    if (nbr > 2 && !chol_mfma_step<2>(A, nbr, piv, Ls, sfail, Ysave)) return false;
-    if (nbr > 3 && !chol_mfma_step<3>(A, nbr, piv, Ls, sfail, Ysave)) return false;
-    if (nbr > 4 && !chol_mfma_step<4>(A, nbr, piv, Ls, sfail, Ysave)) return false;
-    if (nbr > 5 && !chol_mfma_step<5>(A, nbr, piv, Ls, sfail, Ysave)) return false;
-    if (nbr > 6 && !chol_mfma_step<6>(A, nbr, piv, Ls, sfail, Ysave)) return false;
-    if (nbr > 7 && !chol_mfma_step<7>(A, nbr, piv, Ls, sfail, Ysave)) return false;
+    if (!chol_mfma_step<0>(A, nbr, piv, Ls, sfail, Ysave, Usave)) return false;
+    if (nbr > 1 && !chol_mfma_step<1>(A, nbr, piv, Ls, sfail, Ysave, Usave)) return false;
+    if (nbr > 2 && !chol_mfma_step<2>(A, nbr, piv, Ls, sfail, Ysave, Usave)) return false;
+    if (nbr > 3 && !chol_mfma_step<3>(A, nbr, piv, Ls, sfail, Ysave, Usave)) return false;
+    if (nbr > 4 && !chol_mfma_step<4>(A, nbr, piv, Ls, sfail, Ysave, Usave)) return false;
+    if (nbr > 5 && !chol_mfma_step<5>(A, nbr, piv, Ls, sfail, Ysave, Usave)) return false;
+    if (nbr > 6 && !chol_mfma_step<6>(A, nbr, piv, Ls, sfail, Ysave, Usave)) return false;
+    if (nbr > 7 && !chol_mfma_step<7>(A, nbr, piv, Ls, sfail, Ysave, Usave)) return false;
     return true;
 }
 
@@ -350,18 +354,7 @@ __device__ __forceinline__ bool chol_mfma(const TR *__restrict__ Rb, int N_t, in
     const int nbr = (N_t + 15) >> 4;
     UBlocks A;
     load_upper<TR, TW>(A, Rb, nbr, nb, d, pofs);
-    if (!chol_mfma_regs(A, nbr, piv, fc)) return false;
-    if (fc) {
-        const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-#pragma unroll
-        for (int h = 0; h < 2; ++h) {
-            const int C = h ? 7 - w : w;
-#pragma unroll
-            for (int I = 0; I < (h ? 8 : 4); ++I)
-                if (I < C && C < nbr) fc[FCACHE_UO + C * (C - 1) / 2 + I][lane] = ub(A, h, I);
-        }
-    }
-    return true;
+    return chol_mfma_regs(A, nbr, piv, fc, fc ? fc + FCACHE_UO : nullptr);
 }
 
 
@@ -440,7 +433,7 @@ __device__ __forceinline__ bool chol_inv_mfma(const TR *__restrict__ Rb, int N_t
     {
         UBlocks A;
         load_upper<TR, TW>(A, Rb, nbr, nb, d, pofs);
-        if (!chol_mfma_regs(A, nbr, piv, Y)) return false;
+        if (!chol_mfma_regs(A, nbr, piv, Y, nullptr)) return false;
 #pragma unroll
         for (int h = 0; h < 2; ++h) {
             const int C = h ? 7 - w : w;
@@ -999,7 +992,8 @@ static hipError_t launch_pick_t(const StepDesc &d, hipStream_t s)
     if (d.N_t <= REGS_MAX_NT) {
         hipLaunchKernelGGL((pick_regs_kernel<TR, TW>), dim3(1), dim3(256), 0, s, d);
     } else if (d.N_tp <= 16 * BLK_MAX_NB) {
-        if (d.nheld || !d.scratch) return hipErrorInvalidValue;
+        // held block columns: as in the gain kernel (W in R's element type)
+        if (!d.scratch || (d.nheld && sizeof(TW) != sizeof(TR))) return hipErrorInvalidValue;
         const size_t lds = blocked_lds_bytes(d.N_tp >> 4);
         allow_lds(pick_blocked_kernel<TR>, lds);
         hipLaunchKernelGGL(pick_blocked_kernel<TR>, dim3(1), dim3(256), lds, s, d);

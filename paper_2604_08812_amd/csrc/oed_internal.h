@@ -82,7 +82,8 @@ struct StepDesc {
     int nsplit;            // left-looking: column partial sums in C (column kernel: splits of the
                            // W slots; trsm: C_i = R_is - sum of the nsplit partials), 0 = none
     void *C;               // left-looking column partial sums: split q at C + q cstride elements,
-                           // candidate i's block at + i N_tp^2, accumulator order, R's type
+                           // candidate i's block at + i N_tp^2, R's type, transposed: sub-block
+                           // (c, t) holds pick rows 16c.. against candidate rows 16t.. (accumulator order)
     int64_t cstride;
     const int *act_in;     // remaining candidates (gain, pick: before the pick; trsm, syrk: after it)
     int *act_out;          // pick: remaining candidates after the pick
