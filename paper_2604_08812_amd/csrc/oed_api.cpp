@@ -48,11 +48,12 @@ struct oed_ctx {
     bool left = false;
     int max_budget = 0;
     bool diag_current = true;  // the diagonal blocks include every formed block column
-    // right-looking, N_t <= REGS_MAX_NT: the diagonal blocks are kept current eagerly (the gain
-    // kernel subtracts the newest block column from them and writes them back) and the downdate
+    // right-looking, N_t <= REGS_MAX_NT: the diagonal blocks are kept current eagerly (the block
+    // column kernel subtracts each new column from them in place, fuse_diag) and the downdate
     // skips them, so the gains never carry the held columns
     bool eager = false;
-    int newest = -1;  // W slot of the block column the diagonal blocks do not include yet
+    int newest = -1;  // W slot of the block column the diagonal blocks do not include yet (the
+                      // gain launch applies it; only where fuse_diag does not hold)
     void *C = nullptr;         // column partial sums (LEFT_SPLITS x N_c blocks, R's type)
     double *noise_h = nullptr; // per-sensor noise terms by local index (device), or null
     uint32_t flags = 0;
@@ -255,25 +256,20 @@ oed_status enqueue_syrk(oed_ctx *h, StepDesc d)
     return OED_OK;
 }
 
-// Form the block column W of the last pick (Sec. III-D: the new block row of the factor) and
-// subtract the outer products from R.  With delay p > 1 and `full` false, block columns are
-// held (W slots 0 .. nheld-1; the gain and pick kernels correct for them exactly) until p of
-// them are formed, then subtracted in one downdate of inner dimension p N_t: 1/p of the R
-// traffic per pick.  `full` leaves R current.
 // Element size of W.
 size_t welem(const oed_ctx *h) { return h->wtype == W_F64 ? 8 : h->wtype == W_F32 ? 4 : 2; }
 
 constexpr int LEFT_SPLITS = 4;
 
-// Left-looking: form the block column of the last pick s (pick k-1) from K and the k-1 earlier
-// block columns: the partial sums sum_h W_h,i W_h,s^T (column kernel, LEFT_SPLITS parts), then
-// W_i = (K_is - sums) L_s^-T into W slot k-1.  The diagonal blocks get this column at the next
-// gain launch.
 // The block column kernel applies the new column to the diagonal blocks itself (single launches,
 // N_tp <= 128) wherever they are kept current step by step: the eager right-looking path and the
 // left-looking method.  The gain launch then factors them as they are.
 bool fuse_diag(const oed_ctx *h) { return (h->eager || h->left) && h->N_tp <= 128; }
 
+// Left-looking: form the block column of the last pick s (pick k-1) from K and the k-1 earlier
+// block columns: the partial sums sum_h W_h,i W_h,s^T (column kernel, LEFT_SPLITS parts), then
+// W_i = (K_is - sums) L_s^-T into W slot k-1.  The diagonal blocks get this column from the block
+// column kernel (fuse_diag) or at the next gain launch.
 oed_status advance_left(oed_ctx *h)
 {
     if (!h->pending) return OED_OK;
@@ -308,6 +304,11 @@ oed_status advance_left(oed_ctx *h)
     return OED_OK;
 }
 
+// Form the block column W of the last pick (Sec. III-D: the new block row of the factor) and
+// subtract the outer products from R.  With delay p > 1 and `full` false, block columns are
+// held (W slots 0 .. nheld-1; the gain and pick kernels correct for them exactly) until p of
+// them are formed, then subtracted in one downdate of inner dimension p N_t: 1/p of the R
+// traffic per pick.  `full` leaves R current.
 oed_status advance(oed_ctx *h, bool full)
 {
     if (h->left) return advance_left(h);

@@ -239,14 +239,6 @@ __device__ void trsm_body(const StepDesc &d, int p)
     }
 }
 
-// The block column for N_tp = 16 NB <= 128 (single launches): one work-group of NB waves per
-// remaining row i, wave w computing sub-block row tb = w of W_i (all NB sub-blocks of it).  The
-// operands every wave needs -- V_h of the held columns and L_s^-1 -- pass through LDS one
-// 16-column slice at a time, double-buffered: while the waves multiply slice j, the next slice is
-// on its way from L2, and so are the wave's own rows of P_h,i (or of R_is and the left-looking
-// partial sums) for it.  Slices: (h, q) for every held column h and 16-column block q of P_h,i,
-// then q = 0 .. NB-1 of L_s^-1 (only the sub-blocks c >= q of its lower triangle).  Every
-// accumulator sees the products of trsm_body in the same order, so W is bitwise the same.
 constexpr int TRSM_MAX_SPLITS = 4;  // left-looking partial sums the kernel reads (LEFT_SPLITS)
 
 // A row block of a held W (P_h,i), four consecutive inner indices per lane, as loaded: FP32 or
@@ -378,6 +370,15 @@ __device__ __forceinline__ void diag_update(TR *__restrict__ Rd, const doublex4 
     }
 }
 
+// The block column for N_tp = 16 NB <= 128 (single launches): one work-group of NB waves per
+// remaining row i, wave w computing sub-block row tb = w of W_i (all NB sub-blocks of it).  The
+// operands every wave needs -- V_h of the held columns and L_s^-1 -- pass through LDS one
+// 16-column slice at a time, double-buffered: while the waves multiply slice j, the next slice is
+// on its way from L2, and so are the wave's own rows of P_h,i (or of R_is and the left-looking
+// partial sums) for it.  Slices: (h, q) for every held column h and 16-column block q of P_h,i,
+// then q = 0 .. NB-1 of L_s^-1 (only the sub-blocks c >= q of its lower triangle).  Every
+// accumulator sees the products of trsm_body in the same order, so W is bitwise the same.  With
+// d.diag the work-group then applies W_i to candidate i's diagonal block (diag_update).
 template <typename TR, typename TW, int NB, bool LEFT>
 __device__ void trsm_nb_body(const StepDesc &d, int p)
 {
