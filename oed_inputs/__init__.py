@@ -16,6 +16,7 @@ from .synth import (  # noqa: F401
     make_K,
     make_K_lower_panels,
     make_K_sensor_noise,
+    make_K_weighted_noise,
     k_sub_lower,
 )
 from .configs import CONFIGS, batched_instance_specs, Spec  # noqa: F401

@@ -101,6 +101,34 @@ def make_K_sensor_noise(N_s: int, N_t: int, n_m: int, seed: int, c_lo: float = 1
     return G.to(dtype), var
 
 
+def make_K_weighted_noise(N_s: int, N_t: int, n_m: int, seed: int, c: float = 0.01, rho_max: float = 0.8,
+                          w_lo: float = 1.0, w_hi: float = 30.0, device="cpu", dtype=torch.float64):
+    """K = F F^T / n_m + W_c Gamma_noise with noise correlated in time within each sensor and a
+    placement-cost weight per sensor (the weighted noise covariance of Sec. III-G, with a diagonal
+    W_c): sensor j's noise block is ``w_j gamma^2 rho_j^|t-u|`` (a stationary AR(1) correlation of
+    its N_t samples), ``gamma^2 = c mean diag(F F^T / n_m)``; ``rho_j`` uniform in [0, rho_max) and
+    ``w_j`` log-uniform in [w_lo, w_hi] from ``numpy.random.default_rng(seed)``.  Sensors' noises
+    are independent of each other, so W_c Gamma_noise is block-diagonal.  Returns
+    ``(K, blocks)`` with ``blocks`` the FP64 noise blocks as a numpy array (N_s, N_t, N_t).
+    """
+    import numpy as np
+    N_d = N_s * N_t
+    G = torch.zeros((N_d, N_d), dtype=torch.float64, device=device)
+    for cb in range(math.ceil(n_m / TILE)):
+        Fc = f_column_chunk(seed, N_d, n_m, cb, device)
+        G.addmm_(Fc, Fc.t())
+    G /= n_m
+    gamma2 = c * float(G.diagonal().mean().item())
+    rng = np.random.default_rng(seed)
+    rho = rng.uniform(0.0, rho_max, N_s)
+    w = 10.0 ** rng.uniform(np.log10(w_lo), np.log10(w_hi), N_s)
+    lag = np.abs(np.subtract.outer(np.arange(N_t), np.arange(N_t)))
+    blocks = np.stack([w[j] * gamma2 * rho[j] ** lag for j in range(N_s)])
+    for j in range(N_s):
+        G[j * N_t:(j + 1) * N_t, j * N_t:(j + 1) * N_t] += torch.from_numpy(blocks[j]).to(device)
+    return G.to(dtype), blocks
+
+
 def make_K_lower_panels(N_s: int, N_t: int, n_m: int, seed: int, c: float = 0.01,
                         device="cuda", dtype=torch.float64, panel: int = 12800,
                         progress=None):

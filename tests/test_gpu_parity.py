@@ -366,6 +366,29 @@ def test_per_sensor_noise(prec, method, delay):
         assert ref["gap"][div] <= 2 * RTOL[prec] * max(1.0, abs(ref["gain"][div])), (div, ref["gap"][div])
 
 
+@pytest.mark.parametrize("method,delay", [("right", 1), ("right", 4), ("left", 0)])
+@pytest.mark.parametrize("prec", PRECS)
+def test_correlated_sensor_noise_with_cost_weights(prec, method, delay):
+    """Sensor placement cost as a weighted noise covariance W_c Gamma_noise (Sec. III-G, diagonal
+    W_c, weights over a 30x range) on noise correlated in time within each sensor (AR(1) blocks):
+    K carries the weighted blocks and h_j = 1/2 logdet(w_j Gamma_jj); the HIP path against the
+    oracle with the same per-sensor terms, on a ragged N_t."""
+    from oed_inputs import make_K_weighted_noise
+    N_s, N_t, B = 34, 24, 10
+    K, blocks = make_K_weighted_noise(N_s, N_t, 2000, 52)
+    h = np.array([0.5 * np.linalg.slogdet(b)[1] for b in blocks])
+    print(f"weighted noise {prec} {method} delay {delay}", flush=True)
+    with selector(K.to(DEV), N_s, N_t, 1.0, precision=prec, method=method, delay=delay,
+                  noise_half_logdet=h) as sel:
+        idx, gain = sel.greedy(B)
+    ref = oracle.greedy(K.numpy(), N_s, N_t, 1.0, B, noise_hld=h)
+    div = next((k for k in range(B) if idx[k] != ref["idx"][k]), None)
+    upto = B if div is None else div
+    assert np.all(rel_err(gain[:upto], ref["gain"][:upto]) <= RTOL[prec])
+    if div is not None:
+        assert ref["gap"][div] <= 2 * RTOL[prec] * max(1.0, abs(ref["gain"][div])), (div, ref["gap"][div])
+
+
 @pytest.mark.parametrize("prec", PRECS)
 def test_every_tile_order_gives_the_same_selection(prec):
     """The downdate's tile order changes which work-group computes a tile, never the arithmetic:

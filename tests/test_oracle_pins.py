@@ -410,6 +410,48 @@ def test_sensor_noise_telescoping_and_isotropic_special_case():
     np.testing.assert_allclose(iso["gain"], eq["gain"], rtol=1e-13, atol=1e-13)
 
 
+def test_sensor_cost_weight_scales_only_that_sensors_information():
+    """Placement cost as a weighted noise covariance W_c Gamma_noise (Sec. III-G, diagonal W_c) on
+    noise correlated in time within each sensor: scaling sensor j's noise block by w changes K's
+    diagonal block j and h_j = 1/2 logdet(w Gamma_jj).  At a fixed prefix A (j not in A) j's gain is
+    then 1/2 sum ln(1 + lambda_i / w) over the generalised eigenvalues of (P_j, Gamma_jj), P_j the
+    signal part of j's Schur complement: it falls strictly with w and tends to 0 (a sensor with
+    unbounded noise carries no information), while every other candidate's gain stays bitwise the
+    same (j's noise enters no other block)."""
+    from oed_inputs import make_K_weighted_noise
+    N_s, N_t = 10, 4
+    K0, blocks = make_K_weighted_noise(N_s, N_t, 300, 41)
+    K0 = K0.numpy()
+    A, j = [3, 7], 5
+    cand = [c for c in range(N_s) if c not in A]
+    bj = slice(j * N_t, (j + 1) * N_t)
+    ia = oracle.block_index(N_t, A)
+    # signal part of j's Schur complement at A (the noise of j is not coupled to A)
+    Gjj = K0[bj, bj] - blocks[j]
+    P = Gjj - K0[bj, ia] @ np.linalg.solve(K0[np.ix_(ia, ia)], K0[ia, bj])
+    lam = scipy.linalg.eigh(P, blocks[j], eigvals_only=True)
+    assert lam.min() > 0
+    h0 = np.array([0.5 * np.linalg.slogdet(b)[1] for b in blocks])
+    prev, others = None, None
+    for w in (1.0, 4.0, 64.0, 1e6, 1e12):
+        K = K0.copy()
+        K[bj, bj] += (w - 1.0) * blocks[j]
+        h = h0.copy()
+        h[j] += 0.5 * N_t * math.log(w)
+        g = oracle.gains(K, N_t, 1.0, A, cand, noise_hld=h)
+        gj = g[cand.index(j)]
+        ref = 0.5 * float(np.sum(np.log1p(lam / w)))
+        assert abs(gj - ref) <= 1e-9 * max(ref, 1e-6) + 1e-12, (w, gj, ref)
+        if prev is not None:
+            assert gj < prev, (w, gj, prev)
+        prev = gj
+        rest = np.delete(g, cand.index(j))
+        if others is None:
+            others = rest
+        np.testing.assert_array_equal(rest, others)
+    assert prev < 1e-9
+
+
 # --------------------------------------------------------------------------- objective f(S)
 @pytest.mark.parametrize("N_s,N_t,B,seed", [(6, 1, 3, 20), (7, 2, 3, 21), (8, 3, 4, 22)])
 def test_objective_matches_lu_table_for_every_subset(N_s, N_t, B, seed):
