@@ -68,9 +68,8 @@ typedef enum oed_dtype { OED_F64 = 0, OED_F32 = 1 } oed_dtype;
  *  MIXED_BF16X3 : like MIXED_F32, but W is split into BF16 hi + lo parts
  *                 (hi = bf16(w), lo = bf16(w - hi)) and the product is
  *                 hi*hi + hi*lo + lo*hi on BF16 MFMA with FP32 accumulation
- *                 (relative error of each product term about 2^-16).  Needs
- *                 N_t <= 128 (else OED_E_UNSUPPORTED); blocks are padded to a
- *                 multiple of 32 rows instead of 16.
+ *                 (relative error of each product term about 2^-16).  Blocks
+ *                 are padded to a multiple of 32 rows instead of 16.
  * The paper keeps K in FP64 and runs the whole candidate loop in FP32 (Sec. IV);
  * MIXED_F32 keeps the precision-critical factorisations in FP64 instead.
  */
@@ -136,7 +135,8 @@ typedef struct oed_options {
                                    creation (or the last reset) fail once with OED_E_HIP on the
                                    host, before anything of that step is enqueued; 0 = off */
     int32_t tile_size;          /* downdate work-group tile: 128 (128 x 128, four waves), 256 (256 x 256,
-                                   eight waves; MIXED_BF16X3 only, else OED_E_UNSUPPORTED) or 0 =
+                                   eight waves; MIXED_BF16X3 with N_t <= 128 only, else
+                                   OED_E_UNSUPPORTED) or 0 =
                                    automatic (the autotuner's choice with OED_FLAG_AUTOTUNE, else
                                    128) */
     int32_t reserved[1];        /* must be 0 */
@@ -162,9 +162,9 @@ typedef struct oed_options {
  *  LEFT_LOOKING  : the order of Algorithm 1 (Sec. III-D): R keeps K off the diagonal; every
  *                  pick forms only its own block column, K_is - sum over the earlier picks'
  *                  block columns (W history), and updates the diagonal blocks.  About 1/3 of
- *                  the flops of RIGHT_LOOKING at 600 x 128, budget 175.  FP64 and
- *                  MIXED_F32 for N_t <= 1024, MIXED_BF16X3 for N_t <= 128 (else
- *                  OED_E_UNSUPPORTED); the delay option does not apply.
+ *                  the flops of RIGHT_LOOKING at 600 x 128, budget 175.  Every precision
+ *                  for N_t <= 1024 (else OED_E_UNSUPPORTED); the delay option does not
+ *                  apply.
  */
 #define OED_METHOD_RIGHT_LOOKING 0
 #define OED_METHOD_LEFT_LOOKING 1

@@ -807,8 +807,6 @@ oed_status oed_create(oed_ctx **out, const void *K, int32_t dtype, int64_t ld, i
         return cfail(OED_E_ARG, "bad K, dtype, shape, leading dimension or sigma2");
     if (o.precision != OED_PREC_FP64 && o.precision != OED_PREC_MIXED_F32 && o.precision != OED_PREC_MIXED_BF16X3)
         return cfail(OED_E_ARG, "unknown precision");
-    if (o.precision == OED_PREC_MIXED_BF16X3 && N_t > 128)
-        return cfail(OED_E_UNSUPPORTED, "the BF16 split product serves N_t <= 128");
     if (o.delay < 0 || o.delay > MAX_DELAY) return cfail(OED_E_ARG, "delay out of range");
     // held block columns need the register or blocked factorisations (they apply them on the fly)
     if (o.delay > 1 && N_t > BLK_MAX_NTP) return cfail(OED_E_UNSUPPORTED, "delay > 1 needs N_t <= 1024");
@@ -821,8 +819,8 @@ oed_status oed_create(oed_ctx **out, const void *K, int32_t dtype, int64_t ld, i
     if (o.tile_order < OED_TILES_AUTO || o.tile_order > OED_TILES_COL2) return cfail(OED_E_ARG, "unknown tile order");
     if (o.max_device_bytes < 0 || o.debug_fail_step < 0) return cfail(OED_E_ARG, "negative limit or hook step");
     if (o.tile_size != 0 && o.tile_size != 128 && o.tile_size != 256) return cfail(OED_E_ARG, "tile_size: 0, 128 or 256");
-    if (o.tile_size == 256 && o.precision != OED_PREC_MIXED_BF16X3)
-        return cfail(OED_E_UNSUPPORTED, "256 x 256 downdate tiles serve the BF16 split product only");
+    if (o.tile_size == 256 && (o.precision != OED_PREC_MIXED_BF16X3 || N_t > 128))
+        return cfail(OED_E_UNSUPPORTED, "256 x 256 downdate tiles serve the BF16 split product with N_t <= 128");
     for (int r : o.reserved)
         if (r != 0) return cfail(OED_E_ARG, "reserved option fields must be 0");
 

@@ -345,6 +345,119 @@ __device__ void column_bf16_body(const StepDesc &d, int64_t item)
         }
 }
 
+// The BF16 hi + lo form for N_tp = 32 nb32 > 128: the work items and output chunks of
+// column_rt_body, the staging and products of column_bf16_body, with a run-time slice loop.
+__device__ void column_bf16_rt_body(const StepDesc &d, int64_t item)
+{
+    __shared__ u32x4 lds[2][4][8 * 64];  // [buffer][A hi, A lo, B hi, B lo][sub-block * 64 + lane]
+    if (d.state[ST_STATUS] != 0 || d.nsplit <= 0) return;
+    const int N_tp = d.N_tp, nb = N_tp >> 4, nb32 = N_tp >> 5, nchunk = (nb + 7) >> 3;
+    const int64_t rows_t = syrk_tile_rows(d.n_act, N_tp);
+    const int64_t per_split = rows_t * nchunk;
+    const int split = (int)(item / per_split);
+    const int64_t rem = item - split * per_split;
+    const int64_t P = rem / nchunk;
+    const int cc = (int)(rem - P * nchunk);
+    if (split >= d.nsplit) return;
+    const int h0 = (int)((int64_t)split * d.nw / d.nsplit), h1 = (int)((int64_t)(split + 1) * d.nw / d.nsplit);
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int *__restrict__ act = d.act_in;
+    const int rows = d.n_act * N_tp, last = d.n_act - 1;
+    const int s = uniform_at(d.state, ST_LAST);
+    const int64_t bs = (int64_t)N_tp * N_tp;
+    const int ncol = min(8, nb - 8 * cc);
+    // staged operands (BF16 elements; a 16-row sub-block row spans nb * 256 of them): rows of the
+    // tile (A) and the chunk's rows of s (B; past nb clamped)
+    int64_t wA[2], wB[2];
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+        const int sb = wave + 4 * h;
+        const int r = (int)P * 128 + 16 * sb;
+        wA[h] = (int64_t)uniform_at(act, min(r / N_tp, last)) * bs + (int64_t)((r % N_tp) >> 4) * (nb * 256);
+        const int sbB = 8 * cc + sb;
+        wB[h] = (int64_t)s * bs + (int64_t)(sbB < nb ? sbB : 0) * (nb * 256);
+    }
+    int64_t off[2];
+    bool ok[2];
+#pragma unroll
+    for (int b = 0; b < 2; ++b) {
+        const int r = (int)P * 128 + wave * 32 + 16 * b;
+        ok[b] = r < rows;
+        off[b] = (int64_t)uniform_at(act, min(r / N_tp, last)) * bs + ((8 * cc * nb + ((r % N_tp) >> 4)) << 8);
+    }
+    const bool any = ok[0];
+    typedef const unsigned short *bp;
+    const bp Wh0 = (bp)d.W + lane * 8, Wl0 = (bp)d.W2 + lane * 8;
+    const int64_t wslot = d.wslot;
+    floatx4 acc[2][8];
+#pragma unroll
+    for (int b = 0; b < 2; ++b)
+#pragma unroll
+        for (int c = 0; c < 8; ++c) acc[b][c] = floatx4{0, 0, 0, 0};
+    u32x4 st[2][4];
+    auto stage = [&](bp hi, bp lo) {
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            st[h][0] = *reinterpret_cast<const u32x4 *>(hi + wA[h]);
+            st[h][1] = *reinterpret_cast<const u32x4 *>(lo + wA[h]);
+            st[h][2] = *reinterpret_cast<const u32x4 *>(hi + wB[h]);
+            st[h][3] = *reinterpret_cast<const u32x4 *>(lo + wB[h]);
+        }
+    };
+    auto put = [&](int buf) {
+#pragma unroll
+        for (int h = 0; h < 2; ++h)
+#pragma unroll
+            for (int k = 0; k < 4; ++k) lds[buf][k][(wave + 4 * h) * 64 + lane] = st[h][k];
+    };
+    stage(Wh0 + h0 * wslot, Wl0 + h0 * wslot);
+    put(0);
+    __syncthreads();
+    int buf = 0;
+    for (int slot = h0; slot < h1; ++slot) {
+        const bp chi = Wh0 + slot * wslot, clo = Wl0 + slot * wslot;
+        for (int q = 0; q < nb32; ++q) {
+            const bool more = q + 1 < nb32 || slot + 1 < h1;
+            if (more) {
+                if (q + 1 < nb32)
+                    stage(chi + ((q + 1) << 9), clo + ((q + 1) << 9));
+                else
+                    stage(chi + wslot, clo + wslot);
+            }
+            if (any) {
+                u32x4 ah[2], al[2];
+#pragma unroll
+                for (int b = 0; b < 2; ++b) {
+                    ah[b] = lds[buf][0][(2 * wave + b) * 64 + lane];
+                    al[b] = lds[buf][1][(2 * wave + b) * 64 + lane];
+                }
+#pragma unroll
+                for (int c = 0; c < 8; ++c) {
+                    const u32x4 wh = lds[buf][2][c * 64 + lane], wl = lds[buf][3][c * 64 + lane];
+#pragma unroll
+                    for (int b = 0; b < 2; ++b) {
+                        acc[b][c] = mfma_bf16(wh, ah[b], acc[b][c]);
+                        acc[b][c] = mfma_bf16(wl, ah[b], acc[b][c]);
+                        acc[b][c] = mfma_bf16(wh, al[b], acc[b][c]);
+                    }
+                }
+            }
+            if (more) put(buf ^ 1);
+            __syncthreads();
+            buf ^= 1;
+        }
+    }
+    float *Cq = (float *)d.C + split * d.cstride + lane * 4;
+#pragma unroll
+    for (int b = 0; b < 2; ++b)
+        if (ok[b]) {
+#pragma unroll
+            for (int c = 0; c < 8; ++c)
+                if (c < ncol) st4(Cq + off[b] + ((c * nb) << 8), acc[b][c]);
+        }
+}
+
 // ---------------------------------------------------------------------------------------------
 // Kernels: single instance (descriptor by value) and batched (descriptor array).
 
@@ -363,6 +476,14 @@ __global__ void __launch_bounds__(256, (sizeof(T) == 4 ? 4 : 2)) column_rt_kerne
     const int64_t item = xcd_item(blockIdx.x, per_xcd);
     if (item >= d.nitems) return;
     column_rt_body<T>(d, item);
+}
+
+// d.nitems here counts (split, row tile, column chunk) items
+__global__ void __launch_bounds__(256, 2) column_bf16_rt_kernel(StepDesc d, int64_t per_xcd)
+{
+    const int64_t item = xcd_item(blockIdx.x, per_xcd);
+    if (item >= d.nitems) return;
+    column_bf16_rt_body(d, item);
 }
 
 template <int NB32>
@@ -428,13 +549,15 @@ hipError_t launch_column(const StepDesc &d, int rtype, int wtype, hipStream_t s)
     if (d.n_act <= 0 || d.nsplit <= 0 || d.nitems <= 0) return hipSuccess;
     if (d.N_tp % 16 != 0 || d.nw < d.nsplit || !d.C) return hipErrorInvalidValue;
     if (d.N_tp > 128) {
-        if (wtype == W_BF16X3) return hipErrorInvalidValue;
+        if (wtype == W_BF16X3 && (d.N_tp % 32 != 0 || !d.W2)) return hipErrorInvalidValue;
         // one item per (split, row tile, 128-column chunk of the pick)
         StepDesc e = d;
         e.nitems = d.nitems * ((d.N_tp / 16 + 7) / 8);
         const int64_t per_xcd = (e.nitems + 7) / 8;
         const dim3 grid((unsigned)(per_xcd * 8)), block(256);
-        if (rtype == R_F64)
+        if (wtype == W_BF16X3)
+            hipLaunchKernelGGL(column_bf16_rt_kernel, grid, block, 0, s, e, per_xcd);
+        else if (rtype == R_F64)
             hipLaunchKernelGGL(column_rt_kernel<double>, grid, block, 0, s, e, per_xcd);
         else
             hipLaunchKernelGGL(column_rt_kernel<float>, grid, block, 0, s, e, per_xcd);

@@ -661,10 +661,10 @@ __device__ void pick_lds_body(const StepDesc &d, double *lds)
 __device__ __forceinline__ int64_t ublk(int I, int C) { return ((int64_t)C * (C + 1) / 2 + I) << 8; }
 
 // Copy the candidate's diagonal block of R (lower blocks, TR) into S as upper FP64 blocks.
-// With held W blocks (slots 0 .. d.nheld-1 at candidate offset pofs, same element type as R)
-// their products P_I P_C^T are subtracted, and with d.wb the corrected block is written back
-// to R (left-looking: the newest block column applied to the diagonal block in place).
-template <typename TR>
+// With held W blocks (slots 0 .. d.nheld-1 at candidate offset pofs: FP64, FP32 or BF16 hi + lo
+// parts) their products P_I P_C^T are subtracted, and with d.wb the corrected block is written
+// back to R (left-looking: the newest block column applied to the diagonal block in place).
+template <typename TR, typename TW>
 __device__ void load_upper_global(const TR *__restrict__ Rb, int nb, int nbr, double *__restrict__ S,
                                   const StepDesc &d, int64_t pofs)
 {
@@ -677,8 +677,9 @@ __device__ void load_upper_global(const TR *__restrict__ Rb, int nb, int nbr, do
 #pragma unroll
             for (int r = 0; r < 4; ++r) v[r] = (double)blk[4 * r];
             for (int hp = 0; hp < d.nheld; ++hp) {
-                const TR *Pw = (const TR *)d.W + hp * d.wslot + pofs;
-                const auto q = HeldProd<TR>::run(Pw, nullptr, I, C, nb, nbr, lane);
+                const TW *Pw = (const TW *)d.W + hp * d.wslot + pofs;
+                const TW *Pw2 = d.W2 ? (const TW *)d.W2 + hp * d.wslot + pofs : nullptr;
+                const auto q = HeldProd<TW>::run(Pw, Pw2, I, C, nb, nbr, lane);
 #pragma unroll
                 for (int r = 0; r < 4; ++r) v[r] -= (double)q[r];
             }
@@ -757,7 +758,7 @@ __host__ __device__ inline size_t blocked_lds_bytes(int nbr)
     return (size_t)(nbr + 1) * 64 * sizeof(doublex4) + (size_t)16 * nbr * sizeof(double);
 }
 
-template <typename TR>
+template <typename TR, typename TW>
 __device__ void gain_blocked_body(const StepDesc &d, int p, unsigned char *dyn)
 {
     __shared__ double red[4];
@@ -770,7 +771,7 @@ __device__ void gain_blocked_body(const StepDesc &d, int p, unsigned char *dyn)
     double *S = d.scratch + p * (nblk << 8);
     const int i = uniform_at(d.act_in, p);
     const int64_t bs = (int64_t)d.N_tp * d.N_tp;
-    load_upper_global((const TR *)d.R + blk_index(i, i) * bs, nbr, nbr, S, d, i * bs);
+    load_upper_global<TR, TW>((const TR *)d.R + blk_index(i, i) * bs, nbr, nbr, S, d, i * bs);
     __syncthreads();
     if (!chol_blocked(S, nbr, piv, nullptr, Ub, &sfail)) {
         if (threadIdx.x == 0) d.gains[p] = -INFINITY;
@@ -784,7 +785,7 @@ __device__ void gain_blocked_body(const StepDesc &d, int p, unsigned char *dyn)
 // columns q (wave q % 4, no barriers): Z_qq = (U_qq^-1)^T and, down the column,
 // Z_pq = -(U_pp^-1)^T sum_{r = q}^{p-1} U_rp^T Z_rq; Z is written to Linv in the operand order.
 // Scratch: S (nblk blocks), U_pp^-1 (nbr blocks), Z (nblk lower blocks, (p, q) at p(p+1)/2 + q).
-template <typename TR>
+template <typename TR, typename TW>
 __device__ void pick_blocked_body(const StepDesc &d, unsigned char *dyn)
 {
     __shared__ double red[4];
@@ -803,7 +804,7 @@ __device__ void pick_blocked_body(const StepDesc &d, unsigned char *dyn)
     const int64_t nblk = (int64_t)nbr * (nbr + 1) / 2;
     double *S = d.scratch, *Yg = S + (nblk << 8), *Z = Yg + ((int64_t)nbr << 8);
     const int64_t bs = (int64_t)d.N_tp * d.N_tp;
-    load_upper_global((const TR *)d.R + blk_index(s, s) * bs, nbr, nbr, S, d, s * bs);
+    load_upper_global<TR, TW>((const TR *)d.R + blk_index(s, s) * bs, nbr, nbr, S, d, s * bs);
     __syncthreads();
     if (!chol_blocked(S, nbr, piv, Yg, Ub, &sfail)) {
         if (tid == 0) d.state[ST_STATUS] = 2;
@@ -887,18 +888,18 @@ __global__ void __launch_bounds__(256, 1) pick_regs_batched(const StepDesc *__re
     pick_regs_body<TR, TW>(d);
 }
 
-template <typename TR>
+template <typename TR, typename TW>
 __global__ void __launch_bounds__(256) gain_blocked_kernel(StepDesc d)
 {
     extern __shared__ double dyn[];
-    gain_blocked_body<TR>(d, blockIdx.x, (unsigned char *)dyn);
+    gain_blocked_body<TR, TW>(d, blockIdx.x, (unsigned char *)dyn);
 }
 
-template <typename TR>
+template <typename TR, typename TW>
 __global__ void __launch_bounds__(256) pick_blocked_kernel(StepDesc d)
 {
     extern __shared__ double dyn[];
-    pick_blocked_body<TR>(d, (unsigned char *)dyn);
+    pick_blocked_body<TR, TW>(d, (unsigned char *)dyn);
 }
 
 template <typename TR>
@@ -973,10 +974,10 @@ static hipError_t launch_gain_t(const StepDesc &d, hipStream_t s)
     if (d.N_t <= REGS_MAX_NT) {
         hipLaunchKernelGGL((gain_regs_kernel<TR, TW>), dim3(d.n_act), dim3(256), 0, s, d);
     } else if (d.N_tp <= 16 * BLK_MAX_NB) {
-        if (!d.scratch || (d.nheld && sizeof(TW) != sizeof(TR))) return hipErrorInvalidValue;
+        if (!d.scratch) return hipErrorInvalidValue;
         const size_t lds = blocked_lds_bytes(d.N_tp >> 4);
-        allow_lds(gain_blocked_kernel<TR>, lds);
-        hipLaunchKernelGGL(gain_blocked_kernel<TR>, dim3(d.n_act), dim3(256), lds, s, d);
+        allow_lds(gain_blocked_kernel<TR, TW>, lds);
+        hipLaunchKernelGGL((gain_blocked_kernel<TR, TW>), dim3(d.n_act), dim3(256), lds, s, d);
     } else {
         if (d.nheld) return hipErrorInvalidValue;
         const size_t lds = d.scratch ? 0 : gain_lds_bytes(d.N_t);
@@ -992,11 +993,11 @@ static hipError_t launch_pick_t(const StepDesc &d, hipStream_t s)
     if (d.N_t <= REGS_MAX_NT) {
         hipLaunchKernelGGL((pick_regs_kernel<TR, TW>), dim3(1), dim3(256), 0, s, d);
     } else if (d.N_tp <= 16 * BLK_MAX_NB) {
-        // held block columns: as in the gain kernel (W in R's element type)
-        if (!d.scratch || (d.nheld && sizeof(TW) != sizeof(TR))) return hipErrorInvalidValue;
+        // held block columns: as in the gain kernel
+        if (!d.scratch) return hipErrorInvalidValue;
         const size_t lds = blocked_lds_bytes(d.N_tp >> 4);
-        allow_lds(pick_blocked_kernel<TR>, lds);
-        hipLaunchKernelGGL(pick_blocked_kernel<TR>, dim3(1), dim3(256), lds, s, d);
+        allow_lds(pick_blocked_kernel<TR, TW>, lds);
+        hipLaunchKernelGGL((pick_blocked_kernel<TR, TW>), dim3(1), dim3(256), lds, s, d);
     } else {
         if (d.nheld) return hipErrorInvalidValue;
         const size_t lds = d.scratch ? 0 : pick_lds_bytes(d.N_t);

@@ -167,8 +167,9 @@ hipError_t launch_column(const StepDesc &d, int rtype, int wtype, hipStream_t s)
 hipError_t launch_column_batched(const StepDesc *descs, int n, int64_t total, int N_tp, int rtype, int wtype,
                                  hipStream_t s);
 // Downdate kernels: SYRK_DIRECT streams W operands from global memory per wave (any N_tp);
-// SYRK_LDS stages them through LDS with a software pipeline (N_tp <= 128).  W_BF16X3 always
-// runs the BF16 split-product kernel (N_tp a multiple of 32, <= 128).
+// SYRK_LDS stages them through LDS with a software pipeline (a run-time slice loop for
+// N_tp > 128).  W_BF16X3 always runs the BF16 split-product kernel (N_tp a multiple of 32; above
+// 128 single instances with SYRK_LDS only).
 // SYRK_BIG: 256 x 256 tiles, eight waves (the BF16 split product only; its work items are
 // syrk_tiles_big()).
 enum SyrkVariant { SYRK_DIRECT = 0, SYRK_LDS = 1, SYRK_BIG = 2, SYRK_NVARIANTS = 3 };

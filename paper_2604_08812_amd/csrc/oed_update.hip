@@ -442,6 +442,103 @@ __device__ void syrk_bf16_body(const StepDesc &d, int64_t tile)
 }
 
 // ---------------------------------------------------------------------------------------------
+// The BF16 split-product downdate for N_tp = 32 nb32 > 128 (run-time block size): the staging and
+// products of syrk_bf16_body with a run-time slice loop, and R read in the epilogue four blocks at a
+// time (the K extent is long against the tile's R traffic, as in syrk_lds_rt_body).
+__device__ void syrk_bf16_rt_body(const StepDesc &d, int64_t tile)
+{
+    __shared__ u32x4 lds[2][4][8 * 64];  // [buffer][A hi, A lo, B hi, B lo][sub-block * 64 + lane]
+    if (d.state[ST_STATUS] != 0) return;
+    int64_t P, Q;
+    if (!super_tile(tile, syrk_tile_rows(d.n_act, d.N_tp), d.stl, P, Q)) return;
+    const int nb32 = d.N_tp >> 5;
+    float *__restrict__ R = (float *)d.R;
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6), wr = wave >> 1, wc = wave & 1;
+    TileMap m;
+    tile_map_n(d, d.N_tp, P, Q, wave, m);  // W offsets in BF16 elements: a 16 x 32 tile is 512
+    float *Rl = R + lane * 4;
+    typedef const unsigned short *bp;
+    const bp Wh0 = (bp)d.W + lane * 8, Wl0 = (bp)d.W2 + lane * 8;
+    const int64_t wslot = d.wslot;
+
+    floatx4 acc[16];
+#pragma unroll
+    for (int f = 0; f < 16; ++f) acc[f] = floatx4{0, 0, 0, 0};
+    u32x4 st[2][4];  // [h][A hi, A lo, B hi, B lo]
+    auto stage = [&](bp hi, bp lo) {
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            st[h][0] = *reinterpret_cast<const u32x4 *>(hi + m.wA[h]);
+            st[h][1] = *reinterpret_cast<const u32x4 *>(lo + m.wA[h]);
+            st[h][2] = *reinterpret_cast<const u32x4 *>(hi + m.wB[h]);
+            st[h][3] = *reinterpret_cast<const u32x4 *>(lo + m.wB[h]);
+        }
+    };
+    auto put = [&](int buf) {
+#pragma unroll
+        for (int h = 0; h < 2; ++h)
+#pragma unroll
+            for (int k = 0; k < 4; ++k) lds[buf][k][(wave + 4 * h) * 64 + lane] = st[h][k];
+    };
+    auto mma = [&](int buf) {
+        if (!m.any) return;
+        u32x4 wh[4], wl[4];
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+            wh[c] = lds[buf][2][(wc * 4 + c) * 64 + lane];
+            wl[c] = lds[buf][3][(wc * 4 + c) * 64 + lane];
+        }
+#pragma unroll
+        for (int b = 0; b < 4; ++b) {
+            const u32x4 ah = lds[buf][0][(wr * 4 + b) * 64 + lane];
+            const u32x4 al = lds[buf][1][(wr * 4 + b) * 64 + lane];
+#pragma unroll
+            for (int c = 0; c < 4; ++c) {
+                acc[4 * b + c] = mfma_bf16(ah, wh[c], acc[4 * b + c]);
+                acc[4 * b + c] = mfma_bf16(ah, wl[c], acc[4 * b + c]);
+                acc[4 * b + c] = mfma_bf16(al, wh[c], acc[4 * b + c]);
+            }
+        }
+    };
+    stage(Wh0, Wl0);
+    put(0);
+    __syncthreads();
+    int buf = 0;
+    const int nw = d.nw;
+    for (int slot = 0; slot < nw; ++slot) {
+        const bp chi = Wh0 + slot * wslot, clo = Wl0 + slot * wslot;
+        const bool last = slot + 1 == nw;
+        // 32-wide slice q of a staged sub-block row sits 512 q elements after its slice 0
+        for (int q = 0; q < nb32; ++q) {
+            const bool more = q + 1 < nb32 || !last;
+            if (more) {
+                if (q + 1 < nb32)
+                    stage(chi + ((q + 1) << 9), clo + ((q + 1) << 9));
+                else
+                    stage(chi + wslot, clo + wslot);
+            }
+            mma(buf);
+            if (more) put(buf ^ 1);
+            __syncthreads();
+            buf ^= 1;
+        }
+    }
+
+    if (!m.any) return;
+    constexpr int GR = 4;
+#pragma unroll
+    for (int f0 = 0; f0 < 16; f0 += GR) {
+        floatx4 rt[GR];
+#pragma unroll
+        for (int f = 0; f < GR; ++f) rt[f] = ld4_stream(Rl + m.rblk[f0 + f]);
+#pragma unroll
+        for (int f = 0; f < GR; ++f)
+            if (m.ok[f0 + f]) st4_stream(Rl + m.rblk[f0 + f], rt[f] - acc[f0 + f]);
+    }
+}
+
+// ---------------------------------------------------------------------------------------------
 // The BF16 split-product downdate over 256 x 256 tiles (SYRK_BIG): eight waves, wave w computes
 // rows 64 (w / 2) .. + 63 of the tile against columns 128 (w % 2) .. + 127, 4 x 8 blocks of 16 x 16.
 // Per 32-wide inner slice the work-group stages the 256-row A and B panels, hi and lo parts, in LDS
@@ -643,6 +740,13 @@ __global__ void __launch_bounds__(256, 2) syrk_bf16_batched(const StepDesc *__re
     syrk_bf16_body<NB32>(d, item - d.item0);
 }
 
+__global__ void __launch_bounds__(256, 2) syrk_bf16_rt_kernel(StepDesc d, int64_t per_xcd)
+{
+    const int64_t tile = xcd_item(blockIdx.x, per_xcd);
+    if (tile >= d.nitems) return;
+    syrk_bf16_rt_body(d, tile);
+}
+
 template <int NB32>
 __global__ void __launch_bounds__(512, 1) syrk_bf16_big_kernel(StepDesc d, int64_t per_xcd)
 {
@@ -725,8 +829,14 @@ static void allow_big_lds(K kernel)
 static hipError_t launch_syrk_bf16(const StepDesc *descs, const StepDesc &d, int n, int64_t total, int N_tp, int nw,
                                    int variant, hipStream_t s)
 {
-    if (N_tp < 32 || N_tp % 32 != 0 || N_tp > 128 || nw < 1 || nw > MAX_DELAY) return hipErrorInvalidValue;
+    if (N_tp < 32 || N_tp % 32 != 0 || nw < 1 || nw > MAX_DELAY) return hipErrorInvalidValue;
     const int64_t per_xcd = (total + 7) / 8;
+    if (N_tp > 128) {
+        // single instances with 128 x 128 tiles only: batches hold N_t <= 128
+        if (descs || variant != SYRK_LDS) return hipErrorInvalidValue;
+        hipLaunchKernelGGL(syrk_bf16_rt_kernel, dim3((unsigned)(per_xcd * 8)), dim3(256), 0, s, d, per_xcd);
+        return hipGetLastError();
+    }
     if (variant == SYRK_BIG) {
         const dim3 grid((unsigned)(per_xcd * 8)), block(512);
         switch (N_tp / 32) {

@@ -54,8 +54,10 @@ def test_host_side_argument_validation(lib):
     lib.oed_options_init(ctypes.byref(bad))
     bad.precision = 9
     assert lib.oed_create(ctypes.byref(h), fake, 0, 64, 4, 16, 1.0, None, ctypes.byref(bad)) == E_ARG
-    bad.precision = 2  # BF16 split product: N_t <= 128 only
-    assert lib.oed_create(ctypes.byref(h), fake, 0, 4 * 160, 4, 160, 1.0, None, ctypes.byref(bad)) == 6
+    bad.precision = 2  # BF16 split product, held block columns: N_t <= 1024 (as every precision)
+    bad.delay = 2
+    assert lib.oed_create(ctypes.byref(h), fake, 0, 2 * 1040, 2, 1040, 1.0, None, ctypes.byref(bad)) == 6
+    assert "N_t <= 1024" in lib.oed_last_error(None).decode()
     bad = oed_options()
     lib.oed_options_init(ctypes.byref(bad))
     bad.method = 5
@@ -187,6 +189,10 @@ def test_options_layout_and_create_errors_without_a_gpu(lib):
     assert lib.oed_create(ctypes.byref(h), fake, 0, 64, 4, 16, 1.0, None, ctypes.byref(opt)) == 1
     opt.tile_size = 256      # 256 x 256 downdate tiles: the BF16 split product only
     assert lib.oed_create(ctypes.byref(h), fake, 0, 64, 4, 16, 1.0, None, ctypes.byref(opt)) == 6
+    opt.precision = 2        # ... and for N_t <= 128 only
+    assert lib.oed_create(ctypes.byref(h), fake, 0, 4 * 160, 4, 160, 1.0, None, ctypes.byref(opt)) == 6
+    assert "N_t <= 128" in lib.oed_last_error(None).decode()
+    opt.precision = 0
     opt.tile_size = 0
     opt.reserved[0] = 1
     assert lib.oed_create(ctypes.byref(h), fake, 0, 64, 4, 16, 1.0, None, ctypes.byref(opt)) == 1

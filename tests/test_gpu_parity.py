@@ -48,18 +48,11 @@ CASES = [
 PRECS = ["fp64", "mixed_f32", "mixed_bf16x3"]
 
 
-def supported(prec, N_t):
-    """The BF16 split-product downdate handles N_t <= 128 only."""
-    return prec != "mixed_bf16x3" or N_t <= 128
-
-
 @pytest.mark.parametrize("delay", [1, 2, 4, 8])
 @pytest.mark.parametrize("prec", PRECS)
 @pytest.mark.parametrize("case", CASES, ids=lambda c: "x".join(map(str, c[:2])))
 def test_greedy_matches_oracle(case, prec, delay):
     N_s, N_t, n_m, seed, B = case
-    if not supported(prec, N_t):
-        pytest.skip("N_t > 128 has no BF16 split-product downdate")
     print(f"case N_s={N_s} N_t={N_t} seed={seed} B={B} prec={prec} delay={delay}", flush=True)
     K, Kd, s2 = instance(N_s, N_t, n_m, seed)
     with selector(Kd, N_s, N_t, s2, precision=prec, delay=delay) as sel:
@@ -287,8 +280,6 @@ LEFT_CASES = CASES  # N_t > 128: blocked global-scratch gain kernel with the dia
 @pytest.mark.parametrize("case", LEFT_CASES, ids=lambda c: "x".join(map(str, c[:2])))
 def test_left_looking_matches_oracle_and_right_looking(case, prec):
     N_s, N_t, n_m, seed, B = case
-    if not supported(prec, N_t):
-        pytest.skip("N_t > 128 has no BF16 split-product path")
     print(f"left-looking N_s={N_s} N_t={N_t} seed={seed} B={B} prec={prec}", flush=True)
     K, Kd, s2 = instance(N_s, N_t, n_m, seed)
     with selector(Kd, N_s, N_t, s2, precision=prec, method="left", max_budget=B) as sel:
