@@ -307,7 +307,8 @@ def design_evaluation(K, spec, s2, prec, budget, idx, gain, n):
 
 
 def run_paper_shape(args):
-    """The paper's shape, 600 sensors x 420 observations, mixed FP32.  K (252,000^2) is never whole:
+    """The paper's shape, 600 sensors x 420 observations, mixed FP32 (or --precision mixed_bf16x3,
+    the BF16 split product; FP64 would need 254 GB for the working copy alone).  K (252,000^2) is never whole:
     F stays resident and K's row panels are formed by GEMM and packed one at a time (untimed, like
     the formation of K elsewhere).  A step is one oed_greedy(175) on the packed working copy; the
     selection conditions the working copy, so each step after the first resets and packs again,
@@ -319,18 +320,21 @@ def run_paper_shape(args):
     library()
     spec = CONFIGS["paper_600x420"]
     budget = args.budget or spec.budget
+    prec = args.precision or "mixed_f32"
+    if prec == "fp64":
+        sys.exit("the paper's shape runs the mixed precisions: an FP64 working copy would take 254 GB")
     t0 = time.perf_counter()
     F, scale = f_matrix(spec.N_d, spec.n_m, spec.seed, device="cuda:0", dtype=torch.float32,
                         progress=lambda i, n: log(f"  F column chunk {i}/{n}") if i % 4 == 0 or i == n else None)
     s2 = spec.c * scale
     torch.cuda.synchronize()
     log(f"F {spec.N_d} x {spec.n_m} formed in {time.perf_counter() - t0:.1f} s, sigma2={s2:.6e}")
-    sel = Selector(None, spec.N_s, spec.N_t, s2, precision="mixed_f32", profile=True, delay=args.delay)
+    sel = Selector(None, spec.N_s, spec.N_t, s2, precision=prec, profile=True, delay=args.delay)
     delay, variant, _, tiles = sel.config()
 
-    def pack(target):
+    def pack(target, panel=56):
         t = time.perf_counter()
-        for s0, n, P in k_row_panels(F, spec.N_s, spec.N_t, s2, 56):
+        for s0, n, P in k_row_panels(F, spec.N_s, spec.N_t, s2, panel):
             target.pack_rows(P, s0, n)
             del P
         torch.cuda.synchronize()
@@ -362,9 +366,11 @@ def run_paper_shape(args):
     if not args.no_left:
         # left-looking (Algorithm 1's order) on the same K: pack, free F (the W history needs
         # the room), one timed selection
-        sell = Selector(None, spec.N_s, spec.N_t, s2, precision="mixed_f32", profile=True, method="left",
+        sell = Selector(None, spec.N_s, spec.N_t, s2, precision=prec, profile=True, method="left",
                         max_budget=budget)
-        pack_l = pack(sell)
+        # the BF16 blocks are padded to 448 rows and its W history holds hi and lo parts: narrower
+        # row panels keep F, the panel, R and the history within the GPU's memory
+        pack_l = pack(sell, 56 if prec == "mixed_f32" else 14)
         del F
         torch.cuda.empty_cache()
         F = None
@@ -379,9 +385,11 @@ def run_paper_shape(args):
         sell.close()
         log(f"left-looking: {msl:.1f} ms per selection")
         tfl = pl["syrk_flops"] / (pl["ms"]["syrk"] * 1e-3) / 1e12 if pl["ms"]["syrk"] > 0 else 0.0
+        ex = 3 if prec == "mixed_bf16x3" else 1  # BF16 split product: three MFMA products per one
         left = {"value": round(budget / (msl * 1e-3), 3), "unit": "greedy steps/s", "ms_per_step": round(msl, 3),
-                "column_kernel": {"kernel": "column_rt_kernel<float>", "algorithmic_tflops": round(tfl, 3),
-                                  "peak": PEAK_TFLOPS["mixed_f32"], "frac": round(tfl / PEAK_TFLOPS["mixed_f32"], 4),
+                "column_kernel": {"kernel": "column_bf16_rt_kernel" if ex == 3 else "column_rt_kernel<float>",
+                                  "algorithmic_tflops": round(tfl, 3), "executed_tflops": round(ex * tfl, 3),
+                                  "peak": PEAK_TFLOPS[prec], "frac": round(ex * tfl / PEAK_TFLOPS[prec], 4),
                                   "algorithmic_flops_per_selection": pl["syrk_flops"]},
                 "kernel_ms_per_step": {k: round(v, 3) for k, v in pl["ms"].items()},
                 "pack_s": round(pack_l, 3), "device_bytes_of_handle": devl,
@@ -390,13 +398,14 @@ def run_paper_shape(args):
         "metric": "greedy steps/s + SYRK TFLOP/s (% MFMA peak), mixed vs FP64, same picks",
         "value": round(budget / (ms * 1e-3), 3), "unit": "greedy steps/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": round(ms, 3), "higher_is_better": True, "scaling": "weak",
-        "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "vs_baseline": None, "dtype": "f32" if prec == "mixed_f32" else "bf16x3", "data": "synthetic",
         "config": {"workload": spec.name, "N_s": spec.N_s, "N_t": spec.N_t, "n_m": spec.n_m, "seed": spec.seed,
-                   "budget": budget, "precision": "mixed_f32", "K_dtype": "f32 (row panels, never whole)",
+                   "budget": budget, "precision": prec, "K_dtype": "f32 (row panels, never whole)",
                    "delay": delay, "downdate_variant": ["direct", "lds", "lds256"][variant],
                    "step": "oed_greedy(budget) on the packed working copy"},
-        "roofline": {**roofline_syrk(prof, "mixed_f32", spec.name, delay),
-                     "kernel": "syrk_direct_kernel<float>" if variant == 0 else "syrk_lds_rt_kernel<float>"},
+        "roofline": {**roofline_syrk(prof, prec, spec.name, delay),
+                     "kernel": "syrk_bf16_rt_kernel" if prec == "mixed_bf16x3" else
+                     "syrk_direct_kernel<float>" if variant == 0 else "syrk_lds_rt_kernel<float>"},
         "kernel_ms_per_step": {k: round(v / args.steps, 3) for k, v in prof["ms"].items()},
         "pack_s_per_fill": round(sum(pack_s) / len(pack_s), 3),
         "device_bytes_of_handle": dev_bytes,
@@ -404,7 +413,7 @@ def run_paper_shape(args):
         "paper_context": PAPER_CONTEXT,
     }
     if left is not None:
-        result["left_looking_mixed_f32"] = left
+        result["left_looking_" + prec] = left
     del F
     print(json.dumps(result), flush=True)
 

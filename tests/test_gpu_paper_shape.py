@@ -1,5 +1,5 @@
 """The paper's shape on one GPU: 600 candidate sensors x 420 observations (N_d = 252,000), mixed
-FP32.  The full K (254 GB in FP32) is never formed: F (40 GB) stays resident, K's row panels are
+FP32 and the BF16 split product.  The full K (254 GB in FP32) is never formed: F (40 GB) stays resident, K's row panels are
 formed one GEMM at a time and packed into the working copy (135 GB FP32), each panel freed after
 packing.
 
@@ -45,13 +45,15 @@ def k_sub(F, N_t, n_m, s2, sensors):
 
 
 @pytest.mark.timeout(900)
-def test_paper_shape_first_steps_against_oracle(paper):
+@pytest.mark.parametrize("prec", ["mixed_f32", "mixed_bf16x3"])
+def test_paper_shape_first_steps_against_oracle(paper, prec):
     from paper_2604_08812_amd import Selector
     spec, F, s2 = paper
-    N_s, N_t, rtol = spec.N_s, spec.N_t, RTOL["mixed_f32"]
+    N_s, N_t, rtol = spec.N_s, spec.N_t, RTOL[prec]
     rng = np.random.default_rng(7)
     sample = sorted(rng.choice(N_s, 16, replace=False).tolist())
-    with Selector(None, N_s, N_t, s2, precision="mixed_f32") as sel:
+    print(f"paper shape {prec}", flush=True)
+    with Selector(None, N_s, N_t, s2, precision=prec) as sel:
         for s0, n, P in k_row_panels(F, N_s, N_t, s2, 56):
             sel.pack_rows(P, s0, n)
             del P
@@ -83,7 +85,7 @@ def test_paper_shape_first_steps_against_oracle(paper):
     assert abs(sum(gains) - total) <= rtol * abs(total)
     # the left-looking method (column GEMM over 128-column chunks of the pick, diagonal blocks
     # kept current by the blocked gain kernel) picks the same sensors with the same gains
-    with Selector(None, N_s, N_t, s2, precision="mixed_f32", method="left", max_budget=STEPS) as sel:
+    with Selector(None, N_s, N_t, s2, precision=prec, method="left", max_budget=STEPS) as sel:
         for s0, n, P in k_row_panels(F, N_s, N_t, s2, 56):
             sel.pack_rows(P, s0, n)
             del P
