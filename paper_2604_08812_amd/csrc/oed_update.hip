@@ -443,8 +443,10 @@ __device__ void syrk_bf16_body(const StepDesc &d, int64_t tile)
 
 // ---------------------------------------------------------------------------------------------
 // The BF16 split-product downdate for N_tp = 32 nb32 > 128 (run-time block size): the staging and
-// products of syrk_bf16_body with a run-time slice loop, and R read in the epilogue four blocks at a
-// time (the K extent is long against the tile's R traffic, as in syrk_lds_rt_body).
+// products of syrk_bf16_body with a run-time slice loop.  Half of the tile's sixteen R blocks are
+// loaded two slices before the end, so that the last slices' MFMAs cover their latency, the other
+// half with the epilogue's stores of the first (all sixteen early spill: the kernel keeps two
+// work-groups per CU, which its 64 KB of LDS allow, only within 256 registers).
 __device__ void syrk_bf16_rt_body(const StepDesc &d, int64_t tile)
 {
     __shared__ u32x4 lds[2][4][8 * 64];  // [buffer][A hi, A lo, B hi, B lo][sub-block * 64 + lane]
@@ -481,8 +483,9 @@ __device__ void syrk_bf16_rt_body(const StepDesc &d, int64_t tile)
 #pragma unroll
             for (int k = 0; k < 4; ++k) lds[buf][k][(wave + 4 * h) * 64 + lane] = st[h][k];
     };
+    // the MFMAs run without a branch (a wave with no output block computes products it never
+    // stores), so that the scheduling barrier keeps the next slice's loads ahead of them
     auto mma = [&](int buf) {
-        if (!m.any) return;
         u32x4 wh[4], wl[4];
 #pragma unroll
         for (int c = 0; c < 4; ++c) {
@@ -501,6 +504,7 @@ __device__ void syrk_bf16_rt_body(const StepDesc &d, int64_t tile)
             }
         }
     };
+    floatx4 rt[8];
     stage(Wh0, Wl0);
     put(0);
     __syncthreads();
@@ -518,6 +522,12 @@ __device__ void syrk_bf16_rt_body(const StepDesc &d, int64_t tile)
                 else
                     stage(chi + wslot, clo + wslot);
             }
+            // blocks outside the triangle read a valid address and are not stored
+            if (last && q == nb32 - 2) {
+#pragma unroll
+                for (int f = 0; f < 8; ++f) rt[f] = ld4_stream(Rl + m.rblk[f]);
+            }
+            __builtin_amdgcn_sched_barrier(0);
             mma(buf);
             if (more) put(buf ^ 1);
             __syncthreads();
@@ -526,16 +536,15 @@ __device__ void syrk_bf16_rt_body(const StepDesc &d, int64_t tile)
     }
 
     if (!m.any) return;
-    constexpr int GR = 4;
+    floatx4 r2[8];
 #pragma unroll
-    for (int f0 = 0; f0 < 16; f0 += GR) {
-        floatx4 rt[GR];
+    for (int f = 0; f < 8; ++f) r2[f] = ld4_stream(Rl + m.rblk[8 + f]);
 #pragma unroll
-        for (int f = 0; f < GR; ++f) rt[f] = ld4_stream(Rl + m.rblk[f0 + f]);
+    for (int f = 0; f < 8; ++f)
+        if (m.ok[f]) st4_stream(Rl + m.rblk[f], rt[f] - acc[f]);
 #pragma unroll
-        for (int f = 0; f < GR; ++f)
-            if (m.ok[f0 + f]) st4_stream(Rl + m.rblk[f0 + f], rt[f] - acc[f0 + f]);
-    }
+    for (int f = 0; f < 8; ++f)
+        if (m.ok[8 + f]) st4_stream(Rl + m.rblk[8 + f], r2[f] - acc[8 + f]);
 }
 
 // ---------------------------------------------------------------------------------------------
