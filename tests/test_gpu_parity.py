@@ -63,6 +63,20 @@ def test_greedy_matches_oracle(case, prec, delay):
         assert rep["diverged_steps"] == [] or min(rep["ref"]["gap"]) < 1e-9
 
 
+@pytest.mark.parametrize("prec", PRECS)
+def test_blocks_beyond_the_blocked_factorisation(prec):
+    """N_t = 1040 > 1024: the gains and the pick factor each block element-wise in global scratch,
+    the downdate is the run-time-size kernel of the precision (33 tile rows, the last partial);
+    delay 1, the only depth served there."""
+    N_s, N_t, n_m, seed, B = 4, 1040, 3000, 12, 3
+    print(f"N_t {N_t} {prec}", flush=True)
+    K, Kd, s2 = instance(N_s, N_t, n_m, seed)
+    with selector(Kd, N_s, N_t, s2, precision=prec, delay=1) as sel:
+        idx, gain = sel.greedy(B)
+    rep = check_trajectory(K, N_s, N_t, s2, idx, gain, RTOL[prec])
+    print(f"  max rel gain err {rep['max_rel_err']:.2e}", flush=True)
+
+
 @pytest.mark.parametrize("prefix", [[7, 0, 28, 13], [7, 0, 28]], ids=["even", "odd"])
 @pytest.mark.parametrize("prec", PRECS)
 def test_scores_and_schur_blocks_after_forced_prefix(prec, prefix):
