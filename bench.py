@@ -42,6 +42,8 @@ def parse():
     ap.add_argument("--budget", type=int, default=None, help="override the budget (not the headline)")
     ap.add_argument("--precision", default=None, choices=["fp64", "mixed_f32", "mixed_bf16x3"],
                     help="override the configuration's precision (not the headline)")
+    ap.add_argument("--peaks", action="store_true",
+                    help="measure the box's own ceilings (device copy, vendor GEMMs) and exit")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device copy 4 times (HBM counter calibration)")
     ap.add_argument("--fp64-steps", type=int, default=1)
@@ -136,6 +138,50 @@ def compare_picks(idx, gain, idx_ref, gain_ref):
         if upto else 0.0
     return {"same_picks": agree == budget, "picks_equal_at_position": agree, "first_divergence_step": first_div,
             "max_rel_gain_diff_before_divergence": gerr, "per_step_rel_gain_diff": per_step_diff(gain, gain_ref, upto)}
+
+
+def measured_peaks():
+    """What this GPU reaches outside the selection kernels, as ceilings to read the roofline
+    fractions against: a device-to-device copy of 4 GiB (HBM read + write) and the vendor GEMMs
+    (torch.mm, square, contiguous operands) in FP32, FP64 and BF16, timed with HIP events on
+    torch's stream after one untimed call."""
+    import torch
+    torch.backends.cuda.matmul.allow_tf32 = False
+    dev = "cuda:0"
+
+    def timed(fn, reps):
+        fn()
+        torch.cuda.synchronize()
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        for _ in range(reps):
+            fn()
+        b.record()
+        torch.cuda.synchronize()
+        return a.elapsed_time(b) / reps
+
+    out = {}
+    src = torch.ones(1 << 30, dtype=torch.float32, device=dev)
+    dst = torch.empty_like(src)
+    ms = timed(lambda: dst.copy_(src), 10)
+    out["copy"] = {"bytes_moved": 2 * 4 << 30, "ms": round(ms, 3), "TB/s": round(2 * 4 * (1 << 30) / ms / 1e9, 3),
+                   "frac_of_8TB/s": round(2 * 4 * (1 << 30) / ms / 1e9 / 8.0, 4)}
+    del src, dst
+    peak = {"fp32": 157.3, "fp64": 78.6, "bf16": 2500.0}
+    out["gemm"] = []
+    for name, dt, N in (("fp32", torch.float32, 8192), ("fp32", torch.float32, 16384), ("fp64", torch.float64, 8192),
+                        ("bf16", torch.bfloat16, 8192), ("bf16", torch.bfloat16, 16384)):
+        g = torch.Generator(device=dev)
+        g.manual_seed(N)
+        x = torch.randn(N, N, device=dev, dtype=torch.float32, generator=g).to(dt)
+        y = torch.randn(N, N, device=dev, dtype=torch.float32, generator=g).to(dt)
+        ms = timed(lambda: torch.mm(x, y), 5)
+        tf = 2.0 * N ** 3 / ms / 1e9
+        out["gemm"].append({"dtype": name, "N": N, "ms": round(ms, 3), "TFLOP/s": round(tf, 1),
+                            "frac_of_peak": round(tf / peak[name], 4)})
+        log(f"torch.mm {name} {N}: {tf:.1f} TFLOP/s")
+        del x, y
+    print(json.dumps({"measured_peaks": out, "device": torch.cuda.get_device_name(0)}), flush=True)
 
 
 def copy_calibration():
@@ -563,6 +609,8 @@ def main():
 
     if args.copy_calibration:
         return copy_calibration()
+    if args.peaks:
+        return measured_peaks()
     library()
     if args.config == "batched_48":
         return run_batched(args)
