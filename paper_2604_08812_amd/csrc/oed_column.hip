@@ -100,12 +100,25 @@ __device__ void column_body(const StepDesc &d, int64_t item)
                 for (int b = 0; b < 2; ++b) a[b] = lds[buf][0][(2 * wave + b) * 64 + lane];
 #pragma unroll
                 for (int c = 0; c < NB; ++c) w[c] = lds[buf][1][c * 64 + alane];
+                if constexpr (sizeof(T) == 4) {
+                    // FP32: pick row block by pick row block (the first MFMAs need a and w[0] only;
+                    // per output block the MFMAs keep their order, as in the downdate): 5.8% faster
+                    // at 600 x 128 than each k-step over all blocks in turn, which FP64 keeps (1.3%
+                    // slower there this way)
 #pragma unroll
-                for (int s4 = 0; s4 < 4; ++s4)
+                    for (int c = 0; c < NB; ++c)
 #pragma unroll
-                    for (int b = 0; b < 2; ++b)
+                        for (int s4 = 0; s4 < 4; ++s4)
 #pragma unroll
-                        for (int c = 0; c < NB; ++c) acc[b][c] = mfma16(w[c][s4], a[b][s4], acc[b][c]);
+                            for (int b = 0; b < 2; ++b) acc[b][c] = mfma16(w[c][s4], a[b][s4], acc[b][c]);
+                } else {
+#pragma unroll
+                    for (int s4 = 0; s4 < 4; ++s4)
+#pragma unroll
+                        for (int b = 0; b < 2; ++b)
+#pragma unroll
+                            for (int c = 0; c < NB; ++c) acc[b][c] = mfma16(w[c][s4], a[b][s4], acc[b][c]);
+                }
             }
             if (more) {
 #pragma unroll
