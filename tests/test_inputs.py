@@ -71,3 +71,30 @@ def test_row_panels_are_the_lower_block_triangle_of_K():
     assert seen == [(0, 3), (3, 3), (6, 1)]
     Kref, s2ref = make_K(N_s, N_t, n_m, seed=4)
     assert torch.allclose(Kref, K, rtol=0, atol=1e-12) and abs(s2ref - s2) <= 1e-14 * s2
+
+
+def test_weighted_time_correlated_noise_recipe():
+    """K = F F^T / n_m + blockdiag(w_j gamma^2 rho_j^|t-u|): the signal part is make_K's (same F),
+    each noise block is a scaled AR(1) correlation (positive definite, Toeplitz, lag-1 ratio rho_j),
+    weights and correlations in their ranges, nothing between sensors."""
+    from oed_inputs import make_K_weighted_noise
+    N_s, N_t, n_m, seed = 7, 5, 200, 9
+    K, blocks = make_K_weighted_noise(N_s, N_t, n_m, seed, w_lo=2.0, w_hi=40.0, rho_max=0.7)
+    K = K.numpy()
+    K0, s2 = make_K(N_s, N_t, n_m, seed)
+    G = K0.numpy() - s2 * np.eye(N_s * N_t)      # F F^T / n_m of the same F
+    gamma2 = 0.01 * float(np.mean(np.diag(G)))
+    D = K - G
+    for j in range(N_s):
+        for i in range(N_s):
+            blk = D[i * N_t:(i + 1) * N_t, j * N_t:(j + 1) * N_t]
+            if i != j:
+                assert np.abs(blk).max() <= 1e-14
+        B = blocks[j]
+        np.testing.assert_allclose(D[j * N_t:(j + 1) * N_t, j * N_t:(j + 1) * N_t], B, rtol=1e-12, atol=1e-16)
+        w = B[0, 0] / gamma2
+        rho = B[0, 1] / B[0, 0]
+        assert 2.0 <= w <= 40.0 and 0.0 <= rho < 0.7
+        lag = np.abs(np.subtract.outer(np.arange(N_t), np.arange(N_t)))
+        np.testing.assert_allclose(B, w * gamma2 * rho ** lag, rtol=1e-12)
+        assert np.linalg.eigvalsh(B).min() > 0
